@@ -1,0 +1,710 @@
+/*
+ * psfm_oracle.c -- plain FP64 CPU reference for the PSF-matching hot path of
+ * Price & Magnier, "Pan-STARRS PSF-Matching for Subtraction and Stacking".
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg load this library.  The product path (the HIP
+ * library) never links, calls or includes anything from here, and this file
+ * shares no code, header, table or helper with it.
+ *
+ * Every function computes the paper's definition directly, in double
+ * precision, without blocking, separability or reordering beyond what the
+ * definition states:
+ *   - basis kernels: Section 2, Eq. 7 with the zero-sum requirement of
+ *     Section 2 (flux conservation) -- each k_i (i >= 1) sums to zero;
+ *   - design matrix, normal equations: Section 2, Eqs. 3-6 with c = 0, p = 0;
+ *   - spatial variation evaluated at the stamp centre: Section 2;
+ *   - stamp validity: Section 3.3 (masked pixels in the footprint);
+ *   - rejection of discrepant stamps: Sections 3.3 and 3.6;
+ *   - patch-wise constant kernels: Section 3.5;
+ *   - BAD/POOR masking: Section 3.4;
+ *   - image and variance convolution: Section 4.2, Eqs. 12-13;
+ *   - covariance pseudo-matrix: Section 4.2 (Eqs. 10-11 applied to a kernel),
+ *     covariance factor and Section 4.3 (sample average, factor removal);
+ *   - image subtraction noise: Section 4.3.
+ * Readings of points the paper leaves open are stated where they are used.
+ *
+ * Conventions: images are row-major, element (x, y) at [y * pitch + x];
+ * kernels are (2h+1)^2 arrays indexed [(v + h) * (2h+1) + (u + h)] with u the
+ * column (x) offset and v the row (y) offset; masks are uint8, non-zero means
+ * masked.  OpenMP threads run over stamps and over patches, as the paper's
+ * implementation threads over stamps and patches (Section 3.5).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_MAX_GAUSS 8
+
+typedef struct {
+    int n_gauss;
+    double sigma[ORC_MAX_GAUSS];
+    int degree[ORC_MAX_GAUSS];
+    int h;              /* kernel half width: u, v in [-h, h] */
+    int S;              /* spatial polynomial order */
+    int r;              /* stamp half width: stamp is (2r+1)^2 pixels */
+    int P;              /* side of the constant-kernel patches */
+    double clip_sigma;  /* rejection threshold in standard deviations */
+    int max_iter;       /* maximum number of solutions */
+    int min_stamps;     /* fewer usable stamps is an error */
+    double bad_frac;    /* BAD/POOR fraction of sum(k^2) */
+} orc_config;
+
+typedef struct {
+    double chi2, dof, chi2_dof, kernel_sum_centre, cov_discarded_frac;
+    int n_used, n_rejected, n_iter, info;
+} orc_stats;
+
+/* stamp flag bits */
+#define ORC_STAMP_INVALID   1   /* footprint leaves the image or touches a mask */
+#define ORC_STAMP_REJECTED  2   /* removed by the rejection iterations */
+#define ORC_STAMP_NONFINITE 4   /* non-finite pixel or non-positive variance */
+/* output mask bits */
+#define ORC_MASK_BAD       1
+#define ORC_MASK_CONV_BAD  2
+#define ORC_MASK_CONV_POOR 4
+
+static double ipow(double x, int n) {
+    double r = 1.0;
+    for (int k = 0; k < n; k++) r *= x;
+    return r;
+}
+
+int orc_n_basis(const orc_config* c) {
+    int n = 0;
+    for (int j = 0; j < c->n_gauss; j++) n += (c->degree[j] + 1) * (c->degree[j] + 2) / 2;
+    return n;
+}
+
+int orc_n_spatial(const orc_config* c) { return (c->S + 1) * (c->S + 2) / 2; }
+
+int orc_n_unknowns(const orc_config* c) { return orc_n_basis(c) * orc_n_spatial(c) + 1; }
+
+/*
+ * Kernel basis (Section 2, Eq. 7; Section 3.1).  For Gaussian j of width
+ * sigma_j and each polynomial term u^p v^q with p + q <= degree_j (terms
+ * ordered by total degree d, then p from d down to 0):
+ *     raw(u, v) = u^p v^q exp(-(u^2 + v^2) / (2 sigma_j^2)).
+ * Reading of the printed exponent: its sign is lost in the source; a Gaussian
+ * that decays away from the centre is meant.
+ * The first term carries the flux: k_0 = raw_0 / sum(raw_0) (unit sum).
+ * The zero-sum requirement of Section 2 is met by subtracting k_0 from each
+ * other term that has a non-zero sum (p and q both even):
+ *     k_i = raw_i / sum(raw_i) - k_0,
+ * while terms odd in u or v already sum to zero and are scaled to unit L1
+ * norm: k_i = raw_i / sum(|raw_i|).
+ */
+void orc_basis(const orc_config* c, double* k) {
+    const int K = 2 * c->h + 1, T = K * K, h = c->h;
+    double* raw = (double*)malloc(sizeof(double) * T);
+    int i = 0;
+    for (int j = 0; j < c->n_gauss; j++) {
+        const double s2 = 2.0 * c->sigma[j] * c->sigma[j];
+        for (int d = 0; d <= c->degree[j]; d++) {
+            for (int p = d; p >= 0; p--) {
+                const int q = d - p;
+                double sum = 0.0, sabs = 0.0;
+                for (int v = -h; v <= h; v++)
+                    for (int u = -h; u <= h; u++) {
+                        double val = ipow(u, p) * ipow(v, q) * exp(-(double)(u * u + v * v) / s2);
+                        raw[(v + h) * K + (u + h)] = val;
+                        sum += val;
+                        sabs += fabs(val);
+                    }
+                double* ki = k + (size_t)i * T;
+                if (i == 0) {
+                    for (int t = 0; t < T; t++) ki[t] = raw[t] / sum;
+                } else if (p % 2 == 0 && q % 2 == 0) {
+                    for (int t = 0; t < T; t++) ki[t] = raw[t] / sum - k[t];
+                } else {
+                    for (int t = 0; t < T; t++) ki[t] = raw[t] / sabs;
+                }
+                i++;
+            }
+        }
+    }
+    free(raw);
+}
+
+/*
+ * Spatial polynomial terms g_s(x, y) (Section 2: ordinary polynomials x^l y^m).
+ * Reading: coordinates are scaled to [-1, 1] over the image,
+ *     xt = (2x - (W-1)) / (W-1),  yt = (2y - (H-1)) / (H-1),
+ * and the terms x^l y^m with l + m <= S are ordered by degree, then l
+ * descending: 1, x, y, x^2, xy, y^2, ...
+ */
+void orc_spatial(int S, double x, double y, int W, int H, double* g) {
+    const double xt = W > 1 ? (2.0 * x - (W - 1)) / (double)(W - 1) : 0.0;
+    const double yt = H > 1 ? (2.0 * y - (H - 1)) / (double)(H - 1) : 0.0;
+    int s = 0;
+    for (int d = 0; d <= S; d++)
+        for (int l = d; l >= 0; l--) g[s++] = ipow(xt, l) * ipow(yt, d - l);
+}
+
+/*
+ * Local kernel coefficients at a point: alpha_i(x, y) = sum_s a[i*ns + s] g_s(x, y)
+ * for the nb kernel terms, plus the background coefficient (last unknown) in
+ * alpha[nb].  Unknown ordering: kernel term i, spatial term s at i*ns + s;
+ * the constant background last.
+ */
+void orc_local_coeffs(const orc_config* c, const double* a, double x, double y, int W, int H,
+                      double* alpha) {
+    const int nb = orc_n_basis(c), ns = orc_n_spatial(c), N = nb * ns + 1;
+    double g[64];
+    orc_spatial(c->S, x, y, W, H, g);
+    for (int i = 0; i < nb; i++) {
+        double s = 0.0;
+        for (int t = 0; t < ns; t++) s += a[i * ns + t] * g[t];
+        alpha[i] = s;
+    }
+    alpha[nb] = a[N - 1];
+}
+
+/* The kernel realised at a point: K(u, v) = sum_i alpha_i(x, y) k_i(u, v). */
+void orc_kernel_at(const orc_config* c, const double* kb, const double* a, double x, double y,
+                   int W, int H, double* K) {
+    const int nb = orc_n_basis(c), T = (2 * c->h + 1) * (2 * c->h + 1);
+    double* alpha = (double*)malloc(sizeof(double) * (nb + 1));
+    orc_local_coeffs(c, a, x, y, W, H, alpha);
+    for (int t = 0; t < T; t++) {
+        double s = 0.0;
+        for (int i = 0; i < nb; i++) s += alpha[i] * kb[(size_t)i * T + t];
+        K[t] = s;
+    }
+    free(alpha);
+}
+
+/*
+ * Per-stamp normal equations (Section 2, Eqs. 3-6 with c_i = 0 and P = 0).
+ * For every stamp pixel (x, y), with the true convolution of Section 4.2,
+ *     A_i(x, y) = sum_{u,v} k_i(u, v) I1(x - u, y - v)     (i < nb)
+ *     A_nb      = 1                                        (constant background)
+ *     w = 1 / V2(x, y),  d = I2(x, y)
+ * and the stamp accumulates M_s = sum w A A^T (L x L, L = nb + 1),
+ * b_s = sum w A d and e_s = sum w d^2.
+ * Validity (Section 3.3): a stamp whose convolution footprint
+ * [x-r-h, x+r+h]^2 leaves the image or holds a masked I1 pixel, or whose
+ * stamp [x-r, x+r]^2 holds a masked I2 pixel, is flagged INVALID; a stamp
+ * holding a non-finite I1/I2 value or a variance that is not finite and
+ * positive is flagged NONFINITE.  Flagged stamps get zero sums.
+ */
+void orc_fit_stamps(const orc_config* c, const double* kb, const float* I1, const uint8_t* M1,
+                    const float* I2, const float* V2, const uint8_t* M2, int W, int H,
+                    int64_t pitch, const int32_t* xy, int n, double* Ms, double* bs, double* es,
+                    int32_t* npix, int32_t* flags) {
+    const int nb = orc_n_basis(c), L = nb + 1, h = c->h, r = c->r, K = 2 * h + 1,
+              T = K * K;
+#pragma omp parallel for schedule(dynamic)
+    for (int s = 0; s < n; s++) {
+        const int xc = xy[2 * s], yc = xy[2 * s + 1], R = r + h;
+        double* M = Ms + (size_t)s * L * L;
+        double* b = bs + (size_t)s * L;
+        int flag = 0;
+        memset(M, 0, sizeof(double) * L * L);
+        memset(b, 0, sizeof(double) * L);
+        es[s] = 0.0;
+        npix[s] = 0;
+        if (xc - R < 0 || yc - R < 0 || xc + R >= W || yc + R >= H) {
+            flag |= ORC_STAMP_INVALID;
+        } else {
+            for (int y = yc - R; y <= yc + R; y++)
+                for (int x = xc - R; x <= xc + R; x++)
+                    if (M1[y * pitch + x]) flag |= ORC_STAMP_INVALID;
+            for (int y = yc - r; y <= yc + r; y++)
+                for (int x = xc - r; x <= xc + r; x++)
+                    if (M2[y * pitch + x]) flag |= ORC_STAMP_INVALID;
+            if (!flag) {
+                for (int y = yc - R; y <= yc + R; y++)
+                    for (int x = xc - R; x <= xc + R; x++)
+                        if (!isfinite(I1[y * pitch + x])) flag |= ORC_STAMP_NONFINITE;
+                for (int y = yc - r; y <= yc + r; y++)
+                    for (int x = xc - r; x <= xc + r; x++) {
+                        const float v2 = V2[y * pitch + x];
+                        if (!isfinite(I2[y * pitch + x]) || !isfinite(v2) || !(v2 > 0.0f))
+                            flag |= ORC_STAMP_NONFINITE;
+                    }
+            }
+        }
+        flags[s] = flag;
+        if (flag) continue;
+        double* A = (double*)malloc(sizeof(double) * L);
+        double* win = (double*)malloc(sizeof(double) * T);
+        for (int y = yc - r; y <= yc + r; y++) {
+            for (int x = xc - r; x <= xc + r; x++) {
+                for (int v = -h; v <= h; v++)
+                    for (int u = -h; u <= h; u++)
+                        win[(v + h) * K + (u + h)] = I1[(int64_t)(y - v) * pitch + (x - u)];
+                for (int i = 0; i < nb; i++) {
+                    const double* ki = kb + (size_t)i * T;
+                    double acc = 0.0;
+                    for (int t = 0; t < T; t++) acc += ki[t] * win[t];
+                    A[i] = acc;
+                }
+                A[nb] = 1.0;
+                const double w = 1.0 / (double)V2[y * pitch + x];
+                const double d = (double)I2[y * pitch + x];
+                for (int i = 0; i < L; i++) {
+                    for (int j = 0; j < L; j++) M[i * L + j] += w * A[i] * A[j];
+                    b[i] += w * A[i] * d;
+                }
+                es[s] += w * d * d;
+            }
+        }
+        npix[s] = (2 * r + 1) * (2 * r + 1);
+        free(A);
+        free(win);
+    }
+}
+
+/*
+ * Assembly of the full normal equations from the per-stamp sums, with the
+ * spatial terms evaluated at the stamp centres (Section 2):
+ *     M[(i,s),(j,t)] = sum_stamps g_s g_t M_s[i][j]
+ *     M[(i,s),bg]    = sum_stamps g_s M_s[i][nb]
+ *     M[bg,bg]       = sum_stamps M_s[nb][nb]
+ * and likewise for the right-hand side.  Only stamps with used[s] != 0 count.
+ */
+void orc_assemble(const orc_config* c, int W, int H, const int32_t* xy, int n, const double* Ms,
+                  const double* bs, const uint8_t* used, double* M, double* b) {
+    const int nb = orc_n_basis(c), ns = orc_n_spatial(c), N = nb * ns + 1, L = nb + 1;
+    double g[64];
+    memset(M, 0, sizeof(double) * N * N);
+    memset(b, 0, sizeof(double) * N);
+    for (int s = 0; s < n; s++) {
+        if (!used[s]) continue;
+        orc_spatial(c->S, xy[2 * s], xy[2 * s + 1], W, H, g);
+        const double* Mss = Ms + (size_t)s * L * L;
+        const double* bss = bs + (size_t)s * L;
+        for (int i = 0; i < nb; i++)
+            for (int sa = 0; sa < ns; sa++) {
+                const int row = i * ns + sa;
+                for (int j = 0; j < nb; j++)
+                    for (int t = 0; t < ns; t++)
+                        M[(size_t)row * N + j * ns + t] += g[sa] * g[t] * Mss[i * L + j];
+                M[(size_t)row * N + N - 1] += g[sa] * Mss[i * L + nb];
+                M[(size_t)(N - 1) * N + row] += g[sa] * Mss[nb * L + i];
+                b[row] += g[sa] * bss[i];
+            }
+        M[(size_t)(N - 1) * N + N - 1] += Mss[nb * L + nb];
+        b[N - 1] += bss[nb];
+    }
+}
+
+/*
+ * Solution of M a = b "by regular matrix methods" (Section 2): symmetric
+ * equilibration D = diag(M)^(-1/2), Cholesky factorisation of D M D, forward
+ * and back substitution, a = D y.  Returns 0, or k > 0 when the k-th pivot
+ * (1-based) is not positive.
+ */
+int orc_cholesky_solve(int N, const double* M, const double* b, double* a) {
+    double* D = (double*)malloc(sizeof(double) * N);
+    double* Lm = (double*)malloc(sizeof(double) * (size_t)N * N);
+    double* y = (double*)malloc(sizeof(double) * N);
+    int info = 0;
+    for (int i = 0; i < N; i++) {
+        if (!(M[(size_t)i * N + i] > 0.0)) { info = i + 1; goto done; }
+        D[i] = 1.0 / sqrt(M[(size_t)i * N + i]);
+    }
+    for (int i = 0; i < N; i++)
+        for (int j = 0; j < N; j++) Lm[(size_t)i * N + j] = D[i] * M[(size_t)i * N + j] * D[j];
+    for (int k = 0; k < N; k++) {
+        double s = Lm[(size_t)k * N + k];
+        for (int p = 0; p < k; p++) s -= Lm[(size_t)k * N + p] * Lm[(size_t)k * N + p];
+        if (!(s > 0.0)) { info = k + 1; goto done; }
+        const double lkk = sqrt(s);
+        Lm[(size_t)k * N + k] = lkk;
+        for (int i = k + 1; i < N; i++) {
+            double t = Lm[(size_t)i * N + k];
+            for (int p = 0; p < k; p++) t -= Lm[(size_t)i * N + p] * Lm[(size_t)k * N + p];
+            Lm[(size_t)i * N + k] = t / lkk;
+        }
+    }
+    for (int i = 0; i < N; i++) {          /* L z = D b */
+        double t = D[i] * b[i];
+        for (int p = 0; p < i; p++) t -= Lm[(size_t)i * N + p] * y[p];
+        y[i] = t / Lm[(size_t)i * N + i];
+    }
+    for (int i = N - 1; i >= 0; i--) {     /* L^T y = z */
+        double t = y[i];
+        for (int p = i + 1; p < N; p++) t -= Lm[(size_t)p * N + i] * y[p];
+        y[i] = t / Lm[(size_t)i * N + i];
+    }
+    for (int i = 0; i < N; i++) a[i] = D[i] * y[i];
+done:
+    free(D);
+    free(Lm);
+    free(y);
+    return info;
+}
+
+/*
+ * Residual chi^2 of one stamp for a solution a, from its sums:
+ *     chi2_s = e_s - 2 alpha^T b_s + alpha^T M_s alpha,
+ * alpha the local coefficients at the stamp centre (kernel terms and
+ * background).  This equals sum w (A alpha - d)^2 over the stamp pixels.
+ */
+double orc_stamp_chi2(const orc_config* c, const double* a, int W, int H, int xc, int yc,
+                      const double* Mss, const double* bss, double es) {
+    const int nb = orc_n_basis(c), L = nb + 1;
+    double alpha[512];
+    orc_local_coeffs(c, a, xc, yc, W, H, alpha);
+    double q = 0.0, lin = 0.0;
+    for (int i = 0; i < L; i++) {
+        double t = 0.0;
+        for (int j = 0; j < L; j++) t += Mss[i * L + j] * alpha[j];
+        q += alpha[i] * t;
+        lin += alpha[i] * bss[i];
+    }
+    return es - 2.0 * lin + q;
+}
+
+/*
+ * Solution with rejection of discrepant stamps (Sections 3.3, 3.5, 3.6).
+ * Readings: the per-stamp statistic is q_s = chi2_s / npix_s (the mean
+ * squared normalised residual, with no flux softening); after each solution
+ * the used stamps with q_s > mean + clip_sigma * std (population standard
+ * deviation over the used stamps) are rejected and the equations are
+ * re-assembled and re-solved, up to max_iter solutions or until nothing
+ * changes.  Rejected stamps are not replaced.  A clip that would leave fewer
+ * than min_stamps stamps is not applied.  Stamps flagged on input (any bit)
+ * are not used.  Returns 0, -3 (fewer than min_stamps usable stamps) or -4
+ * (matrix not positive definite; stats->info holds the pivot).
+ * Output flags gain ORC_STAMP_REJECTED for rejected stamps; chi2[s] holds
+ * the residual of every unflagged-on-input stamp under the final solution
+ * (0 for the others).
+ */
+int orc_solve(const orc_config* c, int W, int H, const int32_t* xy, int n, const double* Ms,
+              const double* bs, const double* es, const int32_t* npix, int32_t* flags,
+              double* coeffs, double* chi2, orc_stats* st) {
+    const int nb = orc_n_basis(c), ns = orc_n_spatial(c), N = nb * ns + 1, L = nb + 1;
+    uint8_t* used = (uint8_t*)calloc(n > 0 ? n : 1, 1);
+    uint8_t* fitted = (uint8_t*)calloc(n > 0 ? n : 1, 1);
+    double* M = (double*)malloc(sizeof(double) * (size_t)N * N);
+    double* b = (double*)malloc(sizeof(double) * N);
+    int ret = 0, iter = 0, n_rej = 0;
+    memset(st, 0, sizeof(*st));
+    for (int s = 0; s < n; s++) {
+        used[s] = flags[s] == 0;
+        fitted[s] = used[s];
+        chi2[s] = 0.0;
+    }
+    for (int i = 0; i < N; i++) coeffs[i] = 0.0;
+    for (;;) {
+        int n_used = 0;
+        for (int s = 0; s < n; s++) n_used += used[s];
+        if (n_used < c->min_stamps) { ret = -3; st->info = -3; break; }
+        orc_assemble(c, W, H, xy, n, Ms, bs, used, M, b);
+        int info = orc_cholesky_solve(N, M, b, coeffs);
+        if (info) { ret = -4; st->info = info; break; }
+        iter++;
+        for (int s = 0; s < n; s++)
+            chi2[s] = fitted[s] ? orc_stamp_chi2(c, coeffs, W, H, xy[2 * s], xy[2 * s + 1],
+                                                  Ms + (size_t)s * L * L, bs + (size_t)s * L, es[s])
+                                : 0.0;
+        if (iter >= c->max_iter) break;
+        double mean = 0.0, var = 0.0;
+        for (int s = 0; s < n; s++)
+            if (used[s]) mean += chi2[s] / npix[s];
+        mean /= n_used;
+        for (int s = 0; s < n; s++)
+            if (used[s]) {
+                const double dq = chi2[s] / npix[s] - mean;
+                var += dq * dq;
+            }
+        const double thr = mean + c->clip_sigma * sqrt(var / n_used);
+        int n_new = 0;
+        for (int s = 0; s < n; s++)
+            if (used[s] && chi2[s] / npix[s] > thr) n_new++;
+        if (n_new == 0 || n_used - n_new < c->min_stamps) break;
+        for (int s = 0; s < n; s++)
+            if (used[s] && chi2[s] / npix[s] > thr) {
+                used[s] = 0;
+                flags[s] |= ORC_STAMP_REJECTED;
+                n_rej++;
+            }
+    }
+    st->n_iter = iter;
+    st->n_rejected = n_rej;
+    if (ret == 0) {
+        double c2 = 0.0, np = 0.0;
+        int nu = 0;
+        for (int s = 0; s < n; s++)
+            if (used[s]) { c2 += chi2[s]; np += npix[s]; nu++; }
+        st->chi2 = c2;
+        st->dof = np - N;
+        st->chi2_dof = c2 / (np - N);
+        st->n_used = nu;
+        double alpha[512];
+        orc_local_coeffs(c, coeffs, 0.5 * (W - 1), 0.5 * (H - 1), W, H, alpha);
+        st->kernel_sum_centre = alpha[0];   /* the other terms sum to zero */
+    }
+    free(used);
+    free(fitted);
+    free(M);
+    free(b);
+    return ret;
+}
+
+/*
+ * BAD/POOR radius (Section 3.4).  Reading: the smallest box radius r in
+ * [0, h] such that the kernel's squared weight outside the box
+ * max(|u|,|v|) <= r is below bad_frac of the total; h if none is.
+ */
+int orc_bad_radius(const double* K, int h, double frac) {
+    const int Kw = 2 * h + 1;
+    double tot = 0.0;
+    for (int t = 0; t < Kw * Kw; t++) tot += K[t] * K[t];
+    for (int r = 0; r <= h; r++) {
+        double out = 0.0;
+        for (int v = -h; v <= h; v++)
+            for (int u = -h; u <= h; u++)
+                if (abs(u) > r || abs(v) > r) out += K[(v + h) * Kw + (u + h)] * K[(v + h) * Kw + (u + h)];
+        if (out < frac * tot) return r;
+    }
+    return h;
+}
+
+/*
+ * Covariance pseudo-matrix of a kernel (Section 4.2, Eqs. 10-11 applied to a
+ * convolution): the covariance between a pixel and the pixel displaced by
+ * delta, relative to the input variance, is
+ *     raw(delta) = sum_{u,u'} k(u) k(u') C_in(delta + u - u'),
+ * for |delta| <= 2h + c_in (per axis), an array of side 4h + 2c_in + 1.
+ * cov_in is (2c_in+1)^2 with its centre at zero offset; NULL means the
+ * uncorrelated input (a single unit centre value).
+ */
+void orc_cov_raw(const double* K, int h, const double* cov_in, int c_in, double* raw) {
+    const int Kw = 2 * h + 1, Cw = 2 * c_in + 1, R = 2 * h + c_in, Rw = 2 * R + 1;
+    for (int dy = -R; dy <= R; dy++)
+        for (int dx = -R; dx <= R; dx++) {
+            double s = 0.0;
+            for (int v = -h; v <= h; v++)
+                for (int u = -h; u <= h; u++) {
+                    const double ku = K[(v + h) * Kw + (u + h)];
+                    if (ku == 0.0) continue;
+                    for (int wy = -c_in; wy <= c_in; wy++)
+                        for (int wx = -c_in; wx <= c_in; wx++) {
+                            /* C_in(delta + u - u') is needed at w = delta + u - u' */
+                            const int u2 = dx + u - wx, v2 = dy + v - wy;
+                            if (u2 < -h || u2 > h || v2 < -h || v2 > h) continue;
+                            const double cw = cov_in ? cov_in[(wy + c_in) * Cw + (wx + c_in)]
+                                                     : (wx == 0 && wy == 0 ? 1.0 : 0.0);
+                            s += ku * K[(v2 + h) * Kw + (u2 + h)] * cw;
+                        }
+                }
+            raw[(dy + R) * Rw + (dx + R)] = s;
+        }
+}
+
+/*
+ * Covariance factor of a kernel (Section 4.2): with K = [sum k^2]^-1 absorbed
+ * into the pseudo-matrix, C'(delta) = K raw(delta) and the factor is its
+ * centre value C'(0) = raw(0) / sum k^2.
+ */
+double orc_cov_factor(const double* Kk, int h, const double* cov_in, int c_in) {
+    const int Kw = 2 * h + 1, Cw = 2 * c_in + 1;
+    double s2 = 0.0, raw0 = 0.0;
+    for (int t = 0; t < Kw * Kw; t++) s2 += Kk[t] * Kk[t];
+    for (int v = -h; v <= h; v++)
+        for (int u = -h; u <= h; u++)
+            for (int v2 = -h; v2 <= h; v2++)
+                for (int u2 = -h; u2 <= h; u2++) {
+                    const int wx = u - u2, wy = v - v2;
+                    if (wx < -c_in || wx > c_in || wy < -c_in || wy > c_in) continue;
+                    const double cw = cov_in ? cov_in[(wy + c_in) * Cw + (wx + c_in)]
+                                             : (wx == 0 && wy == 0 ? 1.0 : 0.0);
+                    raw0 += Kk[(v + h) * Kw + (u + h)] * Kk[(v2 + h) * Kw + (u2 + h)] * cw;
+                }
+    return s2 > 0.0 ? raw0 / s2 : 0.0;
+}
+
+/* Patch p of the P x P grid anchored at (0, 0); edge patches are clipped and
+   the kernel is realised at the clipped patch's centre (Section 3.5). */
+static void patch_bounds(int W, int H, int P, int p, int* x0, int* x1, int* y0, int* y1) {
+    const int npx = (W + P - 1) / P;
+    const int px = p % npx, py = p / npx;
+    *x0 = px * P;
+    *x1 = *x0 + P < W ? *x0 + P : W;
+    *y0 = py * P;
+    *y1 = *y0 + P < H ? *y0 + P : H;
+}
+
+int orc_n_patches(const orc_config* c, int W, int H) {
+    return ((W + c->P - 1) / c->P) * ((H + c->P - 1) / c->P);
+}
+
+void orc_patch_kernel(const orc_config* c, const double* kb, const double* a, int W, int H, int p,
+                      double* K) {
+    int x0, x1, y0, y1;
+    patch_bounds(W, H, c->P, p, &x0, &x1, &y0, &y1);
+    orc_kernel_at(c, kb, a, 0.5 * (x0 + x1 - 1), 0.5 * (y0 + y1 - 1), W, H, K);
+}
+
+/*
+ * Image convolution with the spatially varying kernel (Section 4.2, Eq. 12;
+ * Section 3.5): in each patch, I'(x, y) = sum_{u,v} K_p(u, v) I~(x-u, y-v)
+ * where I~ is I inside the image and unmasked, and 0 otherwise (masked pixels
+ * do not contribute, Section 3.4).  Output mask (Section 3.4): CONV_BAD if a
+ * masked or out-of-image input pixel lies within box radius r_bad(p) of the
+ * output pixel, else CONV_POOR if one lies within the kernel's box radius h.
+ */
+void orc_convolve_image(const orc_config* c, const double* kb, const double* a, const float* I,
+                        const uint8_t* Mk, int W, int H, int64_t pitch, float* out,
+                        uint8_t* out_mask) {
+    const int h = c->h, Kw = 2 * h + 1, T = Kw * Kw, np = orc_n_patches(c, W, H);
+#pragma omp parallel for schedule(dynamic)
+    for (int p = 0; p < np; p++) {
+        int x0, x1, y0, y1;
+        double* K = (double*)malloc(sizeof(double) * T);
+        patch_bounds(W, H, c->P, p, &x0, &x1, &y0, &y1);
+        orc_patch_kernel(c, kb, a, W, H, p, K);
+        const int rb = orc_bad_radius(K, h, c->bad_frac);
+        for (int y = y0; y < y1; y++)
+            for (int x = x0; x < x1; x++) {
+                double s = 0.0;
+                int dmin = h + 1;
+                for (int v = -h; v <= h; v++)
+                    for (int u = -h; u <= h; u++) {
+                        const int xx = x - u, yy = y - v;
+                        if (xx >= 0 && xx < W && yy >= 0 && yy < H && !Mk[(int64_t)yy * pitch + xx]) {
+                            s += K[(v + h) * Kw + (u + h)] * (double)I[(int64_t)yy * pitch + xx];
+                        } else {
+                            const int dd = abs(u) > abs(v) ? abs(u) : abs(v);
+                            if (dd < dmin) dmin = dd;
+                        }
+                    }
+                out[(int64_t)y * pitch + x] = (float)s;
+                out_mask[(int64_t)y * pitch + x] =
+                    dmin <= rb ? ORC_MASK_CONV_BAD : (dmin <= h ? ORC_MASK_CONV_POOR : 0);
+            }
+        free(K);
+    }
+}
+
+/*
+ * Variance propagation (Section 4.2, Eq. 13, and Section 4.3):
+ *     V'(x, y) = f_p * sum_{u,v} K_p(u, v)^2 V~(x-u, y-v)
+ * with V~ zero where masked or outside the image and f_p the covariance
+ * factor of the patch kernel, moved into the variance map.
+ * Image pseudo-matrix (Section 4.3): the mean of C' = raw / sum k^2 over the
+ * kernels realised at the centres of a 3 x 3 partition of the image (reading
+ * of "a much smaller array of kernels"), divided by its centre value (the
+ * factor already applied to the variance), then cropped (or zero-padded) to
+ * (2 c_out + 1)^2.  *discarded receives the fraction of sum |C| cut off.
+ */
+void orc_propagate_variance(const orc_config* c, const double* kb, const double* a, const float* V,
+                            const uint8_t* Mk, int W, int H, int64_t pitch, const double* cov_in,
+                            int c_in, float* var_out, double* cov_out, int c_out,
+                            double* discarded) {
+    const int h = c->h, Kw = 2 * h + 1, T = Kw * Kw, np = orc_n_patches(c, W, H);
+#pragma omp parallel for schedule(dynamic)
+    for (int p = 0; p < np; p++) {
+        int x0, x1, y0, y1;
+        double* K = (double*)malloc(sizeof(double) * T);
+        patch_bounds(W, H, c->P, p, &x0, &x1, &y0, &y1);
+        orc_patch_kernel(c, kb, a, W, H, p, K);
+        const double f = orc_cov_factor(K, h, cov_in, c_in);
+        for (int y = y0; y < y1; y++)
+            for (int x = x0; x < x1; x++) {
+                double s = 0.0;
+                for (int v = -h; v <= h; v++)
+                    for (int u = -h; u <= h; u++) {
+                        const int xx = x - u, yy = y - v;
+                        if (xx >= 0 && xx < W && yy >= 0 && yy < H && !Mk[(int64_t)yy * pitch + xx]) {
+                            const double kk = K[(v + h) * Kw + (u + h)];
+                            s += kk * kk * (double)V[(int64_t)yy * pitch + xx];
+                        }
+                    }
+                var_out[(int64_t)y * pitch + x] = (float)(f * s);
+            }
+        free(K);
+    }
+    /* pseudo-matrix from a 3 x 3 sample of kernels */
+    const int R = 2 * h + c_in, Rw = 2 * R + 1, Ow = 2 * c_out + 1;
+    double* avg = (double*)calloc((size_t)Rw * Rw, sizeof(double));
+    double* raw = (double*)malloc(sizeof(double) * Rw * Rw);
+    double* K = (double*)malloc(sizeof(double) * T);
+    for (int jy = 0; jy < 3; jy++)
+        for (int jx = 0; jx < 3; jx++) {
+            const int cx0 = jx * W / 3, cx1 = (jx + 1) * W / 3;
+            const int cy0 = jy * H / 3, cy1 = (jy + 1) * H / 3;
+            orc_kernel_at(c, kb, a, 0.5 * (cx0 + cx1 - 1), 0.5 * (cy0 + cy1 - 1), W, H, K);
+            double s2 = 0.0;
+            for (int t = 0; t < T; t++) s2 += K[t] * K[t];
+            orc_cov_raw(K, h, cov_in, c_in, raw);
+            for (int t = 0; t < Rw * Rw; t++) avg[t] += (s2 > 0.0 ? raw[t] / s2 : 0.0) / 9.0;
+        }
+    const double centre = avg[R * Rw + R];
+    double tot = 0.0, kept = 0.0;
+    for (int t = 0; t < Rw * Rw; t++) {
+        avg[t] = centre != 0.0 ? avg[t] / centre : 0.0;
+        tot += fabs(avg[t]);
+    }
+    for (int dy = -c_out; dy <= c_out; dy++)
+        for (int dx = -c_out; dx <= c_out; dx++) {
+            double val = 0.0;
+            if (dx >= -R && dx <= R && dy >= -R && dy <= R) val = avg[(dy + R) * Rw + (dx + R)];
+            cov_out[(dy + c_out) * Ow + (dx + c_out)] = val;
+            kept += fabs(val);
+        }
+    if (discarded) *discarded = tot > 0.0 ? (tot - kept) / tot : 0.0;
+    free(avg);
+    free(raw);
+    free(K);
+}
+
+/*
+ * Difference image (Section 2 sign convention read as science minus model,
+ * so new flux is positive; Section 4.3 for the noise):
+ *     D = I2 - I1' - d0,  V_D = V2 + V1',
+ *     mask_D = (M2 != 0 ? BAD : 0) | mask1';
+ * at pixels masked in image 2 the difference and its variance are set to 0.
+ * The pseudo-matrices are averaged with weights equal to the mean variance
+ * of each input over its unmasked pixels (mask 0):
+ *     C_D = (v2 C2 + v1' C1') / (v2 + v1'),
+ * each zero-padded or cropped to (2 c_d + 1)^2; cov2 NULL is the
+ * uncorrelated (unit centre) pseudo-matrix.
+ */
+void orc_subtract(const orc_config* c, const double* a, const float* I2, const float* V2,
+                  const uint8_t* M2, const float* conv, const float* conv_var,
+                  const uint8_t* conv_mask, int W, int H, int64_t pitch, const double* cov2,
+                  int c2, const double* cov_conv, int cc, float* diff, float* diff_var,
+                  uint8_t* diff_mask, double* cov_diff, int cd) {
+    const int N = orc_n_unknowns(c);
+    const double d0 = a[N - 1];
+    double s2 = 0.0, sc = 0.0;
+    long n2 = 0, nc = 0;
+    for (int y = 0; y < H; y++)
+        for (int x = 0; x < W; x++) {
+            const int64_t o = (int64_t)y * pitch + x;
+            if (M2[o]) {
+                diff[o] = 0.0f;
+                diff_var[o] = 0.0f;
+                diff_mask[o] = ORC_MASK_BAD | conv_mask[o];
+            } else {
+                diff[o] = (float)((double)I2[o] - (double)conv[o] - d0);
+                diff_var[o] = (float)((double)V2[o] + (double)conv_var[o]);
+                diff_mask[o] = conv_mask[o];
+                s2 += V2[o];
+                n2++;
+            }
+            if (!conv_mask[o]) {
+                sc += conv_var[o];
+                nc++;
+            }
+        }
+    const double v2 = n2 ? s2 / n2 : 0.0, vc = nc ? sc / nc : 0.0;
+    const int Dw = 2 * cd + 1;
+    for (int dy = -cd; dy <= cd; dy++)
+        for (int dx = -cd; dx <= cd; dx++) {
+            double a2 = 0.0, ac = 0.0;
+            if (cov2) {
+                if (abs(dx) <= c2 && abs(dy) <= c2) a2 = cov2[(dy + c2) * (2 * c2 + 1) + (dx + c2)];
+            } else {
+                a2 = (dx == 0 && dy == 0) ? 1.0 : 0.0;
+            }
+            if (abs(dx) <= cc && abs(dy) <= cc) ac = cov_conv[(dy + cc) * (2 * cc + 1) + (dx + cc)];
+            cov_diff[(dy + cd) * Dw + (dx + cd)] = (v2 + vc) > 0.0 ? (v2 * a2 + vc * ac) / (v2 + vc) : 0.0;
+        }
+}
