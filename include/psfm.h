@@ -1,0 +1,255 @@
+/*
+ * psfm.h -- C interface of the MI355X (gfx950) PSF-matching library.
+ *
+ * The library computes the data-parallel hot path of Alard-Lupton-style PSF
+ * matching as formulated by Price & Magnier, "Pan-STARRS PSF-Matching for
+ * Subtraction and Stacking":
+ *   1. convolve reference-image stamps with every kernel basis function and
+ *      accumulate the variance-weighted normal equations of each stamp
+ *      (psfm_fit_stamps; Section 2, Eqs. 3-6),
+ *   2. assemble the equations with the spatial polynomial terms evaluated at
+ *      the stamp centres, solve them, reject discrepant stamps and re-solve
+ *      (psfm_solve; Section 2 and Sections 3.3, 3.5, 3.6),
+ *   3. apply the spatially varying kernel to the whole image in constant-
+ *      kernel patches, with BAD/POOR mask propagation (psfm_convolve_image;
+ *      Sections 3.4, 3.5, Section 4.2 Eq. 12),
+ *   4. propagate the variance map and the covariance pseudo-matrix
+ *      (psfm_propagate_variance; Section 4.2 Eq. 13, Sections 4.2-4.3),
+ *   5. form the difference image with its variance, mask and pseudo-matrix
+ *      (psfm_subtract; Section 4.3).
+ *
+ * Conventions shared by every call
+ *   - Images are row-major float32: pixel (x, y) of a W x H image is element
+ *     y * pitch + x (pitch >= W, in elements).  Masks are uint8 planes with
+ *     the same pitch (in bytes); a non-zero input mask value means "masked".
+ *   - Every pixel, stamp, matrix and coefficient pointer is a DEVICE pointer
+ *     owned by the caller; the library never allocates, frees or retains them.
+ *     psfm_fit_stats pointers are device pointers as well.
+ *   - Every call is asynchronous and ordered on `stream` (a hipStream_t; NULL
+ *     is the default stream).  Host-detectable argument errors are returned
+ *     before anything is launched.  Numerical failures found on the device
+ *     (too few stamps, a matrix that is not positive definite) are written to
+ *     psfm_fit_stats.info; the call itself still returns PSFM_OK.
+ *   - Calls allocate nothing: scratch memory is the caller's workspace `ws`
+ *     (device memory of at least psfm_workspace_bytes() bytes, 256-byte
+ *     aligned).  Concurrent calls need separate workspaces.  A context is
+ *     read-only after psfm_create and may be shared by concurrent calls.
+ *   - Masked pixels, and pixels outside the image, never contribute a value
+ *     (not even a NaN) to a convolution.
+ *
+ * Unknowns.  With nb kernel basis terms and ns = (S+1)(S+2)/2 spatial terms
+ * the coefficient vector has N = nb * ns + 1 float64 entries: kernel term i
+ * with spatial term s at index i * ns + s, the constant background last.
+ * Term 0 carries the flux (unit sum); every other term sums to zero, so the
+ * kernel sum at a point is the local coefficient of term 0 there.
+ */
+#ifndef PSFM_H
+#define PSFM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PSFM_MAX_GAUSS 8
+
+/* Return codes. */
+typedef enum {
+    PSFM_OK = 0,
+    PSFM_ERR_INVALID_ARG = -1,   /* NULL pointer, negative size, bad config value */
+    PSFM_ERR_SHAPE = -2,         /* image too small for the kernel, pitch < W, ... */
+    PSFM_ERR_TOO_FEW_STAMPS = -3,/* (device, in stats.info) fewer than min_stamps usable */
+    PSFM_ERR_NOT_PD = -4,        /* (device) normal matrix not positive definite */
+    PSFM_ERR_HIP = -5,           /* a HIP runtime call failed */
+    PSFM_ERR_WORKSPACE = -6,     /* workspace missing or smaller than required */
+    PSFM_ERR_UNSUPPORTED = -7    /* configuration outside what the kernels support */
+} psfm_status;
+
+/* Stamp flag bits (stamp_flags). */
+#define PSFM_STAMP_INVALID   1   /* footprint leaves the image or touches a masked pixel */
+#define PSFM_STAMP_REJECTED  2   /* removed by the rejection iterations of psfm_solve */
+#define PSFM_STAMP_NONFINITE 4   /* non-finite pixel, or variance not finite and > 0 */
+#define PSFM_STAMP_EXCLUDED  8   /* excluded by the caller before psfm_solve */
+
+/* Output mask bits. */
+#define PSFM_MASK_BAD       1    /* masked in the input (difference image: image 2) */
+#define PSFM_MASK_CONV_BAD  2    /* masked input within the BAD radius of the kernel */
+#define PSFM_MASK_CONV_POOR 4    /* masked input within the kernel footprint only */
+
+/* Arithmetic of the stamp fit. */
+#define PSFM_PREC_FP32 0         /* FP32 basis convolution, FP32-MFMA Gram */
+#define PSFM_PREC_BF16 1         /* reserved: BF16 MFMA Gram */
+#define PSFM_PREC_FP16 2         /* reserved: FP16 MFMA Gram */
+
+/*
+ * Method parameters.
+ *   Kernel basis (Section 2, Eq. 7; Section 3.1): n_gauss Gaussians of width
+ *   sigma[j] (pixels) times the monomials u^p v^q with p + q <= degree[j];
+ *   terms are ordered by Gaussian, then total degree d, then p from d down
+ *   to 0.  Term 0 (the narrowest Gaussian, unit sum) carries the flux; the
+ *   other terms are made zero-sum (Section 2): even terms as
+ *   raw/sum(raw) - k_0, odd terms as raw/sum(|raw|).
+ *   The kernel is (2 half_width + 1)^2 pixels.
+ *   Spatial variation (Section 2): ordinary polynomials x^l y^m, l + m <=
+ *   spatial_order, in coordinates scaled to [-1, 1] over the image, ordered by
+ *   degree then l descending; evaluated at stamp centres for the fit and at
+ *   patch centres for the application.
+ *   Stamps are (2 stamp_half + 1)^2 pixels; the weights are 1 / V2.
+ *   Rejection (Sections 3.3, 3.6): after each solution the used stamps with
+ *   chi2_s / npix_s > mean + clip_sigma * std (population, over used stamps)
+ *   are rejected and the equations re-solved, at most max_iter solutions; a
+ *   clip that would leave fewer than min_stamps stamps is not applied.
+ *   Application (Section 3.5): constant kernels on patch x patch squares
+ *   anchored at (0, 0), realised at each (clipped) patch centre.
+ *   BAD/POOR (Section 3.4): the BAD box radius is the smallest r with
+ *   sum_{max(|u|,|v|) > r} k^2 < bad_frac * sum k^2.
+ */
+typedef struct psfm_config {
+    int n_gauss;
+    double sigma[PSFM_MAX_GAUSS];
+    int degree[PSFM_MAX_GAUSS];
+    int half_width;        /* h: kernel taps u, v in [-h, h]; 1 <= h <= 16 */
+    int spatial_order;     /* S: 0..6 */
+    int stamp_half;        /* r: stamp is (2r+1)^2; 1 <= r <= 32 */
+    int patch;             /* P: side of the constant-kernel patches, >= 1 */
+    double clip_sigma;     /* rejection threshold (default 3) */
+    int max_iter;          /* maximum number of solutions (default 3) */
+    int min_stamps;        /* minimum usable stamps (default 3) */
+    double bad_frac;       /* BAD/POOR fraction (default 0.2) */
+    int precision;         /* PSFM_PREC_* */
+    int reserved;
+} psfm_config;
+
+/* Quality record of a fit (device memory, written by the library). */
+typedef struct psfm_fit_stats {
+    double chi2;               /* sum of chi2_s over used stamps */
+    double dof;                /* sum of npix_s over used stamps - N */
+    double chi2_dof;           /* chi2 / dof */
+    double kernel_sum_centre;  /* kernel sum realised at the image centre */
+    double cov_discarded_frac; /* share of sum|C| cut off by the pseudo-matrix crop */
+    int n_used;                /* stamps in the final solution */
+    int n_rejected;            /* stamps rejected by this solve */
+    int n_iter;                /* solutions computed */
+    int info;                  /* 0 ok; k > 0: pivot k not positive; -3: too few stamps */
+} psfm_fit_stats;
+
+typedef struct psfm_context psfm_context;
+
+/* Fills *cfg with the defaults: 3 Gaussians (0.7, 1.5, 3.0 px) x degrees
+   (6, 4, 2) = 49 terms, h = 10, S = 0, r = 20, P = 64, clip 3, 3 solutions,
+   3 stamps, bad_frac 0.2, FP32. */
+void psfm_config_default(psfm_config* cfg);
+
+/* Validates cfg, builds the basis tables (FP64 on the host) and uploads them
+   to the current HIP device.  *out receives a context the caller destroys
+   with psfm_destroy.  This is the only call that allocates device memory. */
+int psfm_create(const psfm_config* cfg, psfm_context** out);
+int psfm_destroy(psfm_context* ctx);
+
+int psfm_n_basis(const psfm_context* ctx);      /* nb */
+int psfm_n_spatial(const psfm_context* ctx);    /* ns */
+int psfm_n_unknowns(const psfm_context* ctx);   /* N = nb * ns + 1 */
+int psfm_stamp_dim(const psfm_context* ctx);    /* L = nb + 1: per-stamp matrix side */
+
+/* Bytes of workspace that every call below needs for a W x H image and
+   n_stamps stamps (the maximum over the calls); 0 on invalid arguments. */
+size_t psfm_workspace_bytes(const psfm_context* ctx, int W, int H, int n_stamps);
+
+/*
+ * Per-stamp normal equations (Section 2, Eqs. 3-6 with c = 0, p = 0).
+ * For stamp s centred on (x, y) = stamp_xy[2s], stamp_xy[2s+1] and every
+ * pixel of its (2r+1)^2 square: A_i = k_i (x) I1 (true convolution, Eq. 12),
+ * A_nb = 1 (background), w = 1 / V2, d = I2;
+ *   stamp_M[s] = sum w A A^T   (L x L, row-major, symmetric),
+ *   stamp_b[s] = sum w A d     (L),   stamp_e[s] = sum w d^2,
+ *   stamp_npix[s] = (2r+1)^2,  stamp_flags[s] = 0,
+ * or, for a stamp failing the validity test of Section 3.3 (footprint
+ * [x-r-h, x+r+h]^2 outside the image or masked in M1; stamp masked in M2;
+ * non-finite or non-positive data), the flag bits and zero sums.
+ * Arithmetic: FP32 separable basis convolution, FP32 MFMA Gram, per-band
+ * partial sums added in FP64.  Inputs: I1, M1 (convolved image), I2, V2, M2
+ * (target), all W x H with `pitch`.  Outputs are float64/int32 device arrays
+ * of n_stamps entries (stamp_M n*L*L, stamp_b n*L).
+ */
+int psfm_fit_stamps(const psfm_context* ctx, const float* I1, const uint8_t* M1, const float* I2,
+                    const float* V2, const uint8_t* M2, int W, int H, int64_t pitch,
+                    const int32_t* stamp_xy, int n_stamps, double* stamp_M, double* stamp_b,
+                    double* stamp_e, int32_t* stamp_npix, int32_t* stamp_flags, void* ws,
+                    size_t ws_bytes, void* stream);
+
+/*
+ * Assembly, solution and rejection (Section 2; Sections 3.3, 3.5, 3.6).
+ * Stamps with any stamp_flags bit set on entry are not used.  The equations
+ *   M[(i,s),(j,t)] = sum_used g_s(c) g_t(c) M_s[i][j], background last,
+ * are solved in FP64 (equilibrated Cholesky); each solution is followed by
+ * the per-stamp residual chi2_s = e_s - 2 alpha^T b_s + alpha^T M_s alpha
+ * (alpha: local coefficients at the stamp centre) and the sigma-clip.
+ * Outputs: coeffs (N float64), stamp_chi2 (n float64, 0 for stamps flagged on
+ * entry), stamp_flags gains PSFM_STAMP_REJECTED, *stats (device).  On a
+ * device-detected failure stats->info is set (-3 or the failing pivot) and
+ * coeffs hold zeros.
+ */
+int psfm_solve(const psfm_context* ctx, int W, int H, const int32_t* stamp_xy, int n_stamps,
+               const double* stamp_M, const double* stamp_b, const double* stamp_e,
+               const int32_t* stamp_npix, int32_t* stamp_flags, double* coeffs,
+               double* stamp_chi2, psfm_fit_stats* stats, void* ws, size_t ws_bytes,
+               void* stream);
+
+/*
+ * Image convolution with the spatially varying kernel (Section 4.2, Eq. 12;
+ * Section 3.5) and BAD/POOR masking (Section 3.4):
+ *   out(x, y) = sum_{u,v} K_p(u, v) I~(x - u, y - v),  p the patch of (x, y),
+ * with I~ = I where inside the image and M == 0, else 0; out_mask(x, y) is
+ * PSFM_MASK_CONV_BAD if a masked or outside input lies within the BAD box
+ * radius of K_p, else PSFM_MASK_CONV_POOR if one lies within h, else 0.
+ * coeffs: N float64 (device).  out, out_mask: W x H with `pitch`.
+ */
+int psfm_convolve_image(const psfm_context* ctx, const double* coeffs, const float* I,
+                        const uint8_t* M, int W, int H, int64_t pitch, float* out,
+                        uint8_t* out_mask, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Variance and covariance propagation (Section 4.2, Eq. 13 and the
+ * covariance factor; Section 4.3):
+ *   var_out(x, y) = f_p * sum_{u,v} K_p(u, v)^2 V~(x - u, y - v),
+ * f_p = raw_p(0) / sum K_p^2 the covariance factor of the patch kernel, with
+ *   raw(delta) = sum_{u,u'} K(u) K(u') C_in(delta + u - u').
+ * cov_out ((2 cov_out_half + 1)^2 float64, centre = zero offset) is the mean
+ * of raw / sum K^2 over the kernels realised at the centres of a 3 x 3
+ * partition of the image, divided by its centre value, cropped or
+ * zero-padded.  cov_in ((2 cov_in_half + 1)^2 float64) may be NULL: the
+ * uncorrelated input.  If stats is not NULL, stats->cov_discarded_frac
+ * receives the share of sum|C| cut off by the crop.
+ */
+int psfm_propagate_variance(const psfm_context* ctx, const double* coeffs, const float* V,
+                            const uint8_t* M, int W, int H, int64_t pitch, const double* cov_in,
+                            int cov_in_half, float* var_out, double* cov_out, int cov_out_half,
+                            psfm_fit_stats* stats, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Difference image (Section 4.3; sign: science minus matched reference):
+ *   diff = I2 - conv - d0, diff_var = V2 + conv_var,
+ *   diff_mask = (M2 != 0 ? PSFM_MASK_BAD : 0) | conv_mask,
+ * with diff = diff_var = 0 where M2 != 0; d0 = coeffs[N-1] the background.
+ * cov_diff ((2 cov_diff_half + 1)^2 float64) = (v2 C2 + vc Cc) / (v2 + vc),
+ * v2 and vc the mean of V2 over M2 == 0 and of conv_var over conv_mask == 0;
+ * cov2 NULL is the uncorrelated pseudo-matrix; inputs are zero-padded or
+ * cropped to the output size.
+ */
+int psfm_subtract(const psfm_context* ctx, const double* coeffs, const float* I2, const float* V2,
+                  const uint8_t* M2, const float* conv, const float* conv_var,
+                  const uint8_t* conv_mask, int W, int H, int64_t pitch, const double* cov2,
+                  int cov2_half, const double* cov_conv, int cov_conv_half, float* diff,
+                  float* diff_var, uint8_t* diff_mask, double* cov_diff, int cov_diff_half,
+                  void* ws, size_t ws_bytes, void* stream);
+
+/* Human-readable text of a psfm_status value (static storage). */
+const char* psfm_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSFM_H */

@@ -426,6 +426,8 @@ int orc_solve(const orc_config* c, int W, int H, const int32_t* xy, int n, const
     }
     st->n_iter = iter;
     st->n_rejected = n_rej;
+    if (ret != 0)
+        for (int i = 0; i < N; i++) coeffs[i] = 0.0;   /* no solution on failure */
     if (ret == 0) {
         double c2 = 0.0, np = 0.0;
         int nu = 0;

@@ -1,0 +1,225 @@
+// Context creation: configuration checks and the kernel-basis tables.
+//
+// The basis (Section 2, Eq. 7 with the zero-sum requirement; Section 3.1) is
+// evaluated once on the host in FP64 and uploaded:
+//   * full taps k_i(u, v) in FP64, used to realise per-patch kernels;
+//   * the separable factors of each raw term,
+//       raw_i(u, v) = f_{j,p}(u) f_{j,q}(v),  f_{j,e}(t) = t^e exp(-t^2 / 2 sigma_j^2),
+//     in FP32 with the per-term normalisation psi_i and a flag z_i saying
+//     whether k_0 is subtracted, so that the stamp fit can form
+//       k_i (x) I = psi_i [f_{j,p} (x)_x (f_{j,q} (x)_y I)] - z_i (k_0 (x) I)
+//     with two 1-D passes instead of a 2-D one.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+namespace psfm {
+
+int check_hip(hipError_t e) {
+    (void)e;
+    return PSFM_ERR_HIP;
+}
+
+int fit_bands(const psfm_context* ctx) { return (2 * ctx->r + 1 + PSFM_FIT_BR - 1) / PSFM_FIT_BR; }
+
+int n_patches(const psfm_context* ctx, int W, int H) {
+    const int P = ctx->cfg.patch;
+    return ((W + P - 1) / P) * ((H + P - 1) / P);
+}
+
+}  // namespace psfm
+
+extern "C" {
+
+void psfm_config_default(psfm_config* cfg) {
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->n_gauss = 3;
+    cfg->sigma[0] = 0.7;
+    cfg->sigma[1] = 1.5;
+    cfg->sigma[2] = 3.0;
+    cfg->degree[0] = 6;
+    cfg->degree[1] = 4;
+    cfg->degree[2] = 2;
+    cfg->half_width = 10;
+    cfg->spatial_order = 0;
+    cfg->stamp_half = 20;
+    cfg->patch = 64;
+    cfg->clip_sigma = 3.0;
+    cfg->max_iter = 3;
+    cfg->min_stamps = 3;
+    cfg->bad_frac = 0.2;
+    cfg->precision = PSFM_PREC_FP32;
+}
+
+static double ipow(double x, int n) {
+    double r = 1.0;
+    for (int k = 0; k < n; k++) r *= x;
+    return r;
+}
+
+int psfm_create(const psfm_config* cfg, psfm_context** out) {
+    if (!cfg || !out) return PSFM_ERR_INVALID_ARG;
+    *out = nullptr;
+    const psfm_config& c = *cfg;
+    if (c.n_gauss < 1 || c.n_gauss > PSFM_MAX_GAUSS) return PSFM_ERR_INVALID_ARG;
+    int nb = 0, nf = 0;
+    for (int j = 0; j < c.n_gauss; j++) {
+        if (!(c.sigma[j] > 0.0) || c.degree[j] < 0 || c.degree[j] > 12) return PSFM_ERR_INVALID_ARG;
+        nb += (c.degree[j] + 1) * (c.degree[j] + 2) / 2;
+        nf += c.degree[j] + 1;
+    }
+    if (c.half_width < 1 || c.stamp_half < 1 || c.patch < 1 || c.spatial_order < 0 ||
+        c.max_iter < 1 || c.min_stamps < 1 || !(c.clip_sigma > 0.0) || !(c.bad_frac > 0.0) ||
+        !(c.bad_frac <= 1.0))
+        return PSFM_ERR_INVALID_ARG;
+    if (c.half_width > PSFM_HMAX || c.stamp_half > PSFM_RMAX || c.spatial_order > 6 ||
+        nb + 2 > PSFM_GRAM_COLS || nf > 32 || c.precision != PSFM_PREC_FP32)
+        return PSFM_ERR_UNSUPPORTED;
+
+    psfm_context* ctx = new psfm_context();
+    ctx->cfg = c;
+    ctx->nb = nb;
+    ctx->nf = nf;
+    ctx->ns = (c.spatial_order + 1) * (c.spatial_order + 2) / 2;
+    ctx->N = nb * ctx->ns + 1;
+    ctx->L = nb + 1;
+    ctx->h = c.half_width;
+    ctx->r = c.stamp_half;
+    ctx->KW = 2 * c.half_width + 1;
+    ctx->T = ctx->KW * ctx->KW;
+    const int h = ctx->h, KW = ctx->KW, T = ctx->T;
+
+    // host tables
+    std::vector<double> kb((size_t)nb * T);
+    std::vector<float> fac((size_t)nf * KW);
+    std::vector<int> rowf(nb), colf(nb);
+    std::vector<float> psi(nb), z(nb);
+    int foff = 0;
+    for (int j = 0; j < c.n_gauss; j++) {
+        const double s2 = 2.0 * c.sigma[j] * c.sigma[j];
+        for (int e = 0; e <= c.degree[j]; e++)
+            for (int t = -h; t <= h; t++)
+                fac[(size_t)(foff + e) * KW + (t + h)] = (float)(ipow(t, e) * std::exp(-(double)t * t / s2));
+        foff += c.degree[j] + 1;
+    }
+    int i = 0;
+    foff = 0;
+    std::vector<double> raw(T);
+    for (int j = 0; j < c.n_gauss; j++) {
+        const double s2 = 2.0 * c.sigma[j] * c.sigma[j];
+        for (int d = 0; d <= c.degree[j]; d++) {
+            for (int p = d; p >= 0; p--) {
+                const int q = d - p;
+                double sum = 0.0, sabs = 0.0;
+                for (int v = -h; v <= h; v++)
+                    for (int u = -h; u <= h; u++) {
+                        const double val = ipow(u, p) * ipow(v, q) * std::exp(-(double)(u * u + v * v) / s2);
+                        raw[(v + h) * KW + (u + h)] = val;
+                        sum += val;
+                        sabs += std::fabs(val);
+                    }
+                double* ki = kb.data() + (size_t)i * T;
+                double norm;
+                bool sub_k0 = false;
+                if (i == 0) {
+                    norm = 1.0 / sum;
+                } else if (p % 2 == 0 && q % 2 == 0) {
+                    norm = 1.0 / sum;
+                    sub_k0 = true;
+                } else {
+                    norm = 1.0 / sabs;
+                }
+                for (int t = 0; t < T; t++) ki[t] = raw[t] * norm - (sub_k0 ? kb[t] : 0.0);
+                rowf[i] = foff + p;
+                colf[i] = foff + q;
+                psi[i] = (float)norm;
+                z[i] = sub_k0 ? 1.0f : 0.0f;
+                i++;
+            }
+        }
+        foff += c.degree[j] + 1;
+    }
+
+    // one device block for all tables
+    psfm::Carver layout(nullptr);
+    double* d_kb = layout.take<double>(kb.size());
+    float* d_fac = layout.take<float>(fac.size());
+    int* d_rowf = layout.take<int>(nb);
+    int* d_colf = layout.take<int>(nb);
+    float* d_psi = layout.take<float>(nb);
+    float* d_z = layout.take<float>(nb);
+    const size_t bytes = layout.off;
+    char* blk = nullptr;
+    if (hipMalloc(&blk, bytes) != hipSuccess) {
+        delete ctx;
+        return PSFM_ERR_HIP;
+    }
+    auto rebase = [&](auto* p) { return reinterpret_cast<decltype(p)>(blk + reinterpret_cast<size_t>(p)); };
+    ctx->dev_block = blk;
+    ctx->kb64 = rebase(d_kb);
+    ctx->fac = rebase(d_fac);
+    ctx->term_rowf = rebase(d_rowf);
+    ctx->term_colf = rebase(d_colf);
+    ctx->term_psi = rebase(d_psi);
+    ctx->term_z = rebase(d_z);
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = hipMemcpy(ctx->kb64, kb.data(), kb.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ctx->fac, fac.data(), fac.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ctx->term_rowf, rowf.data(), nb * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ctx->term_colf, colf.data(), nb * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ctx->term_psi, psi.data(), nb * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ctx->term_z, z.data(), nb * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(blk);
+        delete ctx;
+        return PSFM_ERR_HIP;
+    }
+    *out = ctx;
+    return PSFM_OK;
+}
+
+int psfm_destroy(psfm_context* ctx) {
+    if (!ctx) return PSFM_ERR_INVALID_ARG;
+    hipError_t e = hipFree(ctx->dev_block);
+    delete ctx;
+    return e == hipSuccess ? PSFM_OK : PSFM_ERR_HIP;
+}
+
+int psfm_n_basis(const psfm_context* ctx) { return ctx ? ctx->nb : -1; }
+int psfm_n_spatial(const psfm_context* ctx) { return ctx ? ctx->ns : -1; }
+int psfm_n_unknowns(const psfm_context* ctx) { return ctx ? ctx->N : -1; }
+int psfm_stamp_dim(const psfm_context* ctx) { return ctx ? ctx->L : -1; }
+
+size_t psfm_workspace_bytes(const psfm_context* ctx, int W, int H, int n_stamps) {
+    if (!ctx || W < 1 || H < 1 || n_stamps < 0) return 0;
+    size_t b = psfm::fit_workspace(ctx, n_stamps);
+    size_t s = psfm::solve_workspace(ctx, n_stamps);
+    size_t c = psfm::conv_workspace(ctx, W, H);
+    size_t d = psfm::subtract_workspace(ctx, W, H);
+    size_t m = b;
+    if (s > m) m = s;
+    if (c > m) m = c;
+    if (d > m) m = d;
+    return psfm::align_up(m, 256) + 256;
+}
+
+const char* psfm_status_string(int status) {
+    switch (status) {
+        case PSFM_OK: return "ok";
+        case PSFM_ERR_INVALID_ARG: return "invalid argument";
+        case PSFM_ERR_SHAPE: return "invalid image or stamp shape";
+        case PSFM_ERR_TOO_FEW_STAMPS: return "too few usable stamps";
+        case PSFM_ERR_NOT_PD: return "normal matrix not positive definite";
+        case PSFM_ERR_HIP: return "HIP runtime error";
+        case PSFM_ERR_WORKSPACE: return "workspace missing or too small";
+        case PSFM_ERR_UNSUPPORTED: return "configuration not supported by the kernels";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,525 @@
+// Application of the solution to the whole image (Sections 3.4, 3.5, 4.2, 4.3).
+//
+//   k_patch_kernels  one workgroup per constant-kernel patch: local
+//                    coefficients at the patch centre, K_p = sum alpha_i k_i
+//                    (FP64), the BAD box radius and the covariance factor;
+//                    stores K_p and f_p K_p^2 as FP32 taps, column-major
+//                    (u outer) so that one kernel column is 2h+1 consecutive
+//                    words for the scalar cache.
+//   k_conv_tile      one workgroup per 64 x 64 output tile inside a patch:
+//                    halo tile of the (masked -> 0) input in LDS, direct
+//                    (2h+1)^2-tap convolution on the FP32 VALU with 16
+//                    outputs per thread held in registers and the taps
+//                    broadcast from SGPRs; for images also the BAD/POOR mask
+//                    from a bit-packed halo mask.
+//   k_cov_samples /  covariance pseudo-matrix of the kernels realised at the
+//   k_cov_finish     centres of a 3 x 3 partition, averaged, normalised to
+//                    the centre, cropped.
+//   k_subtract /     difference image, its variance and mask, per-block
+//   k_subtract_cov   variance sums and the weighted pseudo-matrix.
+#include "internal.h"
+
+namespace {
+
+constexpr int TILE = PSFM_TILE;
+
+struct PatchGeom {
+    int npx, npy, tpp;
+};
+
+__host__ __device__ inline PatchGeom patch_geom(int W, int H, int P) {
+    PatchGeom g;
+    g.npx = (W + P - 1) / P;
+    g.npy = (H + P - 1) / P;
+    g.tpp = (P + TILE - 1) / TILE;
+    return g;
+}
+
+// Local coefficients at (x, y) into alpha[0..nb) (LDS), by threads < nb.
+__device__ void local_alpha(const double* __restrict__ a, int nb, int ns, int S, double x, double y,
+                            int W, int H, double* alpha) {
+    if ((int)threadIdx.x < nb) {
+        double g[32];
+        psfm_spatial_terms(S, x, y, W, H, g);
+        double v = 0.0;
+        for (int q = 0; q < ns; q++) v += a[threadIdx.x * ns + q] * g[q];
+        alpha[threadIdx.x] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_patch_kernels(
+    const double* __restrict__ a, const double* __restrict__ kb, int nb, int ns, int S, int W,
+    int H, int P, int h, const double* __restrict__ cov_in, int c_in, double bad_frac,
+    float* __restrict__ taps, float* __restrict__ taps2, int* __restrict__ rbad) {
+    __shared__ double alpha[64];
+    __shared__ double Kd[(2 * PSFM_HMAX + 1) * (2 * PSFM_HMAX + 1)];
+    __shared__ double ring[PSFM_HMAX + 1];
+    __shared__ double red[16];
+    const int KW = 2 * h + 1, T = KW * KW;
+    const int p = blockIdx.x, tid = threadIdx.x;
+    const int npx = (W + P - 1) / P;
+    const int px = p % npx, py = p / npx;
+    const int x0 = px * P, x1 = min(x0 + P, W), y0 = py * P, y1 = min(y0 + P, H);
+    local_alpha(a, nb, ns, S, 0.5 * (x0 + x1 - 1), 0.5 * (y0 + y1 - 1), W, H, alpha);
+    __syncthreads();
+    double s2 = 0.0;
+    for (int t = tid; t < T; t += 256) {
+        double k = 0.0;
+        for (int i = 0; i < nb; i++) k += alpha[i] * kb[(size_t)i * T + t];
+        Kd[t] = k;
+        s2 += k * k;
+    }
+    const double sumk2 = psfm_block_sum(s2, red);
+    if (tid <= h) {   // squared weight on the ring max(|u|,|v|) = tid
+        const int rr = tid;
+        double s = 0.0;
+        for (int v = -rr; v <= rr; v++)
+            for (int u = -rr; u <= rr; u++)
+                if (max(abs(u), abs(v)) == rr) {
+                    const double k = Kd[(v + h) * KW + (u + h)];
+                    s += k * k;
+                }
+        ring[rr] = s;
+    }
+    double f = 1.0;
+    if (cov_in) {
+        const int Cw = 2 * c_in + 1;
+        double r0 = 0.0;
+        for (int t = tid; t < T; t += 256) {
+            const int v = t / KW - h, u = t % KW - h;
+            double q = 0.0;
+            for (int wy = -c_in; wy <= c_in; wy++)
+                for (int wx = -c_in; wx <= c_in; wx++) {
+                    const int u2 = u - wx, v2 = v - wy;
+                    if (u2 < -h || u2 > h || v2 < -h || v2 > h) continue;
+                    q += cov_in[(wy + c_in) * Cw + (wx + c_in)] * Kd[(v2 + h) * KW + (u2 + h)];
+                }
+            r0 += Kd[t] * q;
+        }
+        const double raw0 = psfm_block_sum(r0, red);
+        f = sumk2 > 0.0 ? raw0 / sumk2 : 0.0;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int rb = h;
+        double outside = 0.0;
+        for (int rr = 0; rr <= h; rr++) outside += ring[rr];
+        const double tot = outside;
+        for (int rr = 0; rr <= h; rr++) {
+            outside -= ring[rr];
+            if (outside < bad_frac * tot) {
+                rb = rr;
+                break;
+            }
+        }
+        if (rbad) rbad[p] = rb;
+    }
+    for (int t = tid; t < T; t += 256) {
+        const int uu = t / KW, vv = t % KW;    // output column-major
+        const double k = Kd[vv * KW + uu];
+        if (taps) taps[(size_t)p * T + t] = (float)k;
+        if (taps2) taps2[(size_t)p * T + t] = (float)(f * k * k);
+    }
+}
+
+// MODE 0: image (writes out and out_mask); MODE 1: variance.
+template <int H_, int MODE>
+__global__ __launch_bounds__(256) void k_conv_tile(const float* __restrict__ src,
+                                                   const uint8_t* __restrict__ M, int W, int H,
+                                                   int64_t pitch, int P, const float* __restrict__ taps,
+                                                   const int* __restrict__ rbad, float* __restrict__ out,
+                                                   uint8_t* __restrict__ out_mask) {
+    constexpr int KW = 2 * H_ + 1;
+    constexpr int HW = TILE + 2 * H_;
+    constexpr int NWB = (HW + 31) / 32 + 1;
+    __shared__ float halo[HW * HW];
+    __shared__ uint32_t badw[HW][NWB];
+    const int tid = threadIdx.x;
+    const PatchGeom g = patch_geom(W, H, P);
+    const int px = blockIdx.x / g.tpp, sx = blockIdx.x % g.tpp;
+    const int py = blockIdx.y / g.tpp, sy = blockIdx.y % g.tpp;
+    const int X0 = px * P + sx * TILE, Y0 = py * P + sy * TILE;
+    const int X1 = min(min(X0 + TILE, (px + 1) * P), W);
+    const int Y1 = min(min(Y0 + TILE, (py + 1) * P), H);
+    if (X0 >= X1 || Y0 >= Y1) return;
+    const int p = py * g.npx + px;
+
+    for (int e = tid; e < HW * NWB; e += 256) (&badw[0][0])[e] = 0u;
+    __syncthreads();
+    int anybad = 0;
+    for (int e = tid; e < HW * HW; e += 256) {
+        const int hy = e / HW, hx = e - hy * HW;
+        const int gy = Y0 - H_ + hy, gx = X0 - H_ + hx;
+        float v = 0.0f;
+        bool ok = gx >= 0 && gx < W && gy >= 0 && gy < H;
+        if (ok) {
+            const int64_t o = (int64_t)gy * pitch + gx;
+            ok = M[o] == 0;
+            if (ok) v = src[o];
+        }
+        halo[e] = v;
+        if (!ok) {
+            anybad = 1;
+            if (MODE == 0) atomicOr(&badw[hy][hx >> 5], 1u << (hx & 31));
+        }
+    }
+    anybad = __syncthreads_or(anybad);
+
+    const int lx = tid & 63;
+    const int r0 = (tid >> 6) * 16;
+    float acc[16];
+#pragma unroll
+    for (int j = 0; j < 16; j++) acc[j] = 0.0f;
+    const float* kt = taps + (size_t)p * KW * KW;
+    for (int uu = 0; uu < KW; uu++) {
+        float kc[KW];
+#pragma unroll
+        for (int vv = 0; vv < KW; vv++) kc[vv] = kt[uu * KW + vv];
+        const float* col = halo + r0 * HW + lx + 2 * H_ - uu;
+#pragma unroll
+        for (int hr = 0; hr < 16 + 2 * H_; hr++) {
+            const float val = col[hr * HW];
+#pragma unroll
+            for (int j = 0; j < 16; j++) {
+                const int vv = j + 2 * H_ - hr;
+                if (vv >= 0 && vv < KW) acc[j] = fmaf(kc[vv], val, acc[j]);
+            }
+        }
+    }
+    const int gx = X0 + lx;
+    if (gx < X1) {
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+            const int gy = Y0 + r0 + j;
+            if (gy < Y1) out[(int64_t)gy * pitch + gx] = acc[j];
+        }
+    }
+    if (MODE == 0) {
+        uint64_t poorv = 0, badv = 0;
+        const int rb = rbad[p];
+        if (anybad) {
+            const uint64_t kmask = (KW >= 64) ? ~0ull : ((1ull << KW) - 1ull);
+            const uint64_t bmask = (1ull << (2 * rb + 1)) - 1ull;
+            const int w = lx >> 5, sh = lx & 31;
+#pragma unroll
+            for (int hr = 0; hr < 16 + 2 * H_; hr++) {
+                const uint32_t* bw = badw[r0 + hr];
+                const uint64_t bits = ((uint64_t)bw[w] | ((uint64_t)bw[w + 1] << 32)) >> sh;
+                const uint64_t win = bits & kmask;      // halo columns [lx, lx + 2h]
+                if (win) poorv |= 1ull << hr;
+                if ((win >> (H_ - rb)) & bmask) badv |= 1ull << hr;
+            }
+        }
+        if (gx < X1) {
+#pragma unroll
+            for (int j = 0; j < 16; j++) {
+                const int gy = Y0 + r0 + j;
+                if (gy < Y1) {
+                    uint8_t m = 0;
+                    if (anybad) {
+                        if ((badv >> (j + H_ - rb)) & ((1ull << (2 * rb + 1)) - 1ull)) m = PSFM_MASK_CONV_BAD;
+                        else if ((poorv >> j) & ((KW >= 64) ? ~0ull : ((1ull << KW) - 1ull))) m = PSFM_MASK_CONV_POOR;
+                    }
+                    out_mask[(int64_t)gy * pitch + gx] = m;
+                }
+            }
+        }
+    }
+}
+
+template <int H_, int MODE>
+int launch_conv(const float* src, const uint8_t* M, int W, int H, int64_t pitch, int P,
+                const float* taps, const int* rbad, float* out, uint8_t* out_mask, hipStream_t st) {
+    const PatchGeom g = patch_geom(W, H, P);
+    dim3 grid(g.npx * g.tpp, g.npy * g.tpp);
+    hipLaunchKernelGGL((k_conv_tile<H_, MODE>), grid, dim3(256), 0, st, src, M, W, H, pitch, P, taps,
+                       rbad, out, out_mask);
+    PSFM_HIP_CHECK(hipGetLastError());
+    return PSFM_OK;
+}
+
+template <int MODE>
+int dispatch_conv(int h, const float* src, const uint8_t* M, int W, int H, int64_t pitch, int P,
+                  const float* taps, const int* rbad, float* out, uint8_t* out_mask, hipStream_t st) {
+    switch (h) {
+#define PSFM_CONV_CASE(HH) \
+    case HH: return launch_conv<HH, MODE>(src, M, W, H, pitch, P, taps, rbad, out, out_mask, st);
+        PSFM_CONV_CASE(1) PSFM_CONV_CASE(2) PSFM_CONV_CASE(3) PSFM_CONV_CASE(4) PSFM_CONV_CASE(5)
+        PSFM_CONV_CASE(6) PSFM_CONV_CASE(7) PSFM_CONV_CASE(8) PSFM_CONV_CASE(9) PSFM_CONV_CASE(10)
+        PSFM_CONV_CASE(11) PSFM_CONV_CASE(12) PSFM_CONV_CASE(13) PSFM_CONV_CASE(14)
+        PSFM_CONV_CASE(15) PSFM_CONV_CASE(16)
+#undef PSFM_CONV_CASE
+        default: return PSFM_ERR_UNSUPPORTED;
+    }
+}
+
+// raw(delta) / sum K^2 for the kernel realised at the centre of cell
+// blockIdx.x of the 3 x 3 partition; blockIdx.y chunks the offsets.
+__global__ __launch_bounds__(256) void k_cov_samples(const double* __restrict__ a,
+                                                     const double* __restrict__ kb, int nb, int ns,
+                                                     int S, int W, int H, int h,
+                                                     const double* __restrict__ cov_in, int c_in,
+                                                     double* __restrict__ samples) {
+    __shared__ double alpha[64];
+    __shared__ double Kd[(2 * PSFM_HMAX + 1) * (2 * PSFM_HMAX + 1)];
+    __shared__ double red[16];
+    const int KW = 2 * h + 1, T = KW * KW;
+    const int R = 2 * h + c_in, Rw = 2 * R + 1;
+    const int j = blockIdx.x, tid = threadIdx.x;
+    const int jx = j % 3, jy = j / 3;
+    const int cx0 = jx * W / 3, cx1 = (jx + 1) * W / 3, cy0 = jy * H / 3, cy1 = (jy + 1) * H / 3;
+    local_alpha(a, nb, ns, S, 0.5 * (cx0 + cx1 - 1), 0.5 * (cy0 + cy1 - 1), W, H, alpha);
+    __syncthreads();
+    double s2 = 0.0;
+    for (int t = tid; t < T; t += 256) {
+        double k = 0.0;
+        for (int i = 0; i < nb; i++) k += alpha[i] * kb[(size_t)i * T + t];
+        Kd[t] = k;
+        s2 += k * k;
+    }
+    const double sumk2 = psfm_block_sum(s2, red);
+    const int d = blockIdx.y * 256 + tid;
+    if (d >= Rw * Rw) return;
+    const int dy = d / Rw - R, dx = d % Rw - R;
+    const int Cw = 2 * c_in + 1;
+    double raw = 0.0;
+    for (int v = -h; v <= h; v++)
+        for (int u = -h; u <= h; u++) {
+            const double ku = Kd[(v + h) * KW + (u + h)];
+            double q = 0.0;
+            for (int wy = -c_in; wy <= c_in; wy++)
+                for (int wx = -c_in; wx <= c_in; wx++) {
+                    const int u2 = dx + u - wx, v2 = dy + v - wy;
+                    if (u2 < -h || u2 > h || v2 < -h || v2 > h) continue;
+                    const double cw = cov_in ? cov_in[(wy + c_in) * Cw + (wx + c_in)] : 1.0;
+                    q += cw * Kd[(v2 + h) * KW + (u2 + h)];
+                }
+            raw += ku * q;
+        }
+    samples[(size_t)j * Rw * Rw + d] = sumk2 > 0.0 ? raw / sumk2 : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_cov_finish(const double* __restrict__ samples, int R,
+                                                    double* __restrict__ avg,
+                                                    double* __restrict__ cov_out, int c_out,
+                                                    psfm_fit_stats* stats) {
+    __shared__ double red[16];
+    __shared__ double s_centre;
+    const int Rw = 2 * R + 1, n = Rw * Rw, tid = threadIdx.x;
+    for (int d = tid; d < n; d += 256) {
+        double s = 0.0;
+        for (int j = 0; j < PSFM_COV_SAMPLES; j++) s += samples[(size_t)j * n + d] / 9.0;
+        avg[d] = s;
+    }
+    __syncthreads();
+    if (tid == 0) s_centre = avg[R * Rw + R];
+    __syncthreads();
+    const double centre = s_centre;
+    double tot = 0.0;
+    for (int d = tid; d < n; d += 256) {
+        const double v = centre != 0.0 ? avg[d] / centre : 0.0;
+        avg[d] = v;
+        tot += fabs(v);
+    }
+    tot = psfm_block_sum(tot, red);
+    const int Ow = 2 * c_out + 1;
+    double kept = 0.0;
+    for (int e = tid; e < Ow * Ow; e += 256) {
+        const int dy = e / Ow - c_out, dx = e % Ow - c_out;
+        double v = 0.0;
+        if (dx >= -R && dx <= R && dy >= -R && dy <= R) v = avg[(dy + R) * Rw + (dx + R)];
+        cov_out[e] = v;
+        kept += fabs(v);
+    }
+    kept = psfm_block_sum(kept, red);
+    if (tid == 0 && stats) stats->cov_discarded_frac = tot > 0.0 ? (tot - kept) / tot : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_subtract(
+    const float* __restrict__ I2, const float* __restrict__ V2, const uint8_t* __restrict__ M2,
+    const float* __restrict__ conv, const float* __restrict__ conv_var,
+    const uint8_t* __restrict__ conv_mask, int W, int H, int64_t pitch,
+    const double* __restrict__ d0p, float* __restrict__ diff, float* __restrict__ diff_var, uint8_t* __restrict__ diff_mask,
+    double* __restrict__ partials) {
+    __shared__ double red[16];
+    const double d0 = *d0p;
+    double s2 = 0.0, n2 = 0.0, sc = 0.0, nc = 0.0;
+    for (int y = blockIdx.x; y < H; y += gridDim.x) {
+        for (int x = threadIdx.x; x < W; x += 256) {
+            const int64_t o = (int64_t)y * pitch + x;
+            const uint8_t m2 = M2[o], cm = conv_mask[o];
+            const float cv = conv_var[o];
+            if (m2) {
+                diff[o] = 0.0f;
+                diff_var[o] = 0.0f;
+                diff_mask[o] = (uint8_t)(PSFM_MASK_BAD | cm);
+            } else {
+                const float v2 = V2[o];
+                diff[o] = (float)((double)I2[o] - (double)conv[o] - d0);
+                diff_var[o] = (float)((double)v2 + (double)cv);
+                diff_mask[o] = cm;
+                s2 += v2;
+                n2 += 1.0;
+            }
+            if (!cm) {
+                sc += cv;
+                nc += 1.0;
+            }
+        }
+    }
+    s2 = psfm_block_sum(s2, red);
+    n2 = psfm_block_sum(n2, red);
+    sc = psfm_block_sum(sc, red);
+    nc = psfm_block_sum(nc, red);
+    if (threadIdx.x == 0) {
+        double* q = partials + 4 * blockIdx.x;
+        q[0] = s2;
+        q[1] = n2;
+        q[2] = sc;
+        q[3] = nc;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_subtract_cov(const double* __restrict__ partials, int nblk,
+                                                      const double* __restrict__ cov2, int c2,
+                                                      const double* __restrict__ covc, int cc,
+                                                      double* __restrict__ covd, int cd) {
+    __shared__ double red[16];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblk; b += 256)
+        for (int k = 0; k < 4; k++) v[k] += partials[4 * b + k];
+    for (int k = 0; k < 4; k++) v[k] = psfm_block_sum(v[k], red);
+    const double v2 = v[1] > 0.0 ? v[0] / v[1] : 0.0;
+    const double vc = v[3] > 0.0 ? v[2] / v[3] : 0.0;
+    const int Dw = 2 * cd + 1;
+    for (int e = threadIdx.x; e < Dw * Dw; e += 256) {
+        const int dy = e / Dw - cd, dx = e % Dw - cd;
+        double a2 = 0.0, ac = 0.0;
+        if (cov2) {
+            if (abs(dx) <= c2 && abs(dy) <= c2) a2 = cov2[(dy + c2) * (2 * c2 + 1) + (dx + c2)];
+        } else {
+            a2 = (dx == 0 && dy == 0) ? 1.0 : 0.0;
+        }
+        if (covc && abs(dx) <= cc && abs(dy) <= cc) ac = covc[(dy + cc) * (2 * cc + 1) + (dx + cc)];
+        covd[e] = (v2 + vc) > 0.0 ? (v2 * a2 + vc * ac) / (v2 + vc) : 0.0;
+    }
+}
+
+constexpr int SUB_BLOCKS = 1024;
+
+}  // namespace
+
+namespace psfm {
+
+size_t conv_workspace(const psfm_context* ctx, int W, int H) {
+    const int np = n_patches(ctx, W, H);
+    const int R = 2 * ctx->h + 32;   // room for cov_in_half up to 32
+    Carver c(nullptr);
+    c.take<float>((size_t)np * ctx->T);
+    c.take<float>((size_t)np * ctx->T);
+    c.take<int>(np);
+    c.take<double>((size_t)PSFM_COV_SAMPLES * (2 * R + 1) * (2 * R + 1));
+    c.take<double>((size_t)(2 * R + 1) * (2 * R + 1));
+    return c.off;
+}
+
+size_t subtract_workspace(const psfm_context*, int, int) {
+    Carver c(nullptr);
+    c.take<double>(4 * SUB_BLOCKS);
+    return c.off;
+}
+
+}  // namespace psfm
+
+static int check_image_args(const psfm_context* ctx, int W, int H, int64_t pitch) {
+    if (!ctx) return PSFM_ERR_INVALID_ARG;
+    if (W < 1 || H < 1 || pitch < W) return PSFM_ERR_SHAPE;
+    return PSFM_OK;
+}
+
+extern "C" int psfm_convolve_image(const psfm_context* ctx, const double* coeffs, const float* I,
+                                   const uint8_t* M, int W, int H, int64_t pitch, float* out,
+                                   uint8_t* out_mask, void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_image_args(ctx, W, H, pitch);
+    if (rc) return rc;
+    if (!coeffs || !I || !M || !out || !out_mask) return PSFM_ERR_INVALID_ARG;
+    if (!ws || ws_bytes < psfm::conv_workspace(ctx, W, H)) return PSFM_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    const int np = psfm::n_patches(ctx, W, H);
+    psfm::Carver c(ws);
+    float* taps = c.take<float>((size_t)np * ctx->T);
+    c.take<float>((size_t)np * ctx->T);
+    int* rbad = c.take<int>(np);
+    const psfm_config& cf = ctx->cfg;
+    hipLaunchKernelGGL(k_patch_kernels, dim3(np), dim3(256), 0, st, coeffs, ctx->kb64, ctx->nb,
+                       ctx->ns, cf.spatial_order, W, H, cf.patch, ctx->h, (const double*)nullptr, 0,
+                       cf.bad_frac, taps, (float*)nullptr, rbad);
+    PSFM_HIP_CHECK(hipGetLastError());
+    return dispatch_conv<0>(ctx->h, I, M, W, H, pitch, cf.patch, taps, rbad, out, out_mask, st);
+}
+
+extern "C" int psfm_propagate_variance(const psfm_context* ctx, const double* coeffs,
+                                       const float* V, const uint8_t* M, int W, int H,
+                                       int64_t pitch, const double* cov_in, int cov_in_half,
+                                       float* var_out, double* cov_out, int cov_out_half,
+                                       psfm_fit_stats* stats, void* ws, size_t ws_bytes,
+                                       void* stream) {
+    int rc = check_image_args(ctx, W, H, pitch);
+    if (rc) return rc;
+    if (!coeffs || !V || !M || !var_out || !cov_out || cov_out_half < 0 || cov_in_half < 0)
+        return PSFM_ERR_INVALID_ARG;
+    if (cov_in_half > 32 || cov_out_half > 2 * ctx->h + 64) return PSFM_ERR_UNSUPPORTED;
+    if (!cov_in) cov_in_half = 0;
+    if (!ws || ws_bytes < psfm::conv_workspace(ctx, W, H)) return PSFM_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    const int np = psfm::n_patches(ctx, W, H);
+    psfm::Carver c(ws);
+    c.take<float>((size_t)np * ctx->T);
+    float* taps2 = c.take<float>((size_t)np * ctx->T);
+    c.take<int>(np);
+    const int Rmax = 2 * ctx->h + 32;
+    double* samples = c.take<double>((size_t)PSFM_COV_SAMPLES * (2 * Rmax + 1) * (2 * Rmax + 1));
+    double* avg = c.take<double>((size_t)(2 * Rmax + 1) * (2 * Rmax + 1));
+    const psfm_config& cf = ctx->cfg;
+    hipLaunchKernelGGL(k_patch_kernels, dim3(np), dim3(256), 0, st, coeffs, ctx->kb64, ctx->nb,
+                       ctx->ns, cf.spatial_order, W, H, cf.patch, ctx->h, cov_in, cov_in_half,
+                       cf.bad_frac, (float*)nullptr, taps2, (int*)nullptr);
+    PSFM_HIP_CHECK(hipGetLastError());
+    rc = dispatch_conv<1>(ctx->h, V, M, W, H, pitch, cf.patch, taps2, nullptr, var_out, nullptr, st);
+    if (rc) return rc;
+    const int R = 2 * ctx->h + cov_in_half, Rw = 2 * R + 1;
+    hipLaunchKernelGGL(k_cov_samples, dim3(PSFM_COV_SAMPLES, (Rw * Rw + 255) / 256), dim3(256), 0, st,
+                       coeffs, ctx->kb64, ctx->nb, ctx->ns, cf.spatial_order, W, H, ctx->h, cov_in,
+                       cov_in_half, samples);
+    hipLaunchKernelGGL(k_cov_finish, dim3(1), dim3(256), 0, st, samples, R, avg, cov_out,
+                       cov_out_half, stats);
+    PSFM_HIP_CHECK(hipGetLastError());
+    return PSFM_OK;
+}
+
+extern "C" int psfm_subtract(const psfm_context* ctx, const double* coeffs, const float* I2,
+                             const float* V2, const uint8_t* M2, const float* conv,
+                             const float* conv_var, const uint8_t* conv_mask, int W, int H,
+                             int64_t pitch, const double* cov2, int cov2_half,
+                             const double* cov_conv, int cov_conv_half, float* diff,
+                             float* diff_var, uint8_t* diff_mask, double* cov_diff,
+                             int cov_diff_half, void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_image_args(ctx, W, H, pitch);
+    if (rc) return rc;
+    if (!coeffs || !I2 || !V2 || !M2 || !conv || !conv_var || !conv_mask || !diff || !diff_var ||
+        !diff_mask || !cov_diff || cov2_half < 0 || cov_conv_half < 0 || cov_diff_half < 0)
+        return PSFM_ERR_INVALID_ARG;
+    if (!ws || ws_bytes < psfm::subtract_workspace(ctx, W, H)) return PSFM_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    psfm::Carver c(ws);
+    double* partials = c.take<double>(4 * SUB_BLOCKS);
+    const int nblk = std::min(H, SUB_BLOCKS);
+    // the background coefficient is the last unknown, read on the device
+    hipLaunchKernelGGL(k_subtract, dim3(nblk), dim3(256), 0, st, I2, V2, M2, conv, conv_var, conv_mask,
+                       W, H, pitch, coeffs + (ctx->N - 1), diff, diff_var, diff_mask, partials);
+    PSFM_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_subtract_cov, dim3(1), dim3(256), 0, st, partials, nblk, cov2, cov2_half,
+                       cov_conv, cov_conv_half, cov_diff, cov_diff_half);
+    PSFM_HIP_CHECK(hipGetLastError());
+    return PSFM_OK;
+}

@@ -1,0 +1,353 @@
+// Per-stamp normal equations (Section 2, Eqs. 3-6 with c = 0, p = 0).
+//
+// One workgroup handles one band of PSFM_FIT_BR rows of one stamp:
+//   1. the band's input window of I1 (band rows + 2h halo rows, stamp width
+//      + 2h columns) is read from HBM into LDS, masked/non-finite pixels
+//      become zeros and raise the stamp flags (validity, Section 3.3);
+//   2. column pass: each distinct 1-D factor f_{j,e}(v) is applied along y
+//      (FP32 FMA, the window column held in registers);
+//   3. for every stamp row of the band: row pass of each basis term
+//      (f_{j,p} along x over the column-pass output of f_{j,q}), the
+//      zero-sum fix-up A_i = psi_i R_i - z_i A_0, the weighting by sqrt(1/V2)
+//      and the extra columns sqrt(w) (background) and sqrt(w) * I2 (target);
+//      the 64-column weighted row block is then folded into the Gram
+//      G = A~^T A~ with v_mfma_f32_16x16x4f32 (10 lower 16x16 blocks, spread
+//      over the 4 waves);
+//   4. the band's partial Gram is written in FP32; a second kernel adds the
+//      bands of each stamp in FP64 and scatters M_s, b_s, e_s.
+#include "internal.h"
+
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int BR = PSFM_FIT_BR;
+constexpr int SEG = 12;          // stamp pixels per row-pass item
+constexpr int AT_STRIDE = 80;    // LDS row stride of the weighted block (bank spread)
+constexpr int GC = PSFM_GRAM_COLS;
+
+struct FitLds {
+    int win, col, R, At, sw, dt, psi, z, total;  // float offsets
+};
+
+__host__ __device__ inline FitLds fit_lds_layout(int h, int r, int nb, int nf) {
+    const int WC = 2 * r + 1 + 2 * h;
+    const int npad = (2 * r + 1 + 3) / 4 * 4;
+    FitLds L;
+    int o = 0;
+    L.win = o;  o += (BR + 2 * h) * WC;
+    L.col = o;  o += nf * BR * WC + SEG + 2 * h + 4;   // slack for the last row-pass loads
+    L.R = o;    o += npad * nb;
+    L.At = o;   o += npad * AT_STRIDE;
+    L.sw = o;   o += BR * (2 * r + 1);
+    L.dt = o;   o += BR * (2 * r + 1);
+    L.psi = o;  o += 64;
+    L.z = o;    o += 64;
+    L.total = o + 4;
+    return L;
+}
+
+template <int H_>
+__global__ __launch_bounds__(256) void k_fit_band(
+    const float* __restrict__ I1, const uint8_t* __restrict__ M1, const float* __restrict__ I2,
+    const float* __restrict__ V2, const uint8_t* __restrict__ M2, int W, int H, int64_t pitch,
+    const int32_t* __restrict__ xy, int r, int nbands, const float* __restrict__ fac,
+    const int* __restrict__ rowf, const int* __restrict__ colf, const float* __restrict__ psi,
+    const float* __restrict__ zf, int nb, int nf, float* __restrict__ part,
+    int* __restrict__ band_flags) {
+    constexpr int KW = 2 * H_ + 1;
+    extern __shared__ float lds[];
+    __shared__ int s_flags;
+
+    const int tid = threadIdx.x;
+    const int s = blockIdx.x / nbands;
+    const int band = blockIdx.x % nbands;
+    const int xc = xy[2 * s], yc = xy[2 * s + 1];
+    const int R = r + H_;
+    const int NPX = 2 * r + 1;
+    const int WC = NPX + 2 * H_;
+    const int npad = (NPX + 3) / 4 * 4;
+    const FitLds Lo = fit_lds_layout(H_, r, nb, nf);
+    float* win = lds + Lo.win;
+    float* colb = lds + Lo.col;
+    float* Rb = lds + Lo.R;
+    float* At = lds + Lo.At;
+    float* swb = lds + Lo.sw;
+    float* dtb = lds + Lo.dt;
+    float* psib = lds + Lo.psi;
+    float* zb = lds + Lo.z;
+
+    if (xc - R < 0 || yc - R < 0 || xc + R >= W || yc + R >= H) {
+        if (tid == 0) band_flags[blockIdx.x] = PSFM_STAMP_INVALID;
+        return;
+    }
+    if (tid == 0) s_flags = 0;
+    if (tid < 64) {
+        psib[tid] = tid < nb ? psi[tid] : 0.0f;
+        zb[tid] = tid < nb ? zf[tid] : 0.0f;
+    }
+    __syncthreads();
+
+    const int y_l0 = band * BR;
+    const int nbr = min(BR, NPX - y_l0);
+    // ---- 1. input window and stamp pixel data
+    int fl = 0;
+    {
+        const int rows = BR + 2 * H_;
+        const int gy0 = yc - r + y_l0 - H_;
+        const int gx0 = xc - R;
+        for (int e = tid; e < rows * WC; e += 256) {
+            const int wr = e / WC, wc = e - wr * WC;
+            float v = 0.0f;
+            if (wr < nbr + 2 * H_) {
+                const int64_t o = (int64_t)(gy0 + wr) * pitch + (gx0 + wc);
+                const float x = I1[o];
+                if (M1[o]) fl |= PSFM_STAMP_INVALID;
+                else if (!isfinite(x)) fl |= PSFM_STAMP_NONFINITE;
+                else v = x;
+            }
+            win[e] = v;
+        }
+        for (int e = tid; e < nbr * NPX; e += 256) {
+            const int br = e / NPX, x = e - br * NPX;
+            const int64_t o = (int64_t)(yc - r + y_l0 + br) * pitch + (xc - r + x);
+            const float i2 = I2[o], v2 = V2[o];
+            float sw = 0.0f, dt = 0.0f;
+            if (M2[o]) {
+                fl |= PSFM_STAMP_INVALID;
+            } else if (!isfinite(i2) || !isfinite(v2) || !(v2 > 0.0f)) {
+                fl |= PSFM_STAMP_NONFINITE;
+            } else {
+                sw = 1.0f / sqrtf(v2);
+                dt = sw * i2;
+            }
+            swb[e] = sw;
+            dtb[e] = dt;
+        }
+    }
+    if (fl) atomicOr(&s_flags, fl);
+    __syncthreads();
+    const int flags = s_flags;
+    if (flags) {
+        if (tid == 0) band_flags[blockIdx.x] = flags;
+        return;
+    }
+
+    // ---- 2. column pass: colb[f][br][wc] = sum_v f(v) I1(wc, br - v)
+    for (int item = tid; item < nf * WC; item += 256) {
+        const int f = item / WC, wc = item - f * WC;
+        float tap[KW];
+#pragma unroll
+        for (int vv = 0; vv < KW; vv++) tap[vv] = fac[f * KW + vv];
+        float acc[BR];
+#pragma unroll
+        for (int br = 0; br < BR; br++) acc[br] = 0.0f;
+#pragma unroll
+        for (int br = 0; br < BR; br++) {
+#pragma unroll
+            for (int vv = 0; vv < KW; vv++) acc[br] = fmaf(tap[vv], win[(br + 2 * H_ - vv) * WC + wc], acc[br]);
+        }
+        float* dst = colb + (f * BR) * WC + wc;
+#pragma unroll
+        for (int br = 0; br < BR; br++) dst[br * WC] = acc[br];
+    }
+    __syncthreads();
+
+    // ---- 3. rows of the band
+    const int lane = tid & 63, wave = tid >> 6;
+    floatx4 acc[3];
+#pragma unroll
+    for (int q = 0; q < 3; q++) acc[q] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int nseg = (NPX + SEG - 1) / SEG;
+    for (int br = 0; br < nbr; br++) {
+        // 3a. row pass: Rb[x][i] = sum_u f_{j,p}(u) colb[f_{j,q}][br][x + 2h - uu]
+        for (int item = tid; item < nb * nseg; item += 256) {
+            const int i = item / nseg, seg = item - i * nseg;
+            const int x0 = seg * SEG;
+            const float* tp = fac + rowf[i] * KW;
+            float tap[KW];
+#pragma unroll
+            for (int uu = 0; uu < KW; uu++) tap[uu] = tp[uu];
+            const float* src = colb + (colf[i] * BR + br) * WC + x0;
+            float a[SEG];
+#pragma unroll
+            for (int k = 0; k < SEG; k++) {
+                a[k] = 0.0f;
+#pragma unroll
+                for (int uu = 0; uu < KW; uu++) a[k] = fmaf(tap[uu], src[k + 2 * H_ - uu], a[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < SEG; k++)
+                if (x0 + k < NPX) Rb[(x0 + k) * nb + i] = a[k];
+        }
+        __syncthreads();
+        // 3b. zero-sum fix-up, weights, extra columns
+        for (int e = tid; e < npad * GC; e += 256) {
+            const int x = e / GC, c = e - x * GC;
+            float v = 0.0f;
+            if (x < NPX) {
+                const float sw = swb[br * NPX + x];
+                if (c < nb) v = sw * (psib[c] * Rb[x * nb + c] - zb[c] * (psib[0] * Rb[x * nb]));
+                else if (c == nb) v = sw;
+                else if (c == nb + 1) v = dtb[br * NPX + x];
+            }
+            At[x * AT_STRIDE + c] = v;
+        }
+        __syncthreads();
+        // 3c. Gram blocks on MFMA.  Wave blocks (bm, bn): w0 (0,0)(1,0)(1,1);
+        // w1 (2,0)(2,1)(2,2); w2 (3,0)(3,1); w3 (3,2)(3,3).
+        for (int ks = 0; ks < npad / 4; ks++) {
+            const float* rowp = At + (4 * ks + (lane >> 4)) * AT_STRIDE + (lane & 15);
+            if (wave == 0) {
+                const float a0 = rowp[0], a1 = rowp[16];
+                acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, a0, acc[0], 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, a0, acc[1], 0, 0, 0);
+                acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, a1, acc[2], 0, 0, 0);
+            } else if (wave == 1) {
+                const float a0 = rowp[0], a1 = rowp[16], a2 = rowp[32];
+                acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, a0, acc[0], 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, a1, acc[1], 0, 0, 0);
+                acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, a2, acc[2], 0, 0, 0);
+            } else if (wave == 2) {
+                const float a0 = rowp[0], a1 = rowp[16], a3 = rowp[48];
+                acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a3, a0, acc[0], 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a3, a1, acc[1], 0, 0, 0);
+            } else {
+                const float a2 = rowp[32], a3 = rowp[48];
+                acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a3, a2, acc[0], 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a3, a3, acc[1], 0, 0, 0);
+            }
+        }
+        // Rb may be rewritten only after every wave finished 3b (barrier above);
+        // At is rewritten after the barrier that follows the next row pass.
+    }
+
+    // ---- 4. partial Gram out: rows 16 bm + 4 (lane / 16) + q, column 16 bn + lane % 16
+    float* G = part + (size_t)blockIdx.x * GC * GC;
+    const int bms[4][3] = {{0, 1, 1}, {2, 2, 2}, {3, 3, -1}, {3, 3, -1}};
+    const int bns[4][3] = {{0, 0, 1}, {0, 1, 2}, {0, 1, -1}, {2, 3, -1}};
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+        const int bm = bms[wave][q], bn = bns[wave][q];
+        if (bm < 0) continue;
+        const int col = 16 * bn + (lane & 15);
+#pragma unroll
+        for (int e = 0; e < 4; e++) G[(16 * bm + 4 * (lane >> 4) + e) * GC + col] = acc[q][e];
+    }
+    if (tid == 0) band_flags[blockIdx.x] = 0;
+}
+
+// Sum of the band partials of each stamp in FP64 and scatter to M_s, b_s, e_s.
+__global__ __launch_bounds__(256) void k_fit_reduce(const float* __restrict__ part,
+                                                    const int* __restrict__ band_flags, int nbands,
+                                                    int nb, int npix, double* __restrict__ Ms,
+                                                    double* __restrict__ bs, double* __restrict__ es,
+                                                    int32_t* __restrict__ npix_out,
+                                                    int32_t* __restrict__ flags_out) {
+    const int s = blockIdx.x, tid = threadIdx.x;
+    const int L = nb + 1;
+    int fl = 0;
+    for (int b = 0; b < nbands; b++) fl |= band_flags[s * nbands + b];
+    if (fl & PSFM_STAMP_INVALID) fl = PSFM_STAMP_INVALID;
+    double* M = Ms + (size_t)s * L * L;
+    double* bv = bs + (size_t)s * L;
+    const float* P0 = part + (size_t)s * nbands * GC * GC;
+    for (int e = tid; e < L * L; e += 256) {
+        const int i = e / L, j = e - i * L;
+        double v = 0.0;
+        if (!fl) {
+            const int hi = i > j ? i : j, lo = i > j ? j : i;
+            for (int b = 0; b < nbands; b++) v += (double)P0[(size_t)b * GC * GC + hi * GC + lo];
+        }
+        M[e] = v;
+    }
+    for (int i = tid; i <= L; i += 256) {
+        double v = 0.0;
+        if (!fl)
+            for (int b = 0; b < nbands; b++) v += (double)P0[(size_t)b * GC * GC + (nb + 1) * GC + i];
+        if (i < L) bv[i] = v;
+        else es[s] = v;
+    }
+    if (tid == 0) {
+        npix_out[s] = fl ? 0 : npix;
+        flags_out[s] = fl;
+    }
+}
+
+template <int H_>
+int launch_fit(const psfm_context* ctx, const float* I1, const uint8_t* M1, const float* I2,
+               const float* V2, const uint8_t* M2, int W, int H, int64_t pitch, const int32_t* xy,
+               int n, float* part, int* bflags, hipStream_t st) {
+    const int nbands = psfm::fit_bands(ctx);
+    const FitLds Lo = fit_lds_layout(H_, ctx->r, ctx->nb, ctx->nf);
+    const size_t lds = (size_t)Lo.total * sizeof(float);
+    static bool attr_set = false;
+    if (!attr_set) {
+        PSFM_HIP_CHECK(hipFuncSetAttribute((const void*)k_fit_band<H_>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 64));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_fit_band<H_>, dim3(n * nbands), dim3(256), lds, st, I1, M1, I2, V2, M2, W, H,
+                       pitch, xy, ctx->r, nbands, ctx->fac, ctx->term_rowf, ctx->term_colf,
+                       ctx->term_psi, ctx->term_z, ctx->nb, ctx->nf, part, bflags);
+    PSFM_HIP_CHECK(hipGetLastError());
+    return PSFM_OK;
+}
+
+}  // namespace
+
+namespace psfm {
+
+size_t fit_lds_bytes(const psfm_context* ctx) {
+    return (size_t)fit_lds_layout(ctx->h, ctx->r, ctx->nb, ctx->nf).total * sizeof(float);
+}
+
+size_t fit_workspace(const psfm_context* ctx, int n_stamps) {
+    Carver c(nullptr);
+    const size_t nbl = (size_t)n_stamps * fit_bands(ctx);
+    c.take<float>(nbl * GC * GC);
+    c.take<int>(nbl);
+    return c.off;
+}
+
+}  // namespace psfm
+
+extern "C" int psfm_fit_stamps(const psfm_context* ctx, const float* I1, const uint8_t* M1,
+                               const float* I2, const float* V2, const uint8_t* M2, int W, int H,
+                               int64_t pitch, const int32_t* stamp_xy, int n_stamps,
+                               double* stamp_M, double* stamp_b, double* stamp_e,
+                               int32_t* stamp_npix, int32_t* stamp_flags, void* ws,
+                               size_t ws_bytes, void* stream) {
+    if (!ctx || n_stamps < 0) return PSFM_ERR_INVALID_ARG;
+    if (W < 1 || H < 1 || pitch < W) return PSFM_ERR_SHAPE;
+    if (n_stamps == 0) return PSFM_OK;
+    if (!I1 || !M1 || !I2 || !V2 || !M2 || !stamp_xy || !stamp_M || !stamp_b || !stamp_e ||
+        !stamp_npix || !stamp_flags)
+        return PSFM_ERR_INVALID_ARG;
+    if (psfm::fit_lds_bytes(ctx) > 160 * 1024 - 64) return PSFM_ERR_UNSUPPORTED;
+    const size_t need = psfm::fit_workspace(ctx, n_stamps);
+    if (!ws || ws_bytes < need) return PSFM_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    psfm::Carver c(ws);
+    const size_t nbl = (size_t)n_stamps * psfm::fit_bands(ctx);
+    float* part = c.take<float>(nbl * GC * GC);
+    int* bflags = c.take<int>(nbl);
+    int rc;
+    switch (ctx->h) {
+#define PSFM_FIT_CASE(HH) \
+    case HH: rc = launch_fit<HH>(ctx, I1, M1, I2, V2, M2, W, H, pitch, stamp_xy, n_stamps, part, bflags, st); break;
+        PSFM_FIT_CASE(1) PSFM_FIT_CASE(2) PSFM_FIT_CASE(3) PSFM_FIT_CASE(4) PSFM_FIT_CASE(5)
+        PSFM_FIT_CASE(6) PSFM_FIT_CASE(7) PSFM_FIT_CASE(8) PSFM_FIT_CASE(9) PSFM_FIT_CASE(10)
+        PSFM_FIT_CASE(11) PSFM_FIT_CASE(12) PSFM_FIT_CASE(13) PSFM_FIT_CASE(14) PSFM_FIT_CASE(15)
+        PSFM_FIT_CASE(16)
+#undef PSFM_FIT_CASE
+        default: return PSFM_ERR_UNSUPPORTED;
+    }
+    if (rc != PSFM_OK) return rc;
+    const int npix = (2 * ctx->r + 1) * (2 * ctx->r + 1);
+    hipLaunchKernelGGL(k_fit_reduce, dim3(n_stamps), dim3(256), 0, st, part, bflags,
+                       psfm::fit_bands(ctx), ctx->nb, npix, stamp_M, stamp_b, stamp_e, stamp_npix,
+                       stamp_flags);
+    PSFM_HIP_CHECK(hipGetLastError());
+    return PSFM_OK;
+}

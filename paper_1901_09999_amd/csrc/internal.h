@@ -1,0 +1,106 @@
+// Internal declarations of the PSF-matching library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/psfm.h"
+
+#define PSFM_HMAX 16          // largest supported kernel half width
+#define PSFM_RMAX 32          // largest supported stamp half width
+#define PSFM_GRAM_COLS 64     // Gram width: nb terms + sqrt(w) + d~ (+ zero padding)
+#define PSFM_FIT_BR 12        // stamp rows per fit workgroup (band)
+#define PSFM_TILE 64          // output tile side of the image convolution
+#define PSFM_COV_SAMPLES 9    // 3 x 3 kernels for the image pseudo-matrix
+
+struct psfm_context {
+    psfm_config cfg;
+    int nb;     // kernel basis terms
+    int ns;     // spatial terms
+    int N;      // unknowns
+    int L;      // per-stamp matrix side (nb + 1)
+    int nf;     // distinct 1-D factors (Gaussian j, power e)
+    int h, r, KW, T;
+    // device tables
+    double* kb64;     // [nb][T] full basis taps, FP64 (row v major: [(v+h)*KW + (u+h)])
+    float* fac;       // [nf][KW] 1-D factors e-th power x Gaussian j, at offsets -h..h
+    int* term_rowf;   // [nb] factor index of the u (row-pass) profile of term i
+    int* term_colf;   // [nb] factor index of the v (column-pass) profile of term i
+    float* term_psi;  // [nb] normalisation of the separable product
+    float* term_z;    // [nb] 1 if k_0 is subtracted (even terms i >= 1), else 0
+    void* dev_block;  // single allocation backing all of the above
+};
+
+namespace psfm {
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Carves consecutive 256-byte aligned regions out of a workspace.
+struct Carver {
+    char* base;
+    size_t off = 0;
+    explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+    // With a null base the returned pointers are the byte offsets (layout mode).
+    template <class T>
+    T* take(size_t count) {
+        off = align_up(off, 256);
+        T* p = reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(base) + off);
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+// Per-call workspace needs (bytes).
+size_t fit_workspace(const psfm_context* ctx, int n_stamps);
+size_t solve_workspace(const psfm_context* ctx, int n_stamps);
+size_t conv_workspace(const psfm_context* ctx, int W, int H);
+size_t subtract_workspace(const psfm_context* ctx, int W, int H);
+
+int fit_bands(const psfm_context* ctx);
+int n_patches(const psfm_context* ctx, int W, int H);
+
+int check_hip(hipError_t e);
+
+}  // namespace psfm
+
+#define PSFM_HIP_CHECK(call)                          \
+    do {                                              \
+        hipError_t e_ = (call);                       \
+        if (e_ != hipSuccess) return psfm::check_hip(e_); \
+    } while (0)
+
+// ---------------------------------------------------------------- device helpers
+
+// Spatial terms x^l y^m (l + m <= S), degree-major with l descending, in
+// coordinates scaled to [-1, 1] over the image.
+__device__ __forceinline__ void psfm_spatial_terms(int S, double x, double y, int W, int H,
+                                                   double* g) {
+    const double xt = W > 1 ? (2.0 * x - (W - 1)) / (double)(W - 1) : 0.0;
+    const double yt = H > 1 ? (2.0 * y - (H - 1)) / (double)(H - 1) : 0.0;
+    int s = 0;
+    for (int d = 0; d <= S; d++) {
+        for (int l = d; l >= 0; l--) {
+            double v = 1.0;
+            for (int k = 0; k < l; k++) v *= xt;
+            for (int k = 0; k < d - l; k++) v *= yt;
+            g[s++] = v;
+        }
+    }
+}
+
+// Fixed-order sum over a workgroup of up to 1024 threads (deterministic).
+// Every thread of the block must call it; `red` holds >= 16 doubles in LDS.
+__device__ __forceinline__ double psfm_block_sum(double v, double* red) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int w = 0; w < nw; w++) s += red[w];
+    __syncthreads();
+    return s;
+}

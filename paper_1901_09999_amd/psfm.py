@@ -1,0 +1,328 @@
+"""Python binding of the HIP library ``libpsfm.so`` (C interface in
+``include/psfm.h``).
+
+This module only marshals arguments: torch tensors supply device memory and
+the current HIP stream; every step of the computation runs in the library's
+kernels.  Importing it on a machine without the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpsfm.so")
+
+MAX_GAUSS = 8
+STAMP_INVALID, STAMP_REJECTED, STAMP_NONFINITE, STAMP_EXCLUDED = 1, 2, 4, 8
+MASK_BAD, MASK_CONV_BAD, MASK_CONV_POOR = 1, 2, 4
+PREC_FP32, PREC_BF16, PREC_FP16 = 0, 1, 2
+
+
+class PsfmError(RuntimeError):
+    pass
+
+
+class CConfig(C.Structure):
+    _fields_ = [
+        ("n_gauss", C.c_int),
+        ("sigma", C.c_double * MAX_GAUSS),
+        ("degree", C.c_int * MAX_GAUSS),
+        ("half_width", C.c_int),
+        ("spatial_order", C.c_int),
+        ("stamp_half", C.c_int),
+        ("patch", C.c_int),
+        ("clip_sigma", C.c_double),
+        ("max_iter", C.c_int),
+        ("min_stamps", C.c_int),
+        ("bad_frac", C.c_double),
+        ("precision", C.c_int),
+        ("reserved", C.c_int),
+    ]
+
+
+class CStats(C.Structure):
+    _fields_ = [
+        ("chi2", C.c_double),
+        ("dof", C.c_double),
+        ("chi2_dof", C.c_double),
+        ("kernel_sum_centre", C.c_double),
+        ("cov_discarded_frac", C.c_double),
+        ("n_used", C.c_int),
+        ("n_rejected", C.c_int),
+        ("n_iter", C.c_int),
+        ("info", C.c_int),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+STATS_BYTES = C.sizeof(CStats)
+
+_lib = None
+
+
+def lib():
+    """Load ``libpsfm.so``; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise PsfmError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        P, i, i64, sz = C.c_void_p, C.c_int, C.c_int64, C.c_size_t
+        cp = C.POINTER(CConfig)
+        sig = {
+            "psfm_config_default": (None, [cp]),
+            "psfm_create": (i, [cp, C.POINTER(P)]),
+            "psfm_destroy": (i, [P]),
+            "psfm_n_basis": (i, [P]),
+            "psfm_n_spatial": (i, [P]),
+            "psfm_n_unknowns": (i, [P]),
+            "psfm_stamp_dim": (i, [P]),
+            "psfm_workspace_bytes": (sz, [P, i, i, i]),
+            "psfm_fit_stamps": (i, [P, P, P, P, P, P, i, i, i64, P, i, P, P, P, P, P, P, sz, P]),
+            "psfm_solve": (i, [P, i, i, P, i, P, P, P, P, P, P, P, P, P, sz, P]),
+            "psfm_convolve_image": (i, [P, P, P, P, i, i, i64, P, P, P, sz, P]),
+            "psfm_propagate_variance": (i, [P, P, P, P, i, i, i64, P, i, P, P, i, P, P, sz, P]),
+            "psfm_subtract": (i, [P, P, P, P, P, P, P, P, i, i, i64, P, i, P, i, P, P, P, P, i, P,
+                                  sz, P]),
+            "psfm_status_string": (C.c_char_p, [i]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise PsfmError(f"{what}: {lib().psfm_status_string(rc).decode()} ({rc})")
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise PsfmError("tensor must live on the HIP device")
+    if not t.is_contiguous():
+        raise PsfmError("tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@dataclasses.dataclass
+class Config:
+    sigmas: Tuple[float, ...] = (0.7, 1.5, 3.0)
+    degrees: Tuple[int, ...] = (6, 4, 2)
+    h: int = 10
+    S: int = 0
+    r: int = 20
+    P: int = 64
+    clip_sigma: float = 3.0
+    max_iter: int = 3
+    min_stamps: int = 3
+    bad_frac: float = 0.2
+    precision: int = PREC_FP32
+
+    @classmethod
+    def from_workload(cls, wl, **kw):
+        base = dict(sigmas=tuple(wl.sigmas), degrees=tuple(wl.degrees), h=wl.kernel_half,
+                    S=wl.spatial_order, r=wl.stamp_half, P=wl.patch)
+        base.update(kw)
+        return cls(**base)
+
+    def c(self) -> CConfig:
+        c = CConfig()
+        c.n_gauss = len(self.sigmas)
+        for j, (s, d) in enumerate(zip(self.sigmas, self.degrees)):
+            c.sigma[j] = s
+            c.degree[j] = d
+        c.half_width, c.spatial_order, c.stamp_half, c.patch = self.h, self.S, self.r, self.P
+        c.clip_sigma, c.max_iter, c.min_stamps = self.clip_sigma, self.max_iter, self.min_stamps
+        c.bad_frac, c.precision = self.bad_frac, self.precision
+        return c
+
+
+class Context:
+    """A library context (basis tables on the current device) plus cached
+    workspace.  All image arguments are CUDA/HIP torch tensors."""
+
+    def __init__(self, cfg: Config, device: Optional[torch.device] = None):
+        self.cfg = cfg
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+        self._h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().psfm_create(C.byref(cfg.c()), C.byref(self._h)), "psfm_create")
+        self.nb = lib().psfm_n_basis(self._h)
+        self.ns = lib().psfm_n_spatial(self._h)
+        self.N = lib().psfm_n_unknowns(self._h)
+        self.L = lib().psfm_stamp_dim(self._h)
+        self._ws: Optional[torch.Tensor] = None
+
+    def close(self):
+        if self._h:
+            lib().psfm_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def workspace(self, W: int, H: int, n_stamps: int) -> torch.Tensor:
+        need = lib().psfm_workspace_bytes(self._h, W, H, n_stamps)
+        if need == 0:
+            raise PsfmError("invalid workspace request")
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    # ------------------------------------------------------------------ calls
+    def fit_stamps(self, I1, M1, I2, V2, M2, stamps, out=None):
+        H, W = I1.shape
+        n = stamps.shape[0]
+        L = self.L
+        dev = self.device
+        if out is None:
+            out = dict(M=torch.empty((n, L, L), dtype=torch.float64, device=dev),
+                       b=torch.empty((n, L), dtype=torch.float64, device=dev),
+                       e=torch.empty(n, dtype=torch.float64, device=dev),
+                       npix=torch.empty(n, dtype=torch.int32, device=dev),
+                       flags=torch.empty(n, dtype=torch.int32, device=dev))
+        ws = self.workspace(W, H, n)
+        _check(lib().psfm_fit_stamps(self._h, _ptr(I1), _ptr(M1), _ptr(I2), _ptr(V2), _ptr(M2), W, H,
+                                     W, _ptr(stamps), n, _ptr(out["M"]), _ptr(out["b"]),
+                                     _ptr(out["e"]), _ptr(out["npix"]), _ptr(out["flags"]),
+                                     _ptr(ws), ws.numel(), _stream()), "psfm_fit_stamps")
+        return out
+
+    def solve(self, W, H, stamps, fit, flags=None, out=None):
+        n = stamps.shape[0]
+        dev = self.device
+        fl = (fit["flags"] if flags is None else flags).clone()
+        if out is None:
+            out = dict(coeffs=torch.empty(self.N, dtype=torch.float64, device=dev),
+                       chi2=torch.empty(max(n, 1), dtype=torch.float64, device=dev),
+                       stats=torch.zeros(STATS_BYTES, dtype=torch.uint8, device=dev))
+        out["flags"] = fl
+        ws = self.workspace(W, H, n)
+        _check(lib().psfm_solve(self._h, W, H, _ptr(stamps), n, _ptr(fit["M"]), _ptr(fit["b"]),
+                                _ptr(fit["e"]), _ptr(fit["npix"]), _ptr(fl), _ptr(out["coeffs"]),
+                                _ptr(out["chi2"]), _ptr(out["stats"]), _ptr(ws), ws.numel(),
+                                _stream()), "psfm_solve")
+        return out
+
+    def convolve_image(self, coeffs, I, M, out=None, out_mask=None):
+        H, W = I.shape
+        out = torch.empty_like(I) if out is None else out
+        out_mask = torch.empty_like(M) if out_mask is None else out_mask
+        ws = self.workspace(W, H, 0)
+        _check(lib().psfm_convolve_image(self._h, _ptr(coeffs), _ptr(I), _ptr(M), W, H, W,
+                                         _ptr(out), _ptr(out_mask), _ptr(ws), ws.numel(),
+                                         _stream()), "psfm_convolve_image")
+        return out, out_mask
+
+    def propagate_variance(self, coeffs, V, M, cov_in=None, c_out=10, stats=None, out=None,
+                           cov_out=None):
+        H, W = V.shape
+        out = torch.empty_like(V) if out is None else out
+        if cov_out is None:
+            cov_out = torch.empty((2 * c_out + 1, 2 * c_out + 1), dtype=torch.float64,
+                                  device=self.device)
+        c_in = 0 if cov_in is None else (cov_in.shape[0] - 1) // 2
+        ws = self.workspace(W, H, 0)
+        _check(lib().psfm_propagate_variance(self._h, _ptr(coeffs), _ptr(V), _ptr(M), W, H, W,
+                                             _ptr(cov_in), c_in, _ptr(out), _ptr(cov_out), c_out,
+                                             _ptr(stats), _ptr(ws), ws.numel(), _stream()),
+               "psfm_propagate_variance")
+        return out, cov_out
+
+    def subtract(self, coeffs, I2, V2, M2, conv, conv_var, conv_mask, cov_conv, cov2=None,
+                 c_d=None, out=None):
+        H, W = I2.shape
+        cc = (cov_conv.shape[0] - 1) // 2
+        c2 = 0 if cov2 is None else (cov2.shape[0] - 1) // 2
+        cd = max(cc, c2) if c_d is None else c_d
+        if out is None:
+            out = dict(diff=torch.empty_like(I2), diff_var=torch.empty_like(V2),
+                       diff_mask=torch.empty_like(M2),
+                       cov_diff=torch.empty((2 * cd + 1, 2 * cd + 1), dtype=torch.float64,
+                                            device=self.device))
+        ws = self.workspace(W, H, 0)
+        _check(lib().psfm_subtract(self._h, _ptr(coeffs), _ptr(I2), _ptr(V2), _ptr(M2), _ptr(conv),
+                                   _ptr(conv_var), _ptr(conv_mask), W, H, W, _ptr(cov2), c2,
+                                   _ptr(cov_conv), cc, _ptr(out["diff"]), _ptr(out["diff_var"]),
+                                   _ptr(out["diff_mask"]), _ptr(out["cov_diff"]), cd, _ptr(ws),
+                                   ws.numel(), _stream()), "psfm_subtract")
+        return out
+
+    def match_pair(self, I1, V1, M1, I2, V2, M2, stamps, c_out=10, bufs=None):
+        """The whole hot path: fit -> solve -> convolve -> variance -> subtract.
+        ``bufs`` (from :meth:`alloc_pair`) avoids allocations in a timed loop."""
+        H, W = I1.shape
+        b = self.alloc_pair(W, H, stamps.shape[0], c_out) if bufs is None else bufs
+        fit = self.fit_stamps(I1, M1, I2, V2, M2, stamps, out=b["fit"])
+        b["flags_in"].copy_(fit["flags"])
+        sol = self.solve(W, H, stamps, fit, out=b["sol"])
+        conv, cmask = self.convolve_image(sol["coeffs"], I1, M1, out=b["conv"], out_mask=b["conv_mask"])
+        var, cov = self.propagate_variance(sol["coeffs"], V1, M1, c_out=c_out, stats=sol["stats"],
+                                           out=b["var"], cov_out=b["cov"])
+        sub = self.subtract(sol["coeffs"], I2, V2, M2, conv, var, cmask, cov, out=b["sub"])
+        return dict(fit=fit, sol=sol, conv=conv, conv_mask=cmask, var=var, cov=cov, **sub)
+
+    def alloc_pair(self, W, H, n, c_out=10):
+        dev, L = self.device, self.L
+        f32 = dict(dtype=torch.float32, device=dev)
+        return dict(
+            fit=dict(M=torch.empty((n, L, L), dtype=torch.float64, device=dev),
+                     b=torch.empty((n, L), dtype=torch.float64, device=dev),
+                     e=torch.empty(n, dtype=torch.float64, device=dev),
+                     npix=torch.empty(n, dtype=torch.int32, device=dev),
+                     flags=torch.empty(n, dtype=torch.int32, device=dev)),
+            flags_in=torch.empty(n, dtype=torch.int32, device=dev),
+            sol=dict(coeffs=torch.empty(self.N, dtype=torch.float64, device=dev),
+                     chi2=torch.empty(max(n, 1), dtype=torch.float64, device=dev),
+                     stats=torch.zeros(STATS_BYTES, dtype=torch.uint8, device=dev)),
+            conv=torch.empty((H, W), **f32), conv_mask=torch.empty((H, W), dtype=torch.uint8, device=dev),
+            var=torch.empty((H, W), **f32),
+            cov=torch.empty((2 * c_out + 1, 2 * c_out + 1), dtype=torch.float64, device=dev),
+            sub=dict(diff=torch.empty((H, W), **f32), diff_var=torch.empty((H, W), **f32),
+                     diff_mask=torch.empty((H, W), dtype=torch.uint8, device=dev),
+                     cov_diff=torch.empty((2 * c_out + 1, 2 * c_out + 1), dtype=torch.float64,
+                                          device=dev)),
+        )
+
+
+def read_stats(stats: torch.Tensor) -> dict:
+    raw = bytes(stats.cpu().numpy().tobytes())
+    return CStats.from_buffer_copy(raw[:STATS_BYTES]).as_dict()
+
+
+def to_device(pair, device="cuda"):
+    """Upload a synthetic pair's planes and stamp list."""
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
+    return dict(I1=t(pair.I1), V1=t(pair.V1), M1=t(pair.M1), I2=t(pair.I2), V2=t(pair.V2),
+                M2=t(pair.M2), stamps=t(pair.stamps.astype(np.int32)))
+
+
+def exported_symbols() -> Sequence[str]:
+    return ["psfm_config_default", "psfm_create", "psfm_destroy", "psfm_n_basis", "psfm_n_spatial",
+            "psfm_n_unknowns", "psfm_stamp_dim", "psfm_workspace_bytes", "psfm_fit_stamps",
+            "psfm_solve", "psfm_convolve_image", "psfm_propagate_variance", "psfm_subtract",
+            "psfm_status_string"]
