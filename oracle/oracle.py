@@ -101,6 +101,8 @@ def lib():
             "orc_propagate_variance": (None, [cfgp, P, P, P, P, i, i, i64, P, i, P, P, i, P]),
             "orc_subtract": (None, [cfgp, P, P, P, P, P, P, P, i, i, i64, P, i, P, i, P, P, P, P,
                                     i]),
+            "orc_convolve_region": (None, [cfgp, P, P, P, P, P, i, i, i64, P, i, i, i, i, i, P, P,
+                                           P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(_lib, name)
@@ -295,6 +297,25 @@ def propagate_variance(cfg: Config, a, V, M, cov_in=None, c_in=0, c_out=10, kb=N
                                  H, W, _p(None if cov_in is None else _c(cov_in, np.float64)), c_in,
                                  _p(out), _p(cov), c_out, C.byref(disc))
     return out, cov, disc.value
+
+
+def convolve_region(cfg: Config, a, I, V, M, rect, cov_in=None, c_in=0, kb=None):
+    """Image and variance convolution restricted to rect = (x0, y0, x1, y1) of
+    the full image; returns (conv, mask, var) of the rectangle's shape."""
+    kb = basis(cfg) if kb is None else kb
+    M = _c(M, np.uint8)
+    H, W = M.shape
+    x0, y0, x1, y1 = rect
+    Ic = None if I is None else _c(I, np.float32)
+    Vc = None if V is None else _c(V, np.float32)
+    out = np.zeros((y1 - y0, x1 - x0), np.float32) if I is not None else None
+    om = np.zeros((y1 - y0, x1 - x0), np.uint8) if I is not None else None
+    var = np.zeros((y1 - y0, x1 - x0), np.float32) if V is not None else None
+    lib().orc_convolve_region(C.byref(cfg.c()), _p(kb), _p(_c(a, np.float64)), _p(Ic), _p(Vc),
+                              _p(M), W, H, W,
+                              _p(None if cov_in is None else _c(cov_in, np.float64)), c_in,
+                              x0, y0, x1, y1, _p(out), _p(om), _p(var))
+    return out, om, var
 
 
 def subtract(cfg: Config, a, I2, V2, M2, conv, conv_var, conv_mask, cov_conv, cov2=None, c_d=None):

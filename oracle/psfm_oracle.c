@@ -585,6 +585,56 @@ void orc_convolve_image(const orc_config* c, const double* kb, const double* a, 
 }
 
 /*
+ * The same two convolutions (Eqs. 12-13 with the BAD/POOR mask and the
+ * covariance factor) restricted to the output rectangle [rx0, rx1) x
+ * [ry0, ry1) of the full image: every output pixel is computed exactly as
+ * by orc_convolve_image / orc_propagate_variance (same patch grid, same
+ * spatial coordinates), so large images can be checked on samples.
+ * out, out_mask and var_out are (rx1-rx0) x (ry1-ry0), row-major; NULL
+ * outputs are skipped.
+ */
+void orc_convolve_region(const orc_config* c, const double* kb, const double* a, const float* I,
+                         const float* V, const uint8_t* Mk, int W, int H, int64_t pitch,
+                         const double* cov_in, int c_in, int rx0, int ry0, int rx1, int ry1,
+                         float* out, uint8_t* out_mask, float* var_out) {
+    const int h = c->h, Kw = 2 * h + 1, T = Kw * Kw, np = orc_n_patches(c, W, H);
+    const int rw = rx1 - rx0;
+#pragma omp parallel for schedule(dynamic)
+    for (int p = 0; p < np; p++) {
+        int x0, x1, y0, y1;
+        patch_bounds(W, H, c->P, p, &x0, &x1, &y0, &y1);
+        if (x1 <= rx0 || x0 >= rx1 || y1 <= ry0 || y0 >= ry1) continue;
+        double* K = (double*)malloc(sizeof(double) * T);
+        orc_patch_kernel(c, kb, a, W, H, p, K);
+        const int rb = orc_bad_radius(K, h, c->bad_frac);
+        const double f = orc_cov_factor(K, h, cov_in, c_in);
+        for (int y = y0 > ry0 ? y0 : ry0; y < (y1 < ry1 ? y1 : ry1); y++)
+            for (int x = x0 > rx0 ? x0 : rx0; x < (x1 < rx1 ? x1 : rx1); x++) {
+                double s = 0.0, sv = 0.0;
+                int dmin = h + 1;
+                for (int v = -h; v <= h; v++)
+                    for (int u = -h; u <= h; u++) {
+                        const int xx = x - u, yy = y - v;
+                        if (xx >= 0 && xx < W && yy >= 0 && yy < H && !Mk[(int64_t)yy * pitch + xx]) {
+                            const double kk = K[(v + h) * Kw + (u + h)];
+                            if (I) s += kk * (double)I[(int64_t)yy * pitch + xx];
+                            if (V) sv += kk * kk * (double)V[(int64_t)yy * pitch + xx];
+                        } else {
+                            const int dd = abs(u) > abs(v) ? abs(u) : abs(v);
+                            if (dd < dmin) dmin = dd;
+                        }
+                    }
+                const int64_t o = (int64_t)(y - ry0) * rw + (x - rx0);
+                if (out) out[o] = (float)s;
+                if (out_mask)
+                    out_mask[o] = dmin <= rb ? ORC_MASK_CONV_BAD : (dmin <= h ? ORC_MASK_CONV_POOR : 0);
+                if (var_out) var_out[o] = (float)(f * sv);
+            }
+        free(K);
+    }
+}
+
+/*
  * Variance propagation (Section 4.2, Eq. 13, and Section 4.3):
  *     V'(x, y) = f_p * sum_{u,v} K_p(u, v)^2 V~(x-u, y-v)
  * with V~ zero where masked or outside the image and f_p the covariance

@@ -97,14 +97,19 @@ int psfm_create(const psfm_config* cfg, psfm_context** out) {
     // host tables
     std::vector<double> kb((size_t)nb * T);
     std::vector<float> fac((size_t)nf * KW);
+    std::vector<double> fac64((size_t)nf * KW);
+    std::vector<double> psi64(nb);
     std::vector<int> rowf(nb), colf(nb);
     std::vector<float> psi(nb), z(nb);
     int foff = 0;
     for (int j = 0; j < c.n_gauss; j++) {
         const double s2 = 2.0 * c.sigma[j] * c.sigma[j];
         for (int e = 0; e <= c.degree[j]; e++)
-            for (int t = -h; t <= h; t++)
-                fac[(size_t)(foff + e) * KW + (t + h)] = (float)(ipow(t, e) * std::exp(-(double)t * t / s2));
+            for (int t = -h; t <= h; t++) {
+                const double f = ipow(t, e) * std::exp(-(double)t * t / s2);
+                fac64[(size_t)(foff + e) * KW + (t + h)] = f;
+                fac[(size_t)(foff + e) * KW + (t + h)] = (float)f;
+            }
         foff += c.degree[j] + 1;
     }
     int i = 0;
@@ -138,6 +143,7 @@ int psfm_create(const psfm_config* cfg, psfm_context** out) {
                 rowf[i] = foff + p;
                 colf[i] = foff + q;
                 psi[i] = (float)norm;
+                psi64[i] = norm;
                 z[i] = sub_k0 ? 1.0f : 0.0f;
                 i++;
             }
@@ -153,6 +159,8 @@ int psfm_create(const psfm_config* cfg, psfm_context** out) {
     int* d_colf = layout.take<int>(nb);
     float* d_psi = layout.take<float>(nb);
     float* d_z = layout.take<float>(nb);
+    double* d_fac64 = layout.take<double>(fac64.size());
+    double* d_psi64 = layout.take<double>(nb);
     const size_t bytes = layout.off;
     char* blk = nullptr;
     if (hipMalloc(&blk, bytes) != hipSuccess) {
@@ -167,6 +175,8 @@ int psfm_create(const psfm_config* cfg, psfm_context** out) {
     ctx->term_colf = rebase(d_colf);
     ctx->term_psi = rebase(d_psi);
     ctx->term_z = rebase(d_z);
+    ctx->fac64 = rebase(d_fac64);
+    ctx->psi64 = rebase(d_psi64);
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipMemcpy(ctx->kb64, kb.data(), kb.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ctx->fac, fac.data(), fac.size() * sizeof(float), hipMemcpyHostToDevice);
@@ -174,6 +184,8 @@ int psfm_create(const psfm_config* cfg, psfm_context** out) {
     if (e == hipSuccess) e = hipMemcpy(ctx->term_colf, colf.data(), nb * sizeof(int), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ctx->term_psi, psi.data(), nb * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ctx->term_z, z.data(), nb * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ctx->fac64, fac64.data(), fac64.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ctx->psi64, psi64.data(), nb * sizeof(double), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(blk);
         delete ctx;

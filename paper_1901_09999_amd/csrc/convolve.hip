@@ -1,17 +1,15 @@
 // Application of the solution to the whole image (Sections 3.4, 3.5, 4.2, 4.3).
 //
-//   k_patch_kernels  one workgroup per constant-kernel patch: local
-//                    coefficients at the patch centre, K_p = sum alpha_i k_i
-//                    (FP64), the BAD box radius and the covariance factor;
-//                    stores K_p and f_p K_p^2 as FP32 taps, column-major
-//                    (u outer) so that one kernel column is 2h+1 consecutive
-//                    words for the scalar cache.
-//   k_conv_tile      one workgroup per 64 x 64 output tile inside a patch:
-//                    halo tile of the (masked -> 0) input in LDS, direct
-//                    (2h+1)^2-tap convolution on the FP32 VALU with 16
-//                    outputs per thread held in registers and the taps
-//                    broadcast from SGPRs; for images also the BAD/POOR mask
-//                    from a bit-packed halo mask.
+//   k_conv_tile      one workgroup per 64 x 64 output tile inside a
+//                    constant-kernel patch.  Prologue: local coefficients at
+//                    the patch centre, K_p = sum alpha_i k_i in FP64 through
+//                    the separable factors, the BAD box radius and the
+//                    covariance factor; FP32 taps (K_p, or f_p K_p^2 for the
+//                    variance) kept column-major in LDS.  Body: halo tile of
+//                    the (masked -> 0) input in LDS, direct (2h+1)^2-tap
+//                    convolution on the FP32 VALU with 16 outputs per thread
+//                    in registers and the taps broadcast from LDS; for images
+//                    also the BAD/POOR mask from a bit-packed halo mask.
 //   k_cov_samples /  covariance pseudo-matrix of the kernels realised at the
 //   k_cov_finish     centres of a 3 x 3 partition, averaged, normalised to
 //                    the centre, cropped.
@@ -35,57 +33,77 @@ __host__ __device__ inline PatchGeom patch_geom(int W, int H, int P) {
     return g;
 }
 
-// Local coefficients at (x, y) into alpha[0..nb) (LDS), by threads < nb.
-__device__ void local_alpha(const double* __restrict__ a, int nb, int ns, int S, double x, double y,
-                            int W, int H, double* alpha) {
-    if ((int)threadIdx.x < nb) {
-        double g[32];
-        psfm_spatial_terms(S, x, y, W, H, g);
-        double v = 0.0;
-        for (int q = 0; q < ns; q++) v += a[threadIdx.x * ns + q] * g[q];
-        alpha[threadIdx.x] = v;
+// Basis tables as kernel arguments.
+struct BasisArgs {
+    const double* fac64;   // [nf][KW]
+    const double* psi64;   // [nb]
+    const float* z;        // [nb]
+    const int* rowf;       // [nb]
+    const int* colf;       // [nb]
+    int nb, nf, ns, S, h;
+};
+
+// LDS scratch of the kernel realisation.
+struct RealiseLds {
+    double F[32 * (2 * PSFM_HMAX + 1)];
+    double gam[64];
+    int rf[64], cf[64];
+};
+
+// K(u, v) = sum_i alpha_i(x, y) k_i(u, v) in FP64, evaluated through the
+// separable factors: with k_i = psi_i f_{rowf}(u) f_{colf}(v) - z_i k_0,
+//   K = sum_i gamma_i f_{rowf_i}(u) f_{colf_i}(v),
+//   gamma_i = alpha_i psi_i (i >= 1),  gamma_0 = psi_0 (alpha_0 - sum_i z_i alpha_i).
+// Kd receives [(v+h)*KW + (u+h)].  All threads of the block call it.
+__device__ void realise_kernel(const BasisArgs& B, const double* __restrict__ a, double x, double y,
+                               int W, int H, RealiseLds& sh, double* Kd) {
+    const int KW = 2 * B.h + 1, T = KW * KW, tid = threadIdx.x;
+    for (int e = tid; e < B.nf * KW; e += blockDim.x) sh.F[e] = B.fac64[e];
+    if (tid < B.nb) {
+        sh.gam[tid] = psfm_spatial_dot(B.S, x, y, W, H, a + tid * B.ns);   // alpha_i for now
+        sh.rf[tid] = B.rowf[tid];
+        sh.cf[tid] = B.colf[tid];
     }
+    __syncthreads();
+    double c0 = 0.0;
+    for (int i = 1; i < B.nb; i++) c0 += (double)B.z[i] * sh.gam[i];
+    __syncthreads();
+    if (tid < B.nb) sh.gam[tid] = (tid == 0 ? sh.gam[0] - c0 : sh.gam[tid]) * B.psi64[tid];
+    __syncthreads();
+    for (int t = tid; t < T; t += blockDim.x) {
+        const int v = t / KW, u = t - v * KW;
+        double k = 0.0;
+        for (int i = 0; i < B.nb; i++) k += sh.gam[i] * sh.F[sh.rf[i] * KW + u] * sh.F[sh.cf[i] * KW + v];
+        Kd[t] = k;
+    }
+    __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_patch_kernels(
-    const double* __restrict__ a, const double* __restrict__ kb, int nb, int ns, int S, int W,
-    int H, int P, int h, const double* __restrict__ cov_in, int c_in, double bad_frac,
-    float* __restrict__ taps, float* __restrict__ taps2, int* __restrict__ rbad) {
-    __shared__ double alpha[64];
-    __shared__ double Kd[(2 * PSFM_HMAX + 1) * (2 * PSFM_HMAX + 1)];
-    __shared__ double ring[PSFM_HMAX + 1];
-    __shared__ double red[16];
-    const int KW = 2 * h + 1, T = KW * KW;
-    const int p = blockIdx.x, tid = threadIdx.x;
-    const int npx = (W + P - 1) / P;
-    const int px = p % npx, py = p / npx;
-    const int x0 = px * P, x1 = min(x0 + P, W), y0 = py * P, y1 = min(y0 + P, H);
-    local_alpha(a, nb, ns, S, 0.5 * (x0 + x1 - 1), 0.5 * (y0 + y1 - 1), W, H, alpha);
-    __syncthreads();
+// Squared-weight ring sums, BAD radius and covariance factor of the kernel
+// in Kd (FP64, LDS).  All threads call it; results in *rb_out / *f_out (LDS).
+__device__ void kernel_stats(const double* Kd, int h, double bad_frac, const double* __restrict__ cov_in,
+                             int c_in, double* ring, double* red, int* rb_out, double* f_out) {
+    const int KW = 2 * h + 1, T = KW * KW, tid = threadIdx.x;
     double s2 = 0.0;
-    for (int t = tid; t < T; t += 256) {
-        double k = 0.0;
-        for (int i = 0; i < nb; i++) k += alpha[i] * kb[(size_t)i * T + t];
-        Kd[t] = k;
-        s2 += k * k;
-    }
+    for (int t = tid; t < T; t += blockDim.x) s2 += Kd[t] * Kd[t];
     const double sumk2 = psfm_block_sum(s2, red);
     if (tid <= h) {   // squared weight on the ring max(|u|,|v|) = tid
         const int rr = tid;
         double s = 0.0;
-        for (int v = -rr; v <= rr; v++)
-            for (int u = -rr; u <= rr; u++)
-                if (max(abs(u), abs(v)) == rr) {
-                    const double k = Kd[(v + h) * KW + (u + h)];
-                    s += k * k;
-                }
+        for (int v = -rr; v <= rr; v++) {
+            const int step = (v == -rr || v == rr || rr == 0) ? 1 : 2 * rr;
+            for (int u = -rr; u <= rr; u += step) {
+                const double k = Kd[(v + h) * KW + (u + h)];
+                s += k * k;
+            }
+        }
         ring[rr] = s;
     }
     double f = 1.0;
     if (cov_in) {
         const int Cw = 2 * c_in + 1;
         double r0 = 0.0;
-        for (int t = tid; t < T; t += 256) {
+        for (int t = tid; t < T; t += blockDim.x) {
             const int v = t / KW - h, u = t % KW - h;
             double q = 0.0;
             for (int wy = -c_in; wy <= c_in; wy++)
@@ -112,28 +130,35 @@ __global__ __launch_bounds__(256) void k_patch_kernels(
                 break;
             }
         }
-        if (rbad) rbad[p] = rb;
+        *rb_out = rb;
+        *f_out = f;
     }
-    for (int t = tid; t < T; t += 256) {
-        const int uu = t / KW, vv = t % KW;    // output column-major
-        const double k = Kd[vv * KW + uu];
-        if (taps) taps[(size_t)p * T + t] = (float)k;
-        if (taps2) taps2[(size_t)p * T + t] = (float)(f * k * k);
-    }
+    __syncthreads();
 }
 
-// MODE 0: image (writes out and out_mask); MODE 1: variance.
+// One workgroup per 64 x 64 output tile inside a constant-kernel patch.
+// MODE 0: image I' (and the BAD/POOR mask); MODE 1: variance V' = f K^2 (x) V.
+// Prologue: the patch kernel is realised in FP64 (LDS scratch shared with the
+// halo buffer), its FP32 taps (K or f K^2, column-major) kept in LDS.
 template <int H_, int MODE>
-__global__ __launch_bounds__(256) void k_conv_tile(const float* __restrict__ src,
-                                                   const uint8_t* __restrict__ M, int W, int H,
-                                                   int64_t pitch, int P, const float* __restrict__ taps,
-                                                   const int* __restrict__ rbad, float* __restrict__ out,
-                                                   uint8_t* __restrict__ out_mask) {
+__global__ __launch_bounds__(256) void k_conv_tile(
+    const float* __restrict__ src, const uint8_t* __restrict__ M, int W, int H, int64_t pitch,
+    int P, const double* __restrict__ a, BasisArgs B, double bad_frac,
+    const double* __restrict__ cov_in, int c_in, float* __restrict__ out,
+    uint8_t* __restrict__ out_mask) {
     constexpr int KW = 2 * H_ + 1;
+    constexpr int T = KW * KW;
     constexpr int HW = TILE + 2 * H_;
     constexpr int NWB = (HW + 31) / 32 + 1;
-    __shared__ float halo[HW * HW];
+    static_assert(sizeof(float) * HW * HW >= sizeof(RealiseLds) + sizeof(double) * T,
+                  "kernel scratch must fit in the halo buffer");
+    __shared__ __align__(16) float halo[HW * HW];
+    __shared__ __align__(16) float taps[T + 4];
     __shared__ uint32_t badw[HW][NWB];
+    __shared__ double ring[H_ + 1];
+    __shared__ double red[16];
+    __shared__ int s_rb;
+    __shared__ double s_f;
     const int tid = threadIdx.x;
     const PatchGeom g = patch_geom(W, H, P);
     const int px = blockIdx.x / g.tpp, sx = blockIdx.x % g.tpp;
@@ -142,7 +167,22 @@ __global__ __launch_bounds__(256) void k_conv_tile(const float* __restrict__ src
     const int X1 = min(min(X0 + TILE, (px + 1) * P), W);
     const int Y1 = min(min(Y0 + TILE, (py + 1) * P), H);
     if (X0 >= X1 || Y0 >= Y1) return;
-    const int p = py * g.npx + px;
+
+    // ---- patch kernel (FP64) -> FP32 taps
+    {
+        RealiseLds& sh = *reinterpret_cast<RealiseLds*>(halo);
+        double* Kd = reinterpret_cast<double*>(reinterpret_cast<char*>(halo) + sizeof(RealiseLds));
+        const int x0 = px * P, x1 = min(x0 + P, W), y0 = py * P, y1 = min(y0 + P, H);
+        realise_kernel(B, a, 0.5 * (x0 + x1 - 1), 0.5 * (y0 + y1 - 1), W, H, sh, Kd);
+        kernel_stats(Kd, H_, bad_frac, MODE == 1 ? cov_in : nullptr, c_in, ring, red, &s_rb, &s_f);
+        const double f = s_f;
+        for (int t = tid; t < T; t += 256) {
+            const int uu = t / KW, vv = t - uu * KW;     // column-major
+            const double k = Kd[vv * KW + uu];
+            taps[t] = (float)(MODE == 0 ? k : f * k * k);
+        }
+        __syncthreads();
+    }
 
     for (int e = tid; e < HW * NWB; e += 256) (&badw[0][0])[e] = 0u;
     __syncthreads();
@@ -170,11 +210,10 @@ __global__ __launch_bounds__(256) void k_conv_tile(const float* __restrict__ src
     float acc[16];
 #pragma unroll
     for (int j = 0; j < 16; j++) acc[j] = 0.0f;
-    const float* kt = taps + (size_t)p * KW * KW;
     for (int uu = 0; uu < KW; uu++) {
         float kc[KW];
 #pragma unroll
-        for (int vv = 0; vv < KW; vv++) kc[vv] = kt[uu * KW + vv];
+        for (int vv = 0; vv < KW; vv++) kc[vv] = taps[uu * KW + vv];
         const float* col = halo + r0 * HW + lx + 2 * H_ - uu;
 #pragma unroll
         for (int hr = 0; hr < 16 + 2 * H_; hr++) {
@@ -196,7 +235,7 @@ __global__ __launch_bounds__(256) void k_conv_tile(const float* __restrict__ src
     }
     if (MODE == 0) {
         uint64_t poorv = 0, badv = 0;
-        const int rb = rbad[p];
+        const int rb = s_rb;
         if (anybad) {
             const uint64_t kmask = (KW >= 64) ? ~0ull : ((1ull << KW) - 1ull);
             const uint64_t bmask = (1ull << (2 * rb + 1)) - 1ull;
@@ -229,21 +268,23 @@ __global__ __launch_bounds__(256) void k_conv_tile(const float* __restrict__ src
 
 template <int H_, int MODE>
 int launch_conv(const float* src, const uint8_t* M, int W, int H, int64_t pitch, int P,
-                const float* taps, const int* rbad, float* out, uint8_t* out_mask, hipStream_t st) {
+                const double* a, const BasisArgs& B, double bad_frac, const double* cov_in,
+                int c_in, float* out, uint8_t* out_mask, hipStream_t st) {
     const PatchGeom g = patch_geom(W, H, P);
     dim3 grid(g.npx * g.tpp, g.npy * g.tpp);
-    hipLaunchKernelGGL((k_conv_tile<H_, MODE>), grid, dim3(256), 0, st, src, M, W, H, pitch, P, taps,
-                       rbad, out, out_mask);
+    hipLaunchKernelGGL((k_conv_tile<H_, MODE>), grid, dim3(256), 0, st, src, M, W, H, pitch, P, a, B,
+                       bad_frac, cov_in, c_in, out, out_mask);
     PSFM_HIP_CHECK(hipGetLastError());
     return PSFM_OK;
 }
 
 template <int MODE>
-int dispatch_conv(int h, const float* src, const uint8_t* M, int W, int H, int64_t pitch, int P,
-                  const float* taps, const int* rbad, float* out, uint8_t* out_mask, hipStream_t st) {
-    switch (h) {
+int dispatch_conv(const float* src, const uint8_t* M, int W, int H, int64_t pitch, int P,
+                  const double* a, const BasisArgs& B, double bad_frac, const double* cov_in,
+                  int c_in, float* out, uint8_t* out_mask, hipStream_t st) {
+    switch (B.h) {
 #define PSFM_CONV_CASE(HH) \
-    case HH: return launch_conv<HH, MODE>(src, M, W, H, pitch, P, taps, rbad, out, out_mask, st);
+    case HH: return launch_conv<HH, MODE>(src, M, W, H, pitch, P, a, B, bad_frac, cov_in, c_in, out, out_mask, st);
         PSFM_CONV_CASE(1) PSFM_CONV_CASE(2) PSFM_CONV_CASE(3) PSFM_CONV_CASE(4) PSFM_CONV_CASE(5)
         PSFM_CONV_CASE(6) PSFM_CONV_CASE(7) PSFM_CONV_CASE(8) PSFM_CONV_CASE(9) PSFM_CONV_CASE(10)
         PSFM_CONV_CASE(11) PSFM_CONV_CASE(12) PSFM_CONV_CASE(13) PSFM_CONV_CASE(14)
@@ -255,46 +296,41 @@ int dispatch_conv(int h, const float* src, const uint8_t* M, int W, int H, int64
 
 // raw(delta) / sum K^2 for the kernel realised at the centre of cell
 // blockIdx.x of the 3 x 3 partition; blockIdx.y chunks the offsets.
-__global__ __launch_bounds__(256) void k_cov_samples(const double* __restrict__ a,
-                                                     const double* __restrict__ kb, int nb, int ns,
-                                                     int S, int W, int H, int h,
-                                                     const double* __restrict__ cov_in, int c_in,
-                                                     double* __restrict__ samples) {
-    __shared__ double alpha[64];
+//   raw(delta) = sum_w C_in(w) sum_u K(u) K(u + delta - w)
+__global__ __launch_bounds__(256) void k_cov_samples(const double* __restrict__ a, BasisArgs B,
+                                                     int W, int H, const double* __restrict__ cov_in,
+                                                     int c_in, double* __restrict__ samples) {
+    __shared__ RealiseLds sh;
     __shared__ double Kd[(2 * PSFM_HMAX + 1) * (2 * PSFM_HMAX + 1)];
     __shared__ double red[16];
-    const int KW = 2 * h + 1, T = KW * KW;
+    const int h = B.h, KW = 2 * h + 1, T = KW * KW;
     const int R = 2 * h + c_in, Rw = 2 * R + 1;
     const int j = blockIdx.x, tid = threadIdx.x;
     const int jx = j % 3, jy = j / 3;
     const int cx0 = jx * W / 3, cx1 = (jx + 1) * W / 3, cy0 = jy * H / 3, cy1 = (jy + 1) * H / 3;
-    local_alpha(a, nb, ns, S, 0.5 * (cx0 + cx1 - 1), 0.5 * (cy0 + cy1 - 1), W, H, alpha);
-    __syncthreads();
+    realise_kernel(B, a, 0.5 * (cx0 + cx1 - 1), 0.5 * (cy0 + cy1 - 1), W, H, sh, Kd);
     double s2 = 0.0;
-    for (int t = tid; t < T; t += 256) {
-        double k = 0.0;
-        for (int i = 0; i < nb; i++) k += alpha[i] * kb[(size_t)i * T + t];
-        Kd[t] = k;
-        s2 += k * k;
-    }
+    for (int t = tid; t < T; t += 256) s2 += Kd[t] * Kd[t];
     const double sumk2 = psfm_block_sum(s2, red);
     const int d = blockIdx.y * 256 + tid;
     if (d >= Rw * Rw) return;
     const int dy = d / Rw - R, dx = d % Rw - R;
     const int Cw = 2 * c_in + 1;
     double raw = 0.0;
-    for (int v = -h; v <= h; v++)
-        for (int u = -h; u <= h; u++) {
-            const double ku = Kd[(v + h) * KW + (u + h)];
+    for (int wy = -c_in; wy <= c_in; wy++)
+        for (int wx = -c_in; wx <= c_in; wx++) {
+            const double cw = cov_in ? cov_in[(wy + c_in) * Cw + (wx + c_in)] : 1.0;
+            const int ex = dx - wx, ey = dy - wy;          // K(u) K(u + e)
+            if (ex < -2 * h || ex > 2 * h || ey < -2 * h || ey > 2 * h || cw == 0.0) continue;
+            const int u0 = max(-h, -h - ex), u1 = min(h, h - ex);
+            const int v0 = max(-h, -h - ey), v1 = min(h, h - ey);
             double q = 0.0;
-            for (int wy = -c_in; wy <= c_in; wy++)
-                for (int wx = -c_in; wx <= c_in; wx++) {
-                    const int u2 = dx + u - wx, v2 = dy + v - wy;
-                    if (u2 < -h || u2 > h || v2 < -h || v2 > h) continue;
-                    const double cw = cov_in ? cov_in[(wy + c_in) * Cw + (wx + c_in)] : 1.0;
-                    q += cw * Kd[(v2 + h) * KW + (u2 + h)];
-                }
-            raw += ku * q;
+            for (int v = v0; v <= v1; v++) {
+                const double* r1 = Kd + (v + h) * KW + h;
+                const double* r2 = Kd + (v + ey + h) * KW + h + ex;
+                for (int u = u0; u <= u1; u++) q += r1[u] * r2[u];
+            }
+            raw += cw * q;
         }
     samples[(size_t)j * Rw * Rw + d] = sumk2 > 0.0 ? raw / sumk2 : 0.0;
 }
@@ -411,13 +447,9 @@ constexpr int SUB_BLOCKS = 1024;
 
 namespace psfm {
 
-size_t conv_workspace(const psfm_context* ctx, int W, int H) {
-    const int np = n_patches(ctx, W, H);
+size_t conv_workspace(const psfm_context* ctx, int, int) {
     const int R = 2 * ctx->h + 32;   // room for cov_in_half up to 32
     Carver c(nullptr);
-    c.take<float>((size_t)np * ctx->T);
-    c.take<float>((size_t)np * ctx->T);
-    c.take<int>(np);
     c.take<double>((size_t)PSFM_COV_SAMPLES * (2 * R + 1) * (2 * R + 1));
     c.take<double>((size_t)(2 * R + 1) * (2 * R + 1));
     return c.off;
@@ -431,6 +463,21 @@ size_t subtract_workspace(const psfm_context*, int, int) {
 
 }  // namespace psfm
 
+static BasisArgs basis_args(const psfm_context* ctx) {
+    BasisArgs B;
+    B.fac64 = ctx->fac64;
+    B.psi64 = ctx->psi64;
+    B.z = ctx->term_z;
+    B.rowf = ctx->term_rowf;
+    B.colf = ctx->term_colf;
+    B.nb = ctx->nb;
+    B.nf = ctx->nf;
+    B.ns = ctx->ns;
+    B.S = ctx->cfg.spatial_order;
+    B.h = ctx->h;
+    return B;
+}
+
 static int check_image_args(const psfm_context* ctx, int W, int H, int64_t pitch) {
     if (!ctx) return PSFM_ERR_INVALID_ARG;
     if (W < 1 || H < 1 || pitch < W) return PSFM_ERR_SHAPE;
@@ -443,19 +490,12 @@ extern "C" int psfm_convolve_image(const psfm_context* ctx, const double* coeffs
     int rc = check_image_args(ctx, W, H, pitch);
     if (rc) return rc;
     if (!coeffs || !I || !M || !out || !out_mask) return PSFM_ERR_INVALID_ARG;
-    if (!ws || ws_bytes < psfm::conv_workspace(ctx, W, H)) return PSFM_ERR_WORKSPACE;
+    (void)ws;
+    (void)ws_bytes;
     hipStream_t st = (hipStream_t)stream;
-    const int np = psfm::n_patches(ctx, W, H);
-    psfm::Carver c(ws);
-    float* taps = c.take<float>((size_t)np * ctx->T);
-    c.take<float>((size_t)np * ctx->T);
-    int* rbad = c.take<int>(np);
     const psfm_config& cf = ctx->cfg;
-    hipLaunchKernelGGL(k_patch_kernels, dim3(np), dim3(256), 0, st, coeffs, ctx->kb64, ctx->nb,
-                       ctx->ns, cf.spatial_order, W, H, cf.patch, ctx->h, (const double*)nullptr, 0,
-                       cf.bad_frac, taps, (float*)nullptr, rbad);
-    PSFM_HIP_CHECK(hipGetLastError());
-    return dispatch_conv<0>(ctx->h, I, M, W, H, pitch, cf.patch, taps, rbad, out, out_mask, st);
+    return dispatch_conv<0>(I, M, W, H, pitch, cf.patch, coeffs, basis_args(ctx), cf.bad_frac, nullptr,
+                            0, out, out_mask, st);
 }
 
 extern "C" int psfm_propagate_variance(const psfm_context* ctx, const double* coeffs,
@@ -472,25 +512,17 @@ extern "C" int psfm_propagate_variance(const psfm_context* ctx, const double* co
     if (!cov_in) cov_in_half = 0;
     if (!ws || ws_bytes < psfm::conv_workspace(ctx, W, H)) return PSFM_ERR_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
-    const int np = psfm::n_patches(ctx, W, H);
     psfm::Carver c(ws);
-    c.take<float>((size_t)np * ctx->T);
-    float* taps2 = c.take<float>((size_t)np * ctx->T);
-    c.take<int>(np);
     const int Rmax = 2 * ctx->h + 32;
     double* samples = c.take<double>((size_t)PSFM_COV_SAMPLES * (2 * Rmax + 1) * (2 * Rmax + 1));
     double* avg = c.take<double>((size_t)(2 * Rmax + 1) * (2 * Rmax + 1));
     const psfm_config& cf = ctx->cfg;
-    hipLaunchKernelGGL(k_patch_kernels, dim3(np), dim3(256), 0, st, coeffs, ctx->kb64, ctx->nb,
-                       ctx->ns, cf.spatial_order, W, H, cf.patch, ctx->h, cov_in, cov_in_half,
-                       cf.bad_frac, (float*)nullptr, taps2, (int*)nullptr);
-    PSFM_HIP_CHECK(hipGetLastError());
-    rc = dispatch_conv<1>(ctx->h, V, M, W, H, pitch, cf.patch, taps2, nullptr, var_out, nullptr, st);
+    rc = dispatch_conv<1>(V, M, W, H, pitch, cf.patch, coeffs, basis_args(ctx), cf.bad_frac, cov_in,
+                          cov_in_half, var_out, nullptr, st);
     if (rc) return rc;
     const int R = 2 * ctx->h + cov_in_half, Rw = 2 * R + 1;
     hipLaunchKernelGGL(k_cov_samples, dim3(PSFM_COV_SAMPLES, (Rw * Rw + 255) / 256), dim3(256), 0, st,
-                       coeffs, ctx->kb64, ctx->nb, ctx->ns, cf.spatial_order, W, H, ctx->h, cov_in,
-                       cov_in_half, samples);
+                       coeffs, basis_args(ctx), W, H, cov_in, cov_in_half, samples);
     hipLaunchKernelGGL(k_cov_finish, dim3(1), dim3(256), 0, st, samples, R, avg, cov_out,
                        cov_out_half, stats);
     PSFM_HIP_CHECK(hipGetLastError());

@@ -13,8 +13,10 @@
 //      the 64-column weighted row block is then folded into the Gram
 //      G = A~^T A~ with v_mfma_f32_16x16x4f32 (10 lower 16x16 blocks, spread
 //      over the 4 waves);
-//   4. the band's partial Gram is written in FP32; a second kernel adds the
-//      bands of each stamp in FP64 and scatters M_s, b_s, e_s.
+//      The MFMA accumulators (FP32) are flushed into FP64 registers after
+//      every stamp row, so FP32 sums never span more than 2r+1 pixels;
+//   4. the band's partial Gram is written in FP64; a second kernel adds the
+//      bands of each stamp and scatters M_s, b_s, e_s.
 #include "internal.h"
 
 namespace {
@@ -53,7 +55,7 @@ __global__ __launch_bounds__(256) void k_fit_band(
     const float* __restrict__ V2, const uint8_t* __restrict__ M2, int W, int H, int64_t pitch,
     const int32_t* __restrict__ xy, int r, int nbands, const float* __restrict__ fac,
     const int* __restrict__ rowf, const int* __restrict__ colf, const float* __restrict__ psi,
-    const float* __restrict__ zf, int nb, int nf, float* __restrict__ part,
+    const float* __restrict__ zf, int nb, int nf, double* __restrict__ part,
     int* __restrict__ band_flags) {
     constexpr int KW = 2 * H_ + 1;
     extern __shared__ float lds[];
@@ -126,12 +128,24 @@ __global__ __launch_bounds__(256) void k_fit_band(
         }
     }
     if (fl) atomicOr(&s_flags, fl);
-    __syncthreads();
+    // Offset: the window mean c is removed before the basis convolution and
+    // added back to term 0 only (every other term sums to zero, so it is
+    // blind to a constant).  The FP32 rounding of the zero-sum terms then
+    // scales with |I1 - c| instead of |I1| (the sky).
+    double wsum = 0.0;
+    {
+        const int rows = nbr + 2 * H_;
+        for (int e = tid; e < rows * WC; e += 256) wsum += win[e];
+    }
+    __shared__ double red[16];
+    const float cshift = (float)(psfm_block_sum(wsum, red) / ((nbr + 2 * H_) * WC));
     const int flags = s_flags;
     if (flags) {
         if (tid == 0) band_flags[blockIdx.x] = flags;
         return;
     }
+    for (int e = tid; e < (nbr + 2 * H_) * WC; e += 256) win[e] -= cshift;
+    __syncthreads();
 
     // ---- 2. column pass: colb[f][br][wc] = sum_v f(v) I1(wc, br - v)
     for (int item = tid; item < nf * WC; item += 256) {
@@ -156,8 +170,13 @@ __global__ __launch_bounds__(256) void k_fit_band(
     // ---- 3. rows of the band
     const int lane = tid & 63, wave = tid >> 6;
     floatx4 acc[3];
+    double acc64[3][4];
 #pragma unroll
-    for (int q = 0; q < 3; q++) acc[q] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int q = 0; q < 3; q++) {
+        acc[q] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int e = 0; e < 4; e++) acc64[q][e] = 0.0;
+    }
     const int nseg = (NPX + SEG - 1) / SEG;
     for (int br = 0; br < nbr; br++) {
         // 3a. row pass: Rb[x][i] = sum_u f_{j,p}(u) colb[f_{j,q}][br][x + 2h - uu]
@@ -187,7 +206,8 @@ __global__ __launch_bounds__(256) void k_fit_band(
             float v = 0.0f;
             if (x < NPX) {
                 const float sw = swb[br * NPX + x];
-                if (c < nb) v = sw * (psib[c] * Rb[x * nb + c] - zb[c] * (psib[0] * Rb[x * nb]));
+                if (c < nb) v = sw * (psib[c] * Rb[x * nb + c] - zb[c] * (psib[0] * Rb[x * nb]) +
+                                      (c == 0 ? cshift : 0.0f));
                 else if (c == nb) v = sw;
                 else if (c == nb + 1) v = dtb[br * NPX + x];
             }
@@ -218,12 +238,19 @@ __global__ __launch_bounds__(256) void k_fit_band(
                 acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a3, a3, acc[1], 0, 0, 0);
             }
         }
+        // FP32 MFMA sums cover one stamp row; rows are added in FP64.
+#pragma unroll
+        for (int q = 0; q < 3; q++) {
+#pragma unroll
+            for (int e = 0; e < 4; e++) acc64[q][e] += (double)acc[q][e];
+            acc[q] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        }
         // Rb may be rewritten only after every wave finished 3b (barrier above);
         // At is rewritten after the barrier that follows the next row pass.
     }
 
     // ---- 4. partial Gram out: rows 16 bm + 4 (lane / 16) + q, column 16 bn + lane % 16
-    float* G = part + (size_t)blockIdx.x * GC * GC;
+    double* G = part + (size_t)blockIdx.x * GC * GC;
     const int bms[4][3] = {{0, 1, 1}, {2, 2, 2}, {3, 3, -1}, {3, 3, -1}};
     const int bns[4][3] = {{0, 0, 1}, {0, 1, 2}, {0, 1, -1}, {2, 3, -1}};
 #pragma unroll
@@ -232,13 +259,13 @@ __global__ __launch_bounds__(256) void k_fit_band(
         if (bm < 0) continue;
         const int col = 16 * bn + (lane & 15);
 #pragma unroll
-        for (int e = 0; e < 4; e++) G[(16 * bm + 4 * (lane >> 4) + e) * GC + col] = acc[q][e];
+        for (int e = 0; e < 4; e++) G[(16 * bm + 4 * (lane >> 4) + e) * GC + col] = acc64[q][e];
     }
     if (tid == 0) band_flags[blockIdx.x] = 0;
 }
 
 // Sum of the band partials of each stamp in FP64 and scatter to M_s, b_s, e_s.
-__global__ __launch_bounds__(256) void k_fit_reduce(const float* __restrict__ part,
+__global__ __launch_bounds__(256) void k_fit_reduce(const double* __restrict__ part,
                                                     const int* __restrict__ band_flags, int nbands,
                                                     int nb, int npix, double* __restrict__ Ms,
                                                     double* __restrict__ bs, double* __restrict__ es,
@@ -251,20 +278,20 @@ __global__ __launch_bounds__(256) void k_fit_reduce(const float* __restrict__ pa
     if (fl & PSFM_STAMP_INVALID) fl = PSFM_STAMP_INVALID;
     double* M = Ms + (size_t)s * L * L;
     double* bv = bs + (size_t)s * L;
-    const float* P0 = part + (size_t)s * nbands * GC * GC;
+    const double* P0 = part + (size_t)s * nbands * GC * GC;
     for (int e = tid; e < L * L; e += 256) {
         const int i = e / L, j = e - i * L;
         double v = 0.0;
         if (!fl) {
             const int hi = i > j ? i : j, lo = i > j ? j : i;
-            for (int b = 0; b < nbands; b++) v += (double)P0[(size_t)b * GC * GC + hi * GC + lo];
+            for (int b = 0; b < nbands; b++) v += P0[(size_t)b * GC * GC + hi * GC + lo];
         }
         M[e] = v;
     }
     for (int i = tid; i <= L; i += 256) {
         double v = 0.0;
         if (!fl)
-            for (int b = 0; b < nbands; b++) v += (double)P0[(size_t)b * GC * GC + (nb + 1) * GC + i];
+            for (int b = 0; b < nbands; b++) v += P0[(size_t)b * GC * GC + (nb + 1) * GC + i];
         if (i < L) bv[i] = v;
         else es[s] = v;
     }
@@ -277,15 +304,15 @@ __global__ __launch_bounds__(256) void k_fit_reduce(const float* __restrict__ pa
 template <int H_>
 int launch_fit(const psfm_context* ctx, const float* I1, const uint8_t* M1, const float* I2,
                const float* V2, const uint8_t* M2, int W, int H, int64_t pitch, const int32_t* xy,
-               int n, float* part, int* bflags, hipStream_t st) {
+               int n, double* part, int* bflags, hipStream_t st) {
     const int nbands = psfm::fit_bands(ctx);
     const FitLds Lo = fit_lds_layout(H_, ctx->r, ctx->nb, ctx->nf);
     const size_t lds = (size_t)Lo.total * sizeof(float);
-    static bool attr_set = false;
-    if (!attr_set) {
+    static size_t attr_set = 0;      // dynamic LDS granted so far
+    if (lds > attr_set) {
         PSFM_HIP_CHECK(hipFuncSetAttribute((const void*)k_fit_band<H_>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 64));
-        attr_set = true;
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        attr_set = lds;
     }
     hipLaunchKernelGGL(k_fit_band<H_>, dim3(n * nbands), dim3(256), lds, st, I1, M1, I2, V2, M2, W, H,
                        pitch, xy, ctx->r, nbands, ctx->fac, ctx->term_rowf, ctx->term_colf,
@@ -305,7 +332,7 @@ size_t fit_lds_bytes(const psfm_context* ctx) {
 size_t fit_workspace(const psfm_context* ctx, int n_stamps) {
     Carver c(nullptr);
     const size_t nbl = (size_t)n_stamps * fit_bands(ctx);
-    c.take<float>(nbl * GC * GC);
+    c.take<double>(nbl * GC * GC);
     c.take<int>(nbl);
     return c.off;
 }
@@ -324,13 +351,13 @@ extern "C" int psfm_fit_stamps(const psfm_context* ctx, const float* I1, const u
     if (!I1 || !M1 || !I2 || !V2 || !M2 || !stamp_xy || !stamp_M || !stamp_b || !stamp_e ||
         !stamp_npix || !stamp_flags)
         return PSFM_ERR_INVALID_ARG;
-    if (psfm::fit_lds_bytes(ctx) > 160 * 1024 - 64) return PSFM_ERR_UNSUPPORTED;
+    if (psfm::fit_lds_bytes(ctx) > 160 * 1024 - 1024) return PSFM_ERR_UNSUPPORTED;
     const size_t need = psfm::fit_workspace(ctx, n_stamps);
     if (!ws || ws_bytes < need) return PSFM_ERR_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
     psfm::Carver c(ws);
     const size_t nbl = (size_t)n_stamps * psfm::fit_bands(ctx);
-    float* part = c.take<float>(nbl * GC * GC);
+    double* part = c.take<double>(nbl * GC * GC);
     int* bflags = c.take<int>(nbl);
     int rc;
     switch (ctx->h) {

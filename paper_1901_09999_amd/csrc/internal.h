@@ -30,6 +30,8 @@ struct psfm_context {
     int* term_colf;   // [nb] factor index of the v (column-pass) profile of term i
     float* term_psi;  // [nb] normalisation of the separable product
     float* term_z;    // [nb] 1 if k_0 is subtracted (even terms i >= 1), else 0
+    double* fac64;    // [nf][KW] the 1-D factors in FP64
+    double* psi64;    // [nb] normalisations in FP64
     void* dev_block;  // single allocation backing all of the above
 };
 
@@ -88,6 +90,24 @@ __device__ __forceinline__ void psfm_spatial_terms(int S, double x, double y, in
             g[s++] = v;
         }
     }
+}
+
+// sum_s coef[s] g_s(x, y) for the spatial terms above, without a term array.
+__device__ __forceinline__ double psfm_spatial_dot(int S, double x, double y, int W, int H,
+                                                   const double* __restrict__ coef) {
+    const double xt = W > 1 ? (2.0 * x - (W - 1)) / (double)(W - 1) : 0.0;
+    const double yt = H > 1 ? (2.0 * y - (H - 1)) / (double)(H - 1) : 0.0;
+    double acc = 0.0;
+    int s = 0;
+    for (int d = 0; d <= S; d++) {
+        for (int l = d; l >= 0; l--) {
+            double v = 1.0;
+            for (int k = 0; k < l; k++) v *= xt;
+            for (int k = 0; k < d - l; k++) v *= yt;
+            acc += coef[s++] * v;
+        }
+    }
+    return acc;
 }
 
 // Fixed-order sum over a workgroup of up to 1024 threads (deterministic).

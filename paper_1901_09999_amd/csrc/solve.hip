@@ -25,7 +25,16 @@ struct SolveState {
 };
 
 constexpr int CH_NB = 32;        // Cholesky panel width
-constexpr int CH_THREADS = 1024;
+constexpr int CH_PS = 33;        // LDS row stride of the panel (doubles)
+constexpr int CH_THREADS = 512;
+constexpr int CH_NMAX = 496;     // largest system the one-workgroup solver holds
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 
 __global__ void k_solve_init(int n, int N, int ns, int S, int W, int H, int min_stamps,
                              const int32_t* __restrict__ xy, const int32_t* __restrict__ flags,
@@ -61,72 +70,113 @@ __global__ void k_solve_init(int n, int N, int ns, int S, int W, int H, int min_
     }
 }
 
-// One thread per (i, j, s) of the per-stamp index space; loops over stamps.
-__global__ void k_assemble(int n, int nb, int ns, int N, const double* __restrict__ Ms,
-                           const double* __restrict__ bs, const uint8_t* __restrict__ used,
-                           const double* __restrict__ G, double* __restrict__ M,
-                           double* __restrict__ b, const SolveState* st) {
+// One thread per (i, j, s) of the per-stamp index space; loops over stamps
+// (the stamp's weight used_k * g_k is uniform across the workgroup, so it
+// comes through the scalar cache; the loop has no data-dependent branch so
+// the per-stamp loads pipeline).
+template <int NS>
+__global__ __launch_bounds__(256) void k_assemble(int n, int nb, int N, const double* __restrict__ Ms,
+                                                  const double* __restrict__ bs,
+                                                  const double* __restrict__ GU,
+                                                  double* __restrict__ M, double* __restrict__ b,
+                                                  const SolveState* st) {
     if (st->done) return;
     const int L = nb + 1;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nm = L * L * ns;
+    const int nm = L * L * NS;
     if (t < nm) {
-        const int s = t % ns;
-        const int ij = t / ns;
+        const int s = t % NS;
+        const int ij = t / NS;
         const int i = ij / L, j = ij - i * L;
         if (i == nb && s != 0) return;
-        double acc[28];
-        const int nt = (j == nb) ? 1 : ns;
+        double acc[NS];
 #pragma unroll
-        for (int q = 0; q < 28; q++) acc[q] = 0.0;
+        for (int q = 0; q < NS; q++) acc[q] = 0.0;
+#pragma unroll 4
         for (int k = 0; k < n; k++) {
-            if (!used[k]) continue;
             const double m = Ms[(size_t)k * L * L + ij];
-            const double* g = G + (size_t)k * ns;
-            const double gm = ((i == nb) ? 1.0 : g[s]) * m;
+            const double* g = GU + (size_t)k * (NS + 1);     // g_k[0..NS), used_k
+            const double gm = ((i == nb) ? g[NS] : g[NS] * g[s]) * m;
             if (j == nb) {
                 acc[0] += gm;
             } else {
 #pragma unroll
-                for (int q = 0; q < 28; q++)
-                    if (q < nt) acc[q] += g[q] * gm;
+                for (int q = 0; q < NS; q++) acc[q] += g[q] * gm;
             }
         }
-        const int row = (i == nb) ? N - 1 : i * ns + s;
+        const int row = (i == nb) ? N - 1 : i * NS + s;
         if (j == nb) {
             M[(size_t)row * N + N - 1] = acc[0];
         } else {
 #pragma unroll
-            for (int q = 0; q < 28; q++)
-                if (q < nt) M[(size_t)row * N + j * ns + q] = acc[q];
+            for (int q = 0; q < NS; q++) M[(size_t)row * N + j * NS + q] = acc[q];
         }
-    } else if (t < nm + L * ns) {
+    } else if (t < nm + L * NS) {
         const int e = t - nm;
-        const int i = e / ns, s = e - i * ns;
+        const int i = e / NS, s = e - i * NS;
         if (i == nb && s != 0) return;
         double acc = 0.0;
         for (int k = 0; k < n; k++) {
-            if (!used[k]) continue;
-            const double gs = (i == nb) ? 1.0 : G[(size_t)k * ns + s];
+            const double* g = GU + (size_t)k * (NS + 1);
+            const double gs = (i == nb) ? g[NS] : g[NS] * g[s];
             acc += gs * bs[(size_t)k * L + i];
         }
-        b[(i == nb) ? N - 1 : i * ns + s] = acc;
+        b[(i == nb) ? N - 1 : i * NS + s] = acc;
     }
+}
+
+// Stamp weights for the assembly: GU[k] = (g_k[0..ns), used_k).
+__global__ void k_weights(int n, int ns, const double* __restrict__ G,
+                          const uint8_t* __restrict__ used, double* __restrict__ GU,
+                          const SolveState* st) {
+    if (st->done) return;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    for (int q = 0; q < ns; q++) GU[(size_t)t * (ns + 1) + q] = G[(size_t)t * ns + q];
+    GU[(size_t)t * (ns + 1) + ns] = used[t] ? 1.0 : 0.0;
 }
 
 __device__ __forceinline__ double block_sum(double v, double* red) { return psfm_block_sum(v, red); }
 
-// Equilibrated Cholesky and solve of the N x N system in A (overwritten by
-// its factor); x receives the solution.  One workgroup.
+// Equilibrated Cholesky and solve of the N x N system in A (lower triangle
+// overwritten by the factor); x receives the solution.  One workgroup.
+// Per 32-column panel (staged in LDS):
+//   * wave 0 factors the 32 x 32 diagonal block, rows in registers, the
+//     pivot column broadcast through LDS, 1/sqrt by v_rsq_f64 + 2 Newton
+//     steps (no workgroup barrier per column);
+//   * every other panel row is solved against it by its own thread
+//     (right-looking, independent FMAs per step);
+//   * the forward substitution L z = D b advances by the same 32 unknowns
+//     while the panel is in LDS;
+//   * the trailing lower triangle is updated with v_mfma_f64_16x16x4f64 on
+//     16 x 16 tiles (read-modify-write of the L2-resident workspace).
+// The back substitution L^T w = z then walks the panels in reverse, each
+// staged in LDS by a coalesced bulk load.
+typedef double double4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double rsqrt_nr(double d) {
+    double r = __builtin_amdgcn_rsq(d);
+    r = r * (1.5 - 0.5 * d * r * r);
+    r = r * (1.5 - 0.5 * d * r * r);
+    return r;
+}
+
 __global__ __launch_bounds__(CH_THREADS) void k_cholesky(int N, double* __restrict__ A,
                                                          const double* __restrict__ b,
                                                          double* __restrict__ x,
                                                          double* __restrict__ y, SolveState* st) {
     if (st->done) return;
-    extern __shared__ double P[];        // panel [N][CH_NB]
-    __shared__ double Dq[512];
+    extern __shared__ double P[];        // panel [N + 16][CH_PS]
+    __shared__ double Dq[CH_NMAX];
+    __shared__ double zb[CH_NMAX];
+    __shared__ double dinv[CH_NMAX];
+    __shared__ double part[CH_NB * (CH_THREADS / 32)];
+    __shared__ double cb[64];
     __shared__ int s_bad;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int NW = CH_THREADS / 64;
+    constexpr int NPART = CH_THREADS / 32;
+    (void)y;
     if (tid == 0) s_bad = 0;
     __syncthreads();
     for (int i = tid; i < N; i += CH_THREADS) {
@@ -145,155 +195,148 @@ __global__ __launch_bounds__(CH_THREADS) void k_cholesky(int N, double* __restri
         }
         return;
     }
-    // equilibrate the lower triangle
-    for (size_t e = tid; e < (size_t)N * N; e += CH_THREADS) {
-        const int i = (int)(e / N), j = (int)(e - (size_t)i * N);
-        if (j <= i) A[e] *= Dq[i] * Dq[j];
-    }
+    for (int i = tid; i < N; i += CH_THREADS) zb[i] = Dq[i] * b[i];
+    const int tr = tid >> 5, tc = tid & 31, TR = CH_THREADS / 32;
+    for (int i = tr; i < N; i += TR)
+        for (int j = tc; j <= i; j += 32) A[(size_t)i * N + j] *= Dq[i] * Dq[j];
     __syncthreads();
     for (int k0 = 0; k0 < N; k0 += CH_NB) {
         const int nk = min(CH_NB, N - k0);
         const int rows = N - k0;
-        for (int e = tid; e < rows * CH_NB; e += CH_THREADS) {
-            const int i = e / CH_NB, c = e - i * CH_NB;
-            P[e] = (c < nk && c <= i) ? A[(size_t)(k0 + i) * N + k0 + c] : 0.0;
-        }
+        for (int i = tr; i < rows + 16; i += TR)
+            P[i * CH_PS + tc] = (i < rows && tc < nk && (i >= nk || tc <= i))
+                                    ? A[(size_t)(k0 + i) * N + k0 + tc] : 0.0;
         __syncthreads();
-        for (int c = 0; c < nk; c++) {
-            const double piv = P[c * CH_NB + c];
-            __syncthreads();
-            if (!(piv > 0.0)) {
-                if (tid == 0) {
-                    st->info = k0 + c + 1;
-                    st->done = 1;
-                }
-                return;
-            }
-            const double lkk = sqrt(piv);
-            const double inv = 1.0 / lkk;
-            for (int i = c + 1 + tid; i < rows; i += CH_THREADS) P[i * CH_NB + c] *= inv;
-            if (tid == 0) P[c * CH_NB + c] = lkk;
-            __syncthreads();
-            const int nr = nk - c - 1;
-            if (nr > 0) {
-                for (int e = tid; e < (rows - c - 1) * nr; e += CH_THREADS) {
-                    const int i = c + 1 + e / nr, j = c + 1 + e % nr;
-                    if (j <= i) P[i * CH_NB + j] -= P[i * CH_NB + c] * P[j * CH_NB + c];
-                }
-            }
-            __syncthreads();
-        }
-        for (int e = tid; e < rows * nk; e += CH_THREADS) {
-            const int i = e / nk, c = e - i * nk;
-            if (c <= i) A[(size_t)(k0 + i) * N + k0 + c] = P[i * CH_NB + c];
-        }
-        // trailing update, 4x4 register tiles over the lower triangle of the
-        // remaining (rows - nk) x (rows - nk) block
-        const int m = rows - nk;
-        if (m > 0) {
-            const int tb = (m + 3) / 4;
-            const int ntiles = tb * (tb + 1) / 2;
-            for (int tI = tid; tI < ntiles; tI += CH_THREADS) {
-                // decode lower-triangular tile index (ti >= tj)
-                int ti = (int)((sqrt(8.0 * tI + 1.0) - 1.0) * 0.5);
-                while ((ti + 1) * (ti + 2) / 2 <= tI) ti++;
-                while (ti * (ti + 1) / 2 > tI) ti--;
-                const int tj = tI - ti * (ti + 1) / 2;
-                double acc[4][4];
-#pragma unroll
-                for (int a = 0; a < 4; a++)
-#pragma unroll
-                    for (int q = 0; q < 4; q++) acc[a][q] = 0.0;
-                const int i0 = nk + 4 * ti, j0 = nk + 4 * tj;
-                for (int c = 0; c < nk; c++) {
-                    double pi[4], pj[4];
-#pragma unroll
-                    for (int a = 0; a < 4; a++) {
-                        pi[a] = (i0 + a < rows) ? P[(i0 + a) * CH_NB + c] : 0.0;
-                        pj[a] = (j0 + a < rows) ? P[(j0 + a) * CH_NB + c] : 0.0;
-                    }
-#pragma unroll
-                    for (int a = 0; a < 4; a++)
-#pragma unroll
-                        for (int q = 0; q < 4; q++) acc[a][q] += pi[a] * pj[q];
-                }
-#pragma unroll
-                for (int a = 0; a < 4; a++)
-#pragma unroll
-                    for (int q = 0; q < 4; q++) {
-                        const int i = i0 + a, j = j0 + q;
-                        if (i < rows && j <= i) A[(size_t)(k0 + i) * N + (k0 + j)] -= acc[a][q];
-                    }
-            }
-        }
-        __syncthreads();
-    }
-    // Forward substitution L z = D b, then back substitution L^T w = z, in
-    // blocks of 32 unknowns: the off-diagonal part of each block is a
-    // parallel (coalesced) matrix-vector product, the 32 x 32 diagonal
-    // system is solved by one wave from LDS.
-    double* zb = P;                       // [N] right-hand side / solution
-    double* Dg = P + 512;                 // [32][33] diagonal block
-    double* part = P + 512 + 32 * 33;     // [32][32] partial dot products
-    for (int i = tid; i < N; i += CH_THREADS) zb[i] = Dq[i] * b[i];
-    __syncthreads();
-    const int lane = tid & 63, wave = tid >> 6;
-    for (int k0 = 0; k0 < N; k0 += 32) {
-        const int nk = min(32, N - k0);
-        // part[r][w] = sum_{p in chunk w} L[k0+r][p] z[p], p < k0
-        {
-            const int r = tid >> 5, w = tid & 31;      // 32 rows x 32 chunks
-            double acc = 0.0;
-            if (r < nk)
-                for (int p = w; p < k0; p += 32) acc += A[(size_t)(k0 + r) * N + p] * zb[p];
-            part[r * 32 + w] = acc;
-            for (int e = tid; e < nk * nk; e += CH_THREADS) {
-                const int i = e / nk, c = e - i * nk;
-                Dg[i * 33 + c] = c <= i ? A[(size_t)(k0 + i) * N + k0 + c] : 0.0;
-            }
-        }
-        __syncthreads();
+        // ---- diagonal block (wave 0)
         if (wave == 0) {
-            double v = 0.0;
-            if (lane < nk) {
-                v = zb[k0 + lane];
-                for (int w = 0; w < 32; w++) v -= part[lane * 32 + w];
+            double r[CH_NB];
+#pragma unroll
+            for (int c = 0; c < CH_NB; c++) r[c] = lane < nk ? P[lane * CH_PS + c] : 0.0;
+            int bad = 0;
+#pragma unroll
+            for (int c = 0; c < CH_NB; c++) {
+                if (c < nk && !bad) {
+                    if (lane < CH_NB) cb[lane] = r[c];
+                    wave_sync();
+                    const double d = cb[c];
+                    if (!(d > 0.0)) {
+                        bad = c + 1;
+                    } else {
+                        const double inv = rsqrt_nr(d);
+                        const double t = (lane > c && lane < nk) ? r[c] * inv * inv : 0.0;
+#pragma unroll
+                        for (int j = c + 1; j < CH_NB; j++) r[j] -= t * cb[j];
+                        r[c] = lane == c ? d * inv : (lane > c ? r[c] * inv : r[c]);
+                        if (lane == 0) dinv[k0 + c] = inv;
+                    }
+                    wave_sync();
+                }
             }
+            if (lane < nk) {
+#pragma unroll
+                for (int c = 0; c < CH_NB; c++) P[lane * CH_PS + c] = c <= lane ? r[c] : 0.0;
+            }
+            if (lane == 0) s_bad = bad;
+        }
+        __syncthreads();
+        if (s_bad) {
+            if (tid == 0) {
+                st->info = k0 + s_bad;
+                st->done = 1;
+            }
+            return;
+        }
+        // ---- panel rows below the diagonal block: a L_diag^T = row
+        for (int i = nk + tid; i < rows; i += CH_THREADS) {
+            double a[CH_NB];
+#pragma unroll
+            for (int c = 0; c < CH_NB; c++) a[c] = P[i * CH_PS + c];
+#pragma unroll
+            for (int c = 0; c < CH_NB; c++) {
+                if (c < nk) {
+                    a[c] *= dinv[k0 + c];
+#pragma unroll
+                    for (int q = c + 1; q < CH_NB; q++) a[q] -= a[c] * P[q * CH_PS + c];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < CH_NB; c++) P[i * CH_PS + c] = a[c];
+        }
+        // ---- forward substitution for this block of unknowns (wave 0)
+        if (wave == 0) {
+            double v = lane < nk ? zb[k0 + lane] : 0.0;
             for (int c = 0; c < nk; c++) {
-                const double vc = __shfl(v, c) / Dg[c * 33 + c];
+                const double vc = __shfl(v, c) * dinv[k0 + c];
                 if (lane == c) v = vc;
-                if (lane > c && lane < nk) v -= Dg[lane * 33 + c] * vc;
+                if (lane > c && lane < nk) v -= P[lane * CH_PS + c] * vc;
             }
             if (lane < nk) zb[k0 + lane] = v;
         }
         __syncthreads();
+        for (int i = nk + tid; i < rows; i += CH_THREADS) {
+            double acc = 0.0;
+            for (int c = 0; c < nk; c++) acc += P[i * CH_PS + c] * zb[k0 + c];
+            zb[k0 + i] -= acc;
+        }
+        for (int i = tr; i < rows; i += TR)
+            if (tc < nk && (i >= nk || tc <= i)) A[(size_t)(k0 + i) * N + k0 + tc] = P[i * CH_PS + tc];
+        // ---- trailing update on FP64 MFMA: 16 x 16 tiles of the lower triangle
+        const int m = rows - nk;
+        if (m > 0) {
+            const int mt = (m + 15) / 16;
+            const int ntile = mt * (mt + 1) / 2;
+            for (int tI = wave; tI < ntile; tI += NW) {
+                int ti = (int)((sqrt(8.0 * tI + 1.0) - 1.0) * 0.5);
+                while ((ti + 1) * (ti + 2) / 2 <= tI) ti++;
+                while (ti * (ti + 1) / 2 > tI) ti--;
+                const int tj = tI - ti * (ti + 1) / 2;
+                const int i0 = nk + 16 * ti, j0 = nk + 16 * tj;
+                const int jj = j0 + (lane & 15);
+                double4v c;
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const int ii = i0 + (lane >> 4) + 4 * e;   // f64 MFMA D layout
+                    c[e] = (ii < rows && jj <= ii) ? A[(size_t)(k0 + ii) * N + k0 + jj] : 0.0;
+                }
+                const double* pa = P + (i0 + (lane & 15)) * CH_PS + (lane >> 4);
+                const double* pb = P + (j0 + (lane & 15)) * CH_PS + (lane >> 4);
+#pragma unroll
+                for (int cc = 0; cc < CH_NB; cc += 4)
+                    c = __builtin_amdgcn_mfma_f64_16x16x4f64(-pa[cc], pb[cc], c, 0, 0, 0);
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const int ii = i0 + (lane >> 4) + 4 * e;   // f64 MFMA D layout
+                    if (ii < rows && jj <= ii) A[(size_t)(k0 + ii) * N + k0 + jj] = c[e];
+                }
+            }
+        }
+        __syncthreads();
     }
-    for (int k1 = N; k1 > 0; k1 -= 32) {
-        const int k0 = k1 >= 32 ? k1 - 32 : 0;
-        const int nk = k1 - k0;
-        // part[c][w] = sum_{p >= k1, p in chunk w} L[p][k0+c] w[p]
+    // ---- back substitution L^T w = z, panels in reverse
+    for (int k0 = ((N - 1) / CH_NB) * CH_NB; k0 >= 0; k0 -= CH_NB) {
+        const int nk = min(CH_NB, N - k0);
+        const int rows = N - k0;
+        for (int i = tr; i < rows; i += TR)
+            P[i * CH_PS + tc] = (tc < nk && (i >= nk || tc <= i)) ? A[(size_t)(k0 + i) * N + k0 + tc] : 0.0;
+        __syncthreads();
         {
             const int c = tid & 31, w = tid >> 5;
             double acc = 0.0;
             if (c < nk)
-                for (int p = k1 + w; p < N; p += 32) acc += A[(size_t)p * N + k0 + c] * zb[p];
-            part[c * 32 + w] = acc;
-            for (int e = tid; e < nk * nk; e += CH_THREADS) {
-                const int i = e / nk, cc = e - i * nk;
-                Dg[i * 33 + cc] = cc <= i ? A[(size_t)(k0 + i) * N + k0 + cc] : 0.0;
-            }
+                for (int i = nk + w; i < rows; i += NPART) acc += P[i * CH_PS + c] * zb[k0 + i];
+            part[c * NPART + w] = acc;
         }
         __syncthreads();
         if (wave == 0) {
             double v = 0.0;
             if (lane < nk) {
                 v = zb[k0 + lane];
-                for (int w = 0; w < 32; w++) v -= part[lane * 32 + w];
+                for (int w = 0; w < NPART; w++) v -= part[lane * NPART + w];
             }
             for (int c = nk - 1; c >= 0; c--) {
-                const double vc = __shfl(v, c) / Dg[c * 33 + c];
+                const double vc = __shfl(v, c) * dinv[k0 + c];
                 if (lane == c) v = vc;
-                if (lane < c) v -= Dg[c * 33 + lane] * vc;
+                if (lane < c) v -= P[c * CH_PS + lane] * vc;
             }
             if (lane < nk) zb[k0 + lane] = v;
         }
@@ -328,20 +371,20 @@ __global__ __launch_bounds__(1024) void k_chi2_clip(
             }
             alpha[wave][lane] = al;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        wave_sync();
+        // lane j: u_j = sum_i alpha_i M_s[i][j] (row-wise coalesced reads)
         double part = 0.0;
         if (lane < L) {
-            const double* Mr = Ms + (size_t)s * L * L + (size_t)lane * L;
-            double tq = 0.0;
-            for (int j = 0; j < L; j++) tq += Mr[j] * alpha[wave][j];
+            const double* Mc = Ms + (size_t)s * L * L + lane;
+            double u = 0.0;
+#pragma unroll 8
+            for (int i = 0; i < L; i++) u += alpha[wave][i] * Mc[(size_t)i * L];
             const double al = alpha[wave][lane];
-            part = al * tq - 2.0 * al * bs[(size_t)s * L + lane];
+            part = al * u - 2.0 * al * bs[(size_t)s * L + lane];
         }
         for (int o = 32; o > 0; o >>= 1) part += __shfl_down(part, o);
         if (lane == 0) chi2[s] = es[s] + part;
-        __builtin_amdgcn_wave_barrier();
+        wave_sync();
     }
     __syncthreads();
     if (tid == 0) st->n_iter += 1;
@@ -443,6 +486,7 @@ size_t solve_workspace(const psfm_context* ctx, int n) {
     c.take<uint8_t>(n + 1);
     c.take<uint8_t>(n + 1);
     c.take<double>((size_t)n * ctx->ns + 1);
+    c.take<double>((size_t)n * (ctx->ns + 1) + 1);
     c.take<double>((size_t)ctx->N * ctx->N);
     c.take<double>(ctx->N);
     c.take<double>(ctx->N);
@@ -461,27 +505,28 @@ extern "C" int psfm_solve(const psfm_context* ctx, int W, int H, const int32_t* 
     if (n_stamps > 0 && (!stamp_xy || !stamp_M || !stamp_b || !stamp_e || !stamp_npix ||
                          !stamp_flags || !stamp_chi2))
         return PSFM_ERR_INVALID_ARG;
-    if (ctx->N > 512) return PSFM_ERR_UNSUPPORTED;
+    if (ctx->N > CH_NMAX) return PSFM_ERR_UNSUPPORTED;
     const size_t need = psfm::solve_workspace(ctx, n_stamps);
     if (!ws || ws_bytes < need) return PSFM_ERR_WORKSPACE;
-    const size_t lds = (size_t)std::max(ctx->N * CH_NB, 2600) * sizeof(double);
-    if (lds > 150 * 1024) return PSFM_ERR_UNSUPPORTED;
+    const size_t lds = (size_t)(ctx->N + 16) * CH_PS * sizeof(double);
+    if (lds > 140 * 1024) return PSFM_ERR_UNSUPPORTED;
     hipStream_t st = (hipStream_t)stream;
     psfm::Carver c(ws);
     SolveState* state = c.take<SolveState>(1);
     uint8_t* used = c.take<uint8_t>(n_stamps + 1);
     uint8_t* fitted = c.take<uint8_t>(n_stamps + 1);
     double* G = c.take<double>((size_t)n_stamps * ctx->ns + 1);
+    double* GU = c.take<double>((size_t)n_stamps * (ctx->ns + 1) + 1);
     double* M = c.take<double>((size_t)ctx->N * ctx->N);
     double* b = c.take<double>(ctx->N);
     double* y = c.take<double>(ctx->N);
     const int nb = ctx->nb, ns = ctx->ns, N = ctx->N, L = ctx->L;
     const psfm_config& cf = ctx->cfg;
-    static bool attr_set = false;
-    if (!attr_set) {
+    static size_t attr_set = 0;      // dynamic LDS granted so far
+    if (lds > attr_set) {
         PSFM_HIP_CHECK(hipFuncSetAttribute((const void*)k_cholesky,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024));
-        attr_set = true;
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        attr_set = lds;
     }
     const int nt = std::max(n_stamps, N);
     hipLaunchKernelGGL(k_solve_init, dim3((nt + 255) / 256), dim3(256), 0, st, n_stamps, N, ns,
@@ -490,8 +535,17 @@ extern "C" int psfm_solve(const psfm_context* ctx, int W, int H, const int32_t* 
     PSFM_HIP_CHECK(hipGetLastError());
     const int nthreads_asm = L * L * ns + L * ns;
     for (int it = 0; it < cf.max_iter; it++) {
-        hipLaunchKernelGGL(k_assemble, dim3((nthreads_asm + 255) / 256), dim3(256), 0, st, n_stamps,
-                           nb, ns, N, stamp_M, stamp_b, used, G, M, b, state);
+        hipLaunchKernelGGL(k_weights, dim3((n_stamps + 255) / 256 + 1), dim3(256), 0, st, n_stamps, ns,
+                           G, used, GU, state);
+        const dim3 ag((nthreads_asm + 255) / 256);
+        switch (ns) {
+#define PSFM_ASM_CASE(NSV) \
+    case NSV: hipLaunchKernelGGL(k_assemble<NSV>, ag, dim3(256), 0, st, n_stamps, nb, N, stamp_M, stamp_b, GU, M, b, state); break;
+            PSFM_ASM_CASE(1) PSFM_ASM_CASE(3) PSFM_ASM_CASE(6) PSFM_ASM_CASE(10) PSFM_ASM_CASE(15)
+            PSFM_ASM_CASE(21) PSFM_ASM_CASE(28)
+#undef PSFM_ASM_CASE
+            default: return PSFM_ERR_UNSUPPORTED;
+        }
         hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(CH_THREADS), lds, st, N, M, b, coeffs, y, state);
         hipLaunchKernelGGL(k_chi2_clip, dim3(1), dim3(1024), 0, st, n_stamps, nb, ns, N, cf.max_iter,
                            cf.min_stamps, cf.clip_sigma, stamp_M, stamp_b, stamp_e, stamp_npix, G,

@@ -1,0 +1,72 @@
+"""The C interface without a GPU: the built library loads, exports every
+function declared in include/psfm.h, and rejects bad arguments on the host
+before anything is launched."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "psfm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(psfm_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1901_09999_amd import psfm
+    if not os.path.exists(psfm.LIB_PATH):
+        pytest.skip("libpsfm.so not built")
+    return psfm.lib()
+
+
+def test_header_declares_the_hot_path():
+    names = declared_functions()
+    for f in ("psfm_fit_stamps", "psfm_solve", "psfm_convolve_image", "psfm_propagate_variance",
+              "psfm_subtract"):
+        assert f in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_binding_covers_header():
+    from paper_1901_09999_amd import psfm
+    assert set(psfm.exported_symbols()) == set(declared_functions())
+
+
+def test_host_argument_checks(lib):
+    from paper_1901_09999_amd import psfm
+    cfg = psfm.CConfig()
+    lib.psfm_config_default(C.byref(cfg))
+    assert cfg.n_gauss == 3 and cfg.half_width == 10 and list(cfg.degree[:3]) == [6, 4, 2]
+    assert abs(cfg.bad_frac - 0.2) < 1e-15 and cfg.max_iter == 3 and cfg.min_stamps == 3
+    h = C.c_void_p()
+    assert lib.psfm_create(None, C.byref(h)) == -1
+    bad = psfm.CConfig()
+    lib.psfm_config_default(C.byref(bad))
+    bad.n_gauss = 0
+    assert lib.psfm_create(C.byref(bad), C.byref(h)) == -1
+    bad.n_gauss = 3
+    bad.sigma[1] = -1.0
+    assert lib.psfm_create(C.byref(bad), C.byref(h)) == -1
+    lib.psfm_config_default(C.byref(bad))
+    bad.half_width = 40
+    assert lib.psfm_create(C.byref(bad), C.byref(h)) == -7
+    lib.psfm_config_default(C.byref(bad))
+    bad.degree[0] = 9                     # 55 + 15 + 6 terms: beyond the 64-column Gram
+    assert lib.psfm_create(C.byref(bad), C.byref(h)) == -7
+    assert lib.psfm_workspace_bytes(None, 10, 10, 1) == 0
+    assert lib.psfm_fit_stamps(None, *([None] * 5), 10, 10, 10, None, 1, *([None] * 5), None, 0,
+                               None) == -1
+    assert lib.psfm_solve(None, 10, 10, None, 1, *([None] * 8), None, 0, None) == -1
+    assert lib.psfm_convolve_image(None, None, None, None, 10, 10, 10, None, None, None, 0, None) == -1
+    for code in range(-7, 1):
+        assert lib.psfm_status_string(code).decode()
