@@ -70,33 +70,60 @@ __global__ void k_solve_init(int n, int N, int ns, int S, int W, int H, int min_
     }
 }
 
-// One thread per (i, j, s) of the per-stamp index space; loops over stamps
-// (the stamp's weight used_k * g_k is uniform across the workgroup, so it
-// comes through the scalar cache; the loop has no data-dependent branch so
-// the per-stamp loads pipeline).
+// Stamp-major copy of the stamp sums: Mt[ij][k] = M_k[ij], bt[i][k] = b_k[i],
+// so that the assembly reads each (i, j) entry of all stamps contiguously.
+__global__ void k_transpose_sums(int n, int L, const double* __restrict__ Ms,
+                                 const double* __restrict__ bs, double* __restrict__ Mt,
+                                 double* __restrict__ bt) {
+    const int LL = L * L;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < (size_t)n * (LL + L);
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(e % n);
+        const size_t r = e / n;
+        if (r < (size_t)LL) Mt[r * n + k] = Ms[(size_t)k * LL + r];
+        else bt[(r - LL) * n + k] = bs[(size_t)k * L + (r - LL)];
+    }
+}
+
+// One item per (i, j, s) of the per-stamp index space, 32 items per
+// workgroup; the stamps are split over 8 threads per item (stamp-major
+// sums, so consecutive stamps are consecutive words) and the partial sums
+// are added in LDS in a fixed order.
+constexpr int ASM_ITEMS = 32, ASM_CHUNKS = 8;
+
 template <int NS>
-__global__ __launch_bounds__(256) void k_assemble(int n, int nb, int N, const double* __restrict__ Ms,
-                                                  const double* __restrict__ bs,
+__global__ __launch_bounds__(256) void k_assemble(int n, int nb, int N, const double* __restrict__ Mt,
+                                                  const double* __restrict__ bt,
                                                   const double* __restrict__ GU,
                                                   double* __restrict__ M, double* __restrict__ b,
                                                   const SolveState* st) {
     if (st->done) return;
+    __shared__ double red[ASM_ITEMS][ASM_CHUNKS][NS];
     const int L = nb + 1;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int chunk = threadIdx.x % ASM_CHUNKS, li = threadIdx.x / ASM_CHUNKS;
+    const int t = blockIdx.x * ASM_ITEMS + li;
     const int nm = L * L * NS;
-    if (t < nm) {
-        const int s = t % NS;
-        const int ij = t / NS;
-        const int i = ij / L, j = ij - i * L;
-        if (i == nb && s != 0) return;
-        double acc[NS];
+    double acc[NS];
 #pragma unroll
-        for (int q = 0; q < NS; q++) acc[q] = 0.0;
-#pragma unroll 4
-        for (int k = 0; k < n; k++) {
-            const double m = Ms[(size_t)k * L * L + ij];
+    for (int q = 0; q < NS; q++) acc[q] = 0.0;
+    int kind = 0, i = 0, j = 0, s = 0, ij = 0;
+    if (t < nm) {
+        s = t % NS;
+        ij = t / NS;
+        i = ij / L;
+        j = ij - i * L;
+        kind = (i == nb && s != 0) ? 0 : 1;
+    } else if (t < nm + L * NS) {
+        const int e = t - nm;
+        i = e / NS;
+        s = e - i * NS;
+        kind = (i == nb && s != 0) ? 0 : 2;
+    }
+    if (kind == 1) {
+        const double* mrow = Mt + (size_t)ij * n;
+        for (int k = chunk; k < n; k += ASM_CHUNKS) {
             const double* g = GU + (size_t)k * (NS + 1);     // g_k[0..NS), used_k
-            const double gm = ((i == nb) ? g[NS] : g[NS] * g[s]) * m;
+            const double gm = ((i == nb) ? g[NS] : g[NS] * g[s]) * mrow[k];
             if (j == nb) {
                 acc[0] += gm;
             } else {
@@ -104,6 +131,24 @@ __global__ __launch_bounds__(256) void k_assemble(int n, int nb, int N, const do
                 for (int q = 0; q < NS; q++) acc[q] += g[q] * gm;
             }
         }
+    } else if (kind == 2) {
+        const double* brow = bt + (size_t)i * n;
+        for (int k = chunk; k < n; k += ASM_CHUNKS) {
+            const double* g = GU + (size_t)k * (NS + 1);
+            acc[0] += ((i == nb) ? g[NS] : g[NS] * g[s]) * brow[k];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NS; q++) red[li][chunk][q] = acc[q];
+    __syncthreads();
+    if (chunk != 0 || kind == 0) return;
+#pragma unroll
+    for (int q = 0; q < NS; q++) {
+        double v = 0.0;
+        for (int c = 0; c < ASM_CHUNKS; c++) v += red[li][c][q];
+        acc[q] = v;
+    }
+    if (kind == 1) {
         const int row = (i == nb) ? N - 1 : i * NS + s;
         if (j == nb) {
             M[(size_t)row * N + N - 1] = acc[0];
@@ -111,17 +156,8 @@ __global__ __launch_bounds__(256) void k_assemble(int n, int nb, int N, const do
 #pragma unroll
             for (int q = 0; q < NS; q++) M[(size_t)row * N + j * NS + q] = acc[q];
         }
-    } else if (t < nm + L * NS) {
-        const int e = t - nm;
-        const int i = e / NS, s = e - i * NS;
-        if (i == nb && s != 0) return;
-        double acc = 0.0;
-        for (int k = 0; k < n; k++) {
-            const double* g = GU + (size_t)k * (NS + 1);
-            const double gs = (i == nb) ? g[NS] : g[NS] * g[s];
-            acc += gs * bs[(size_t)k * L + i];
-        }
-        b[(i == nb) ? N - 1 : i * NS + s] = acc;
+    } else {
+        b[(i == nb) ? N - 1 : i * NS + s] = acc[0];
     }
 }
 
@@ -141,17 +177,20 @@ __device__ __forceinline__ double block_sum(double v, double* red) { return psfm
 // Equilibrated Cholesky and solve of the N x N system in A (lower triangle
 // overwritten by the factor); x receives the solution.  One workgroup.
 // Per 32-column panel (staged in LDS):
-//   * wave 0 factors the 32 x 32 diagonal block, rows in registers, the
-//     pivot column broadcast through LDS, 1/sqrt by v_rsq_f64 + 2 Newton
-//     steps (no workgroup barrier per column);
-//   * every other panel row is solved against it by its own thread
-//     (right-looking, independent FMAs per step);
-//   * the forward substitution L z = D b advances by the same 32 unknowns
-//     while the panel is in LDS;
+//   * wave 0 factors the 32 x 32 diagonal block: rows in registers, the
+//     pivot column broadcast through a double-buffered LDS column that is
+//     published before the rest of the row updates (one column of
+//     look-ahead inside the wave); 1/sqrt by v_rsq_f64 + 2 Newton steps;
+//   * wave 0 then inverts the two 16 x 16 diagonal sub-blocks (one column of
+//     each inverse per lane);
+//   * the panel rows below are solved against the diagonal block as FP64
+//     MFMA products with those inverses (16-row tiles, one wave each);
+//   * the forward substitution L z = D b advances by the panel's unknowns
+//     (small mat-vecs with the inverses);
 //   * the trailing lower triangle is updated with v_mfma_f64_16x16x4f64 on
-//     16 x 16 tiles (read-modify-write of the L2-resident workspace).
-// The back substitution L^T w = z then walks the panels in reverse, each
-// staged in LDS by a coalesced bulk load.
+//     16 x 16 tiles, four tiles' loads in flight per wave.
+// The back substitution L^T w = z walks the panels in reverse with the
+// stored inverses.
 typedef double double4v __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ double rsqrt_nr(double d) {
@@ -161,22 +200,24 @@ __device__ __forceinline__ double rsqrt_nr(double d) {
     return r;
 }
 
+constexpr int IL_S = 17;   // LDS row stride of the 16 x 16 inverses
+
 __global__ __launch_bounds__(CH_THREADS) void k_cholesky(int N, double* __restrict__ A,
                                                          const double* __restrict__ b,
                                                          double* __restrict__ x,
-                                                         double* __restrict__ y, SolveState* st) {
+                                                         double* __restrict__ ILg, SolveState* st) {
     if (st->done) return;
     extern __shared__ double P[];        // panel [N + 16][CH_PS]
     __shared__ double Dq[CH_NMAX];
-    __shared__ double zb[CH_NMAX];
-    __shared__ double dinv[CH_NMAX];
+    __shared__ double zb[CH_NMAX + 32];
+    __shared__ double dinv[CH_NMAX + 32];
+    __shared__ double IL[2][16 * IL_S];
     __shared__ double part[CH_NB * (CH_THREADS / 32)];
-    __shared__ double cb[64];
+    __shared__ double cb[2][64];
     __shared__ int s_bad;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     constexpr int NW = CH_THREADS / 64;
     constexpr int NPART = CH_THREADS / 32;
-    (void)y;
     if (tid == 0) s_bad = 0;
     __syncthreads();
     for (int i = tid; i < N; i += CH_THREADS) {
@@ -195,11 +236,15 @@ __global__ __launch_bounds__(CH_THREADS) void k_cholesky(int N, double* __restri
         }
         return;
     }
-    for (int i = tid; i < N; i += CH_THREADS) zb[i] = Dq[i] * b[i];
+    for (int i = tid; i < N + 32; i += CH_THREADS) {
+        zb[i] = i < N ? Dq[i] * b[i] : 0.0;
+        dinv[i] = 0.0;
+    }
     const int tr = tid >> 5, tc = tid & 31, TR = CH_THREADS / 32;
     for (int i = tr; i < N; i += TR)
         for (int j = tc; j <= i; j += 32) A[(size_t)i * N + j] *= Dq[i] * Dq[j];
     __syncthreads();
+    const int l16 = lane & 15, l4 = lane >> 4;
     for (int k0 = 0; k0 < N; k0 += CH_NB) {
         const int nk = min(CH_NB, N - k0);
         const int rows = N - k0;
@@ -207,25 +252,30 @@ __global__ __launch_bounds__(CH_THREADS) void k_cholesky(int N, double* __restri
             P[i * CH_PS + tc] = (i < rows && tc < nk && (i >= nk || tc <= i))
                                     ? A[(size_t)(k0 + i) * N + k0 + tc] : 0.0;
         __syncthreads();
-        // ---- diagonal block (wave 0)
+        // ---- diagonal block and its two 16 x 16 inverses (wave 0)
         if (wave == 0) {
             double r[CH_NB];
 #pragma unroll
             for (int c = 0; c < CH_NB; c++) r[c] = lane < nk ? P[lane * CH_PS + c] : 0.0;
             int bad = 0;
+            if (lane < CH_NB) cb[0][lane] = r[0];
+            wave_sync();
 #pragma unroll
             for (int c = 0; c < CH_NB; c++) {
                 if (c < nk && !bad) {
-                    if (lane < CH_NB) cb[lane] = r[c];
-                    wave_sync();
-                    const double d = cb[c];
+                    const double* col = cb[c & 1];
+                    const double d = col[c];
                     if (!(d > 0.0)) {
                         bad = c + 1;
                     } else {
                         const double inv = rsqrt_nr(d);
                         const double t = (lane > c && lane < nk) ? r[c] * inv * inv : 0.0;
+                        if (c + 1 < CH_NB) {
+                            r[c + 1] -= t * col[c + 1];
+                            if (lane < CH_NB) cb[(c + 1) & 1][lane] = r[c + 1];
+                        }
 #pragma unroll
-                        for (int j = c + 1; j < CH_NB; j++) r[j] -= t * cb[j];
+                        for (int j = c + 2; j < CH_NB; j++) r[j] -= t * col[j];
                         r[c] = lane == c ? d * inv : (lane > c ? r[c] * inv : r[c]);
                         if (lane == 0) dinv[k0 + c] = inv;
                     }
@@ -237,6 +287,26 @@ __global__ __launch_bounds__(CH_THREADS) void k_cholesky(int N, double* __restri
                 for (int c = 0; c < CH_NB; c++) P[lane * CH_PS + c] = c <= lane ? r[c] : 0.0;
             }
             if (lane == 0) s_bad = bad;
+            wave_sync();
+            if (!bad && lane < 32) {
+                // column j of the inverse of diagonal sub-block g (rows/cols 16 g .. 16 g + 15)
+                const int g = lane >> 4, j = lane & 15, base = 16 * g;
+                double xv[16];
+#pragma unroll
+                for (int q = 0; q < 16; q++) xv[q] = q == j ? 1.0 : 0.0;
+#pragma unroll
+                for (int c = 0; c < 16; c++) {
+                    xv[c] *= dinv[k0 + base + c];
+#pragma unroll
+                    for (int q = c + 1; q < 16; q++) xv[q] -= P[(base + q) * CH_PS + base + c] * xv[c];
+                }
+                double* ilg = ILg + (size_t)(k0 / CH_NB) * 512 + g * 256;
+#pragma unroll
+                for (int q = 0; q < 16; q++) {
+                    IL[g][q * IL_S + j] = xv[q];
+                    ilg[q * 16 + j] = xv[q];
+                }
+            }
         }
         __syncthreads();
         if (s_bad) {
@@ -246,67 +316,128 @@ __global__ __launch_bounds__(CH_THREADS) void k_cholesky(int N, double* __restri
             }
             return;
         }
-        // ---- panel rows below the diagonal block: a L_diag^T = row
-        for (int i = nk + tid; i < rows; i += CH_THREADS) {
-            double a[CH_NB];
+        // ---- panel rows below the diagonal block, 16-row tiles on MFMA:
+        //      X1 = A1 inv(L11)^T, X2 = (A2 - X1 L21^T) inv(L22)^T
+        const int m = rows - nk;
+        if (m > 0) {
+            const int nt = (m + 15) / 16;
+            for (int t = wave; t < nt; t += NW) {
+                const int r0 = nk + 16 * t;
+                double4v acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int c = 0; c < CH_NB; c++) a[c] = P[i * CH_PS + c];
+                for (int kk = 0; kk < 16; kk += 4)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(P[(r0 + l16) * CH_PS + kk + l4],
+                                                               IL[0][l16 * IL_S + kk + l4], acc, 0, 0, 0);
+                wave_sync();
 #pragma unroll
-            for (int c = 0; c < CH_NB; c++) {
-                if (c < nk) {
-                    a[c] *= dinv[k0 + c];
+                for (int e = 0; e < 4; e++) P[(r0 + l4 + 4 * e) * CH_PS + l16] = acc[e];
+                wave_sync();
 #pragma unroll
-                    for (int q = c + 1; q < CH_NB; q++) a[q] -= a[c] * P[q * CH_PS + c];
-                }
+                for (int e = 0; e < 4; e++) acc[e] = P[(r0 + l4 + 4 * e) * CH_PS + 16 + l16];
+#pragma unroll
+                for (int kk = 0; kk < 16; kk += 4)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-P[(r0 + l16) * CH_PS + kk + l4],
+                                                               P[(16 + l16) * CH_PS + kk + l4], acc, 0, 0, 0);
+                wave_sync();
+#pragma unroll
+                for (int e = 0; e < 4; e++) P[(r0 + l4 + 4 * e) * CH_PS + 16 + l16] = acc[e];
+                wave_sync();
+                double4v acc2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int kk = 0; kk < 16; kk += 4)
+                    acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(P[(r0 + l16) * CH_PS + 16 + kk + l4],
+                                                                IL[1][l16 * IL_S + kk + l4], acc2, 0, 0, 0);
+                wave_sync();
+#pragma unroll
+                for (int e = 0; e < 4; e++) P[(r0 + l4 + 4 * e) * CH_PS + 16 + l16] = acc2[e];
             }
-#pragma unroll
-            for (int c = 0; c < CH_NB; c++) P[i * CH_PS + c] = a[c];
         }
-        // ---- forward substitution for this block of unknowns (wave 0)
+        // ---- forward substitution for the panel's unknowns (wave 0)
         if (wave == 0) {
-            double v = lane < nk ? zb[k0 + lane] : 0.0;
-            for (int c = 0; c < nk; c++) {
-                const double vc = __shfl(v, c) * dinv[k0 + c];
-                if (lane == c) v = vc;
-                if (lane > c && lane < nk) v -= P[lane * CH_PS + c] * vc;
+            double z1 = 0.0;
+            if (lane < 16) {
+                for (int k = 0; k < 16; k++) z1 += IL[0][lane * IL_S + k] * zb[k0 + k];
             }
-            if (lane < nk) zb[k0 + lane] = v;
+            wave_sync();
+            if (lane < 16) zb[k0 + lane] = z1;
+            wave_sync();
+            double s2 = 0.0;
+            if (lane >= 16 && lane < 32) {
+                const int i = lane - 16;
+                s2 = zb[k0 + 16 + i];
+                for (int k = 0; k < 16; k++) s2 -= P[(16 + i) * CH_PS + k] * zb[k0 + k];
+            }
+            wave_sync();
+            if (lane >= 16 && lane < 32) zb[k0 + lane] = s2;
+            wave_sync();
+            double z2 = 0.0;
+            if (lane >= 16 && lane < 32) {
+                const int i = lane - 16;
+                for (int k = 0; k < 16; k++) z2 += IL[1][i * IL_S + k] * zb[k0 + 16 + k];
+            }
+            wave_sync();
+            if (lane >= 16 && lane < 32 && lane < nk) zb[k0 + lane] = z2;
         }
         __syncthreads();
         for (int i = nk + tid; i < rows; i += CH_THREADS) {
             double acc = 0.0;
-            for (int c = 0; c < nk; c++) acc += P[i * CH_PS + c] * zb[k0 + c];
+#pragma unroll 8
+            for (int c = 0; c < CH_NB; c++) acc += P[i * CH_PS + c] * zb[k0 + c];
             zb[k0 + i] -= acc;
         }
         for (int i = tr; i < rows; i += TR)
             if (tc < nk && (i >= nk || tc <= i)) A[(size_t)(k0 + i) * N + k0 + tc] = P[i * CH_PS + tc];
         // ---- trailing update on FP64 MFMA: 16 x 16 tiles of the lower triangle
-        const int m = rows - nk;
         if (m > 0) {
             const int mt = (m + 15) / 16;
             const int ntile = mt * (mt + 1) / 2;
-            for (int tI = wave; tI < ntile; tI += NW) {
-                int ti = (int)((sqrt(8.0 * tI + 1.0) - 1.0) * 0.5);
-                while ((ti + 1) * (ti + 2) / 2 <= tI) ti++;
-                while (ti * (ti + 1) / 2 > tI) ti--;
-                const int tj = tI - ti * (ti + 1) / 2;
-                const int i0 = nk + 16 * ti, j0 = nk + 16 * tj;
-                const int jj = j0 + (lane & 15);
-                double4v c;
+            for (int base = wave; base < ntile; base += 4 * NW) {
+                double4v c[4];
+                int ti[4], tj[4];
 #pragma unroll
-                for (int e = 0; e < 4; e++) {
-                    const int ii = i0 + (lane >> 4) + 4 * e;   // f64 MFMA D layout
-                    c[e] = (ii < rows && jj <= ii) ? A[(size_t)(k0 + ii) * N + k0 + jj] : 0.0;
+                for (int q = 0; q < 4; q++) {
+                    const int tI = base + q * NW;
+                    int a = 0, bj = 0;
+                    if (tI < ntile) {
+                        a = (int)((sqrt(8.0 * tI + 1.0) - 1.0) * 0.5);
+                        while ((a + 1) * (a + 2) / 2 <= tI) a++;
+                        while (a * (a + 1) / 2 > tI) a--;
+                        bj = tI - a * (a + 1) / 2;
+                    } else {
+                        a = -1;
+                    }
+                    ti[q] = a;
+                    tj[q] = bj;
+                    const int i0 = nk + 16 * a, jj = nk + 16 * bj + l16;
+#pragma unroll
+                    for (int e = 0; e < 4; e++) {
+                        const int ii = i0 + l4 + 4 * e;       // f64 MFMA D layout
+                        c[q][e] = (a >= 0 && ii < rows && jj <= ii) ? A[(size_t)(k0 + ii) * N + k0 + jj] : 0.0;
+                    }
                 }
-                const double* pa = P + (i0 + (lane & 15)) * CH_PS + (lane >> 4);
-                const double* pb = P + (j0 + (lane & 15)) * CH_PS + (lane >> 4);
+                const double* pa[4];
+                const double* pb[4];
 #pragma unroll
-                for (int cc = 0; cc < CH_NB; cc += 4)
-                    c = __builtin_amdgcn_mfma_f64_16x16x4f64(-pa[cc], pb[cc], c, 0, 0, 0);
+                for (int q = 0; q < 4; q++) {
+                    const int tq = ti[q] < 0 ? 0 : ti[q];     // idle slots compute on row 0 (discarded)
+                    pa[q] = P + (nk + 16 * tq + l16) * CH_PS + l4;
+                    pb[q] = P + (nk + 16 * tj[q] + l16) * CH_PS + l4;
+                }
 #pragma unroll
-                for (int e = 0; e < 4; e++) {
-                    const int ii = i0 + (lane >> 4) + 4 * e;   // f64 MFMA D layout
-                    if (ii < rows && jj <= ii) A[(size_t)(k0 + ii) * N + k0 + jj] = c[e];
+                for (int cc = 0; cc < CH_NB; cc += 4) {
+#pragma unroll
+                    for (int q = 0; q < 4; q++)
+                        c[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-pa[q][cc], pb[q][cc], c[q], 0, 0, 0);
+                }
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    if (ti[q] < 0) continue;
+                    const int i0 = nk + 16 * ti[q], jj = nk + 16 * tj[q] + l16;
+#pragma unroll
+                    for (int e = 0; e < 4; e++) {
+                        const int ii = i0 + l4 + 4 * e;
+                        if (ii < rows && jj <= ii) A[(size_t)(k0 + ii) * N + k0 + jj] = c[q][e];
+                    }
                 }
             }
         }
@@ -318,6 +449,10 @@ __global__ __launch_bounds__(CH_THREADS) void k_cholesky(int N, double* __restri
         const int rows = N - k0;
         for (int i = tr; i < rows; i += TR)
             P[i * CH_PS + tc] = (tc < nk && (i >= nk || tc <= i)) ? A[(size_t)(k0 + i) * N + k0 + tc] : 0.0;
+        for (int e = tid; e < 512; e += CH_THREADS) {
+            const int g = e >> 8, q = (e >> 4) & 15, j = e & 15;
+            IL[g][q * IL_S + j] = ILg[(size_t)(k0 / CH_NB) * 512 + e];
+        }
         __syncthreads();
         {
             const int c = tid & 31, w = tid >> 5;
@@ -333,59 +468,94 @@ __global__ __launch_bounds__(CH_THREADS) void k_cholesky(int N, double* __restri
                 v = zb[k0 + lane];
                 for (int w = 0; w < NPART; w++) v -= part[lane * NPART + w];
             }
-            for (int c = nk - 1; c >= 0; c--) {
-                const double vc = __shfl(v, c) * dinv[k0 + c];
-                if (lane == c) v = vc;
-                if (lane < c) v -= P[c * CH_PS + lane] * vc;
+            if (lane < 32) zb[k0 + lane] = lane < nk ? v : 0.0;
+            wave_sync();
+            // w2 = inv(L22)^T rhs2
+            double w2 = 0.0;
+            if (lane >= 16 && lane < 32) {
+                const int i = lane - 16;
+                for (int k = 0; k < 16; k++) w2 += IL[1][k * IL_S + i] * zb[k0 + 16 + k];
             }
-            if (lane < nk) zb[k0 + lane] = v;
+            wave_sync();
+            if (lane >= 16 && lane < 32) zb[k0 + lane] = w2;
+            wave_sync();
+            // rhs1 -= L21^T w2 ; w1 = inv(L11)^T rhs1
+            double r1 = 0.0;
+            if (lane < 16) {
+                r1 = zb[k0 + lane];
+                for (int k = 0; k < 16; k++) r1 -= P[(16 + k) * CH_PS + lane] * zb[k0 + 16 + k];
+            }
+            wave_sync();
+            if (lane < 16) zb[k0 + lane] = r1;
+            wave_sync();
+            double w1 = 0.0;
+            if (lane < 16) {
+                for (int k = 0; k < 16; k++) w1 += IL[0][k * IL_S + lane] * zb[k0 + k];
+            }
+            wave_sync();
+            if (lane < 16 && lane < nk) zb[k0 + lane] = w1;
         }
         __syncthreads();
     }
     for (int i = tid; i < N; i += CH_THREADS) x[i] = Dq[i] * zb[i];
 }
 
-// chi2_s = e_s - 2 alpha^T b_s + alpha^T M_s alpha for every fitted stamp,
-// then the sigma-clip over the used stamps.
-__global__ __launch_bounds__(1024) void k_chi2_clip(
-    int n, int nb, int ns, int N, int max_iter, int min_stamps, double clip_sigma,
-    const double* __restrict__ Ms, const double* __restrict__ bs, const double* __restrict__ es,
-    const int32_t* __restrict__ npix, const double* __restrict__ G, const double* __restrict__ a,
-    uint8_t* __restrict__ used, const uint8_t* __restrict__ fitted, int32_t* __restrict__ flags,
-    double* __restrict__ chi2, SolveState* st) {
+// chi2_s = e_s - 2 alpha^T b_s + alpha^T M_s alpha for every fitted stamp
+// (one wave per stamp; alpha = local coefficients at the stamp centre).
+__global__ __launch_bounds__(64) void k_chi2(int n, int nb, int ns, int N,
+                                             const double* __restrict__ Ms,
+                                             const double* __restrict__ bs,
+                                             const double* __restrict__ es,
+                                             const double* __restrict__ G,
+                                             const double* __restrict__ a,
+                                             const uint8_t* __restrict__ fitted,
+                                             double* __restrict__ chi2, const SolveState* st) {
     if (st->done) return;
-    __shared__ double alpha[16][64];
+    const int s = blockIdx.x, lane = threadIdx.x;
+    if (!fitted[s]) return;
+    __shared__ double alpha[64];
+    const int L = nb + 1;
+    if (lane < L) {
+        double al;
+        if (lane < nb) {
+            al = 0.0;
+            for (int q = 0; q < ns; q++) al += a[lane * ns + q] * G[(size_t)s * ns + q];
+        } else {
+            al = a[N - 1];
+        }
+        alpha[lane] = al;
+    }
+    wave_sync();
+    double part = 0.0;
+    if (lane < L) {
+        const double* Mc = Ms + (size_t)s * L * L + lane;
+        double u0 = 0.0, u1 = 0.0, u2 = 0.0, u3 = 0.0;
+        int i = 0;
+        for (; i + 3 < L; i += 4) {
+            u0 += alpha[i] * Mc[(size_t)i * L];
+            u1 += alpha[i + 1] * Mc[(size_t)(i + 1) * L];
+            u2 += alpha[i + 2] * Mc[(size_t)(i + 2) * L];
+            u3 += alpha[i + 3] * Mc[(size_t)(i + 3) * L];
+        }
+        for (; i < L; i++) u0 += alpha[i] * Mc[(size_t)i * L];
+        const double al = alpha[lane];
+        part = al * ((u0 + u1) + (u2 + u3)) - 2.0 * al * bs[(size_t)s * L + lane];
+    }
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_down(part, o);
+    if (lane == 0) chi2[s] = es[s] + part;
+}
+
+// Sigma-clip over the used stamps after a solution (one workgroup).
+__global__ __launch_bounds__(1024) void k_clip(int n, int max_iter, int min_stamps,
+                                               double clip_sigma,
+                                               const int32_t* __restrict__ npix,
+                                               uint8_t* __restrict__ used,
+                                               int32_t* __restrict__ flags,
+                                               const double* __restrict__ chi2, SolveState* st) {
+    if (st->done) return;
     __shared__ double red[16];
     __shared__ double s_thr;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int L = nb + 1;
-    for (int s = wave; s < n; s += 16) {
-        if (!fitted[s]) continue;               // wave-uniform
-        if (lane < L) {
-            double al;
-            if (lane < nb) {
-                al = 0.0;
-                for (int q = 0; q < ns; q++) al += a[lane * ns + q] * G[(size_t)s * ns + q];
-            } else {
-                al = a[N - 1];
-            }
-            alpha[wave][lane] = al;
-        }
-        wave_sync();
-        // lane j: u_j = sum_i alpha_i M_s[i][j] (row-wise coalesced reads)
-        double part = 0.0;
-        if (lane < L) {
-            const double* Mc = Ms + (size_t)s * L * L + lane;
-            double u = 0.0;
-#pragma unroll 8
-            for (int i = 0; i < L; i++) u += alpha[wave][i] * Mc[(size_t)i * L];
-            const double al = alpha[wave][lane];
-            part = al * u - 2.0 * al * bs[(size_t)s * L + lane];
-        }
-        for (int o = 32; o > 0; o >>= 1) part += __shfl_down(part, o);
-        if (lane == 0) chi2[s] = es[s] + part;
-        wave_sync();
-    }
+    const int tid = threadIdx.x;
     __syncthreads();
     if (tid == 0) st->n_iter += 1;
     __syncthreads();
@@ -489,7 +659,9 @@ size_t solve_workspace(const psfm_context* ctx, int n) {
     c.take<double>((size_t)n * (ctx->ns + 1) + 1);
     c.take<double>((size_t)ctx->N * ctx->N);
     c.take<double>(ctx->N);
-    c.take<double>(ctx->N);
+    c.take<double>((size_t)512 * ((ctx->N + CH_NB - 1) / CH_NB));
+    c.take<double>((size_t)n * ctx->L * ctx->L + 1);
+    c.take<double>((size_t)n * ctx->L + 1);
     return c.off;
 }
 
@@ -519,7 +691,9 @@ extern "C" int psfm_solve(const psfm_context* ctx, int W, int H, const int32_t* 
     double* GU = c.take<double>((size_t)n_stamps * (ctx->ns + 1) + 1);
     double* M = c.take<double>((size_t)ctx->N * ctx->N);
     double* b = c.take<double>(ctx->N);
-    double* y = c.take<double>(ctx->N);
+    double* ILg = c.take<double>((size_t)512 * ((ctx->N + CH_NB - 1) / CH_NB));
+    double* Mt = c.take<double>((size_t)n_stamps * ctx->L * ctx->L + 1);
+    double* bt = c.take<double>((size_t)n_stamps * ctx->L + 1);
     const int nb = ctx->nb, ns = ctx->ns, N = ctx->N, L = ctx->L;
     const psfm_config& cf = ctx->cfg;
     static size_t attr_set = 0;      // dynamic LDS granted so far
@@ -534,22 +708,25 @@ extern "C" int psfm_solve(const psfm_context* ctx, int W, int H, const int32_t* 
                        G, stamp_chi2, coeffs, state);
     PSFM_HIP_CHECK(hipGetLastError());
     const int nthreads_asm = L * L * ns + L * ns;
+    if (n_stamps > 0)
+        hipLaunchKernelGGL(k_transpose_sums, dim3(256), dim3(256), 0, st, n_stamps, L, stamp_M, stamp_b, Mt, bt);
     for (int it = 0; it < cf.max_iter; it++) {
         hipLaunchKernelGGL(k_weights, dim3((n_stamps + 255) / 256 + 1), dim3(256), 0, st, n_stamps, ns,
                            G, used, GU, state);
-        const dim3 ag((nthreads_asm + 255) / 256);
+        const dim3 ag((nthreads_asm + ASM_ITEMS - 1) / ASM_ITEMS);
         switch (ns) {
 #define PSFM_ASM_CASE(NSV) \
-    case NSV: hipLaunchKernelGGL(k_assemble<NSV>, ag, dim3(256), 0, st, n_stamps, nb, N, stamp_M, stamp_b, GU, M, b, state); break;
+    case NSV: hipLaunchKernelGGL(k_assemble<NSV>, ag, dim3(256), 0, st, n_stamps, nb, N, Mt, bt, GU, M, b, state); break;
             PSFM_ASM_CASE(1) PSFM_ASM_CASE(3) PSFM_ASM_CASE(6) PSFM_ASM_CASE(10) PSFM_ASM_CASE(15)
             PSFM_ASM_CASE(21) PSFM_ASM_CASE(28)
 #undef PSFM_ASM_CASE
             default: return PSFM_ERR_UNSUPPORTED;
         }
-        hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(CH_THREADS), lds, st, N, M, b, coeffs, y, state);
-        hipLaunchKernelGGL(k_chi2_clip, dim3(1), dim3(1024), 0, st, n_stamps, nb, ns, N, cf.max_iter,
-                           cf.min_stamps, cf.clip_sigma, stamp_M, stamp_b, stamp_e, stamp_npix, G,
-                           coeffs, used, fitted, stamp_flags, stamp_chi2, state);
+        hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(CH_THREADS), lds, st, N, M, b, coeffs, ILg, state);
+        hipLaunchKernelGGL(k_chi2, dim3(std::max(n_stamps, 1)), dim3(64), 0, st, n_stamps, nb, ns, N,
+                           stamp_M, stamp_b, stamp_e, G, coeffs, fitted, stamp_chi2, state);
+        hipLaunchKernelGGL(k_clip, dim3(1), dim3(1024), 0, st, n_stamps, cf.max_iter, cf.min_stamps,
+                           cf.clip_sigma, stamp_npix, used, stamp_flags, stamp_chi2, state);
     }
     hipLaunchKernelGGL(k_solve_finish, dim3(1), dim3(1024), 0, st, n_stamps, nb, ns, N,
                        cf.spatial_order, W, H, stamp_npix, used, stamp_chi2, coeffs, state, stats);
