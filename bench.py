@@ -1,18 +1,24 @@
 """Throughput of the PSF-matching hot path on one MI355X.
 
-One step = one whole pass of the path over one synthetic image pair already
-resident in HBM:
+One step = one whole pass of the path over synthetic input already resident
+in HBM.
+
+Default workload (one pair):
     psfm_fit_stamps -> psfm_solve (with rejection) -> psfm_convolve_image
     -> psfm_propagate_variance -> psfm_subtract
-Workload: 2048 x 2048 FP32 pair, science PSF sigma 1.4 -> 2.6 px across the
-field with ellipticity up to 0.2, 2000 sources, 10% mask, 21 x 21 kernel with
-the 49-term ISIS basis x spatial order 2 (295 unknowns), 100 stamps of 41 x 41,
+on a 2048 x 2048 FP32 pair, science PSF sigma 1.4 -> 2.6 px across the field
+with ellipticity up to 0.2, 2000 sources, 10% mask, 21 x 21 kernel with the
+49-term ISIS basis x spatial order 2 (295 unknowns), 100 stamps of 41 x 41,
 variance map and a 21 x 21 covariance pseudo-matrix.
 
-Prints one JSON line.  `value` is pixels of the pair per second (Mpix/s).
-`roofline` is for the dominant kernel (the image convolution tile kernel),
-timed with HIP events around its call on the stream it runs on;
-`cpu_baseline` is the FP64 oracle on the host's cores on the same pair.
+--workload cfg3: one batch of 64 independent pairs of uneven size (1024 to
+6000 px a side, spatial order 0-3, 50-400 stamps) through psfm_batch_* as one
+HIP graph; also reports the p50 / p99 completion latency of the pairs.
+
+Prints one JSON line.  `value` is pixels matched per second (Mpix/s).
+`roofline` is for the dominant kernel (the image convolution), timed with HIP
+events on the stream it runs on; `cpu_baseline` is the FP64 oracle on the
+host's cores on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -41,6 +47,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cfg1")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--retune", action="store_true", help="ignore cached batch launch shapes")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="bound on the oracle's timed sample")
     return ap.parse_args()
@@ -84,6 +91,139 @@ def cpu_baseline(wl, pair, budget_s):
                        f"OpenMP over stamps and patches"), res
 
 
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def bench_batch(args, torch, psfm, synth):
+    from paper_1901_09999_amd import tune
+    spec = synth.BATCHES[args.workload]
+    cfg_index = int(args.workload[-1])
+    wls = [synth.batch_pair_workload(spec, k, cfg_index) for k in range(spec.n_pairs)]
+    t0 = time.perf_counter()
+    dps = []
+    for k, wl in enumerate(wls):
+        dps.append(synth.make_pair_device(wl, synth.workload_seed(cfg_index, k)))
+        if k % 16 == 15:
+            torch.cuda.synchronize()
+            log(f"generated {k + 1}/{len(wls)} pairs ({time.perf_counter() - t0:.1f} s)")
+    px = np.array([wl.pixels for wl in wls], dtype=np.float64)
+    total_px = float(px.sum())
+    ctx = psfm.Context(psfm.Config(h=spec.kernel_half, r=spec.stamp_half, S=0))
+    pairs = [dict(I1=d.I1, V1=d.V1, M1=d.M1, I2=d.I2, V2=d.V2, M2=d.M2,
+                  stamps=torch.from_numpy(d.stamps.astype(np.int32)).cuda(),
+                  S=d.workload.spatial_order) for d in dps]
+    grid, order, table = tune.choose(ctx, pairs, c_out=10, log=log, use_cache=not args.retune)
+    log(f"tuned: apply_grid {grid}, order {order}")
+    b = psfm.Batch(ctx, pairs, c_out=10, apply_grid=grid, order=order)
+    b.run()
+    torch.cuda.synchronize()
+    # stage times (eager, events on the batch stream)
+    stage = np.zeros(3)
+    reps = 3
+    for _ in range(reps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        with torch.cuda.stream(b.stream):
+            ev[0].record()
+            for sidx in range(3):
+                b.run_stage(sidx)
+                ev[sidx + 1].record()
+        ev[3].synchronize()
+        stage += [ev[i].elapsed_time(ev[i + 1]) for i in range(3)]
+    stage /= reps
+    b.capture()
+    for _ in range(args.warmup):
+        b.launch()
+    torch.cuda.synchronize()
+    lat, per = [], []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(b.stream):
+            e0.record()
+        b.launch()
+        with torch.cuda.stream(b.stream):
+            e1.record()
+        e1.synchronize()
+        per.append(e0.elapsed_time(e1))
+        lat.append(b.latencies_s() * 1e3)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ms_per_step = 1e3 * wall / args.steps
+    lat = np.concatenate(lat)
+    st = [b.stats(k) for k in range(len(wls))]
+    T = (2 * spec.kernel_half + 1) ** 2
+    flops = 4.0 * T * total_px                 # I' and V' (2T flop per pixel each)
+    apply_us = stage[2] * 1e3
+    achieved = flops / (apply_us * 1e-6) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": round(total_px / 1e6 / (ms_per_step * 1e-3), 2),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {len(wls)} independent pairs, "
+                               f"{total_px / 1e6:.0f} Mpx in all, sides U{{{spec.size_lo}..{spec.size_hi}}}, "
+                               f"spatial order U{{0..{spec.S_max}}}, stamps U{{{spec.stamps_lo}.."
+                               f"{spec.stamps_hi}}}, 21^2 kernel, 49-term ISIS basis, "
+                               f"{int(spec.variable_frac * 100)}% variable sources, one HIP graph",
+                   "pairs": len(wls), "total_pixels": int(total_px),
+                   "apply_grid": grid, "tile_order": order, "parallelism": "single GPU"},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                       "p99": round(float(np.percentile(lat, 99)), 3),
+                       "max": round(float(lat.max()), 3)},
+        "graph_ms_per_step": round(float(np.median(per)), 4),
+        "stages_ms": {k: round(float(v), 4) for k, v in zip(["fit", "solve", "apply"], stage)},
+        "fit": {"solved": int(sum(s["info"] == 0 for s in st)),
+                "rejected_stamps": int(sum(s["n_rejected"] for s in st)),
+                "chi2_dof_median": float(np.median([s["chi2_dof"] for s in st if s["info"] == 0]))},
+        "roofline": dict(kernel="k_match_tiles_b (fused I', V', D over all pairs; stage also holds "
+                                "the pseudo-matrix kernels)",
+                         bound="alu", achieved=round(achieved, 2), peak=FP32_VALU_PEAK_TFLOPS,
+                         unit="TFLOP/s", frac=round(achieved / FP32_VALU_PEAK_TFLOPS, 4),
+                         traffic=None, avg_launch_us=round(apply_us, 2),
+                         algorithmic_flops_per_launch=flops),
+        "tuning": table,
+    }
+    if not args.no_cpu_baseline:
+        import oracle as O
+        O.build()
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+        os.environ.setdefault("OMP_NUM_THREADS", str(threads))
+        order_px = np.argsort(px)
+        done_px, spent, used, rel = 0.0, 0.0, [], []
+        for k in order_px:
+            if spent > 0 and spent + spent / max(len(used), 1) > args.cpu_seconds:
+                break
+            hp = dps[k].host()
+            t1 = time.perf_counter()
+            ref = O.match_pair(O.Config.from_workload(wls[k]), hp, c_out=10)
+            spent += time.perf_counter() - t1
+            done_px += px[k]
+            used.append(int(k))
+            rs = ref["stats"]
+            if rs["info"] == 0 and st[k]["info"] == 0:
+                rel.append((abs(st[k]["kernel_sum_centre"] / rs["kernel_sum_centre"] - 1),
+                            abs(st[k]["chi2_dof"] / rs["chi2_dof"] - 1)))
+        out["cpu_baseline"] = dict(
+            value=round(done_px / 1e6 / spent, 3), unit="Mpix/s", cores=threads, kind="oracle",
+            sample=f"whole path on the {len(used)} smallest pair(s) of the batch "
+                   f"({done_px / 1e6:.1f} Mpx, {spent:.1f} s), FP64, OpenMP over stamps and "
+                   f"patches; rate = their pixels / their time")
+        if rel:
+            out["parity_vs_oracle"] = {"pairs": used,
+                                       "kernel_sum_rel_max": max(r[0] for r in rel),
+                                       "chi2_dof_rel_max": max(r[1] for r in rel)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -96,6 +236,8 @@ def main():
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a HIP device")
+    if args.workload in synth.BATCHES:
+        return bench_batch(args, torch, psfm, synth)
     wl = synth.WORKLOADS[args.workload]
     cfg_index = int(args.workload[-1])
     pair = synth.make_pair(wl, synth.workload_seed(cfg_index))

@@ -245,6 +245,104 @@ int psfm_subtract(const psfm_context* ctx, const double* coeffs, const float* I2
                   float* diff_var, uint8_t* diff_mask, double* cov_diff, int cov_diff_half,
                   void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * Batched matching of many independent image pairs: the whole path of the
+ * calls above (fit, solve with rejection, image and variance convolution,
+ * covariance pseudo-matrix, difference) for every pair of a batch, with each
+ * stage covering all pairs in one launch (Sections 2-4 per pair; the pairs
+ * share nothing but the context's basis, h, r, patch and rejection settings).
+ *
+ * Per pair the results equal those of the single-pair calls, except that
+ * the difference image is formed in the same pass as the convolutions (the
+ * convolved image and its variance are written only if requested) and the
+ * variance means of C_D are summed per tile instead of per row block.
+ */
+typedef struct psfm_pair {
+    /* inputs (device); image 1 is convolved to match image 2 */
+    const float* I1;
+    const float* V1;
+    const uint8_t* M1;
+    const float* I2;
+    const float* V2;
+    const uint8_t* M2;
+    int width, height;
+    int64_t pitch;              /* elements (bytes for the masks) */
+    const int32_t* stamp_xy;    /* n_stamps (x, y) centres */
+    int n_stamps;
+    int spatial_order;          /* S of this pair (0..6, N = nb ns + 1 <= 496) */
+    const double* cov1;         /* input pseudo-matrix of image 1, NULL: uncorrelated */
+    int cov1_half;              /* 0..32 */
+    const double* cov2;         /* input pseudo-matrix of image 2, NULL: uncorrelated */
+    int cov2_half;
+    /* outputs (device) */
+    double* coeffs;             /* N(S) float64 */
+    psfm_fit_stats* stats;
+    float* diff;
+    float* diff_var;
+    uint8_t* diff_mask;
+    double* cov_conv;           /* (2 cov_conv_half + 1)^2: pseudo-matrix of the convolved image */
+    int cov_conv_half;
+    double* cov_diff;           /* (2 cov_diff_half + 1)^2: pseudo-matrix of the difference */
+    int cov_diff_half;
+    /* optional outputs (device, NULL: not written) */
+    float* conv;                /* I' */
+    float* conv_var;            /* V' */
+    uint8_t* conv_mask;         /* BAD/POOR of I' (required if conv is given) */
+    int32_t* stamp_flags;       /* n_stamps */
+    double* stamp_chi2;         /* n_stamps */
+} psfm_pair;
+
+/* Launch shape of a batch.  apply_grid: workgroups of the fused apply kernel,
+   which visits the 64 x 64 tiles of all pairs in a grid-stride loop (0: one
+   workgroup per tile).  order: order of the pairs in the tile list
+   (0 as given, 1 smallest first, 2 largest first). */
+typedef struct psfm_batch_tuning {
+    int apply_grid;
+    int order;
+} psfm_batch_tuning;
+
+typedef struct psfm_batch psfm_batch;
+
+/* Workspace bytes of a batch (0 on invalid arguments). */
+size_t psfm_batch_workspace_bytes(const psfm_context* ctx, const psfm_pair* pairs, int n_pairs);
+
+/*
+ * Validates the pairs (host array of n_pairs descriptors, copied), lays out
+ * the workspace and uploads the pair descriptors and work lists into it
+ * (ordered on `stream`; the call waits for the upload).  times (device,
+ * n_pairs + 1 uint64, nullable) receives at each run the start time (entry
+ * 0) and each pair's completion time (entry 1 + p) in wall-clock ticks
+ * (psfm_wall_clock_hz per second).  *out receives a host-side plan freed by
+ * psfm_batch_destroy; no device memory is allocated.  The workspace and the
+ * pair buffers must outlive the plan.
+ */
+int psfm_batch_plan(const psfm_context* ctx, const psfm_pair* pairs, int n_pairs,
+                    const psfm_batch_tuning* tuning, void* ws, size_t ws_bytes, uint64_t* times,
+                    void* stream, psfm_batch** out);
+
+/* Launches every stage of the batch on `stream` (about 10 + 8 max_iter
+   kernels); capturable into a HIP graph.  Runs of one plan must not overlap. */
+int psfm_batch_run(psfm_batch* batch, void* stream);
+
+/* One stage of psfm_batch_run: 0 = start time and stamp fits, 1 = solve
+   loop, 2 = pseudo-matrices and the fused convolution / difference pass.
+   Running stages 0, 1, 2 in order is psfm_batch_run (for timing stages). */
+int psfm_batch_run_stage(psfm_batch* batch, int stage, void* stream);
+
+/* Changes the apply grid of a plan (tuning->order is fixed at plan time).
+   Drops a captured graph. */
+int psfm_batch_set_tuning(psfm_batch* batch, const psfm_batch_tuning* tuning);
+
+/* Captures psfm_batch_run on `stream` (not the NULL stream) into a HIP graph
+   kept by the plan; psfm_batch_graph_launch replays it on `stream`. */
+int psfm_batch_graph_capture(psfm_batch* batch, void* stream);
+int psfm_batch_graph_launch(psfm_batch* batch, void* stream);
+
+int psfm_batch_destroy(psfm_batch* batch);
+
+/* Tick rate of the device wall clock used by the batch time stamps. */
+double psfm_wall_clock_hz(void);
+
 /* Human-readable text of a psfm_status value (static storage). */
 const char* psfm_status_string(int status);
 

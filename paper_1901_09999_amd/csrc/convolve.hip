@@ -136,10 +136,123 @@ __device__ void kernel_stats(const double* Kd, int h, double bad_frac, const dou
     __syncthreads();
 }
 
+// Halo tile [HW x HW] of the input around the output tile at (X0, Y0):
+// masked and out-of-image pixels read as 0; with BITS, their positions are
+// also set in the bit-packed mask badw.  Returns (block-wide) whether any
+// halo pixel was masked or outside.
+template <int H_, bool BITS>
+__device__ int load_halo(const float* __restrict__ src, const uint8_t* __restrict__ M, int W, int H,
+                         int64_t pitch, int X0, int Y0, float* __restrict__ halo,
+                         uint32_t (*badw)[(TILE + 2 * H_ + 31) / 32 + 1]) {
+    constexpr int HW = TILE + 2 * H_;
+    constexpr int NWB = (HW + 31) / 32 + 1;
+    const int tid = threadIdx.x;
+    if (BITS) {
+        for (int e = tid; e < HW * NWB; e += 256) (&badw[0][0])[e] = 0u;
+        __syncthreads();
+    }
+    int anybad = 0;
+    for (int e = tid; e < HW * HW; e += 256) {
+        const int hy = e / HW, hx = e - hy * HW;
+        const int gy = Y0 - H_ + hy, gx = X0 - H_ + hx;
+        float v = 0.0f;
+        bool ok = gx >= 0 && gx < W && gy >= 0 && gy < H;
+        if (ok) {
+            const int64_t o = (int64_t)gy * pitch + gx;
+            ok = M[o] == 0;
+            if (ok) v = src[o];
+        }
+        halo[e] = v;
+        if (!ok) {
+            anybad = 1;
+            if (BITS) atomicOr(&badw[hy][hx >> 5], 1u << (hx & 31));
+        }
+    }
+    return __syncthreads_or(anybad);
+}
+
+// Direct (2h+1)^2-tap convolution of 16 consecutive output rows of column lx
+// (rows r0 .. r0+15 of the tile) from the LDS halo; taps column-major in LDS.
+template <int H_>
+__device__ __forceinline__ void conv16(const float* __restrict__ halo, const float* __restrict__ taps,
+                                       int lx, int r0, float acc[16]) {
+    constexpr int KW = 2 * H_ + 1;
+    constexpr int HW = TILE + 2 * H_;
+#pragma unroll
+    for (int j = 0; j < 16; j++) acc[j] = 0.0f;
+    for (int uu = 0; uu < KW; uu++) {
+        float kc[KW];
+#pragma unroll
+        for (int vv = 0; vv < KW; vv++) kc[vv] = taps[uu * KW + vv];
+        const float* col = halo + r0 * HW + lx + 2 * H_ - uu;
+#pragma unroll
+        for (int hr = 0; hr < 16 + 2 * H_; hr++) {
+            const float val = col[hr * HW];
+#pragma unroll
+            for (int j = 0; j < 16; j++) {
+                const int vv = j + 2 * H_ - hr;
+                if (vv >= 0 && vv < KW) acc[j] = fmaf(kc[vv], val, acc[j]);
+            }
+        }
+    }
+}
+
+// BAD / POOR flags of the 16 outputs from the bit-packed halo mask: POOR if
+// a masked input lies within the kernel footprint, BAD if within box
+// radius rb.  Bit j of the results is output row r0 + j.
+template <int H_>
+__device__ __forceinline__ void mask16(const uint32_t (*badw)[(TILE + 2 * H_ + 31) / 32 + 1],
+                                       int rb, int lx, int r0, uint32_t* bad16, uint32_t* poor16) {
+    constexpr int KW = 2 * H_ + 1;
+    const uint64_t kmask = (KW >= 64) ? ~0ull : ((1ull << KW) - 1ull);
+    const uint64_t bmask = (1ull << (2 * rb + 1)) - 1ull;
+    const int w = lx >> 5, sh = lx & 31;
+    uint64_t poorv = 0, badv = 0;
+#pragma unroll
+    for (int hr = 0; hr < 16 + 2 * H_; hr++) {
+        const uint32_t* bw = badw[r0 + hr];
+        const uint64_t bits = ((uint64_t)bw[w] | ((uint64_t)bw[w + 1] << 32)) >> sh;
+        const uint64_t win = bits & kmask;      // halo columns [lx, lx + 2h]
+        if (win) poorv |= 1ull << hr;
+        if ((win >> (H_ - rb)) & bmask) badv |= 1ull << hr;
+    }
+    uint32_t b = 0, q = 0;
+#pragma unroll
+    for (int j = 0; j < 16; j++) {
+        if ((badv >> (j + H_ - rb)) & bmask) b |= 1u << j;
+        if ((poorv >> j) & kmask) q |= 1u << j;
+    }
+    *bad16 = b;
+    *poor16 = q;
+}
+
+// Realises the patch kernel of patch (px, py) in FP64 in the LDS scratch
+// (overlaid on the halo buffer) and stores its FP32 taps column-major:
+// tapsK = K (if non-null), tapsV = f K^2 (if non-null).  Returns rb in *rb.
+template <int H_>
+__device__ void patch_taps(const BasisArgs& B, const double* __restrict__ a, int W, int H, int P,
+                           int px, int py, double bad_frac, const double* __restrict__ cov_in,
+                           int c_in, float* __restrict__ scratch, float* tapsK, float* tapsV,
+                           double* ring, double* red, int* s_rb, double* s_f) {
+    constexpr int KW = 2 * H_ + 1;
+    constexpr int T = KW * KW;
+    RealiseLds& sh = *reinterpret_cast<RealiseLds*>(scratch);
+    double* Kd = reinterpret_cast<double*>(reinterpret_cast<char*>(scratch) + sizeof(RealiseLds));
+    const int x0 = px * P, x1 = min(x0 + P, W), y0 = py * P, y1 = min(y0 + P, H);
+    realise_kernel(B, a, 0.5 * (x0 + x1 - 1), 0.5 * (y0 + y1 - 1), W, H, sh, Kd);
+    kernel_stats(Kd, H_, bad_frac, tapsV ? cov_in : nullptr, c_in, ring, red, s_rb, s_f);
+    const double f = *s_f;
+    for (int t = threadIdx.x; t < T; t += 256) {
+        const int uu = t / KW, vv = t - uu * KW;     // column-major
+        const double k = Kd[vv * KW + uu];
+        if (tapsK) tapsK[t] = (float)k;
+        if (tapsV) tapsV[t] = (float)(f * k * k);
+    }
+    __syncthreads();
+}
+
 // One workgroup per 64 x 64 output tile inside a constant-kernel patch.
 // MODE 0: image I' (and the BAD/POOR mask); MODE 1: variance V' = f K^2 (x) V.
-// Prologue: the patch kernel is realised in FP64 (LDS scratch shared with the
-// halo buffer), its FP32 taps (K or f K^2, column-major) kept in LDS.
 template <int H_, int MODE>
 __global__ __launch_bounds__(256) void k_conv_tile(
     const float* __restrict__ src, const uint8_t* __restrict__ M, int W, int H, int64_t pitch,
@@ -168,63 +281,14 @@ __global__ __launch_bounds__(256) void k_conv_tile(
     const int Y1 = min(min(Y0 + TILE, (py + 1) * P), H);
     if (X0 >= X1 || Y0 >= Y1) return;
 
-    // ---- patch kernel (FP64) -> FP32 taps
-    {
-        RealiseLds& sh = *reinterpret_cast<RealiseLds*>(halo);
-        double* Kd = reinterpret_cast<double*>(reinterpret_cast<char*>(halo) + sizeof(RealiseLds));
-        const int x0 = px * P, x1 = min(x0 + P, W), y0 = py * P, y1 = min(y0 + P, H);
-        realise_kernel(B, a, 0.5 * (x0 + x1 - 1), 0.5 * (y0 + y1 - 1), W, H, sh, Kd);
-        kernel_stats(Kd, H_, bad_frac, MODE == 1 ? cov_in : nullptr, c_in, ring, red, &s_rb, &s_f);
-        const double f = s_f;
-        for (int t = tid; t < T; t += 256) {
-            const int uu = t / KW, vv = t - uu * KW;     // column-major
-            const double k = Kd[vv * KW + uu];
-            taps[t] = (float)(MODE == 0 ? k : f * k * k);
-        }
-        __syncthreads();
-    }
-
-    for (int e = tid; e < HW * NWB; e += 256) (&badw[0][0])[e] = 0u;
-    __syncthreads();
-    int anybad = 0;
-    for (int e = tid; e < HW * HW; e += 256) {
-        const int hy = e / HW, hx = e - hy * HW;
-        const int gy = Y0 - H_ + hy, gx = X0 - H_ + hx;
-        float v = 0.0f;
-        bool ok = gx >= 0 && gx < W && gy >= 0 && gy < H;
-        if (ok) {
-            const int64_t o = (int64_t)gy * pitch + gx;
-            ok = M[o] == 0;
-            if (ok) v = src[o];
-        }
-        halo[e] = v;
-        if (!ok) {
-            anybad = 1;
-            if (MODE == 0) atomicOr(&badw[hy][hx >> 5], 1u << (hx & 31));
-        }
-    }
-    anybad = __syncthreads_or(anybad);
+    patch_taps<H_>(B, a, W, H, P, px, py, bad_frac, cov_in, c_in, halo, MODE == 0 ? taps : nullptr,
+                   MODE == 1 ? taps : nullptr, ring, red, &s_rb, &s_f);
+    const int anybad = load_halo<H_, MODE == 0>(src, M, W, H, pitch, X0, Y0, halo, badw);
 
     const int lx = tid & 63;
     const int r0 = (tid >> 6) * 16;
     float acc[16];
-#pragma unroll
-    for (int j = 0; j < 16; j++) acc[j] = 0.0f;
-    for (int uu = 0; uu < KW; uu++) {
-        float kc[KW];
-#pragma unroll
-        for (int vv = 0; vv < KW; vv++) kc[vv] = taps[uu * KW + vv];
-        const float* col = halo + r0 * HW + lx + 2 * H_ - uu;
-#pragma unroll
-        for (int hr = 0; hr < 16 + 2 * H_; hr++) {
-            const float val = col[hr * HW];
-#pragma unroll
-            for (int j = 0; j < 16; j++) {
-                const int vv = j + 2 * H_ - hr;
-                if (vv >= 0 && vv < KW) acc[j] = fmaf(kc[vv], val, acc[j]);
-            }
-        }
-    }
+    conv16<H_>(halo, taps, lx, r0, acc);
     const int gx = X0 + lx;
     if (gx < X1) {
 #pragma unroll
@@ -234,31 +298,15 @@ __global__ __launch_bounds__(256) void k_conv_tile(
         }
     }
     if (MODE == 0) {
-        uint64_t poorv = 0, badv = 0;
-        const int rb = s_rb;
-        if (anybad) {
-            const uint64_t kmask = (KW >= 64) ? ~0ull : ((1ull << KW) - 1ull);
-            const uint64_t bmask = (1ull << (2 * rb + 1)) - 1ull;
-            const int w = lx >> 5, sh = lx & 31;
-#pragma unroll
-            for (int hr = 0; hr < 16 + 2 * H_; hr++) {
-                const uint32_t* bw = badw[r0 + hr];
-                const uint64_t bits = ((uint64_t)bw[w] | ((uint64_t)bw[w + 1] << 32)) >> sh;
-                const uint64_t win = bits & kmask;      // halo columns [lx, lx + 2h]
-                if (win) poorv |= 1ull << hr;
-                if ((win >> (H_ - rb)) & bmask) badv |= 1ull << hr;
-            }
-        }
+        uint32_t bad16 = 0, poor16 = 0;
+        if (anybad) mask16<H_>(badw, s_rb, lx, r0, &bad16, &poor16);
         if (gx < X1) {
 #pragma unroll
             for (int j = 0; j < 16; j++) {
                 const int gy = Y0 + r0 + j;
                 if (gy < Y1) {
-                    uint8_t m = 0;
-                    if (anybad) {
-                        if ((badv >> (j + H_ - rb)) & ((1ull << (2 * rb + 1)) - 1ull)) m = PSFM_MASK_CONV_BAD;
-                        else if ((poorv >> j) & ((KW >= 64) ? ~0ull : ((1ull << KW) - 1ull))) m = PSFM_MASK_CONV_POOR;
-                    }
+                    const uint8_t m = ((bad16 >> j) & 1u) ? PSFM_MASK_CONV_BAD
+                                      : ((poor16 >> j) & 1u) ? PSFM_MASK_CONV_POOR : 0;
                     out_mask[(int64_t)gy * pitch + gx] = m;
                 }
             }
@@ -294,25 +342,25 @@ int dispatch_conv(const float* src, const uint8_t* M, int W, int H, int64_t pitc
     }
 }
 
-// raw(delta) / sum K^2 for the kernel realised at the centre of cell
-// blockIdx.x of the 3 x 3 partition; blockIdx.y chunks the offsets.
+// raw(delta) / sum K^2 for the kernel realised at the centre of cell j of the
+// 3 x 3 partition; chunk selects 256 of the offsets.
 //   raw(delta) = sum_w C_in(w) sum_u K(u) K(u + delta - w)
-__global__ __launch_bounds__(256) void k_cov_samples(const double* __restrict__ a, BasisArgs B,
-                                                     int W, int H, const double* __restrict__ cov_in,
-                                                     int c_in, double* __restrict__ samples) {
+__device__ void cov_samples_body(const double* __restrict__ a, const BasisArgs& B, int W, int H,
+                                 const double* __restrict__ cov_in, int c_in,
+                                 double* __restrict__ samples, const int j, const int chunk) {
     __shared__ RealiseLds sh;
     __shared__ double Kd[(2 * PSFM_HMAX + 1) * (2 * PSFM_HMAX + 1)];
     __shared__ double red[16];
     const int h = B.h, KW = 2 * h + 1, T = KW * KW;
     const int R = 2 * h + c_in, Rw = 2 * R + 1;
-    const int j = blockIdx.x, tid = threadIdx.x;
+    const int tid = threadIdx.x;
     const int jx = j % 3, jy = j / 3;
     const int cx0 = jx * W / 3, cx1 = (jx + 1) * W / 3, cy0 = jy * H / 3, cy1 = (jy + 1) * H / 3;
     realise_kernel(B, a, 0.5 * (cx0 + cx1 - 1), 0.5 * (cy0 + cy1 - 1), W, H, sh, Kd);
     double s2 = 0.0;
     for (int t = tid; t < T; t += 256) s2 += Kd[t] * Kd[t];
     const double sumk2 = psfm_block_sum(s2, red);
-    const int d = blockIdx.y * 256 + tid;
+    const int d = chunk * 256 + tid;
     if (d >= Rw * Rw) return;
     const int dy = d / Rw - R, dx = d % Rw - R;
     const int Cw = 2 * c_in + 1;
@@ -335,10 +383,24 @@ __global__ __launch_bounds__(256) void k_cov_samples(const double* __restrict__ 
     samples[(size_t)j * Rw * Rw + d] = sumk2 > 0.0 ? raw / sumk2 : 0.0;
 }
 
-__global__ __launch_bounds__(256) void k_cov_finish(const double* __restrict__ samples, int R,
-                                                    double* __restrict__ avg,
-                                                    double* __restrict__ cov_out, int c_out,
-                                                    psfm_fit_stats* stats) {
+__global__ __launch_bounds__(256) void k_cov_samples(const double* __restrict__ a, BasisArgs B,
+                                                     int W, int H, const double* __restrict__ cov_in,
+                                                     int c_in, double* __restrict__ samples) {
+    cov_samples_body(a, B, W, H, cov_in, c_in, samples, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(256) void k_cov_samples_b(const PairDesc* __restrict__ pairs, BasisArgs B0) {
+    const PairDesc& p = pairs[blockIdx.z];
+    const int Rw = 2 * (2 * B0.h + p.cov1_half) + 1;
+    if ((int)blockIdx.y * 256 >= Rw * Rw) return;
+    BasisArgs B = B0;
+    B.ns = p.ns;
+    B.S = p.S;
+    cov_samples_body(p.coeffs, B, p.W, p.H, p.cov1, p.cov1_half, p.cov_samples, blockIdx.x, blockIdx.y);
+}
+
+__device__ void cov_finish_body(const double* __restrict__ samples, int R, double* __restrict__ avg,
+                                double* __restrict__ cov_out, int c_out, psfm_fit_stats* stats) {
     __shared__ double red[16];
     __shared__ double s_centre;
     const int Rw = 2 * R + 1, n = Rw * Rw, tid = threadIdx.x;
@@ -369,6 +431,18 @@ __global__ __launch_bounds__(256) void k_cov_finish(const double* __restrict__ s
     }
     kept = psfm_block_sum(kept, red);
     if (tid == 0 && stats) stats->cov_discarded_frac = tot > 0.0 ? (tot - kept) / tot : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_cov_finish(const double* __restrict__ samples, int R,
+                                                    double* __restrict__ avg,
+                                                    double* __restrict__ cov_out, int c_out,
+                                                    psfm_fit_stats* stats) {
+    cov_finish_body(samples, R, avg, cov_out, c_out, stats);
+}
+
+__global__ __launch_bounds__(256) void k_cov_finish_b(const PairDesc* __restrict__ pairs, int h) {
+    const PairDesc& p = pairs[blockIdx.x];
+    cov_finish_body(p.cov_samples, 2 * h + p.cov1_half, p.cov_avg, p.cov, p.cov_half, p.stats);
 }
 
 __global__ __launch_bounds__(256) void k_subtract(
@@ -416,13 +490,16 @@ __global__ __launch_bounds__(256) void k_subtract(
     }
 }
 
-__global__ __launch_bounds__(256) void k_subtract_cov(const double* __restrict__ partials, int nblk,
-                                                      const double* __restrict__ cov2, int c2,
-                                                      const double* __restrict__ covc, int cc,
-                                                      double* __restrict__ covd, int cd) {
+// C_D = (v2 C_2 + vc C') / (v2 + vc), with v2 and vc the mean variances of
+// the unmasked pixels of image 2 and of the convolved image, summed from the
+// per-block partials [nparts][4] = (sum V2, n2, sum V', n').
+__device__ void cov_diff_body(const double* __restrict__ partials, int nparts,
+                              const double* __restrict__ cov2, int c2,
+                              const double* __restrict__ covc, int cc, double* __restrict__ covd,
+                              int cd) {
     __shared__ double red[16];
     double v[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int b = threadIdx.x; b < nblk; b += 256)
+    for (int b = threadIdx.x; b < nparts; b += 256)
         for (int k = 0; k < 4; k++) v[k] += partials[4 * b + k];
     for (int k = 0; k < 4; k++) v[k] = psfm_block_sum(v[k], red);
     const double v2 = v[1] > 0.0 ? v[0] / v[1] : 0.0;
@@ -438,6 +515,147 @@ __global__ __launch_bounds__(256) void k_subtract_cov(const double* __restrict__
         }
         if (covc && abs(dx) <= cc && abs(dy) <= cc) ac = covc[(dy + cc) * (2 * cc + 1) + (dx + cc)];
         covd[e] = (v2 + vc) > 0.0 ? (v2 * a2 + vc * ac) / (v2 + vc) : 0.0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_subtract_cov(const double* __restrict__ partials, int nblk,
+                                                      const double* __restrict__ cov2, int c2,
+                                                      const double* __restrict__ covc, int cc,
+                                                      double* __restrict__ covd, int cd) {
+    cov_diff_body(partials, nblk, cov2, c2, covc, cc, covd, cd);
+}
+
+// Fused apply for every pair of a batch: per 64 x 64 tile (flattened over
+// all pairs, pair after pair, visited by a grid-stride loop) the patch
+// kernel is realised once; I' = K (x) I1 with its BAD/POOR mask, then
+// D = I2 - I' - d0; V' = f K^2 (x) V1, then V_D = V2 + V'.  The tile's
+// variance sums go to the pair's partials; the workgroup that finishes a
+// pair's last tile forms that pair's C_D and stamps its completion time.
+template <int H_>
+__global__ __launch_bounds__(256) void k_match_tiles_b(const PairDesc* __restrict__ pairs,
+                                                       const int* __restrict__ tile_pair,
+                                                       int n_tiles, BasisArgs B0, int P,
+                                                       double bad_frac) {
+    constexpr int KW = 2 * H_ + 1;
+    constexpr int T = KW * KW;
+    constexpr int HW = TILE + 2 * H_;
+    constexpr int NWB = (HW + 31) / 32 + 1;
+    static_assert(sizeof(float) * HW * HW >= sizeof(RealiseLds) + sizeof(double) * T,
+                  "kernel scratch must fit in the halo buffer");
+    __shared__ __align__(16) float halo[HW * HW];
+    __shared__ __align__(16) float tapsK[T + 4];
+    __shared__ __align__(16) float tapsV[T + 4];
+    __shared__ uint32_t badw[HW][NWB];
+    __shared__ double ring[H_ + 1];
+    __shared__ double red[16];
+    __shared__ int s_rb;
+    __shared__ double s_f;
+    __shared__ int s_last;
+    const int tid = threadIdx.x;
+    const int lx = tid & 63;
+    const int r0 = (tid >> 6) * 16;
+    for (int item = blockIdx.x; item < n_tiles; item += gridDim.x) {
+        const PairDesc& p = pairs[tile_pair[item]];
+        const int W = p.W, H = p.H;
+        const int64_t pitch = p.pitch;
+        const int t = item - p.tile_off;
+        const PatchGeom g = patch_geom(W, H, P);
+        const int tx = t % p.ntx, ty = t / p.ntx;
+        const int px = tx / g.tpp, sx = tx % g.tpp;
+        const int py = ty / g.tpp, sy = ty % g.tpp;
+        const int X0 = px * P + sx * TILE, Y0 = py * P + sy * TILE;
+        const int X1 = min(min(X0 + TILE, (px + 1) * P), W);
+        const int Y1 = min(min(Y0 + TILE, (py + 1) * P), H);
+        double s2 = 0.0, n2 = 0.0, sc = 0.0, nc = 0.0;
+        if (X0 < X1 && Y0 < Y1) {
+            BasisArgs B = B0;
+            B.ns = p.ns;
+            B.S = p.S;
+            patch_taps<H_>(B, p.coeffs, W, H, P, px, py, bad_frac, p.cov1, p.cov1_half, halo, tapsK,
+                           tapsV, ring, red, &s_rb, &s_f);
+            const int anybad = load_halo<H_, true>(p.I1, p.M1, W, H, pitch, X0, Y0, halo, badw);
+            float acc[16];
+            conv16<H_>(halo, tapsK, lx, r0, acc);
+            uint32_t bad16 = 0, poor16 = 0;
+            if (anybad) mask16<H_>(badw, s_rb, lx, r0, &bad16, &poor16);
+            const double d0 = p.coeffs[p.N - 1];
+            const int gx = X0 + lx;
+            uint32_t m2bits = 0;
+            if (gx < X1) {
+#pragma unroll
+                for (int j = 0; j < 16; j++) {
+                    const int gy = Y0 + r0 + j;
+                    if (gy < Y1) {
+                        const int64_t o = (int64_t)gy * pitch + gx;
+                        const uint8_t cm = ((bad16 >> j) & 1u) ? PSFM_MASK_CONV_BAD
+                                           : ((poor16 >> j) & 1u) ? PSFM_MASK_CONV_POOR : 0;
+                        if (p.conv) {
+                            p.conv[o] = acc[j];
+                            p.conv_mask[o] = cm;
+                        }
+                        if (p.M2[o]) {
+                            m2bits |= 1u << j;
+                            p.diff[o] = 0.0f;
+                            p.diff_mask[o] = (uint8_t)(PSFM_MASK_BAD | cm);
+                        } else {
+                            p.diff[o] = (float)((double)p.I2[o] - (double)acc[j] - d0);
+                            p.diff_mask[o] = cm;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            load_halo<H_, false>(p.V1, p.M1, W, H, pitch, X0, Y0, halo, badw);
+            conv16<H_>(halo, tapsV, lx, r0, acc);
+            if (gx < X1) {
+#pragma unroll
+                for (int j = 0; j < 16; j++) {
+                    const int gy = Y0 + r0 + j;
+                    if (gy < Y1) {
+                        const int64_t o = (int64_t)gy * pitch + gx;
+                        const float cv = acc[j];
+                        if (p.var) p.var[o] = cv;
+                        if ((m2bits >> j) & 1u) {
+                            p.diff_var[o] = 0.0f;
+                        } else {
+                            const float v2 = p.V2[o];
+                            p.diff_var[o] = (float)((double)v2 + (double)cv);
+                            s2 += v2;
+                            n2 += 1.0;
+                        }
+                        if (!((bad16 | poor16) >> j & 1u)) {
+                            sc += cv;
+                            nc += 1.0;
+                        }
+                    }
+                }
+            }
+        }
+        s2 = psfm_block_sum(s2, red);
+        n2 = psfm_block_sum(n2, red);
+        sc = psfm_block_sum(sc, red);
+        nc = psfm_block_sum(nc, red);
+        if (tid == 0) {
+            double* q = p.sub_part + 4 * (size_t)t;
+            q[0] = s2;
+            q[1] = n2;
+            q[2] = sc;
+            q[3] = nc;
+            __threadfence();
+            const unsigned prev = atomicAdd(p.tiles_done, 1u);
+            s_last = prev + 1 == (unsigned)(p.ntx * p.nty);
+        }
+        __syncthreads();
+        if (s_last) {
+            __threadfence();
+            cov_diff_body(p.sub_part, p.ntx * p.nty, p.cov2, p.cov2_half, p.cov, p.cov_half,
+                          p.cov_diff, p.cov_diff_half);
+            if (tid == 0 && p.t_done) {
+                __threadfence();
+                *p.t_done = wall_clock64();
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -461,9 +679,9 @@ size_t subtract_workspace(const psfm_context*, int, int) {
     return c.off;
 }
 
-}  // namespace psfm
+int cov_sample_side(const psfm_context* ctx, int c_in) { return 2 * (2 * ctx->h + c_in) + 1; }
 
-static BasisArgs basis_args(const psfm_context* ctx) {
+static BasisArgs basis_args_of(const psfm_context* ctx) {
     BasisArgs B;
     B.fac64 = ctx->fac64;
     B.psi64 = ctx->psi64;
@@ -477,6 +695,42 @@ static BasisArgs basis_args(const psfm_context* ctx) {
     B.h = ctx->h;
     return B;
 }
+
+template <int H_>
+int launch_match_tiles(const psfm_context* ctx, const PairDesc* pairs, const int* tile_pair,
+                       int n_tiles, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_match_tiles_b<H_>, dim3(grid), dim3(256), 0, st, pairs, tile_pair, n_tiles,
+                       basis_args_of(ctx), ctx->cfg.patch, ctx->cfg.bad_frac);
+    PSFM_HIP_CHECK(hipGetLastError());
+    return PSFM_OK;
+}
+
+int batch_apply(const psfm_context* ctx, const PairDesc* pairs, const int* tile_pair, int n_pairs,
+                int n_tiles, int max_cov_in, int conv_grid, hipStream_t st) {
+    if (n_pairs == 0) return PSFM_OK;
+    const int Rw = cov_sample_side(ctx, max_cov_in);
+    hipLaunchKernelGGL(k_cov_samples_b, dim3(PSFM_COV_SAMPLES, (Rw * Rw + 255) / 256, n_pairs),
+                       dim3(256), 0, st, pairs, basis_args_of(ctx));
+    hipLaunchKernelGGL(k_cov_finish_b, dim3(n_pairs), dim3(256), 0, st, pairs, ctx->h);
+    PSFM_HIP_CHECK(hipGetLastError());
+    if (n_tiles == 0) return PSFM_OK;
+    const int grid = (conv_grid > 0 && conv_grid < n_tiles) ? conv_grid : n_tiles;
+    switch (ctx->h) {
+#define PSFM_MT_CASE(HH) \
+    case HH: return launch_match_tiles<HH>(ctx, pairs, tile_pair, n_tiles, grid, st);
+        PSFM_MT_CASE(1) PSFM_MT_CASE(2) PSFM_MT_CASE(3) PSFM_MT_CASE(4) PSFM_MT_CASE(5)
+        PSFM_MT_CASE(6) PSFM_MT_CASE(7) PSFM_MT_CASE(8) PSFM_MT_CASE(9) PSFM_MT_CASE(10)
+        PSFM_MT_CASE(11) PSFM_MT_CASE(12) PSFM_MT_CASE(13) PSFM_MT_CASE(14) PSFM_MT_CASE(15)
+        PSFM_MT_CASE(16)
+#undef PSFM_MT_CASE
+        default: return PSFM_ERR_UNSUPPORTED;
+    }
+}
+
+}  // namespace psfm
+
+static BasisArgs basis_args(const psfm_context* ctx) { return psfm::basis_args_of(ctx); }
+
 
 static int check_image_args(const psfm_context* ctx, int W, int H, int64_t pitch) {
     if (!ctx) return PSFM_ERR_INVALID_ARG;

@@ -49,21 +49,53 @@ __host__ __device__ inline FitLds fit_lds_layout(int h, int r, int nb, int nf) {
     return L;
 }
 
+// Arguments of one stamp fit (one image pair).
+struct FitArgs {
+    const float* I1;
+    const uint8_t* M1;
+    const float* I2;
+    const float* V2;
+    const uint8_t* M2;
+    int W, H;
+    int64_t pitch;
+    const int32_t* xy;
+    int r, nbands;
+    const float* fac;
+    const int* rowf;
+    const int* colf;
+    const float* psi;
+    const float* zf;
+    int nb, nf;
+    double* part;
+    int* band_flags;
+};
+
+// One band of one stamp (item = stamp * nbands + band).
 template <int H_>
-__global__ __launch_bounds__(256) void k_fit_band(
-    const float* __restrict__ I1, const uint8_t* __restrict__ M1, const float* __restrict__ I2,
-    const float* __restrict__ V2, const uint8_t* __restrict__ M2, int W, int H, int64_t pitch,
-    const int32_t* __restrict__ xy, int r, int nbands, const float* __restrict__ fac,
-    const int* __restrict__ rowf, const int* __restrict__ colf, const float* __restrict__ psi,
-    const float* __restrict__ zf, int nb, int nf, double* __restrict__ part,
-    int* __restrict__ band_flags) {
+__device__ void fit_band_body(const FitArgs& a, const int item, float* __restrict__ lds) {
+    const float* __restrict__ I1 = a.I1;
+    const uint8_t* __restrict__ M1 = a.M1;
+    const float* __restrict__ I2 = a.I2;
+    const float* __restrict__ V2 = a.V2;
+    const uint8_t* __restrict__ M2 = a.M2;
+    const int W = a.W, H = a.H;
+    const int64_t pitch = a.pitch;
+    const int32_t* __restrict__ xy = a.xy;
+    const int r = a.r, nbands = a.nbands;
+    const float* __restrict__ fac = a.fac;
+    const int* __restrict__ rowf = a.rowf;
+    const int* __restrict__ colf = a.colf;
+    const float* __restrict__ psi = a.psi;
+    const float* __restrict__ zf = a.zf;
+    const int nb = a.nb, nf = a.nf;
+    double* __restrict__ part = a.part;
+    int* __restrict__ band_flags = a.band_flags;
     constexpr int KW = 2 * H_ + 1;
-    extern __shared__ float lds[];
     __shared__ int s_flags;
 
     const int tid = threadIdx.x;
-    const int s = blockIdx.x / nbands;
-    const int band = blockIdx.x % nbands;
+    const int s = item / nbands;
+    const int band = item % nbands;
     const int xc = xy[2 * s], yc = xy[2 * s + 1];
     const int R = r + H_;
     const int NPX = 2 * r + 1;
@@ -80,7 +112,7 @@ __global__ __launch_bounds__(256) void k_fit_band(
     float* zb = lds + Lo.z;
 
     if (xc - R < 0 || yc - R < 0 || xc + R >= W || yc + R >= H) {
-        if (tid == 0) band_flags[blockIdx.x] = PSFM_STAMP_INVALID;
+        if (tid == 0) band_flags[item] = PSFM_STAMP_INVALID;
         return;
     }
     if (tid == 0) s_flags = 0;
@@ -141,7 +173,7 @@ __global__ __launch_bounds__(256) void k_fit_band(
     const float cshift = (float)(psfm_block_sum(wsum, red) / ((nbr + 2 * H_) * WC));
     const int flags = s_flags;
     if (flags) {
-        if (tid == 0) band_flags[blockIdx.x] = flags;
+        if (tid == 0) band_flags[item] = flags;
         return;
     }
     for (int e = tid; e < (nbr + 2 * H_) * WC; e += 256) win[e] -= cshift;
@@ -250,7 +282,7 @@ __global__ __launch_bounds__(256) void k_fit_band(
     }
 
     // ---- 4. partial Gram out: rows 16 bm + 4 (lane / 16) + q, column 16 bn + lane % 16
-    double* G = part + (size_t)blockIdx.x * GC * GC;
+    double* G = part + (size_t)item * GC * GC;
     const int bms[4][3] = {{0, 1, 1}, {2, 2, 2}, {3, 3, -1}, {3, 3, -1}};
     const int bns[4][3] = {{0, 0, 1}, {0, 1, 2}, {0, 1, -1}, {2, 3, -1}};
 #pragma unroll
@@ -261,17 +293,44 @@ __global__ __launch_bounds__(256) void k_fit_band(
 #pragma unroll
         for (int e = 0; e < 4; e++) G[(16 * bm + 4 * (lane >> 4) + e) * GC + col] = acc64[q][e];
     }
-    if (tid == 0) band_flags[blockIdx.x] = 0;
+    if (tid == 0) band_flags[item] = 0;
+}
+
+template <int H_>
+__global__ __launch_bounds__(256) void k_fit_band(FitArgs a) {
+    extern __shared__ float lds[];
+    fit_band_body<H_>(a, blockIdx.x, lds);
+}
+
+// All bands of all stamps of all pairs of a batch; item_pair maps the
+// flattened band index to its pair.
+template <int H_>
+__global__ __launch_bounds__(256) void k_fit_band_b(const PairDesc* __restrict__ pairs,
+                                                    const int* __restrict__ item_pair, FitArgs base) {
+    extern __shared__ float lds[];
+    const PairDesc& pd = pairs[item_pair[blockIdx.x]];
+    FitArgs a = base;
+    a.I1 = pd.I1;
+    a.M1 = pd.M1;
+    a.I2 = pd.I2;
+    a.V2 = pd.V2;
+    a.M2 = pd.M2;
+    a.W = pd.W;
+    a.H = pd.H;
+    a.pitch = pd.pitch;
+    a.xy = pd.xy;
+    a.part = pd.part;
+    a.band_flags = pd.bflags;
+    fit_band_body<H_>(a, blockIdx.x - pd.band_off, lds);
 }
 
 // Sum of the band partials of each stamp in FP64 and scatter to M_s, b_s, e_s.
-__global__ __launch_bounds__(256) void k_fit_reduce(const double* __restrict__ part,
-                                                    const int* __restrict__ band_flags, int nbands,
-                                                    int nb, int npix, double* __restrict__ Ms,
-                                                    double* __restrict__ bs, double* __restrict__ es,
-                                                    int32_t* __restrict__ npix_out,
-                                                    int32_t* __restrict__ flags_out) {
-    const int s = blockIdx.x, tid = threadIdx.x;
+__device__ void fit_reduce_body(const double* __restrict__ part, const int* __restrict__ band_flags,
+                                int nbands, int nb, int npix, double* __restrict__ Ms,
+                                double* __restrict__ bs, double* __restrict__ es,
+                                int32_t* __restrict__ npix_out, int32_t* __restrict__ flags_out,
+                                const int s) {
+    const int tid = threadIdx.x;
     const int L = nb + 1;
     int fl = 0;
     for (int b = 0; b < nbands; b++) fl |= band_flags[s * nbands + b];
@@ -301,24 +360,77 @@ __global__ __launch_bounds__(256) void k_fit_reduce(const double* __restrict__ p
     }
 }
 
+__global__ __launch_bounds__(256) void k_fit_reduce(const double* __restrict__ part,
+                                                    const int* __restrict__ band_flags, int nbands,
+                                                    int nb, int npix, double* __restrict__ Ms,
+                                                    double* __restrict__ bs, double* __restrict__ es,
+                                                    int32_t* __restrict__ npix_out,
+                                                    int32_t* __restrict__ flags_out) {
+    fit_reduce_body(part, band_flags, nbands, nb, npix, Ms, bs, es, npix_out, flags_out, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_fit_reduce_b(const PairDesc* __restrict__ pairs,
+                                                      const int* __restrict__ stamp_pair, int nbands,
+                                                      int nb, int npix) {
+    const PairDesc& pd = pairs[stamp_pair[blockIdx.x]];
+    fit_reduce_body(pd.part, pd.bflags, nbands, nb, npix, pd.Ms, pd.bs, pd.es, pd.npix, pd.flags,
+                    blockIdx.x - pd.stamp_off);
+}
+
+FitArgs base_fit_args(const psfm_context* ctx) {
+    FitArgs a{};
+    a.r = ctx->r;
+    a.nbands = psfm::fit_bands(ctx);
+    a.fac = ctx->fac;
+    a.rowf = ctx->term_rowf;
+    a.colf = ctx->term_colf;
+    a.psi = ctx->term_psi;
+    a.zf = ctx->term_z;
+    a.nb = ctx->nb;
+    a.nf = ctx->nf;
+    return a;
+}
+
 template <int H_>
-int launch_fit(const psfm_context* ctx, const float* I1, const uint8_t* M1, const float* I2,
-               const float* V2, const uint8_t* M2, int W, int H, int64_t pitch, const int32_t* xy,
-               int n, double* part, int* bflags, hipStream_t st) {
-    const int nbands = psfm::fit_bands(ctx);
-    const FitLds Lo = fit_lds_layout(H_, ctx->r, ctx->nb, ctx->nf);
-    const size_t lds = (size_t)Lo.total * sizeof(float);
-    static size_t attr_set = 0;      // dynamic LDS granted so far
-    if (lds > attr_set) {
+int set_fit_lds(size_t lds) {
+    static size_t granted = 0;      // dynamic LDS granted so far (both kernels)
+    if (lds > granted) {
         PSFM_HIP_CHECK(hipFuncSetAttribute((const void*)k_fit_band<H_>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        attr_set = lds;
+        PSFM_HIP_CHECK(hipFuncSetAttribute((const void*)k_fit_band_b<H_>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        granted = lds;
     }
-    hipLaunchKernelGGL(k_fit_band<H_>, dim3(n * nbands), dim3(256), lds, st, I1, M1, I2, V2, M2, W, H,
-                       pitch, xy, ctx->r, nbands, ctx->fac, ctx->term_rowf, ctx->term_colf,
-                       ctx->term_psi, ctx->term_z, ctx->nb, ctx->nf, part, bflags);
+    return PSFM_OK;
+}
+
+template <int H_>
+int launch_fit(const psfm_context* ctx, const FitArgs& a, int n_items, const PairDesc* pairs,
+               const int* item_pair, hipStream_t st) {
+    const FitLds Lo = fit_lds_layout(H_, ctx->r, ctx->nb, ctx->nf);
+    const size_t lds = (size_t)Lo.total * sizeof(float);
+    int rc = set_fit_lds<H_>(lds);
+    if (rc) return rc;
+    if (pairs)
+        hipLaunchKernelGGL(k_fit_band_b<H_>, dim3(n_items), dim3(256), lds, st, pairs, item_pair, a);
+    else
+        hipLaunchKernelGGL(k_fit_band<H_>, dim3(n_items), dim3(256), lds, st, a);
     PSFM_HIP_CHECK(hipGetLastError());
     return PSFM_OK;
+}
+
+int dispatch_fit(const psfm_context* ctx, const FitArgs& a, int n_items, const PairDesc* pairs,
+                 const int* item_pair, hipStream_t st) {
+    switch (ctx->h) {
+#define PSFM_FIT_CASE(HH) \
+    case HH: return launch_fit<HH>(ctx, a, n_items, pairs, item_pair, st);
+        PSFM_FIT_CASE(1) PSFM_FIT_CASE(2) PSFM_FIT_CASE(3) PSFM_FIT_CASE(4) PSFM_FIT_CASE(5)
+        PSFM_FIT_CASE(6) PSFM_FIT_CASE(7) PSFM_FIT_CASE(8) PSFM_FIT_CASE(9) PSFM_FIT_CASE(10)
+        PSFM_FIT_CASE(11) PSFM_FIT_CASE(12) PSFM_FIT_CASE(13) PSFM_FIT_CASE(14) PSFM_FIT_CASE(15)
+        PSFM_FIT_CASE(16)
+#undef PSFM_FIT_CASE
+        default: return PSFM_ERR_UNSUPPORTED;
+    }
 }
 
 }  // namespace
@@ -327,6 +439,34 @@ namespace psfm {
 
 size_t fit_lds_bytes(const psfm_context* ctx) {
     return (size_t)fit_lds_layout(ctx->h, ctx->r, ctx->nb, ctx->nf).total * sizeof(float);
+}
+
+// Grants the fit kernels their dynamic LDS (done ahead of a graph capture).
+int fit_prepare(const psfm_context* ctx) {
+    const size_t lds = fit_lds_bytes(ctx);
+    switch (ctx->h) {
+#define PSFM_FIT_PREP(HH) \
+    case HH: return set_fit_lds<HH>(lds);
+        PSFM_FIT_PREP(1) PSFM_FIT_PREP(2) PSFM_FIT_PREP(3) PSFM_FIT_PREP(4) PSFM_FIT_PREP(5)
+        PSFM_FIT_PREP(6) PSFM_FIT_PREP(7) PSFM_FIT_PREP(8) PSFM_FIT_PREP(9) PSFM_FIT_PREP(10)
+        PSFM_FIT_PREP(11) PSFM_FIT_PREP(12) PSFM_FIT_PREP(13) PSFM_FIT_PREP(14) PSFM_FIT_PREP(15)
+        PSFM_FIT_PREP(16)
+#undef PSFM_FIT_PREP
+        default: return PSFM_ERR_UNSUPPORTED;
+    }
+}
+
+int batch_fit(const psfm_context* ctx, const PairDesc* pairs, const int* item_pair,
+              const int* stamp_pair, int n_items, int n_stamps, hipStream_t st) {
+    if (fit_lds_bytes(ctx) > 160 * 1024 - 1024) return PSFM_ERR_UNSUPPORTED;
+    if (n_items == 0) return PSFM_OK;
+    int rc = dispatch_fit(ctx, base_fit_args(ctx), n_items, pairs, item_pair, st);
+    if (rc) return rc;
+    const int npix = (2 * ctx->r + 1) * (2 * ctx->r + 1);
+    hipLaunchKernelGGL(k_fit_reduce_b, dim3(n_stamps), dim3(256), 0, st, pairs, stamp_pair,
+                       fit_bands(ctx), ctx->nb, npix);
+    PSFM_HIP_CHECK(hipGetLastError());
+    return PSFM_OK;
 }
 
 size_t fit_workspace(const psfm_context* ctx, int n_stamps) {
@@ -359,17 +499,19 @@ extern "C" int psfm_fit_stamps(const psfm_context* ctx, const float* I1, const u
     const size_t nbl = (size_t)n_stamps * psfm::fit_bands(ctx);
     double* part = c.take<double>(nbl * GC * GC);
     int* bflags = c.take<int>(nbl);
-    int rc;
-    switch (ctx->h) {
-#define PSFM_FIT_CASE(HH) \
-    case HH: rc = launch_fit<HH>(ctx, I1, M1, I2, V2, M2, W, H, pitch, stamp_xy, n_stamps, part, bflags, st); break;
-        PSFM_FIT_CASE(1) PSFM_FIT_CASE(2) PSFM_FIT_CASE(3) PSFM_FIT_CASE(4) PSFM_FIT_CASE(5)
-        PSFM_FIT_CASE(6) PSFM_FIT_CASE(7) PSFM_FIT_CASE(8) PSFM_FIT_CASE(9) PSFM_FIT_CASE(10)
-        PSFM_FIT_CASE(11) PSFM_FIT_CASE(12) PSFM_FIT_CASE(13) PSFM_FIT_CASE(14) PSFM_FIT_CASE(15)
-        PSFM_FIT_CASE(16)
-#undef PSFM_FIT_CASE
-        default: return PSFM_ERR_UNSUPPORTED;
-    }
+    FitArgs a = base_fit_args(ctx);
+    a.I1 = I1;
+    a.M1 = M1;
+    a.I2 = I2;
+    a.V2 = V2;
+    a.M2 = M2;
+    a.W = W;
+    a.H = H;
+    a.pitch = pitch;
+    a.xy = stamp_xy;
+    a.part = part;
+    a.band_flags = bflags;
+    int rc = dispatch_fit(ctx, a, n_stamps * a.nbands, nullptr, nullptr, st);
     if (rc != PSFM_OK) return rc;
     const int npix = (2 * ctx->r + 1) * (2 * ctx->r + 1);
     hipLaunchKernelGGL(k_fit_reduce, dim3(n_stamps), dim3(256), 0, st, part, bflags,

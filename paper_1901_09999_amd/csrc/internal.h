@@ -35,6 +35,84 @@ struct psfm_context {
     void* dev_block;  // single allocation backing all of the above
 };
 
+// Device-side state of one solve (rejection loop).
+struct SolveState {
+    int done;
+    int info;
+    int n_iter;
+    int n_rej;
+    int n_used;
+    int pad[3];
+};
+
+// Everything the kernels need about one image pair: inputs, outputs, the
+// pair's share of the workspace and its offsets in the flattened work lists
+// of a batch.  Built on the host; single-pair calls pass it by value, batched
+// calls read it from a device array.
+struct PairDesc {
+    const float* I1;
+    const float* V1;
+    const uint8_t* M1;
+    const float* I2;
+    const float* V2;
+    const uint8_t* M2;
+    int W, H;
+    int64_t pitch;
+    const int32_t* xy;
+    int n;                 // stamps
+    int S, ns, N;
+    // per-stamp results
+    double* Ms;
+    double* bs;
+    double* es;
+    int32_t* npix;
+    int32_t* flags;
+    double* chi2;
+    // solution
+    double* coeffs;
+    psfm_fit_stats* stats;
+    // solve scratch
+    SolveState* st;
+    uint8_t* used;
+    uint8_t* fitted;
+    double* G;
+    double* GU;
+    double* Mt;
+    double* bt;
+    double* A;
+    double* b;
+    double* ILg;
+    // fit scratch
+    double* part;
+    int* bflags;
+    // input covariance pseudo-matrices (nullable: uncorrelated)
+    const double* cov1;
+    int cov1_half;
+    const double* cov2;
+    int cov2_half;
+    // image outputs and their scratch
+    float* conv;
+    uint8_t* conv_mask;
+    float* var;
+    double* cov;
+    int cov_half;
+    float* diff;
+    float* diff_var;
+    uint8_t* diff_mask;
+    double* cov_diff;
+    int cov_diff_half;
+    double* cov_samples;
+    double* cov_avg;
+    double* sub_part;                // [tiles][4] variance sums of the tiles
+    unsigned int* tiles_done;        // tiles finished (batch completion counter)
+    uint64_t* t_done;                // completion time stamp (nullable)
+    // offsets in the flattened work lists of a batch
+    int band_off;
+    int stamp_off;
+    int tile_off;
+    int ntx, nty;
+};
+
 namespace psfm {
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -64,6 +142,22 @@ int fit_bands(const psfm_context* ctx);
 int n_patches(const psfm_context* ctx, int W, int H);
 
 int check_hip(hipError_t e);
+
+// Batched stages (all pairs of a batch per launch); pairs, item/stamp/tile
+// maps are device arrays.
+int batch_fit(const psfm_context* ctx, const PairDesc* pairs, const int* item_pair,
+              const int* stamp_pair, int n_items, int n_stamps, hipStream_t st);
+int batch_solve(const psfm_context* ctx, const PairDesc* pairs, const int* stamp_pair, int n_pairs,
+                int n_stamps_total, int max_n, int max_N, unsigned ns_mask, hipStream_t st);
+int batch_apply(const psfm_context* ctx, const PairDesc* pairs, const int* tile_pair, int n_pairs,
+                int n_tiles, int max_cov_in, int conv_grid, hipStream_t st);
+int fit_prepare(const psfm_context* ctx);
+size_t fit_lds_bytes(const psfm_context* ctx);
+int solve_lds_grant(size_t lds);
+size_t solve_lds_bytes(int N);
+int solve_max_unknowns();
+size_t solve_il_doubles(int N);
+int cov_sample_side(const psfm_context* ctx, int c_in);
 
 }  // namespace psfm
 

@@ -15,15 +15,6 @@
 
 namespace {
 
-struct SolveState {
-    int done;
-    int info;
-    int n_iter;
-    int n_rej;
-    int n_used;
-    int pad[3];
-};
-
 constexpr int CH_NB = 32;        // Cholesky panel width
 constexpr int CH_PS = 33;        // LDS row stride of the panel (doubles)
 constexpr int CH_THREADS = 512;
@@ -36,12 +27,12 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 
-__global__ void k_solve_init(int n, int N, int ns, int S, int W, int H, int min_stamps,
-                             const int32_t* __restrict__ xy, const int32_t* __restrict__ flags,
-                             uint8_t* __restrict__ used, uint8_t* __restrict__ fitted,
-                             double* __restrict__ G, double* __restrict__ chi2,
-                             double* __restrict__ coeffs, SolveState* st) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ void solve_init_body(int n, int N, int ns, int S, int W, int H, int min_stamps,
+                                const int32_t* __restrict__ xy, const int32_t* __restrict__ flags,
+                                uint8_t* __restrict__ used, uint8_t* __restrict__ fitted,
+                                double* __restrict__ G, double* __restrict__ chi2,
+                                double* __restrict__ coeffs, SolveState* st, const int bid) {
+    const int t = bid * blockDim.x + threadIdx.x;
     if (t < n) {
         const int u = flags[t] == 0;
         used[t] = u;
@@ -52,7 +43,7 @@ __global__ void k_solve_init(int n, int N, int ns, int S, int W, int H, int min_
         for (int s = 0; s < ns; s++) G[(size_t)t * ns + s] = g[s];
     }
     if (t < N) coeffs[t] = 0.0;
-    if (blockIdx.x == 0) {
+    if (bid == 0) {
         __shared__ int cnt;
         if (threadIdx.x == 0) cnt = 0;
         __syncthreads();
@@ -70,19 +61,47 @@ __global__ void k_solve_init(int n, int N, int ns, int S, int W, int H, int min_
     }
 }
 
+__global__ void k_solve_init(int n, int N, int ns, int S, int W, int H, int min_stamps,
+                             const int32_t* __restrict__ xy, const int32_t* __restrict__ flags,
+                             uint8_t* __restrict__ used, uint8_t* __restrict__ fitted,
+                             double* __restrict__ G, double* __restrict__ chi2,
+                             double* __restrict__ coeffs, SolveState* st) {
+    solve_init_body(n, N, ns, S, W, H, min_stamps, xy, flags, used, fitted, G, chi2, coeffs, st,
+                    blockIdx.x);
+}
+
+// Batched forms: blockIdx.y is the pair (uneven pairs leave blocks idle).
+__global__ void k_solve_init_b(const PairDesc* __restrict__ pairs, int min_stamps) {
+    const PairDesc& p = pairs[blockIdx.y];
+    if ((int)blockIdx.x * (int)blockDim.x >= max(max(p.n, p.N), 1)) return;
+    solve_init_body(p.n, p.N, p.ns, p.S, p.W, p.H, min_stamps, p.xy, p.flags, p.used, p.fitted,
+                    p.G, p.chi2, p.coeffs, p.st, blockIdx.x);
+}
+
 // Stamp-major copy of the stamp sums: Mt[ij][k] = M_k[ij], bt[i][k] = b_k[i],
 // so that the assembly reads each (i, j) entry of all stamps contiguously.
-__global__ void k_transpose_sums(int n, int L, const double* __restrict__ Ms,
-                                 const double* __restrict__ bs, double* __restrict__ Mt,
-                                 double* __restrict__ bt) {
+__device__ void transpose_sums_body(int n, int L, const double* __restrict__ Ms,
+                                    const double* __restrict__ bs, double* __restrict__ Mt,
+                                    double* __restrict__ bt, int bid, int nblk) {
     const int LL = L * L;
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < (size_t)n * (LL + L);
-         e += (size_t)gridDim.x * blockDim.x) {
+    for (size_t e = (size_t)bid * blockDim.x + threadIdx.x; e < (size_t)n * (LL + L);
+         e += (size_t)nblk * blockDim.x) {
         const int k = (int)(e % n);
         const size_t r = e / n;
         if (r < (size_t)LL) Mt[r * n + k] = Ms[(size_t)k * LL + r];
         else bt[(r - LL) * n + k] = bs[(size_t)k * L + (r - LL)];
     }
+}
+
+__global__ void k_transpose_sums(int n, int L, const double* __restrict__ Ms,
+                                 const double* __restrict__ bs, double* __restrict__ Mt,
+                                 double* __restrict__ bt) {
+    transpose_sums_body(n, L, Ms, bs, Mt, bt, blockIdx.x, gridDim.x);
+}
+
+__global__ void k_transpose_sums_b(const PairDesc* __restrict__ pairs, int L) {
+    const PairDesc& p = pairs[blockIdx.y];
+    transpose_sums_body(p.n, L, p.Ms, p.bs, p.Mt, p.bt, blockIdx.x, gridDim.x);
 }
 
 // One item per (i, j, s) of the per-stamp index space, 32 items per
@@ -92,16 +111,15 @@ __global__ void k_transpose_sums(int n, int L, const double* __restrict__ Ms,
 constexpr int ASM_ITEMS = 32, ASM_CHUNKS = 8;
 
 template <int NS>
-__global__ __launch_bounds__(256) void k_assemble(int n, int nb, int N, const double* __restrict__ Mt,
-                                                  const double* __restrict__ bt,
-                                                  const double* __restrict__ GU,
-                                                  double* __restrict__ M, double* __restrict__ b,
-                                                  const SolveState* st) {
+__device__ void assemble_body(int n, int nb, int N, const double* __restrict__ Mt,
+                              const double* __restrict__ bt, const double* __restrict__ GU,
+                              double* __restrict__ M, double* __restrict__ b, const SolveState* st,
+                              const int bid) {
     if (st->done) return;
     __shared__ double red[ASM_ITEMS][ASM_CHUNKS][NS];
     const int L = nb + 1;
     const int chunk = threadIdx.x % ASM_CHUNKS, li = threadIdx.x / ASM_CHUNKS;
-    const int t = blockIdx.x * ASM_ITEMS + li;
+    const int t = bid * ASM_ITEMS + li;
     const int nm = L * L * NS;
     double acc[NS];
 #pragma unroll
@@ -161,15 +179,44 @@ __global__ __launch_bounds__(256) void k_assemble(int n, int nb, int N, const do
     }
 }
 
+template <int NS>
+__global__ __launch_bounds__(256) void k_assemble(int n, int nb, int N, const double* __restrict__ Mt,
+                                                  const double* __restrict__ bt,
+                                                  const double* __restrict__ GU,
+                                                  double* __restrict__ M, double* __restrict__ b,
+                                                  const SolveState* st) {
+    assemble_body<NS>(n, nb, N, Mt, bt, GU, M, b, st, blockIdx.x);
+}
+
+// Batched: only the pairs with NS spatial terms take part in this launch.
+template <int NS>
+__global__ __launch_bounds__(256) void k_assemble_b(const PairDesc* __restrict__ pairs, int nb) {
+    const PairDesc& p = pairs[blockIdx.y];
+    const int L = nb + 1;
+    if (p.ns != NS || (int)blockIdx.x * ASM_ITEMS >= L * L * NS + L * NS) return;
+    assemble_body<NS>(p.n, nb, p.N, p.Mt, p.bt, p.GU, p.A, p.b, p.st, blockIdx.x);
+}
+
 // Stamp weights for the assembly: GU[k] = (g_k[0..ns), used_k).
-__global__ void k_weights(int n, int ns, const double* __restrict__ G,
-                          const uint8_t* __restrict__ used, double* __restrict__ GU,
-                          const SolveState* st) {
+__device__ void weights_body(int n, int ns, const double* __restrict__ G,
+                             const uint8_t* __restrict__ used, double* __restrict__ GU,
+                             const SolveState* st, int bid) {
     if (st->done) return;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = bid * blockDim.x + threadIdx.x;
     if (t >= n) return;
     for (int q = 0; q < ns; q++) GU[(size_t)t * (ns + 1) + q] = G[(size_t)t * ns + q];
     GU[(size_t)t * (ns + 1) + ns] = used[t] ? 1.0 : 0.0;
+}
+
+__global__ void k_weights(int n, int ns, const double* __restrict__ G,
+                          const uint8_t* __restrict__ used, double* __restrict__ GU,
+                          const SolveState* st) {
+    weights_body(n, ns, G, used, GU, st, blockIdx.x);
+}
+
+__global__ void k_weights_b(const PairDesc* __restrict__ pairs) {
+    const PairDesc& p = pairs[blockIdx.y];
+    weights_body(p.n, p.ns, p.G, p.used, p.GU, p.st, blockIdx.x);
 }
 
 __device__ __forceinline__ double block_sum(double v, double* red) { return psfm_block_sum(v, red); }
@@ -202,10 +249,8 @@ __device__ __forceinline__ double rsqrt_nr(double d) {
 
 constexpr int IL_S = 17;   // LDS row stride of the 16 x 16 inverses
 
-__global__ __launch_bounds__(CH_THREADS) void k_cholesky(int N, double* __restrict__ A,
-                                                         const double* __restrict__ b,
-                                                         double* __restrict__ x,
-                                                         double* __restrict__ ILg, SolveState* st) {
+__device__ void cholesky_body(int N, double* __restrict__ A, const double* __restrict__ b,
+                              double* __restrict__ x, double* __restrict__ ILg, SolveState* st) {
     if (st->done) return;
     extern __shared__ double P[];        // panel [N + 16][CH_PS]
     __shared__ double Dq[CH_NMAX];
@@ -500,18 +545,28 @@ __global__ __launch_bounds__(CH_THREADS) void k_cholesky(int N, double* __restri
     for (int i = tid; i < N; i += CH_THREADS) x[i] = Dq[i] * zb[i];
 }
 
+__global__ __launch_bounds__(CH_THREADS) void k_cholesky(int N, double* __restrict__ A,
+                                                         const double* __restrict__ b,
+                                                         double* __restrict__ x,
+                                                         double* __restrict__ ILg, SolveState* st) {
+    cholesky_body(N, A, b, x, ILg, st);
+}
+
+// Batched: one workgroup per pair, all solved concurrently.
+__global__ __launch_bounds__(CH_THREADS) void k_cholesky_b(const PairDesc* __restrict__ pairs) {
+    const PairDesc& p = pairs[blockIdx.x];
+    cholesky_body(p.N, p.A, p.b, p.coeffs, p.ILg, p.st);
+}
+
 // chi2_s = e_s - 2 alpha^T b_s + alpha^T M_s alpha for every fitted stamp
 // (one wave per stamp; alpha = local coefficients at the stamp centre).
-__global__ __launch_bounds__(64) void k_chi2(int n, int nb, int ns, int N,
-                                             const double* __restrict__ Ms,
-                                             const double* __restrict__ bs,
-                                             const double* __restrict__ es,
-                                             const double* __restrict__ G,
-                                             const double* __restrict__ a,
-                                             const uint8_t* __restrict__ fitted,
-                                             double* __restrict__ chi2, const SolveState* st) {
+__device__ void chi2_body(int nb, int ns, int N, const double* __restrict__ Ms,
+                          const double* __restrict__ bs, const double* __restrict__ es,
+                          const double* __restrict__ G, const double* __restrict__ a,
+                          const uint8_t* __restrict__ fitted, double* __restrict__ chi2,
+                          const SolveState* st, const int s) {
     if (st->done) return;
-    const int s = blockIdx.x, lane = threadIdx.x;
+    const int lane = threadIdx.x;
     if (!fitted[s]) return;
     __shared__ double alpha[64];
     const int L = nb + 1;
@@ -545,13 +600,29 @@ __global__ __launch_bounds__(64) void k_chi2(int n, int nb, int ns, int N,
     if (lane == 0) chi2[s] = es[s] + part;
 }
 
+__global__ __launch_bounds__(64) void k_chi2(int nb, int ns, int N, const double* __restrict__ Ms,
+                                             const double* __restrict__ bs,
+                                             const double* __restrict__ es,
+                                             const double* __restrict__ G,
+                                             const double* __restrict__ a,
+                                             const uint8_t* __restrict__ fitted,
+                                             double* __restrict__ chi2, const SolveState* st) {
+    chi2_body(nb, ns, N, Ms, bs, es, G, a, fitted, chi2, st, blockIdx.x);
+}
+
+// Batched: one wave per stamp of every pair (stamp_pair maps the flat index).
+__global__ __launch_bounds__(64) void k_chi2_b(const PairDesc* __restrict__ pairs,
+                                               const int* __restrict__ stamp_pair, int nb) {
+    const PairDesc& p = pairs[stamp_pair[blockIdx.x]];
+    chi2_body(nb, p.ns, p.N, p.Ms, p.bs, p.es, p.G, p.coeffs, p.fitted, p.chi2, p.st,
+              blockIdx.x - p.stamp_off);
+}
+
 // Sigma-clip over the used stamps after a solution (one workgroup).
-__global__ __launch_bounds__(1024) void k_clip(int n, int max_iter, int min_stamps,
-                                               double clip_sigma,
-                                               const int32_t* __restrict__ npix,
-                                               uint8_t* __restrict__ used,
-                                               int32_t* __restrict__ flags,
-                                               const double* __restrict__ chi2, SolveState* st) {
+__device__ void clip_body(int n, int max_iter, int min_stamps, double clip_sigma,
+                          const int32_t* __restrict__ npix, uint8_t* __restrict__ used,
+                          int32_t* __restrict__ flags, const double* __restrict__ chi2,
+                          SolveState* st) {
     if (st->done) return;
     __shared__ double red[16];
     __shared__ double s_thr;
@@ -602,10 +673,26 @@ __global__ __launch_bounds__(1024) void k_clip(int n, int max_iter, int min_stam
     }
 }
 
-__global__ void k_solve_finish(int n, int nb, int ns, int N, int S, int W, int H,
-                               const int32_t* __restrict__ npix, const uint8_t* __restrict__ used,
-                               const double* __restrict__ chi2, double* __restrict__ coeffs,
-                               const SolveState* st, psfm_fit_stats* stats) {
+__global__ __launch_bounds__(1024) void k_clip(int n, int max_iter, int min_stamps,
+                                               double clip_sigma,
+                                               const int32_t* __restrict__ npix,
+                                               uint8_t* __restrict__ used,
+                                               int32_t* __restrict__ flags,
+                                               const double* __restrict__ chi2, SolveState* st) {
+    clip_body(n, max_iter, min_stamps, clip_sigma, npix, used, flags, chi2, st);
+}
+
+__global__ __launch_bounds__(1024) void k_clip_b(const PairDesc* __restrict__ pairs, int max_iter,
+                                                 int min_stamps, double clip_sigma) {
+    const PairDesc& p = pairs[blockIdx.x];
+    clip_body(p.n, max_iter, min_stamps, clip_sigma, p.npix, p.used, p.flags, p.chi2, p.st);
+}
+
+__device__ void solve_finish_body(int n, int ns, int N, int S, int W, int H,
+                                  const int32_t* __restrict__ npix,
+                                  const uint8_t* __restrict__ used,
+                                  const double* __restrict__ chi2, double* __restrict__ coeffs,
+                                  const SolveState* st, psfm_fit_stats* stats) {
     __shared__ double red[16];
     const int tid = threadIdx.x;
     double c2 = 0.0, np = 0.0, nu = 0.0;
@@ -646,6 +733,19 @@ __global__ void k_solve_finish(int n, int nb, int ns, int N, int S, int W, int H
     }
 }
 
+__global__ void k_solve_finish(int n, int ns, int N, int S, int W, int H,
+                               const int32_t* __restrict__ npix, const uint8_t* __restrict__ used,
+                               const double* __restrict__ chi2, double* __restrict__ coeffs,
+                               const SolveState* st, psfm_fit_stats* stats) {
+    solve_finish_body(n, ns, N, S, W, H, npix, used, chi2, coeffs, st, stats);
+}
+
+__global__ void k_solve_finish_b(const PairDesc* __restrict__ pairs) {
+    const PairDesc& p = pairs[blockIdx.x];
+    solve_finish_body(p.n, p.ns, p.N, p.S, p.W, p.H, p.npix, p.used, p.chi2, p.coeffs, p.st,
+                      p.stats);
+}
+
 }  // namespace
 
 namespace psfm {
@@ -663,6 +763,61 @@ size_t solve_workspace(const psfm_context* ctx, int n) {
     c.take<double>((size_t)n * ctx->L * ctx->L + 1);
     c.take<double>((size_t)n * ctx->L + 1);
     return c.off;
+}
+
+int solve_lds_grant(size_t lds) {
+    static size_t granted = 0;      // dynamic LDS granted so far (both forms)
+    if (lds > granted) {
+        PSFM_HIP_CHECK(hipFuncSetAttribute((const void*)k_cholesky,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        PSFM_HIP_CHECK(hipFuncSetAttribute((const void*)k_cholesky_b,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        granted = lds;
+    }
+    return PSFM_OK;
+}
+
+size_t solve_lds_bytes(int N) { return (size_t)(N + 16) * CH_PS * sizeof(double); }
+int solve_max_unknowns() { return CH_NMAX; }
+size_t solve_il_doubles(int N) { return (size_t)512 * ((N + CH_NB - 1) / CH_NB); }
+
+// The whole solve loop for every pair of a batch: each launch covers all
+// pairs (blockIdx.y or one workgroup per pair); pairs that converged or
+// failed idle through the remaining rounds.
+int batch_solve(const psfm_context* ctx, const PairDesc* pairs, const int* stamp_pair, int n_pairs,
+                int n_stamps_total, int max_n, int max_N, unsigned ns_mask, hipStream_t st) {
+    if (n_pairs == 0) return PSFM_OK;
+    const psfm_config& cf = ctx->cfg;
+    const int nb = ctx->nb, L = ctx->L;
+    const size_t lds = solve_lds_bytes(max_N);
+    int rc = solve_lds_grant(lds);
+    if (rc) return rc;
+    const int nt = std::max(std::max(max_n, max_N), 1);
+    hipLaunchKernelGGL(k_solve_init_b, dim3((nt + 255) / 256, n_pairs), dim3(256), 0, st, pairs,
+                       cf.min_stamps);
+    hipLaunchKernelGGL(k_transpose_sums_b, dim3(64, n_pairs), dim3(256), 0, st, pairs, L);
+    PSFM_HIP_CHECK(hipGetLastError());
+    for (int it = 0; it < cf.max_iter; it++) {
+        hipLaunchKernelGGL(k_weights_b, dim3((max_n + 255) / 256 + 1, n_pairs), dim3(256), 0, st, pairs);
+#define PSFM_ASM_B(NSV)                                                                          \
+        if (ns_mask & (1u << NSV)) {                                                             \
+            const int items = L * L * NSV + L * NSV;                                             \
+            hipLaunchKernelGGL(k_assemble_b<NSV>, dim3((items + ASM_ITEMS - 1) / ASM_ITEMS, n_pairs), \
+                               dim3(256), 0, st, pairs, nb);                                      \
+        }
+        PSFM_ASM_B(1) PSFM_ASM_B(3) PSFM_ASM_B(6) PSFM_ASM_B(10) PSFM_ASM_B(15) PSFM_ASM_B(21)
+        PSFM_ASM_B(28)
+#undef PSFM_ASM_B
+        hipLaunchKernelGGL(k_cholesky_b, dim3(n_pairs), dim3(CH_THREADS), lds, st, pairs);
+        if (n_stamps_total > 0)
+            hipLaunchKernelGGL(k_chi2_b, dim3(n_stamps_total), dim3(64), 0, st, pairs, stamp_pair, nb);
+        hipLaunchKernelGGL(k_clip_b, dim3(n_pairs), dim3(1024), 0, st, pairs, cf.max_iter,
+                           cf.min_stamps, cf.clip_sigma);
+        PSFM_HIP_CHECK(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_solve_finish_b, dim3(n_pairs), dim3(1024), 0, st, pairs);
+    PSFM_HIP_CHECK(hipGetLastError());
+    return PSFM_OK;
 }
 
 }  // namespace psfm
@@ -696,12 +851,8 @@ extern "C" int psfm_solve(const psfm_context* ctx, int W, int H, const int32_t* 
     double* bt = c.take<double>((size_t)n_stamps * ctx->L + 1);
     const int nb = ctx->nb, ns = ctx->ns, N = ctx->N, L = ctx->L;
     const psfm_config& cf = ctx->cfg;
-    static size_t attr_set = 0;      // dynamic LDS granted so far
-    if (lds > attr_set) {
-        PSFM_HIP_CHECK(hipFuncSetAttribute((const void*)k_cholesky,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        attr_set = lds;
-    }
+    int rc = psfm::solve_lds_grant(lds);
+    if (rc) return rc;
     const int nt = std::max(n_stamps, N);
     hipLaunchKernelGGL(k_solve_init, dim3((nt + 255) / 256), dim3(256), 0, st, n_stamps, N, ns,
                        cf.spatial_order, W, H, cf.min_stamps, stamp_xy, stamp_flags, used, fitted,
@@ -723,12 +874,13 @@ extern "C" int psfm_solve(const psfm_context* ctx, int W, int H, const int32_t* 
             default: return PSFM_ERR_UNSUPPORTED;
         }
         hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(CH_THREADS), lds, st, N, M, b, coeffs, ILg, state);
-        hipLaunchKernelGGL(k_chi2, dim3(std::max(n_stamps, 1)), dim3(64), 0, st, n_stamps, nb, ns, N,
-                           stamp_M, stamp_b, stamp_e, G, coeffs, fitted, stamp_chi2, state);
+        if (n_stamps > 0)
+            hipLaunchKernelGGL(k_chi2, dim3(n_stamps), dim3(64), 0, st, nb, ns, N, stamp_M, stamp_b,
+                               stamp_e, G, coeffs, fitted, stamp_chi2, state);
         hipLaunchKernelGGL(k_clip, dim3(1), dim3(1024), 0, st, n_stamps, cf.max_iter, cf.min_stamps,
                            cf.clip_sigma, stamp_npix, used, stamp_flags, stamp_chi2, state);
     }
-    hipLaunchKernelGGL(k_solve_finish, dim3(1), dim3(1024), 0, st, n_stamps, nb, ns, N,
+    hipLaunchKernelGGL(k_solve_finish, dim3(1), dim3(1024), 0, st, n_stamps, ns, N,
                        cf.spatial_order, W, H, stamp_npix, used, stamp_chi2, coeffs, state, stats);
     PSFM_HIP_CHECK(hipGetLastError());
     return PSFM_OK;

@@ -65,6 +65,28 @@ class CStats(C.Structure):
 
 STATS_BYTES = C.sizeof(CStats)
 
+
+class CPair(C.Structure):
+    _fields_ = [
+        ("I1", C.c_void_p), ("V1", C.c_void_p), ("M1", C.c_void_p),
+        ("I2", C.c_void_p), ("V2", C.c_void_p), ("M2", C.c_void_p),
+        ("width", C.c_int), ("height", C.c_int), ("pitch", C.c_int64),
+        ("stamp_xy", C.c_void_p), ("n_stamps", C.c_int), ("spatial_order", C.c_int),
+        ("cov1", C.c_void_p), ("cov1_half", C.c_int),
+        ("cov2", C.c_void_p), ("cov2_half", C.c_int),
+        ("coeffs", C.c_void_p), ("stats", C.c_void_p),
+        ("diff", C.c_void_p), ("diff_var", C.c_void_p), ("diff_mask", C.c_void_p),
+        ("cov_conv", C.c_void_p), ("cov_conv_half", C.c_int),
+        ("cov_diff", C.c_void_p), ("cov_diff_half", C.c_int),
+        ("conv", C.c_void_p), ("conv_var", C.c_void_p), ("conv_mask", C.c_void_p),
+        ("stamp_flags", C.c_void_p), ("stamp_chi2", C.c_void_p),
+    ]
+
+
+class CTuning(C.Structure):
+    _fields_ = [("apply_grid", C.c_int), ("order", C.c_int)]
+
+
 _lib = None
 
 
@@ -93,6 +115,16 @@ def lib():
             "psfm_subtract": (i, [P, P, P, P, P, P, P, P, i, i, i64, P, i, P, i, P, P, P, P, i, P,
                                   sz, P]),
             "psfm_status_string": (C.c_char_p, [i]),
+            "psfm_batch_workspace_bytes": (sz, [P, C.POINTER(CPair), i]),
+            "psfm_batch_plan": (i, [P, C.POINTER(CPair), i, C.POINTER(CTuning), P, sz, P, P,
+                                    C.POINTER(P)]),
+            "psfm_batch_run": (i, [P, P]),
+            "psfm_batch_run_stage": (i, [P, i, P]),
+            "psfm_batch_set_tuning": (i, [P, C.POINTER(CTuning)]),
+            "psfm_batch_graph_capture": (i, [P, P]),
+            "psfm_batch_graph_launch": (i, [P, P]),
+            "psfm_batch_destroy": (i, [P]),
+            "psfm_wall_clock_hz": (C.c_double, []),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -309,6 +341,120 @@ class Context:
         )
 
 
+class Batch:
+    """A planned batch of independent pairs (``psfm_batch_*``).
+
+    ``pairs`` is a sequence of dicts with device tensors I1, V1, M1, I2, V2,
+    M2, stamps and an int ``S`` (spatial order), optionally ``cov1`` /
+    ``cov2``.  Outputs are allocated here, once; :meth:`run` launches the
+    whole batch, :meth:`capture` / :meth:`launch` go through one HIP graph.
+    ``keep_conv`` also writes I', V' and their mask per pair.
+    """
+
+    def __init__(self, ctx: Context, pairs, c_out: int = 10, keep_conv: bool = False,
+                 apply_grid: int = 0, order: int = 0, stream: Optional[torch.cuda.Stream] = None):
+        self.ctx = ctx
+        dev = ctx.device
+        self.stream = torch.cuda.Stream(device=dev) if stream is None else stream
+        self.n = len(pairs)
+        self.inputs = list(pairs)
+        self.out = []
+        cp = (CPair * self.n)()
+        f32 = dict(dtype=torch.float32, device=dev)
+        for k, q in enumerate(pairs):
+            H, W = q["I1"].shape
+            S = int(q["S"])
+            ns = (S + 1) * (S + 2) // 2
+            N = ctx.nb * ns + 1
+            n = q["stamps"].shape[0]
+            cov1, cov2 = q.get("cov1"), q.get("cov2")
+            c2 = 0 if cov2 is None else (cov2.shape[0] - 1) // 2
+            cd = max(c_out, c2)
+            o = dict(coeffs=torch.zeros(N, dtype=torch.float64, device=dev),
+                     stats=torch.zeros(STATS_BYTES, dtype=torch.uint8, device=dev),
+                     diff=torch.empty((H, W), **f32), diff_var=torch.empty((H, W), **f32),
+                     diff_mask=torch.empty((H, W), dtype=torch.uint8, device=dev),
+                     cov=torch.empty((2 * c_out + 1,) * 2, dtype=torch.float64, device=dev),
+                     cov_diff=torch.empty((2 * cd + 1,) * 2, dtype=torch.float64, device=dev),
+                     flags=torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+                     chi2=torch.empty(max(n, 1), dtype=torch.float64, device=dev))
+            if keep_conv:
+                o.update(conv=torch.empty((H, W), **f32), var=torch.empty((H, W), **f32),
+                         conv_mask=torch.empty((H, W), dtype=torch.uint8, device=dev))
+            self.out.append(o)
+            c = cp[k]
+            c.I1, c.V1, c.M1 = _ptr(q["I1"]), _ptr(q["V1"]), _ptr(q["M1"])
+            c.I2, c.V2, c.M2 = _ptr(q["I2"]), _ptr(q["V2"]), _ptr(q["M2"])
+            c.width, c.height, c.pitch = W, H, W
+            c.stamp_xy, c.n_stamps, c.spatial_order = _ptr(q["stamps"]), n, S
+            c.cov1, c.cov1_half = _ptr(cov1), 0 if cov1 is None else (cov1.shape[0] - 1) // 2
+            c.cov2, c.cov2_half = _ptr(cov2), c2
+            c.coeffs, c.stats = _ptr(o["coeffs"]), _ptr(o["stats"])
+            c.diff, c.diff_var, c.diff_mask = _ptr(o["diff"]), _ptr(o["diff_var"]), _ptr(o["diff_mask"])
+            c.cov_conv, c.cov_conv_half = _ptr(o["cov"]), c_out
+            c.cov_diff, c.cov_diff_half = _ptr(o["cov_diff"]), cd
+            if keep_conv:
+                c.conv, c.conv_var, c.conv_mask = _ptr(o["conv"]), _ptr(o["var"]), _ptr(o["conv_mask"])
+            c.stamp_flags, c.stamp_chi2 = _ptr(o["flags"]), _ptr(o["chi2"])
+        self._cpairs = cp
+        need = lib().psfm_batch_workspace_bytes(ctx.handle, cp, self.n)
+        if need == 0:
+            raise PsfmError("invalid batch")
+        self.ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        self.times = torch.zeros(self.n + 1, dtype=torch.int64, device=dev)
+        self._h = C.c_void_p()
+        tu = CTuning(apply_grid, order)
+        with torch.cuda.stream(self.stream):
+            _check(lib().psfm_batch_plan(ctx.handle, cp, self.n, C.byref(tu), _ptr(self.ws),
+                                         self.ws.numel(), _ptr(self.times), _stream(),
+                                         C.byref(self._h)), "psfm_batch_plan")
+        self.tick_hz = lib().psfm_wall_clock_hz()
+
+    def close(self):
+        if self._h:
+            lib().psfm_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_apply_grid(self, grid: int):
+        _check(lib().psfm_batch_set_tuning(self._h, C.byref(CTuning(grid, 0))), "psfm_batch_set_tuning")
+
+    def run(self):
+        """Launch the batch on the batch stream (ordered after the current stream)."""
+        self.stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(self.stream):
+            _check(lib().psfm_batch_run(self._h, _stream()), "psfm_batch_run")
+        torch.cuda.current_stream().wait_stream(self.stream)
+
+    def run_stage(self, stage: int):
+        """One stage (0 fit, 1 solve, 2 apply) on the current stream."""
+        _check(lib().psfm_batch_run_stage(self._h, stage, _stream()), "psfm_batch_run_stage")
+
+    def capture(self):
+        torch.cuda.synchronize()
+        with torch.cuda.stream(self.stream):
+            _check(lib().psfm_batch_graph_capture(self._h, _stream()), "psfm_batch_graph_capture")
+
+    def launch(self):
+        self.stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(self.stream):
+            _check(lib().psfm_batch_graph_launch(self._h, _stream()), "psfm_batch_graph_launch")
+        torch.cuda.current_stream().wait_stream(self.stream)
+
+    def latencies_s(self) -> np.ndarray:
+        """Completion time of each pair after the start of the last run (s)."""
+        t = self.times.cpu().numpy().astype(np.uint64)
+        return (t[1:] - t[0]).astype(np.float64) / self.tick_hz
+
+    def stats(self, k: int) -> dict:
+        return read_stats(self.out[k]["stats"])
+
+
 def read_stats(stats: torch.Tensor) -> dict:
     raw = bytes(stats.cpu().numpy().tobytes())
     return CStats.from_buffer_copy(raw[:STATS_BYTES]).as_dict()
@@ -325,4 +471,6 @@ def exported_symbols() -> Sequence[str]:
     return ["psfm_config_default", "psfm_create", "psfm_destroy", "psfm_n_basis", "psfm_n_spatial",
             "psfm_n_unknowns", "psfm_stamp_dim", "psfm_workspace_bytes", "psfm_fit_stamps",
             "psfm_solve", "psfm_convolve_image", "psfm_propagate_variance", "psfm_subtract",
-            "psfm_status_string"]
+            "psfm_status_string", "psfm_batch_workspace_bytes", "psfm_batch_plan",
+            "psfm_batch_run", "psfm_batch_run_stage", "psfm_batch_set_tuning", "psfm_batch_graph_capture",
+            "psfm_batch_graph_launch", "psfm_batch_destroy", "psfm_wall_clock_hz"]

@@ -183,13 +183,13 @@ class Pair:
         return self.workload.height
 
 
-def select_stamps(xs, ys, fluxes, M1, M2, n_stamps: int, r: int, h: int,
-                  grid: Optional[int] = None) -> np.ndarray:
-    """Pick stamp centres from the known catalogue: the brightest source in each
-    cell of a subregion grid whose footprint lies inside the image and away
-    from masked pixels; further passes take the next-brightest per cell until
-    ``n_stamps`` are found (or candidates run out)."""
-    H, W = M1.shape
+def _pick_stamps(xs, ys, fluxes, W: int, H: int, n_stamps: int, r: int, h: int,
+                 grid: Optional[int], footprint_bad) -> np.ndarray:
+    """Candidate walk shared by both stamp pickers: the brightest source in
+    each cell of a subregion grid whose footprint lies inside the image and
+    passes ``footprint_bad(x, y)`` (False = clean); further passes take the
+    next-brightest per cell until ``n_stamps`` are found (or candidates run
+    out)."""
     if grid is None:
         grid = max(1, int(math.ceil(math.sqrt(n_stamps))))
     cx = np.clip((xs * grid / W).astype(int), 0, grid - 1)
@@ -198,15 +198,6 @@ def select_stamps(xs, ys, fluxes, M1, M2, n_stamps: int, r: int, h: int,
     cells: Dict[Tuple[int, int], List[int]] = {}
     for k in order:
         cells.setdefault((int(cx[k]), int(cy[k])), []).append(int(k))
-    bad1 = M1 != 0
-    bad2 = M2 != 0
-    # summed-area tables make the footprint tests O(1)
-    sat1 = np.pad(bad1.astype(np.int64).cumsum(0).cumsum(1), ((1, 0), (1, 0)))
-    sat2 = np.pad(bad2.astype(np.int64).cumsum(0).cumsum(1), ((1, 0), (1, 0)))
-
-    def box_any(sat, x0, y0, x1, y1):
-        return (sat[y1 + 1, x1 + 1] - sat[y0, x1 + 1] - sat[y1 + 1, x0] + sat[y0, x0]) > 0
-
     chosen: List[Tuple[int, int]] = []
     taken = set()
     keys = sorted(cells.keys(), key=lambda t: (t[1], t[0]))
@@ -227,9 +218,7 @@ def select_stamps(xs, ys, fluxes, M1, M2, n_stamps: int, r: int, h: int,
                     continue
                 if (x, y) in taken:
                     continue
-                if box_any(sat1, x - R, y - R, x + R, y + R):
-                    continue
-                if box_any(sat2, x - r, y - r, x + r, y + r):
+                if footprint_bad(x, y):
                     continue
                 chosen.append((x, y))
                 taken.add((x, y))
@@ -238,6 +227,26 @@ def select_stamps(xs, ys, fluxes, M1, M2, n_stamps: int, r: int, h: int,
         if not progress:
             break
     return np.asarray(chosen, dtype=np.int32).reshape(-1, 2)
+
+
+def select_stamps(xs, ys, fluxes, M1, M2, n_stamps: int, r: int, h: int,
+                  grid: Optional[int] = None) -> np.ndarray:
+    """Pick stamp centres from the known catalogue (see :func:`_pick_stamps`):
+    the footprint [x-r-h, x+r+h]^2 must be clean in M1 and the stamp
+    [x-r, x+r]^2 clean in M2."""
+    H, W = M1.shape
+    # summed-area tables make the footprint tests O(1)
+    sat1 = np.pad((M1 != 0).astype(np.int64).cumsum(0).cumsum(1), ((1, 0), (1, 0)))
+    sat2 = np.pad((M2 != 0).astype(np.int64).cumsum(0).cumsum(1), ((1, 0), (1, 0)))
+
+    def box_any(sat, x0, y0, x1, y1):
+        return (sat[y1 + 1, x1 + 1] - sat[y0, x1 + 1] - sat[y1 + 1, x0] + sat[y0, x0]) > 0
+
+    def bad(x, y):
+        R = r + h
+        return box_any(sat1, x - R, y - R, x + R, y + R) or box_any(sat2, x - r, y - r, x + r, y + r)
+
+    return _pick_stamps(xs, ys, fluxes, W, H, n_stamps, r, h, grid, bad)
 
 
 def make_pair(wl: Workload, seed: int, theta: Optional[float] = None,
@@ -294,3 +303,180 @@ def scaled(wl: Workload, name: str, width: int, height: int, n_sources: Optional
 
 def gaussian_noise_image(rng: np.random.Generator, W: int, H: int, var: float) -> np.ndarray:
     return (rng.standard_normal((H, W)) * math.sqrt(var)).astype(np.float32)
+
+
+# --------------------------------------------------------------------------
+# Batches of independent pairs of uneven size, rendered on the GPU.
+
+@dataclasses.dataclass(frozen=True)
+class BatchSpec:
+    """Many independent pairs: per pair W, H ~ U{size_lo..size_hi}; PSF widths
+    of the two images ~ U[sigma_lo, sigma_hi] (the narrower image is the one
+    convolved), ellipticity up to U[0, e_max]; sources at ``density`` per
+    pixel; ``mask_frac`` masked; n_stamps ~ U{stamps_lo..stamps_hi}; spatial
+    order ~ U{0..S_max}; a ``variable_frac`` share of variable sources."""
+
+    n_pairs: int = 64
+    size_lo: int = 1024
+    size_hi: int = 6000
+    sigma_lo: float = 1.0
+    sigma_hi: float = 3.0
+    e_max: float = 0.3
+    density: float = 2000.0 / (2048 * 2048)
+    mask_frac: float = 0.10
+    kernel_half: int = 10
+    stamp_half: int = 20
+    stamps_lo: int = 50
+    stamps_hi: int = 400
+    S_max: int = 3
+    variable_frac: float = 0.05
+
+
+BATCHES: Dict[str, BatchSpec] = {"cfg3": BatchSpec()}
+
+
+def batch_pair_workload(spec: BatchSpec, k: int, cfg_index: int = 3) -> Workload:
+    """The workload of pair k of a batch, drawn from seed 19010999 + 1000 cfg + k."""
+    rng = np.random.default_rng(workload_seed(cfg_index, k))
+    W = int(rng.integers(spec.size_lo, spec.size_hi + 1))
+    H = int(rng.integers(spec.size_lo, spec.size_hi + 1))
+    s_a, s_b = rng.uniform(spec.sigma_lo, spec.sigma_hi, 2)
+    e_a, e_b = rng.uniform(0.0, spec.e_max, 2)
+    lo, hi = (s_a, s_b) if s_a <= s_b else (s_b, s_a)
+    n_st = int(rng.integers(spec.stamps_lo, spec.stamps_hi + 1))
+    S = int(rng.integers(0, spec.S_max + 1))
+    return Workload(f"pair{k}", W, H, max(1, int(round(spec.density * W * H))),
+                    PsfField(lo, lo, e_a), PsfField(hi, hi, e_b), spec.mask_frac,
+                    spec.kernel_half, ISIS_SIGMAS, ISIS_DEGREES, S, n_st, spec.stamp_half,
+                    variable_frac=spec.variable_frac)
+
+
+@dataclasses.dataclass
+class DevicePair:
+    """A pair whose planes live in device memory (torch tensors)."""
+    workload: Workload
+    I1: "object"
+    V1: "object"
+    M1: "object"
+    I2: "object"
+    V2: "object"
+    M2: "object"
+    stamps: np.ndarray
+    xs: np.ndarray
+    ys: np.ndarray
+    fluxes: np.ndarray
+    seed: int
+
+    def host(self) -> Pair:
+        t = lambda a: a.cpu().numpy()
+        return Pair(self.workload, t(self.I1), t(self.V1), t(self.M1), t(self.I2), t(self.V2),
+                    t(self.M2), self.stamps, self.xs, self.ys, self.fluxes, self.seed)
+
+
+def _render_torch(torch, W, H, xs, ys, fluxes, psf: PsfField, theta: float, device):
+    """Device version of :func:`_render` (float32): each source's elliptical
+    Gaussian on a fixed +-6 sigma_a box, scatter-added into the image."""
+    sa, sb = psf.params(xs, ys, W, H)
+    rad = int(math.ceil(6.0 * float(np.max(sa)))) + 1 if len(xs) else 1
+    img = torch.zeros(H * W, dtype=torch.float32, device=device)
+    off = torch.arange(-rad, rad + 1, device=device)
+    c, s = math.cos(theta), math.sin(theta)
+    chunk = max(1, (1 << 24) // (2 * rad + 1) ** 2)
+    for i0 in range(0, len(xs), chunk):
+        sl = slice(i0, i0 + chunk)
+        x0 = torch.as_tensor(xs[sl], dtype=torch.float64, device=device)
+        y0 = torch.as_tensor(ys[sl], dtype=torch.float64, device=device)
+        a = torch.as_tensor(sa[sl], dtype=torch.float64, device=device)
+        b = torch.as_tensor(sb[sl], dtype=torch.float64, device=device)
+        f = torch.as_tensor(fluxes[sl], dtype=torch.float64, device=device)
+        px = torch.floor(x0).long()[:, None, None] + off[None, None, :]
+        py = torch.floor(y0).long()[:, None, None] + off[None, :, None]
+        dx = px - x0[:, None, None]
+        dy = py - y0[:, None, None]
+        pa = c * dx + s * dy
+        pb = -s * dx + c * dy
+        q = (pa / a[:, None, None]) ** 2 + (pb / b[:, None, None]) ** 2
+        val = (f / (2.0 * math.pi * a * b))[:, None, None] * torch.exp(-0.5 * q)
+        ok = (px >= 0) & (px < W) & (py >= 0) & (py < H)
+        idx = (py * W + px)[ok]
+        img.index_add_(0, idx, val[ok].to(torch.float32))
+    return img.view(H, W)
+
+
+def _mask_torch(torch, rng, model, frac: float, saturation: float):
+    H, W = model.shape
+    mask = torch.zeros((H, W), dtype=torch.bool, device=model.device)
+    if frac <= 0:
+        return mask.to(torch.uint8)
+    sat = model > saturation
+    d = sat.clone()
+    d[1:, :] |= sat[:-1, :]
+    d[:-1, :] |= sat[1:, :]
+    d[:, 1:] |= sat[:, :-1]
+    d[:, :-1] |= sat[:, 1:]
+    mask |= d
+    colbad = mask.float().mean(0)                       # masked share of each column
+    cols = torch.zeros(W, dtype=torch.bool, device=model.device)
+    frac_now = float(mask.float().mean())
+    while frac_now < frac:
+        w = int(rng.integers(4, 65))
+        x0 = int(rng.integers(0, max(W - w, 1)))
+        cols[x0:x0 + w] = True
+        frac_now = float(torch.where(cols, torch.ones_like(colbad), colbad).mean())
+    mask[:, cols] = True
+    return mask.to(torch.uint8)
+
+
+def make_pair_device(wl: Workload, seed: int, device="cuda", n_stamps: Optional[int] = None) -> DevicePair:
+    """Render a pair on the GPU with torch (same recipe as :func:`make_pair`:
+    sources, variable share, masks, noise, NaN in masked pixels, stamps from
+    the catalogue; the random streams differ from the CPU generator's)."""
+    import torch
+
+    rng = np.random.default_rng(seed)
+    W, H = wl.width, wl.height
+    xs = rng.uniform(0, W, wl.n_sources)
+    ys = rng.uniform(0, H, wl.n_sources)
+    fluxes = np.exp(rng.uniform(math.log(wl.flux_lo), math.log(wl.flux_hi), wl.n_sources))
+    f2 = fluxes.copy()
+    if wl.variable_frac > 0:
+        var = rng.uniform(0, 1, wl.n_sources) < wl.variable_frac
+        f2[var] *= rng.uniform(0.5, 2.0, int(var.sum()))
+    th = float(rng.uniform(0, math.pi))
+    m1 = _render_torch(torch, W, H, xs, ys, fluxes, wl.ref_psf, 0.0, device)
+    m2 = _render_torch(torch, W, H, xs, ys, f2, wl.sci_psf, th, device)
+    M1 = _mask_torch(torch, rng, m1, wl.mask_frac, wl.saturation)
+    M2 = _mask_torch(torch, rng, m2, wl.mask_frac, wl.saturation)
+    g = torch.Generator(device=device)
+    g.manual_seed(seed + 1)
+    V1 = m1 + wl.sky
+    V2 = m2 + wl.sky
+    del m1, m2
+    I1 = V1 + torch.randn((H, W), generator=g, device=device) * torch.sqrt(V1)
+    I2 = V2 + torch.randn((H, W), generator=g, device=device) * torch.sqrt(V2)
+    nan = torch.tensor(float("nan"), device=device)
+    I1 = torch.where(M1 != 0, nan, I1)
+    V1 = torch.where(M1 != 0, nan, V1)
+    I2 = torch.where(M2 != 0, nan, I2)
+    V2 = torch.where(M2 != 0, nan, V2)
+    # footprint tests through summed-area tables on the device
+    r, h = wl.stamp_half, wl.kernel_half
+
+    def box_bad(M, R):
+        sat = torch.nn.functional.pad((M != 0).to(torch.int32).cumsum(0).cumsum(1), (1, 0, 1, 0))
+        Hh, Ww = M.shape
+        out = torch.ones((Hh, Ww), dtype=torch.bool, device=M.device)
+        if 2 * R + 1 <= min(Hh, Ww):
+            y0, x0 = R, R
+            box = (sat[2 * R + 1:, 2 * R + 1:] - sat[:-2 * R - 1, 2 * R + 1:]
+                   - sat[2 * R + 1:, :-2 * R - 1] + sat[:-2 * R - 1, :-2 * R - 1])
+            out[y0:Hh - R, x0:Ww - R] = box > 0
+        return out.cpu().numpy()
+
+    bad1 = box_bad(M1, r + h)
+    bad2 = box_bad(M2, r)
+    ns = wl.n_stamps if n_stamps is None else n_stamps
+    stamps = _pick_stamps(xs, ys, fluxes, W, H, ns, r, h, None,
+                          lambda x, y: bool(bad1[y, x]) or bool(bad2[y, x]))
+    return DevicePair(wl, I1.contiguous(), V1.contiguous(), M1, I2.contiguous(), V2.contiguous(),
+                      M2, stamps, xs, ys, fluxes, seed)

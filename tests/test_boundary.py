@@ -70,3 +70,15 @@ def test_host_argument_checks(lib):
     assert lib.psfm_convolve_image(None, None, None, None, 10, 10, 10, None, None, None, 0, None) == -1
     for code in range(-7, 1):
         assert lib.psfm_status_string(code).decode()
+
+
+def test_batch_host_argument_checks(lib):
+    h = C.c_void_p()
+    assert lib.psfm_batch_workspace_bytes(None, None, 1) == 0
+    assert lib.psfm_batch_plan(None, None, 1, None, None, 0, None, None, C.byref(h)) == -1
+    assert lib.psfm_batch_run(None, None) == -1
+    assert lib.psfm_batch_run_stage(None, 0, None) == -1
+    assert lib.psfm_batch_set_tuning(None, None) == -1
+    assert lib.psfm_batch_graph_capture(None, None) == -1
+    assert lib.psfm_batch_graph_launch(None, None) == -1
+    assert lib.psfm_batch_destroy(None) == -1

@@ -1,0 +1,135 @@
+"""Batched matching (psfm_batch_*) against the single-pair calls and the oracle.
+
+The batch runs the same device code per pair as the single-pair calls (fit,
+solve, patch kernels, convolution), so coefficients, statistics, stamp flags,
+convolved planes, masks, difference planes and the convolved pseudo-matrix
+are compared bit for bit; only C_D differs in the order of its FP64 variance
+sums (per tile instead of per row block), so it is held to 1e-12 relative.
+One pair of each batch is also checked against the FP64 oracle at the
+whole-path targets (kernel sum 1e-4, chi2/dof 1%).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1901_09999_amd import synth
+
+from gpu_common import hip
+
+pytestmark = pytest.mark.gpu
+
+# (width, height, S, n_stamps, n_sources): uneven sizes, spatial orders and
+# stamp counts, 10% variable sources (so that stamps are rejected), a pair
+# smaller than one tile, and two with too few stamps to solve.
+SPECS = [(300, 260, 0, 30, 200), (520, 384, 2, 40, 400), (330, 353, 1, 25, 300),
+         (640, 512, 3, 60, 600), (120, 90, 0, 2, 20), (60, 50, 0, 0, 5)]
+
+
+def _pairs(specs, seed0=4242):
+    out = []
+    for k, (W, H, S, n, nsrc) in enumerate(specs):
+        wl = synth.scaled(synth.WORKLOADS["cfg1"], f"batch{k}", W, H, n_stamps=max(n, 1),
+                          spatial_order=S, n_sources=nsrc, mask_frac=0.04, variable_frac=0.1)
+        p = synth.make_pair(wl, seed0 + k)
+        if n == 0:
+            p.stamps = p.stamps[:0]
+        out.append((wl, p))
+    return out
+
+
+def _single(psfm, torch, wl, pair, c_out):
+    ctx = psfm.Context(psfm.Config.from_workload(wl))
+    d = psfm.to_device(pair)
+    r = ctx.match_pair(d["I1"], d["V1"], d["M1"], d["I2"], d["V2"], d["M2"], d["stamps"],
+                       c_out=c_out)
+    torch.cuda.synchronize()
+    return r
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _batch(psfm, torch, pairs, c_out, **kw):
+    ctx = psfm.Context(psfm.Config.from_workload(pairs[0][0], S=0))
+    dev = [dict(psfm.to_device(p), S=wl.spatial_order) for wl, p in pairs]
+    b = psfm.Batch(ctx, dev, c_out=c_out, keep_conv=True, **kw)
+    return ctx, dev, b
+
+
+@pytest.mark.parametrize("order,grid", [(0, 0), (1, 64), (2, 1)])
+def test_batch_matches_single_pair_calls(order, grid):
+    torch, psfm = hip()
+    pairs = _pairs(SPECS)
+    c_out = 10
+    print(f"batch of {len(pairs)} pairs, order {order}, apply grid {grid}", flush=True)
+    ctx, dev, b = _batch(psfm, torch, pairs, c_out, order=order, apply_grid=grid)
+    b.run()
+    torch.cuda.synchronize()
+    for k, (wl, pair) in enumerate(pairs):
+        s = _single(psfm, torch, wl, pair, c_out)
+        o = b.out[k]
+        n = pair.stamps.shape[0]
+        st_b, st_s = b.stats(k), psfm.read_stats(s["sol"]["stats"])
+        for f in ("info", "n_used", "n_rejected", "n_iter"):
+            assert st_b[f] == st_s[f], (k, f, st_b, st_s)
+        for f in ("chi2_dof", "kernel_sum_centre", "cov_discarded_frac"):
+            assert st_b[f] == st_s[f], (k, f, st_b[f], st_s[f])
+        assert np.array_equal(_np(o["coeffs"]), _np(s["sol"]["coeffs"])), k
+        if n:
+            assert np.array_equal(_np(o["flags"])[:n], _np(s["sol"]["flags"])[:n]), k
+        assert np.array_equal(_np(o["conv"]), _np(s["conv"])), k
+        assert np.array_equal(_np(o["conv_mask"]), _np(s["conv_mask"])), k
+        assert np.array_equal(_np(o["var"]), _np(s["var"])), k
+        assert np.array_equal(_np(o["cov"]), _np(s["cov"])), k
+        assert np.array_equal(_np(o["diff"]), _np(s["diff"])), k
+        assert np.array_equal(_np(o["diff_var"]), _np(s["diff_var"])), k
+        assert np.array_equal(_np(o["diff_mask"]), _np(s["diff_mask"])), k
+        cd_b, cd_s = _np(o["cov_diff"]), _np(s["cov_diff"])
+        assert np.max(np.abs(cd_b - cd_s)) <= 1e-12 * np.max(np.abs(cd_s)), k
+    # the pairs with too few stamps fail alone; their neighbours are unaffected
+    assert b.stats(4)["info"] == -3 and b.stats(5)["info"] == -3
+    assert all(b.stats(k)["info"] == 0 for k in range(4)), [b.stats(k) for k in range(4)]
+    assert sum(b.stats(k)["n_rejected"] for k in range(4)) > 0
+
+
+def test_batch_against_oracle():
+    torch, psfm = hip()
+    pairs = _pairs(SPECS[:4], seed0=777)
+    ctx, dev, b = _batch(psfm, torch, pairs, 10)
+    b.run()
+    torch.cuda.synchronize()
+    for k in (1, 3):
+        wl, pair = pairs[k]
+        ref = O.match_pair(O.Config.from_workload(wl), pair, c_out=10)
+        st, rs = b.stats(k), ref["stats"]
+        ks = abs(st["kernel_sum_centre"] / rs["kernel_sum_centre"] - 1)
+        cd = abs(st["chi2_dof"] / rs["chi2_dof"] - 1)
+        print(f"pair {k} (S={wl.spatial_order}): kernel sum {ks:.2e}, chi2/dof {cd:.2e}")
+        assert st["info"] == 0 and ks < 1e-4 and cd < 1e-2
+        scale = np.sqrt(np.nanmax(pair.V2))
+        dd = _np(b.out[k]["diff"]) - ref["diff"]
+        ok = (ref["diff_mask"] == 0) & (_np(b.out[k]["diff_mask"]) == 0)
+        assert np.max(np.abs(dd[ok])) < 5e-2 * scale
+
+
+def test_batch_graph_replays_match_eager():
+    torch, psfm = hip()
+    pairs = _pairs(SPECS[:4], seed0=99)
+    ctx, dev, b = _batch(psfm, torch, pairs, 10, apply_grid=128)
+    b.run()
+    torch.cuda.synchronize()
+    ref = [{k: _np(v).copy() for k, v in o.items()} for o in b.out]
+    b.capture()
+    for rep in range(3):
+        for o in b.out:                       # eager work between replays
+            o["diff"].fill_(0.0)
+            o["coeffs"].fill_(0.0)
+        torch.cuda.synchronize()
+        b.launch()
+        torch.cuda.synchronize()
+        for k, o in enumerate(b.out):
+            for f in ("coeffs", "diff", "diff_var", "diff_mask", "conv", "cov_diff"):
+                assert np.array_equal(_np(o[f]), ref[k][f]), (rep, k, f)
+        lat = b.latencies_s()
+        assert np.all(lat > 0) and np.all(lat < 10.0), lat
