@@ -78,10 +78,16 @@ typedef enum {
 #define PSFM_MASK_CONV_BAD  2    /* masked input within the BAD radius of the kernel */
 #define PSFM_MASK_CONV_POOR 4    /* masked input within the kernel footprint only */
 
-/* Arithmetic of the stamp fit. */
-#define PSFM_PREC_FP32 0         /* FP32 basis convolution, FP32-MFMA Gram */
-#define PSFM_PREC_BF16 1         /* reserved: BF16 MFMA Gram */
-#define PSFM_PREC_FP16 2         /* reserved: FP16 MFMA Gram */
+/* Arithmetic of the stamp fit (the normal equations of Section 2, Eq. 6).
+   FP32: FP32 basis convolution, FP32-MFMA Gram, per-row FP64 sums.
+   BF16 / FP16: the same FP32 design rounded to 16 bits for a 16-bit MFMA
+   Gram (FP32 accumulation, per-row FP64 sums); psfm_solve then refines each
+   FP64 Cholesky solution `refine` times against residuals recomputed in
+   FP64 from the FP32 design (iterative refinement), and takes every chi2_s
+   from those pixel residuals. */
+#define PSFM_PREC_FP32 0
+#define PSFM_PREC_BF16 1
+#define PSFM_PREC_FP16 2
 
 /*
  * Method parameters.
@@ -119,7 +125,7 @@ typedef struct psfm_config {
     int min_stamps;        /* minimum usable stamps (default 3) */
     double bad_frac;       /* BAD/POOR fraction (default 0.2) */
     int precision;         /* PSFM_PREC_* */
-    int reserved;
+    int refine;            /* refinement steps of the 16-bit modes (0..4, default 1) */
 } psfm_config;
 
 /* Quality record of a fit (device memory, written by the library). */
@@ -139,7 +145,7 @@ typedef struct psfm_context psfm_context;
 
 /* Fills *cfg with the defaults: 3 Gaussians (0.7, 1.5, 3.0 px) x degrees
    (6, 4, 2) = 49 terms, h = 10, S = 0, r = 20, P = 64, clip 3, 3 solutions,
-   3 stamps, bad_frac 0.2, FP32. */
+   3 stamps, bad_frac 0.2, FP32, 1 refinement step (16-bit modes only). */
 void psfm_config_default(psfm_config* cfg);
 
 /* Validates cfg, builds the basis tables (FP64 on the host) and uploads them
@@ -157,6 +163,10 @@ int psfm_stamp_dim(const psfm_context* ctx);    /* L = nb + 1: per-stamp matrix 
    n_stamps stamps (the maximum over the calls); 0 on invalid arguments. */
 size_t psfm_workspace_bytes(const psfm_context* ctx, int W, int H, int n_stamps);
 
+/* Floats of the stamp design that psfm_fit_stamps writes and psfm_solve
+   reads in the 16-bit modes: n_stamps * (nb + 2) * (2r + 1)^2 (0 in FP32). */
+size_t psfm_stamp_design_floats(const psfm_context* ctx, int n_stamps);
+
 /*
  * Per-stamp normal equations (Section 2, Eqs. 3-6 with c = 0, p = 0).
  * For stamp s centred on (x, y) = stamp_xy[2s], stamp_xy[2s+1] and every
@@ -169,15 +179,18 @@ size_t psfm_workspace_bytes(const psfm_context* ctx, int W, int H, int n_stamps)
  * [x-r-h, x+r+h]^2 outside the image or masked in M1; stamp masked in M2;
  * non-finite or non-positive data), the flag bits and zero sums.
  * Arithmetic: FP32 separable basis convolution, FP32 MFMA Gram, per-band
- * partial sums added in FP64.  Inputs: I1, M1 (convolved image), I2, V2, M2
- * (target), all W x H with `pitch`.  Outputs are float64/int32 device arrays
- * of n_stamps entries (stamp_M n*L*L, stamp_b n*L).
+ * partial sums added in FP64 (16-bit Gram in the BF16 / FP16 modes, see
+ * PSFM_PREC_*).  Inputs: I1, M1 (convolved image), I2, V2, M2 (target), all
+ * W x H with `pitch`.  Outputs are float64/int32 device arrays of n_stamps
+ * entries (stamp_M n*L*L, stamp_b n*L).  stamp_design (16-bit modes only,
+ * else may be NULL; psfm_stamp_design_floats floats): per stamp the FP32
+ * weighted design, column-major [term 0..nb-1, sqrt(w), sqrt(w) I2][pixel].
  */
 int psfm_fit_stamps(const psfm_context* ctx, const float* I1, const uint8_t* M1, const float* I2,
                     const float* V2, const uint8_t* M2, int W, int H, int64_t pitch,
                     const int32_t* stamp_xy, int n_stamps, double* stamp_M, double* stamp_b,
-                    double* stamp_e, int32_t* stamp_npix, int32_t* stamp_flags, void* ws,
-                    size_t ws_bytes, void* stream);
+                    double* stamp_e, int32_t* stamp_npix, int32_t* stamp_flags,
+                    float* stamp_design, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Assembly, solution and rejection (Section 2; Sections 3.3, 3.5, 3.6).
@@ -189,13 +202,15 @@ int psfm_fit_stamps(const psfm_context* ctx, const float* I1, const uint8_t* M1,
  * Outputs: coeffs (N float64), stamp_chi2 (n float64, 0 for stamps flagged on
  * entry), stamp_flags gains PSFM_STAMP_REJECTED, *stats (device).  On a
  * device-detected failure stats->info is set (-3 or the failing pivot) and
- * coeffs hold zeros.
+ * coeffs hold zeros.  In the 16-bit modes stamp_design (from
+ * psfm_fit_stamps) is required: each solution is refined against residuals
+ * from it and chi2_s is taken from those residuals.
  */
 int psfm_solve(const psfm_context* ctx, int W, int H, const int32_t* stamp_xy, int n_stamps,
                const double* stamp_M, const double* stamp_b, const double* stamp_e,
-               const int32_t* stamp_npix, int32_t* stamp_flags, double* coeffs,
-               double* stamp_chi2, psfm_fit_stats* stats, void* ws, size_t ws_bytes,
-               void* stream);
+               const int32_t* stamp_npix, int32_t* stamp_flags, const float* stamp_design,
+               double* coeffs, double* stamp_chi2, psfm_fit_stats* stats, void* ws,
+               size_t ws_bytes, void* stream);
 
 /*
  * Image convolution with the spatially varying kernel (Section 4.2, Eq. 12;

@@ -54,6 +54,7 @@ void psfm_config_default(psfm_config* cfg) {
     cfg->min_stamps = 3;
     cfg->bad_frac = 0.2;
     cfg->precision = PSFM_PREC_FP32;
+    cfg->refine = 1;
 }
 
 static double ipow(double x, int n) {
@@ -78,7 +79,8 @@ int psfm_create(const psfm_config* cfg, psfm_context** out) {
         !(c.bad_frac <= 1.0))
         return PSFM_ERR_INVALID_ARG;
     if (c.half_width > PSFM_HMAX || c.stamp_half > PSFM_RMAX || c.spatial_order > 6 ||
-        nb + 2 > PSFM_GRAM_COLS || nf > 32 || c.precision != PSFM_PREC_FP32)
+        nb + 2 > PSFM_GRAM_COLS || nf > 32 || c.precision < PSFM_PREC_FP32 ||
+        c.precision > PSFM_PREC_FP16 || c.refine < 0 || c.refine > 4)
         return PSFM_ERR_UNSUPPORTED;
 
     psfm_context* ctx = new psfm_context();
@@ -218,6 +220,12 @@ size_t psfm_workspace_bytes(const psfm_context* ctx, int W, int H, int n_stamps)
     if (c > m) m = c;
     if (d > m) m = d;
     return psfm::align_up(m, 256) + 256;
+}
+
+size_t psfm_stamp_design_floats(const psfm_context* ctx, int n_stamps) {
+    if (!ctx || n_stamps < 0 || ctx->cfg.precision == PSFM_PREC_FP32) return 0;
+    const size_t npx = (size_t)(2 * ctx->r + 1) * (2 * ctx->r + 1);
+    return (size_t)n_stamps * (ctx->nb + 2) * npx;
 }
 
 const char* psfm_status_string(int status) {

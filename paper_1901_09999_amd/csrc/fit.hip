@@ -17,16 +17,41 @@
 //      every stamp row, so FP32 sums never span more than 2r+1 pixels;
 //   4. the band's partial Gram is written in FP64; a second kernel adds the
 //      bands of each stamp and scatters M_s, b_s, e_s.
+// 16-bit modes (PSFM_PREC_FP16 / _BF16): the weighted row block is rounded to
+// 16 bits, stored column-major, and folded in with v_mfma_f32_16x16x32_{f16,
+// bf16} (FP32 accumulation, FP64 per row as above); the FP32 block itself
+// (terms, sqrt(w), d~) is written to the stamp design for the refinement of
+// the solution, which recomputes residuals from it.
 #include "internal.h"
 
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+template <int PREC>
+__device__ __forceinline__ unsigned short to16(float v) {
+    if constexpr (PREC == PSFM_PREC_FP16) return __builtin_bit_cast(unsigned short, (_Float16)v);
+    else return __builtin_bit_cast(unsigned short, (__bf16)v);
+}
+
+template <int PREC>
+__device__ __forceinline__ floatx4 mfma16(u16x8 a, u16x8 b, floatx4 c) {
+    if constexpr (PREC == PSFM_PREC_FP16)
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(half8, a),
+                                                      __builtin_bit_cast(half8, b), c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                       __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
 
 constexpr int BR = PSFM_FIT_BR;
 constexpr int SEG = 12;          // stamp pixels per row-pass item
 constexpr int AT_STRIDE = 80;    // LDS row stride of the weighted block (bank spread)
 constexpr int GC = PSFM_GRAM_COLS;
+constexpr int A16S = 104;        // LDS column stride (halves) of the 16-bit block: up to 96 pixels
 
 struct FitLds {
     int win, col, R, At, sw, dt, psi, z, total;  // float offsets
@@ -37,10 +62,11 @@ __host__ __device__ inline FitLds fit_lds_layout(int h, int r, int nb, int nf) {
     const int npad = (2 * r + 1 + 3) / 4 * 4;
     FitLds L;
     int o = 0;
-    L.win = o;  o += (BR + 2 * h) * WC;
-    L.col = o;  o += nf * BR * WC + SEG + 2 * h + 4;   // slack for the last row-pass loads
-    L.R = o;    o += npad * nb;
-    L.At = o;   o += npad * AT_STRIDE;
+    auto a4 = [](int x) { return (x + 3) / 4 * 4; };   // 16-byte aligned regions
+    L.win = o;  o += a4((BR + 2 * h) * WC);
+    L.col = o;  o += a4(nf * BR * WC + SEG + 2 * h + 4);   // slack for the last row-pass loads
+    L.R = o;    o += a4(npad * nb);
+    L.At = o;   o += a4(npad * AT_STRIDE > GC * A16S / 2 ? npad * AT_STRIDE : GC * A16S / 2);
     L.sw = o;   o += BR * (2 * r + 1);
     L.dt = o;   o += BR * (2 * r + 1);
     L.psi = o;  o += 64;
@@ -68,10 +94,11 @@ struct FitArgs {
     int nb, nf;
     double* part;
     int* band_flags;
+    float* design;     // 16-bit modes: [stamp][nb + 2][(2r+1)^2] FP32 block, column-major
 };
 
 // One band of one stamp (item = stamp * nbands + band).
-template <int H_>
+template <int H_, int PREC>
 __device__ void fit_band_body(const FitArgs& a, const int item, float* __restrict__ lds) {
     const float* __restrict__ I1 = a.I1;
     const uint8_t* __restrict__ M1 = a.M1;
@@ -232,6 +259,7 @@ __device__ void fit_band_body(const FitArgs& a, const int item, float* __restric
                 if (x0 + k < NPX) Rb[(x0 + k) * nb + i] = a[k];
         }
         __syncthreads();
+        if constexpr (PREC == PSFM_PREC_FP32) {
         // 3b. zero-sum fix-up, weights, extra columns
         for (int e = tid; e < npad * GC; e += 256) {
             const int x = e / GC, c = e - x * GC;
@@ -270,6 +298,51 @@ __device__ void fit_band_body(const FitArgs& a, const int item, float* __restric
                 acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a3, a3, acc[1], 0, 0, 0);
             }
         }
+        } else {
+        // 3b'. the same block, rounded to 16 bits, column-major A16[c][x]
+        //      (pixels padded to a multiple of 32); FP32 values to the design
+        unsigned short* A16 = reinterpret_cast<unsigned short*>(At);
+        const int kp = (NPX + 31) / 32 * 32;
+        float* dsg = a.design + (size_t)s * (nb + 2) * (NPX * NPX) + (size_t)(y_l0 + br) * NPX;
+        for (int e = tid; e < GC * kp; e += 256) {
+            const int c = e / kp, x = e - c * kp;
+            float v = 0.0f;
+            if (x < NPX) {
+                const float sw = swb[br * NPX + x];
+                if (c < nb) v = sw * (psib[c] * Rb[x * nb + c] - zb[c] * (psib[0] * Rb[x * nb]) +
+                                      (c == 0 ? cshift : 0.0f));
+                else if (c == nb) v = sw;
+                else if (c == nb + 1) v = dtb[br * NPX + x];
+                if (c < nb + 2) dsg[(size_t)c * (NPX * NPX) + x] = v;
+            }
+            A16[c * A16S + x] = to16<PREC>(v);
+        }
+        __syncthreads();
+        // 3c'. Gram blocks, K = 32 pixels per instruction (same wave blocks)
+        for (int ks = 0; ks < kp / 32; ks++) {
+            const unsigned short* colp = A16 + (lane & 15) * A16S + 32 * ks + 8 * (lane >> 4);
+            auto ld = [&](int b) { return *reinterpret_cast<const u16x8*>(colp + 16 * b * A16S); };
+            if (wave == 0) {
+                const u16x8 a0 = ld(0), a1 = ld(1);
+                acc[0] = mfma16<PREC>(a0, a0, acc[0]);
+                acc[1] = mfma16<PREC>(a1, a0, acc[1]);
+                acc[2] = mfma16<PREC>(a1, a1, acc[2]);
+            } else if (wave == 1) {
+                const u16x8 a0 = ld(0), a1 = ld(1), a2 = ld(2);
+                acc[0] = mfma16<PREC>(a2, a0, acc[0]);
+                acc[1] = mfma16<PREC>(a2, a1, acc[1]);
+                acc[2] = mfma16<PREC>(a2, a2, acc[2]);
+            } else if (wave == 2) {
+                const u16x8 a0 = ld(0), a1 = ld(1), a3 = ld(3);
+                acc[0] = mfma16<PREC>(a3, a0, acc[0]);
+                acc[1] = mfma16<PREC>(a3, a1, acc[1]);
+            } else {
+                const u16x8 a2 = ld(2), a3 = ld(3);
+                acc[0] = mfma16<PREC>(a3, a2, acc[0]);
+                acc[1] = mfma16<PREC>(a3, a3, acc[1]);
+            }
+        }
+        }
         // FP32 MFMA sums cover one stamp row; rows are added in FP64.
 #pragma unroll
         for (int q = 0; q < 3; q++) {
@@ -296,10 +369,10 @@ __device__ void fit_band_body(const FitArgs& a, const int item, float* __restric
     if (tid == 0) band_flags[item] = 0;
 }
 
-template <int H_>
+template <int H_, int PREC>
 __global__ __launch_bounds__(256) void k_fit_band(FitArgs a) {
     extern __shared__ float lds[];
-    fit_band_body<H_>(a, blockIdx.x, lds);
+    fit_band_body<H_, PREC>(a, blockIdx.x, lds);
 }
 
 // All bands of all stamps of all pairs of a batch; item_pair maps the
@@ -321,7 +394,7 @@ __global__ __launch_bounds__(256) void k_fit_band_b(const PairDesc* __restrict__
     a.xy = pd.xy;
     a.part = pd.part;
     a.band_flags = pd.bflags;
-    fit_band_body<H_>(a, blockIdx.x - pd.band_off, lds);
+    fit_band_body<H_, PSFM_PREC_FP32>(a, blockIdx.x - pd.band_off, lds);
 }
 
 // Sum of the band partials of each stamp in FP64 and scatter to M_s, b_s, e_s.
@@ -393,9 +466,13 @@ FitArgs base_fit_args(const psfm_context* ctx) {
 
 template <int H_>
 int set_fit_lds(size_t lds) {
-    static size_t granted = 0;      // dynamic LDS granted so far (both kernels)
+    static size_t granted = 0;      // dynamic LDS granted so far (all forms)
     if (lds > granted) {
-        PSFM_HIP_CHECK(hipFuncSetAttribute((const void*)k_fit_band<H_>,
+        PSFM_HIP_CHECK(hipFuncSetAttribute((const void*)k_fit_band<H_, PSFM_PREC_FP32>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        PSFM_HIP_CHECK(hipFuncSetAttribute((const void*)k_fit_band<H_, PSFM_PREC_FP16>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        PSFM_HIP_CHECK(hipFuncSetAttribute((const void*)k_fit_band<H_, PSFM_PREC_BF16>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         PSFM_HIP_CHECK(hipFuncSetAttribute((const void*)k_fit_band_b<H_>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -411,10 +488,15 @@ int launch_fit(const psfm_context* ctx, const FitArgs& a, int n_items, const Pai
     const size_t lds = (size_t)Lo.total * sizeof(float);
     int rc = set_fit_lds<H_>(lds);
     if (rc) return rc;
+    const int prec = ctx->cfg.precision;
     if (pairs)
         hipLaunchKernelGGL(k_fit_band_b<H_>, dim3(n_items), dim3(256), lds, st, pairs, item_pair, a);
+    else if (prec == PSFM_PREC_FP16)
+        hipLaunchKernelGGL((k_fit_band<H_, PSFM_PREC_FP16>), dim3(n_items), dim3(256), lds, st, a);
+    else if (prec == PSFM_PREC_BF16)
+        hipLaunchKernelGGL((k_fit_band<H_, PSFM_PREC_BF16>), dim3(n_items), dim3(256), lds, st, a);
     else
-        hipLaunchKernelGGL(k_fit_band<H_>, dim3(n_items), dim3(256), lds, st, a);
+        hipLaunchKernelGGL((k_fit_band<H_, PSFM_PREC_FP32>), dim3(n_items), dim3(256), lds, st, a);
     PSFM_HIP_CHECK(hipGetLastError());
     return PSFM_OK;
 }
@@ -459,6 +541,7 @@ int fit_prepare(const psfm_context* ctx) {
 int batch_fit(const psfm_context* ctx, const PairDesc* pairs, const int* item_pair,
               const int* stamp_pair, int n_items, int n_stamps, hipStream_t st) {
     if (fit_lds_bytes(ctx) > 160 * 1024 - 1024) return PSFM_ERR_UNSUPPORTED;
+    if (ctx->cfg.precision != PSFM_PREC_FP32) return PSFM_ERR_UNSUPPORTED;
     if (n_items == 0) return PSFM_OK;
     int rc = dispatch_fit(ctx, base_fit_args(ctx), n_items, pairs, item_pair, st);
     if (rc) return rc;
@@ -483,9 +566,11 @@ extern "C" int psfm_fit_stamps(const psfm_context* ctx, const float* I1, const u
                                const float* I2, const float* V2, const uint8_t* M2, int W, int H,
                                int64_t pitch, const int32_t* stamp_xy, int n_stamps,
                                double* stamp_M, double* stamp_b, double* stamp_e,
-                               int32_t* stamp_npix, int32_t* stamp_flags, void* ws,
-                               size_t ws_bytes, void* stream) {
+                               int32_t* stamp_npix, int32_t* stamp_flags, float* stamp_design,
+                               void* ws, size_t ws_bytes, void* stream) {
     if (!ctx || n_stamps < 0) return PSFM_ERR_INVALID_ARG;
+    if (ctx->cfg.precision != PSFM_PREC_FP32 && n_stamps > 0 && !stamp_design)
+        return PSFM_ERR_INVALID_ARG;
     if (W < 1 || H < 1 || pitch < W) return PSFM_ERR_SHAPE;
     if (n_stamps == 0) return PSFM_OK;
     if (!I1 || !M1 || !I2 || !V2 || !M2 || !stamp_xy || !stamp_M || !stamp_b || !stamp_e ||
@@ -511,6 +596,7 @@ extern "C" int psfm_fit_stamps(const psfm_context* ctx, const float* I1, const u
     a.xy = stamp_xy;
     a.part = part;
     a.band_flags = bflags;
+    a.design = stamp_design;
     int rc = dispatch_fit(ctx, a, n_stamps * a.nbands, nullptr, nullptr, st);
     if (rc != PSFM_OK) return rc;
     const int npix = (2 * ctx->r + 1) * (2 * ctx->r + 1);

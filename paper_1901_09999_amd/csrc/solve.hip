@@ -240,6 +240,7 @@ __device__ __forceinline__ double block_sum(double v, double* red) { return psfm
 // stored inverses.
 typedef double double4v __attribute__((ext_vector_type(4)));
 
+
 __device__ __forceinline__ double rsqrt_nr(double d) {
     double r = __builtin_amdgcn_rsq(d);
     r = r * (1.5 - 0.5 * d * r * r);
@@ -249,8 +250,72 @@ __device__ __forceinline__ double rsqrt_nr(double d) {
 
 constexpr int IL_S = 17;   // LDS row stride of the 16 x 16 inverses
 
+// Back substitution L^T w = z with the factor in the lower triangle of A and
+// the stored inverses of the 16 x 16 diagonal sub-blocks; z (LDS) is
+// overwritten by w.  P, IL, part are LDS scratch of the caller.
+__device__ void back_subst(int N, const double* __restrict__ A, const double* __restrict__ ILg,
+                           double* zb, double* P, double (*IL)[16 * IL_S], double* part) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int NPART = CH_THREADS / 32;
+    const int tr = tid >> 5, tc = tid & 31, TR = CH_THREADS / 32;
+    for (int k0 = ((N - 1) / CH_NB) * CH_NB; k0 >= 0; k0 -= CH_NB) {
+        const int nk = min(CH_NB, N - k0);
+        const int rows = N - k0;
+        for (int i = tr; i < rows; i += TR)
+            P[i * CH_PS + tc] = (tc < nk && (i >= nk || tc <= i)) ? A[(size_t)(k0 + i) * N + k0 + tc] : 0.0;
+        for (int e = tid; e < 512; e += CH_THREADS) {
+            const int g = e >> 8, q = (e >> 4) & 15, j = e & 15;
+            IL[g][q * IL_S + j] = ILg[(size_t)(k0 / CH_NB) * 512 + e];
+        }
+        __syncthreads();
+        {
+            const int c = tid & 31, w = tid >> 5;
+            double acc = 0.0;
+            if (c < nk)
+                for (int i = nk + w; i < rows; i += NPART) acc += P[i * CH_PS + c] * zb[k0 + i];
+            part[c * NPART + w] = acc;
+        }
+        __syncthreads();
+        if (wave == 0) {
+            double v = 0.0;
+            if (lane < nk) {
+                v = zb[k0 + lane];
+                for (int w = 0; w < NPART; w++) v -= part[lane * NPART + w];
+            }
+            if (lane < 32) zb[k0 + lane] = lane < nk ? v : 0.0;
+            wave_sync();
+            // w2 = inv(L22)^T rhs2
+            double w2 = 0.0;
+            if (lane >= 16 && lane < 32) {
+                const int i = lane - 16;
+                for (int k = 0; k < 16; k++) w2 += IL[1][k * IL_S + i] * zb[k0 + 16 + k];
+            }
+            wave_sync();
+            if (lane >= 16 && lane < 32) zb[k0 + lane] = w2;
+            wave_sync();
+            // rhs1 -= L21^T w2 ; w1 = inv(L11)^T rhs1
+            double r1 = 0.0;
+            if (lane < 16) {
+                r1 = zb[k0 + lane];
+                for (int k = 0; k < 16; k++) r1 -= P[(16 + k) * CH_PS + lane] * zb[k0 + 16 + k];
+            }
+            wave_sync();
+            if (lane < 16) zb[k0 + lane] = r1;
+            wave_sync();
+            double w1 = 0.0;
+            if (lane < 16) {
+                for (int k = 0; k < 16; k++) w1 += IL[0][k * IL_S + lane] * zb[k0 + k];
+            }
+            wave_sync();
+            if (lane < 16 && lane < nk) zb[k0 + lane] = w1;
+        }
+        __syncthreads();
+    }
+}
+
 __device__ void cholesky_body(int N, double* __restrict__ A, const double* __restrict__ b,
-                              double* __restrict__ x, double* __restrict__ ILg, SolveState* st) {
+                              double* __restrict__ x, double* __restrict__ ILg,
+                              double* __restrict__ Dg, SolveState* st) {
     if (st->done) return;
     extern __shared__ double P[];        // panel [N + 16][CH_PS]
     __shared__ double Dq[CH_NMAX];
@@ -262,7 +327,6 @@ __device__ void cholesky_body(int N, double* __restrict__ A, const double* __res
     __shared__ int s_bad;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     constexpr int NW = CH_THREADS / 64;
-    constexpr int NPART = CH_THREADS / 32;
     if (tid == 0) s_bad = 0;
     __syncthreads();
     for (int i = tid; i < N; i += CH_THREADS) {
@@ -284,6 +348,7 @@ __device__ void cholesky_body(int N, double* __restrict__ A, const double* __res
     for (int i = tid; i < N + 32; i += CH_THREADS) {
         zb[i] = i < N ? Dq[i] * b[i] : 0.0;
         dinv[i] = 0.0;
+        if (Dg && i < N) Dg[i] = Dq[i];
     }
     const int tr = tid >> 5, tc = tid & 31, TR = CH_THREADS / 32;
     for (int i = tr; i < N; i += TR)
@@ -488,74 +553,178 @@ __device__ void cholesky_body(int N, double* __restrict__ A, const double* __res
         }
         __syncthreads();
     }
-    // ---- back substitution L^T w = z, panels in reverse
-    for (int k0 = ((N - 1) / CH_NB) * CH_NB; k0 >= 0; k0 -= CH_NB) {
-        const int nk = min(CH_NB, N - k0);
-        const int rows = N - k0;
-        for (int i = tr; i < rows; i += TR)
-            P[i * CH_PS + tc] = (tc < nk && (i >= nk || tc <= i)) ? A[(size_t)(k0 + i) * N + k0 + tc] : 0.0;
-        for (int e = tid; e < 512; e += CH_THREADS) {
-            const int g = e >> 8, q = (e >> 4) & 15, j = e & 15;
-            IL[g][q * IL_S + j] = ILg[(size_t)(k0 / CH_NB) * 512 + e];
-        }
-        __syncthreads();
-        {
-            const int c = tid & 31, w = tid >> 5;
-            double acc = 0.0;
-            if (c < nk)
-                for (int i = nk + w; i < rows; i += NPART) acc += P[i * CH_PS + c] * zb[k0 + i];
-            part[c * NPART + w] = acc;
-        }
-        __syncthreads();
-        if (wave == 0) {
-            double v = 0.0;
-            if (lane < nk) {
-                v = zb[k0 + lane];
-                for (int w = 0; w < NPART; w++) v -= part[lane * NPART + w];
-            }
-            if (lane < 32) zb[k0 + lane] = lane < nk ? v : 0.0;
-            wave_sync();
-            // w2 = inv(L22)^T rhs2
-            double w2 = 0.0;
-            if (lane >= 16 && lane < 32) {
-                const int i = lane - 16;
-                for (int k = 0; k < 16; k++) w2 += IL[1][k * IL_S + i] * zb[k0 + 16 + k];
-            }
-            wave_sync();
-            if (lane >= 16 && lane < 32) zb[k0 + lane] = w2;
-            wave_sync();
-            // rhs1 -= L21^T w2 ; w1 = inv(L11)^T rhs1
-            double r1 = 0.0;
-            if (lane < 16) {
-                r1 = zb[k0 + lane];
-                for (int k = 0; k < 16; k++) r1 -= P[(16 + k) * CH_PS + lane] * zb[k0 + 16 + k];
-            }
-            wave_sync();
-            if (lane < 16) zb[k0 + lane] = r1;
-            wave_sync();
-            double w1 = 0.0;
-            if (lane < 16) {
-                for (int k = 0; k < 16; k++) w1 += IL[0][k * IL_S + lane] * zb[k0 + k];
-            }
-            wave_sync();
-            if (lane < 16 && lane < nk) zb[k0 + lane] = w1;
-        }
-        __syncthreads();
-    }
+    back_subst(N, A, ILg, zb, P, IL, part);
     for (int i = tid; i < N; i += CH_THREADS) x[i] = Dq[i] * zb[i];
 }
 
 __global__ __launch_bounds__(CH_THREADS) void k_cholesky(int N, double* __restrict__ A,
                                                          const double* __restrict__ b,
                                                          double* __restrict__ x,
-                                                         double* __restrict__ ILg, SolveState* st) {
-    cholesky_body(N, A, b, x, ILg, st);
+                                                         double* __restrict__ ILg,
+                                                         double* __restrict__ Dg, SolveState* st) {
+    cholesky_body(N, A, b, x, ILg, Dg, st);
 }
 
 // Batched: one workgroup per pair, all solved concurrently.
 __global__ __launch_bounds__(CH_THREADS) void k_cholesky_b(const PairDesc* __restrict__ pairs) {
     const PairDesc& p = pairs[blockIdx.x];
-    cholesky_body(p.N, p.A, p.b, p.coeffs, p.ILg, p.st);
+    cholesky_body(p.N, p.A, p.b, p.coeffs, p.ILg, nullptr, p.st);
+}
+
+// Solution of M d = g with the factor left by cholesky_body (equilibrated
+// lower triangle in A, 1/sqrt(diag M) in Dg, the inverses of the 16 x 16
+// diagonal sub-blocks in ILg); x += d.  One workgroup.  This is the
+// correction step of the iterative refinement of the 16-bit modes.
+__device__ void resolve_body(int N, const double* __restrict__ A, const double* __restrict__ ILg,
+                             const double* __restrict__ Dg, const double* __restrict__ g,
+                             double* __restrict__ x, const SolveState* st) {
+    if (st->done) return;
+    extern __shared__ double P[];
+    __shared__ double zb[CH_NMAX + 32];
+    __shared__ double Dq[CH_NMAX];
+    __shared__ double IL[2][16 * IL_S];
+    __shared__ double part[CH_NB * (CH_THREADS / 32)];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tr = tid >> 5, tc = tid & 31, TR = CH_THREADS / 32;
+    for (int i = tid; i < N + 32; i += CH_THREADS) {
+        zb[i] = i < N ? Dg[i] * g[i] : 0.0;
+        if (i < N) Dq[i] = Dg[i];
+    }
+    // forward substitution L z = D g, panel by panel
+    for (int k0 = 0; k0 < N; k0 += CH_NB) {
+        const int nk = min(CH_NB, N - k0);
+        const int rows = N - k0;
+        for (int i = tr; i < rows; i += TR)
+            P[i * CH_PS + tc] = (tc < nk && (i >= nk || tc <= i)) ? A[(size_t)(k0 + i) * N + k0 + tc] : 0.0;
+        for (int e = tid; e < 512; e += CH_THREADS) {
+            const int gg = e >> 8, q = (e >> 4) & 15, j = e & 15;
+            IL[gg][q * IL_S + j] = ILg[(size_t)(k0 / CH_NB) * 512 + e];
+        }
+        __syncthreads();
+        if (wave == 0) {
+            double z1 = 0.0;
+            if (lane < 16)
+                for (int k = 0; k < 16; k++) z1 += IL[0][lane * IL_S + k] * zb[k0 + k];
+            wave_sync();
+            if (lane < 16) zb[k0 + lane] = z1;
+            wave_sync();
+            double s2 = 0.0;
+            if (lane >= 16 && lane < 32) {
+                const int i = lane - 16;
+                s2 = zb[k0 + 16 + i];
+                for (int k = 0; k < 16; k++) s2 -= P[(16 + i) * CH_PS + k] * zb[k0 + k];
+            }
+            wave_sync();
+            if (lane >= 16 && lane < 32) zb[k0 + lane] = s2;
+            wave_sync();
+            double z2 = 0.0;
+            if (lane >= 16 && lane < 32) {
+                const int i = lane - 16;
+                for (int k = 0; k < 16; k++) z2 += IL[1][i * IL_S + k] * zb[k0 + 16 + k];
+            }
+            wave_sync();
+            if (lane >= 16 && lane < 32 && lane < nk) zb[k0 + lane] = z2;
+        }
+        __syncthreads();
+        for (int i = nk + tid; i < rows; i += CH_THREADS) {
+            double acc = 0.0;
+#pragma unroll 8
+            for (int c = 0; c < CH_NB; c++) acc += P[i * CH_PS + c] * zb[k0 + c];
+            zb[k0 + i] -= acc;
+        }
+        __syncthreads();
+    }
+    back_subst(N, A, ILg, zb, P, IL, part);
+    for (int i = tid; i < N; i += CH_THREADS) x[i] += Dq[i] * zb[i];
+}
+
+__global__ __launch_bounds__(CH_THREADS) void k_resolve(int N, const double* __restrict__ A,
+                                                        const double* __restrict__ ILg,
+                                                        const double* __restrict__ Dg,
+                                                        const double* __restrict__ g,
+                                                        double* __restrict__ x, const SolveState* st) {
+    resolve_body(N, A, ILg, Dg, g, x, st);
+}
+
+// Pixel residuals of every fitted stamp at the current coefficients, from
+// the FP32 stamp design [nb + 2][npix] (terms, sqrt(w), d~) left by the fit:
+//   e = d~ - sum_c design_c alpha_c,  chi2_s = e^T e,  g_s = design^T e
+// with FP64 accumulation; g_s goes stamp-major to gt[c * n + s].
+__global__ __launch_bounds__(256) void k_resid(int n, int nb, int ns, int N, int npix,
+                                               const float* __restrict__ design,
+                                               const double* __restrict__ G,
+                                               const double* __restrict__ a,
+                                               const uint8_t* __restrict__ fitted,
+                                               double* __restrict__ gt, double* __restrict__ chi2,
+                                               const SolveState* st) {
+    if (st->done) return;
+    const int s = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int L = nb + 1;
+    __shared__ double alpha[64];
+    __shared__ double red[4][64];
+    __shared__ double cred[4];
+    if (!fitted[s]) {
+        if (tid < L) gt[(size_t)tid * n + s] = 0.0;
+        return;
+    }
+    if (tid < L) {
+        double al;
+        if (tid < nb) {
+            al = 0.0;
+            for (int q = 0; q < ns; q++) al += a[tid * ns + q] * G[(size_t)s * ns + q];
+        } else {
+            al = a[N - 1];
+        }
+        alpha[tid] = al;
+    }
+    __syncthreads();
+    const float* D = design + (size_t)s * (nb + 2) * npix;
+    double g[64];
+#pragma unroll
+    for (int c = 0; c < 64; c++) g[c] = 0.0;
+    double chi = 0.0;
+    for (int p = tid; p < npix; p += 256) {
+        double e = (double)D[(size_t)(nb + 1) * npix + p];
+#pragma unroll
+        for (int c = 0; c < 64; c++)
+            if (c < L) e -= alpha[c] * (double)D[(size_t)c * npix + p];
+        chi += e * e;
+#pragma unroll
+        for (int c = 0; c < 64; c++)
+            if (c < L) g[c] += (double)D[(size_t)c * npix + p] * e;
+    }
+#pragma unroll
+    for (int c = 0; c < 64; c++) {
+        if (c < L) {
+            double v = g[c];
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+            if (lane == 0) red[wave][c] = v;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) chi += __shfl_xor(chi, o);
+    if (lane == 0) cred[wave] = chi;
+    __syncthreads();
+    if (tid < L) gt[(size_t)tid * n + s] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+    if (tid == 0) chi2[s] = (cred[0] + cred[1]) + (cred[2] + cred[3]);
+}
+
+// g[(i,q)] = sum_used g_q(c_k) g_k[i], g[N-1] = sum_used g_k[nb]: the
+// right-hand side of the correction, assembled like b.
+__global__ void k_assemble_vec(int n, int nb, int ns, int N, const double* __restrict__ gt,
+                               const double* __restrict__ GU, double* __restrict__ gv,
+                               const SolveState* st) {
+    if (st->done) return;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N) return;
+    const int i = (t == N - 1) ? nb : t / ns;
+    const int q = (t == N - 1) ? -1 : t - (t / ns) * ns;
+    double acc = 0.0;
+    for (int k = 0; k < n; k++) {
+        const double* gk = GU + (size_t)k * (ns + 1);
+        const double w = q < 0 ? gk[ns] : gk[ns] * gk[q];
+        acc += w * gt[(size_t)i * n + k];
+    }
+    gv[t] = acc;
 }
 
 // chi2_s = e_s - 2 alpha^T b_s + alpha^T M_s alpha for every fitted stamp
@@ -762,6 +931,9 @@ size_t solve_workspace(const psfm_context* ctx, int n) {
     c.take<double>((size_t)512 * ((ctx->N + CH_NB - 1) / CH_NB));
     c.take<double>((size_t)n * ctx->L * ctx->L + 1);
     c.take<double>((size_t)n * ctx->L + 1);
+    c.take<double>(ctx->N);                          // 1 / sqrt(diag M)
+    c.take<double>((size_t)n * ctx->L + 1);          // residual gradients, stamp-major
+    c.take<double>(ctx->N);                          // assembled correction right-hand side
     return c.off;
 }
 
@@ -771,6 +943,8 @@ int solve_lds_grant(size_t lds) {
         PSFM_HIP_CHECK(hipFuncSetAttribute((const void*)k_cholesky,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         PSFM_HIP_CHECK(hipFuncSetAttribute((const void*)k_cholesky_b,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        PSFM_HIP_CHECK(hipFuncSetAttribute((const void*)k_resolve,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         granted = lds;
     }
@@ -825,9 +999,11 @@ int batch_solve(const psfm_context* ctx, const PairDesc* pairs, const int* stamp
 extern "C" int psfm_solve(const psfm_context* ctx, int W, int H, const int32_t* stamp_xy,
                           int n_stamps, const double* stamp_M, const double* stamp_b,
                           const double* stamp_e, const int32_t* stamp_npix, int32_t* stamp_flags,
-                          double* coeffs, double* stamp_chi2, psfm_fit_stats* stats, void* ws,
-                          size_t ws_bytes, void* stream) {
+                          const float* stamp_design, double* coeffs, double* stamp_chi2,
+                          psfm_fit_stats* stats, void* ws, size_t ws_bytes, void* stream) {
     if (!ctx || n_stamps < 0 || !coeffs || !stats) return PSFM_ERR_INVALID_ARG;
+    const bool mixed = ctx->cfg.precision != PSFM_PREC_FP32;
+    if (mixed && n_stamps > 0 && !stamp_design) return PSFM_ERR_INVALID_ARG;
     if (W < 1 || H < 1) return PSFM_ERR_SHAPE;
     if (n_stamps > 0 && (!stamp_xy || !stamp_M || !stamp_b || !stamp_e || !stamp_npix ||
                          !stamp_flags || !stamp_chi2))
@@ -849,7 +1025,11 @@ extern "C" int psfm_solve(const psfm_context* ctx, int W, int H, const int32_t* 
     double* ILg = c.take<double>((size_t)512 * ((ctx->N + CH_NB - 1) / CH_NB));
     double* Mt = c.take<double>((size_t)n_stamps * ctx->L * ctx->L + 1);
     double* bt = c.take<double>((size_t)n_stamps * ctx->L + 1);
+    double* Dg = c.take<double>(ctx->N);
+    double* gt = c.take<double>((size_t)n_stamps * ctx->L + 1);
+    double* gv = c.take<double>(ctx->N);
     const int nb = ctx->nb, ns = ctx->ns, N = ctx->N, L = ctx->L;
+    const int npix = (2 * ctx->r + 1) * (2 * ctx->r + 1);
     const psfm_config& cf = ctx->cfg;
     int rc = psfm::solve_lds_grant(lds);
     if (rc) return rc;
@@ -873,10 +1053,24 @@ extern "C" int psfm_solve(const psfm_context* ctx, int W, int H, const int32_t* 
 #undef PSFM_ASM_CASE
             default: return PSFM_ERR_UNSUPPORTED;
         }
-        hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(CH_THREADS), lds, st, N, M, b, coeffs, ILg, state);
-        if (n_stamps > 0)
+        hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(CH_THREADS), lds, st, N, M, b, coeffs, ILg,
+                           mixed ? Dg : nullptr, state);
+        if (mixed && n_stamps > 0) {
+            // 16-bit sums: refine against FP32 pixel residuals, then chi2 from pixels
+            for (int k = 0; k < cf.refine; k++) {
+                hipLaunchKernelGGL(k_resid, dim3(n_stamps), dim3(256), 0, st, n_stamps, nb, ns, N,
+                                   npix, stamp_design, G, coeffs, fitted, gt, stamp_chi2, state);
+                hipLaunchKernelGGL(k_assemble_vec, dim3((N + 255) / 256), dim3(256), 0, st, n_stamps,
+                                   nb, ns, N, gt, GU, gv, state);
+                hipLaunchKernelGGL(k_resolve, dim3(1), dim3(CH_THREADS), lds, st, N, M, ILg, Dg, gv,
+                                   coeffs, state);
+            }
+            hipLaunchKernelGGL(k_resid, dim3(n_stamps), dim3(256), 0, st, n_stamps, nb, ns, N, npix,
+                               stamp_design, G, coeffs, fitted, gt, stamp_chi2, state);
+        } else if (n_stamps > 0) {
             hipLaunchKernelGGL(k_chi2, dim3(n_stamps), dim3(64), 0, st, nb, ns, N, stamp_M, stamp_b,
                                stamp_e, G, coeffs, fitted, stamp_chi2, state);
+        }
         hipLaunchKernelGGL(k_clip, dim3(1), dim3(1024), 0, st, n_stamps, cf.max_iter, cf.min_stamps,
                            cf.clip_sigma, stamp_npix, used, stamp_flags, stamp_chi2, state);
     }

@@ -42,7 +42,7 @@ class CConfig(C.Structure):
         ("min_stamps", C.c_int),
         ("bad_frac", C.c_double),
         ("precision", C.c_int),
-        ("reserved", C.c_int),
+        ("refine", C.c_int),
     ]
 
 
@@ -108,8 +108,9 @@ def lib():
             "psfm_n_unknowns": (i, [P]),
             "psfm_stamp_dim": (i, [P]),
             "psfm_workspace_bytes": (sz, [P, i, i, i]),
-            "psfm_fit_stamps": (i, [P, P, P, P, P, P, i, i, i64, P, i, P, P, P, P, P, P, sz, P]),
-            "psfm_solve": (i, [P, i, i, P, i, P, P, P, P, P, P, P, P, P, sz, P]),
+            "psfm_stamp_design_floats": (sz, [P, i]),
+            "psfm_fit_stamps": (i, [P, P, P, P, P, P, i, i, i64, P, i, P, P, P, P, P, P, P, sz, P]),
+            "psfm_solve": (i, [P, i, i, P, i, P, P, P, P, P, P, P, P, P, P, sz, P]),
             "psfm_convolve_image": (i, [P, P, P, P, i, i, i64, P, P, P, sz, P]),
             "psfm_propagate_variance": (i, [P, P, P, P, i, i, i64, P, i, P, P, i, P, P, sz, P]),
             "psfm_subtract": (i, [P, P, P, P, P, P, P, P, i, i, i64, P, i, P, i, P, P, P, P, i, P,
@@ -166,6 +167,7 @@ class Config:
     min_stamps: int = 3
     bad_frac: float = 0.2
     precision: int = PREC_FP32
+    refine: int = 1
 
     @classmethod
     def from_workload(cls, wl, **kw):
@@ -182,7 +184,7 @@ class Config:
             c.degree[j] = d
         c.half_width, c.spatial_order, c.stamp_half, c.patch = self.h, self.S, self.r, self.P
         c.clip_sigma, c.max_iter, c.min_stamps = self.clip_sigma, self.max_iter, self.min_stamps
-        c.bad_frac, c.precision = self.bad_frac, self.precision
+        c.bad_frac, c.precision, c.refine = self.bad_frac, self.precision, self.refine
         return c
 
 
@@ -236,13 +238,20 @@ class Context:
                        b=torch.empty((n, L), dtype=torch.float64, device=dev),
                        e=torch.empty(n, dtype=torch.float64, device=dev),
                        npix=torch.empty(n, dtype=torch.int32, device=dev),
-                       flags=torch.empty(n, dtype=torch.int32, device=dev))
+                       flags=torch.empty(n, dtype=torch.int32, device=dev),
+                       design=self.design_buffer(n))
         ws = self.workspace(W, H, n)
         _check(lib().psfm_fit_stamps(self._h, _ptr(I1), _ptr(M1), _ptr(I2), _ptr(V2), _ptr(M2), W, H,
                                      W, _ptr(stamps), n, _ptr(out["M"]), _ptr(out["b"]),
                                      _ptr(out["e"]), _ptr(out["npix"]), _ptr(out["flags"]),
-                                     _ptr(ws), ws.numel(), _stream()), "psfm_fit_stamps")
+                                     _ptr(out.get("design")), _ptr(ws), ws.numel(), _stream()),
+               "psfm_fit_stamps")
         return out
+
+    def design_buffer(self, n):
+        """FP32 stamp design of the 16-bit modes (None in FP32)."""
+        k = lib().psfm_stamp_design_floats(self._h, n)
+        return torch.empty(k, dtype=torch.float32, device=self.device) if k else None
 
     def solve(self, W, H, stamps, fit, flags=None, out=None):
         n = stamps.shape[0]
@@ -255,7 +264,8 @@ class Context:
         out["flags"] = fl
         ws = self.workspace(W, H, n)
         _check(lib().psfm_solve(self._h, W, H, _ptr(stamps), n, _ptr(fit["M"]), _ptr(fit["b"]),
-                                _ptr(fit["e"]), _ptr(fit["npix"]), _ptr(fl), _ptr(out["coeffs"]),
+                                _ptr(fit["e"]), _ptr(fit["npix"]), _ptr(fl), _ptr(fit.get("design")),
+                                _ptr(out["coeffs"]),
                                 _ptr(out["chi2"]), _ptr(out["stats"]), _ptr(ws), ws.numel(),
                                 _stream()), "psfm_solve")
         return out
@@ -326,7 +336,8 @@ class Context:
                      b=torch.empty((n, L), dtype=torch.float64, device=dev),
                      e=torch.empty(n, dtype=torch.float64, device=dev),
                      npix=torch.empty(n, dtype=torch.int32, device=dev),
-                     flags=torch.empty(n, dtype=torch.int32, device=dev)),
+                     flags=torch.empty(n, dtype=torch.int32, device=dev),
+                     design=self.design_buffer(n)),
             flags_in=torch.empty(n, dtype=torch.int32, device=dev),
             sol=dict(coeffs=torch.empty(self.N, dtype=torch.float64, device=dev),
                      chi2=torch.empty(max(n, 1), dtype=torch.float64, device=dev),
@@ -469,7 +480,8 @@ def to_device(pair, device="cuda"):
 
 def exported_symbols() -> Sequence[str]:
     return ["psfm_config_default", "psfm_create", "psfm_destroy", "psfm_n_basis", "psfm_n_spatial",
-            "psfm_n_unknowns", "psfm_stamp_dim", "psfm_workspace_bytes", "psfm_fit_stamps",
+            "psfm_n_unknowns", "psfm_stamp_dim", "psfm_workspace_bytes", "psfm_stamp_design_floats",
+            "psfm_fit_stamps",
             "psfm_solve", "psfm_convolve_image", "psfm_propagate_variance", "psfm_subtract",
             "psfm_status_string", "psfm_batch_workspace_bytes", "psfm_batch_plan",
             "psfm_batch_run", "psfm_batch_run_stage", "psfm_batch_set_tuning", "psfm_batch_graph_capture",

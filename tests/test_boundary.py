@@ -48,6 +48,7 @@ def test_host_argument_checks(lib):
     lib.psfm_config_default(C.byref(cfg))
     assert cfg.n_gauss == 3 and cfg.half_width == 10 and list(cfg.degree[:3]) == [6, 4, 2]
     assert abs(cfg.bad_frac - 0.2) < 1e-15 and cfg.max_iter == 3 and cfg.min_stamps == 3
+    assert cfg.precision == 0 and cfg.refine == 1
     h = C.c_void_p()
     assert lib.psfm_create(None, C.byref(h)) == -1
     bad = psfm.CConfig()
@@ -63,10 +64,17 @@ def test_host_argument_checks(lib):
     lib.psfm_config_default(C.byref(bad))
     bad.degree[0] = 9                     # 55 + 15 + 6 terms: beyond the 64-column Gram
     assert lib.psfm_create(C.byref(bad), C.byref(h)) == -7
+    lib.psfm_config_default(C.byref(bad))
+    bad.precision = 3
+    assert lib.psfm_create(C.byref(bad), C.byref(h)) == -7
+    lib.psfm_config_default(C.byref(bad))
+    bad.refine = 5
+    assert lib.psfm_create(C.byref(bad), C.byref(h)) == -7
+    assert lib.psfm_stamp_design_floats(None, 4) == 0
     assert lib.psfm_workspace_bytes(None, 10, 10, 1) == 0
-    assert lib.psfm_fit_stamps(None, *([None] * 5), 10, 10, 10, None, 1, *([None] * 5), None, 0,
+    assert lib.psfm_fit_stamps(None, *([None] * 5), 10, 10, 10, None, 1, *([None] * 6), None, 0,
                                None) == -1
-    assert lib.psfm_solve(None, 10, 10, None, 1, *([None] * 8), None, 0, None) == -1
+    assert lib.psfm_solve(None, 10, 10, None, 1, *([None] * 9), None, 0, None) == -1
     assert lib.psfm_convolve_image(None, None, None, None, 10, 10, 10, None, None, None, 0, None) == -1
     for code in range(-7, 1):
         assert lib.psfm_status_string(code).decode()
