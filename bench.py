@@ -48,6 +48,11 @@ def parse():
     ap.add_argument("--workload", default="cfg1")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--retune", action="store_true", help="ignore cached batch launch shapes")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16", "bf16"],
+                    help="arithmetic of the stamp fit for the reported value")
+    ap.add_argument("--refine", type=int, default=None, help="refinement steps of 16-bit modes")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip timing the other fit arithmetic beside the reported one")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="bound on the oracle's timed sample")
     return ap.parse_args()
@@ -241,46 +246,59 @@ def main():
     wl = synth.WORKLOADS[args.workload]
     cfg_index = int(args.workload[-1])
     pair = synth.make_pair(wl, synth.workload_seed(cfg_index))
-    ctx = psfm.Context(psfm.Config.from_workload(wl))
     d = psfm.to_device(pair)
     W, H, n = wl.width, wl.height, pair.stamps.shape[0]
-    bufs = ctx.alloc_pair(W, H, n, wl.cov_half)
+    precs = {"fp32": psfm.PREC_FP32, "fp16": psfm.PREC_FP16, "bf16": psfm.PREC_BF16}
 
-    def step(ev=None):
-        f = ctx.fit_stamps(d["I1"], d["M1"], d["I2"], d["V2"], d["M2"], d["stamps"], out=bufs["fit"])
-        if ev: ev[0].record()
-        s = ctx.solve(W, H, d["stamps"], f, out=bufs["sol"])
-        if ev: ev[1].record()
-        ctx.convolve_image(s["coeffs"], d["I1"], d["M1"], out=bufs["conv"], out_mask=bufs["conv_mask"])
-        if ev: ev[2].record()
-        ctx.propagate_variance(s["coeffs"], d["V1"], d["M1"], c_out=wl.cov_half, stats=s["stats"],
-                               out=bufs["var"], cov_out=bufs["cov"])
-        if ev: ev[3].record()
-        ctx.subtract(s["coeffs"], d["I2"], d["V2"], d["M2"], bufs["conv"], bufs["var"],
-                     bufs["conv_mask"], bufs["cov"], out=bufs["sub"])
-        if ev: ev[4].record()
+    def run_mode(prec_name, steps, warmup):
+        prec = precs[prec_name]
+        refine = args.refine if args.refine is not None else (2 if prec == psfm.PREC_BF16 else 1)
+        ctx = psfm.Context(psfm.Config.from_workload(wl, precision=prec, refine=refine))
+        bufs = ctx.alloc_pair(W, H, n, wl.cov_half)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
-    start = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    start.record()
-    for k in range(args.steps):
-        step(evs[k])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = 1e3 * wall / args.steps
-    # stage times (ms): fit, solve, convolve, variance, subtract
-    stage = np.zeros(5)
-    for k in range(args.steps):
-        prev = start if k == 0 else evs[k - 1][4]
-        marks = [prev] + evs[k]
-        stage += [marks[i].elapsed_time(marks[i + 1]) for i in range(5)]
-    stage /= args.steps
-    gpu_ms = float(start.elapsed_time(evs[-1][4])) / args.steps
-    stats = psfm.read_stats(bufs["sol"]["stats"])
+        def step(ev=None):
+            f = ctx.fit_stamps(d["I1"], d["M1"], d["I2"], d["V2"], d["M2"], d["stamps"], out=bufs["fit"])
+            if ev: ev[0].record()
+            s = ctx.solve(W, H, d["stamps"], f, out=bufs["sol"])
+            if ev: ev[1].record()
+            ctx.convolve_image(s["coeffs"], d["I1"], d["M1"], out=bufs["conv"], out_mask=bufs["conv_mask"])
+            if ev: ev[2].record()
+            ctx.propagate_variance(s["coeffs"], d["V1"], d["M1"], c_out=wl.cov_half, stats=s["stats"],
+                                   out=bufs["var"], cov_out=bufs["cov"])
+            if ev: ev[3].record()
+            ctx.subtract(s["coeffs"], d["I2"], d["V2"], d["M2"], bufs["conv"], bufs["var"],
+                         bufs["conv_mask"], bufs["cov"], out=bufs["sub"])
+            if ev: ev[4].record()
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+        start = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        start.record()
+        for k in range(steps):
+            step(evs[k])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        stage = np.zeros(5)
+        for k in range(steps):
+            prev = start if k == 0 else evs[k - 1][4]
+            marks = [prev] + evs[k]
+            stage += [marks[i].elapsed_time(marks[i + 1]) for i in range(5)]
+        stage /= steps
+        gpu_ms = float(start.elapsed_time(evs[-1][4])) / steps
+        stats = psfm.read_stats(bufs["sol"]["stats"])
+        return dict(ms_per_step=1e3 * wall / steps, stage=stage, gpu_ms=gpu_ms, stats=stats,
+                    refine=refine)
+
+    main_run = run_mode(args.precision, args.steps, args.warmup)
+    other = None
+    if not args.no_compare:
+        other_name = "fp16" if args.precision == "fp32" else "fp32"
+        other = (other_name, run_mode(other_name, args.steps, args.warmup))
+    ms_per_step, stage, gpu_ms, stats = (main_run["ms_per_step"], main_run["stage"],
+                                         main_run["gpu_ms"], main_run["stats"])
 
     # roofline of the dominant kernel: the image convolution (one launch per step)
     conv_us = stage[2] * 1e3
@@ -304,13 +322,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if args.precision == "fp32" else f"{args.precision} gram, f32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {W}x{H} FP32 pair, {wl.n_sources} sources, "
                                f"{int(wl.mask_frac * 100)}% mask, {2 * wl.kernel_half + 1}^2 kernel, "
                                f"{wl.n_basis}-term ISIS basis x spatial order {wl.spatial_order} "
                                f"({wl.n_unknowns} unknowns), {n} stamps of {2 * wl.stamp_half + 1}^2, "
-                               f"plain FP32 path",
+                               f"{args.precision} stamp fit",
                    "width": W, "height": H, "n_stamps": n, "unknowns": wl.n_unknowns,
                    "parallelism": "single GPU"},
         "stages_ms": {k: round(float(v), 4) for k, v in
@@ -320,6 +338,17 @@ def main():
                 "n_used": stats["n_used"], "n_iter": stats["n_iter"]},
         "roofline": roof,
     }
+    if other is not None:
+        o = other[1]
+        out["compare"] = {"precision": other[0], "refine": o["refine"],
+                          "value": round(W * H / 1e6 / (o["ms_per_step"] * 1e-3), 2),
+                          "ms_per_step": round(o["ms_per_step"], 4),
+                          "stages_ms": {k: round(float(v), 4) for k, v in
+                                        zip(["fit", "solve", "convolve", "variance", "subtract"],
+                                            o["stage"])},
+                          "fit": {"chi2_dof": o["stats"]["chi2_dof"],
+                                  "kernel_sum_centre": o["stats"]["kernel_sum_centre"],
+                                  "n_used": o["stats"]["n_used"]}}
     if not args.no_cpu_baseline:
         base, res = cpu_baseline(wl, pair, args.cpu_seconds)
         out["cpu_baseline"] = base
@@ -327,6 +356,11 @@ def main():
         out["parity_vs_oracle"] = {
             "kernel_sum_rel": abs(stats["kernel_sum_centre"] / ref["kernel_sum_centre"] - 1),
             "chi2_dof_rel": abs(stats["chi2_dof"] / ref["chi2_dof"] - 1)}
+        if other is not None:
+            os_ = other[1]["stats"]
+            out["compare"]["parity_vs_oracle"] = {
+                "kernel_sum_rel": abs(os_["kernel_sum_centre"] / ref["kernel_sum_centre"] - 1),
+                "chi2_dof_rel": abs(os_["chi2_dof"] / ref["chi2_dof"] - 1)}
     print(json.dumps(out), flush=True)
 
 

@@ -532,7 +532,7 @@ __global__ __launch_bounds__(256) void k_subtract_cov(const double* __restrict__
 // variance sums go to the pair's partials; the workgroup that finishes a
 // pair's last tile forms that pair's C_D and stamps its completion time.
 template <int H_>
-__global__ __launch_bounds__(256) void k_match_tiles_b(const PairDesc* __restrict__ pairs,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_match_tiles_b(const PairDesc* __restrict__ pairs,
                                                        const int* __restrict__ tile_pair,
                                                        int n_tiles, BasisArgs B0, int P,
                                                        double bad_frac) {

@@ -253,7 +253,7 @@ constexpr int IL_S = 17;   // LDS row stride of the 16 x 16 inverses
 // Back substitution L^T w = z with the factor in the lower triangle of A and
 // the stored inverses of the 16 x 16 diagonal sub-blocks; z (LDS) is
 // overwritten by w.  P, IL, part are LDS scratch of the caller.
-__device__ void back_subst(int N, const double* __restrict__ A, const double* __restrict__ ILg,
+__device__ __forceinline__ void back_subst(int N, const double* __restrict__ A, const double* __restrict__ ILg,
                            double* zb, double* P, double (*IL)[16 * IL_S], double* part) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     constexpr int NPART = CH_THREADS / 32;
@@ -313,7 +313,7 @@ __device__ void back_subst(int N, const double* __restrict__ A, const double* __
     }
 }
 
-__device__ void cholesky_body(int N, double* __restrict__ A, const double* __restrict__ b,
+__device__ __forceinline__ void cholesky_body(int N, double* __restrict__ A, const double* __restrict__ b,
                               double* __restrict__ x, double* __restrict__ ILg,
                               double* __restrict__ Dg, SolveState* st) {
     if (st->done) return;
@@ -575,7 +575,7 @@ __global__ __launch_bounds__(CH_THREADS) void k_cholesky_b(const PairDesc* __res
 // lower triangle in A, 1/sqrt(diag M) in Dg, the inverses of the 16 x 16
 // diagonal sub-blocks in ILg); x += d.  One workgroup.  This is the
 // correction step of the iterative refinement of the 16-bit modes.
-__device__ void resolve_body(int N, const double* __restrict__ A, const double* __restrict__ ILg,
+__device__ __forceinline__ void resolve_body(int N, const double* __restrict__ A, const double* __restrict__ ILg,
                              const double* __restrict__ Dg, const double* __restrict__ g,
                              double* __restrict__ x, const SolveState* st) {
     if (st->done) return;
@@ -650,6 +650,10 @@ __global__ __launch_bounds__(CH_THREADS) void k_resolve(int N, const double* __r
 // the FP32 stamp design [nb + 2][npix] (terms, sqrt(w), d~) left by the fit:
 //   e = d~ - sum_c design_c alpha_c,  chi2_s = e^T e,  g_s = design^T e
 // with FP64 accumulation; g_s goes stamp-major to gt[c * n + s].
+// Phase 1: one pixel per thread, e kept in LDS; phase 2: one wave per column,
+// the lanes striding over the pixels (coalesced), then a wave sum.
+constexpr int RES_MAXPIX = (2 * PSFM_RMAX + 1) * (2 * PSFM_RMAX + 1);
+
 __global__ __launch_bounds__(256) void k_resid(int n, int nb, int ns, int N, int npix,
                                                const float* __restrict__ design,
                                                const double* __restrict__ G,
@@ -661,8 +665,8 @@ __global__ __launch_bounds__(256) void k_resid(int n, int nb, int ns, int N, int
     const int s = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int L = nb + 1;
     __shared__ double alpha[64];
-    __shared__ double red[4][64];
-    __shared__ double cred[4];
+    __shared__ float ebuf[RES_MAXPIX];
+    __shared__ double red[16];
     if (!fitted[s]) {
         if (tid < L) gt[(size_t)tid * n + s] = 0.0;
         return;
@@ -679,33 +683,22 @@ __global__ __launch_bounds__(256) void k_resid(int n, int nb, int ns, int N, int
     }
     __syncthreads();
     const float* D = design + (size_t)s * (nb + 2) * npix;
-    double g[64];
-#pragma unroll
-    for (int c = 0; c < 64; c++) g[c] = 0.0;
     double chi = 0.0;
     for (int p = tid; p < npix; p += 256) {
         double e = (double)D[(size_t)(nb + 1) * npix + p];
-#pragma unroll
-        for (int c = 0; c < 64; c++)
-            if (c < L) e -= alpha[c] * (double)D[(size_t)c * npix + p];
+        for (int c = 0; c < L; c++) e -= alpha[c] * (double)D[(size_t)c * npix + p];
         chi += e * e;
-#pragma unroll
-        for (int c = 0; c < 64; c++)
-            if (c < L) g[c] += (double)D[(size_t)c * npix + p] * e;
+        ebuf[p] = (float)e;
     }
-#pragma unroll
-    for (int c = 0; c < 64; c++) {
-        if (c < L) {
-            double v = g[c];
-            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-            if (lane == 0) red[wave][c] = v;
-        }
+    chi = psfm_block_sum(chi, red);     // also orders ebuf before phase 2
+    for (int c = wave; c < L; c += 4) {
+        const float* Dc = D + (size_t)c * npix;
+        double acc = 0.0;
+        for (int p = lane; p < npix; p += 64) acc += (double)Dc[p] * (double)ebuf[p];
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+        if (lane == 0) gt[(size_t)c * n + s] = acc;
     }
-    for (int o = 32; o > 0; o >>= 1) chi += __shfl_xor(chi, o);
-    if (lane == 0) cred[wave] = chi;
-    __syncthreads();
-    if (tid < L) gt[(size_t)tid * n + s] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
-    if (tid == 0) chi2[s] = (cred[0] + cred[1]) + (cred[2] + cred[3]);
+    if (tid == 0) chi2[s] = chi;
 }
 
 // g[(i,q)] = sum_used g_q(c_k) g_k[i], g[N-1] = sum_used g_k[nb]: the
