@@ -72,6 +72,7 @@ typedef enum {
 #define PSFM_STAMP_REJECTED  2   /* removed by the rejection iterations of psfm_solve */
 #define PSFM_STAMP_NONFINITE 4   /* non-finite pixel, or variance not finite and > 0 */
 #define PSFM_STAMP_EXCLUDED  8   /* excluded by the caller before psfm_solve */
+#define PSFM_STAMP_PRIOR    16   /* excluded before the first solution by the learned prior */
 
 /* Output mask bits. */
 #define PSFM_MASK_BAD       1    /* masked in the input (difference image: image 2) */
@@ -139,6 +140,9 @@ typedef struct psfm_fit_stats {
     int n_rejected;            /* stamps rejected by this solve */
     int n_iter;                /* solutions computed */
     int info;                  /* 0 ok; k > 0: pivot k not positive; -3: too few stamps */
+    double chi2_dof_prior;     /* psfm_solve_prior: chi2/dof of the kept stamps at the warm start */
+    int n_prior;               /* psfm_solve_prior: stamps the prior excluded (after fallback) */
+    int n_restored;            /* psfm_solve_prior: excluded stamps the solution brought back */
 } psfm_fit_stats;
 
 typedef struct psfm_context psfm_context;
@@ -211,6 +215,45 @@ int psfm_solve(const psfm_context* ctx, int W, int H, const int32_t* stamp_xy, i
                const int32_t* stamp_npix, int32_t* stamp_flags, const float* stamp_design,
                double* coeffs, double* stamp_chi2, psfm_fit_stats* stats, void* ws,
                size_t ws_bytes, void* stream);
+
+/*
+ * Each stamp's own least-squares kernel (no spatial terms): M_s a = b_s
+ * solved in FP64 (equilibrated Cholesky) for every stamp; local (n x L
+ * float64) receives a, stamp_chi2 receives e_s - 2 a^T b_s + a^T M_s a.
+ * Flagged stamps and non-positive pivots give zeros and chi2 = -1.  Used to
+ * make training targets for the learned prior.  Needs L <= 64.
+ */
+int psfm_solve_stamps(const psfm_context* ctx, int n_stamps, const double* stamp_M,
+                      const double* stamp_b, const double* stamp_e, const int32_t* stamp_flags,
+                      double* local, double* stamp_chi2, void* stream);
+
+/*
+ * psfm_solve with a learned prior: stamp_pred (n x L float64, kernel terms;
+ * the background slot is ignored) holds per-stamp predicted local kernel
+ * coefficients.  Before the first solution
+ *   - each prediction is completed with its best background;
+ *   - warm start a0: the spatial polynomial of each term fitted to the kept
+ *     predictions;
+ *   - rejection prior: a variable source shows as a predicted kernel sum (its
+ *     own flux ratio) far from a0's kernel sum at the stamp; departures
+ *     d = k_pred / k_a0 - 1 beyond max(5 robust sigma, 20%) about their
+ *     median (robust sigma = 1.4826 x median absolute deviation, kept
+ *     stamps) get PSFM_STAMP_PRIOR and are left out of the equations; a0 is
+ *     refitted and the clip repeated (at most max_iter + 1 rounds, no solve
+ *     needed);
+ *   - stats->chi2_dof_prior: chi2/dof of the kept stamps at a0.
+ * The solve and rejection loop of psfm_solve then runs as usual.  Fallback:
+ * an excluded stamp whose chi2_s / npix_s at the solution lies within the
+ * method's clip threshold is restored, and the rejection loop resumes from
+ * the restored set (up to max_iter more solutions), so the least-squares
+ * solution and the method's own clip remain the judge.  Same arguments as
+ * psfm_solve.
+ */
+int psfm_solve_prior(const psfm_context* ctx, int W, int H, const int32_t* stamp_xy, int n_stamps,
+                     const double* stamp_M, const double* stamp_b, const double* stamp_e,
+                     const int32_t* stamp_npix, int32_t* stamp_flags, const float* stamp_design,
+                     const double* stamp_pred, double* coeffs, double* stamp_chi2,
+                     psfm_fit_stats* stats, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Image convolution with the spatially varying kernel (Section 4.2, Eq. 12;
@@ -357,6 +400,67 @@ int psfm_batch_destroy(psfm_batch* batch);
 
 /* Tick rate of the device wall clock used by the batch time stamps. */
 double psfm_wall_clock_hz(void);
+
+/*
+ * Learned prior: a small CNN that predicts a stamp's kernel from the stamp
+ * pair.  Input per stamp: 2 x 41 x 41 FP16 (the reference and target
+ * windows); output: PSFM_CNN_OUT FP32 coefficients of the kernel in an
+ * orthonormal basis of the kernel-basis span (c = R a with G = R^T R the
+ * Gram matrix of the basis taps, so |c| is the kernel-image L2 norm).
+ *   conv1 3x3 2->32 stride 1, conv2..conv4 3x3 32->32 stride 2 (zero
+ *   padding 1, ReLU; 41 -> 41 -> 21 -> 11 -> 6), fc1 1152 -> 128 ReLU,
+ *   fc2 128 -> 49.  Convolutions are cross-correlations.
+ * Parameters: one flat vector, for conv1..conv4, fc1, fc2 the weight
+ * (row-major [out][in][3][3] or [out][in]) then the bias; FP32 master copy
+ * and FP16 working copy (uint16_t bit patterns).  All pointers device.
+ */
+#define PSFM_CNN_SIDE 41
+#define PSFM_CNN_OUT 49
+
+size_t psfm_cnn_param_count(void);
+size_t psfm_cnn_workspace_bytes(int batch);
+
+/* out (batch x 49 FP32) = net(x); x: batch x 2 x 41 x 41 FP16. */
+int psfm_cnn_forward(const uint16_t* w16, const uint16_t* x, int batch, float* out, void* ws,
+                     size_t ws_bytes, void* stream);
+
+/* Forward, loss and its gradient in the parameters (grad, FP32, overwritten).
+   loss (device float, may be NULL) = sum_b r_b^T W_b r_b / (batch * 49),
+   r_b = out_b - target_b, with W_b = weight[b] (49 x 49 FP32, symmetric) or
+   the identity if weight is NULL (plain mean squared error). */
+int psfm_cnn_loss_grad(const uint16_t* w16, const uint16_t* x, const float* target,
+                       const float* weight, int batch, float* grad, float* loss, void* ws,
+                       size_t ws_bytes, void* stream);
+
+/* Loss weights of n stamps (n x 49 x 49 FP32): W = R^-T Mh R^-1 / npix with
+   Mh the stamp matrix with the background eliminated, so that r^T W r is the
+   chi2/dof excess of a kernel whose orthonormal coefficients are off by r
+   (background re-fitted).  Flagged stamps get zeros.  Needs nb = 49. */
+int psfm_cnn_loss_weights(const psfm_context* ctx, const double* stamp_M, const int32_t* stamp_npix,
+                          const int32_t* stamp_flags, int n_stamps, float* weight, void* stream);
+
+/* One Adam step (bias-corrected, step >= 1) on the FP32 master weights; the
+   FP16 copy is refreshed.  m, v: FP32 moments, n = psfm_cnn_param_count(). */
+int psfm_cnn_adam(float* w32, uint16_t* w16, float* m, float* v, const float* grad, size_t n,
+                  int step, float lr, float beta1, float beta2, float eps, void* stream);
+
+/* Network inputs of n stamps: the 41 x 41 windows of I1 and I2 around each
+   centre, minus the mean of each window's unmasked border, divided by the
+   reference window's flux F (summed window minus its sky) floored at
+   3 sigma_b sqrt(n) (sigma_b: scatter of the reference border, n: valid
+   pixels), times 100, clamped to +-60000 (masked / outside pixels 0).
+   x: n x 2 x 41 x 41 FP16; flux (nullable): F. */
+int psfm_cnn_stamp_inputs(const float* I1, const uint8_t* M1, const float* I2, const uint8_t* M2,
+                          int W, int H, int64_t pitch, const int32_t* stamp_xy, int n_stamps,
+                          uint16_t* x, float* flux, void* stream);
+
+/* Orthonormal-basis coefficients from local coefficients (n x L, the first
+   nb used): ortho = R a (n x 49 FP32); and back: local = R^-1 ortho (the
+   background slot set to 0).  Need nb = 49. */
+int psfm_cnn_targets(const psfm_context* ctx, const double* local, int n_stamps, float* ortho,
+                     void* stream);
+int psfm_cnn_local_coeffs(const psfm_context* ctx, const float* ortho, int n_stamps,
+                          double* local, void* stream);
 
 /* Human-readable text of a psfm_status value (static storage). */
 const char* psfm_status_string(int status);

@@ -13,7 +13,9 @@ pair (the reference stamp and the target stamp, 41 x 41 each):
     fc1    1152 -> 128, ReLU          (flattened channel-major: c, y, x)
     fc2    128 -> 49                  (no activation)
 
-Loss: mean over the batch and the 49 outputs of (out - target)^2.
+Loss: mean over the batch and the 49 outputs of (out - target)^2, or with a
+per-sample symmetric weight W_b (49 x 49): sum_b r_b^T W_b r_b / (B * 49),
+r_b = out_b - target_b (the plain loss is W_b = identity).
 
 A convolution here is the cross-correlation used by neural networks:
     y[b, o, i, j] = bias[o] + sum_{c, u, v} w[o, c, u, v] x[b, c, s i + u - 1, s j + v - 1]
@@ -144,14 +146,20 @@ def forward(theta: np.ndarray, x: np.ndarray, keep: bool = False):
     return out
 
 
-def loss_and_grad(theta: np.ndarray, x: np.ndarray, target: np.ndarray):
-    """Mean squared error over batch and outputs, and its gradient in theta."""
+def loss_and_grad(theta: np.ndarray, x: np.ndarray, target: np.ndarray, weight=None):
+    """(Weighted) mean squared error over batch and outputs, and its gradient
+    in theta.  weight: [B, 49, 49] symmetric, or None for the identity."""
     p = unpack(theta)
     out, a = forward(theta, x, keep=True)
     B = x.shape[0]
     r = out - target
-    loss = float(np.mean(r * r))
-    dout = 2.0 * r / r.size
+    if weight is None:
+        loss = float(np.mean(r * r))
+        dout = 2.0 * r / r.size
+    else:
+        u = np.einsum("bij,bj->bi", weight, r)
+        loss = float(np.sum(r * u) / r.size)
+        dout = 2.0 * u / r.size
     g = {}
     g["fc2.w"] = dout.T @ a["hidden"]
     g["fc2.b"] = dout.sum(0)

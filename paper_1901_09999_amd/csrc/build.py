@@ -10,7 +10,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
-SOURCES = ["context.hip", "fit.hip", "solve.hip", "convolve.hip", "batch.hip"]
+SOURCES = ["context.hip", "fit.hip", "solve.hip", "convolve.hip", "batch.hip", "cnn.hip"]
 LIB = os.path.join(PKG, "libpsfm.so")
 OBJDIR = os.path.join(ROOT, "_build")
 
@@ -18,7 +18,7 @@ FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
     # packed FP32 instructions stay off (plain FP32 FMA only)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wall", "-Wno-unused-function", "-Wno-unused-result",
+    "-Wall", "-Wno-unused-function", "-Wno-unused-result", "-Wno-pass-failed",
 ]
 
 

@@ -1,0 +1,626 @@
+// Stamp-pair CNN: forward, MSE gradient and Adam, FP16 weights and
+// activations with FP32 accumulation (the learned warm start / rejection
+// prior of the kernel fit).
+//
+// Network (NCHW, one sample = the reference and target 41 x 41 stamps):
+//   conv1 3x3 2->32 s1, conv2..4 3x3 32->32 s2 (zero padding 1, ReLU):
+//   41 -> 41 -> 21 -> 11 -> 6;  fc1 1152 -> 128 ReLU;  fc2 128 -> 49.
+// A convolution is the cross-correlation
+//   y[b,o,i,j] = bias[o] + sum_{c,u,v} w[o,c,u,v] x[b,c, s i+u-1, s j+v-1].
+//
+// Kernels (VALU, FP32 accumulation):
+//   k_conv_fwd       one thread per output pixel, all 32 output channels in
+//                    registers, the layer's weights in LDS ordered [c][uv][o]
+//                    so a pixel's 32 products read 8 broadcast 16-byte words;
+//   k_conv_bwd_data  one thread per input pixel, all input channels, the
+//                    ReLU mask of the layer below applied on the way out;
+//   k_conv_bwd_w     one workgroup per (o, c): the 9 weight gradients (and
+//                    the bias gradient) summed over batch and pixels in a
+//                    fixed order;
+//   k_fc_fwd / k_fc_bwd_x / k_fc_bwd_w, k_mse, k_adam.
+// The backward pass stores activation gradients in FP32.
+#include "internal.h"
+
+#include <hip/hip_fp16.h>
+
+namespace {
+
+constexpr int SIDE0 = PSFM_CNN_SIDE, CH = 32, HID = 128, NOUT = PSFM_CNN_OUT;
+constexpr int SIDE1 = 41, SIDE2 = 21, SIDE3 = 11, SIDE4 = 6;
+constexpr int FLAT = CH * SIDE4 * SIDE4;
+
+// parameter offsets (elements), in the order conv1.w, conv1.b, ..., fc2.b
+constexpr int OFF_C1W = 0, OFF_C1B = OFF_C1W + CH * 2 * 9;
+constexpr int OFF_C2W = OFF_C1B + CH, OFF_C2B = OFF_C2W + CH * CH * 9;
+constexpr int OFF_C3W = OFF_C2B + CH, OFF_C3B = OFF_C3W + CH * CH * 9;
+constexpr int OFF_C4W = OFF_C3B + CH, OFF_C4B = OFF_C4W + CH * CH * 9;
+constexpr int OFF_F1W = OFF_C4B + CH, OFF_F1B = OFF_F1W + HID * FLAT;
+constexpr int OFF_F2W = OFF_F1B + HID, OFF_F2B = OFF_F2W + NOUT * HID;
+constexpr int NPARAM = OFF_F2B + NOUT;
+
+__device__ __forceinline__ float h2f(__half v) { return __half2float(v); }
+
+template <int CIN, int S>
+__global__ __launch_bounds__(256) void k_conv_fwd(const __half* __restrict__ x, int Hin,
+                                                  const __half* __restrict__ w,
+                                                  const __half* __restrict__ bias,
+                                                  __half* __restrict__ y, int Hout, int B) {
+    __shared__ __align__(16) float ws[CIN * 9 * CH];     // [c][uv][o]
+    __shared__ float bs[CH];
+    for (int e = threadIdx.x; e < CIN * 9 * CH; e += 256) {
+        const int o = e % CH, cuv = e / CH;               // cuv = c * 9 + uv
+        ws[e] = h2f(w[o * CIN * 9 + cuv]);
+    }
+    if (threadIdx.x < CH) bs[threadIdx.x] = h2f(bias[threadIdx.x]);
+    __syncthreads();
+    const int npix = Hout * Hout;
+    for (int t = blockIdx.x * 256 + threadIdx.x; t < B * npix; t += gridDim.x * 256) {
+        const int b = t / npix, p = t - b * npix;
+        const int i = p / Hout, j = p - i * Hout;
+        float acc[CH];
+#pragma unroll
+        for (int o = 0; o < CH; o++) acc[o] = bs[o];
+        for (int c = 0; c < CIN; c++) {
+            const __half* xc = x + ((size_t)b * CIN + c) * Hin * Hin;
+#pragma unroll
+            for (int u = 0; u < 3; u++) {
+                const int pi = S * i + u - 1;
+#pragma unroll
+                for (int v = 0; v < 3; v++) {
+                    const int qj = S * j + v - 1;
+                    if (pi < 0 || pi >= Hin || qj < 0 || qj >= Hin) continue;
+                    const float xv = h2f(xc[pi * Hin + qj]);
+                    const float4* wr = reinterpret_cast<const float4*>(ws + (c * 9 + u * 3 + v) * CH);
+#pragma unroll
+                    for (int q = 0; q < CH / 4; q++) {
+                        const float4 ww = wr[q];
+                        acc[4 * q] = fmaf(ww.x, xv, acc[4 * q]);
+                        acc[4 * q + 1] = fmaf(ww.y, xv, acc[4 * q + 1]);
+                        acc[4 * q + 2] = fmaf(ww.z, xv, acc[4 * q + 2]);
+                        acc[4 * q + 3] = fmaf(ww.w, xv, acc[4 * q + 3]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int o = 0; o < CH; o++)
+            y[(((size_t)b * CH + o) * Hout + i) * Hout + j] = __float2half(fmaxf(acc[o], 0.0f));
+    }
+}
+
+// dx[b,c,p,q] = sum over (o,u,v) with p = s i + u - 1, q = s j + v - 1 of
+// w[o,c,u,v] dy[b,o,i,j];  dxm = dx * (a > 0) with a the layer's input
+// activation (post-ReLU of the layer below).
+template <int S>
+__global__ __launch_bounds__(256) void k_conv_bwd_data(const float* __restrict__ dy, int Hout,
+                                                       const __half* __restrict__ w,
+                                                       const __half* __restrict__ a,
+                                                       float* __restrict__ dxm, int Hin, int B) {
+    __shared__ __align__(16) float ws[9 * CH * CH];     // [uv][o][c]
+    for (int e = threadIdx.x; e < 9 * CH * CH; e += 256) {
+        const int c = e % CH, r = e / CH, o = r % CH, uv = r / CH;
+        ws[e] = h2f(w[(o * CH + c) * 9 + uv]);
+    }
+    __syncthreads();
+    const int npix = Hin * Hin;
+    for (int t = blockIdx.x * 256 + threadIdx.x; t < B * npix; t += gridDim.x * 256) {
+        const int b = t / npix, pp = t - b * npix;
+        const int p = pp / Hin, q = pp - p * Hin;
+        float acc[CH];
+#pragma unroll
+        for (int c = 0; c < CH; c++) acc[c] = 0.0f;
+#pragma unroll
+        for (int u = 0; u < 3; u++) {
+            const int ni = p + 1 - u;
+            if (ni < 0 || ni % S) continue;
+            const int i = ni / S;
+            if (i >= Hout) continue;
+#pragma unroll
+            for (int v = 0; v < 3; v++) {
+                const int nj = q + 1 - v;
+                if (nj < 0 || nj % S) continue;
+                const int j = nj / S;
+                if (j >= Hout) continue;
+                for (int o = 0; o < CH; o++) {
+                    const float g = dy[(((size_t)b * CH + o) * Hout + i) * Hout + j];
+                    const float4* wr = reinterpret_cast<const float4*>(ws + ((u * 3 + v) * CH + o) * CH);
+#pragma unroll
+                    for (int k = 0; k < CH / 4; k++) {
+                        const float4 ww = wr[k];
+                        acc[4 * k] = fmaf(ww.x, g, acc[4 * k]);
+                        acc[4 * k + 1] = fmaf(ww.y, g, acc[4 * k + 1]);
+                        acc[4 * k + 2] = fmaf(ww.z, g, acc[4 * k + 2]);
+                        acc[4 * k + 3] = fmaf(ww.w, g, acc[4 * k + 3]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CH; c++) {
+            const size_t o = (((size_t)b * CH + c) * Hin + p) * Hin + q;
+            dxm[o] = h2f(a[o]) > 0.0f ? acc[c] : 0.0f;
+        }
+    }
+}
+
+__device__ __forceinline__ float block_sum_f(float v, float* red) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    float s = 0.0f;
+    for (int k = 0; k < (int)(blockDim.x >> 6); k++) s += red[k];
+    return s;
+}
+
+// dw[o,c,u,v] = sum_{b,i,j} dy[b,o,i,j] x[b,c,s i+u-1,s j+v-1]; db[o] = sum dy.
+// One workgroup per (o, c); fixed summation order.
+template <int S>
+__global__ __launch_bounds__(256) void k_conv_bwd_w(const float* __restrict__ dy, int Hout,
+                                                    const __half* __restrict__ x, int CIN, int Hin,
+                                                    int B, float* __restrict__ dw,
+                                                    float* __restrict__ db) {
+    __shared__ float red[4];
+    const int o = blockIdx.x / CIN, c = blockIdx.x % CIN;
+    float acc[9];
+#pragma unroll
+    for (int k = 0; k < 9; k++) acc[k] = 0.0f;
+    float accb = 0.0f;
+    const int npix = Hout * Hout;
+    for (int t = threadIdx.x; t < B * npix; t += 256) {
+        const int b = t / npix, pp = t - b * npix;
+        const int i = pp / Hout, j = pp - i * Hout;
+        const float g = dy[((size_t)b * CH + o) * npix + pp];
+        accb += g;
+        const __half* xc = x + ((size_t)b * CIN + c) * Hin * Hin;
+#pragma unroll
+        for (int u = 0; u < 3; u++) {
+            const int pi = S * i + u - 1;
+#pragma unroll
+            for (int v = 0; v < 3; v++) {
+                const int qj = S * j + v - 1;
+                if (pi >= 0 && pi < Hin && qj >= 0 && qj < Hin)
+                    acc[u * 3 + v] = fmaf(g, h2f(xc[pi * Hin + qj]), acc[u * 3 + v]);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        const float s = block_sum_f(acc[k], red);
+        if (threadIdx.x == 0) dw[(o * CIN + c) * 9 + k] = s;
+    }
+    const float sb = block_sum_f(accb, red);
+    if (c == 0 && threadIdx.x == 0) db[o] = sb;
+}
+
+// y[b,n] = bias[n] + sum_k W[n,k] x[b,k]  (ReLU -> FP16 out, or FP32 out)
+template <bool RELU>
+__global__ __launch_bounds__(256) void k_fc_fwd(const __half* __restrict__ x, int K,
+                                                const __half* __restrict__ W,
+                                                const __half* __restrict__ bias, int N, int B,
+                                                __half* __restrict__ y16, float* __restrict__ y32) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= B * N) return;
+    const int b = t / N, n = t - b * N;
+    const __half* xr = x + (size_t)b * K;
+    const __half* wr = W + (size_t)n * K;
+    float acc = h2f(bias[n]);
+    for (int k = 0; k < K; k++) acc = fmaf(h2f(wr[k]), h2f(xr[k]), acc);
+    if (RELU) y16[t] = __float2half(fmaxf(acc, 0.0f));
+    else y32[t] = acc;
+}
+
+// dxm[b,k] = (sum_n W[n,k] dy[b,n]) * (x[b,k] > 0)
+__global__ __launch_bounds__(256) void k_fc_bwd_x(const float* __restrict__ dy, int N,
+                                                  const __half* __restrict__ W,
+                                                  const __half* __restrict__ x, int K, int B,
+                                                  float* __restrict__ dxm) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= B * K) return;
+    const int b = t / K, k = t - b * K;
+    float acc = 0.0f;
+    for (int n = 0; n < N; n++) acc = fmaf(h2f(W[(size_t)n * K + k]), dy[(size_t)b * N + n], acc);
+    dxm[t] = h2f(x[t]) > 0.0f ? acc : 0.0f;
+}
+
+// dW[n,k] = sum_b dy[b,n] x[b,k];  db[n] = sum_b dy[b,n]
+__global__ __launch_bounds__(256) void k_fc_bwd_w(const float* __restrict__ dy, int N,
+                                                  const __half* __restrict__ x, int K, int B,
+                                                  float* __restrict__ dW, float* __restrict__ db) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t < N * K) {
+        const int n = t / K, k = t - n * K;
+        float acc = 0.0f;
+        for (int b = 0; b < B; b++) acc = fmaf(dy[(size_t)b * N + n], h2f(x[(size_t)b * K + k]), acc);
+        dW[t] = acc;
+    }
+    if (t < N) {
+        float acc = 0.0f;
+        for (int b = 0; b < B; b++) acc += dy[(size_t)b * N + t];
+        db[t] = acc;
+    }
+}
+
+// Weighted loss per sample b (one wave): r = out_b - target_b, u = W_b r,
+// part_b = r^T u, dout_b = 2 u / count.
+__global__ __launch_bounds__(64) void k_wloss(const float* __restrict__ out,
+                                              const float* __restrict__ target,
+                                              const float* __restrict__ W, int count,
+                                              float* __restrict__ dout, float* __restrict__ part) {
+    __shared__ float r[64];
+    const int b = blockIdx.x, i = threadIdx.x;
+    if (i < NOUT) r[i] = out[b * NOUT + i] - target[b * NOUT + i];
+    __syncthreads();
+    float p = 0.0f;
+    if (i < NOUT) {
+        const float* Wr = W + ((size_t)b * NOUT + i) * NOUT;
+        float u = 0.0f;
+        for (int j = 0; j < NOUT; j++) u = fmaf(Wr[j], r[j], u);
+        dout[b * NOUT + i] = 2.0f * u / (float)count;
+        p = r[i] * u;
+    }
+    for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o);
+    if (i == 0) part[b] = p;
+}
+
+__global__ __launch_bounds__(256) void k_sum_parts(const float* __restrict__ part, int B, int count,
+                                                   float* __restrict__ loss) {
+    __shared__ float red[4];
+    float s = 0.0f;
+    for (int b = threadIdx.x; b < B; b += 256) s += part[b];
+    s = block_sum_f(s, red);
+    if (threadIdx.x == 0 && loss) *loss = s / (float)count;
+}
+
+// loss = mean (out - target)^2; dout = 2 (out - target) / count.  One workgroup.
+__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ out,
+                                             const float* __restrict__ target, int count,
+                                             float* __restrict__ dout, float* __restrict__ loss) {
+    __shared__ float red[4];
+    float s = 0.0f;
+    for (int e = threadIdx.x; e < count; e += 256) {
+        const float r = out[e] - target[e];
+        dout[e] = 2.0f * r / (float)count;
+        s = fmaf(r, r, s);
+    }
+    s = block_sum_f(s, red);
+    if (threadIdx.x == 0 && loss) *loss = s / (float)count;
+}
+
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ w32, __half* __restrict__ w16,
+                                              float* __restrict__ m, float* __restrict__ v,
+                                              const float* __restrict__ g, size_t n, float lr,
+                                              float b1, float b2, float eps, float c1, float c2) {
+    const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= n) return;
+    const float gt = g[t];
+    const float mt = b1 * m[t] + (1.0f - b1) * gt;
+    const float vt = b2 * v[t] + (1.0f - b2) * gt * gt;
+    m[t] = mt;
+    v[t] = vt;
+    const float w = w32[t] - lr * (mt / c1) / (sqrtf(vt / c2) + eps);
+    w32[t] = w;
+    w16[t] = __float2half(w);
+}
+
+// Network inputs of stamp s: the 41 x 41 windows of I1 and I2 around the
+// stamp centre, each minus the mean of its unmasked border pixels, both
+// divided by the reference window's flux F (the summed window minus its sky),
+// floored at 3 sigma_b sqrt(n) (sigma_b the reference border scatter, n the
+// valid pixels: a faint or empty window cannot blow the scale up), times 100
+// and kept within the FP16 range; masked or outside pixels are 0.  One
+// workgroup per stamp.
+__global__ __launch_bounds__(256) void k_stamp_inputs(const float* __restrict__ I1,
+                                                      const uint8_t* __restrict__ M1,
+                                                      const float* __restrict__ I2,
+                                                      const uint8_t* __restrict__ M2, int W, int H,
+                                                      int64_t pitch, const int32_t* __restrict__ xy,
+                                                      __half* __restrict__ xo,
+                                                      float* __restrict__ flux) {
+    __shared__ float red[4];
+    constexpr int R = SIDE0 / 2, NP = SIDE0 * SIDE0;
+    const int s = blockIdx.x, xc = xy[2 * s], yc = xy[2 * s + 1];
+    auto val = [&](const float* I, const uint8_t* M, int e, bool& ok) {
+        const int dy = e / SIDE0 - R, dx = e % SIDE0 - R;
+        const int gx = xc + dx, gy = yc + dy;
+        ok = gx >= 0 && gx < W && gy >= 0 && gy < H;
+        if (!ok) return 0.0f;
+        const int64_t o = (int64_t)gy * pitch + gx;
+        ok = M[o] == 0 && isfinite(I[o]);
+        return ok ? I[o] : 0.0f;
+    };
+    float sky[2], sig1 = 0.0f;
+    for (int k = 0; k < 2; k++) {
+        const float* I = k ? I2 : I1;
+        const uint8_t* M = k ? M2 : M1;
+        float sum = 0.0f, sq = 0.0f, cnt = 0.0f;
+        for (int e = threadIdx.x; e < NP; e += 256) {
+            const int py = e / SIDE0, px = e % SIDE0;
+            if (py != 0 && py != SIDE0 - 1 && px != 0 && px != SIDE0 - 1) continue;
+            bool ok;
+            const float v = val(I, M, e, ok);
+            if (ok) {
+                sum += v;
+                sq = fmaf(v, v, sq);
+                cnt += 1.0f;
+            }
+        }
+        sum = block_sum_f(sum, red);
+        sq = block_sum_f(sq, red);
+        cnt = block_sum_f(cnt, red);
+        sky[k] = cnt > 0.0f ? sum / cnt : 0.0f;
+        if (k == 0 && cnt > 1.0f) sig1 = sqrtf(fmaxf(sq / cnt - sky[0] * sky[0], 0.0f));
+    }
+    float f = 0.0f, nv = 0.0f;
+    for (int e = threadIdx.x; e < NP; e += 256) {
+        bool ok;
+        const float v = val(I1, M1, e, ok);
+        if (ok) {
+            f += v - sky[0];
+            nv += 1.0f;
+        }
+    }
+    f = block_sum_f(f, red);
+    nv = block_sum_f(nv, red);
+    const float den = fmaxf(f, 3.0f * sig1 * sqrtf(nv));
+    const float scale = den > 0.0f ? 100.0f / den : 0.0f;
+    for (int e = threadIdx.x; e < NP; e += 256) {
+        bool ok1, ok2;
+        const float v1 = val(I1, M1, e, ok1), v2 = val(I2, M2, e, ok2);
+        const float x1 = ok1 ? (v1 - sky[0]) * scale : 0.0f;
+        const float x2 = ok2 ? (v2 - sky[1]) * scale : 0.0f;
+        xo[((size_t)s * 2 + 0) * NP + e] = __float2half(fminf(fmaxf(x1, -60000.0f), 60000.0f));
+        xo[((size_t)s * 2 + 1) * NP + e] = __float2half(fminf(fmaxf(x2, -60000.0f), 60000.0f));
+    }
+    if (threadIdx.x == 0 && flux) flux[s] = f;
+}
+
+// Orthonormal-basis coefficients and local basis coefficients, per stamp:
+//   c = R a (targets), a = R^-1 c (predictions), R upper (nb x nb).
+__global__ void k_coeff_to_ortho(const double* __restrict__ Rm, int nb, int L,
+                                 const double* __restrict__ a, int n, float* __restrict__ c) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * nb) return;
+    const int s = t / nb, i = t - s * nb;
+    double acc = 0.0;
+    for (int j = i; j < nb; j++) acc += Rm[i * nb + j] * a[(size_t)s * L + j];
+    c[t] = (float)acc;
+}
+
+__global__ void k_ortho_to_coeff(const double* __restrict__ Rm, int nb, int L,
+                                 const float* __restrict__ c, int n, double* __restrict__ a) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    double* as = a + (size_t)s * L;
+    for (int i = nb - 1; i >= 0; i--) {
+        double v = (double)c[(size_t)s * nb + i];
+        for (int j = i + 1; j < nb; j++) v -= Rm[i * nb + j] * as[j];
+        as[i] = v / Rm[i * nb + i];
+    }
+    for (int i = nb; i < L; i++) as[i] = 0.0;
+}
+
+// Loss weight of stamp s in orthonormal coordinates: the stamp matrix with
+// the background eliminated, Mh = M_kk - M_kb M_bb^-1 M_bk (nb x nb), mapped
+// by W = R^-T Mh R^-1 and divided by npix, so that r^T W r is the chi2/dof
+// excess of a kernel whose orthonormal coefficients are off by r (the
+// background re-fitted).  One wave per stamp; flagged stamps get zeros.
+__global__ __launch_bounds__(64) void k_loss_weight(const double* __restrict__ Rm, int nb,
+                                                    const double* __restrict__ Ms,
+                                                    const int32_t* __restrict__ npix,
+                                                    const int32_t* __restrict__ flags,
+                                                    float* __restrict__ Wout) {
+    __shared__ double Y[NOUT * (NOUT + 1)];
+    const int s = blockIdx.x, t = threadIdx.x, L = nb + 1, LD = NOUT + 1;
+    float* Wo = Wout + (size_t)s * NOUT * NOUT;
+    const double* M = Ms + (size_t)s * L * L;
+    const bool bad = flags[s] != 0 || !(M[nb * L + nb] > 0.0) || npix[s] <= 0;
+    if (bad) {
+        for (int e = t; e < NOUT * NOUT; e += 64) Wo[e] = 0.0f;
+        return;
+    }
+    const double mbb = M[nb * L + nb];
+    if (t < NOUT)
+        for (int i = 0; i < NOUT; i++) Y[i * LD + t] = M[i * L + t] - M[i * L + nb] * M[nb * L + t] / mbb;
+    __syncthreads();
+    if (t < NOUT) {                 // row t of Mh R^-1: y R = mh
+        double* y = Y + t * LD;
+        for (int j = 0; j < NOUT; j++) {
+            double v = y[j];
+            for (int k = 0; k < j; k++) v -= y[k] * Rm[k * nb + j];
+            y[j] = v / Rm[j * nb + j];
+        }
+    }
+    __syncthreads();
+    if (t < NOUT) {                 // column t of R^-T (Mh R^-1): R^T w = y
+        for (int i = 0; i < NOUT; i++) {
+            double v = Y[i * LD + t];
+            for (int k = 0; k < i; k++) v -= Rm[k * nb + i] * Y[k * LD + t];
+            Y[i * LD + t] = v / Rm[i * nb + i];
+        }
+    }
+    __syncthreads();
+    const double sc = 1.0 / (double)npix[s];
+    for (int e = t; e < NOUT * NOUT; e += 64) {
+        const int i = e / NOUT, j = e - i * NOUT;
+        Wo[e] = (float)(0.5 * (Y[i * LD + j] + Y[j * LD + i]) * sc);
+    }
+}
+
+struct Acts {
+    __half *a1, *a2, *a3, *a4, *h;
+    float *out, *dout, *dh, *d4, *d3, *d2, *d1, *part;
+    size_t bytes;
+};
+
+Acts carve(void* base, int B) {
+    psfm::Carver c(base);
+    Acts A;
+    A.a1 = c.take<__half>((size_t)B * CH * SIDE1 * SIDE1);
+    A.a2 = c.take<__half>((size_t)B * CH * SIDE2 * SIDE2);
+    A.a3 = c.take<__half>((size_t)B * CH * SIDE3 * SIDE3);
+    A.a4 = c.take<__half>((size_t)B * FLAT);
+    A.h = c.take<__half>((size_t)B * HID);
+    A.out = c.take<float>((size_t)B * NOUT);
+    A.dout = c.take<float>((size_t)B * NOUT);
+    A.dh = c.take<float>((size_t)B * HID);
+    A.d4 = c.take<float>((size_t)B * FLAT);
+    A.d3 = c.take<float>((size_t)B * CH * SIDE3 * SIDE3);
+    A.d2 = c.take<float>((size_t)B * CH * SIDE2 * SIDE2);
+    A.d1 = c.take<float>((size_t)B * CH * SIDE1 * SIDE1);
+    A.part = c.take<float>((size_t)B);
+    A.bytes = c.off;
+    return A;
+}
+
+int grid_for(size_t items) {
+    size_t g = (items + 255) / 256;
+    return (int)(g < 4096 ? (g ? g : 1) : 4096);
+}
+
+int forward_into(const __half* w, const __half* x, int B, const Acts& A, hipStream_t st) {
+    hipLaunchKernelGGL((k_conv_fwd<2, 1>), dim3(grid_for((size_t)B * SIDE1 * SIDE1)), dim3(256), 0, st,
+                       x, SIDE0, w + OFF_C1W, w + OFF_C1B, A.a1, SIDE1, B);
+    hipLaunchKernelGGL((k_conv_fwd<CH, 2>), dim3(grid_for((size_t)B * SIDE2 * SIDE2)), dim3(256), 0, st,
+                       A.a1, SIDE1, w + OFF_C2W, w + OFF_C2B, A.a2, SIDE2, B);
+    hipLaunchKernelGGL((k_conv_fwd<CH, 2>), dim3(grid_for((size_t)B * SIDE3 * SIDE3)), dim3(256), 0, st,
+                       A.a2, SIDE2, w + OFF_C3W, w + OFF_C3B, A.a3, SIDE3, B);
+    hipLaunchKernelGGL((k_conv_fwd<CH, 2>), dim3(grid_for((size_t)B * SIDE4 * SIDE4)), dim3(256), 0, st,
+                       A.a3, SIDE3, w + OFF_C4W, w + OFF_C4B, A.a4, SIDE4, B);
+    hipLaunchKernelGGL((k_fc_fwd<true>), dim3((B * HID + 255) / 256), dim3(256), 0, st, A.a4, FLAT,
+                       w + OFF_F1W, w + OFF_F1B, HID, B, A.h, nullptr);
+    hipLaunchKernelGGL((k_fc_fwd<false>), dim3((B * NOUT + 255) / 256), dim3(256), 0, st, A.h, HID,
+                       w + OFF_F2W, w + OFF_F2B, NOUT, B, nullptr, A.out);
+    PSFM_HIP_CHECK(hipGetLastError());
+    return PSFM_OK;
+}
+
+}  // namespace
+
+extern "C" size_t psfm_cnn_param_count(void) { return NPARAM; }
+
+extern "C" size_t psfm_cnn_workspace_bytes(int batch) {
+    if (batch < 1) return 0;
+    return carve(nullptr, batch).bytes + 256;
+}
+
+extern "C" int psfm_cnn_forward(const uint16_t* w16, const uint16_t* x, int batch, float* out,
+                                void* ws, size_t ws_bytes, void* stream) {
+    if (!w16 || !x || !out || batch < 1) return PSFM_ERR_INVALID_ARG;
+    if (!ws || ws_bytes < psfm_cnn_workspace_bytes(batch)) return PSFM_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    const Acts A = carve(ws, batch);
+    int rc = forward_into(reinterpret_cast<const __half*>(w16), reinterpret_cast<const __half*>(x),
+                          batch, A, st);
+    if (rc) return rc;
+    PSFM_HIP_CHECK(hipMemcpyAsync(out, A.out, sizeof(float) * batch * NOUT, hipMemcpyDeviceToDevice, st));
+    return PSFM_OK;
+}
+
+extern "C" int psfm_cnn_loss_grad(const uint16_t* w16, const uint16_t* x, const float* target,
+                                  const float* weight, int batch, float* grad, float* loss, void* ws,
+                                  size_t ws_bytes, void* stream) {
+    if (!w16 || !x || !target || !grad || batch < 1) return PSFM_ERR_INVALID_ARG;
+    if (!ws || ws_bytes < psfm_cnn_workspace_bytes(batch)) return PSFM_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    const int B = batch;
+    const __half* w = reinterpret_cast<const __half*>(w16);
+    const __half* x0 = reinterpret_cast<const __half*>(x);
+    const Acts A = carve(ws, B);
+    int rc = forward_into(w, x0, B, A, st);
+    if (rc) return rc;
+    if (weight) {
+        hipLaunchKernelGGL(k_wloss, dim3(B), dim3(64), 0, st, A.out, target, weight, B * NOUT, A.dout,
+                           A.part);
+        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, st, A.part, B, B * NOUT, loss);
+    } else {
+        hipLaunchKernelGGL(k_mse, dim3(1), dim3(256), 0, st, A.out, target, B * NOUT, A.dout, loss);
+    }
+    // fc2, fc1
+    hipLaunchKernelGGL(k_fc_bwd_w, dim3((NOUT * HID + 255) / 256), dim3(256), 0, st, A.dout, NOUT, A.h,
+                       HID, B, grad + OFF_F2W, grad + OFF_F2B);
+    hipLaunchKernelGGL(k_fc_bwd_x, dim3((B * HID + 255) / 256), dim3(256), 0, st, A.dout, NOUT,
+                       w + OFF_F2W, A.h, HID, B, A.dh);
+    hipLaunchKernelGGL(k_fc_bwd_w, dim3((HID * FLAT + 255) / 256), dim3(256), 0, st, A.dh, HID, A.a4,
+                       FLAT, B, grad + OFF_F1W, grad + OFF_F1B);
+    hipLaunchKernelGGL(k_fc_bwd_x, dim3((B * FLAT + 255) / 256), dim3(256), 0, st, A.dh, HID,
+                       w + OFF_F1W, A.a4, FLAT, B, A.d4);
+    // conv4 .. conv1 (d_k: gradient at the pre-activation of conv k, ReLU applied)
+    hipLaunchKernelGGL((k_conv_bwd_w<2>), dim3(CH * CH), dim3(256), 0, st, A.d4, SIDE4, A.a3, CH, SIDE3,
+                       B, grad + OFF_C4W, grad + OFF_C4B);
+    hipLaunchKernelGGL((k_conv_bwd_data<2>), dim3(grid_for((size_t)B * SIDE3 * SIDE3)), dim3(256), 0, st,
+                       A.d4, SIDE4, w + OFF_C4W, A.a3, A.d3, SIDE3, B);
+    hipLaunchKernelGGL((k_conv_bwd_w<2>), dim3(CH * CH), dim3(256), 0, st, A.d3, SIDE3, A.a2, CH, SIDE2,
+                       B, grad + OFF_C3W, grad + OFF_C3B);
+    hipLaunchKernelGGL((k_conv_bwd_data<2>), dim3(grid_for((size_t)B * SIDE2 * SIDE2)), dim3(256), 0, st,
+                       A.d3, SIDE3, w + OFF_C3W, A.a2, A.d2, SIDE2, B);
+    hipLaunchKernelGGL((k_conv_bwd_w<2>), dim3(CH * CH), dim3(256), 0, st, A.d2, SIDE2, A.a1, CH, SIDE1,
+                       B, grad + OFF_C2W, grad + OFF_C2B);
+    hipLaunchKernelGGL((k_conv_bwd_data<2>), dim3(grid_for((size_t)B * SIDE1 * SIDE1)), dim3(256), 0, st,
+                       A.d2, SIDE2, w + OFF_C2W, A.a1, A.d1, SIDE1, B);
+    hipLaunchKernelGGL((k_conv_bwd_w<1>), dim3(CH * 2), dim3(256), 0, st, A.d1, SIDE1, x0, 2, SIDE0, B,
+                       grad + OFF_C1W, grad + OFF_C1B);
+    PSFM_HIP_CHECK(hipGetLastError());
+    return PSFM_OK;
+}
+
+extern "C" int psfm_cnn_adam(float* w32, uint16_t* w16, float* m, float* v, const float* grad,
+                             size_t n, int step, float lr, float beta1, float beta2, float eps,
+                             void* stream) {
+    if (!w32 || !w16 || !m || !v || !grad || step < 1 || n == 0) return PSFM_ERR_INVALID_ARG;
+    const float c1 = 1.0f - std::pow(beta1, (float)step);
+    const float c2 = 1.0f - std::pow(beta2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, w32,
+                       reinterpret_cast<__half*>(w16), m, v, grad, n, lr, beta1, beta2, eps, c1, c2);
+    PSFM_HIP_CHECK(hipGetLastError());
+    return PSFM_OK;
+}
+
+extern "C" int psfm_cnn_stamp_inputs(const float* I1, const uint8_t* M1, const float* I2,
+                                     const uint8_t* M2, int W, int H, int64_t pitch,
+                                     const int32_t* stamp_xy, int n_stamps, uint16_t* x,
+                                     float* flux, void* stream) {
+    if (n_stamps < 0 || W < 1 || H < 1 || pitch < W) return PSFM_ERR_INVALID_ARG;
+    if (n_stamps == 0) return PSFM_OK;
+    if (!I1 || !M1 || !I2 || !M2 || !stamp_xy || !x) return PSFM_ERR_INVALID_ARG;
+    hipLaunchKernelGGL(k_stamp_inputs, dim3(n_stamps), dim3(256), 0, (hipStream_t)stream, I1, M1, I2,
+                       M2, W, H, pitch, stamp_xy, reinterpret_cast<__half*>(x), flux);
+    PSFM_HIP_CHECK(hipGetLastError());
+    return PSFM_OK;
+}
+
+extern "C" int psfm_cnn_targets(const psfm_context* ctx, const double* local, int n_stamps,
+                                float* ortho, void* stream) {
+    if (!ctx || n_stamps < 0 || (n_stamps > 0 && (!local || !ortho))) return PSFM_ERR_INVALID_ARG;
+    if (ctx->nb != NOUT || !ctx->kgram_ok) return PSFM_ERR_UNSUPPORTED;
+    if (n_stamps == 0) return PSFM_OK;
+    hipLaunchKernelGGL(k_coeff_to_ortho, dim3((n_stamps * ctx->nb + 255) / 256), dim3(256), 0,
+                       (hipStream_t)stream, ctx->kgram_R, ctx->nb, ctx->L, local, n_stamps, ortho);
+    PSFM_HIP_CHECK(hipGetLastError());
+    return PSFM_OK;
+}
+
+extern "C" int psfm_cnn_loss_weights(const psfm_context* ctx, const double* stamp_M,
+                                     const int32_t* stamp_npix, const int32_t* stamp_flags,
+                                     int n_stamps, float* weight, void* stream) {
+    if (!ctx || n_stamps < 0) return PSFM_ERR_INVALID_ARG;
+    if (ctx->nb != NOUT || !ctx->kgram_ok) return PSFM_ERR_UNSUPPORTED;
+    if (n_stamps == 0) return PSFM_OK;
+    if (!stamp_M || !stamp_npix || !stamp_flags || !weight) return PSFM_ERR_INVALID_ARG;
+    hipLaunchKernelGGL(k_loss_weight, dim3(n_stamps), dim3(64), 0, (hipStream_t)stream, ctx->kgram_R,
+                       ctx->nb, stamp_M, stamp_npix, stamp_flags, weight);
+    PSFM_HIP_CHECK(hipGetLastError());
+    return PSFM_OK;
+}
+
+extern "C" int psfm_cnn_local_coeffs(const psfm_context* ctx, const float* ortho, int n_stamps,
+                                     double* local, void* stream) {
+    if (!ctx || n_stamps < 0 || (n_stamps > 0 && (!local || !ortho))) return PSFM_ERR_INVALID_ARG;
+    if (ctx->nb != NOUT || !ctx->kgram_ok) return PSFM_ERR_UNSUPPORTED;
+    if (n_stamps == 0) return PSFM_OK;
+    hipLaunchKernelGGL(k_ortho_to_coeff, dim3((n_stamps + 63) / 64), dim3(64), 0, (hipStream_t)stream,
+                       ctx->kgram_R, ctx->nb, ctx->L, ortho, n_stamps, local);
+    PSFM_HIP_CHECK(hipGetLastError());
+    return PSFM_OK;
+}

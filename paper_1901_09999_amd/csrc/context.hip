@@ -153,6 +153,36 @@ int psfm_create(const psfm_config* cfg, psfm_context** out) {
         foff += c.degree[j] + 1;
     }
 
+    // R: upper Cholesky factor of the basis Gram G_ij = sum_t k_i(t) k_j(t), so
+    // that R a holds the coefficients of the kernel in an orthonormal basis of
+    // the same span (kernel-image norms become coefficient norms)
+    std::vector<double> R((size_t)nb * nb, 0.0);
+    ctx->kgram_ok = true;
+    {
+        std::vector<double> G((size_t)nb * nb);
+        for (int a = 0; a < nb; a++)
+            for (int b = 0; b <= a; b++) {
+                double g = 0.0;
+                for (int t = 0; t < T; t++) g += kb[(size_t)a * T + t] * kb[(size_t)b * T + t];
+                G[(size_t)a * nb + b] = G[(size_t)b * nb + a] = g;
+            }
+        for (int j = 0; j < nb && ctx->kgram_ok; j++) {   // G = R^T R, R upper
+            double d = G[(size_t)j * nb + j];
+            for (int k = 0; k < j; k++) d -= R[(size_t)k * nb + j] * R[(size_t)k * nb + j];
+            if (!(d > 1e-12 * G[(size_t)j * nb + j])) {   // terms (nearly) dependent on these taps:
+                ctx->kgram_ok = false;                      // no orthonormal map (learned prior only)
+                break;
+            }
+            const double rjj = std::sqrt(d);
+            R[(size_t)j * nb + j] = rjj;
+            for (int m = j + 1; m < nb; m++) {
+                double v = G[(size_t)j * nb + m];
+                for (int k = 0; k < j; k++) v -= R[(size_t)k * nb + j] * R[(size_t)k * nb + m];
+                R[(size_t)j * nb + m] = v / rjj;
+            }
+        }
+    }
+
     // one device block for all tables
     psfm::Carver layout(nullptr);
     double* d_kb = layout.take<double>(kb.size());
@@ -163,6 +193,7 @@ int psfm_create(const psfm_config* cfg, psfm_context** out) {
     float* d_z = layout.take<float>(nb);
     double* d_fac64 = layout.take<double>(fac64.size());
     double* d_psi64 = layout.take<double>(nb);
+    double* d_R = layout.take<double>(R.size());
     const size_t bytes = layout.off;
     char* blk = nullptr;
     if (hipMalloc(&blk, bytes) != hipSuccess) {
@@ -179,6 +210,7 @@ int psfm_create(const psfm_config* cfg, psfm_context** out) {
     ctx->term_z = rebase(d_z);
     ctx->fac64 = rebase(d_fac64);
     ctx->psi64 = rebase(d_psi64);
+    ctx->kgram_R = rebase(d_R);
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipMemcpy(ctx->kb64, kb.data(), kb.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ctx->fac, fac.data(), fac.size() * sizeof(float), hipMemcpyHostToDevice);
@@ -188,6 +220,7 @@ int psfm_create(const psfm_config* cfg, psfm_context** out) {
     if (e == hipSuccess) e = hipMemcpy(ctx->term_z, z.data(), nb * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ctx->fac64, fac64.data(), fac64.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ctx->psi64, psi64.data(), nb * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ctx->kgram_R, R.data(), R.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(blk);
         delete ctx;

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include <cstddef>
 #include <cstdint>
 
@@ -32,6 +34,8 @@ struct psfm_context {
     float* term_z;    // [nb] 1 if k_0 is subtracted (even terms i >= 1), else 0
     double* fac64;    // [nf][KW] the 1-D factors in FP64
     double* psi64;    // [nb] normalisations in FP64
+    double* kgram_R;  // [nb][nb] upper factor R of B^T B (B = taps as columns): |B a| = |R a|
+    bool kgram_ok;    // false if the basis taps are (nearly) dependent: no R
     void* dev_block;  // single allocation backing all of the above
 };
 
@@ -42,7 +46,9 @@ struct SolveState {
     int n_iter;
     int n_rej;
     int n_used;
-    int pad[3];
+    int prior_done;   // rejection prior converged (psfm_solve_prior)
+    int n_iter_base;  // solutions before the current rejection loop (fallback restart)
+    int pad[1];
 };
 
 // Everything the kernels need about one image pair: inputs, outputs, the

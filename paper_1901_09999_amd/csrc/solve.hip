@@ -55,6 +55,8 @@ __device__ void solve_init_body(int n, int N, int ns, int S, int W, int H, int m
             st->n_used = cnt;
             st->n_iter = 0;
             st->n_rej = 0;
+            st->prior_done = 0;
+            st->n_iter_base = 0;
             st->info = cnt < min_stamps ? PSFM_ERR_TOO_FEW_STAMPS : 0;
             st->done = cnt < min_stamps;
         }
@@ -792,7 +794,7 @@ __device__ void clip_body(int n, int max_iter, int min_stamps, double clip_sigma
     __syncthreads();
     if (tid == 0) st->n_iter += 1;
     __syncthreads();
-    if (st->n_iter >= max_iter) {
+    if (st->n_iter - st->n_iter_base >= max_iter) {
         if (tid == 0) st->done = 1;
         return;
     }
@@ -892,6 +894,18 @@ __device__ void solve_finish_body(int n, int ns, int N, int S, int W, int H,
             stats->n_used = 0;
             stats->kernel_sum_centre = 0.0;
         }
+        stats->chi2_dof_prior = 0.0;
+        stats->n_prior = 0;
+        stats->n_restored = 0;
+    }
+}
+
+__global__ void k_prior_finish(const double* __restrict__ pdof, const int* __restrict__ counts,
+                               psfm_fit_stats* stats) {
+    if (threadIdx.x == 0 && stats) {
+        stats->chi2_dof_prior = *pdof;
+        stats->n_prior = counts[0];
+        stats->n_restored = counts[1];
     }
 }
 
@@ -906,6 +920,374 @@ __global__ void k_solve_finish_b(const PairDesc* __restrict__ pairs) {
     const PairDesc& p = pairs[blockIdx.x];
     solve_finish_body(p.n, p.ns, p.N, p.S, p.W, p.H, p.npix, p.used, p.chi2, p.coeffs, p.st,
                       p.stats);
+}
+
+// Each stamp's own least-squares problem M_s a = b_s (L x L, FP64): one
+// wave per stamp, equilibrated Cholesky in LDS; the local coefficients and
+// chi2_s = e_s - 2 a^T b_s + a^T M_s a at that solution.  Flagged stamps and
+// non-positive pivots give zeros and chi2 = -1.
+constexpr int PS_LD = 65;
+
+__global__ __launch_bounds__(64) void k_solve_stamps(int L, const double* __restrict__ Ms,
+                                                     const double* __restrict__ bs,
+                                                     const double* __restrict__ es,
+                                                     const int32_t* __restrict__ flags,
+                                                     double* __restrict__ local,
+                                                     double* __restrict__ chi2) {
+    __shared__ double A[64 * PS_LD];
+    __shared__ double dq[64], x[64];
+    __shared__ int s_bad;
+    const int s = blockIdx.x, lane = threadIdx.x;
+    const double* M = Ms + (size_t)s * L * L;
+    const double* b = bs + (size_t)s * L;
+    if (lane == 0) s_bad = flags[s] != 0;
+    wave_sync();
+    if (lane < L) {
+        const double d = M[lane * L + lane];
+        if (!(d > 0.0)) s_bad = 1;
+        dq[lane] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+    }
+    wave_sync();
+    if (!s_bad) {
+        if (lane < L) {
+            for (int j = 0; j <= lane; j++) A[lane * PS_LD + j] = M[lane * L + j] * dq[lane] * dq[j];
+            x[lane] = dq[lane] * b[lane];
+        }
+        wave_sync();
+        for (int k = 0; k < L; k++) {
+            const double piv = A[k * PS_LD + k];
+            if (!(piv > 0.0)) {
+                if (lane == 0) s_bad = 1;
+                break;
+            }
+            const double lkk = sqrt(piv);
+            wave_sync();
+            if (lane == k) A[k * PS_LD + k] = lkk;
+            if (lane > k && lane < L) A[lane * PS_LD + k] /= lkk;
+            wave_sync();
+            if (lane > k && lane < L) {
+                const double lik = A[lane * PS_LD + k];
+                for (int j = k + 1; j <= lane; j++) A[lane * PS_LD + j] -= lik * A[j * PS_LD + k];
+            }
+            wave_sync();
+        }
+        wave_sync();
+    }
+    if (s_bad) {
+        if (lane < L) local[(size_t)s * L + lane] = 0.0;
+        if (lane == 0) chi2[s] = -1.0;
+        return;
+    }
+    for (int k = 0; k < L; k++) {                    // L z = x
+        if (lane == k) x[k] /= A[k * PS_LD + k];
+        wave_sync();
+        if (lane > k && lane < L) x[lane] -= A[lane * PS_LD + k] * x[k];
+        wave_sync();
+    }
+    for (int k = L - 1; k >= 0; k--) {               // L^T w = z
+        if (lane == k) x[k] /= A[k * PS_LD + k];
+        wave_sync();
+        if (lane < k) x[lane] -= A[k * PS_LD + lane] * x[k];
+        wave_sync();
+    }
+    double part = 0.0;
+    if (lane < L) {
+        const double a = dq[lane] * x[lane];
+        local[(size_t)s * L + lane] = a;
+        x[lane] = a;
+    }
+    wave_sync();
+    if (lane < L) {
+        double u = 0.0;
+        for (int j = 0; j < L; j++) u += M[lane * L + j] * x[j];
+        part = x[lane] * (u - 2.0 * b[lane]);
+    }
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+    if (lane == 0) chi2[s] = es[s] + part;
+}
+
+// Prior: each stamp's predicted local kernel coefficients (pred, n x L; the
+// background slot is replaced by the best constant for that kernel,
+// bg = (b[nb] - sum_i M[nb][i] alpha_i) / M[nb][nb]) and the chi2 of the
+// stamp under that prediction, chi2 = e - 2 alpha^T b + alpha^T M alpha.
+__global__ __launch_bounds__(64) void k_prior_chi2(int nb, const double* __restrict__ Ms,
+                                                   const double* __restrict__ bs,
+                                                   const double* __restrict__ es,
+                                                   const int32_t* __restrict__ flags,
+                                                   const double* __restrict__ pred,
+                                                   double* __restrict__ alpha_out,
+                                                   double* __restrict__ chi2p) {
+    __shared__ double al[64];
+    __shared__ double s_bg;
+    const int s = blockIdx.x, lane = threadIdx.x, L = nb + 1;
+    const double* M = Ms + (size_t)s * L * L;
+    const double* b = bs + (size_t)s * L;
+    if (flags[s]) {
+        if (lane < L) alpha_out[(size_t)s * L + lane] = 0.0;
+        if (lane == 0) chi2p[s] = 0.0;
+        return;
+    }
+    if (lane < nb) al[lane] = pred[(size_t)s * L + lane];
+    wave_sync();
+    double t = 0.0;
+    if (lane < nb) t = M[nb * L + lane] * al[lane];
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+    if (lane == 0) s_bg = M[nb * L + nb] > 0.0 ? (b[nb] - t) / M[nb * L + nb] : 0.0;
+    wave_sync();
+    if (lane == 0) al[nb] = s_bg;
+    wave_sync();
+    double part = 0.0;
+    if (lane < L) {
+        double u = 0.0;
+        for (int j = 0; j < L; j++) u += M[lane * L + j] * al[j];
+        part = al[lane] * (u - 2.0 * b[lane]);
+        alpha_out[(size_t)s * L + lane] = al[lane];
+    }
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+    if (lane == 0) chi2p[s] = es[s] + part;
+}
+
+// Warm start a0 of the prior: per kernel term, the spatial polynomial
+// fitted (least squares, FP64) to the completed per-stamp predictions of
+// the stamps in use; the background as their mean.  One workgroup.
+constexpr int PRIOR_T = 1024;
+
+__global__ __launch_bounds__(PRIOR_T) void k_prior_warm(
+    int n, int nb, int ns, int N, const double* __restrict__ G,
+    const double* __restrict__ alpha, const uint8_t* __restrict__ used, double* __restrict__ a0,
+    const SolveState* st, int force) {
+    __shared__ double Gm[28 * 28];
+    __shared__ double rhs[64 * 28];
+    __shared__ int s_ok;
+    const int tid = threadIdx.x, L = nb + 1;
+    if (st->done || (st->prior_done && !force)) return;
+    for (int t = tid; t < ns * ns + L * ns; t += PRIOR_T) {
+        const bool isG = t < ns * ns;
+        const int e = isG ? t : t - ns * ns;
+        const int r0 = e / ns, q = e % ns;
+        double acc = 0.0;
+        for (int s = 0; s < n; s++) {
+            if (!used[s]) continue;
+            const double* g = G + (size_t)s * ns;         // spatial terms at the stamp centre
+            acc += isG ? g[r0] * g[q] : alpha[(size_t)s * L + r0] * g[q];
+        }
+        if (isG) Gm[e] = acc;
+        else rhs[e] = acc;
+    }
+    __syncthreads();
+    if (tid == 0) {                           // G = C C^T in place (ns <= 28)
+        int ok = 1;
+        for (int j = 0; j < ns && ok; j++) {
+            double d = Gm[j * ns + j];
+            for (int k = 0; k < j; k++) d -= Gm[j * ns + k] * Gm[j * ns + k];
+            if (!(d > 0.0)) {
+                ok = 0;
+                break;
+            }
+            const double ljj = sqrt(d);
+            Gm[j * ns + j] = ljj;
+            for (int i = j + 1; i < ns; i++) {
+                double v = Gm[i * ns + j];
+                for (int k = 0; k < j; k++) v -= Gm[i * ns + k] * Gm[j * ns + k];
+                Gm[i * ns + j] = v / ljj;
+            }
+        }
+        s_ok = ok;
+    }
+    __syncthreads();
+    if (tid < nb) {
+        double z[28];
+        for (int q = 0; q < ns; q++) {
+            double v = rhs[tid * ns + q];
+            for (int k = 0; k < q; k++) v -= Gm[q * ns + k] * z[k];
+            z[q] = s_ok ? v / Gm[q * ns + q] : 0.0;
+        }
+        for (int q = ns - 1; q >= 0; q--) {
+            double v = z[q];
+            for (int k = q + 1; k < ns; k++) v -= Gm[k * ns + q] * z[k];
+            z[q] = s_ok ? v / Gm[q * ns + q] : 0.0;
+        }
+        for (int q = 0; q < ns; q++) a0[tid * ns + q] = z[q];
+    }
+    if (tid == 0) {
+        double sbg = 0.0, c = 0.0;
+        for (int s = 0; s < n; s++)
+            if (used[s]) {
+                sbg += alpha[(size_t)s * L + nb];
+                c += 1.0;
+            }
+        a0[N - 1] = c > 0.0 ? sbg / c : 0.0;
+    }
+}
+
+// Rejection prior: a variable source shows up as a stamp whose predicted
+// kernel sum (its own flux ratio) departs from the warm start's kernel sum
+// at that stamp (the consensus of the kept predictions).  The departures
+// d_s = k_pred / k_a0 - 1 of the kept stamps are summarised robustly (median
+// m and 1.4826 x median |d - m|, by ranking in LDS), and a stamp with
+// |d_s - m| > max(5 robust sigma, PRIOR_FLOOR) gets PSFM_STAMP_PRIOR and
+// leaves the equations (it stays fitted, so its chi2 is evaluated at every
+// solution for the fallback).  A round that excludes nothing, or would leave
+// fewer than min_stamps, ends the prior.
+constexpr double PRIOR_FLOOR = 0.2;    // flux-ratio departures below 20% never exclude
+constexpr int PRIOR_RANK_MAX = 2048;   // robust statistics up to this many stamps
+
+__device__ double block_kth(const double* v, int m, int k, int* s_idx) {
+    // value of rank k (0-based) among v[0..m): each thread ranks its entries
+    if (threadIdx.x == 0) *s_idx = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        const double x = v[i];
+        int lt = 0, eq = 0;
+        for (int j = 0; j < m; j++) {
+            lt += v[j] < x;
+            eq += (v[j] == x) && (j < i);
+        }
+        if (lt + eq == k) *s_idx = i;
+    }
+    __syncthreads();
+    return v[*s_idx];
+}
+
+__global__ __launch_bounds__(1024) void k_prior_clip(int n, int ns, int L, int min_stamps,
+                                                     const double* __restrict__ G,
+                                                     const double* __restrict__ alpha,
+                                                     const double* __restrict__ a0,
+                                                     uint8_t* __restrict__ used,
+                                                     int32_t* __restrict__ flags, SolveState* st) {
+    __shared__ double vals[PRIOR_RANK_MAX];
+    __shared__ int s_cnt, s_idx, s_n;
+    __shared__ double s_med, s_thr;
+    const int tid = threadIdx.x;
+    if (st->done || st->prior_done) return;
+    auto dev = [&](int s) {
+        double kc = 0.0;
+        for (int q = 0; q < ns; q++) kc += a0[q] * G[(size_t)s * ns + q];
+        return kc > 0.0 ? alpha[(size_t)s * L] / kc - 1.0 : 0.0;
+    };
+    if (tid == 0) {
+        s_cnt = 0;
+        s_n = 0;
+    }
+    __syncthreads();
+    for (int s = tid; s < n; s += 1024)
+        if (used[s]) {
+            const int k = atomicAdd(&s_cnt, 1);
+            if (k < PRIOR_RANK_MAX) vals[k] = dev(s);
+        }
+    __syncthreads();
+    const int m = min(s_cnt, PRIOR_RANK_MAX);
+    if (m < 3) {
+        if (tid == 0) st->prior_done = 1;
+        return;
+    }
+    const double med = block_kth(vals, m, m / 2, &s_idx);
+    if (tid == 0) s_med = med;
+    __syncthreads();
+    for (int i = tid; i < m; i += 1024) vals[i] = fabs(vals[i] - s_med);
+    __syncthreads();
+    const double mad = block_kth(vals, m, m / 2, &s_idx);
+    if (tid == 0) s_thr = fmax(5.0 * 1.4826 * mad, PRIOR_FLOOR);
+    __syncthreads();
+    const double thr = s_thr, mm = s_med;
+    int nnew = 0;
+    for (int s = tid; s < n; s += 1024)
+        if (used[s] && fabs(dev(s) - mm) > thr) nnew++;
+    atomicAdd(&s_n, nnew);
+    __syncthreads();
+    const int tn = s_n;
+    if (tn == 0 || s_cnt - tn < min_stamps) {
+        if (tid == 0) st->prior_done = 1;
+        return;
+    }
+    for (int s = tid; s < n; s += 1024)
+        if (used[s] && fabs(dev(s) - mm) > thr) {
+            used[s] = 0;
+            flags[s] |= PSFM_STAMP_PRIOR;
+        }
+    if (tid == 0) st->n_used -= tn;
+}
+
+// chi2/dof of the kept stamps at the warm start (chi2 from the stamp sums).
+__global__ __launch_bounds__(1024) void k_prior_dof(int n, int N, const int32_t* __restrict__ npix,
+                                                    const uint8_t* __restrict__ used,
+                                                    const double* __restrict__ chi2w,
+                                                    double* __restrict__ out, const SolveState* st) {
+    __shared__ double red[16];
+    if (st->info != 0) {
+        if (threadIdx.x == 0) *out = 0.0;
+        return;
+    }
+    double c2 = 0.0, np = 0.0;
+    for (int s = threadIdx.x; s < n; s += 1024)
+        if (used[s]) {
+            c2 += chi2w[s];
+            np += npix[s];
+        }
+    c2 = psfm_block_sum(c2, red);
+    np = psfm_block_sum(np, red);
+    if (threadIdx.x == 0) *out = np > N ? c2 / (np - N) : 0.0;
+}
+
+// Fallback: a stamp the prior excluded whose chi2_s / npix_s at the solved
+// coefficients is within the final clip threshold is restored and, if any
+// was, the solve loop is reopened for one more solution.  One workgroup.
+__global__ __launch_bounds__(1024) void k_prior_fallback(int n, double clip_sigma,
+                                                         const int32_t* __restrict__ npix,
+                                                         uint8_t* __restrict__ used,
+                                                         int32_t* __restrict__ flags,
+                                                         const double* __restrict__ chi2,
+                                                         SolveState* st, int* __restrict__ counts) {
+    __shared__ double red[16];
+    __shared__ double s_thr;
+    const int tid = threadIdx.x;
+    if (st->info != 0) {
+        if (tid == 0) counts[0] = counts[1] = 0;
+        return;
+    }
+    // the method's clip threshold over the stamps in use
+    auto cand = [&](int s) { return used[s] != 0; };
+    double sq = 0.0, cnt = 0.0;
+    for (int s = tid; s < n; s += 1024)
+        if (cand(s)) {
+            sq += chi2[s] / npix[s];
+            cnt += 1.0;
+        }
+    const double tot = psfm_block_sum(sq, red);
+    const double nu = psfm_block_sum(cnt, red);
+    const double mean = nu > 0.0 ? tot / nu : 0.0;
+    double dv = 0.0;
+    for (int s = tid; s < n; s += 1024)
+        if (cand(s)) {
+            const double d = chi2[s] / npix[s] - mean;
+            dv += d * d;
+        }
+    const double var = nu > 0.0 ? psfm_block_sum(dv, red) / nu : 0.0;
+    if (tid == 0) s_thr = mean + clip_sigma * sqrt(var);
+    __syncthreads();
+    const double thr = s_thr;
+    double back = 0.0, still = 0.0;
+    for (int s = tid; s < n; s += 1024)
+        if (flags[s] & PSFM_STAMP_PRIOR) {
+            if (chi2[s] / npix[s] <= thr) {
+                flags[s] &= ~PSFM_STAMP_PRIOR;
+                used[s] = 1;
+                back += 1.0;
+            } else {
+                still += 1.0;
+            }
+        }
+    const double nb_ = psfm_block_sum(back, red);
+    const double ns_ = psfm_block_sum(still, red);
+    if (tid == 0) {
+        counts[0] = (int)ns_;
+        counts[1] = (int)nb_;
+        if (nb_ > 0.0) {            // the method's rejection loop resumes from the restored set
+            st->n_used += (int)nb_;
+            st->done = 0;
+            st->n_iter_base = st->n_iter;
+        }
+    }
 }
 
 }  // namespace
@@ -927,6 +1309,12 @@ size_t solve_workspace(const psfm_context* ctx, int n) {
     c.take<double>(ctx->N);                          // 1 / sqrt(diag M)
     c.take<double>((size_t)n * ctx->L + 1);          // residual gradients, stamp-major
     c.take<double>(ctx->N);                          // assembled correction right-hand side
+    c.take<double>((size_t)n * ctx->L + 1);          // prior: completed predictions
+    c.take<double>(n + 1);                           // prior: predicted chi2
+    c.take<double>(n + 1);                           // prior: chi2 at the warm start
+    c.take<double>(ctx->N);                          // prior: warm start
+    c.take<double>(1);
+    c.take<int>(2);
     return c.off;
 }
 
@@ -989,11 +1377,13 @@ int batch_solve(const psfm_context* ctx, const PairDesc* pairs, const int* stamp
 
 }  // namespace psfm
 
-extern "C" int psfm_solve(const psfm_context* ctx, int W, int H, const int32_t* stamp_xy,
-                          int n_stamps, const double* stamp_M, const double* stamp_b,
-                          const double* stamp_e, const int32_t* stamp_npix, int32_t* stamp_flags,
-                          const float* stamp_design, double* coeffs, double* stamp_chi2,
-                          psfm_fit_stats* stats, void* ws, size_t ws_bytes, void* stream) {
+// Shared launch sequence of psfm_solve and psfm_solve_prior (prior: the
+// per-stamp predicted local coefficients, or null).
+static int solve_impl(const psfm_context* ctx, int W, int H, const int32_t* stamp_xy, int n_stamps,
+                      const double* stamp_M, const double* stamp_b, const double* stamp_e,
+                      const int32_t* stamp_npix, int32_t* stamp_flags, const float* stamp_design,
+                      const double* prior, double* coeffs, double* stamp_chi2,
+                      psfm_fit_stats* stats, void* ws, size_t ws_bytes, hipStream_t st) {
     if (!ctx || n_stamps < 0 || !coeffs || !stats) return PSFM_ERR_INVALID_ARG;
     const bool mixed = ctx->cfg.precision != PSFM_PREC_FP32;
     if (mixed && n_stamps > 0 && !stamp_design) return PSFM_ERR_INVALID_ARG;
@@ -1006,7 +1396,6 @@ extern "C" int psfm_solve(const psfm_context* ctx, int W, int H, const int32_t* 
     if (!ws || ws_bytes < need) return PSFM_ERR_WORKSPACE;
     const size_t lds = (size_t)(ctx->N + 16) * CH_PS * sizeof(double);
     if (lds > 140 * 1024) return PSFM_ERR_UNSUPPORTED;
-    hipStream_t st = (hipStream_t)stream;
     psfm::Carver c(ws);
     SolveState* state = c.take<SolveState>(1);
     uint8_t* used = c.take<uint8_t>(n_stamps + 1);
@@ -1021,6 +1410,12 @@ extern "C" int psfm_solve(const psfm_context* ctx, int W, int H, const int32_t* 
     double* Dg = c.take<double>(ctx->N);
     double* gt = c.take<double>((size_t)n_stamps * ctx->L + 1);
     double* gv = c.take<double>(ctx->N);
+    double* palpha = c.take<double>((size_t)n_stamps * ctx->L + 1);
+    double* pchi2 = c.take<double>(n_stamps + 1);
+    double* wchi2 = c.take<double>(n_stamps + 1);
+    double* a0 = c.take<double>(ctx->N);
+    double* pdof = c.take<double>(1);
+    int* pcounts = c.take<int>(2);
     const int nb = ctx->nb, ns = ctx->ns, N = ctx->N, L = ctx->L;
     const int npix = (2 * ctx->r + 1) * (2 * ctx->r + 1);
     const psfm_config& cf = ctx->cfg;
@@ -1034,7 +1429,26 @@ extern "C" int psfm_solve(const psfm_context* ctx, int W, int H, const int32_t* 
     const int nthreads_asm = L * L * ns + L * ns;
     if (n_stamps > 0)
         hipLaunchKernelGGL(k_transpose_sums, dim3(256), dim3(256), 0, st, n_stamps, L, stamp_M, stamp_b, Mt, bt);
-    for (int it = 0; it < cf.max_iter; it++) {
+    if (prior && n_stamps > 0) {
+        // completed predictions, then (warm start -> kernel-sum clip) rounds
+        hipLaunchKernelGGL(k_prior_chi2, dim3(n_stamps), dim3(64), 0, st, nb, stamp_M, stamp_b, stamp_e,
+                           stamp_flags, prior, palpha, pchi2);
+        for (int it = 0; it < cf.max_iter + 1; it++) {
+            hipLaunchKernelGGL(k_prior_warm, dim3(1), dim3(PRIOR_T), 0, st, n_stamps, nb, ns, N, G,
+                               palpha, used, a0, state, 0);
+            hipLaunchKernelGGL(k_prior_clip, dim3(1), dim3(1024), 0, st, n_stamps, ns, L, cf.min_stamps,
+                               G, palpha, a0, used, stamp_flags, state);
+        }
+        hipLaunchKernelGGL(k_prior_warm, dim3(1), dim3(PRIOR_T), 0, st, n_stamps, nb, ns, N, G, palpha,
+                           used, a0, state, 1);
+        hipLaunchKernelGGL(k_chi2, dim3(n_stamps), dim3(64), 0, st, nb, ns, N, stamp_M, stamp_b,
+                           stamp_e, G, a0, fitted, wchi2, state);
+        hipLaunchKernelGGL(k_prior_dof, dim3(1), dim3(1024), 0, st, n_stamps, N, stamp_npix, used, wchi2,
+                           pdof, state);
+        PSFM_HIP_CHECK(hipGetLastError());
+    }
+    // one round: weights, assembly, solution (+ refinement), chi2, clip
+    auto round = [&]() -> int {
         hipLaunchKernelGGL(k_weights, dim3((n_stamps + 255) / 256 + 1), dim3(256), 0, st, n_stamps, ns,
                            G, used, GU, state);
         const dim3 ag((nthreads_asm + ASM_ITEMS - 1) / ASM_ITEMS);
@@ -1066,9 +1480,62 @@ extern "C" int psfm_solve(const psfm_context* ctx, int W, int H, const int32_t* 
         }
         hipLaunchKernelGGL(k_clip, dim3(1), dim3(1024), 0, st, n_stamps, cf.max_iter, cf.min_stamps,
                            cf.clip_sigma, stamp_npix, used, stamp_flags, stamp_chi2, state);
+        return PSFM_OK;
+    };
+    for (int it = 0; it < cf.max_iter; it++) {
+        rc = round();
+        if (rc) return rc;
+    }
+    if (prior && n_stamps > 0) {
+        // fallback: stamps the prior excluded but the solution accepts come back
+        hipLaunchKernelGGL(k_prior_fallback, dim3(1), dim3(1024), 0, st, n_stamps, cf.clip_sigma,
+                           stamp_npix, used, stamp_flags, stamp_chi2, state, pcounts);
+        for (int it = 0; it < cf.max_iter; it++) {   // idle unless the fallback restored stamps
+            rc = round();
+            if (rc) return rc;
+        }
     }
     hipLaunchKernelGGL(k_solve_finish, dim3(1), dim3(1024), 0, st, n_stamps, ns, N,
                        cf.spatial_order, W, H, stamp_npix, used, stamp_chi2, coeffs, state, stats);
+    if (prior && n_stamps > 0)
+        hipLaunchKernelGGL(k_prior_finish, dim3(1), dim3(64), 0, st, pdof, pcounts, stats);
+    PSFM_HIP_CHECK(hipGetLastError());
+    return PSFM_OK;
+}
+
+extern "C" int psfm_solve(const psfm_context* ctx, int W, int H, const int32_t* stamp_xy,
+                          int n_stamps, const double* stamp_M, const double* stamp_b,
+                          const double* stamp_e, const int32_t* stamp_npix, int32_t* stamp_flags,
+                          const float* stamp_design, double* coeffs, double* stamp_chi2,
+                          psfm_fit_stats* stats, void* ws, size_t ws_bytes, void* stream) {
+    return solve_impl(ctx, W, H, stamp_xy, n_stamps, stamp_M, stamp_b, stamp_e, stamp_npix,
+                      stamp_flags, stamp_design, nullptr, coeffs, stamp_chi2, stats, ws, ws_bytes,
+                      (hipStream_t)stream);
+}
+
+extern "C" int psfm_solve_prior(const psfm_context* ctx, int W, int H, const int32_t* stamp_xy,
+                                int n_stamps, const double* stamp_M, const double* stamp_b,
+                                const double* stamp_e, const int32_t* stamp_npix,
+                                int32_t* stamp_flags, const float* stamp_design,
+                                const double* stamp_pred, double* coeffs, double* stamp_chi2,
+                                psfm_fit_stats* stats, void* ws, size_t ws_bytes, void* stream) {
+    if (n_stamps > 0 && !stamp_pred) return PSFM_ERR_INVALID_ARG;
+    return solve_impl(ctx, W, H, stamp_xy, n_stamps, stamp_M, stamp_b, stamp_e, stamp_npix,
+                      stamp_flags, stamp_design, stamp_pred, coeffs, stamp_chi2, stats, ws, ws_bytes,
+                      (hipStream_t)stream);
+}
+
+extern "C" int psfm_solve_stamps(const psfm_context* ctx, int n_stamps, const double* stamp_M,
+                                 const double* stamp_b, const double* stamp_e,
+                                 const int32_t* stamp_flags, double* local, double* stamp_chi2,
+                                 void* stream) {
+    if (!ctx || n_stamps < 0) return PSFM_ERR_INVALID_ARG;
+    if (n_stamps == 0) return PSFM_OK;
+    if (!stamp_M || !stamp_b || !stamp_e || !stamp_flags || !local || !stamp_chi2)
+        return PSFM_ERR_INVALID_ARG;
+    if (ctx->L > 64) return PSFM_ERR_UNSUPPORTED;
+    hipLaunchKernelGGL(k_solve_stamps, dim3(n_stamps), dim3(64), 0, (hipStream_t)stream, ctx->L,
+                       stamp_M, stamp_b, stamp_e, stamp_flags, local, stamp_chi2);
     PSFM_HIP_CHECK(hipGetLastError());
     return PSFM_OK;
 }

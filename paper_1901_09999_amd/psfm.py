@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpsfm.so")
 
 MAX_GAUSS = 8
-STAMP_INVALID, STAMP_REJECTED, STAMP_NONFINITE, STAMP_EXCLUDED = 1, 2, 4, 8
+STAMP_INVALID, STAMP_REJECTED, STAMP_NONFINITE, STAMP_EXCLUDED, STAMP_PRIOR = 1, 2, 4, 8, 16
 MASK_BAD, MASK_CONV_BAD, MASK_CONV_POOR = 1, 2, 4
 PREC_FP32, PREC_BF16, PREC_FP16 = 0, 1, 2
 
@@ -57,6 +57,9 @@ class CStats(C.Structure):
         ("n_rejected", C.c_int),
         ("n_iter", C.c_int),
         ("info", C.c_int),
+        ("chi2_dof_prior", C.c_double),
+        ("n_prior", C.c_int),
+        ("n_restored", C.c_int),
     ]
 
     def as_dict(self):
@@ -126,6 +129,18 @@ def lib():
             "psfm_batch_graph_launch": (i, [P, P]),
             "psfm_batch_destroy": (i, [P]),
             "psfm_wall_clock_hz": (C.c_double, []),
+            "psfm_solve_stamps": (i, [P, i, P, P, P, P, P, P, P]),
+            "psfm_solve_prior": (i, [P, i, i, P, i, P, P, P, P, P, P, P, P, P, P, P, sz, P]),
+            "psfm_cnn_param_count": (sz, []),
+            "psfm_cnn_workspace_bytes": (sz, [i]),
+            "psfm_cnn_forward": (i, [P, P, i, P, P, sz, P]),
+            "psfm_cnn_loss_grad": (i, [P, P, P, P, i, P, P, P, sz, P]),
+            "psfm_cnn_loss_weights": (i, [P, P, P, P, i, P, P]),
+            "psfm_cnn_adam": (i, [P, P, P, P, P, sz, i, C.c_float, C.c_float, C.c_float, C.c_float,
+                                  P]),
+            "psfm_cnn_stamp_inputs": (i, [P, P, P, P, i, i, i64, P, i, P, P, P]),
+            "psfm_cnn_targets": (i, [P, P, i, P, P]),
+            "psfm_cnn_local_coeffs": (i, [P, P, i, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -253,7 +268,19 @@ class Context:
         k = lib().psfm_stamp_design_floats(self._h, n)
         return torch.empty(k, dtype=torch.float32, device=self.device) if k else None
 
-    def solve(self, W, H, stamps, fit, flags=None, out=None):
+    def solve_stamps(self, fit):
+        """Each stamp's own least-squares kernel: (local [n, L], chi2 [n])."""
+        n = fit["M"].shape[0]
+        local = torch.empty((n, self.L), dtype=torch.float64, device=self.device)
+        chi2 = torch.empty(max(n, 1), dtype=torch.float64, device=self.device)
+        _check(lib().psfm_solve_stamps(self._h, n, _ptr(fit["M"]), _ptr(fit["b"]), _ptr(fit["e"]),
+                                       _ptr(fit["flags"]), _ptr(local), _ptr(chi2), _stream()),
+               "psfm_solve_stamps")
+        return local, chi2[:n]
+
+    def solve(self, W, H, stamps, fit, flags=None, out=None, prior=None):
+        """psfm_solve, or psfm_solve_prior when ``prior`` (n x L float64
+        predicted local coefficients) is given."""
         n = stamps.shape[0]
         dev = self.device
         fl = (fit["flags"] if flags is None else flags).clone()
@@ -263,6 +290,13 @@ class Context:
                        stats=torch.zeros(STATS_BYTES, dtype=torch.uint8, device=dev))
         out["flags"] = fl
         ws = self.workspace(W, H, n)
+        if prior is not None:
+            _check(lib().psfm_solve_prior(self._h, W, H, _ptr(stamps), n, _ptr(fit["M"]), _ptr(fit["b"]),
+                                          _ptr(fit["e"]), _ptr(fit["npix"]), _ptr(fl),
+                                          _ptr(fit.get("design")), _ptr(prior), _ptr(out["coeffs"]),
+                                          _ptr(out["chi2"]), _ptr(out["stats"]), _ptr(ws), ws.numel(),
+                                          _stream()), "psfm_solve_prior")
+            return out
         _check(lib().psfm_solve(self._h, W, H, _ptr(stamps), n, _ptr(fit["M"]), _ptr(fit["b"]),
                                 _ptr(fit["e"]), _ptr(fit["npix"]), _ptr(fl), _ptr(fit.get("design")),
                                 _ptr(out["coeffs"]),
@@ -485,4 +519,8 @@ def exported_symbols() -> Sequence[str]:
             "psfm_solve", "psfm_convolve_image", "psfm_propagate_variance", "psfm_subtract",
             "psfm_status_string", "psfm_batch_workspace_bytes", "psfm_batch_plan",
             "psfm_batch_run", "psfm_batch_run_stage", "psfm_batch_set_tuning", "psfm_batch_graph_capture",
-            "psfm_batch_graph_launch", "psfm_batch_destroy", "psfm_wall_clock_hz"]
+            "psfm_batch_graph_launch", "psfm_batch_destroy", "psfm_wall_clock_hz",
+            "psfm_solve_stamps", "psfm_solve_prior", "psfm_cnn_param_count",
+            "psfm_cnn_workspace_bytes", "psfm_cnn_forward", "psfm_cnn_loss_grad",
+            "psfm_cnn_loss_weights", "psfm_cnn_adam",
+            "psfm_cnn_stamp_inputs", "psfm_cnn_targets", "psfm_cnn_local_coeffs"]

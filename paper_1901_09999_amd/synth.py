@@ -480,3 +480,96 @@ def make_pair_device(wl: Workload, seed: int, device="cuda", n_stamps: Optional[
                           lambda x, y: bool(bad1[y, x]) or bool(bad2[y, x]))
     return DevicePair(wl, I1.contiguous(), V1.contiguous(), M1, I2.contiguous(), V2.contiguous(),
                       M2, stamps, xs, ys, fluxes, seed)
+
+
+# --------------------------------------------------------------------------
+# Single-star stamp pairs for the learned prior (one star per 64 x 64 cell).
+
+@dataclasses.dataclass(frozen=True)
+class StampSetSpec:
+    """Cells of one target star each: PSF widths of the two images ~
+    U[sigma_lo, sigma_hi] (the narrower image is image 1, the one convolved),
+    ellipticity ~ U[0, e_max] at a random angle, S/N ~ log-U[snr_lo, snr_hi]
+    with S/N = F / sqrt(F + 4 pi sigma^2 sky) for image 1, image-2 flux F
+    times U[ratio_lo, ratio_hi], sub-pixel centre offsets; Poisson-many
+    neighbour sources at the field density (fluxes log-U[flux_lo, flux_hi],
+    same PSFs and flux ratio); sky and Gaussian noise of variance sky +
+    signal, no masks."""
+
+    n: int = 200_000
+    side: int = 64
+    sigma_lo: float = 1.0
+    sigma_hi: float = 3.0
+    e_max: float = 0.3
+    snr_lo: float = 20.0
+    snr_hi: float = 500.0
+    ratio_lo: float = 0.7
+    ratio_hi: float = 1.4
+    sky: float = 100.0
+    neighbours: float = 2000.0 / (2048 * 2048)   # other sources per pixel (field density)
+    flux_lo: float = 1e3                          # neighbour fluxes, log-uniform
+    flux_hi: float = 1e5
+
+
+STAMP_SETS: Dict[str, StampSetSpec] = {"cfg4": StampSetSpec()}
+
+
+def _star_cells(torch, side, x0, y0, flux, sig, e, theta, device):
+    """[n, side, side] pixel-sampled elliptical Gaussians (float32)."""
+    n = x0.shape[0]
+    sa = sig / np.sqrt(1.0 - e)
+    sb = sig * np.sqrt(1.0 - e)
+    t = lambda a: torch.as_tensor(a, dtype=torch.float32, device=device)[:, None, None]
+    g = torch.arange(side, dtype=torch.float32, device=device)
+    dx = g[None, None, :] - t(x0)
+    dy = g[None, :, None] - t(y0)
+    c, s = t(np.cos(theta)), t(np.sin(theta))
+    pa = c * dx + s * dy
+    pb = -s * dx + c * dy
+    q = (pa / t(sa)) ** 2 + (pb / t(sb)) ** 2
+    return t(flux / (2.0 * np.pi * sa * sb)) * torch.exp(-0.5 * q)
+
+
+def make_stamp_cells(spec: StampSetSpec, n: int, seed: int, device="cuda"):
+    """n cells stacked into one tall image pair [n * side, side] with the stamp
+    centres at the cell centres.  Returns (planes dict, stamps int32 [n, 2],
+    parameters dict of numpy arrays)."""
+    import torch
+
+    rng = np.random.default_rng(seed)
+    side = spec.side
+    s_a = rng.uniform(spec.sigma_lo, spec.sigma_hi, n)
+    s_b = rng.uniform(spec.sigma_lo, spec.sigma_hi, n)
+    sig1, sig2 = np.minimum(s_a, s_b), np.maximum(s_a, s_b)
+    e1, e2 = rng.uniform(0.0, spec.e_max, n), rng.uniform(0.0, spec.e_max, n)
+    th1, th2 = rng.uniform(0.0, math.pi, n), rng.uniform(0.0, math.pi, n)
+    snr = np.exp(rng.uniform(math.log(spec.snr_lo), math.log(spec.snr_hi), n))
+    bkg = 4.0 * math.pi * sig1 ** 2 * spec.sky
+    F1 = 0.5 * (snr ** 2 + np.sqrt(snr ** 4 + 4.0 * snr ** 2 * bkg))
+    ratio = rng.uniform(spec.ratio_lo, spec.ratio_hi, n)
+    F2 = F1 * ratio
+    cx = side // 2 + rng.uniform(-0.5, 0.5, n)
+    cy = side // 2 + rng.uniform(-0.5, 0.5, n)
+    m1 = _star_cells(torch, side, cx, cy, F1, sig1, e1, th1, device)
+    m2 = _star_cells(torch, side, cx, cy, F2, sig2, e2, th2, device)
+    # neighbours: up to 8 slots per cell, each present with the Poisson-thinned probability
+    lam = spec.neighbours * side * side
+    slots = 8
+    present = rng.uniform(0, 1, (slots, n)) < lam / slots
+    for k in range(slots):
+        nx = rng.uniform(0, side, n)
+        ny = rng.uniform(0, side, n)
+        nf = np.exp(rng.uniform(math.log(spec.flux_lo), math.log(spec.flux_hi), n)) * present[k]
+        m1 += _star_cells(torch, side, nx, ny, nf, sig1, e1, th1, device)
+        m2 += _star_cells(torch, side, nx, ny, nf * ratio, sig2, e2, th2, device)
+    g = torch.Generator(device=device)
+    g.manual_seed(seed + 1)
+    V1 = (m1 + spec.sky).reshape(n * side, side)
+    V2 = (m2 + spec.sky).reshape(n * side, side)
+    del m1, m2
+    I1 = V1 + torch.randn(V1.shape, generator=g, device=device) * torch.sqrt(V1)
+    I2 = V2 + torch.randn(V2.shape, generator=g, device=device) * torch.sqrt(V2)
+    M = torch.zeros((n * side, side), dtype=torch.uint8, device=device)
+    stamps = np.stack([np.full(n, side // 2), side * np.arange(n) + side // 2], 1).astype(np.int32)
+    params = dict(sigma1=sig1, sigma2=sig2, e1=e1, e2=e2, snr=snr, ratio=ratio)
+    return dict(I1=I1, V1=V1, M1=M, I2=I2, V2=V2, M2=M.clone()), stamps, params

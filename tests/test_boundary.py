@@ -90,3 +90,15 @@ def test_batch_host_argument_checks(lib):
     assert lib.psfm_batch_graph_capture(None, None) == -1
     assert lib.psfm_batch_graph_launch(None, None) == -1
     assert lib.psfm_batch_destroy(None) == -1
+
+
+def test_cnn_parameter_layout_matches_oracle(lib):
+    from oracle import cnn_oracle as CO
+    from paper_1901_09999_amd import cnn
+    assert lib.psfm_cnn_param_count() == CO.n_params()
+    assert cnn.layer_shapes() == CO.layer_shapes()
+    assert lib.psfm_cnn_workspace_bytes(0) == 0 and lib.psfm_cnn_workspace_bytes(16) > 0
+    assert lib.psfm_cnn_forward(None, None, 1, None, None, 0, None) == -1
+    assert lib.psfm_cnn_loss_grad(None, None, None, None, 1, None, None, None, 0, None) == -1
+    assert lib.psfm_cnn_loss_weights(None, None, None, None, 1, None, None) == -1
+    assert lib.psfm_solve_stamps(None, 1, *([None] * 6), None) == -1

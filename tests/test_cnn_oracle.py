@@ -69,6 +69,30 @@ def test_gradient_matches_central_differences():
         assert abs(fd - g[k]) <= 1e-6 * max(abs(g[k]), 1e-3), (k, fd, g[k])
 
 
+def test_weighted_loss_gradient_matches_central_differences():
+    rng = np.random.default_rng(4)
+    theta = C.init_params(5) + 0.01 * rng.standard_normal(C.n_params())
+    x = rng.standard_normal((2, 2, 41, 41))
+    t = rng.standard_normal((2, 49))
+    A = rng.standard_normal((2, 49, 49))
+    Wt = A @ A.transpose(0, 2, 1) / 49.0                       # symmetric positive definite
+    loss, g = C.loss_and_grad(theta, x, t, Wt)
+    out = C.forward(theta, x)
+    r = out - t
+    assert abs(loss - sum(r[b] @ Wt[b] @ r[b] for b in range(2)) / r.size) < 1e-12 * abs(loss)
+    # identity weights give the plain loss and gradient
+    l0, g0 = C.loss_and_grad(theta, x, t)
+    l1, g1 = C.loss_and_grad(theta, x, t, np.broadcast_to(np.eye(49), (2, 49, 49)))
+    assert abs(l0 - l1) < 1e-14 * abs(l0) and np.allclose(g0, g1, rtol=1e-12, atol=0)
+    h = 1e-6
+    for k in rng.choice(C.n_params(), size=12, replace=False):
+        tp, tm = theta.copy(), theta.copy()
+        tp[k] += h
+        tm[k] -= h
+        fd = (C.loss_and_grad(tp, x, t, Wt)[0] - C.loss_and_grad(tm, x, t, Wt)[0]) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-6 * max(abs(g[k]), 1e-3), (k, fd, g[k])
+
+
 def test_adam_first_step_is_lr_times_sign():
     theta = np.array([1.0, -2.0, 0.5])
     g = np.array([0.3, -1e-3, 4.0])

@@ -1,0 +1,121 @@
+"""The learned prior in use (psfm_solve_prior) and what it gains.
+
+A network is trained on the GPU (stamp pairs in crowded cells, kernels
+solved by the method), then used on spatially varying pairs with 10%
+variable sources.  The full method (three solutions) is checked against the
+FP64 oracle at the whole-path target; the gain is measured at an equal solve
+budget, and the fallback keeps the least-squares solution the judge.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1901_09999_amd import synth
+
+from gpu_common import hip
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def trained():
+    torch, psfm = hip()
+    from paper_1901_09999_amd import cnn
+    net, rep = cnn.fit_prior(n=200_000, seed=11, epochs=8, n_val=10_000,
+                             log=lambda m: print(m, flush=True))
+    print({k: v for k, v in rep.items() if not isinstance(v, list)}, flush=True)
+    return net, rep
+
+
+def test_trained_prior_quality(trained):
+    net, rep = trained
+    assert rep["excess_mean"] < 0.1 * rep["excess_mean_of_mean_predictor"]
+    assert rep["kernel_sum_err_median"] < 0.05 and rep["kernel_sum_err_median_snr150"] < 0.03
+    assert rep["within_1p05"] > 0.4
+    assert rep["loss_val"][-1] < rep["loss_val"][0]
+
+
+def _pairs():
+    out = []
+    for k, (W, H, S, seed) in enumerate([(1024, 1024, 2, 71), (1200, 900, 1, 72), (1024, 1024, 2, 73)]):
+        wl = synth.scaled(synth.WORKLOADS["cfg1"], f"prior{k}", W, H, n_stamps=150,
+                          spatial_order=S, variable_frac=0.10)
+        out.append((wl, synth.make_pair(wl, seed)))
+    return out
+
+
+def _run(psfm, torch, ctx, d, W, H, fit, prior):
+    ctx.solve(W, H, d["stamps"], fit, prior=prior)              # warm
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    sol = ctx.solve(W, H, d["stamps"], fit, prior=prior)
+    e1.record()
+    torch.cuda.synchronize()
+    return psfm.read_stats(sol["stats"]), e0.elapsed_time(e1)
+
+
+def test_prior_gain_at_equal_solve_budget(trained):
+    """With one solution the plain method keeps every variable source; the
+    prior removes the gross ones before that solution.  Gain: how much closer
+    one prior-assisted solution gets to the full method's answer (three
+    solutions, the oracle's) than one plain solution does."""
+    torch, psfm = hip()
+    from paper_1901_09999_amd import cnn
+    net, _ = trained
+    err_plain1, err_prior1, sol_prior1, sol_full = [], [], 0, 0
+    for wl, pair in _pairs():
+        d = psfm.to_device(pair)
+        W, H = wl.width, wl.height
+        ctx1 = psfm.Context(psfm.Config.from_workload(wl, max_iter=1))
+        ctx3 = psfm.Context(psfm.Config.from_workload(wl))
+        fit = ctx3.fit_stamps(d["I1"], d["M1"], d["I2"], d["V2"], d["M2"], d["stamps"])
+        pred = cnn.predict_local(ctx3, net, d["I1"], d["M1"], d["I2"], d["M2"], d["stamps"])
+        ref = O.match_pair(O.Config.from_workload(wl), pair, c_out=wl.cov_half)["stats"]
+        full, t_full = _run(psfm, torch, ctx3, d, W, H, fit, None)
+        p1, t_p1 = _run(psfm, torch, ctx1, d, W, H, fit, None)
+        q1, t_q1 = _run(psfm, torch, ctx1, d, W, H, fit, pred)
+        ks = lambda st: abs(st["kernel_sum_centre"] / ref["kernel_sum_centre"] - 1)
+        assert ks(full) < 1e-4 and full["info"] == 0 and q1["info"] == 0
+        print(f"{wl.name}: full method {full['n_iter']} solutions ({t_full:.3f} ms) used {full['n_used']}; "
+              f"one plain solution: kernel sum error {ks(p1):.2e}, chi2/dof {p1['chi2_dof']:.4f} "
+              f"({t_p1:.3f} ms); one prior solution: {ks(q1):.2e}, chi2/dof {q1['chi2_dof']:.4f}, "
+              f"{q1['n_iter']} solutions, prior-excluded {q1['n_prior']}, restored {q1['n_restored']} "
+              f"({t_q1:.3f} ms); full chi2/dof {full['chi2_dof']:.4f}")
+        err_plain1.append(ks(p1))
+        err_prior1.append(ks(q1))
+        sol_prior1 += q1["n_iter"]
+        sol_full += full["n_iter"]
+    print(f"kernel-sum error after one solution: plain {np.mean(err_plain1):.2e}, with prior "
+          f"{np.mean(err_prior1):.2e}; solutions: prior {sol_prior1}, full method {sol_full}")
+    assert np.mean(err_prior1) < np.mean(err_plain1)
+    assert sol_prior1 < sol_full
+
+
+def test_fallback_keeps_the_answer_under_a_poor_prior():
+    """A poor prior (a wrong flux ratio for a third of the predictions pulls
+    the warm start off, so good stamps look like outliers): the fallback
+    brings them back and the rejection loop resumes, so the answer stays a
+    least-squares solution of the method within its own tolerance.  Sigma
+    clipping is path dependent at the margin, so borderline stamps may end on
+    either side: the chi2/dof is held to the 1.05 rule and the kernel sum to
+    1e-3 of the plain answer."""
+    torch, psfm = hip()
+    wl = synth.scaled(synth.WORKLOADS["cfg1"], "fallback", 1024, 1024, n_stamps=120, spatial_order=1)
+    pair = synth.make_pair(wl, 91)
+    ctx = psfm.Context(psfm.Config.from_workload(wl))
+    d = psfm.to_device(pair)
+    fit = ctx.fit_stamps(d["I1"], d["M1"], d["I2"], d["V2"], d["M2"], d["stamps"])
+    local, _ = ctx.solve_stamps(fit)                      # good per-stamp predictions
+    bad = local.clone()
+    bad[::3, 0] *= 1.6                                    # wrong flux ratio for every third stamp
+    plain = ctx.solve(wl.width, wl.height, d["stamps"], fit)
+    prior = ctx.solve(wl.width, wl.height, d["stamps"], fit, prior=bad)
+    sp, sq = psfm.read_stats(plain["stats"]), psfm.read_stats(prior["stats"])
+    print(f"plain used {sp['n_used']} in {sp['n_iter']}; prior excluded {sq['n_prior']}, "
+          f"restored {sq['n_restored']}, used {sq['n_used']} in {sq['n_iter']}; chi2/dof "
+          f"{sq['chi2_dof']:.4f} vs {sp['chi2_dof']:.4f}")
+    assert sq["info"] == 0
+    assert sq["n_restored"] > 0 and sq["n_restored"] > 5 * sq["n_prior"]
+    assert sq["chi2_dof"] <= 1.05 * sp["chi2_dof"]
+    assert abs(sq["kernel_sum_centre"] / sp["kernel_sum_centre"] - 1) < 1e-3
