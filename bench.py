@@ -16,9 +16,11 @@ variance map and a 21 x 21 covariance pseudo-matrix.
 HIP graph; also reports the p50 / p99 completion latency of the pairs.
 
 Prints one JSON line.  `value` is pixels matched per second (Mpix/s).
-`roofline` is for the dominant kernel (the image convolution), timed with HIP
-events on the stream it runs on; `cpu_baseline` is the FP64 oracle on the
-host's cores on a bounded sample of the same workload.
+`roofline` is for the kernel with the largest share of the step (the FP64
+Cholesky at these system sizes; `roofline_other` holds the image
+convolution), each timed with HIP events on the stream it runs on; for the
+batch, the fused convolution/difference kernel.  `cpu_baseline` is the FP64
+oracle on the host's cores on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -35,6 +37,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP32_VALU_PEAK_TFLOPS = 157.3     # MI355X published FP32 vector peak (packed)
+FP64_PEAK_TFLOPS = 78.6           # MI355X published FP64 vector and matrix peak
 HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
 METRIC = "Mpix/s PSF-matched subtraction (fit+convolve), plain vs mixed/learned @χ² tol"
@@ -53,6 +56,8 @@ def parse():
     ap.add_argument("--refine", type=int, default=None, help="refinement steps of 16-bit modes")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip timing the other fit arithmetic beside the reported one")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (calibrates HBM counters)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="bound on the oracle's timed sample")
     return ap.parse_args()
@@ -241,6 +246,14 @@ def main():
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a HIP device")
+    if args.copy_mb > 0:
+        src = torch.empty(args.copy_mb << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)             # one plain elementwise kernel: read N, write N
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.copy_mb} MiB read + {args.copy_mb} MiB written")
+        del src, dst
     if args.workload in synth.BATCHES:
         return bench_batch(args, torch, psfm, synth)
     wl = synth.WORKLOADS[args.workload]
@@ -300,16 +313,49 @@ def main():
     ms_per_step, stage, gpu_ms, stats = (main_run["ms_per_step"], main_run["stage"],
                                          main_run["gpu_ms"], main_run["stats"])
 
-    # roofline of the dominant kernel: the image convolution (one launch per step)
+    # rooflines: the FP64 Cholesky (one per solution, latency-bound) and the
+    # image convolution (one launch per step, FP32 VALU-bound)
     conv_us = stage[2] * 1e3
     T = (2 * wl.kernel_half + 1) ** 2
     flops = 2.0 * T * W * H
     achieved = flops / (conv_us * 1e-6) / 1e12
     traffic = measured_traffic(os.path.join(ROOT, "paper_1901_09999_amd", "csrc", "convolve.hip"))
-    roof = dict(kernel="k_conv_tile (image, MODE 0)", bound="alu", achieved=round(achieved, 2),
-                peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s", frac=round(achieved / FP32_VALU_PEAK_TFLOPS, 4),
-                traffic=traffic, avg_launch_us=round(conv_us, 2),
-                algorithmic_flops_per_launch=flops)
+    roof_conv = dict(kernel="k_conv_tile<h, 0> (image convolution)", bound="alu",
+                     achieved=round(achieved, 2), peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s",
+                     frac=round(achieved / FP32_VALU_PEAK_TFLOPS, 4), traffic=traffic,
+                     avg_launch_us=round(conv_us, 2), algorithmic_flops_per_launch=flops,
+                     launches_per_step=1)
+    Nu = wl.n_unknowns
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    A = torch.randn((Nu, Nu), generator=g, dtype=torch.float64, device="cuda")
+    Mspd = (A @ A.T + Nu * torch.eye(Nu, dtype=torch.float64, device="cuda")).contiguous()
+    bvec = torch.ones(Nu, dtype=torch.float64, device="cuda")
+    xw, infow = torch.empty_like(bvec), torch.zeros(1, dtype=torch.int32, device="cuda")
+    cws = torch.empty(int(psfm.lib().psfm_cholesky_workspace_bytes(Nu)), dtype=torch.uint8, device="cuda")
+    for _ in range(3):
+        psfm.cholesky_solve(Mspd, bvec, xw, infow, cws)
+    reps = 20
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        psfm.cholesky_solve(Mspd, bvec, xw, infow, cws)
+    e1.record()
+    torch.cuda.synchronize()
+    chol_us = e0.elapsed_time(e1) * 1e3 / reps
+    chol_flops = Nu ** 3 / 3.0 + 2.0 * Nu ** 2
+    chol_per_step = stats["n_iter"]
+    roof_chol = dict(kernel=f"k_cholesky<true> (FP64 equilibrated Cholesky + substitutions, N={Nu})",
+                     bound="mfma", achieved=round(chol_flops / (chol_us * 1e-6) / 1e12, 4),
+                     peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
+                     frac=round(chol_flops / (chol_us * 1e-6) / 1e12 / FP64_PEAK_TFLOPS, 6),
+                     traffic=None, avg_launch_us=round(chol_us, 2),
+                     algorithmic_flops_per_launch=chol_flops, launches_per_step=chol_per_step)
+    share_chol = chol_per_step * chol_us / (gpu_ms * 1e3)
+    share_conv = conv_us / (gpu_ms * 1e3)
+    roof, roof_other = (roof_chol, roof_conv) if share_chol >= share_conv else (roof_conv, roof_chol)
+    roof["share_of_step"] = round(max(share_chol, share_conv), 3)
+    roof_other["share_of_step"] = round(min(share_chol, share_conv), 3)
 
     out = {
         "metric": METRIC,
@@ -337,6 +383,7 @@ def main():
         "fit": {"chi2_dof": stats["chi2_dof"], "kernel_sum_centre": stats["kernel_sum_centre"],
                 "n_used": stats["n_used"], "n_iter": stats["n_iter"]},
         "roofline": roof,
+        "roofline_other": roof_other,
     }
     if other is not None:
         o = other[1]

@@ -217,6 +217,19 @@ int psfm_solve(const psfm_context* ctx, int W, int H, const int32_t* stamp_xy, i
                size_t ws_bytes, void* stream);
 
 /*
+ * The dense solve of psfm_solve on its own (Section 2: the normal equations
+ * M a = b are symmetric positive definite): symmetric equilibration
+ * D = diag(M)^-1/2, FP64 Cholesky of D M D in one workgroup (32-column
+ * panels in LDS, FP64 MFMA trailing updates), forward and back substitution.
+ * M: n x n float64 row-major (only the lower triangle is read; not
+ * modified), b, x: n float64, info (device int): 0, or the 1-based pivot
+ * that was not positive (x then undefined).  n <= 496.
+ */
+size_t psfm_cholesky_workspace_bytes(int n);
+int psfm_cholesky_solve(int n, const double* M, const double* b, double* x, int* info, void* ws,
+                        size_t ws_bytes, void* stream);
+
+/*
  * Each stamp's own least-squares kernel (no spatial terms): M_s a = b_s
  * solved in FP64 (equilibrated Cholesky) for every stamp; local (n x L
  * float64) receives a, stamp_chi2 receives e_s - 2 a^T b_s + a^T M_s a.

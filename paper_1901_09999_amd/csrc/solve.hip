@@ -1,16 +1,19 @@
 // Assembly, solution and rejection (Section 2; Sections 3.3, 3.5, 3.6).
 //
 // Stream-ordered loop of at most max_iter rounds, each made of
-//   k_assemble  - M[(i,s),(j,t)] = sum_used g_s g_t M_s[i][j] (FP64, many
-//                 workgroups, one thread per (i, j, s));
-//   k_cholesky  - one 1024-thread workgroup: symmetric equilibration,
+//   k_weights / k_assemble - M[(i,s),(j,t)] = sum_used g_s g_t M_s[i][j]
+//                 (FP64, stamp-major sums, one item per (i, j, s));
+//   k_cholesky  - one 512-thread workgroup: symmetric equilibration,
 //                 blocked right-looking Cholesky (32-column panels in LDS,
-//                 trailing update read-modify-write in L2-resident
-//                 workspace), forward and back substitution;
-//   k_chi2_clip - per-stamp chi2 from the stamp sums and the sigma-clip.
+//                 FP64 MFMA trailing update read-modify-write in the
+//                 L2-resident workspace), forward and back substitution;
+//   16-bit modes: k_resid / k_assemble_vec / k_resolve refinement steps;
+//   k_chi2 + k_clip - per-stamp chi2 (from the stamp sums, or from pixels
+//                 in the 16-bit modes) and the sigma-clip.
 // A device-side state word ends the loop early (converged, or failed);
 // later kernels of the unrolled loop then return at once, so the host never
-// waits on the device.
+// waits on the device.  Also here: the batched forms (one workgroup per pair
+// for the Cholesky), the per-stamp solves and the learned-prior kernels.
 #include "internal.h"
 
 namespace {
@@ -559,12 +562,31 @@ __device__ __forceinline__ void cholesky_body(int N, double* __restrict__ A, con
     for (int i = tid; i < N; i += CH_THREADS) x[i] = Dq[i] * zb[i];
 }
 
+// OWN: the standalone solve (psfm_cholesky_solve) copies the lower triangle
+// of M into the work matrix first and reports the pivot status; a separate
+// instantiation, so that profiles tell the two uses apart.
+template <bool OWN>
 __global__ __launch_bounds__(CH_THREADS) void k_cholesky(int N, double* __restrict__ A,
                                                          const double* __restrict__ b,
                                                          double* __restrict__ x,
                                                          double* __restrict__ ILg,
-                                                         double* __restrict__ Dg, SolveState* st) {
+                                                         double* __restrict__ Dg, SolveState* st,
+                                                         const double* __restrict__ Msrc,
+                                                         int* __restrict__ info) {
+    if (OWN) {
+        for (int i = threadIdx.x >> 5; i < N; i += CH_THREADS / 32)
+            for (int j = threadIdx.x & 31; j <= i; j += 32) A[(size_t)i * N + j] = Msrc[(size_t)i * N + j];
+        if (threadIdx.x == 0) {
+            st->done = 0;
+            st->info = 0;
+        }
+        __syncthreads();
+    }
     cholesky_body(N, A, b, x, ILg, Dg, st);
+    if (OWN) {
+        __syncthreads();
+        if (threadIdx.x == 0) *info = st->info;
+    }
 }
 
 // Batched: one workgroup per pair, all solved concurrently.
@@ -1321,7 +1343,9 @@ size_t solve_workspace(const psfm_context* ctx, int n) {
 int solve_lds_grant(size_t lds) {
     static size_t granted = 0;      // dynamic LDS granted so far (both forms)
     if (lds > granted) {
-        PSFM_HIP_CHECK(hipFuncSetAttribute((const void*)k_cholesky,
+        PSFM_HIP_CHECK(hipFuncSetAttribute((const void*)k_cholesky<false>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        PSFM_HIP_CHECK(hipFuncSetAttribute((const void*)k_cholesky<true>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         PSFM_HIP_CHECK(hipFuncSetAttribute((const void*)k_cholesky_b,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -1460,8 +1484,8 @@ static int solve_impl(const psfm_context* ctx, int W, int H, const int32_t* stam
 #undef PSFM_ASM_CASE
             default: return PSFM_ERR_UNSUPPORTED;
         }
-        hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(CH_THREADS), lds, st, N, M, b, coeffs, ILg,
-                           mixed ? Dg : nullptr, state);
+        hipLaunchKernelGGL(k_cholesky<false>, dim3(1), dim3(CH_THREADS), lds, st, N, M, b, coeffs, ILg,
+                           mixed ? Dg : nullptr, state, nullptr, nullptr);
         if (mixed && n_stamps > 0) {
             // 16-bit sums: refine against FP32 pixel residuals, then chi2 from pixels
             for (int k = 0; k < cf.refine; k++) {
@@ -1523,6 +1547,34 @@ extern "C" int psfm_solve_prior(const psfm_context* ctx, int W, int H, const int
     return solve_impl(ctx, W, H, stamp_xy, n_stamps, stamp_M, stamp_b, stamp_e, stamp_npix,
                       stamp_flags, stamp_design, stamp_pred, coeffs, stamp_chi2, stats, ws, ws_bytes,
                       (hipStream_t)stream);
+}
+
+extern "C" size_t psfm_cholesky_workspace_bytes(int n) {
+    if (n < 1) return 0;
+    psfm::Carver c(nullptr);
+    c.take<SolveState>(1);
+    c.take<double>((size_t)n * n);
+    c.take<double>(psfm::solve_il_doubles(n));
+    return c.off + 256;
+}
+
+extern "C" int psfm_cholesky_solve(int n, const double* M, const double* b, double* x, int* info,
+                                   void* ws, size_t ws_bytes, void* stream) {
+    if (n < 1 || !M || !b || !x || !info) return PSFM_ERR_INVALID_ARG;
+    if (n > CH_NMAX) return PSFM_ERR_UNSUPPORTED;
+    if (!ws || ws_bytes < psfm_cholesky_workspace_bytes(n)) return PSFM_ERR_WORKSPACE;
+    const size_t lds = psfm::solve_lds_bytes(n);
+    int rc = psfm::solve_lds_grant(lds);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    psfm::Carver c(ws);
+    SolveState* state = c.take<SolveState>(1);
+    double* A = c.take<double>((size_t)n * n);
+    double* ILg = c.take<double>(psfm::solve_il_doubles(n));
+    hipLaunchKernelGGL(k_cholesky<true>, dim3(1), dim3(CH_THREADS), lds, st, n, A, b, x, ILg, nullptr,
+                       state, M, info);
+    PSFM_HIP_CHECK(hipGetLastError());
+    return PSFM_OK;
 }
 
 extern "C" int psfm_solve_stamps(const psfm_context* ctx, int n_stamps, const double* stamp_M,

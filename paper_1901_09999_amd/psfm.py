@@ -130,6 +130,8 @@ def lib():
             "psfm_batch_destroy": (i, [P]),
             "psfm_wall_clock_hz": (C.c_double, []),
             "psfm_solve_stamps": (i, [P, i, P, P, P, P, P, P, P]),
+            "psfm_cholesky_workspace_bytes": (sz, [i]),
+            "psfm_cholesky_solve": (i, [i, P, P, P, P, P, sz, P]),
             "psfm_solve_prior": (i, [P, i, i, P, i, P, P, P, P, P, P, P, P, P, P, P, sz, P]),
             "psfm_cnn_param_count": (sz, []),
             "psfm_cnn_workspace_bytes": (sz, [i]),
@@ -500,6 +502,19 @@ class Batch:
         return read_stats(self.out[k]["stats"])
 
 
+def cholesky_solve(M: torch.Tensor, b: torch.Tensor, x: Optional[torch.Tensor] = None,
+                   info: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None):
+    """psfm_cholesky_solve on device tensors (M n x n, b n, float64)."""
+    n = b.numel()
+    x = torch.empty_like(b) if x is None else x
+    info = torch.zeros(1, dtype=torch.int32, device=b.device) if info is None else info
+    if ws is None:
+        ws = torch.empty(int(lib().psfm_cholesky_workspace_bytes(n)), dtype=torch.uint8, device=b.device)
+    _check(lib().psfm_cholesky_solve(n, _ptr(M), _ptr(b), _ptr(x), _ptr(info), _ptr(ws), ws.numel(),
+                                     _stream()), "psfm_cholesky_solve")
+    return x, info
+
+
 def read_stats(stats: torch.Tensor) -> dict:
     raw = bytes(stats.cpu().numpy().tobytes())
     return CStats.from_buffer_copy(raw[:STATS_BYTES]).as_dict()
@@ -520,7 +535,8 @@ def exported_symbols() -> Sequence[str]:
             "psfm_status_string", "psfm_batch_workspace_bytes", "psfm_batch_plan",
             "psfm_batch_run", "psfm_batch_run_stage", "psfm_batch_set_tuning", "psfm_batch_graph_capture",
             "psfm_batch_graph_launch", "psfm_batch_destroy", "psfm_wall_clock_hz",
-            "psfm_solve_stamps", "psfm_solve_prior", "psfm_cnn_param_count",
+            "psfm_solve_stamps", "psfm_solve_prior", "psfm_cholesky_workspace_bytes",
+            "psfm_cholesky_solve", "psfm_cnn_param_count",
             "psfm_cnn_workspace_bytes", "psfm_cnn_forward", "psfm_cnn_loss_grad",
             "psfm_cnn_loss_weights", "psfm_cnn_adam",
             "psfm_cnn_stamp_inputs", "psfm_cnn_targets", "psfm_cnn_local_coeffs"]

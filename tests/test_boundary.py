@@ -102,3 +102,6 @@ def test_cnn_parameter_layout_matches_oracle(lib):
     assert lib.psfm_cnn_loss_grad(None, None, None, None, 1, None, None, None, 0, None) == -1
     assert lib.psfm_cnn_loss_weights(None, None, None, None, 1, None, None) == -1
     assert lib.psfm_solve_stamps(None, 1, *([None] * 6), None) == -1
+    assert lib.psfm_cholesky_workspace_bytes(0) == 0 and lib.psfm_cholesky_workspace_bytes(295) > 0
+    assert lib.psfm_cholesky_solve(0, None, None, None, None, None, 0, None) == -1
+    assert lib.psfm_cholesky_solve(600, *([None] * 4), None, 0, None) == -1

@@ -326,3 +326,31 @@ def test_noiseless_inspan_recovery_gpu():
     assert abs(_np(out["sol"]["coeffs"])[-1] - 5.0) < 1e-2
     clean = _np(out["diff_mask"]) == 0
     assert np.max(np.abs(_np(out["diff"])[clean])) < 2e-4 * np.abs(I2).max()
+
+
+def test_cholesky_solve_matches_oracle():
+    """psfm_cholesky_solve on the assembled 295 x 295 normal matrix of the
+    2048^2 pair: the same solution as the oracle's equilibrated Cholesky
+    (FP64 both; residual and kernel sum to 1e-9), and the same failing pivot
+    for a matrix made indefinite."""
+    torch, psfm = hip()
+    wl, pair = pair_for("cfg1", SEEDS["cfg1"])
+    ref = oracle_run("cfg1", SEEDS["cfg1"])
+    cfg = O.Config.from_workload(wl)
+    used = (ref["fit"]["flags"] == 0).astype(np.uint8)
+    M, b = O.assemble(cfg, wl.width, wl.height, pair.stamps, ref["fit"]["M"], ref["fit"]["b"], used)
+    xo, info_o = O.cholesky_solve(M, b)
+    x, info = psfm.cholesky_solve(torch.from_numpy(M).cuda(), torch.from_numpy(b).cuda())
+    torch.cuda.synchronize()
+    x = _np(x)
+    assert int(_np(info)[0]) == 0 and info_o == 0
+    assert np.linalg.norm(M @ x - b) <= 1e-9 * np.linalg.norm(b)
+    g = O.spatial(cfg, 0.5 * (wl.width - 1), 0.5 * (wl.height - 1), wl.width, wl.height)
+    ns = len(g)
+    assert abs((x[:ns] @ g) / (xo[:ns] @ g) - 1) < 1e-9
+    M2 = M.copy()
+    M2[100, 100] = -1.0
+    _, info_o2 = O.cholesky_solve(M2, b)
+    _, info2 = psfm.cholesky_solve(torch.from_numpy(M2).cuda(), torch.from_numpy(b).cuda())
+    torch.cuda.synchronize()
+    assert int(_np(info2)[0]) == info_o2 == 101
