@@ -11,7 +11,7 @@ with ellipticity up to 0.2, 2000 sources, 10% mask, 21 x 21 kernel with the
 49-term ISIS basis x spatial order 2 (295 unknowns), 100 stamps of 41 x 41,
 variance map and a 21 x 21 covariance pseudo-matrix.
 
---workload cfg3: one batch of 64 independent pairs of uneven size (1024 to
+--workload batch64: one batch of 64 independent pairs of uneven size (1024 to
 6000 px a side, spatial order 0-3, 50-400 stamps) through psfm_batch_* as one
 HIP graph; also reports the p50 / p99 completion latency of the pairs.
 
@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cfg1")
+    ap.add_argument("--workload", default="pair2048")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--retune", action="store_true", help="ignore cached batch launch shapes")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16", "bf16"],
@@ -71,7 +71,7 @@ def source_sha(path):
 def measured_traffic(kernel_src):
     """HBM bytes per launch of the convolution kernel from the committed
     rocprofv3 counter summary, if it was taken on the current source."""
-    path = os.path.join(PROFILES, "conv_tile_cfg1_traffic.json")
+    path = os.path.join(PROFILES, "conv_tile_pair2048_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -108,12 +108,12 @@ def log(msg):
 def bench_batch(args, torch, psfm, synth):
     from paper_1901_09999_amd import tune
     spec = synth.BATCHES[args.workload]
-    cfg_index = int(args.workload[-1])
-    wls = [synth.batch_pair_workload(spec, k, cfg_index) for k in range(spec.n_pairs)]
+    seed_index = synth.SEED_INDEX[args.workload]
+    wls = [synth.batch_pair_workload(spec, k, seed_index) for k in range(spec.n_pairs)]
     t0 = time.perf_counter()
     dps = []
     for k, wl in enumerate(wls):
-        dps.append(synth.make_pair_device(wl, synth.workload_seed(cfg_index, k)))
+        dps.append(synth.make_pair_device(wl, synth.workload_seed(seed_index, k)))
         if k % 16 == 15:
             torch.cuda.synchronize()
             log(f"generated {k + 1}/{len(wls)} pairs ({time.perf_counter() - t0:.1f} s)")
@@ -238,8 +238,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(the multi-GPU sharding is described, not built)"}))
+        print(json.dumps({"error": "psfm runs on one GPU; --gpus must be 1 "
+                                   "(sharding over several GPUs is not implemented)"}))
         sys.exit(2)
     import torch
     from paper_1901_09999_amd import psfm, synth
@@ -257,8 +257,8 @@ def main():
     if args.workload in synth.BATCHES:
         return bench_batch(args, torch, psfm, synth)
     wl = synth.WORKLOADS[args.workload]
-    cfg_index = int(args.workload[-1])
-    pair = synth.make_pair(wl, synth.workload_seed(cfg_index))
+    seed_index = synth.SEED_INDEX[args.workload]
+    pair = synth.make_pair(wl, synth.workload_seed(seed_index))
     d = psfm.to_device(pair)
     W, H, n = wl.width, wl.height, pair.stamps.shape[0]
     precs = {"fp32": psfm.PREC_FP32, "fp16": psfm.PREC_FP16, "bf16": psfm.PREC_BF16}

@@ -160,7 +160,7 @@ def to_local(ctx: psfm.Context, ortho: torch.Tensor) -> torch.Tensor:
     return a
 
 
-def make_dataset(n: int, seed: int, spec: synth.StampSetSpec = synth.STAMP_SETS["cfg4"],
+def make_dataset(n: int, seed: int, spec: synth.StampSetSpec = synth.STAMP_SETS["cells200k"],
                  chunk: int = 25_000, log: Optional[Callable[[str], None]] = None) -> dict:
     """Inputs, method-solved targets and loss weights for n single-star stamp
     pairs: the fit of each cell's stamp (psfm_fit_stamps), its own

@@ -226,25 +226,7 @@ __global__ void k_weights_b(const PairDesc* __restrict__ pairs) {
 
 __device__ __forceinline__ double block_sum(double v, double* red) { return psfm_block_sum(v, red); }
 
-// Equilibrated Cholesky and solve of the N x N system in A (lower triangle
-// overwritten by the factor); x receives the solution.  One workgroup.
-// Per 32-column panel (staged in LDS):
-//   * wave 0 factors the 32 x 32 diagonal block: rows in registers, the
-//     pivot column broadcast through a double-buffered LDS column that is
-//     published before the rest of the row updates (one column of
-//     look-ahead inside the wave); 1/sqrt by v_rsq_f64 + 2 Newton steps;
-//   * wave 0 then inverts the two 16 x 16 diagonal sub-blocks (one column of
-//     each inverse per lane);
-//   * the panel rows below are solved against the diagonal block as FP64
-//     MFMA products with those inverses (16-row tiles, one wave each);
-//   * the forward substitution L z = D b advances by the panel's unknowns
-//     (small mat-vecs with the inverses);
-//   * the trailing lower triangle is updated with v_mfma_f64_16x16x4f64 on
-//     16 x 16 tiles, four tiles' loads in flight per wave.
-// The back substitution L^T w = z walks the panels in reverse with the
-// stored inverses.
 typedef double double4v __attribute__((ext_vector_type(4)));
-
 
 __device__ __forceinline__ double rsqrt_nr(double d) {
     double r = __builtin_amdgcn_rsq(d);
@@ -253,89 +235,364 @@ __device__ __forceinline__ double rsqrt_nr(double d) {
     return r;
 }
 
-constexpr int IL_S = 17;   // LDS row stride of the 16 x 16 inverses
+// 1/d: v_rcp_f64 and two Newton steps.
+__device__ __forceinline__ double rcp_nr(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    r = fma(r, fma(-d, r, 1.0), r);
+    return r;
+}
+
+// Value of v in lane l of the wave (l a compile-time constant after unrolling).
+__device__ __forceinline__ double readlane_d(double v, int l) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+    return __hiloint2double(hi, lo);
+}
+
+constexpr int PL_CHUNK = 8;      // panel rows in flight per thread
+constexpr int IV_DOUBLES = CH_NB * CH_NB;   // stored inverse of one 32 x 32 diagonal block
+
+// Rows [r_lo, r_hi) (relative to k0) of the 32 panel columns k0 .. k0 + 31:
+// the lower triangle of S (row stride N) for rows below r_end and columns
+// below nk, zeros elsewhere, into P[(r) * CH_PS + c].  With Dq given, each
+// element is equilibrated on the way (S d_i d_j).  Loads are unconditional
+// from clamped addresses, PL_CHUNK per thread in flight before the first
+// store.
+__device__ __forceinline__ void load_panel(int N, const double* __restrict__ S, int k0, int nk,
+                                           int r_lo, int r_hi, int r_end, double* P,
+                                           const double* Dq) {
+    const int tr = threadIdx.x >> 5, tc = threadIdx.x & 31, TR = CH_THREADS / 32;
+    for (int base = r_lo + tr; base < r_hi; base += TR * PL_CHUNK) {
+        double v[PL_CHUNK];
+#pragma unroll
+        for (int u = 0; u < PL_CHUNK; u++) {
+            const int i = base + TR * u;
+            const bool in = i < r_end && tc < nk && (i >= nk || tc <= i);
+            v[u] = S[in ? (k0 + i) * N + k0 + tc : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < PL_CHUNK; u++) {
+            const int i = base + TR * u;
+            const bool in = i < r_end && tc < nk && (i >= nk || tc <= i);
+            if (i < r_hi) P[i * CH_PS + tc] = !in ? 0.0 : Dq ? v[u] * (Dq[k0 + i] * Dq[k0 + tc]) : v[u];
+        }
+    }
+}
+
+// The stored inverse of panel p's 32 x 32 diagonal block into Iv (LDS,
+// row stride CH_PS).
+__device__ __forceinline__ void load_inverse(const double* __restrict__ ILg, int p, double* Iv) {
+    for (int e = threadIdx.x; e < IV_DOUBLES; e += CH_THREADS)
+        Iv[(e >> 5) * CH_PS + (e & 31)] = ILg[(size_t)p * IV_DOUBLES + e];
+}
+
+// z <- Iv z over the panel's unknowns (forward substitution through the
+// diagonal block), by the first 32 lanes of wave 0.
+__device__ __forceinline__ void diag_forward(int k0, int nk, const double* Iv, double* zb) {
+    const int lane = threadIdx.x & 63;
+    double z = 0.0;
+    if (lane < CH_NB) {
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};      // FP64 latency: four independent chains
+#pragma unroll
+        for (int k = 0; k < CH_NB; k++) s4[k & 3] += Iv[lane * CH_PS + k] * zb[k0 + k];
+        z = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+    }
+    wave_sync();
+    if (lane < nk) zb[k0 + lane] = z;
+}
 
 // Back substitution L^T w = z with the factor in the lower triangle of A and
-// the stored inverses of the 16 x 16 diagonal sub-blocks; z (LDS) is
-// overwritten by w.  P, IL, part are LDS scratch of the caller.
+// the stored diagonal-block inverses; z (LDS) is overwritten by w.  Per
+// panel, in reverse: rhs = z_p - L_below^T w_below (all threads), then
+// w_p = Iv^T rhs (wave 0).  P, Iv, part are LDS scratch of the caller.
 __device__ __forceinline__ void back_subst(int N, const double* __restrict__ A, const double* __restrict__ ILg,
-                           double* zb, double* P, double (*IL)[16 * IL_S], double* part) {
+                           double* zb, double* P, double* Iv, double* part) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     constexpr int NPART = CH_THREADS / 32;
-    const int tr = tid >> 5, tc = tid & 31, TR = CH_THREADS / 32;
     for (int k0 = ((N - 1) / CH_NB) * CH_NB; k0 >= 0; k0 -= CH_NB) {
         const int nk = min(CH_NB, N - k0);
         const int rows = N - k0;
-        for (int i = tr; i < rows; i += TR)
-            P[i * CH_PS + tc] = (tc < nk && (i >= nk || tc <= i)) ? A[(size_t)(k0 + i) * N + k0 + tc] : 0.0;
-        for (int e = tid; e < 512; e += CH_THREADS) {
-            const int g = e >> 8, q = (e >> 4) & 15, j = e & 15;
-            IL[g][q * IL_S + j] = ILg[(size_t)(k0 / CH_NB) * 512 + e];
-        }
+        load_panel(N, A, k0, nk, nk, rows, rows, P, nullptr);
+        load_inverse(ILg, k0 / CH_NB, Iv);
         __syncthreads();
         {
             const int c = tid & 31, w = tid >> 5;
-            double acc = 0.0;
-            if (c < nk)
-                for (int i = nk + w; i < rows; i += NPART) acc += P[i * CH_PS + c] * zb[k0 + i];
-            part[c * NPART + w] = acc;
+            double a0 = 0.0, a1 = 0.0;
+            if (c < nk) {
+                int i = nk + w;
+                for (; i + NPART < rows; i += 2 * NPART) {
+                    a0 += P[i * CH_PS + c] * zb[k0 + i];
+                    a1 += P[(i + NPART) * CH_PS + c] * zb[k0 + i + NPART];
+                }
+                if (i < rows) a0 += P[i * CH_PS + c] * zb[k0 + i];
+            }
+            part[c * NPART + w] = a0 + a1;
         }
         __syncthreads();
         if (wave == 0) {
             double v = 0.0;
             if (lane < nk) {
-                v = zb[k0 + lane];
-                for (int w = 0; w < NPART; w++) v -= part[lane * NPART + w];
+                double p4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int w = 0; w < NPART; w++) p4[w & 3] += part[lane * NPART + w];
+                v = zb[k0 + lane] - ((p4[0] + p4[1]) + (p4[2] + p4[3]));
             }
-            if (lane < 32) zb[k0 + lane] = lane < nk ? v : 0.0;
+            if (lane < CH_NB) zb[k0 + lane] = v;
             wave_sync();
-            // w2 = inv(L22)^T rhs2
-            double w2 = 0.0;
-            if (lane >= 16 && lane < 32) {
-                const int i = lane - 16;
-                for (int k = 0; k < 16; k++) w2 += IL[1][k * IL_S + i] * zb[k0 + 16 + k];
-            }
-            wave_sync();
-            if (lane >= 16 && lane < 32) zb[k0 + lane] = w2;
-            wave_sync();
-            // rhs1 -= L21^T w2 ; w1 = inv(L11)^T rhs1
-            double r1 = 0.0;
-            if (lane < 16) {
-                r1 = zb[k0 + lane];
-                for (int k = 0; k < 16; k++) r1 -= P[(16 + k) * CH_PS + lane] * zb[k0 + 16 + k];
+            double wv = 0.0;
+            if (lane < CH_NB) {
+                double s4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int i = 0; i < CH_NB; i++) s4[i & 3] += Iv[i * CH_PS + lane] * zb[k0 + i];
+                wv = (s4[0] + s4[1]) + (s4[2] + s4[3]);
             }
             wave_sync();
-            if (lane < 16) zb[k0 + lane] = r1;
-            wave_sync();
-            double w1 = 0.0;
-            if (lane < 16) {
-                for (int k = 0; k < 16; k++) w1 += IL[0][k * IL_S + lane] * zb[k0 + k];
-            }
-            wave_sync();
-            if (lane < 16 && lane < nk) zb[k0 + lane] = w1;
+            if (lane < nk) zb[k0 + lane] = wv;
         }
         __syncthreads();
     }
 }
 
-__device__ __forceinline__ void cholesky_body(int N, double* __restrict__ A, const double* __restrict__ b,
+// Cholesky of the nk x nk diagonal block in rows 0 .. nk - 1 of Q (row
+// stride CH_PS, lower triangle, zeros above and beyond nk), in place, by one
+// wave, and the inverse of the factor.
+//   Factor: rows in the lanes' registers, right-looking in the L D L^T form:
+//   the pivot chain is d_(c+1) = A_(c+1,c+1) - A_(c+1,c)^2 / d_c (a
+//   reciprocal and one FMA per column, operands read from the pivot row's
+//   lane), and each step's column reaches the other lanes through a
+//   double-buffered LDS column (cb).  The 32 steps are straight-line code
+//   (selects, no branches or barriers: LDS accesses of one wave are ordered)
+//   so that the next pivot's reciprocal overlaps the current column's
+//   updates.  Then L = L_unit D^(1/2).
+//   Inverse: the two 16 x 16 diagonal sub-blocks by substitution on the
+//   unit-diagonal factor (one column per lane), the off-diagonal block as -I22 (L21 I11) on FP64 MFMA; the
+//   32 x 32 result goes to Iv (LDS, zeros above the diagonal) and to ivg.
+// dd, ds: LDS [32] scratch.  Returns 0, or the 1-based column of the first
+// non-positive pivot.
+__device__ __forceinline__ int factor_diag(int nk, double* Q, double* Iv, double* __restrict__ ivg,
+                                           double (*cb)[64], double* dd, double* ds) {
+    const int lane = threadIdx.x & 63, row = lane & 31;
+    const int l16 = lane & 15, l4 = lane >> 4;
+    constexpr int PF = 6;        // column entries read ahead into registers
+    double r[CH_NB], pre[PF];
+#pragma unroll
+    for (int c = 0; c < CH_NB; c++) r[c] = row < nk ? Q[row * CH_PS + c] : 0.0;
+    cb[0][lane] = r[0];
+#pragma unroll
+    for (int u = 0; u < PF; u++) pre[u] = 1 + u < CH_NB ? cb[0][1 + u] : 0.0;
+    double dc = readlane_d(r[0], 0);
+    int bad = 0;
+#pragma unroll
+    for (int c = 0; c < CH_NB; c++) {
+        const bool live = c < nk, ok = dc > 0.0;
+        bad = (bad == 0 && live && !ok) ? c + 1 : bad;
+        const double d = live && ok ? dc : 1.0;
+        dd[c] = d;
+        const double rc = rcp_nr(d);
+        if (c + 1 < CH_NB) {
+            const double a = readlane_d(r[c + 1], c + 1), q = readlane_d(r[c], c + 1);
+            dc = fma(-q * q, rc, a);
+        }
+        const double t = (row > c && row < nk) ? r[c] * rc : 0.0;
+        const double* col = cb[c & 1];
+        // column c: entries c + 1 .. c + PF were read ahead (pre), the rest now
+        double cur[PF];
+#pragma unroll
+        for (int u = 0; u < PF; u++) cur[u] = pre[u];
+        if (c + 1 < CH_NB) {
+            r[c + 1] -= t * cur[0];
+            cb[(c + 1) & 1][lane] = r[c + 1];
+            // the head of the next step's column, so that its latency
+            // overlaps this step's updates (LDS accesses of one wave are in order)
+#pragma unroll
+            for (int u = 0; u < PF; u++) pre[u] = c + 2 + u < CH_NB ? cb[(c + 1) & 1][c + 2 + u] : 0.0;
+        }
+#pragma unroll
+        for (int j = c + 2; j < CH_NB; j++) r[j] -= t * (j - c - 1 < PF ? cur[j - c - 1] : col[j]);
+    }
+    if (bad) return bad;
+    // 1/sqrt(d_c) per pivot (one per lane), then L = L_unit D^(1/2) row by row
+    const double dm = dd[row];
+    const double sm = rsqrt_nr(dm);
+    if (lane < CH_NB) ds[lane] = lane < nk ? sm : 0.0;
+    wave_sync();
+#pragma unroll
+    for (int c0 = 0; c0 < CH_NB; c0 += 8) {
+        double sc[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) sc[u] = ds[c0 + u];
+        if (lane < nk) {
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const int c = c0 + u;
+                Q[row * CH_PS + c] = c < row ? r[c] * sc[u] : c == row ? dm * sm : 0.0;
+            }
+        }
+    }
+    wave_sync();
+    // inverses of the diagonal 16 x 16 sub-blocks: column j of block g per lane
+    if (lane < CH_NB) {
+        const int g = lane >> 4, j = lane & 15, base = 16 * g;
+        double xv[16];
+        // inv(L_gg) = D^(-1/2) inv(U) with U = L_gg D^(-1/2) unit lower: the
+        // substitution chain is one FMA per column
+#pragma unroll
+        for (int q = 0; q < 16; q++) xv[q] = q == j ? 1.0 : 0.0;
+#pragma unroll
+        for (int c = 0; c < 16; c++) {
+            const double sc = ds[base + c];
+#pragma unroll
+            for (int q = c + 1; q < 16; q++) xv[q] -= (Q[(base + q) * CH_PS + base + c] * sc) * xv[c];
+        }
+#pragma unroll
+        for (int q = 0; q < 16; q++) Iv[(base + q) * CH_PS + base + j] = xv[q] * ds[base + q];
+    }
+    wave_sync();
+    // T = L21 I11 (kept in the upper-right block of Iv), I21 = -I22 T
+    double4v acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Q[(16 + l16) * CH_PS + kk + l4],
+                                                   Iv[(kk + l4) * CH_PS + l16], acc, 0, 0, 0);
+    wave_sync();
+#pragma unroll
+    for (int e = 0; e < 4; e++) Iv[(l4 + 4 * e) * CH_PS + 16 + l16] = acc[e];
+    wave_sync();
+    double4v acc2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4)
+        acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(Iv[(16 + l16) * CH_PS + 16 + kk + l4],
+                                                    Iv[(kk + l4) * CH_PS + 16 + l16], acc2, 0, 0, 0);
+    wave_sync();
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+        Iv[(16 + l4 + 4 * e) * CH_PS + l16] = -acc2[e];
+        Iv[(l4 + 4 * e) * CH_PS + 16 + l16] = 0.0;
+    }
+    wave_sync();
+    for (int e = lane; e < IV_DOUBLES; e += 64) ivg[e] = Iv[(e >> 5) * CH_PS + (e & 31)];
+    return 0;
+}
+
+// Trailing update of one 32 x 32 block (block row a2 >= block column b2 of
+// the lower triangle below the panel):  C <- C - L_a L_b^T  with L_a, L_b
+// the panel rows (in P) of the block's rows and columns, as four 16 x 16
+// tiles on v_mfma_f64_16x16x4f64 (three on a diagonal block).  C comes from
+// S, equilibrated by Dq when given (the first touch of that element); the
+// product runs from zero while the C loads are in flight.  Results go to A,
+// or, with Dn given (the block that is the next diagonal block), to Dn with
+// zeros above the diagonal and beyond the matrix.  Blocks wholly inside the
+// lower triangle take a path without per-element predicates.
+__device__ __forceinline__ void trail_block(int N, int k0, int nk, int rows, int a2, int b2,
+                                            const double* __restrict__ S, double* __restrict__ A,
+                                            const double* Dq, const double* P, double* Dn) {
+    const int lane = threadIdx.x & 63, l16 = lane & 15, l4 = lane >> 4;
+    const int r0 = nk + 32 * a2, c0 = nk + 32 * b2;      // relative to k0
+    const bool diag = a2 == b2;
+    const bool full = !diag && r0 + 32 <= rows && !Dq && !Dn;
+    const int base = (k0 + r0 + l4) * N + k0 + c0 + l16;  // element (r0 + l4, c0 + l16)
+    double4v c[4], acc[4];
+    // sub-tile s = 2 sr + sc: rows r0 + 16 sr + l4 + 4 e, columns c0 + 16 sc + l16
+    if (full) {
+#pragma unroll
+        for (int s = 0; s < 4; s++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) c[s][e] = S[base + (16 * (s >> 1) + 4 * e) * N + 16 * (s & 1)];
+    } else {
+#pragma unroll
+        for (int s = 0; s < 4; s++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int ii = r0 + 16 * (s >> 1) + l4 + 4 * e, jj = c0 + 16 * (s & 1) + l16;
+                const bool in = ii < rows && jj <= ii;
+                c[s][e] = S[in ? base + (16 * (s >> 1) + 4 * e) * N + 16 * (s & 1) : 0];
+            }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; s++) acc[s] = double4v{0.0, 0.0, 0.0, 0.0};
+    // operand rows beyond the panel buffer are clamped (their outputs are discarded)
+    const int rmax = rows + 15;
+    const double* pa0 = P + (r0 + l16) * CH_PS + l4;
+    const double* pa1 = P + min(r0 + 16 + l16, rmax) * CH_PS + l4;
+    const double* pb0 = P + (c0 + l16) * CH_PS + l4;
+    const double* pb1 = P + min(c0 + 16 + l16, rmax) * CH_PS + l4;
+    if (diag) {
+#pragma unroll
+        for (int cc = 0; cc < CH_NB; cc += 4) {
+            const double a0 = pa0[cc], a1 = pa1[cc], b0 = pb0[cc], b1 = pb1[cc];
+            acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0], 0, 0, 0);
+            acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[2], 0, 0, 0);
+            acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[3], 0, 0, 0);
+        }
+    } else {
+#pragma unroll
+        for (int cc = 0; cc < CH_NB; cc += 4) {
+            const double a0 = pa0[cc], a1 = pa1[cc], b0 = pb0[cc], b1 = pb1[cc];
+            acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[1], 0, 0, 0);
+            acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[2], 0, 0, 0);
+            acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[3], 0, 0, 0);
+        }
+    }
+    if (full) {
+#pragma unroll
+        for (int s = 0; s < 4; s++)
+#pragma unroll
+            for (int e = 0; e < 4; e++)
+                A[base + (16 * (s >> 1) + 4 * e) * N + 16 * (s & 1)] = c[s][e] - acc[s][e];
+        return;
+    }
+#pragma unroll
+    for (int s = 0; s < 4; s++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const int ii = r0 + 16 * (s >> 1) + l4 + 4 * e, jj = c0 + 16 * (s & 1) + l16;
+            const bool in = ii < rows && jj <= ii;
+            const double cv = Dq && in ? c[s][e] * (Dq[k0 + ii] * Dq[k0 + jj]) : c[s][e];
+            const double v = cv - acc[s][e];
+            if (Dn) Dn[(ii - nk) * CH_PS + (jj - nk)] = in ? v : 0.0;
+            else if (in) A[base + (16 * (s >> 1) + 4 * e) * N + 16 * (s & 1)] = v;
+        }
+}
+
+// Equilibrated blocked right-looking Cholesky and solve of the N x N system
+// M x = b; M's lower triangle is read from S (M itself, or a separate copy)
+// and the factor of D M D (D = diag(M)^(-1/2)) is left in the lower
+// triangle of A; x receives the solution.  One workgroup.  Per 32-column
+// panel (in LDS):
+//   * the panel rows below the diagonal block are multiplied by the inverse
+//     of its factor (FP64 MFMA, 16-row tiles, one wave each);
+//   * the forward substitution L z = D b advances by the panel's unknowns;
+//   * the trailing lower triangle is updated on FP64 MFMA in 32 x 32 blocks
+//     handed out to the waves from an LDS counter.  Wave 0 first forms the
+//     block that is the next diagonal block, in LDS, and factors and inverts
+//     it (look-ahead), so the serial pivot chain of the next panel overlaps
+//     the update of the rest of the matrix.
+// Equilibration happens on each element's first read (the first panel and
+// the first trailing update), so M is read once.  The back substitution
+// L^T w = z walks the panels in reverse with the stored inverses (IV_DOUBLES
+// per panel in ILg).
+__device__ __forceinline__ void cholesky_body(int N, double* __restrict__ A, const double* __restrict__ S,
+                              const double* __restrict__ b,
                               double* __restrict__ x, double* __restrict__ ILg,
                               double* __restrict__ Dg, SolveState* st) {
     if (st->done) return;
-    extern __shared__ double P[];        // panel [N + 16][CH_PS]
+    extern __shared__ double P[];        // panel [max(N, 32) + 16][CH_PS]
     __shared__ double Dq[CH_NMAX];
     __shared__ double zb[CH_NMAX + 32];
-    __shared__ double dinv[CH_NMAX + 32];
-    __shared__ double IL[2][16 * IL_S];
-    __shared__ double part[CH_NB * (CH_THREADS / 32)];
+    __shared__ double Iv[CH_NB * CH_PS];  // inverse of the current diagonal block
+    __shared__ double Dn[CH_NB * CH_PS];  // next diagonal block; back substitution partials
     __shared__ double cb[2][64];
-    __shared__ int s_bad;
+    __shared__ double dd[CH_NB], ds[CH_NB];
+    __shared__ int s_bad, s_next;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     constexpr int NW = CH_THREADS / 64;
     if (tid == 0) s_bad = 0;
     __syncthreads();
     for (int i = tid; i < N; i += CH_THREADS) {
-        const double d = A[(size_t)i * N + i];
+        const double d = S[i * N + i];
         if (!(d > 0.0)) atomicOr(&s_bad, 1);
         Dq[i] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
     }
@@ -352,78 +609,34 @@ __device__ __forceinline__ void cholesky_body(int N, double* __restrict__ A, con
     }
     for (int i = tid; i < N + 32; i += CH_THREADS) {
         zb[i] = i < N ? Dq[i] * b[i] : 0.0;
-        dinv[i] = 0.0;
         if (Dg && i < N) Dg[i] = Dq[i];
     }
-    const int tr = tid >> 5, tc = tid & 31, TR = CH_THREADS / 32;
-    for (int i = tr; i < N; i += TR)
-        for (int j = tc; j <= i; j += 32) A[(size_t)i * N + j] *= Dq[i] * Dq[j];
-    __syncthreads();
+    // first panel: read (equilibrated) and factor its diagonal block
+    {
+        const int nk = min(CH_NB, N);
+        load_panel(N, S, 0, nk, 0, N + 16, N, P, Dq);
+        if (tid == 0) s_next = 1;
+        __syncthreads();
+        if (wave == 0) {
+            const int bad = factor_diag(nk, P, Iv, ILg, cb, dd, ds);
+            if (lane == 0) s_bad = bad;
+        }
+        __syncthreads();
+    }
     const int l16 = lane & 15, l4 = lane >> 4;
     for (int k0 = 0; k0 < N; k0 += CH_NB) {
         const int nk = min(CH_NB, N - k0);
         const int rows = N - k0;
-        for (int i = tr; i < rows + 16; i += TR)
-            P[i * CH_PS + tc] = (i < rows && tc < nk && (i >= nk || tc <= i))
-                                    ? A[(size_t)(k0 + i) * N + k0 + tc] : 0.0;
-        __syncthreads();
-        // ---- diagonal block and its two 16 x 16 inverses (wave 0)
-        if (wave == 0) {
-            double r[CH_NB];
-#pragma unroll
-            for (int c = 0; c < CH_NB; c++) r[c] = lane < nk ? P[lane * CH_PS + c] : 0.0;
-            int bad = 0;
-            if (lane < CH_NB) cb[0][lane] = r[0];
-            wave_sync();
-#pragma unroll
-            for (int c = 0; c < CH_NB; c++) {
-                if (c < nk && !bad) {
-                    const double* col = cb[c & 1];
-                    const double d = col[c];
-                    if (!(d > 0.0)) {
-                        bad = c + 1;
-                    } else {
-                        const double inv = rsqrt_nr(d);
-                        const double t = (lane > c && lane < nk) ? r[c] * inv * inv : 0.0;
-                        if (c + 1 < CH_NB) {
-                            r[c + 1] -= t * col[c + 1];
-                            if (lane < CH_NB) cb[(c + 1) & 1][lane] = r[c + 1];
-                        }
-#pragma unroll
-                        for (int j = c + 2; j < CH_NB; j++) r[j] -= t * col[j];
-                        r[c] = lane == c ? d * inv : (lane > c ? r[c] * inv : r[c]);
-                        if (lane == 0) dinv[k0 + c] = inv;
-                    }
-                    wave_sync();
-                }
+        if (k0 > 0) {
+            // diagonal block: factored by the look-ahead; rows below from A
+            load_panel(N, A, k0, nk, nk, rows + 16, rows, P, nullptr);
+            for (int e = tid; e < CH_NB * CH_NB; e += CH_THREADS) {
+                const int i = e >> 5, j = e & 31;
+                P[i * CH_PS + j] = Dn[i * CH_PS + j];
             }
-            if (lane < nk) {
-#pragma unroll
-                for (int c = 0; c < CH_NB; c++) P[lane * CH_PS + c] = c <= lane ? r[c] : 0.0;
-            }
-            if (lane == 0) s_bad = bad;
-            wave_sync();
-            if (!bad && lane < 32) {
-                // column j of the inverse of diagonal sub-block g (rows/cols 16 g .. 16 g + 15)
-                const int g = lane >> 4, j = lane & 15, base = 16 * g;
-                double xv[16];
-#pragma unroll
-                for (int q = 0; q < 16; q++) xv[q] = q == j ? 1.0 : 0.0;
-#pragma unroll
-                for (int c = 0; c < 16; c++) {
-                    xv[c] *= dinv[k0 + base + c];
-#pragma unroll
-                    for (int q = c + 1; q < 16; q++) xv[q] -= P[(base + q) * CH_PS + base + c] * xv[c];
-                }
-                double* ilg = ILg + (size_t)(k0 / CH_NB) * 512 + g * 256;
-#pragma unroll
-                for (int q = 0; q < 16; q++) {
-                    IL[g][q * IL_S + j] = xv[q];
-                    ilg[q * 16 + j] = xv[q];
-                }
-            }
+            if (tid == 0) s_next = 1;
+            __syncthreads();
         }
-        __syncthreads();
         if (s_bad) {
             if (tid == 0) {
                 st->info = k0 + s_bad;
@@ -431,139 +644,80 @@ __device__ __forceinline__ void cholesky_body(int N, double* __restrict__ A, con
             }
             return;
         }
-        // ---- panel rows below the diagonal block, 16-row tiles on MFMA:
-        //      X1 = A1 inv(L11)^T, X2 = (A2 - X1 L21^T) inv(L22)^T
+        // ---- panel rows below the diagonal block: X = A_below Iv^T, 16-row
+        //      tiles on MFMA (the tile's operands are read before it is written)
         const int m = rows - nk;
         if (m > 0) {
             const int nt = (m + 15) / 16;
             for (int t = wave; t < nt; t += NW) {
                 const int r0 = nk + 16 * t;
-                double4v acc = {0.0, 0.0, 0.0, 0.0};
+                double a[CH_NB / 4];
 #pragma unroll
-                for (int kk = 0; kk < 16; kk += 4)
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(P[(r0 + l16) * CH_PS + kk + l4],
-                                                               IL[0][l16 * IL_S + kk + l4], acc, 0, 0, 0);
+                for (int q = 0; q < CH_NB / 4; q++) a[q] = P[(r0 + l16) * CH_PS + 4 * q + l4];
+                double4v x0 = {0.0, 0.0, 0.0, 0.0}, x1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int q = 0; q < 4; q++)
+                    x0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], Iv[l16 * CH_PS + 4 * q + l4], x0, 0, 0, 0);
+#pragma unroll
+                for (int q = 0; q < CH_NB / 4; q++)
+                    x1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], Iv[(16 + l16) * CH_PS + 4 * q + l4], x1, 0, 0, 0);
                 wave_sync();
 #pragma unroll
-                for (int e = 0; e < 4; e++) P[(r0 + l4 + 4 * e) * CH_PS + l16] = acc[e];
-                wave_sync();
-#pragma unroll
-                for (int e = 0; e < 4; e++) acc[e] = P[(r0 + l4 + 4 * e) * CH_PS + 16 + l16];
-#pragma unroll
-                for (int kk = 0; kk < 16; kk += 4)
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-P[(r0 + l16) * CH_PS + kk + l4],
-                                                               P[(16 + l16) * CH_PS + kk + l4], acc, 0, 0, 0);
-                wave_sync();
-#pragma unroll
-                for (int e = 0; e < 4; e++) P[(r0 + l4 + 4 * e) * CH_PS + 16 + l16] = acc[e];
-                wave_sync();
-                double4v acc2 = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int kk = 0; kk < 16; kk += 4)
-                    acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(P[(r0 + l16) * CH_PS + 16 + kk + l4],
-                                                                IL[1][l16 * IL_S + kk + l4], acc2, 0, 0, 0);
-                wave_sync();
-#pragma unroll
-                for (int e = 0; e < 4; e++) P[(r0 + l4 + 4 * e) * CH_PS + 16 + l16] = acc2[e];
+                for (int e = 0; e < 4; e++) {
+                    P[(r0 + l4 + 4 * e) * CH_PS + l16] = x0[e];
+                    P[(r0 + l4 + 4 * e) * CH_PS + 16 + l16] = x1[e];
+                }
             }
         }
         // ---- forward substitution for the panel's unknowns (wave 0)
-        if (wave == 0) {
-            double z1 = 0.0;
-            if (lane < 16) {
-                for (int k = 0; k < 16; k++) z1 += IL[0][lane * IL_S + k] * zb[k0 + k];
-            }
-            wave_sync();
-            if (lane < 16) zb[k0 + lane] = z1;
-            wave_sync();
-            double s2 = 0.0;
-            if (lane >= 16 && lane < 32) {
-                const int i = lane - 16;
-                s2 = zb[k0 + 16 + i];
-                for (int k = 0; k < 16; k++) s2 -= P[(16 + i) * CH_PS + k] * zb[k0 + k];
-            }
-            wave_sync();
-            if (lane >= 16 && lane < 32) zb[k0 + lane] = s2;
-            wave_sync();
-            double z2 = 0.0;
-            if (lane >= 16 && lane < 32) {
-                const int i = lane - 16;
-                for (int k = 0; k < 16; k++) z2 += IL[1][i * IL_S + k] * zb[k0 + 16 + k];
-            }
-            wave_sync();
-            if (lane >= 16 && lane < 32 && lane < nk) zb[k0 + lane] = z2;
-        }
+        if (wave == 0) diag_forward(k0, nk, Iv, zb);
         __syncthreads();
         for (int i = nk + tid; i < rows; i += CH_THREADS) {
-            double acc = 0.0;
-#pragma unroll 8
-            for (int c = 0; c < CH_NB; c++) acc += P[i * CH_PS + c] * zb[k0 + c];
-            zb[k0 + i] -= acc;
+            double s4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < CH_NB; c++) s4[c & 3] += P[i * CH_PS + c] * zb[k0 + c];
+            zb[k0 + i] -= (s4[0] + s4[1]) + (s4[2] + s4[3]);
         }
-        for (int i = tr; i < rows; i += TR)
-            if (tc < nk && (i >= nk || tc <= i)) A[(size_t)(k0 + i) * N + k0 + tc] = P[i * CH_PS + tc];
-        // ---- trailing update on FP64 MFMA: 16 x 16 tiles of the lower triangle
+        {
+            const int tr = tid >> 5, tc = tid & 31, TR = CH_THREADS / 32;
+            for (int i = tr; i < rows; i += TR)
+                if (tc < nk && (i >= nk || tc <= i)) A[(k0 + i) * N + k0 + tc] = P[i * CH_PS + tc];
+        }
+        // ---- trailing update, with the next diagonal block first (wave 0)
         if (m > 0) {
-            const int mt = (m + 15) / 16;
-            const int ntile = mt * (mt + 1) / 2;
-            for (int base = wave; base < ntile; base += 4 * NW) {
-                double4v c[4];
-                int ti[4], tj[4];
-#pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    const int tI = base + q * NW;
-                    int a = 0, bj = 0;
-                    if (tI < ntile) {
-                        a = (int)((sqrt(8.0 * tI + 1.0) - 1.0) * 0.5);
-                        while ((a + 1) * (a + 2) / 2 <= tI) a++;
-                        while (a * (a + 1) / 2 > tI) a--;
-                        bj = tI - a * (a + 1) / 2;
-                    } else {
-                        a = -1;
-                    }
-                    ti[q] = a;
-                    tj[q] = bj;
-                    const int i0 = nk + 16 * a, jj = nk + 16 * bj + l16;
-#pragma unroll
-                    for (int e = 0; e < 4; e++) {
-                        const int ii = i0 + l4 + 4 * e;       // f64 MFMA D layout
-                        c[q][e] = (a >= 0 && ii < rows && jj <= ii) ? A[(size_t)(k0 + ii) * N + k0 + jj] : 0.0;
-                    }
-                }
-                const double* pa[4];
-                const double* pb[4];
-#pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    const int tq = ti[q] < 0 ? 0 : ti[q];     // idle slots compute on row 0 (discarded)
-                    pa[q] = P + (nk + 16 * tq + l16) * CH_PS + l4;
-                    pb[q] = P + (nk + 16 * tj[q] + l16) * CH_PS + l4;
-                }
-#pragma unroll
-                for (int cc = 0; cc < CH_NB; cc += 4) {
-#pragma unroll
-                    for (int q = 0; q < 4; q++)
-                        c[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-pa[q][cc], pb[q][cc], c[q], 0, 0, 0);
-                }
-#pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    if (ti[q] < 0) continue;
-                    const int i0 = nk + 16 * ti[q], jj = nk + 16 * tj[q] + l16;
-#pragma unroll
-                    for (int e = 0; e < 4; e++) {
-                        const int ii = i0 + l4 + 4 * e;
-                        if (ii < rows && jj <= ii) A[(size_t)(k0 + ii) * N + k0 + jj] = c[q][e];
-                    }
-                }
+            const int mt = (m + 31) / 32;
+            const int nblk = mt * (mt + 1) / 2;
+            const double* src = k0 == 0 ? S : A;
+            const double* dq = k0 == 0 ? Dq : nullptr;
+            if (wave == 0) {
+                // the serial chain of the next panel: first in issue order on its SIMD
+                __builtin_amdgcn_s_setprio(3);
+                trail_block(N, k0, nk, rows, 0, 0, src, A, dq, P, Dn);
+                wave_sync();
+                const int bad = factor_diag(min(CH_NB, m), Dn, Iv,
+                                            ILg + (size_t)((k0 + nk) / CH_NB) * IV_DOUBLES, cb, dd, ds);
+                if (lane == 0) s_bad = bad;
+                __builtin_amdgcn_s_setprio(0);
+            }
+            for (;;) {
+                int g = 0;
+                if (lane == 0) g = atomicAdd(&s_next, 1);
+                g = __shfl(g, 0);
+                if (g >= nblk) break;
+                int a2 = (int)((sqrtf(8.0f * g + 1.0f) - 1.0f) * 0.5f);
+                while ((a2 + 1) * (a2 + 2) / 2 <= g) a2++;
+                while (a2 * (a2 + 1) / 2 > g) a2--;
+                trail_block(N, k0, nk, rows, a2, g - a2 * (a2 + 1) / 2, src, A, dq, P, nullptr);
             }
         }
         __syncthreads();
     }
-    back_subst(N, A, ILg, zb, P, IL, part);
+    back_subst(N, A, ILg, zb, P, Iv, Dn);
     for (int i = tid; i < N; i += CH_THREADS) x[i] = Dq[i] * zb[i];
 }
 
-// OWN: the standalone solve (psfm_cholesky_solve) copies the lower triangle
-// of M into the work matrix first and reports the pivot status; a separate
+// OWN: the standalone solve (psfm_cholesky_solve) reads M from a separate
+// matrix (left untouched) and reports the pivot status; a separate
 // instantiation, so that profiles tell the two uses apart.
 template <bool OWN>
 __global__ __launch_bounds__(CH_THREADS) void k_cholesky(int N, double* __restrict__ A,
@@ -574,15 +728,13 @@ __global__ __launch_bounds__(CH_THREADS) void k_cholesky(int N, double* __restri
                                                          const double* __restrict__ Msrc,
                                                          int* __restrict__ info) {
     if (OWN) {
-        for (int i = threadIdx.x >> 5; i < N; i += CH_THREADS / 32)
-            for (int j = threadIdx.x & 31; j <= i; j += 32) A[(size_t)i * N + j] = Msrc[(size_t)i * N + j];
         if (threadIdx.x == 0) {
             st->done = 0;
             st->info = 0;
         }
         __syncthreads();
     }
-    cholesky_body(N, A, b, x, ILg, Dg, st);
+    cholesky_body(N, A, OWN ? Msrc : A, b, x, ILg, Dg, st);
     if (OWN) {
         __syncthreads();
         if (threadIdx.x == 0) *info = st->info;
@@ -592,13 +744,13 @@ __global__ __launch_bounds__(CH_THREADS) void k_cholesky(int N, double* __restri
 // Batched: one workgroup per pair, all solved concurrently.
 __global__ __launch_bounds__(CH_THREADS) void k_cholesky_b(const PairDesc* __restrict__ pairs) {
     const PairDesc& p = pairs[blockIdx.x];
-    cholesky_body(p.N, p.A, p.b, p.coeffs, p.ILg, nullptr, p.st);
+    cholesky_body(p.N, p.A, p.A, p.b, p.coeffs, p.ILg, nullptr, p.st);
 }
 
 // Solution of M d = g with the factor left by cholesky_body (equilibrated
-// lower triangle in A, 1/sqrt(diag M) in Dg, the inverses of the 16 x 16
-// diagonal sub-blocks in ILg); x += d.  One workgroup.  This is the
-// correction step of the iterative refinement of the 16-bit modes.
+// lower triangle in A, 1/sqrt(diag M) in Dg, the diagonal-block inverses in
+// ILg); x += d.  One workgroup.  This is the correction step of the
+// iterative refinement of the 16-bit modes.
 __device__ __forceinline__ void resolve_body(int N, const double* __restrict__ A, const double* __restrict__ ILg,
                              const double* __restrict__ Dg, const double* __restrict__ g,
                              double* __restrict__ x, const SolveState* st) {
@@ -606,10 +758,9 @@ __device__ __forceinline__ void resolve_body(int N, const double* __restrict__ A
     extern __shared__ double P[];
     __shared__ double zb[CH_NMAX + 32];
     __shared__ double Dq[CH_NMAX];
-    __shared__ double IL[2][16 * IL_S];
+    __shared__ double Iv[CH_NB * CH_PS];
     __shared__ double part[CH_NB * (CH_THREADS / 32)];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int tr = tid >> 5, tc = tid & 31, TR = CH_THREADS / 32;
+    const int tid = threadIdx.x, wave = tid >> 6;
     for (int i = tid; i < N + 32; i += CH_THREADS) {
         zb[i] = i < N ? Dg[i] * g[i] : 0.0;
         if (i < N) Dq[i] = Dg[i];
@@ -618,47 +769,20 @@ __device__ __forceinline__ void resolve_body(int N, const double* __restrict__ A
     for (int k0 = 0; k0 < N; k0 += CH_NB) {
         const int nk = min(CH_NB, N - k0);
         const int rows = N - k0;
-        for (int i = tr; i < rows; i += TR)
-            P[i * CH_PS + tc] = (tc < nk && (i >= nk || tc <= i)) ? A[(size_t)(k0 + i) * N + k0 + tc] : 0.0;
-        for (int e = tid; e < 512; e += CH_THREADS) {
-            const int gg = e >> 8, q = (e >> 4) & 15, j = e & 15;
-            IL[gg][q * IL_S + j] = ILg[(size_t)(k0 / CH_NB) * 512 + e];
-        }
+        load_panel(N, A, k0, nk, nk, rows, rows, P, nullptr);
+        load_inverse(ILg, k0 / CH_NB, Iv);
         __syncthreads();
-        if (wave == 0) {
-            double z1 = 0.0;
-            if (lane < 16)
-                for (int k = 0; k < 16; k++) z1 += IL[0][lane * IL_S + k] * zb[k0 + k];
-            wave_sync();
-            if (lane < 16) zb[k0 + lane] = z1;
-            wave_sync();
-            double s2 = 0.0;
-            if (lane >= 16 && lane < 32) {
-                const int i = lane - 16;
-                s2 = zb[k0 + 16 + i];
-                for (int k = 0; k < 16; k++) s2 -= P[(16 + i) * CH_PS + k] * zb[k0 + k];
-            }
-            wave_sync();
-            if (lane >= 16 && lane < 32) zb[k0 + lane] = s2;
-            wave_sync();
-            double z2 = 0.0;
-            if (lane >= 16 && lane < 32) {
-                const int i = lane - 16;
-                for (int k = 0; k < 16; k++) z2 += IL[1][i * IL_S + k] * zb[k0 + 16 + k];
-            }
-            wave_sync();
-            if (lane >= 16 && lane < 32 && lane < nk) zb[k0 + lane] = z2;
-        }
+        if (wave == 0) diag_forward(k0, nk, Iv, zb);
         __syncthreads();
         for (int i = nk + tid; i < rows; i += CH_THREADS) {
-            double acc = 0.0;
-#pragma unroll 8
-            for (int c = 0; c < CH_NB; c++) acc += P[i * CH_PS + c] * zb[k0 + c];
-            zb[k0 + i] -= acc;
+            double s4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < CH_NB; c++) s4[c & 3] += P[i * CH_PS + c] * zb[k0 + c];
+            zb[k0 + i] -= (s4[0] + s4[1]) + (s4[2] + s4[3]);
         }
         __syncthreads();
     }
-    back_subst(N, A, ILg, zb, P, IL, part);
+    back_subst(N, A, ILg, zb, P, Iv, part);
     for (int i = tid; i < N; i += CH_THREADS) x[i] += Dq[i] * zb[i];
 }
 
@@ -1325,7 +1449,7 @@ size_t solve_workspace(const psfm_context* ctx, int n) {
     c.take<double>((size_t)n * (ctx->ns + 1) + 1);
     c.take<double>((size_t)ctx->N * ctx->N);
     c.take<double>(ctx->N);
-    c.take<double>((size_t)512 * ((ctx->N + CH_NB - 1) / CH_NB));
+    c.take<double>(psfm::solve_il_doubles(ctx->N));
     c.take<double>((size_t)n * ctx->L * ctx->L + 1);
     c.take<double>((size_t)n * ctx->L + 1);
     c.take<double>(ctx->N);                          // 1 / sqrt(diag M)
@@ -1356,9 +1480,11 @@ int solve_lds_grant(size_t lds) {
     return PSFM_OK;
 }
 
-size_t solve_lds_bytes(int N) { return (size_t)(N + 16) * CH_PS * sizeof(double); }
+// panel buffer: N + 16 rows (16-row tiles overrun the panel), at least 48
+// (the diagonal-block routines address all 32 rows of the block)
+size_t solve_lds_bytes(int N) { return (size_t)(max(N, CH_NB) + 16) * CH_PS * sizeof(double); }
 int solve_max_unknowns() { return CH_NMAX; }
-size_t solve_il_doubles(int N) { return (size_t)512 * ((N + CH_NB - 1) / CH_NB); }
+size_t solve_il_doubles(int N) { return (size_t)IV_DOUBLES * ((N + CH_NB - 1) / CH_NB); }
 
 // The whole solve loop for every pair of a batch: each launch covers all
 // pairs (blockIdx.y or one workgroup per pair); pairs that converged or
@@ -1418,8 +1544,7 @@ static int solve_impl(const psfm_context* ctx, int W, int H, const int32_t* stam
     if (ctx->N > CH_NMAX) return PSFM_ERR_UNSUPPORTED;
     const size_t need = psfm::solve_workspace(ctx, n_stamps);
     if (!ws || ws_bytes < need) return PSFM_ERR_WORKSPACE;
-    const size_t lds = (size_t)(ctx->N + 16) * CH_PS * sizeof(double);
-    if (lds > 140 * 1024) return PSFM_ERR_UNSUPPORTED;
+    const size_t lds = psfm::solve_lds_bytes(ctx->N);
     psfm::Carver c(ws);
     SolveState* state = c.take<SolveState>(1);
     uint8_t* used = c.take<uint8_t>(n_stamps + 1);
@@ -1428,7 +1553,7 @@ static int solve_impl(const psfm_context* ctx, int W, int H, const int32_t* stam
     double* GU = c.take<double>((size_t)n_stamps * (ctx->ns + 1) + 1);
     double* M = c.take<double>((size_t)ctx->N * ctx->N);
     double* b = c.take<double>(ctx->N);
-    double* ILg = c.take<double>((size_t)512 * ((ctx->N + CH_NB - 1) / CH_NB));
+    double* ILg = c.take<double>(psfm::solve_il_doubles(ctx->N));
     double* Mt = c.take<double>((size_t)n_stamps * ctx->L * ctx->L + 1);
     double* bt = c.take<double>((size_t)n_stamps * ctx->L + 1);
     double* Dg = c.take<double>(ctx->N);

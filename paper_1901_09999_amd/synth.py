@@ -99,19 +99,24 @@ ISIS_DEGREES = (6, 4, 2)
 
 WORKLOADS: Dict[str, Workload] = {
     # Plain method, CPU-seconds scale.
-    "cfg0": Workload("cfg0", 512, 512, 200, PsfField(1.5, 1.5), PsfField(2.2, 2.2),
+    "pair512": Workload("pair512", 512, 512, 200, PsfField(1.5, 1.5), PsfField(2.2, 2.2),
                      0.0, 10, ISIS_SIGMAS, ISIS_DEGREES, 0, 50, 20),
     # Plain FP32 GPU path with a spatially varying science PSF and a 10% mask.
-    "cfg1": Workload("cfg1", 2048, 2048, 2000, PsfField(1.2, 1.2), PsfField(1.4, 2.6, 0.2),
+    "pair2048": Workload("pair2048", 2048, 2048, 2000, PsfField(1.2, 1.2), PsfField(1.4, 2.6, 0.2),
                      0.10, 10, ISIS_SIGMAS, ISIS_DEGREES, 2, 100, 20),
     # Detector-chip-sized pair (GPC1 chip), 15% mask, 25x25 kernel, order 3.
-    "cfg2": Workload("cfg2", 4846, 4868, 8000, PsfField(1.2, 1.2), PsfField(1.4, 2.6, 0.2),
+    "chip4846": Workload("chip4846", 4846, 4868, 8000, PsfField(1.2, 1.2), PsfField(1.4, 2.6, 0.2),
                      0.15, 12, ISIS_SIGMAS, ISIS_DEGREES, 3, 400, 24),
 }
 
 
-def workload_seed(cfg_index: int, pair: int = 0) -> int:
-    return SEED_BASE + 1000 * cfg_index + pair
+# seed index of each named workload (pair k of a workload uses
+# SEED_BASE + 1000 * index + k)
+SEED_INDEX: Dict[str, int] = {"pair512": 0, "pair2048": 1, "chip4846": 2, "batch64": 3, "cells200k": 4}
+
+
+def workload_seed(index: int, pair: int = 0) -> int:
+    return SEED_BASE + 1000 * index + pair
 
 
 def _render(W: int, H: int, xs, ys, fluxes, psf: PsfField, theta: float) -> np.ndarray:
@@ -332,7 +337,7 @@ class BatchSpec:
     variable_frac: float = 0.05
 
 
-BATCHES: Dict[str, BatchSpec] = {"cfg3": BatchSpec()}
+BATCHES: Dict[str, BatchSpec] = {"batch64": BatchSpec()}
 
 
 def batch_pair_workload(spec: BatchSpec, k: int, cfg_index: int = 3) -> Workload:
@@ -511,7 +516,7 @@ class StampSetSpec:
     flux_hi: float = 1e5
 
 
-STAMP_SETS: Dict[str, StampSetSpec] = {"cfg4": StampSetSpec()}
+STAMP_SETS: Dict[str, StampSetSpec] = {"cells200k": StampSetSpec()}
 
 
 def _star_cells(torch, side, x0, y0, flux, sig, e, theta, device):

@@ -28,7 +28,7 @@ SPECS = [(300, 260, 0, 30, 200), (520, 384, 2, 40, 400), (330, 353, 1, 25, 300),
 def _pairs(specs, seed0=4242):
     out = []
     for k, (W, H, S, n, nsrc) in enumerate(specs):
-        wl = synth.scaled(synth.WORKLOADS["cfg1"], f"batch{k}", W, H, n_stamps=max(n, 1),
+        wl = synth.scaled(synth.WORKLOADS["pair2048"], f"batch{k}", W, H, n_stamps=max(n, 1),
                           spatial_order=S, n_sources=nsrc, mask_frac=0.04, variable_frac=0.1)
         p = synth.make_pair(wl, seed0 + k)
         if n == 0:

@@ -82,7 +82,7 @@ def test_adam_matches_oracle():
 def test_stamp_inputs_definition():
     torch, psfm = hip()
     from paper_1901_09999_amd import cnn
-    wl = synth.scaled(synth.WORKLOADS["cfg1"], "inp", 200, 150, n_sources=60, n_stamps=6)
+    wl = synth.scaled(synth.WORKLOADS["pair2048"], "inp", 200, 150, n_sources=60, n_stamps=6)
     p = synth.make_pair(wl, 31)
     d = psfm.to_device(p)
     st = np.array([[100, 75], [10, 12], [190, 140]], np.int32)    # inside, corner, edge
@@ -114,7 +114,7 @@ def test_stamp_inputs_definition():
 def test_per_stamp_solve_and_ortho_map_against_oracle():
     torch, psfm = hip()
     from paper_1901_09999_amd import cnn
-    spec = synth.STAMP_SETS["cfg4"]
+    spec = synth.STAMP_SETS["cells200k"]
     planes, stamps, par = synth.make_stamp_cells(spec, 64, 123)
     ctx = psfm.Context(psfm.Config(h=10, r=20, S=0, min_stamps=1))
     st = torch.from_numpy(stamps).cuda()

@@ -27,7 +27,7 @@ from gpu_common import hip, norm_err_M, oracle_run, pair_for
 
 pytestmark = pytest.mark.gpu
 
-SEEDS = {"cfg0": synth.workload_seed(0), "cfg1": synth.workload_seed(1)}
+SEEDS = {"pair512": synth.workload_seed(0), "pair2048": synth.workload_seed(1)}
 
 
 def _ctx(wl, **kw):
@@ -39,7 +39,7 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
-@pytest.mark.parametrize("name", ["cfg0", "cfg1"])
+@pytest.mark.parametrize("name", ["pair512", "pair2048"])
 def test_fit_stamps_parity(name):
     torch, psfm = hip()
     wl, pair = pair_for(name, SEEDS[name])
@@ -63,7 +63,7 @@ def test_fit_stamps_parity(name):
     assert np.max(np.abs(_np(fit["b"]) - ref["b"]) / den) < 2e-5
 
 
-@pytest.mark.parametrize("name", ["cfg0", "cfg1"])
+@pytest.mark.parametrize("name", ["pair512", "pair2048"])
 def test_solve_parity_same_sums(name):
     torch, psfm = hip()
     wl, pair = pair_for(name, SEEDS[name])
@@ -85,7 +85,7 @@ def test_solve_parity_same_sums(name):
     assert np.allclose(chi2, run["chi2"], rtol=1e-8, atol=1e-6)
 
 
-@pytest.mark.parametrize("name", ["cfg0", "cfg1"])
+@pytest.mark.parametrize("name", ["pair512", "pair2048"])
 def test_whole_path_parity(name):
     torch, psfm = hip()
     wl, pair = pair_for(name, SEEDS[name])
@@ -132,7 +132,7 @@ def test_whole_path_parity(name):
     assert dm.mean() < 5e-3
 
 
-@pytest.mark.parametrize("name", ["cfg0", "cfg1"])
+@pytest.mark.parametrize("name", ["pair512", "pair2048"])
 def test_convolution_parity(name):
     torch, psfm = hip()
     wl, pair = pair_for(name, SEEDS[name])
@@ -155,8 +155,8 @@ def test_convolution_parity(name):
 
 def test_variance_with_correlated_input():
     torch, psfm = hip()
-    wl, pair = pair_for("cfg0", SEEDS["cfg0"])
-    run = oracle_run("cfg0", SEEDS["cfg0"])
+    wl, pair = pair_for("pair512", SEEDS["pair512"])
+    run = oracle_run("pair512", SEEDS["pair512"])
     cfg = O.Config.from_workload(wl)
     q = np.array([[0.05, 0.2, 0.0], [0.1, 1.0, 0.3], [0.0, 0.2, 0.1]])
     cin = np.zeros((3, 3))
@@ -181,8 +181,8 @@ def test_variance_with_correlated_input():
 
 def test_subtract_parity():
     torch, psfm = hip()
-    wl, pair = pair_for("cfg1", SEEDS["cfg1"])
-    run = oracle_run("cfg1", SEEDS["cfg1"])
+    wl, pair = pair_for("pair2048", SEEDS["pair2048"])
+    run = oracle_run("pair2048", SEEDS["pair2048"])
     ctx = _ctx(wl)
     d = psfm.to_device(pair)
     t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
@@ -207,7 +207,7 @@ def test_ragged_shapes(W, H, P, h, r, S):
     below the 64-pixel tile, several kernel and stamp sizes, masks, and stamps
     whose footprint leaves the image."""
     torch, psfm = hip()
-    base = synth.WORKLOADS["cfg1"]
+    base = synth.WORKLOADS["pair2048"]
     wl = synth.scaled(base, f"rag{W}x{H}", W, H, n_sources=max(40, W * H // 600), n_stamps=30,
                       kernel_half=h, stamp_half=r, spatial_order=S, patch=P)
     pair = synth.make_pair(wl, 4242 + W)
@@ -244,7 +244,7 @@ def test_ragged_shapes(W, H, P, h, r, S):
 
 def test_too_few_stamps_and_empty():
     torch, psfm = hip()
-    wl, pair = pair_for("cfg0", SEEDS["cfg0"])
+    wl, pair = pair_for("pair512", SEEDS["pair512"])
     ctx = _ctx(wl)
     d = psfm.to_device(pair)
     M1 = d["M1"].clone()
@@ -334,8 +334,8 @@ def test_cholesky_solve_matches_oracle():
     (FP64 both; residual and kernel sum to 1e-9), and the same failing pivot
     for a matrix made indefinite."""
     torch, psfm = hip()
-    wl, pair = pair_for("cfg1", SEEDS["cfg1"])
-    ref = oracle_run("cfg1", SEEDS["cfg1"])
+    wl, pair = pair_for("pair2048", SEEDS["pair2048"])
+    ref = oracle_run("pair2048", SEEDS["pair2048"])
     cfg = O.Config.from_workload(wl)
     used = (ref["fit"]["flags"] == 0).astype(np.uint8)
     M, b = O.assemble(cfg, wl.width, wl.height, pair.stamps, ref["fit"]["M"], ref["fit"]["b"], used)

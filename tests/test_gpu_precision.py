@@ -48,7 +48,7 @@ def _run(psfm, torch, wl, pair, **kw):
 @pytest.mark.parametrize("prec,tol", [(2, 2e-3), (1, 1.6e-2)])
 def test_sixteen_bit_gram_and_design(prec, tol):
     torch, psfm = hip()
-    wl, pair = pair_for("cfg1", SEED1)
+    wl, pair = pair_for("pair2048", SEED1)
     ctx32 = psfm.Context(psfm.Config.from_workload(wl))
     ctx16 = psfm.Context(psfm.Config.from_workload(wl, precision=prec))
     d = psfm.to_device(pair)
@@ -77,8 +77,8 @@ def test_sixteen_bit_gram_and_design(prec, tol):
 @pytest.mark.parametrize("prec,refine,ktol", [(2, 1, 1e-4), (1, 2, 3e-4)])
 def test_sixteen_bit_whole_path(prec, refine, ktol):
     torch, psfm = hip()
-    wl, pair = pair_for("cfg1", SEED1)
-    ref = oracle_run("cfg1", SEED1)
+    wl, pair = pair_for("pair2048", SEED1)
+    ref = oracle_run("pair2048", SEED1)
     ctx, d, r = _run(psfm, torch, wl, pair, precision=prec, refine=refine)
     st, rs = psfm.read_stats(r["sol"]["stats"]), ref["stats"]
     ks = abs(st["kernel_sum_centre"] / rs["kernel_sum_centre"] - 1)
@@ -95,8 +95,8 @@ def test_sixteen_bit_whole_path(prec, refine, ktol):
 
 def test_refinement_reduces_the_error():
     torch, psfm = hip()
-    wl, pair = pair_for("cfg1", SEED1)
-    rs = oracle_run("cfg1", SEED1)["stats"]
+    wl, pair = pair_for("pair2048", SEED1)
+    rs = oracle_run("pair2048", SEED1)["stats"]
     errs = []
     for refine in (0, 1):
         _, _, r = _run(psfm, torch, wl, pair, precision=2, refine=refine, max_iter=1)
@@ -115,8 +115,8 @@ def test_refinement_reduces_the_error():
 
 
 @functools.lru_cache(maxsize=1)
-def _cfg2():
-    wl = synth.WORKLOADS["cfg2"]
+def _chip():
+    wl = synth.WORKLOADS["chip4846"]
     pair = synth.make_pair(wl, SEED2)
     cfg = O.Config.from_workload(wl)
     fit = O.fit_stamps(cfg, pair.I1, pair.M1, pair.I2, pair.V2, pair.M2, pair.stamps)
@@ -129,13 +129,13 @@ def test_detector_chip_full_size(prec):
     """4846 x 4868 pair, 25 x 25 kernel, order 3 (491 unknowns), 400 stamps:
     fit and solve against the oracle, image convolution on sampled tiles."""
     torch, psfm = hip()
-    wl, pair, cfg, a_ref, rs = _cfg2()
-    print(f"cfg2 precision {prec}: {pair.stamps.shape[0]} stamps", flush=True)
+    wl, pair, cfg, a_ref, rs = _chip()
+    print(f"chip4846 precision {prec}: {pair.stamps.shape[0]} stamps", flush=True)
     ctx, d, r = _run(psfm, torch, wl, pair, precision=prec, refine=1 if prec != 1 else 2)
     st = psfm.read_stats(r["sol"]["stats"])
     ks = abs(st["kernel_sum_centre"] / rs["kernel_sum_centre"] - 1)
     cd = abs(st["chi2_dof"] / rs["chi2_dof"] - 1)
-    print(f"cfg2 precision {prec}: kernel sum {ks:.2e}, chi2/dof {cd:.2e}, used {st['n_used']} "
+    print(f"chip4846 precision {prec}: kernel sum {ks:.2e}, chi2/dof {cd:.2e}, used {st['n_used']} "
           f"vs {rs['n_used']}")
     assert st["info"] == 0 and ks < 1e-4 and cd < 1e-2
     # convolution with the GPU's own coefficients on sampled tiles (edges, corner, interior)

@@ -38,7 +38,7 @@ def test_trained_prior_quality(trained):
 def _pairs():
     out = []
     for k, (W, H, S, seed) in enumerate([(1024, 1024, 2, 71), (1200, 900, 1, 72), (1024, 1024, 2, 73)]):
-        wl = synth.scaled(synth.WORKLOADS["cfg1"], f"prior{k}", W, H, n_stamps=150,
+        wl = synth.scaled(synth.WORKLOADS["pair2048"], f"prior{k}", W, H, n_stamps=150,
                           spatial_order=S, variable_frac=0.10)
         out.append((wl, synth.make_pair(wl, seed)))
     return out
@@ -101,7 +101,7 @@ def test_fallback_keeps_the_answer_under_a_poor_prior():
     either side: the chi2/dof is held to the 1.05 rule and the kernel sum to
     1e-3 of the plain answer."""
     torch, psfm = hip()
-    wl = synth.scaled(synth.WORKLOADS["cfg1"], "fallback", 1024, 1024, n_stamps=120, spatial_order=1)
+    wl = synth.scaled(synth.WORKLOADS["pair2048"], "fallback", 1024, 1024, n_stamps=120, spatial_order=1)
     pair = synth.make_pair(wl, 91)
     ctx = psfm.Context(psfm.Config.from_workload(wl))
     d = psfm.to_device(pair)

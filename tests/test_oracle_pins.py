@@ -476,7 +476,7 @@ def test_noiseless_difference_is_zero(orc):
 # ----------------------------------------------- rejection (Sections 3.3, 3.6)
 
 def test_rejection_removes_discrepant_stamp(orc):
-    wl = synth.scaled(synth.WORKLOADS["cfg0"], "t", 384, 384, n_stamps=30)
+    wl = synth.scaled(synth.WORKLOADS["pair512"], "t", 384, 384, n_stamps=30)
     pair = synth.make_pair(wl, 1234)
     # plant a transient (a source present only in image 2) in one stamp
     xc, yc = pair.stamps[4]
@@ -500,8 +500,8 @@ def test_too_few_stamps_is_an_error(orc):
     cfg, W, H, I1, I2, V2, Z = _tiny_problem()
     stamps = np.array([[6, 6], [7, 8]], np.int32)
     fit = O.fit_stamps(cfg, I1, Z, I2, V2, Z, stamps)
-    cfg3 = O.Config(**{**cfg.__dict__, "min_stamps": 3})
-    ret, a, chi2, fl, st = O.solve(cfg3, W, H, stamps, fit)
+    cfg_min3 = O.Config(**{**cfg.__dict__, "min_stamps": 3})
+    ret, a, chi2, fl, st = O.solve(cfg_min3, W, H, stamps, fit)
     assert ret == -3 and st["info"] == -3
 
 
@@ -512,7 +512,7 @@ def test_matched_filter_noise_statistic(orc):
     PSF-matching convolution, a Gaussian matched filter's output divided by
     the square root of its expected variance (variance map x covariance
     pseudo-matrix) has unit standard deviation (paper: within 6%)."""
-    wl = synth.WORKLOADS["cfg0"]
+    wl = synth.WORKLOADS["pair512"]
     pair = synth.make_pair(wl, synth.workload_seed(0))
     cfg = O.Config.from_workload(wl)
     res = O.match_pair(cfg, pair)

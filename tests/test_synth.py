@@ -9,7 +9,7 @@ from paper_1901_09999_amd import synth
 
 
 def test_batch_workloads_follow_the_spec():
-    spec = synth.BATCHES["cfg3"]
+    spec = synth.BATCHES["batch64"]
     wls = [synth.batch_pair_workload(spec, k) for k in range(spec.n_pairs)]
     assert len(wls) == 64
     for wl in wls:
@@ -25,7 +25,7 @@ def test_batch_workloads_follow_the_spec():
 
 def test_device_generator_on_cpu():
     torch = pytest.importorskip("torch")
-    wl = synth.scaled(synth.WORKLOADS["cfg1"], "gen", 400, 330, n_sources=300, n_stamps=30,
+    wl = synth.scaled(synth.WORKLOADS["pair2048"], "gen", 400, 330, n_sources=300, n_stamps=30,
                       variable_frac=0.05)
     p = synth.make_pair_device(wl, 1234, device="cpu")
     M1, M2 = p.M1.numpy(), p.M2.numpy()
