@@ -151,21 +151,37 @@ __device__ int load_halo(const float* __restrict__ src, const uint8_t* __restric
         for (int e = tid; e < HW * NWB; e += 256) (&badw[0][0])[e] = 0u;
         __syncthreads();
     }
+    // HALO_CHUNK pixels per thread in flight: the mask and value loads are
+    // unconditional (from a clamped in-image address) so none waits on another
+    constexpr int HALO_CHUNK = 8;
     int anybad = 0;
-    for (int e = tid; e < HW * HW; e += 256) {
-        const int hy = e / HW, hx = e - hy * HW;
-        const int gy = Y0 - H_ + hy, gx = X0 - H_ + hx;
-        float v = 0.0f;
-        bool ok = gx >= 0 && gx < W && gy >= 0 && gy < H;
-        if (ok) {
-            const int64_t o = (int64_t)gy * pitch + gx;
-            ok = M[o] == 0;
-            if (ok) v = src[o];
+    for (int e0 = tid; e0 < HW * HW; e0 += 256 * HALO_CHUNK) {
+        uint8_t m[HALO_CHUNK];
+        float v[HALO_CHUNK];
+        bool in[HALO_CHUNK];
+#pragma unroll
+        for (int u = 0; u < HALO_CHUNK; u++) {
+            const int e = e0 + 256 * u;
+            const int hy = e / HW, hx = e - hy * HW;
+            const int gy = Y0 - H_ + hy, gx = X0 - H_ + hx;
+            in[u] = e < HW * HW && gx >= 0 && gx < W && gy >= 0 && gy < H;
+            const int64_t o = in[u] ? (int64_t)gy * pitch + gx : 0;
+            m[u] = M[o];
+            v[u] = src[o];
         }
-        halo[e] = v;
-        if (!ok) {
-            anybad = 1;
-            if (BITS) atomicOr(&badw[hy][hx >> 5], 1u << (hx & 31));
+#pragma unroll
+        for (int u = 0; u < HALO_CHUNK; u++) {
+            const int e = e0 + 256 * u;
+            if (e >= HW * HW) continue;
+            const bool ok = in[u] && m[u] == 0;
+            halo[e] = ok ? v[u] : 0.0f;
+            if (!ok) {
+                anybad = 1;
+                if (BITS) {
+                    const int hy = e / HW, hx = e - hy * HW;
+                    atomicOr(&badw[hy][hx >> 5], 1u << (hx & 31));
+                }
+            }
         }
     }
     return __syncthreads_or(anybad);
@@ -457,15 +473,15 @@ __global__ __launch_bounds__(256) void k_subtract(
     for (int y = blockIdx.x; y < H; y += gridDim.x) {
         for (int x = threadIdx.x; x < W; x += 256) {
             const int64_t o = (int64_t)y * pitch + x;
+            // all six loads unconditional, so that none waits on another
             const uint8_t m2 = M2[o], cm = conv_mask[o];
-            const float cv = conv_var[o];
+            const float cv = conv_var[o], v2 = V2[o], i2 = I2[o], c1 = conv[o];
             if (m2) {
                 diff[o] = 0.0f;
                 diff_var[o] = 0.0f;
                 diff_mask[o] = (uint8_t)(PSFM_MASK_BAD | cm);
             } else {
-                const float v2 = V2[o];
-                diff[o] = (float)((double)I2[o] - (double)conv[o] - d0);
+                diff[o] = (float)((double)i2 - (double)c1 - d0);
                 diff_var[o] = (float)((double)v2 + (double)cv);
                 diff_mask[o] = cm;
                 s2 += v2;
@@ -580,6 +596,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             if (anybad) mask16<H_>(badw, s_rb, lx, r0, &bad16, &poor16);
             const double d0 = p.coeffs[p.N - 1];
             const int gx = X0 + lx;
+            // the target image's mask, values and variance of the 16 outputs,
+            // loaded together (clamped addresses outside the tile)
+            uint8_t m2v[16];
+            float i2v[16], v2v[16];
+#pragma unroll
+            for (int j = 0; j < 16; j++) {
+                const int gy = Y0 + r0 + j;
+                const int64_t o = (gx < X1 && gy < Y1) ? (int64_t)gy * pitch + gx : 0;
+                m2v[j] = p.M2[o];
+                i2v[j] = p.I2[o];
+                v2v[j] = p.V2[o];
+            }
             uint32_t m2bits = 0;
             if (gx < X1) {
 #pragma unroll
@@ -593,12 +621,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                             p.conv[o] = acc[j];
                             p.conv_mask[o] = cm;
                         }
-                        if (p.M2[o]) {
+                        if (m2v[j]) {
                             m2bits |= 1u << j;
                             p.diff[o] = 0.0f;
                             p.diff_mask[o] = (uint8_t)(PSFM_MASK_BAD | cm);
                         } else {
-                            p.diff[o] = (float)((double)p.I2[o] - (double)acc[j] - d0);
+                            p.diff[o] = (float)((double)i2v[j] - (double)acc[j] - d0);
                             p.diff_mask[o] = cm;
                         }
                     }
@@ -618,7 +646,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                         if ((m2bits >> j) & 1u) {
                             p.diff_var[o] = 0.0f;
                         } else {
-                            const float v2 = p.V2[o];
+                            const float v2 = v2v[j];
                             p.diff_var[o] = (float)((double)v2 + (double)cv);
                             s2 += v2;
                             n2 += 1.0;

@@ -157,17 +157,34 @@ __device__ void fit_band_body(const FitArgs& a, const int item, float* __restric
         const int rows = BR + 2 * H_;
         const int gy0 = yc - r + y_l0 - H_;
         const int gx0 = xc - R;
-        for (int e = tid; e < rows * WC; e += 256) {
-            const int wr = e / WC, wc = e - wr * WC;
-            float v = 0.0f;
-            if (wr < nbr + 2 * H_) {
-                const int64_t o = (int64_t)(gy0 + wr) * pitch + (gx0 + wc);
-                const float x = I1[o];
-                if (M1[o]) fl |= PSFM_STAMP_INVALID;
-                else if (!isfinite(x)) fl |= PSFM_STAMP_NONFINITE;
-                else v = x;
+        // WIN_CHUNK pixels per thread in flight (unconditional loads from a
+        // clamped address; rows past the band read pixel (gy0, gx0))
+        constexpr int WIN_CHUNK = 8;
+        for (int e0 = tid; e0 < rows * WC; e0 += 256 * WIN_CHUNK) {
+            float xv[WIN_CHUNK];
+            uint8_t mv[WIN_CHUNK];
+#pragma unroll
+            for (int u = 0; u < WIN_CHUNK; u++) {
+                const int e = e0 + 256 * u;
+                const int wr = e / WC, wc = e - wr * WC;
+                const bool in = e < rows * WC && wr < nbr + 2 * H_;
+                const int64_t o = (int64_t)(gy0 + (in ? wr : 0)) * pitch + (gx0 + (in ? wc : 0));
+                xv[u] = I1[o];
+                mv[u] = M1[o];
             }
-            win[e] = v;
+#pragma unroll
+            for (int u = 0; u < WIN_CHUNK; u++) {
+                const int e = e0 + 256 * u;
+                if (e >= rows * WC) continue;
+                const int wr = e / WC;
+                float v = 0.0f;
+                if (wr < nbr + 2 * H_) {
+                    if (mv[u]) fl |= PSFM_STAMP_INVALID;
+                    else if (!isfinite(xv[u])) fl |= PSFM_STAMP_NONFINITE;
+                    else v = xv[u];
+                }
+                win[e] = v;
+            }
         }
         for (int e = tid; e < nbr * NPX; e += 256) {
             const int br = e / NPX, x = e - br * NPX;
