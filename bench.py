@@ -15,6 +15,13 @@ variance map and a 21 x 21 covariance pseudo-matrix.
 6000 px a side, spatial order 0-3, 50-400 stamps) through psfm_batch_* as one
 HIP graph; also reports the p50 / p99 completion latency of the pairs.
 
+--workload cells200k: the learned prior's path on crowded single-star cells:
+`value` is CNN training throughput (stamps per second, FP16 forward /
+backward / Adam kernels, batch 256); also the dataset build rate (render,
+per-stamp fit and solve, targets and loss weights) and the cost of a solve
+with the prior beside a plain solve.  `cpu_baseline` is the FP64 NumPy CNN
+oracle's loss, gradient and Adam step on a bounded sample.
+
 Prints one JSON line.  `value` is pixels matched per second (Mpix/s).
 `roofline` is for the kernel with the largest share of the step (the FP64
 Cholesky at these system sizes; `roofline_other` holds the image
@@ -68,10 +75,10 @@ def source_sha(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(kernel_src):
-    """HBM bytes per launch of the convolution kernel from the committed
-    rocprofv3 counter summary, if it was taken on the current source."""
-    path = os.path.join(PROFILES, "conv_tile_pair2048_traffic.json")
+def measured_traffic(record, kernel_src):
+    """HBM bytes per launch of a kernel from its committed rocprofv3 counter
+    summary (profiles/<record>), if that was taken on the current source."""
+    path = os.path.join(PROFILES, record)
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -233,6 +240,116 @@ def bench_batch(args, torch, psfm, synth):
                                        "chi2_dof_rel_max": max(r[1] for r in rel)}
     print(json.dumps(out), flush=True)
 
+# multiply-adds per stamp of one training step of the stamp-pair CNN (forward,
+# data gradients of layers 2..6 and fc, weight gradients of every layer)
+CNN_FWD_MAC = 41 * 41 * 32 * 2 * 9 + 21 * 21 * 32 * 32 * 9 + 11 * 11 * 32 * 32 * 9 + 6 * 6 * 32 * 32 * 9 \
+    + 1152 * 128 + 128 * 49
+CNN_TRAIN_FLOP = 2 * (2 * CNN_FWD_MAC + (CNN_FWD_MAC - 41 * 41 * 32 * 2 * 9))
+
+
+def bench_cells(args, torch, psfm, synth):
+    from paper_1901_09999_amd import cnn
+    B = 256
+    n_data = 25_000
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    data = cnn.make_dataset(n_data, seed=synth.workload_seed(synth.SEED_INDEX["cells200k"]))
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    z = cnn.standardize(data)
+    n = z["x"].shape[0]
+    net = cnn.Net(seed=1)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    g = torch.Generator(device="cpu")
+    g.manual_seed(0)
+    batches = [torch.randint(0, n, (B,), generator=g).cuda() for _ in range(8)]
+
+    def step(k):
+        idx = batches[k % len(batches)]
+        net.loss_grad(z["x"][idx], z["target"][idx], loss, z["weight"][idx])
+        net.adam(1e-3)
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(args.steps):
+        step(k)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    rate = B / (ms * 1e-3)
+    achieved = CNN_TRAIN_FLOP * B / (ms * 1e-3) / 1e12
+
+    # the prior in use: plain solve and solve with the predicted kernels on one pair
+    wl = synth.scaled(synth.WORKLOADS["pair2048"], "prior", 1024, 1024, n_stamps=150, spatial_order=2,
+                      variable_frac=0.10)
+    pair = synth.make_pair(wl, synth.workload_seed(synth.SEED_INDEX["cells200k"], 1))
+    d = psfm.to_device(pair)
+    ctx = psfm.Context(psfm.Config.from_workload(wl))
+    fit = ctx.fit_stamps(d["I1"], d["M1"], d["I2"], d["V2"], d["M2"], d["stamps"])
+    net.fold_output(z["mu"], z["sd"])
+
+    def timed(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    t_plain = timed(lambda: ctx.solve(wl.width, wl.height, d["stamps"], fit))
+    t_pred = timed(lambda: cnn.predict_local(ctx, net, d["I1"], d["M1"], d["I2"], d["M2"], d["stamps"]))
+    pred = cnn.predict_local(ctx, net, d["I1"], d["M1"], d["I2"], d["M2"], d["stamps"])
+    t_prior = timed(lambda: ctx.solve(wl.width, wl.height, d["stamps"], fit, prior=pred))
+
+    out = {
+        "metric": "CNN training throughput (learned prior)",
+        "value": round(rate, 1),
+        "unit": "stamps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16 storage, f32 accumulate",
+        "data": "synthetic",
+        "config": {"workload": f"cells200k: single-star 64x64 cells with neighbours, 41x41 stamp pairs, "
+                               f"batch {B}; dataset of {n} stamps from {n_data} cells"},
+        "roofline": dict(kernel="whole training step (forward, backward, Adam; the weight-gradient "
+                                "kernels hold most of it)", bound="alu",
+                         achieved=round(achieved, 3), peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s",
+                         frac=round(achieved / FP32_VALU_PEAK_TFLOPS, 4), traffic=None,
+                         algorithmic_flops_per_stamp=CNN_TRAIN_FLOP),
+        "dataset": {"stamps_per_s": round(n_data / t_data, 1), "seconds": round(t_data, 3)},
+        "prior": {"solve_ms": round(t_plain, 3), "predict_ms": round(t_pred, 3),
+                  "solve_prior_ms": round(t_prior, 3), "stamps": int(pair.stamps.shape[0])},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import cnn_oracle as CO
+        xs = z["x"][batches[0][:8]].float().cpu().numpy().astype(np.float64)
+        ts = z["target"][batches[0][:8]].cpu().numpy().astype(np.float64)
+        wt = z["weight"][batches[0][:8]].cpu().numpy().astype(np.float64)
+        theta = CO.init_params(1)
+        m, v = np.zeros_like(theta), np.zeros_like(theta)
+        done, c0, w0 = 0, time.process_time(), time.perf_counter()
+        while done == 0 or (time.perf_counter() - w0 < args.cpu_seconds and done < 400):
+            _, gr = CO.loss_and_grad(theta, xs, ts, wt)
+            theta, m, v = CO.adam_step(theta, m, v, gr, done + 1, lr=1e-3)
+            done += xs.shape[0]
+        wall, cpu = time.perf_counter() - w0, time.process_time() - c0
+        out["cpu_baseline"] = dict(value=round(done / wall, 2), unit="stamps/s",
+                                   cores=max(1, int(round(cpu / wall))), kind="oracle",
+                                   sample=f"FP64 NumPy loss, gradient and Adam step on batches of "
+                                          f"{xs.shape[0]} stamps, {done} stamps in {wall:.1f} s")
+    print(json.dumps(out), flush=True)
+
 
 def main():
     args = parse()
@@ -256,6 +373,8 @@ def main():
         del src, dst
     if args.workload in synth.BATCHES:
         return bench_batch(args, torch, psfm, synth)
+    if args.workload in synth.STAMP_SETS:
+        return bench_cells(args, torch, psfm, synth)
     wl = synth.WORKLOADS[args.workload]
     seed_index = synth.SEED_INDEX[args.workload]
     pair = synth.make_pair(wl, synth.workload_seed(seed_index))
@@ -319,7 +438,8 @@ def main():
     T = (2 * wl.kernel_half + 1) ** 2
     flops = 2.0 * T * W * H
     achieved = flops / (conv_us * 1e-6) / 1e12
-    traffic = measured_traffic(os.path.join(ROOT, "paper_1901_09999_amd", "csrc", "convolve.hip"))
+    traffic = measured_traffic("conv_tile_pair2048_traffic.json" if wl.name == "pair2048" else "-",
+                               os.path.join(ROOT, "paper_1901_09999_amd", "csrc", "convolve.hip"))
     roof_conv = dict(kernel="k_conv_tile<h, 0> (image convolution)", bound="alu",
                      achieved=round(achieved, 2), peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s",
                      frac=round(achieved / FP32_VALU_PEAK_TFLOPS, 4), traffic=traffic,
@@ -349,7 +469,9 @@ def main():
                      bound="mfma", achieved=round(chol_flops / (chol_us * 1e-6) / 1e12, 4),
                      peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
                      frac=round(chol_flops / (chol_us * 1e-6) / 1e12 / FP64_PEAK_TFLOPS, 6),
-                     traffic=None, avg_launch_us=round(chol_us, 2),
+                     traffic=measured_traffic(f"cholesky_n{Nu}_traffic.json",
+                                              os.path.join(ROOT, "paper_1901_09999_amd", "csrc", "solve.hip")),
+                     avg_launch_us=round(chol_us, 2),
                      algorithmic_flops_per_launch=chol_flops, launches_per_step=chol_per_step)
     share_chol = chol_per_step * chol_us / (gpu_ms * 1e3)
     share_conv = conv_us / (gpu_ms * 1e3)

@@ -14,9 +14,10 @@
 //                    so a pixel's 32 products read 8 broadcast 16-byte words;
 //   k_conv_bwd_data  one thread per input pixel, all input channels, the
 //                    ReLU mask of the layer below applied on the way out;
-//   k_conv_bwd_w     one workgroup per (o, c): the 9 weight gradients (and
-//                    the bias gradient) summed over batch and pixels in a
-//                    fixed order;
+//   k_conv_bwd_w     one workgroup per (o, c) and batch chunk: partial sums
+//                    of the 9 weight gradients (and the bias gradient) over
+//                    the chunk's pixels; k_conv_bwd_w_sum adds the chunks in
+//                    a fixed order;
 //   k_fc_fwd / k_fc_bwd_x / k_fc_bwd_w, k_mse, k_adam.
 // The backward pass stores activation gradients in FP32.
 #include "internal.h"
@@ -159,39 +160,56 @@ __device__ __forceinline__ float block_sum_f(float v, float* red) {
 template <int S>
 __global__ __launch_bounds__(256) void k_conv_bwd_w(const float* __restrict__ dy, int Hout,
                                                     const __half* __restrict__ x, int CIN, int Hin,
-                                                    int B, float* __restrict__ dw,
-                                                    float* __restrict__ db) {
+                                                    int B, float* __restrict__ part) {
     __shared__ float red[4];
     const int o = blockIdx.x / CIN, c = blockIdx.x % CIN;
+    const int nsplit = gridDim.y, split = blockIdx.y;
+    const int b0 = split * B / nsplit, b1 = (split + 1) * B / nsplit;
     float acc[9];
 #pragma unroll
     for (int k = 0; k < 9; k++) acc[k] = 0.0f;
     float accb = 0.0f;
     const int npix = Hout * Hout;
-    for (int t = threadIdx.x; t < B * npix; t += 256) {
+    for (int t = b0 * npix + threadIdx.x; t < b1 * npix; t += 256) {
         const int b = t / npix, pp = t - b * npix;
         const int i = pp / Hout, j = pp - i * Hout;
         const float g = dy[((size_t)b * CH + o) * npix + pp];
         accb += g;
         const __half* xc = x + ((size_t)b * CIN + c) * Hin * Hin;
+        // nine input loads, unconditional from clamped addresses (zero outside)
+        float xv[9];
 #pragma unroll
-        for (int u = 0; u < 3; u++) {
-            const int pi = S * i + u - 1;
+        for (int u = 0; u < 3; u++)
 #pragma unroll
             for (int v = 0; v < 3; v++) {
-                const int qj = S * j + v - 1;
-                if (pi >= 0 && pi < Hin && qj >= 0 && qj < Hin)
-                    acc[u * 3 + v] = fmaf(g, h2f(xc[pi * Hin + qj]), acc[u * 3 + v]);
+                const int pi = S * i + u - 1, qj = S * j + v - 1;
+                const bool in = pi >= 0 && pi < Hin && qj >= 0 && qj < Hin;
+                const float xx = h2f(xc[in ? pi * Hin + qj : 0]);
+                xv[u * 3 + v] = in ? xx : 0.0f;
             }
-        }
+#pragma unroll
+        for (int k = 0; k < 9; k++) acc[k] = fmaf(g, xv[k], acc[k]);
     }
+    float* pw = part + (size_t)split * (CH * CIN * 9 + CH);
 #pragma unroll
     for (int k = 0; k < 9; k++) {
         const float s = block_sum_f(acc[k], red);
-        if (threadIdx.x == 0) dw[(o * CIN + c) * 9 + k] = s;
+        if (threadIdx.x == 0) pw[(o * CIN + c) * 9 + k] = s;
     }
     const float sb = block_sum_f(accb, red);
-    if (c == 0 && threadIdx.x == 0) db[o] = sb;
+    if (c == 0 && threadIdx.x == 0) pw[CH * CIN * 9 + o] = sb;
+}
+
+// dw = sum over the batch chunks of the partials of k_conv_bwd_w (fixed order).
+__global__ __launch_bounds__(256) void k_conv_bwd_w_sum(const float* __restrict__ part, int nsplit,
+                                                        int nw, float* __restrict__ dw,
+                                                        float* __restrict__ db) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= nw + CH) return;
+    float s = 0.0f;
+    for (int k = 0; k < nsplit; k++) s += part[(size_t)k * (nw + CH) + t];
+    if (t < nw) dw[t] = s;
+    else db[t - nw] = s;
 }
 
 // y[b,n] = bias[n] + sum_k W[n,k] x[b,k]  (ReLU -> FP16 out, or FP32 out)
@@ -448,9 +466,28 @@ __global__ __launch_bounds__(64) void k_loss_weight(const double* __restrict__ R
     }
 }
 
+constexpr int WSPLIT_MAX = 32;   // batch chunks of the weight-gradient reduction
+
+// Weight gradient of one convolution layer: (o, c) pairs x batch chunks
+// (enough workgroups to fill the chip), then the chunk partials summed in
+// a fixed order.
+template <int S>
+void conv_bwd_w(hipStream_t st, const float* dy, int Hout, const __half* x, int CIN, int Hin, int B,
+                float* wpart, float* dw, float* db) {
+    const int pairs = CH * CIN;
+    int nsplit = (2048 + pairs - 1) / pairs;
+    nsplit = nsplit < 1 ? 1 : nsplit > WSPLIT_MAX ? WSPLIT_MAX : nsplit;
+    if (nsplit > B) nsplit = B;
+    hipLaunchKernelGGL((k_conv_bwd_w<S>), dim3(pairs, nsplit), dim3(256), 0, st, dy, Hout, x, CIN, Hin, B,
+                       wpart);
+    const int nw = pairs * 9;
+    hipLaunchKernelGGL(k_conv_bwd_w_sum, dim3((nw + CH + 255) / 256), dim3(256), 0, st, wpart, nsplit, nw,
+                       dw, db);
+}
+
 struct Acts {
     __half *a1, *a2, *a3, *a4, *h;
-    float *out, *dout, *dh, *d4, *d3, *d2, *d1, *part;
+    float *out, *dout, *dh, *d4, *d3, *d2, *d1, *part, *wpart;
     size_t bytes;
 };
 
@@ -470,6 +507,7 @@ Acts carve(void* base, int B) {
     A.d2 = c.take<float>((size_t)B * CH * SIDE2 * SIDE2);
     A.d1 = c.take<float>((size_t)B * CH * SIDE1 * SIDE1);
     A.part = c.take<float>((size_t)B);
+    A.wpart = c.take<float>((size_t)WSPLIT_MAX * (CH * CH * 9 + CH));
     A.bytes = c.off;
     return A;
 }
@@ -547,20 +585,16 @@ extern "C" int psfm_cnn_loss_grad(const uint16_t* w16, const uint16_t* x, const 
     hipLaunchKernelGGL(k_fc_bwd_x, dim3((B * FLAT + 255) / 256), dim3(256), 0, st, A.dh, HID,
                        w + OFF_F1W, A.a4, FLAT, B, A.d4);
     // conv4 .. conv1 (d_k: gradient at the pre-activation of conv k, ReLU applied)
-    hipLaunchKernelGGL((k_conv_bwd_w<2>), dim3(CH * CH), dim3(256), 0, st, A.d4, SIDE4, A.a3, CH, SIDE3,
-                       B, grad + OFF_C4W, grad + OFF_C4B);
+    conv_bwd_w<2>(st, A.d4, SIDE4, A.a3, CH, SIDE3, B, A.wpart, grad + OFF_C4W, grad + OFF_C4B);
     hipLaunchKernelGGL((k_conv_bwd_data<2>), dim3(grid_for((size_t)B * SIDE3 * SIDE3)), dim3(256), 0, st,
                        A.d4, SIDE4, w + OFF_C4W, A.a3, A.d3, SIDE3, B);
-    hipLaunchKernelGGL((k_conv_bwd_w<2>), dim3(CH * CH), dim3(256), 0, st, A.d3, SIDE3, A.a2, CH, SIDE2,
-                       B, grad + OFF_C3W, grad + OFF_C3B);
+    conv_bwd_w<2>(st, A.d3, SIDE3, A.a2, CH, SIDE2, B, A.wpart, grad + OFF_C3W, grad + OFF_C3B);
     hipLaunchKernelGGL((k_conv_bwd_data<2>), dim3(grid_for((size_t)B * SIDE2 * SIDE2)), dim3(256), 0, st,
                        A.d3, SIDE3, w + OFF_C3W, A.a2, A.d2, SIDE2, B);
-    hipLaunchKernelGGL((k_conv_bwd_w<2>), dim3(CH * CH), dim3(256), 0, st, A.d2, SIDE2, A.a1, CH, SIDE1,
-                       B, grad + OFF_C2W, grad + OFF_C2B);
+    conv_bwd_w<2>(st, A.d2, SIDE2, A.a1, CH, SIDE1, B, A.wpart, grad + OFF_C2W, grad + OFF_C2B);
     hipLaunchKernelGGL((k_conv_bwd_data<2>), dim3(grid_for((size_t)B * SIDE1 * SIDE1)), dim3(256), 0, st,
                        A.d2, SIDE2, w + OFF_C2W, A.a1, A.d1, SIDE1, B);
-    hipLaunchKernelGGL((k_conv_bwd_w<1>), dim3(CH * 2), dim3(256), 0, st, A.d1, SIDE1, x0, 2, SIDE0, B,
-                       grad + OFF_C1W, grad + OFF_C1B);
+    conv_bwd_w<1>(st, A.d1, SIDE1, x0, 2, SIDE0, B, A.wpart, grad + OFF_C1W, grad + OFF_C1B);
     PSFM_HIP_CHECK(hipGetLastError());
     return PSFM_OK;
 }
