@@ -14,10 +14,13 @@
 //                    so a pixel's 32 products read 8 broadcast 16-byte words;
 //   k_conv_bwd_data  one thread per input pixel, all input channels, the
 //                    ReLU mask of the layer below applied on the way out;
-//   k_conv_bwd_w     one workgroup per (o, c) and batch chunk: partial sums
-//                    of the 9 weight gradients (and the bias gradient) over
-//                    the chunk's pixels; k_conv_bwd_w_sum adds the chunks in
-//                    a fixed order;
+//   k_conv_bwd_w_gemm  32 -> 32 layers: the weight gradients as a GEMM over
+//                    the pixels, chunks of output gradients and input patches
+//                    staged in LDS, 4 x 9 sums per thread, a partial set per
+//                    workgroup;
+//   k_conv_bwd_w     first layer (2 input channels): one workgroup per (o, c)
+//                    and batch chunk;
+//   k_conv_bwd_w_sum adds the partial sets in a fixed order;
 //   k_fc_fwd / k_fc_bwd_x / k_fc_bwd_w, k_mse, k_adam.
 // The backward pass stores activation gradients in FP32.
 #include "internal.h"
@@ -200,16 +203,128 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(const float* __restrict__ dy
     if (c == 0 && threadIdx.x == 0) pw[CH * CIN * 9 + o] = sb;
 }
 
-// dw = sum over the batch chunks of the partials of k_conv_bwd_w (fixed order).
+// Weight and bias gradients of a 32 -> 32 layer as a GEMM over the pixels
+// p = (b, i, j):  dW[o][(c,u,v)] = sum_p dy[p][o] X[p][(c,u,v)],  X the
+// (zero-padded, strided) input patches.  Workgroup g stages chunks of WG_PIX
+// pixels (g, g + G, ...) of dy and X in LDS; thread (ob, c) accumulates the
+// 4 x 9 sums of outputs 4 ob .. 4 ob + 3 and input channel c (the bias sums
+// ride with c = 0).  Partials per workgroup, (CH * CH * 9 + CH) floats each.
+constexpr int WG_PIX = 32;
+constexpr int WG_MAXG = 256;
+template <int S>
+__global__ __launch_bounds__(256) void k_conv_bwd_w_gemm(const float* __restrict__ dy, int Hout,
+                                                         const __half* __restrict__ x, int Hin, int B,
+                                                         float* __restrict__ part) {
+    __shared__ float sdy[WG_PIX][CH + 1];
+    __shared__ float sx[WG_PIX][CH * 9 + 1];
+    __shared__ int sb[WG_PIX], spp[WG_PIX], si[WG_PIX], sj[WG_PIX];
+    const int tid = threadIdx.x, ob = tid >> 5, c = tid & 31;
+    const int npix = Hout * Hout, NP = B * npix, nch = (NP + WG_PIX - 1) / WG_PIX;
+    float acc[4][9], accb[4];
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+        accb[a] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 9; k++) acc[a][k] = 0.0f;
+    }
+    for (int q = blockIdx.x; q < nch; q += gridDim.x) {
+        const int p0 = q * WG_PIX;
+        // the chunk's pixels (b, i, j), decoded once (b = -1 past the end)
+        if (tid < WG_PIX) {
+            const int pg = p0 + tid, b = pg / npix, pp = pg - b * npix, i = pp / Hout;
+            sb[tid] = pg < NP ? b : -1;
+            spp[tid] = pp;
+            si[tid] = i;
+            sj[tid] = pp - i * Hout;
+        }
+        __syncthreads();
+        // stage dy (WG_PIX x CH) and the patches (WG_PIX x CH*9); loads from
+        // clamped addresses, zero outside the chunk or the input
+        // all loads first (one round trip), then the LDS stores
+        constexpr int ND = WG_PIX * CH / 256, NX = WG_PIX * CH * 9 / 256;
+        float dv[ND];
+        __half xh[NX];
+#pragma unroll
+        for (int k = 0; k < ND; k++) {
+            const int e = tid + 256 * k, pl = e % WG_PIX, o = e / WG_PIX;
+            const int b = sb[pl];
+            dv[k] = dy[b >= 0 ? ((size_t)b * CH + o) * npix + spp[pl] : 0];
+        }
+#pragma unroll
+        for (int k = 0; k < NX; k++) {
+            const int e = tid + 256 * k, pl = e % WG_PIX, cuv = e / WG_PIX;
+            const int cc = cuv / 9, uv = cuv - 9 * cc, u = uv / 3, v = uv - 3 * u;
+            const int b = sb[pl];
+            const int pi = S * si[pl] + u - 1, qj = S * sj[pl] + v - 1;
+            const bool in = b >= 0 && pi >= 0 && pi < Hin && qj >= 0 && qj < Hin;
+            xh[k] = x[in ? ((size_t)b * CH + cc) * Hin * Hin + pi * Hin + qj : 0];
+        }
+#pragma unroll
+        for (int k = 0; k < ND; k++) {
+            const int e = tid + 256 * k, pl = e % WG_PIX, o = e / WG_PIX;
+            sdy[pl][o] = sb[pl] >= 0 ? dv[k] : 0.0f;
+        }
+#pragma unroll
+        for (int k = 0; k < NX; k++) {
+            const int e = tid + 256 * k, pl = e % WG_PIX, cuv = e / WG_PIX;
+            const int cc = cuv / 9, uv = cuv - 9 * cc, u = uv / 3, v = uv - 3 * u;
+            const int pi = S * si[pl] + u - 1, qj = S * sj[pl] + v - 1;
+            const bool in = sb[pl] >= 0 && pi >= 0 && pi < Hin && qj >= 0 && qj < Hin;
+            sx[pl][cuv] = in ? h2f(xh[k]) : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int pl = 0; pl < WG_PIX; pl++) {
+            float g[4], xv[9];
+#pragma unroll
+            for (int a = 0; a < 4; a++) g[a] = sdy[pl][4 * ob + a];
+#pragma unroll
+            for (int k = 0; k < 9; k++) xv[k] = sx[pl][c * 9 + k];
+#pragma unroll
+            for (int a = 0; a < 4; a++) {
+                accb[a] += g[a];
+#pragma unroll
+                for (int k = 0; k < 9; k++) acc[a][k] = fmaf(g[a], xv[k], acc[a][k]);
+            }
+        }
+        __syncthreads();
+    }
+    float* pw = part + (size_t)blockIdx.x * (CH * CH * 9 + CH);
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+        const int o = 4 * ob + a;
+#pragma unroll
+        for (int k = 0; k < 9; k++) pw[(o * CH + c) * 9 + k] = acc[a][k];
+        if (c == 0) pw[CH * CH * 9 + o] = accb[a];
+    }
+}
+
+// dw = sum of the nsplit partial sets of the weight-gradient kernels: 64
+// outputs per workgroup, each summed by four thread groups over fixed ranges
+// of the sets (two accumulators each), the four group sums added in order.
 __global__ __launch_bounds__(256) void k_conv_bwd_w_sum(const float* __restrict__ part, int nsplit,
                                                         int nw, float* __restrict__ dw,
                                                         float* __restrict__ db) {
-    const int t = blockIdx.x * 256 + threadIdx.x;
-    if (t >= nw + CH) return;
-    float s = 0.0f;
-    for (int k = 0; k < nsplit; k++) s += part[(size_t)k * (nw + CH) + t];
-    if (t < nw) dw[t] = s;
-    else db[t - nw] = s;
+    __shared__ float gs[4][64];
+    const int l = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    const int t = blockIdx.x * 64 + l;
+    const int k0 = grp * nsplit / 4, k1 = (grp + 1) * nsplit / 4;
+    float s0 = 0.0f, s1 = 0.0f;
+    if (t < nw + CH) {
+        int k = k0;
+        for (; k + 1 < k1; k += 2) {
+            s0 += part[(size_t)k * (nw + CH) + t];
+            s1 += part[(size_t)(k + 1) * (nw + CH) + t];
+        }
+        if (k < k1) s0 += part[(size_t)k * (nw + CH) + t];
+    }
+    gs[grp][l] = s0 + s1;
+    __syncthreads();
+    if (grp == 0 && t < nw + CH) {
+        const float s = ((gs[0][l] + gs[1][l]) + gs[2][l]) + gs[3][l];
+        if (t < nw) dw[t] = s;
+        else db[t - nw] = s;
+    }
 }
 
 // y[b,n] = bias[n] + sum_k W[n,k] x[b,k]  (ReLU -> FP16 out, or FP32 out)
@@ -474,6 +589,16 @@ constexpr int WSPLIT_MAX = 32;   // batch chunks of the weight-gradient reductio
 template <int S>
 void conv_bwd_w(hipStream_t st, const float* dy, int Hout, const __half* x, int CIN, int Hin, int B,
                 float* wpart, float* dw, float* db) {
+    if (CIN == CH) {
+        const int nch = (B * Hout * Hout + WG_PIX - 1) / WG_PIX;
+        int G = (nch + 7) / 8;                    // at least eight pixel chunks per workgroup
+        G = G < 1 ? 1 : G > WG_MAXG ? WG_MAXG : G;
+        hipLaunchKernelGGL((k_conv_bwd_w_gemm<S>), dim3(G), dim3(256), 0, st, dy, Hout, x, Hin, B, wpart);
+        const int nw = CH * CH * 9;
+        hipLaunchKernelGGL(k_conv_bwd_w_sum, dim3((nw + CH + 63) / 64), dim3(256), 0, st, wpart, G, nw,
+                           dw, db);
+        return;
+    }
     const int pairs = CH * CIN;
     int nsplit = (2048 + pairs - 1) / pairs;
     nsplit = nsplit < 1 ? 1 : nsplit > WSPLIT_MAX ? WSPLIT_MAX : nsplit;
@@ -481,7 +606,7 @@ void conv_bwd_w(hipStream_t st, const float* dy, int Hout, const __half* x, int 
     hipLaunchKernelGGL((k_conv_bwd_w<S>), dim3(pairs, nsplit), dim3(256), 0, st, dy, Hout, x, CIN, Hin, B,
                        wpart);
     const int nw = pairs * 9;
-    hipLaunchKernelGGL(k_conv_bwd_w_sum, dim3((nw + CH + 255) / 256), dim3(256), 0, st, wpart, nsplit, nw,
+    hipLaunchKernelGGL(k_conv_bwd_w_sum, dim3((nw + CH + 63) / 64), dim3(256), 0, st, wpart, nsplit, nw,
                        dw, db);
 }
 
@@ -507,7 +632,7 @@ Acts carve(void* base, int B) {
     A.d2 = c.take<float>((size_t)B * CH * SIDE2 * SIDE2);
     A.d1 = c.take<float>((size_t)B * CH * SIDE1 * SIDE1);
     A.part = c.take<float>((size_t)B);
-    A.wpart = c.take<float>((size_t)WSPLIT_MAX * (CH * CH * 9 + CH));
+    A.wpart = c.take<float>((size_t)(WSPLIT_MAX > WG_MAXG ? WSPLIT_MAX : WG_MAXG) * (CH * CH * 9 + CH));
     A.bytes = c.off;
     return A;
 }
