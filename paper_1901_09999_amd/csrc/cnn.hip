@@ -333,15 +333,21 @@ __global__ __launch_bounds__(256) void k_fc_fwd(const __half* __restrict__ x, in
                                                 const __half* __restrict__ W,
                                                 const __half* __restrict__ bias, int N, int B,
                                                 __half* __restrict__ y16, float* __restrict__ y32) {
-    const int t = blockIdx.x * 256 + threadIdx.x;
+    // one wave per output: the lanes stride over k (coalesced rows of x and
+    // W), then a fixed-order shuffle sum
+    const int t = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (t >= B * N) return;
     const int b = t / N, n = t - b * N;
     const __half* xr = x + (size_t)b * K;
     const __half* wr = W + (size_t)n * K;
-    float acc = h2f(bias[n]);
-    for (int k = 0; k < K; k++) acc = fmaf(h2f(wr[k]), h2f(xr[k]), acc);
-    if (RELU) y16[t] = __float2half(fmaxf(acc, 0.0f));
-    else y32[t] = acc;
+    float acc = 0.0f;
+    for (int k = lane; k < K; k += 64) acc = fmaf(h2f(wr[k]), h2f(xr[k]), acc);
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    acc += h2f(bias[n]);
+    if (lane == 0) {
+        if (RELU) y16[t] = __float2half(fmaxf(acc, 0.0f));
+        else y32[t] = acc;
+    }
 }
 
 // dxm[b,k] = (sum_n W[n,k] dy[b,n]) * (x[b,k] > 0)
@@ -364,9 +370,14 @@ __global__ __launch_bounds__(256) void k_fc_bwd_w(const float* __restrict__ dy, 
     const int t = blockIdx.x * 256 + threadIdx.x;
     if (t < N * K) {
         const int n = t / K, k = t - n * K;
-        float acc = 0.0f;
-        for (int b = 0; b < B; b++) acc = fmaf(dy[(size_t)b * N + n], h2f(x[(size_t)b * K + k]), acc);
-        dW[t] = acc;
+        float a4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        int b = 0;
+        for (; b + 3 < B; b += 4)
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+                a4[u] = fmaf(dy[(size_t)(b + u) * N + n], h2f(x[(size_t)(b + u) * K + k]), a4[u]);
+        for (; b < B; b++) a4[0] = fmaf(dy[(size_t)b * N + n], h2f(x[(size_t)b * K + k]), a4[0]);
+        dW[t] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
     }
     if (t < N) {
         float acc = 0.0f;
@@ -651,9 +662,9 @@ int forward_into(const __half* w, const __half* x, int B, const Acts& A, hipStre
                        A.a2, SIDE2, w + OFF_C3W, w + OFF_C3B, A.a3, SIDE3, B);
     hipLaunchKernelGGL((k_conv_fwd<CH, 2>), dim3(grid_for((size_t)B * SIDE4 * SIDE4)), dim3(256), 0, st,
                        A.a3, SIDE3, w + OFF_C4W, w + OFF_C4B, A.a4, SIDE4, B);
-    hipLaunchKernelGGL((k_fc_fwd<true>), dim3((B * HID + 255) / 256), dim3(256), 0, st, A.a4, FLAT,
+    hipLaunchKernelGGL((k_fc_fwd<true>), dim3((B * HID + 3) / 4), dim3(256), 0, st, A.a4, FLAT,
                        w + OFF_F1W, w + OFF_F1B, HID, B, A.h, nullptr);
-    hipLaunchKernelGGL((k_fc_fwd<false>), dim3((B * NOUT + 255) / 256), dim3(256), 0, st, A.h, HID,
+    hipLaunchKernelGGL((k_fc_fwd<false>), dim3((B * NOUT + 3) / 4), dim3(256), 0, st, A.h, HID,
                        w + OFF_F2W, w + OFF_F2B, NOUT, B, nullptr, A.out);
     PSFM_HIP_CHECK(hipGetLastError());
     return PSFM_OK;
