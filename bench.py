@@ -282,7 +282,9 @@ def bench_cells(args, torch, psfm, synth):
     rate = B / (ms * 1e-3)
     achieved = CNN_TRAIN_FLOP * B / (ms * 1e-3) / 1e12
 
-    # the prior in use: plain solve and solve with the predicted kernels on one pair
+    # the prior in use (after a few untimed epochs, so that the predictions
+    # mean something): plain solve and solve with the predicted kernels on one pair
+    cnn.train(net, z, epochs=4, batch=B)
     wl = synth.scaled(synth.WORKLOADS["pair2048"], "prior", 1024, 1024, n_stamps=150, spatial_order=2,
                       variable_frac=0.10)
     pair = synth.make_pair(wl, synth.workload_seed(synth.SEED_INDEX["cells200k"], 1))
@@ -306,6 +308,8 @@ def bench_cells(args, torch, psfm, synth):
     t_pred = timed(lambda: cnn.predict_local(ctx, net, d["I1"], d["M1"], d["I2"], d["M2"], d["stamps"]))
     pred = cnn.predict_local(ctx, net, d["I1"], d["M1"], d["I2"], d["M2"], d["stamps"])
     t_prior = timed(lambda: ctx.solve(wl.width, wl.height, d["stamps"], fit, prior=pred))
+    sp = psfm.read_stats(ctx.solve(wl.width, wl.height, d["stamps"], fit)["stats"])
+    sq = psfm.read_stats(ctx.solve(wl.width, wl.height, d["stamps"], fit, prior=pred)["stats"])
 
     out = {
         "metric": "CNN training throughput (learned prior)",
@@ -329,7 +333,11 @@ def bench_cells(args, torch, psfm, synth):
                          algorithmic_flops_per_stamp=CNN_TRAIN_FLOP),
         "dataset": {"stamps_per_s": round(n_data / t_data, 1), "seconds": round(t_data, 3)},
         "prior": {"solve_ms": round(t_plain, 3), "predict_ms": round(t_pred, 3),
-                  "solve_prior_ms": round(t_prior, 3), "stamps": int(pair.stamps.shape[0])},
+                  "solve_prior_ms": round(t_prior, 3), "stamps": int(pair.stamps.shape[0]),
+                  "solutions_plain": int(sp["n_iter"]), "solutions_prior": int(sq["n_iter"]),
+                  "prior_excluded": int(sq["n_prior"]), "restored": int(sq["n_restored"]),
+                  "chi2_dof_plain": round(float(sp["chi2_dof"]), 5),
+                  "chi2_dof_prior": round(float(sq["chi2_dof"]), 5)},
     }
     if not args.no_cpu_baseline:
         from oracle import cnn_oracle as CO

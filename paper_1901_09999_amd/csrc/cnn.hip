@@ -532,17 +532,20 @@ __global__ void k_coeff_to_ortho(const double* __restrict__ Rm, int nb, int L,
     c[t] = (float)acc;
 }
 
-__global__ void k_ortho_to_coeff(const double* __restrict__ Rm, int nb, int L,
-                                 const float* __restrict__ c, int n, double* __restrict__ a) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    double* as = a + (size_t)s * L;
-    for (int i = nb - 1; i >= 0; i--) {
-        double v = (double)c[(size_t)s * nb + i];
-        for (int j = i + 1; j < nb; j++) v -= Rm[i * nb + j] * as[j];
-        as[i] = v / Rm[i * nb + i];
+__global__ __launch_bounds__(64) void k_ortho_to_coeff(const double* __restrict__ Rm, int nb, int L,
+                                                        const float* __restrict__ c,
+                                                        double* __restrict__ a) {
+    // one wave per stamp; lane i holds row i of the right-hand side, which
+    // is reduced column by column (a_k = r_k / R_kk, then r_i -= R_ik a_k)
+    const int s = blockIdx.x, i = threadIdx.x;
+    double r = i < nb ? (double)c[(size_t)s * nb + i] : 0.0;
+    double ai = 0.0;
+    for (int k = nb - 1; k >= 0; k--) {
+        const double ak = __shfl(r, k) / Rm[k * nb + k];
+        if (i == k) ai = ak;
+        if (i < k) r -= Rm[i * nb + k] * ak;
     }
-    for (int i = nb; i < L; i++) as[i] = 0.0;
+    if (i < L) a[(size_t)s * L + i] = i < nb ? ai : 0.0;
 }
 
 // Loss weight of stamp s in orthonormal coordinates: the stamp matrix with
@@ -789,8 +792,8 @@ extern "C" int psfm_cnn_local_coeffs(const psfm_context* ctx, const float* ortho
     if (!ctx || n_stamps < 0 || (n_stamps > 0 && (!local || !ortho))) return PSFM_ERR_INVALID_ARG;
     if (ctx->nb != NOUT || !ctx->kgram_ok) return PSFM_ERR_UNSUPPORTED;
     if (n_stamps == 0) return PSFM_OK;
-    hipLaunchKernelGGL(k_ortho_to_coeff, dim3((n_stamps + 63) / 64), dim3(64), 0, (hipStream_t)stream,
-                       ctx->kgram_R, ctx->nb, ctx->L, ortho, n_stamps, local);
+    hipLaunchKernelGGL(k_ortho_to_coeff, dim3(n_stamps), dim3(64), 0, (hipStream_t)stream,
+                       ctx->kgram_R, ctx->nb, ctx->L, ortho, local);
     PSFM_HIP_CHECK(hipGetLastError());
     return PSFM_OK;
 }

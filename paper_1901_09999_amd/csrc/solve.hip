@@ -1211,12 +1211,25 @@ __global__ __launch_bounds__(PRIOR_T) void k_prior_warm(
         const bool isG = t < ns * ns;
         const int e = isG ? t : t - ns * ns;
         const int r0 = e / ns, q = e % ns;
-        double acc = 0.0;
-        for (int s = 0; s < n; s++) {
-            if (!used[s]) continue;
-            const double* g = G + (size_t)s * ns;         // spatial terms at the stamp centre
-            acc += isG ? g[r0] * g[q] : alpha[(size_t)s * L + r0] * g[q];
+        // sum over the used stamps: branch-free, four accumulators (loads of
+        // successive stamps in flight together)
+        double a4[4] = {0.0, 0.0, 0.0, 0.0};
+        int s = 0;
+        for (; s + 3 < n; s += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int ss = s + u;
+                const double* g = G + (size_t)ss * ns;    // spatial terms at the stamp centre
+                const double v = isG ? g[r0] : alpha[(size_t)ss * L + r0];
+                a4[u] += used[ss] ? v * g[q] : 0.0;
+            }
         }
+        for (; s < n; s++) {
+            const double* g = G + (size_t)s * ns;
+            const double v = isG ? g[r0] : alpha[(size_t)s * L + r0];
+            a4[0] += used[s] ? v * g[q] : 0.0;
+        }
+        const double acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
         if (isG) Gm[e] = acc;
         else rhs[e] = acc;
     }
@@ -1255,15 +1268,17 @@ __global__ __launch_bounds__(PRIOR_T) void k_prior_warm(
         }
         for (int q = 0; q < ns; q++) a0[tid * ns + q] = z[q];
     }
-    if (tid == 0) {
-        double sbg = 0.0, c = 0.0;
-        for (int s = 0; s < n; s++)
-            if (used[s]) {
-                sbg += alpha[(size_t)s * L + nb];
-                c += 1.0;
-            }
-        a0[N - 1] = c > 0.0 ? sbg / c : 0.0;
-    }
+    // background: mean of the used stamps' predictions (block sums)
+    __shared__ double red[16];
+    double sbg = 0.0, c = 0.0;
+    for (int s = tid; s < n; s += PRIOR_T)
+        if (used[s]) {
+            sbg += alpha[(size_t)s * L + nb];
+            c += 1.0;
+        }
+    sbg = block_sum(sbg, red);
+    c = block_sum(c, red);
+    if (tid == 0) a0[N - 1] = c > 0.0 ? sbg / c : 0.0;
 }
 
 // Rejection prior: a variable source shows up as a stamp whose predicted
