@@ -82,7 +82,6 @@ struct PairDesc {
     uint8_t* used;
     uint8_t* fitted;
     double* G;
-    double* GU;
     double* Mt;
     double* bt;
     double* A;

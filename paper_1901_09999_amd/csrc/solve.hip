@@ -1,7 +1,7 @@
 // Assembly, solution and rejection (Section 2; Sections 3.3, 3.5, 3.6).
 //
 // Stream-ordered loop of at most max_iter rounds, each made of
-//   k_weights / k_assemble - M[(i,s),(j,t)] = sum_used g_s g_t M_s[i][j]
+//   k_assemble  - M[(i,s),(j,t)] = sum_used g_s g_t M_s[i][j]
 //                 (FP64, stamp-major sums, one item per (i, j, s));
 //   k_cholesky  - one 512-thread workgroup: symmetric equilibration,
 //                 blocked right-looking Cholesky (32-column panels in LDS,
@@ -117,9 +117,9 @@ constexpr int ASM_ITEMS = 32, ASM_CHUNKS = 8;
 
 template <int NS>
 __device__ void assemble_body(int n, int nb, int N, const double* __restrict__ Mt,
-                              const double* __restrict__ bt, const double* __restrict__ GU,
-                              double* __restrict__ M, double* __restrict__ b, const SolveState* st,
-                              const int bid) {
+                              const double* __restrict__ bt, const double* __restrict__ G,
+                              const uint8_t* __restrict__ used, double* __restrict__ M,
+                              double* __restrict__ b, const SolveState* st, const int bid) {
     if (st->done) return;
     __shared__ double red[ASM_ITEMS][ASM_CHUNKS][NS];
     const int L = nb + 1;
@@ -145,8 +145,9 @@ __device__ void assemble_body(int n, int nb, int N, const double* __restrict__ M
     if (kind == 1) {
         const double* mrow = Mt + (size_t)ij * n;
         for (int k = chunk; k < n; k += ASM_CHUNKS) {
-            const double* g = GU + (size_t)k * (NS + 1);     // g_k[0..NS), used_k
-            const double gm = ((i == nb) ? g[NS] : g[NS] * g[s]) * mrow[k];
+            const double* g = G + (size_t)k * NS;            // spatial terms of stamp k
+            const double u = used[k] ? 1.0 : 0.0;
+            const double gm = ((i == nb) ? u : u * g[s]) * mrow[k];
             if (j == nb) {
                 acc[0] += gm;
             } else {
@@ -157,8 +158,9 @@ __device__ void assemble_body(int n, int nb, int N, const double* __restrict__ M
     } else if (kind == 2) {
         const double* brow = bt + (size_t)i * n;
         for (int k = chunk; k < n; k += ASM_CHUNKS) {
-            const double* g = GU + (size_t)k * (NS + 1);
-            acc[0] += ((i == nb) ? g[NS] : g[NS] * g[s]) * brow[k];
+            const double* g = G + (size_t)k * NS;
+            const double u = used[k] ? 1.0 : 0.0;
+            acc[0] += ((i == nb) ? u : u * g[s]) * brow[k];
         }
     }
 #pragma unroll
@@ -187,10 +189,10 @@ __device__ void assemble_body(int n, int nb, int N, const double* __restrict__ M
 template <int NS>
 __global__ __launch_bounds__(256) void k_assemble(int n, int nb, int N, const double* __restrict__ Mt,
                                                   const double* __restrict__ bt,
-                                                  const double* __restrict__ GU,
+                                                  const double* __restrict__ G, const uint8_t* __restrict__ used,
                                                   double* __restrict__ M, double* __restrict__ b,
                                                   const SolveState* st) {
-    assemble_body<NS>(n, nb, N, Mt, bt, GU, M, b, st, blockIdx.x);
+    assemble_body<NS>(n, nb, N, Mt, bt, G, used, M, b, st, blockIdx.x);
 }
 
 // Batched: only the pairs with NS spatial terms take part in this launch.
@@ -199,30 +201,9 @@ __global__ __launch_bounds__(256) void k_assemble_b(const PairDesc* __restrict__
     const PairDesc& p = pairs[blockIdx.y];
     const int L = nb + 1;
     if (p.ns != NS || (int)blockIdx.x * ASM_ITEMS >= L * L * NS + L * NS) return;
-    assemble_body<NS>(p.n, nb, p.N, p.Mt, p.bt, p.GU, p.A, p.b, p.st, blockIdx.x);
+    assemble_body<NS>(p.n, nb, p.N, p.Mt, p.bt, p.G, p.used, p.A, p.b, p.st, blockIdx.x);
 }
 
-// Stamp weights for the assembly: GU[k] = (g_k[0..ns), used_k).
-__device__ void weights_body(int n, int ns, const double* __restrict__ G,
-                             const uint8_t* __restrict__ used, double* __restrict__ GU,
-                             const SolveState* st, int bid) {
-    if (st->done) return;
-    const int t = bid * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    for (int q = 0; q < ns; q++) GU[(size_t)t * (ns + 1) + q] = G[(size_t)t * ns + q];
-    GU[(size_t)t * (ns + 1) + ns] = used[t] ? 1.0 : 0.0;
-}
-
-__global__ void k_weights(int n, int ns, const double* __restrict__ G,
-                          const uint8_t* __restrict__ used, double* __restrict__ GU,
-                          const SolveState* st) {
-    weights_body(n, ns, G, used, GU, st, blockIdx.x);
-}
-
-__global__ void k_weights_b(const PairDesc* __restrict__ pairs) {
-    const PairDesc& p = pairs[blockIdx.y];
-    weights_body(p.n, p.ns, p.G, p.used, p.GU, p.st, blockIdx.x);
-}
 
 __device__ __forceinline__ double block_sum(double v, double* red) { return psfm_block_sum(v, red); }
 
@@ -852,8 +833,8 @@ __global__ __launch_bounds__(256) void k_resid(int n, int nb, int ns, int N, int
 // g[(i,q)] = sum_used g_q(c_k) g_k[i], g[N-1] = sum_used g_k[nb]: the
 // right-hand side of the correction, assembled like b.
 __global__ void k_assemble_vec(int n, int nb, int ns, int N, const double* __restrict__ gt,
-                               const double* __restrict__ GU, double* __restrict__ gv,
-                               const SolveState* st) {
+                               const double* __restrict__ G, const uint8_t* __restrict__ used,
+                               double* __restrict__ gv, const SolveState* st) {
     if (st->done) return;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= N) return;
@@ -861,8 +842,8 @@ __global__ void k_assemble_vec(int n, int nb, int ns, int N, const double* __res
     const int q = (t == N - 1) ? -1 : t - (t / ns) * ns;
     double acc = 0.0;
     for (int k = 0; k < n; k++) {
-        const double* gk = GU + (size_t)k * (ns + 1);
-        const double w = q < 0 ? gk[ns] : gk[ns] * gk[q];
+        const double u = used[k] ? 1.0 : 0.0;
+        const double w = q < 0 ? u : u * G[(size_t)k * ns + q];
         acc += w * gt[(size_t)i * n + k];
     }
     gv[t] = acc;
@@ -1461,7 +1442,6 @@ size_t solve_workspace(const psfm_context* ctx, int n) {
     c.take<uint8_t>(n + 1);
     c.take<uint8_t>(n + 1);
     c.take<double>((size_t)n * ctx->ns + 1);
-    c.take<double>((size_t)n * (ctx->ns + 1) + 1);
     c.take<double>((size_t)ctx->N * ctx->N);
     c.take<double>(ctx->N);
     c.take<double>(psfm::solve_il_doubles(ctx->N));
@@ -1518,7 +1498,6 @@ int batch_solve(const psfm_context* ctx, const PairDesc* pairs, const int* stamp
     hipLaunchKernelGGL(k_transpose_sums_b, dim3(64, n_pairs), dim3(256), 0, st, pairs, L);
     PSFM_HIP_CHECK(hipGetLastError());
     for (int it = 0; it < cf.max_iter; it++) {
-        hipLaunchKernelGGL(k_weights_b, dim3((max_n + 255) / 256 + 1, n_pairs), dim3(256), 0, st, pairs);
 #define PSFM_ASM_B(NSV)                                                                          \
         if (ns_mask & (1u << NSV)) {                                                             \
             const int items = L * L * NSV + L * NSV;                                             \
@@ -1565,7 +1544,6 @@ static int solve_impl(const psfm_context* ctx, int W, int H, const int32_t* stam
     uint8_t* used = c.take<uint8_t>(n_stamps + 1);
     uint8_t* fitted = c.take<uint8_t>(n_stamps + 1);
     double* G = c.take<double>((size_t)n_stamps * ctx->ns + 1);
-    double* GU = c.take<double>((size_t)n_stamps * (ctx->ns + 1) + 1);
     double* M = c.take<double>((size_t)ctx->N * ctx->N);
     double* b = c.take<double>(ctx->N);
     double* ILg = c.take<double>(psfm::solve_il_doubles(ctx->N));
@@ -1611,14 +1589,12 @@ static int solve_impl(const psfm_context* ctx, int W, int H, const int32_t* stam
                            pdof, state);
         PSFM_HIP_CHECK(hipGetLastError());
     }
-    // one round: weights, assembly, solution (+ refinement), chi2, clip
+    // one round: assembly, solution (+ refinement), chi2, clip
     auto round = [&]() -> int {
-        hipLaunchKernelGGL(k_weights, dim3((n_stamps + 255) / 256 + 1), dim3(256), 0, st, n_stamps, ns,
-                           G, used, GU, state);
         const dim3 ag((nthreads_asm + ASM_ITEMS - 1) / ASM_ITEMS);
         switch (ns) {
 #define PSFM_ASM_CASE(NSV) \
-    case NSV: hipLaunchKernelGGL(k_assemble<NSV>, ag, dim3(256), 0, st, n_stamps, nb, N, Mt, bt, GU, M, b, state); break;
+    case NSV: hipLaunchKernelGGL(k_assemble<NSV>, ag, dim3(256), 0, st, n_stamps, nb, N, Mt, bt, G, used, M, b, state); break;
             PSFM_ASM_CASE(1) PSFM_ASM_CASE(3) PSFM_ASM_CASE(6) PSFM_ASM_CASE(10) PSFM_ASM_CASE(15)
             PSFM_ASM_CASE(21) PSFM_ASM_CASE(28)
 #undef PSFM_ASM_CASE
@@ -1632,7 +1608,7 @@ static int solve_impl(const psfm_context* ctx, int W, int H, const int32_t* stam
                 hipLaunchKernelGGL(k_resid, dim3(n_stamps), dim3(256), 0, st, n_stamps, nb, ns, N,
                                    npix, stamp_design, G, coeffs, fitted, gt, stamp_chi2, state);
                 hipLaunchKernelGGL(k_assemble_vec, dim3((N + 255) / 256), dim3(256), 0, st, n_stamps,
-                                   nb, ns, N, gt, GU, gv, state);
+                                   nb, ns, N, gt, G, used, gv, state);
                 hipLaunchKernelGGL(k_resolve, dim3(1), dim3(CH_THREADS), lds, st, N, M, ILg, Dg, gv,
                                    coeffs, state);
             }
