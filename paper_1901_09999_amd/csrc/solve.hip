@@ -216,12 +216,13 @@ __device__ __forceinline__ double rsqrt_nr(double d) {
     return r;
 }
 
-// 1/d: v_rcp_f64 and two Newton steps.
+// 1/d: v_rcp_f64 (relative error e, |e| < 2^-23), then the third-order
+// correction 1/d = r / (1 - e) ~ r (1 + e + e^2), truncation e^3: three
+// dependent operations after the estimate, where two Newton steps take four.
 __device__ __forceinline__ double rcp_nr(double d) {
-    double r = __builtin_amdgcn_rcp(d);
-    r = fma(r, fma(-d, r, 1.0), r);
-    r = fma(r, fma(-d, r, 1.0), r);
-    return r;
+    const double r = __builtin_amdgcn_rcp(d);
+    const double e = fma(-d, r, 1.0);
+    return fma(r, fma(e, e, e), r);
 }
 
 // Value of v in lane l of the wave (l a compile-time constant after unrolling).
@@ -337,123 +338,111 @@ __device__ __forceinline__ void back_subst(int N, const double* __restrict__ A, 
 }
 
 // Cholesky of the nk x nk diagonal block in rows 0 .. nk - 1 of Q (row
-// stride CH_PS, lower triangle, zeros above and beyond nk), in place, by one
-// wave, and the inverse of the factor.
-//   Factor: rows in the lanes' registers, right-looking in the L D L^T form:
-//   the pivot chain is d_(c+1) = A_(c+1,c+1) - A_(c+1,c)^2 / d_c (a
-//   reciprocal and one FMA per column, operands read from the pivot row's
-//   lane), and each step's column reaches the other lanes through a
-//   double-buffered LDS column (cb).  The 32 steps are straight-line code
-//   (selects, no branches or barriers: LDS accesses of one wave are ordered)
-//   so that the next pivot's reciprocal overlaps the current column's
-//   updates.  Then L = L_unit D^(1/2).
-//   Inverse: the two 16 x 16 diagonal sub-blocks by substitution on the
-//   unit-diagonal factor (one column per lane), the off-diagonal block as -I22 (L21 I11) on FP64 MFMA; the
-//   32 x 32 result goes to Iv (LDS, zeros above the diagonal) and to ivg.
+// stride CH_PS, lower triangle, zeros above and beyond nk), by one wave,
+// delivered as the inverse of its factor: L^(-1) (32 x 32, zeros above the
+// diagonal and in the rows beyond nk) into Iv (LDS, row stride CH_PS) and
+// ivg.  Q is not modified.
+//   Lanes 0-31 hold the rows of the block in registers, lanes 32-63 the
+//   columns of X = L_unit^(-1), starting from the identity.  Step c of the
+//   right-looking L D L^T elimination is one instruction stream for both
+//   halves:  v_u -= (v_c / d_c) col_u  for u > c,  col = column c of the
+//   partly reduced block.  On a block row this is the rank-one update; on a
+//   column of X it is forward substitution with the unit factor
+//   (X_uk -= L_uc X_ck), so the inverse costs no instructions of its own.
+//   The pivot chain d_(c+1) = A_(c+1,c+1) - A_(c+1,c)^2 / d_c reads its
+//   operands from the pivot row's lane; each column reaches all lanes
+//   through a double-buffered LDS column (cb), read at the end of the step
+//   that finishes it, so that the read overlaps the next reciprocal.  The
+//   32 steps are straight-line code (LDS accesses of one wave are ordered).
+//   Finally L^(-1) = D^(-1/2) X.
 // dd, ds: LDS [32] scratch.  Returns 0, or the 1-based column of the first
 // non-positive pivot.
-__device__ __forceinline__ int factor_diag(int nk, double* Q, double* Iv, double* __restrict__ ivg,
+__device__ __forceinline__ int factor_diag(int nk, const double* Q, double* Iv, double* __restrict__ ivg,
                                            double (*cb)[64], double* dd, double* ds) {
     const int lane = threadIdx.x & 63, row = lane & 31;
-    const int l16 = lane & 15, l4 = lane >> 4;
-    constexpr int PF = 6;        // column entries read ahead into registers
-    double r[CH_NB], pre[PF];
+    const bool xl = lane >= 32;
+    double r[CH_NB], col[CH_NB];
+    {
+        // every lane loads (clamped row), then v * keep + identity: no
+        // branches.  Rows beyond nk are identity rows, so that their pivots
+        // are 1 and the pivot chain needs no select.  self is made opaque so
+        // that the identity is formed here, not hoisted out of the caller's
+        // loop and kept in registers.
+        const int qr = xl || row >= nk ? 0 : row;
+        const double keep = xl || row >= nk ? 0.0 : 1.0;
+        int self = xl || row >= nk ? row : -1;
+        asm volatile("" : "+v"(self));
 #pragma unroll
-    for (int c = 0; c < CH_NB; c++) r[c] = row < nk ? Q[row * CH_PS + c] : 0.0;
+        for (int c = 0; c < CH_NB; c++)
+            r[c] = fma(Q[qr * CH_PS + c], keep, c == self ? 1.0 : 0.0);
+    }
     cb[0][lane] = r[0];
 #pragma unroll
-    for (int u = 0; u < PF; u++) pre[u] = 1 + u < CH_NB ? cb[0][1 + u] : 0.0;
-    double dc = readlane_d(r[0], 0);
+    for (int u = 1; u < CH_NB; u++) col[u] = cb[0][u];
+    // The pivot of step c + 1 and its reciprocal (rcp_nr's stages) are
+    // formed during step c, one stage between consecutive batches of the
+    // step's updates, so that the chain's latency is covered by them (the
+    // wave issues in order).  Empty asm statements fix that order: a stage's
+    // result and the multiplier pass through one before the next batch, and
+    // each batch's rows through one before the next stage.  The chain has no
+    // select: a non-positive pivot is recorded (bad) and the factorization
+    // is then abandoned by the caller.
     int bad = 0;
+    double rc;
+    {
+        const double d = readlane_d(r[0], 0);
+        bad = 0 < nk && !(d > 0.0) ? 1 : 0;
+        if (lane == 0) dd[0] = d;
+        rc = rcp_nr(d);
+    }
 #pragma unroll
     for (int c = 0; c < CH_NB; c++) {
-        const bool live = c < nk, ok = dc > 0.0;
-        bad = (bad == 0 && live && !ok) ? c + 1 : bad;
-        const double d = live && ok ? dc : 1.0;
-        dd[c] = d;
-        const double rc = rcp_nr(d);
+        const int n = CH_NB - 1 - c, s1 = n / 3, s2 = (2 * n) / 3;
+        // finished rows (and the pivot row) are left alone
+        double t = (xl || row > c) ? r[c] * rc : 0.0;
+        double d = 1.0, y = 1.0;
         if (c + 1 < CH_NB) {
             const double a = readlane_d(r[c + 1], c + 1), q = readlane_d(r[c], c + 1);
-            dc = fma(-q * q, rc, a);
+            d = fma(-q * q, rc, a);
+            bad = (bad == 0 && c + 1 < nk && !(d > 0.0)) ? c + 2 : bad;
+            if (lane == 0) dd[c + 1] = d;
+            y = __builtin_amdgcn_rcp(d);
         }
-        const double t = (row > c && row < nk) ? r[c] * rc : 0.0;
-        const double* col = cb[c & 1];
-        // column c: entries c + 1 .. c + PF were read ahead (pre), the rest now
-        double cur[PF];
+        asm volatile("" : "+v"(t), "+v"(y));
+        auto batch = [&](int k0, int k1) {
 #pragma unroll
-        for (int u = 0; u < PF; u++) cur[u] = pre[u];
-        if (c + 1 < CH_NB) {
-            r[c + 1] -= t * cur[0];
-            cb[(c + 1) & 1][lane] = r[c + 1];
-            // the head of the next step's column, so that its latency
-            // overlaps this step's updates (LDS accesses of one wave are in order)
+            for (int k = k0; k < k1; k++) {
+                r[c + 1 + k] -= t * col[c + 1 + k];
+                if (k == 0) cb[(c + 1) & 1][lane] = r[c + 1];
+            }
 #pragma unroll
-            for (int u = 0; u < PF; u++) pre[u] = c + 2 + u < CH_NB ? cb[(c + 1) & 1][c + 2 + u] : 0.0;
-        }
+            for (int k = k0; k < k1; k++) asm volatile("" : "+v"(r[c + 1 + k]));
+        };
+        batch(0, s1);
+        double e = fma(-d, y, 1.0);
+        asm volatile("" : "+v"(t), "+v"(e));
+        batch(s1, s2);
+        e = fma(e, e, e);
+        asm volatile("" : "+v"(t), "+v"(e));
+        batch(s2, n);
+        const double rcn = fma(y, e, y);      // 1/d (1 + e + e^2), as rcp_nr
+        // column c + 1, for the next step
 #pragma unroll
-        for (int j = c + 2; j < CH_NB; j++) r[j] -= t * (j - c - 1 < PF ? cur[j - c - 1] : col[j]);
+        for (int u = c + 2; u < CH_NB; u++) col[u] = cb[(c + 1) & 1][u];
+        rc = rcn;
     }
     if (bad) return bad;
-    // 1/sqrt(d_c) per pivot (one per lane), then L = L_unit D^(1/2) row by row
-    const double dm = dd[row];
-    const double sm = rsqrt_nr(dm);
-    if (lane < CH_NB) ds[lane] = lane < nk ? sm : 0.0;
+    if (lane < CH_NB) ds[lane] = lane < nk ? rsqrt_nr(dd[lane]) : 0.0;
     wave_sync();
+    if (xl) {
 #pragma unroll
-    for (int c0 = 0; c0 < CH_NB; c0 += 8) {
-        double sc[8];
-#pragma unroll
-        for (int u = 0; u < 8; u++) sc[u] = ds[c0 + u];
-        if (lane < nk) {
-#pragma unroll
-            for (int u = 0; u < 8; u++) {
-                const int c = c0 + u;
-                Q[row * CH_PS + c] = c < row ? r[c] * sc[u] : c == row ? dm * sm : 0.0;
-            }
+        for (int i = 0; i < CH_NB; i++) {
+            const double v = r[i] * ds[i];
+            Iv[i * CH_PS + row] = v;
+            ivg[i * CH_NB + row] = v;
         }
     }
     wave_sync();
-    // inverses of the diagonal 16 x 16 sub-blocks: column j of block g per lane
-    if (lane < CH_NB) {
-        const int g = lane >> 4, j = lane & 15, base = 16 * g;
-        double xv[16];
-        // inv(L_gg) = D^(-1/2) inv(U) with U = L_gg D^(-1/2) unit lower: the
-        // substitution chain is one FMA per column
-#pragma unroll
-        for (int q = 0; q < 16; q++) xv[q] = q == j ? 1.0 : 0.0;
-#pragma unroll
-        for (int c = 0; c < 16; c++) {
-            const double sc = ds[base + c];
-#pragma unroll
-            for (int q = c + 1; q < 16; q++) xv[q] -= (Q[(base + q) * CH_PS + base + c] * sc) * xv[c];
-        }
-#pragma unroll
-        for (int q = 0; q < 16; q++) Iv[(base + q) * CH_PS + base + j] = xv[q] * ds[base + q];
-    }
-    wave_sync();
-    // T = L21 I11 (kept in the upper-right block of Iv), I21 = -I22 T
-    double4v acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int kk = 0; kk < 16; kk += 4)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Q[(16 + l16) * CH_PS + kk + l4],
-                                                   Iv[(kk + l4) * CH_PS + l16], acc, 0, 0, 0);
-    wave_sync();
-#pragma unroll
-    for (int e = 0; e < 4; e++) Iv[(l4 + 4 * e) * CH_PS + 16 + l16] = acc[e];
-    wave_sync();
-    double4v acc2 = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int kk = 0; kk < 16; kk += 4)
-        acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(Iv[(16 + l16) * CH_PS + 16 + kk + l4],
-                                                    Iv[(kk + l4) * CH_PS + 16 + l16], acc2, 0, 0, 0);
-    wave_sync();
-#pragma unroll
-    for (int e = 0; e < 4; e++) {
-        Iv[(16 + l4 + 4 * e) * CH_PS + l16] = -acc2[e];
-        Iv[(l4 + 4 * e) * CH_PS + 16 + l16] = 0.0;
-    }
-    wave_sync();
-    for (int e = lane; e < IV_DOUBLES; e += 64) ivg[e] = Iv[(e >> 5) * CH_PS + (e & 31)];
     return 0;
 }
 
@@ -539,10 +528,11 @@ __device__ __forceinline__ void trail_block(int N, int k0, int nk, int rows, int
 }
 
 // Equilibrated blocked right-looking Cholesky and solve of the N x N system
-// M x = b; M's lower triangle is read from S (M itself, or a separate copy)
-// and the factor of D M D (D = diag(M)^(-1/2)) is left in the lower
-// triangle of A; x receives the solution.  One workgroup.  Per 32-column
-// panel (in LDS):
+// M x = b; M's lower triangle is read from S (M itself, or a separate copy).
+// Of the factor L of D M D (D = diag(M)^(-1/2)) the blocks below the
+// diagonal are left in the lower triangle of A and the 32 x 32 diagonal
+// blocks as their inverses in ILg (A's diagonal blocks are not written);
+// x receives the solution.  One workgroup.  Per 32-column panel (in LDS):
 //   * the panel rows below the diagonal block are multiplied by the inverse
 //     of its factor (FP64 MFMA, 16-row tiles, one wave each);
 //   * the forward substitution L z = D b advances by the panel's unknowns;
@@ -611,10 +601,6 @@ __device__ __forceinline__ void cholesky_body(int N, double* __restrict__ A, con
         if (k0 > 0) {
             // diagonal block: factored by the look-ahead; rows below from A
             load_panel(N, A, k0, nk, nk, rows + 16, rows, P, nullptr);
-            for (int e = tid; e < CH_NB * CH_NB; e += CH_THREADS) {
-                const int i = e >> 5, j = e & 31;
-                P[i * CH_PS + j] = Dn[i * CH_PS + j];
-            }
             if (tid == 0) s_next = 1;
             __syncthreads();
         }
@@ -661,8 +647,8 @@ __device__ __forceinline__ void cholesky_body(int N, double* __restrict__ A, con
         }
         {
             const int tr = tid >> 5, tc = tid & 31, TR = CH_THREADS / 32;
-            for (int i = tr; i < rows; i += TR)
-                if (tc < nk && (i >= nk || tc <= i)) A[(k0 + i) * N + k0 + tc] = P[i * CH_PS + tc];
+            for (int i = nk + tr; i < rows; i += TR)
+                if (tc < nk) A[(k0 + i) * N + k0 + tc] = P[i * CH_PS + tc];
         }
         // ---- trailing update, with the next diagonal block first (wave 0)
         if (m > 0) {
