@@ -7,10 +7,11 @@
 // each cover every pair (Sections 2-4 applied pair by pair):
 //   k_batch_init                      clears the tile counters, start time
 //   k_fit_band_b / k_fit_reduce_b     stamp normal equations of all pairs
-//   solve loop (max_iter rounds)      weights, assembly per spatial order,
+//   solve loop (max_iter rounds)      assembly per spatial order,
 //                                     one Cholesky workgroup per pair,
 //                                     chi2 of all stamps, clip per pair
-//   k_cov_samples_b / k_cov_finish_b  pseudo-matrices of the convolved images
+//   k_cov_auto_b / k_cov_mix_b /      pseudo-matrices of the convolved images
+//   k_cov_finish_b
 //   k_match_tiles_b                   fused convolution + difference over the
 //                                     tiles of all pairs (grid-stride loop);
 //                                     per-pair C_D and completion time
@@ -168,6 +169,8 @@ void lay_out(const psfm_context* ctx, const psfm_pair* q, const int* order, int 
         d.cov_diff = p.cov_diff;
         d.cov_diff_half = p.cov_diff_half;
         d.cov_samples = c.take<double>((size_t)PSFM_COV_SAMPLES * z.Rw * z.Rw);
+        d.cov_auto = p.cov1 ? c.take<double>((size_t)PSFM_COV_SAMPLES * (4 * ctx->h + 1) * (4 * ctx->h + 1))
+                            : nullptr;
         d.cov_avg = c.take<double>((size_t)z.Rw * z.Rw);
         d.sub_part = c.take<double>((size_t)4 * z.ntx * z.nty);
         d.tiles_done = Lo.counters + k;
@@ -230,7 +233,7 @@ extern "C" int psfm_batch_plan(const psfm_context* ctx, const psfm_pair* pairs, 
     // work lists (host) -> workspace
     std::vector<int> item_pair(Lo.n_items + 1, 0), stamp_pair(Lo.n_stamps + 1, 0),
         tile_pair(Lo.n_tiles + 1, 0);
-    int max_n = 0, max_N = 0, max_cov_in = 0;
+    int max_n = 0, max_N = 0, max_cov_in = -1;   // -1: no pair has a correlated input
     unsigned ns_mask = 0;
     for (int k = 0; k < n_pairs; k++) {
         const PairDesc& d = Lo.desc[k];
@@ -240,7 +243,7 @@ extern "C" int psfm_batch_plan(const psfm_context* ctx, const psfm_pair* pairs, 
         for (int i = 0; i < d.ntx * d.nty; i++) tile_pair[d.tile_off + i] = k;
         max_n = std::max(max_n, d.n);
         max_N = std::max(max_N, d.N);
-        max_cov_in = std::max(max_cov_in, d.cov1_half);
+        max_cov_in = std::max(max_cov_in, d.cov1 ? d.cov1_half : -1);
         ns_mask |= 1u << d.ns;
         if (times) Lo.desc[k].t_done = times + 1 + k;
     }

@@ -10,9 +10,11 @@
 //                    convolution on the FP32 VALU with 16 outputs per thread
 //                    in registers and the taps broadcast from LDS; for images
 //                    also the BAD/POOR mask from a bit-packed halo mask.
-//   k_cov_samples /  covariance pseudo-matrix of the kernels realised at the
-//   k_cov_finish     centres of a 3 x 3 partition, averaged, normalised to
-//                    the centre, cropped.
+//   k_cov_auto /     covariance pseudo-matrix of the kernels realised at the
+//   k_cov_mix /      centres of a 3 x 3 partition: each kernel's normalised
+//   k_cov_finish     autocorrelation (one row of offsets per wave), folded
+//                    with a correlated input's pseudo-matrix when there is
+//                    one, then averaged, normalised to the centre, cropped.
 //   k_subtract /     difference image, its variance and mask, per-block
 //   k_subtract_cov   variance sums and the weighted pseudo-matrix.
 #include "internal.h"
@@ -57,24 +59,53 @@ struct RealiseLds {
 // Kd receives [(v+h)*KW + (u+h)].  All threads of the block call it.
 __device__ void realise_kernel(const BasisArgs& B, const double* __restrict__ a, double x, double y,
                                int W, int H, RealiseLds& sh, double* Kd) {
-    const int KW = 2 * B.h + 1, T = KW * KW, tid = threadIdx.x;
+    const int KW = 2 * B.h + 1, T = KW * KW, tid = threadIdx.x, nb = B.nb, ns = B.ns;
     for (int e = tid; e < B.nf * KW; e += blockDim.x) sh.F[e] = B.fac64[e];
-    if (tid < B.nb) {
-        sh.gam[tid] = psfm_spatial_dot(B.S, x, y, W, H, a + tid * B.ns);   // alpha_i for now
-        sh.rf[tid] = B.rowf[tid];
-        sh.cf[tid] = B.colf[tid];
+    if (tid < 64) {
+        // wave 0, lane i: alpha_i(x, y) from the term's ns spatial
+        // coefficients (all loads issued before the first use), the spatial
+        // terms in the order of psfm_spatial_dot
+        const int i = tid < nb ? tid : 0;
+        double cv[28];
+#pragma unroll
+        for (int q = 0; q < 28; q++) cv[q] = a[i * ns + (q < ns ? q : 0)];
+        const double zi = (double)B.z[i], ps = B.psi64[i];
+        const int rf = B.rowf[i], cf = B.colf[i];
+        const double xt = W > 1 ? (2.0 * x - (W - 1)) / (double)(W - 1) : 0.0;
+        const double yt = H > 1 ? (2.0 * y - (H - 1)) / (double)(H - 1) : 0.0;
+        double al = 0.0;
+#pragma unroll
+        for (int d = 0; d <= 6; d++) {
+            if (d <= B.S) {
+#pragma unroll
+                for (int l = d; l >= 0; l--) {
+                    double v = 1.0;
+#pragma unroll
+                    for (int k = 0; k < l; k++) v *= xt;
+#pragma unroll
+                    for (int k = 0; k < d - l; k++) v *= yt;
+                    al += cv[d * (d + 1) / 2 + (d - l)] * v;
+                }
+            }
+        }
+        // c0 = sum_(i >= 1) z_i alpha_i: fixed-order butterfly over the wave
+        double c0 = tid >= 1 && tid < nb ? zi * al : 0.0;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) c0 += __shfl_xor(c0, o);
+        if (tid < nb) {
+            sh.gam[tid] = (tid == 0 ? al - c0 : al) * ps;
+            sh.rf[tid] = rf;
+            sh.cf[tid] = cf;
+        }
     }
-    __syncthreads();
-    double c0 = 0.0;
-    for (int i = 1; i < B.nb; i++) c0 += (double)B.z[i] * sh.gam[i];
-    __syncthreads();
-    if (tid < B.nb) sh.gam[tid] = (tid == 0 ? sh.gam[0] - c0 : sh.gam[tid]) * B.psi64[tid];
     __syncthreads();
     for (int t = tid; t < T; t += blockDim.x) {
         const int v = t / KW, u = t - v * KW;
-        double k = 0.0;
-        for (int i = 0; i < B.nb; i++) k += sh.gam[i] * sh.F[sh.rf[i] * KW + u] * sh.F[sh.cf[i] * KW + v];
-        Kd[t] = k;
+        double k4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (int i = 0; i < nb; i++)
+            k4[i & 3] += sh.gam[i] * sh.F[sh.rf[i] * KW + u] * sh.F[sh.cf[i] * KW + v];
+        Kd[t] = (k4[0] + k4[1]) + (k4[2] + k4[3]);
     }
     __syncthreads();
 }
@@ -358,61 +389,117 @@ int dispatch_conv(const float* src, const uint8_t* M, int W, int H, int64_t pitc
     }
 }
 
-// raw(delta) / sum K^2 for the kernel realised at the centre of cell j of the
-// 3 x 3 partition; chunk selects 256 of the offsets.
-//   raw(delta) = sum_w C_in(w) sum_u K(u) K(u + delta - w)
-__device__ void cov_samples_body(const double* __restrict__ a, const BasisArgs& B, int W, int H,
-                                 const double* __restrict__ cov_in, int c_in,
-                                 double* __restrict__ samples, const int j, const int chunk) {
+// Normalised autocorrelation of the kernel realised at the centre of cell j
+// of the 3 x 3 partition:
+//   A(e) = sum_u K(u) K(u + e) / sum_u K(u)^2,   |e_x|, |e_y| <= 2h,
+// E = 4h + 1 values a side, row-major at out + j E^2.  Workgroup ry takes
+// the row e_y = ry - 2h: its lanes the e_x, its four waves every fourth of
+// the kernel rows that overlap (partial sums added in a fixed order).  The
+// kernel's rows sit in LDS with 2h zeros either side, so every lane runs
+// the same 2h + 1 taps per kernel row.
+__device__ void cov_auto_body(const double* __restrict__ a, const BasisArgs& B, int W, int H,
+                              double* __restrict__ out, const int j, const int ry) {
     __shared__ RealiseLds sh;
     __shared__ double Kd[(2 * PSFM_HMAX + 1) * (2 * PSFM_HMAX + 1)];
+    __shared__ double Kr[(2 * PSFM_HMAX + 1) * (6 * PSFM_HMAX + 1)];
+    __shared__ double part[4][2 * 64];
     __shared__ double red[16];
-    const int h = B.h, KW = 2 * h + 1, T = KW * KW;
-    const int R = 2 * h + c_in, Rw = 2 * R + 1;
-    const int tid = threadIdx.x;
+    const int h = B.h, KW = 2 * h + 1, T = KW * KW, E = 4 * h + 1, RW = 6 * h + 1;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int jx = j % 3, jy = j / 3;
     const int cx0 = jx * W / 3, cx1 = (jx + 1) * W / 3, cy0 = jy * H / 3, cy1 = (jy + 1) * H / 3;
     realise_kernel(B, a, 0.5 * (cx0 + cx1 - 1), 0.5 * (cy0 + cy1 - 1), W, H, sh, Kd);
     double s2 = 0.0;
     for (int t = tid; t < T; t += 256) s2 += Kd[t] * Kd[t];
     const double sumk2 = psfm_block_sum(s2, red);
-    const int d = chunk * 256 + tid;
+    for (int t = tid; t < KW * RW; t += 256) {
+        const int v = t / RW, c = t - v * RW - 2 * h;     // column of K, or padding
+        Kr[t] = (c >= 0 && c < KW) ? Kd[v * KW + c] : 0.0;
+    }
+    __syncthreads();
+    const int ey = ry - 2 * h;
+    const int v0 = max(-h, -h - ey), v1 = min(h, h - ey);
+    for (int q = 0; q < 2; q++) {
+        const int xi = lane + 64 * q;                      // xi = e_x + 2h
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};
+        if (xi < E) {
+            for (int v = v0 + wave; v <= v1; v += 4) {
+                const double* k1 = Kd + (v + h) * KW;            // K(u, v), uniform over the wave
+                const double* k2 = Kr + (v + ey + h) * RW + xi;  // K(u + e_x, v + e_y), u = -h ..
+                int u = 0;
+                for (; u + 4 <= KW; u += 4) {
+                    s4[0] += k1[u] * k2[u];
+                    s4[1] += k1[u + 1] * k2[u + 1];
+                    s4[2] += k1[u + 2] * k2[u + 2];
+                    s4[3] += k1[u + 3] * k2[u + 3];
+                }
+                for (; u < KW; u++) s4[u & 3] += k1[u] * k2[u];
+            }
+        }
+        part[wave][xi] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+    }
+    __syncthreads();
+    const double inv = sumk2 > 0.0 ? 1.0 / sumk2 : 0.0;
+    if (tid < E)
+        out[(size_t)j * E * E + ry * E + tid] =
+            (((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid]) * inv;
+}
+
+__global__ __launch_bounds__(256) void k_cov_auto(const double* __restrict__ a, BasisArgs B, int W,
+                                                  int H, double* __restrict__ out) {
+    cov_auto_body(a, B, W, H, out, blockIdx.x, blockIdx.y);
+}
+
+// Correlated input: raw(delta) / sum K^2 = sum_w C_in(w) A(delta - w) for
+// |delta_x|, |delta_y| <= R = 2h + c_in, from the normalised autocorrelation
+// A of cell j (E^2 values, staged in LDS); chunk selects 256 of the offsets.
+__device__ void cov_mix_body(const double* __restrict__ A, int h, const double* __restrict__ cov_in,
+                             int c_in, double* __restrict__ samples, const int j, const int chunk) {
+    __shared__ double As[(4 * PSFM_HMAX + 1) * (4 * PSFM_HMAX + 1)];
+    const int E = 4 * h + 1, R = 2 * h + c_in, Rw = 2 * R + 1, Cw = 2 * c_in + 1;
+    for (int t = threadIdx.x; t < E * E; t += 256) As[t] = A[(size_t)j * E * E + t];
+    __syncthreads();
+    const int d = chunk * 256 + threadIdx.x;
     if (d >= Rw * Rw) return;
     const int dy = d / Rw - R, dx = d % Rw - R;
-    const int Cw = 2 * c_in + 1;
-    double raw = 0.0;
-    for (int wy = -c_in; wy <= c_in; wy++)
+    double s2[2] = {0.0, 0.0};
+    for (int wy = -c_in; wy <= c_in; wy++) {
+        const int ey = dy - wy;
+        if (ey < -2 * h || ey > 2 * h) continue;
+        const double* crow = cov_in + (wy + c_in) * Cw + c_in;
+        const double* arow = As + (ey + 2 * h) * E + 2 * h;
         for (int wx = -c_in; wx <= c_in; wx++) {
-            const double cw = cov_in ? cov_in[(wy + c_in) * Cw + (wx + c_in)] : 1.0;
-            const int ex = dx - wx, ey = dy - wy;          // K(u) K(u + e)
-            if (ex < -2 * h || ex > 2 * h || ey < -2 * h || ey > 2 * h || cw == 0.0) continue;
-            const int u0 = max(-h, -h - ex), u1 = min(h, h - ex);
-            const int v0 = max(-h, -h - ey), v1 = min(h, h - ey);
-            double q = 0.0;
-            for (int v = v0; v <= v1; v++) {
-                const double* r1 = Kd + (v + h) * KW + h;
-                const double* r2 = Kd + (v + ey + h) * KW + h + ex;
-                for (int u = u0; u <= u1; u++) q += r1[u] * r2[u];
-            }
-            raw += cw * q;
+            const int ex = dx - wx;
+            const bool in = ex >= -2 * h && ex <= 2 * h;
+            const double av = arow[in ? ex : 0];
+            s2[wx & 1] += in ? crow[wx] * av : 0.0;
         }
-    samples[(size_t)j * Rw * Rw + d] = sumk2 > 0.0 ? raw / sumk2 : 0.0;
+    }
+    samples[(size_t)j * Rw * Rw + d] = s2[0] + s2[1];
 }
 
-__global__ __launch_bounds__(256) void k_cov_samples(const double* __restrict__ a, BasisArgs B,
-                                                     int W, int H, const double* __restrict__ cov_in,
-                                                     int c_in, double* __restrict__ samples) {
-    cov_samples_body(a, B, W, H, cov_in, c_in, samples, blockIdx.x, blockIdx.y);
+__global__ __launch_bounds__(256) void k_cov_mix(const double* __restrict__ A, int h,
+                                                 const double* __restrict__ cov_in, int c_in,
+                                                 double* __restrict__ samples) {
+    cov_mix_body(A, h, cov_in, c_in, samples, blockIdx.x, blockIdx.y);
 }
 
-__global__ __launch_bounds__(256) void k_cov_samples_b(const PairDesc* __restrict__ pairs, BasisArgs B0) {
+// Batched: the autocorrelation goes straight to the samples of a pair with
+// an uncorrelated input, else to its cov_auto buffer for k_cov_mix_b.
+__global__ __launch_bounds__(256) void k_cov_auto_b(const PairDesc* __restrict__ pairs, BasisArgs B0) {
     const PairDesc& p = pairs[blockIdx.z];
-    const int Rw = 2 * (2 * B0.h + p.cov1_half) + 1;
-    if ((int)blockIdx.y * 256 >= Rw * Rw) return;
     BasisArgs B = B0;
     B.ns = p.ns;
     B.S = p.S;
-    cov_samples_body(p.coeffs, B, p.W, p.H, p.cov1, p.cov1_half, p.cov_samples, blockIdx.x, blockIdx.y);
+    cov_auto_body(p.coeffs, B, p.W, p.H, p.cov1 ? p.cov_auto : p.cov_samples, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(256) void k_cov_mix_b(const PairDesc* __restrict__ pairs, int h) {
+    const PairDesc& p = pairs[blockIdx.z];
+    if (!p.cov1) return;
+    const int Rw = 2 * (2 * h + p.cov1_half) + 1;
+    if ((int)blockIdx.y * 256 >= Rw * Rw) return;
+    cov_mix_body(p.cov_auto, h, p.cov1, p.cov1_half, p.cov_samples, blockIdx.x, blockIdx.y);
 }
 
 __device__ void cov_finish_body(const double* __restrict__ samples, int R, double* __restrict__ avg,
@@ -695,9 +782,11 @@ namespace psfm {
 
 size_t conv_workspace(const psfm_context* ctx, int, int) {
     const int R = 2 * ctx->h + 32;   // room for cov_in_half up to 32
+    const int E = 4 * ctx->h + 1;
     Carver c(nullptr);
     c.take<double>((size_t)PSFM_COV_SAMPLES * (2 * R + 1) * (2 * R + 1));
     c.take<double>((size_t)(2 * R + 1) * (2 * R + 1));
+    c.take<double>((size_t)PSFM_COV_SAMPLES * E * E);
     return c.off;
 }
 
@@ -736,9 +825,14 @@ int launch_match_tiles(const psfm_context* ctx, const PairDesc* pairs, const int
 int batch_apply(const psfm_context* ctx, const PairDesc* pairs, const int* tile_pair, int n_pairs,
                 int n_tiles, int max_cov_in, int conv_grid, hipStream_t st) {
     if (n_pairs == 0) return PSFM_OK;
-    const int Rw = cov_sample_side(ctx, max_cov_in);
-    hipLaunchKernelGGL(k_cov_samples_b, dim3(PSFM_COV_SAMPLES, (Rw * Rw + 255) / 256, n_pairs),
-                       dim3(256), 0, st, pairs, basis_args_of(ctx));
+    const int E = 4 * ctx->h + 1;
+    hipLaunchKernelGGL(k_cov_auto_b, dim3(PSFM_COV_SAMPLES, E, n_pairs), dim3(256), 0, st,
+                       pairs, basis_args_of(ctx));
+    if (max_cov_in >= 0) {      // some pair has a correlated input
+        const int Rw = cov_sample_side(ctx, max_cov_in);
+        hipLaunchKernelGGL(k_cov_mix_b, dim3(PSFM_COV_SAMPLES, (Rw * Rw + 255) / 256, n_pairs),
+                           dim3(256), 0, st, pairs, ctx->h);
+    }
     hipLaunchKernelGGL(k_cov_finish_b, dim3(n_pairs), dim3(256), 0, st, pairs, ctx->h);
     PSFM_HIP_CHECK(hipGetLastError());
     if (n_tiles == 0) return PSFM_OK;
@@ -798,13 +892,19 @@ extern "C" int psfm_propagate_variance(const psfm_context* ctx, const double* co
     const int Rmax = 2 * ctx->h + 32;
     double* samples = c.take<double>((size_t)PSFM_COV_SAMPLES * (2 * Rmax + 1) * (2 * Rmax + 1));
     double* avg = c.take<double>((size_t)(2 * Rmax + 1) * (2 * Rmax + 1));
+    const int E = 4 * ctx->h + 1;
+    double* autoc = c.take<double>((size_t)PSFM_COV_SAMPLES * E * E);
     const psfm_config& cf = ctx->cfg;
     rc = dispatch_conv<1>(V, M, W, H, pitch, cf.patch, coeffs, basis_args(ctx), cf.bad_frac, cov_in,
                           cov_in_half, var_out, nullptr, st);
     if (rc) return rc;
     const int R = 2 * ctx->h + cov_in_half, Rw = 2 * R + 1;
-    hipLaunchKernelGGL(k_cov_samples, dim3(PSFM_COV_SAMPLES, (Rw * Rw + 255) / 256), dim3(256), 0, st,
-                       coeffs, basis_args(ctx), W, H, cov_in, cov_in_half, samples);
+    // uncorrelated input: the samples are the autocorrelation itself
+    hipLaunchKernelGGL(k_cov_auto, dim3(PSFM_COV_SAMPLES, E), dim3(256), 0, st, coeffs,
+                       basis_args(ctx), W, H, cov_in ? autoc : samples);
+    if (cov_in)
+        hipLaunchKernelGGL(k_cov_mix, dim3(PSFM_COV_SAMPLES, (Rw * Rw + 255) / 256), dim3(256), 0, st,
+                           autoc, ctx->h, cov_in, cov_in_half, samples);
     hipLaunchKernelGGL(k_cov_finish, dim3(1), dim3(256), 0, st, samples, R, avg, cov_out,
                        cov_out_half, stats);
     PSFM_HIP_CHECK(hipGetLastError());

@@ -107,6 +107,7 @@ struct PairDesc {
     double* cov_diff;
     int cov_diff_half;
     double* cov_samples;
+    double* cov_auto;                // kernel autocorrelation (correlated input only)
     double* cov_avg;
     double* sub_part;                // [tiles][4] variance sums of the tiles
     unsigned int* tiles_done;        // tiles finished (batch completion counter)
