@@ -133,3 +133,51 @@ def test_batch_graph_replays_match_eager():
                 assert np.array_equal(_np(o[f]), ref[k][f]), (rep, k, f)
         lat = b.latencies_s()
         assert np.all(lat > 0) and np.all(lat < 10.0), lat
+
+
+def _corr(c_in, seed):
+    """A normalised autocorrelation pseudo-matrix of half-size c_in (the
+    covariance of white noise after a small random filter)."""
+    rng = np.random.default_rng(seed)
+    q = rng.uniform(0.0, 1.0, (c_in + 1, c_in + 1))
+    n = 2 * c_in + 1
+    c = np.zeros((n, n))
+    for dy in range(-c_in, c_in + 1):
+        for dx in range(-c_in, c_in + 1):
+            c[dy + c_in, dx + c_in] = sum(q[y, x] * q[y + dy, x + dx]
+                                          for y in range(c_in + 1) for x in range(c_in + 1)
+                                          if 0 <= y + dy <= c_in and 0 <= x + dx <= c_in)
+    return c / c[c_in, c_in]
+
+
+def test_batch_correlated_inputs_match_single_calls():
+    """Pairs 0 and 2 carry a correlated input (half-sizes 1 and 2), the others
+    none: the convolved variance, its pseudo-matrix and the discarded fraction
+    equal those of psfm_propagate_variance on the same coefficients."""
+    torch, psfm = hip()
+    pairs = _pairs(SPECS[:4])
+    cins = {0: _corr(1, 1), 2: _corr(2, 2)}
+    c_out = 10
+    ctx = psfm.Context(psfm.Config.from_workload(pairs[0][0], S=0))
+    dev = [dict(psfm.to_device(p), S=wl.spatial_order) for wl, p in pairs]
+    for k, c in cins.items():
+        dev[k]["cov1"] = torch.from_numpy(c).cuda()
+    print(f"batch of {len(pairs)} pairs, correlated inputs on {sorted(cins)}", flush=True)
+    b = psfm.Batch(ctx, dev, c_out=c_out, keep_conv=True)
+    b.run()
+    torch.cuda.synchronize()
+    for k, (wl, pair) in enumerate(pairs):
+        o = b.out[k]
+        assert b.stats(k)["info"] == 0, (k, b.stats(k))
+        sctx = psfm.Context(psfm.Config.from_workload(wl))
+        stats = torch.zeros(psfm.STATS_BYTES, dtype=torch.uint8, device="cuda")
+        var, cov = sctx.propagate_variance(o["coeffs"], dev[k]["V1"], dev[k]["M1"],
+                                           cov_in=dev[k].get("cov1"), c_out=c_out, stats=stats)
+        torch.cuda.synchronize()
+        assert np.array_equal(_np(o["var"]), _np(var)), k
+        assert np.array_equal(_np(o["cov"]), _np(cov)), k
+        assert b.stats(k)["cov_discarded_frac"] == psfm.read_stats(stats)["cov_discarded_frac"], k
+        if k in cins:   # the correlated input did change the result
+            _, cov0 = sctx.propagate_variance(o["coeffs"], dev[k]["V1"], dev[k]["M1"], c_out=c_out)
+            torch.cuda.synchronize()
+            assert np.max(np.abs(_np(cov0) - _np(cov))) > 1e-3, k
