@@ -548,6 +548,9 @@ __global__ __launch_bounds__(256) void k_cov_finish_b(const PairDesc* __restrict
     cov_finish_body(p.cov_samples, 2 * h + p.cov1_half, p.cov_avg, p.cov, p.cov_half, p.stats);
 }
 
+// VEC: four neighbouring pixels per thread with 16-byte plane and 4-byte
+// mask accesses (pitch and W multiples of 4, planes 16-byte aligned).
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_subtract(
     const float* __restrict__ I2, const float* __restrict__ V2, const uint8_t* __restrict__ M2,
     const float* __restrict__ conv, const float* __restrict__ conv_var,
@@ -557,26 +560,52 @@ __global__ __launch_bounds__(256) void k_subtract(
     __shared__ double red[16];
     const double d0 = *d0p;
     double s2 = 0.0, n2 = 0.0, sc = 0.0, nc = 0.0;
+    auto pixel = [&](uint8_t m2, uint8_t cm, float cv, float v2, float i2, float c1, float& d, float& dv,
+                     uint8_t& dm) {
+        if (m2) {
+            d = 0.0f;
+            dv = 0.0f;
+            dm = (uint8_t)(PSFM_MASK_BAD | cm);
+        } else {
+            d = (float)((double)i2 - (double)c1 - d0);
+            dv = (float)((double)v2 + (double)cv);
+            dm = cm;
+            s2 += v2;
+            n2 += 1.0;
+        }
+        if (!cm) {
+            sc += cv;
+            nc += 1.0;
+        }
+    };
     for (int y = blockIdx.x; y < H; y += gridDim.x) {
-        for (int x = threadIdx.x; x < W; x += 256) {
-            const int64_t o = (int64_t)y * pitch + x;
-            // all six loads unconditional, so that none waits on another
-            const uint8_t m2 = M2[o], cm = conv_mask[o];
-            const float cv = conv_var[o], v2 = V2[o], i2 = I2[o], c1 = conv[o];
-            if (m2) {
-                diff[o] = 0.0f;
-                diff_var[o] = 0.0f;
-                diff_mask[o] = (uint8_t)(PSFM_MASK_BAD | cm);
-            } else {
-                diff[o] = (float)((double)i2 - (double)c1 - d0);
-                diff_var[o] = (float)((double)v2 + (double)cv);
-                diff_mask[o] = cm;
-                s2 += v2;
-                n2 += 1.0;
+        if constexpr (VEC) {
+            for (int x = 4 * threadIdx.x; x < W; x += 4 * 256) {
+                const int64_t o = (int64_t)y * pitch + x;
+                // all six loads issued before any use
+                const uchar4 m2 = *reinterpret_cast<const uchar4*>(M2 + o);
+                const uchar4 cm = *reinterpret_cast<const uchar4*>(conv_mask + o);
+                const float4 cv = *reinterpret_cast<const float4*>(conv_var + o);
+                const float4 v2 = *reinterpret_cast<const float4*>(V2 + o);
+                const float4 i2 = *reinterpret_cast<const float4*>(I2 + o);
+                const float4 c1 = *reinterpret_cast<const float4*>(conv + o);
+                float4 d, dv;
+                uchar4 dm;
+                pixel(m2.x, cm.x, cv.x, v2.x, i2.x, c1.x, d.x, dv.x, dm.x);
+                pixel(m2.y, cm.y, cv.y, v2.y, i2.y, c1.y, d.y, dv.y, dm.y);
+                pixel(m2.z, cm.z, cv.z, v2.z, i2.z, c1.z, d.z, dv.z, dm.z);
+                pixel(m2.w, cm.w, cv.w, v2.w, i2.w, c1.w, d.w, dv.w, dm.w);
+                *reinterpret_cast<float4*>(diff + o) = d;
+                *reinterpret_cast<float4*>(diff_var + o) = dv;
+                *reinterpret_cast<uchar4*>(diff_mask + o) = dm;
             }
-            if (!cm) {
-                sc += cv;
-                nc += 1.0;
+        } else {
+            for (int x = threadIdx.x; x < W; x += 256) {
+                const int64_t o = (int64_t)y * pitch + x;
+                // all six loads unconditional, so that none waits on another
+                const uint8_t m2 = M2[o], cm = conv_mask[o];
+                const float cv = conv_var[o], v2 = V2[o], i2 = I2[o], c1 = conv[o];
+                pixel(m2, cm, cv, v2, i2, c1, diff[o], diff_var[o], diff_mask[o]);
             }
         }
     }
@@ -929,8 +958,16 @@ extern "C" int psfm_subtract(const psfm_context* ctx, const double* coeffs, cons
     double* partials = c.take<double>(4 * SUB_BLOCKS);
     const int nblk = std::min(H, SUB_BLOCKS);
     // the background coefficient is the last unknown, read on the device
-    hipLaunchKernelGGL(k_subtract, dim3(nblk), dim3(256), 0, st, I2, V2, M2, conv, conv_var, conv_mask,
-                       W, H, pitch, coeffs + (ctx->N - 1), diff, diff_var, diff_mask, partials);
+    const auto al16 = [](const void* q) { return ((uintptr_t)q & 15) == 0; };
+    const bool vec = pitch % 4 == 0 && W % 4 == 0 && al16(I2) && al16(V2) && al16(conv) &&
+                     al16(conv_var) && al16(diff) && al16(diff_var) && al16(M2) && al16(conv_mask) &&
+                     al16(diff_mask);
+    if (vec)
+        hipLaunchKernelGGL(k_subtract<true>, dim3(nblk), dim3(256), 0, st, I2, V2, M2, conv, conv_var, conv_mask,
+                           W, H, pitch, coeffs + (ctx->N - 1), diff, diff_var, diff_mask, partials);
+    else
+        hipLaunchKernelGGL(k_subtract<false>, dim3(nblk), dim3(256), 0, st, I2, V2, M2, conv, conv_var, conv_mask,
+                           W, H, pitch, coeffs + (ctx->N - 1), diff, diff_var, diff_mask, partials);
     PSFM_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(k_subtract_cov, dim3(1), dim3(256), 0, st, partials, nblk, cov2, cov2_half,
                        cov_conv, cov_conv_half, cov_diff, cov_diff_half);

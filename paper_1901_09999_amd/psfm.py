@@ -280,12 +280,16 @@ class Context:
                "psfm_solve_stamps")
         return local, chi2[:n]
 
-    def solve(self, W, H, stamps, fit, flags=None, out=None, prior=None):
+    def solve(self, W, H, stamps, fit, flags=None, out=None, prior=None, flags_inplace=False):
         """psfm_solve, or psfm_solve_prior when ``prior`` (n x L float64
-        predicted local coefficients) is given."""
+        predicted local coefficients) is given.  The stamp flags are updated
+        in a copy, or in ``flags`` itself with ``flags_inplace``."""
         n = stamps.shape[0]
         dev = self.device
-        fl = (fit["flags"] if flags is None else flags).clone()
+        if flags_inplace and flags is not None:
+            fl = flags
+        else:
+            fl = (fit["flags"] if flags is None else flags).clone()
         if out is None:
             out = dict(coeffs=torch.empty(self.N, dtype=torch.float64, device=dev),
                        chi2=torch.empty(max(n, 1), dtype=torch.float64, device=dev),
@@ -357,7 +361,7 @@ class Context:
         b = self.alloc_pair(W, H, stamps.shape[0], c_out) if bufs is None else bufs
         fit = self.fit_stamps(I1, M1, I2, V2, M2, stamps, out=b["fit"])
         b["flags_in"].copy_(fit["flags"])
-        sol = self.solve(W, H, stamps, fit, out=b["sol"])
+        sol = self.solve(W, H, stamps, fit, flags=b["flags_in"], out=b["sol"], flags_inplace=True)
         conv, cmask = self.convolve_image(sol["coeffs"], I1, M1, out=b["conv"], out_mask=b["conv_mask"])
         var, cov = self.propagate_variance(sol["coeffs"], V1, M1, c_out=c_out, stats=sol["stats"],
                                            out=b["var"], cov_out=b["cov"])
