@@ -422,20 +422,39 @@ __device__ void fit_reduce_body(const double* __restrict__ part, const int* __re
                                 const int s) {
     const int tid = threadIdx.x;
     const int L = nb + 1;
-    int fl = 0;
-    for (int b = 0; b < nbands; b++) fl |= band_flags[s * nbands + b];
-    if (fl & PSFM_STAMP_INVALID) fl = PSFM_STAMP_INVALID;
+    __shared__ int s_fl;
+    if (tid < 64) {     // the bands' flags, one per lane, OR over the wave
+        int f = 0;
+        for (int b = tid; b < nbands; b += 64) f |= band_flags[s * nbands + b];
+        for (int o = 32; o > 0; o >>= 1) f |= __shfl_xor(f, o);
+        if (tid == 0) s_fl = (f & PSFM_STAMP_INVALID) ? PSFM_STAMP_INVALID : f;
+    }
+    __syncthreads();
+    const int fl = s_fl;
     double* M = Ms + (size_t)s * L * L;
     double* bv = bs + (size_t)s * L;
     const double* P0 = part + (size_t)s * nbands * GC * GC;
-    for (int e = tid; e < L * L; e += 256) {
-        const int i = e / L, j = e - i * L;
-        double v = 0.0;
-        if (!fl) {
-            const int hi = i > j ? i : j, lo = i > j ? j : i;
-            for (int b = 0; b < nbands; b++) v += P0[(size_t)b * GC * GC + hi * GC + lo];
+    // four entries per thread at a time, their band partials loaded together
+    // (clamped index beyond L * L); each sum runs over the bands in order
+    for (int e0 = tid; e0 < L * L; e0 += 4 * 256) {
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+        int off[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int e = e0 + 256 * u, ec = e < L * L ? e : 0;
+            const int i = ec / L, j = ec - i * L;
+            off[u] = (i > j ? i : j) * GC + (i > j ? j : i);
         }
-        M[e] = v;
+        if (!fl) {
+            for (int b = 0; b < nbands; b++) {
+                const double* Pb = P0 + (size_t)b * GC * GC;
+#pragma unroll
+                for (int u = 0; u < 4; u++) v[u] += Pb[off[u]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            if (e0 + 256 * u < L * L) M[e0 + 256 * u] = v[u];
     }
     for (int i = tid; i <= L; i += 256) {
         double v = 0.0;

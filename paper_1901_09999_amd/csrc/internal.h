@@ -48,7 +48,7 @@ struct SolveState {
     int n_used;
     int prior_done;   // rejection prior converged (psfm_solve_prior)
     int n_iter_base;  // solutions before the current rejection loop (fallback restart)
-    int pad[1];
+    int chi2_done;    // stamps whose chi2 is in (k_chi2_clip); zero between launches
 };
 
 // Everything the kernels need about one image pair: inputs, outputs, the

@@ -60,6 +60,7 @@ __device__ void solve_init_body(int n, int N, int ns, int S, int W, int H, int m
             st->n_rej = 0;
             st->prior_done = 0;
             st->n_iter_base = 0;
+            st->chi2_done = 0;
             st->info = cnt < min_stamps ? PSFM_ERR_TOO_FEW_STAMPS : 0;
             st->done = cnt < min_stamps;
         }
@@ -895,7 +896,7 @@ __global__ __launch_bounds__(64) void k_chi2_b(const PairDesc* __restrict__ pair
               blockIdx.x - p.stamp_off);
 }
 
-// Sigma-clip over the used stamps after a solution (one workgroup).
+// Sigma-clip over the used stamps after a solution (one workgroup, any size).
 __device__ void clip_body(int n, int max_iter, int min_stamps, double clip_sigma,
                           const int32_t* __restrict__ npix, uint8_t* __restrict__ used,
                           int32_t* __restrict__ flags, const double* __restrict__ chi2,
@@ -913,7 +914,7 @@ __device__ void clip_body(int n, int max_iter, int min_stamps, double clip_sigma
     }
     // mean and population std of q_s = chi2_s / npix_s over used stamps
     double sq = 0.0, cnt = 0.0;
-    for (int s = tid; s < n; s += 1024)
+    for (int s = tid; s < n; s += blockDim.x)
         if (used[s]) {
             sq += chi2[s] / npix[s];
             cnt += 1.0;
@@ -922,7 +923,7 @@ __device__ void clip_body(int n, int max_iter, int min_stamps, double clip_sigma
     const double nu = block_sum(cnt, red);
     const double mean = tot / nu;
     double dv = 0.0;
-    for (int s = tid; s < n; s += 1024)
+    for (int s = tid; s < n; s += blockDim.x)
         if (used[s]) {
             const double d = chi2[s] / npix[s] - mean;
             dv += d * d;
@@ -932,14 +933,14 @@ __device__ void clip_body(int n, int max_iter, int min_stamps, double clip_sigma
     __syncthreads();
     const double thr = s_thr;
     double nnew = 0.0;
-    for (int s = tid; s < n; s += 1024)
+    for (int s = tid; s < n; s += blockDim.x)
         if (used[s] && chi2[s] / npix[s] > thr) nnew += 1.0;
     const double tnew = block_sum(nnew, red);
     if (tnew == 0.0 || nu - tnew < (double)min_stamps) {
         if (tid == 0) st->done = 1;
         return;
     }
-    for (int s = tid; s < n; s += 1024)
+    for (int s = tid; s < n; s += blockDim.x)
         if (used[s] && chi2[s] / npix[s] > thr) {
             used[s] = 0;
             flags[s] |= PSFM_STAMP_REJECTED;
@@ -963,6 +964,37 @@ __global__ __launch_bounds__(1024) void k_clip_b(const PairDesc* __restrict__ pa
                                                  int min_stamps, double clip_sigma) {
     const PairDesc& p = pairs[blockIdx.x];
     clip_body(p.n, max_iter, min_stamps, clip_sigma, p.npix, p.used, p.flags, p.chi2, p.st);
+}
+
+// chi2 of every stamp (one wave each), then the clip, in one launch: the
+// workgroup that finishes last (a device-scope counter in the state,
+// acquire-release) runs clip_body and clears the counter for the next
+// round.  No workgroup waits on another.
+__global__ __launch_bounds__(64) void k_chi2_clip(int n, int nb, int ns, int N,
+                                                  const double* __restrict__ Ms,
+                                                  const double* __restrict__ bs,
+                                                  const double* __restrict__ es,
+                                                  const double* __restrict__ G,
+                                                  const double* __restrict__ a,
+                                                  const uint8_t* __restrict__ fitted,
+                                                  double* __restrict__ chi2, int max_iter,
+                                                  int min_stamps, double clip_sigma,
+                                                  const int32_t* __restrict__ npix,
+                                                  uint8_t* __restrict__ used,
+                                                  int32_t* __restrict__ flags, SolveState* st) {
+    if (st->done) return;                 // uniform: no workgroup of this launch changes it first
+    chi2_body(nb, ns, N, Ms, bs, es, G, a, fitted, chi2, st, blockIdx.x);
+    __shared__ int s_last;
+    if (threadIdx.x == 0) {
+        const int prev = __hip_atomic_fetch_add(&st->chi2_done, 1, __ATOMIC_ACQ_REL,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+        s_last = prev == n - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    if (threadIdx.x == 0)
+        __hip_atomic_store(&st->chi2_done, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    clip_body(n, max_iter, min_stamps, clip_sigma, npix, used, flags, chi2, st);
 }
 
 __device__ void solve_finish_body(int n, int ns, int N, int S, int W, int H,
@@ -1601,8 +1633,10 @@ static int solve_impl(const psfm_context* ctx, int W, int H, const int32_t* stam
             hipLaunchKernelGGL(k_resid, dim3(n_stamps), dim3(256), 0, st, n_stamps, nb, ns, N, npix,
                                stamp_design, G, coeffs, fitted, gt, stamp_chi2, state);
         } else if (n_stamps > 0) {
-            hipLaunchKernelGGL(k_chi2, dim3(n_stamps), dim3(64), 0, st, nb, ns, N, stamp_M, stamp_b,
-                               stamp_e, G, coeffs, fitted, stamp_chi2, state);
+            hipLaunchKernelGGL(k_chi2_clip, dim3(n_stamps), dim3(64), 0, st, n_stamps, nb, ns, N,
+                               stamp_M, stamp_b, stamp_e, G, coeffs, fitted, stamp_chi2, cf.max_iter,
+                               cf.min_stamps, cf.clip_sigma, stamp_npix, used, stamp_flags, state);
+            return PSFM_OK;
         }
         hipLaunchKernelGGL(k_clip, dim3(1), dim3(1024), 0, st, n_stamps, cf.max_iter, cf.min_stamps,
                            cf.clip_sigma, stamp_npix, used, stamp_flags, stamp_chi2, state);
