@@ -54,7 +54,7 @@ constexpr int GC = PSFM_GRAM_COLS;
 constexpr int A16S = 104;        // LDS column stride (halves) of the 16-bit block: up to 96 pixels
 
 struct FitLds {
-    int win, col, R, At, sw, dt, psi, z, total;  // float offsets
+    int win, col, R, At, sw, dt, psi, z, fac, rf, cf, total;  // float offsets
 };
 
 __host__ __device__ inline FitLds fit_lds_layout(int h, int r, int nb, int nf) {
@@ -71,6 +71,9 @@ __host__ __device__ inline FitLds fit_lds_layout(int h, int r, int nb, int nf) {
     L.dt = o;   o += BR * (2 * r + 1);
     L.psi = o;  o += 64;
     L.z = o;    o += 64;
+    L.fac = o;  o += a4(nf * (2 * h + 1));
+    L.rf = o;   o += 64;
+    L.cf = o;   o += 64;
     L.total = o + 4;
     return L;
 }
@@ -137,6 +140,9 @@ __device__ void fit_band_body(const FitArgs& a, const int item, float* __restric
     float* dtb = lds + Lo.dt;
     float* psib = lds + Lo.psi;
     float* zb = lds + Lo.z;
+    float* facb = lds + Lo.fac;
+    int* rfb = reinterpret_cast<int*>(lds + Lo.rf);
+    int* cfb = reinterpret_cast<int*>(lds + Lo.cf);
 
     if (xc - R < 0 || yc - R < 0 || xc + R >= W || yc + R >= H) {
         if (tid == 0) band_flags[item] = PSFM_STAMP_INVALID;
@@ -146,7 +152,10 @@ __device__ void fit_band_body(const FitArgs& a, const int item, float* __restric
     if (tid < 64) {
         psib[tid] = tid < nb ? psi[tid] : 0.0f;
         zb[tid] = tid < nb ? zf[tid] : 0.0f;
+        rfb[tid] = tid < nb ? rowf[tid] : 0;
+        cfb[tid] = tid < nb ? colf[tid] : 0;
     }
+    for (int e = tid; e < nf * KW; e += 256) facb[e] = fac[e];   // the 1-D factors, for the row passes
     __syncthreads();
 
     const int y_l0 = band * BR;
@@ -254,16 +263,17 @@ __device__ void fit_band_body(const FitArgs& a, const int item, float* __restric
         for (int e = 0; e < 4; e++) acc64[q][e] = 0.0;
     }
     const int nseg = (NPX + SEG - 1) / SEG;
+    // row-pass item of this thread (the usual case: nb * nseg <= 256), its
+    // taps held in registers across the rows
+    const bool one = nb * nseg <= 256;
+    const int i1 = tid < nb * nseg ? tid / nseg : 0, x01 = (tid - i1 * nseg) * SEG;
+    float tap1[KW];
+#pragma unroll
+    for (int uu = 0; uu < KW; uu++) tap1[uu] = facb[rfb[i1] * KW + uu];
+    const int src1 = cfb[i1] * BR * WC + x01;
     for (int br = 0; br < nbr; br++) {
         // 3a. row pass: Rb[x][i] = sum_u f_{j,p}(u) colb[f_{j,q}][br][x + 2h - uu]
-        for (int item = tid; item < nb * nseg; item += 256) {
-            const int i = item / nseg, seg = item - i * nseg;
-            const int x0 = seg * SEG;
-            const float* tp = fac + rowf[i] * KW;
-            float tap[KW];
-#pragma unroll
-            for (int uu = 0; uu < KW; uu++) tap[uu] = tp[uu];
-            const float* src = colb + (colf[i] * BR + br) * WC + x0;
+        auto row_item = [&](const float* tap, const float* src, int i, int x0) {
             float a[SEG];
 #pragma unroll
             for (int k = 0; k < SEG; k++) {
@@ -274,21 +284,39 @@ __device__ void fit_band_body(const FitArgs& a, const int item, float* __restric
 #pragma unroll
             for (int k = 0; k < SEG; k++)
                 if (x0 + k < NPX) Rb[(x0 + k) * nb + i] = a[k];
+        };
+        if (one) {
+            if (tid < nb * nseg) row_item(tap1, colb + src1 + br * WC, i1, x01);
+        } else {
+            for (int item = tid; item < nb * nseg; item += 256) {
+                const int i = item / nseg, seg = item - i * nseg;
+                const int x0 = seg * SEG;
+                float tap[KW];
+#pragma unroll
+                for (int uu = 0; uu < KW; uu++) tap[uu] = facb[rfb[i] * KW + uu];
+                row_item(tap, colb + (cfb[i] * BR + br) * WC + x0, i, x0);
+            }
         }
         __syncthreads();
         if constexpr (PREC == PSFM_PREC_FP32) {
-        // 3b. zero-sum fix-up, weights, extra columns
-        for (int e = tid; e < npad * GC; e += 256) {
-            const int x = e / GC, c = e - x * GC;
-            float v = 0.0f;
-            if (x < NPX) {
-                const float sw = swb[br * NPX + x];
-                if (c < nb) v = sw * (psib[c] * Rb[x * nb + c] - zb[c] * (psib[0] * Rb[x * nb]) +
-                                      (c == 0 ? cshift : 0.0f));
-                else if (c == nb) v = sw;
-                else if (c == nb + 1) v = dtb[br * NPX + x];
+        // 3b. zero-sum fix-up, weights, extra columns: one column per lane
+        //     (its psi and z in registers), the wave's rows four apart
+        {
+            static_assert(GC == 64, "one Gram column per lane");
+            const int c = tid & (GC - 1);
+            const float pc = c < nb ? psib[c] : 0.0f, zc = c < nb ? zb[c] : 0.0f, p0 = psib[0];
+            const float add = c == 0 ? cshift : 0.0f;
+#pragma unroll 4
+            for (int x = tid >> 6; x < npad; x += 4) {
+                float v = 0.0f;
+                if (x < NPX) {
+                    const float sw = swb[br * NPX + x];
+                    if (c < nb) v = sw * (pc * Rb[x * nb + c] - zc * (p0 * Rb[x * nb]) + add);
+                    else if (c == nb) v = sw;
+                    else if (c == nb + 1) v = dtb[br * NPX + x];
+                }
+                At[x * AT_STRIDE + c] = v;
             }
-            At[x * AT_STRIDE + c] = v;
         }
         __syncthreads();
         // 3c. Gram blocks on MFMA.  Wave blocks (bm, bn): w0 (0,0)(1,0)(1,1);
