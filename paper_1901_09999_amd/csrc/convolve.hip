@@ -507,7 +507,7 @@ __device__ void cov_finish_body(const double* __restrict__ samples, int R, doubl
     __shared__ double red[16];
     __shared__ double s_centre;
     const int Rw = 2 * R + 1, n = Rw * Rw, tid = threadIdx.x;
-    for (int d = tid; d < n; d += 256) {
+    for (int d = tid; d < n; d += blockDim.x) {
         double s = 0.0;
         for (int j = 0; j < PSFM_COV_SAMPLES; j++) s += samples[(size_t)j * n + d] / 9.0;
         avg[d] = s;
@@ -517,7 +517,7 @@ __device__ void cov_finish_body(const double* __restrict__ samples, int R, doubl
     __syncthreads();
     const double centre = s_centre;
     double tot = 0.0;
-    for (int d = tid; d < n; d += 256) {
+    for (int d = tid; d < n; d += blockDim.x) {
         const double v = centre != 0.0 ? avg[d] / centre : 0.0;
         avg[d] = v;
         tot += fabs(v);
@@ -525,7 +525,7 @@ __device__ void cov_finish_body(const double* __restrict__ samples, int R, doubl
     tot = psfm_block_sum(tot, red);
     const int Ow = 2 * c_out + 1;
     double kept = 0.0;
-    for (int e = tid; e < Ow * Ow; e += 256) {
+    for (int e = tid; e < Ow * Ow; e += blockDim.x) {
         const int dy = e / Ow - c_out, dx = e % Ow - c_out;
         double v = 0.0;
         if (dx >= -R && dx <= R && dy >= -R && dy <= R) v = avg[(dy + R) * Rw + (dx + R)];
@@ -536,14 +536,14 @@ __device__ void cov_finish_body(const double* __restrict__ samples, int R, doubl
     if (tid == 0 && stats) stats->cov_discarded_frac = tot > 0.0 ? (tot - kept) / tot : 0.0;
 }
 
-__global__ __launch_bounds__(256) void k_cov_finish(const double* __restrict__ samples, int R,
+__global__ __launch_bounds__(1024) void k_cov_finish(const double* __restrict__ samples, int R,
                                                     double* __restrict__ avg,
                                                     double* __restrict__ cov_out, int c_out,
                                                     psfm_fit_stats* stats) {
     cov_finish_body(samples, R, avg, cov_out, c_out, stats);
 }
 
-__global__ __launch_bounds__(256) void k_cov_finish_b(const PairDesc* __restrict__ pairs, int h) {
+__global__ __launch_bounds__(1024) void k_cov_finish_b(const PairDesc* __restrict__ pairs, int h) {
     const PairDesc& p = pairs[blockIdx.x];
     cov_finish_body(p.cov_samples, 2 * h + p.cov1_half, p.cov_avg, p.cov, p.cov_half, p.stats);
 }
@@ -862,7 +862,7 @@ int batch_apply(const psfm_context* ctx, const PairDesc* pairs, const int* tile_
         hipLaunchKernelGGL(k_cov_mix_b, dim3(PSFM_COV_SAMPLES, (Rw * Rw + 255) / 256, n_pairs),
                            dim3(256), 0, st, pairs, ctx->h);
     }
-    hipLaunchKernelGGL(k_cov_finish_b, dim3(n_pairs), dim3(256), 0, st, pairs, ctx->h);
+    hipLaunchKernelGGL(k_cov_finish_b, dim3(n_pairs), dim3(1024), 0, st, pairs, ctx->h);
     PSFM_HIP_CHECK(hipGetLastError());
     if (n_tiles == 0) return PSFM_OK;
     const int grid = (conv_grid > 0 && conv_grid < n_tiles) ? conv_grid : n_tiles;
@@ -934,7 +934,7 @@ extern "C" int psfm_propagate_variance(const psfm_context* ctx, const double* co
     if (cov_in)
         hipLaunchKernelGGL(k_cov_mix, dim3(PSFM_COV_SAMPLES, (Rw * Rw + 255) / 256), dim3(256), 0, st,
                            autoc, ctx->h, cov_in, cov_in_half, samples);
-    hipLaunchKernelGGL(k_cov_finish, dim3(1), dim3(256), 0, st, samples, R, avg, cov_out,
+    hipLaunchKernelGGL(k_cov_finish, dim3(1), dim3(1024), 0, st, samples, R, avg, cov_out,
                        cov_out_half, stats);
     PSFM_HIP_CHECK(hipGetLastError());
     return PSFM_OK;

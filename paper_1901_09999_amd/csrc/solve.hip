@@ -41,9 +41,7 @@ __device__ void solve_init_body(int n, int N, int ns, int S, int W, int H, int m
         used[t] = u;
         fitted[t] = u;
         chi2[t] = 0.0;
-        double g[64];
-        psfm_spatial_terms(S, xy[2 * t], xy[2 * t + 1], W, H, g);
-        for (int s = 0; s < ns; s++) G[(size_t)t * ns + s] = g[s];
+        psfm_spatial_terms(S, xy[2 * t], xy[2 * t + 1], W, H, G + (size_t)t * ns);   // no local array
     }
     if (t < N) coeffs[t] = 0.0;
     if (bid == 0) {
@@ -1027,11 +1025,8 @@ __device__ void solve_finish_body(int n, int ns, int N, int S, int W, int H,
             stats->dof = np - N;
             stats->chi2_dof = c2 / (np - N);
             stats->n_used = (int)nu;
-            double g[64];
-            psfm_spatial_terms(S, 0.5 * (W - 1), 0.5 * (H - 1), W, H, g);
-            double k = 0.0;
-            for (int q = 0; q < ns; q++) k += coeffs[q] * g[q];
-            stats->kernel_sum_centre = k;
+            // term 0's spatial polynomial at the image centre
+            stats->kernel_sum_centre = psfm_spatial_dot(S, 0.5 * (W - 1), 0.5 * (H - 1), W, H, coeffs);
         } else {
             stats->chi2 = 0.0;
             stats->dof = 0.0;
