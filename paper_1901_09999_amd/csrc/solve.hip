@@ -556,7 +556,7 @@ __device__ __forceinline__ void cholesky_body(int N, double* __restrict__ A, con
     __shared__ double Dn[CH_NB * CH_PS];  // next diagonal block; back substitution partials
     __shared__ double cb[2][64];
     __shared__ double dd[CH_NB], ds[CH_NB];
-    __shared__ int s_bad, s_next;
+    __shared__ int s_bad, s_next, s_d0;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     constexpr int NW = CH_THREADS / 64;
     if (tid == 0) s_bad = 0;
@@ -585,7 +585,10 @@ __device__ __forceinline__ void cholesky_body(int N, double* __restrict__ A, con
     {
         const int nk = min(CH_NB, N);
         load_panel(N, S, 0, nk, 0, N + 16, N, P, Dq);
-        if (tid == 0) s_next = 1;
+        if (tid == 0) {
+            s_next = 1;
+            s_d0 = 0;
+        }
         __syncthreads();
         if (wave == 0) {
             const int bad = factor_diag(nk, P, Iv, ILg, cb, dd, ds);
@@ -600,7 +603,10 @@ __device__ __forceinline__ void cholesky_body(int N, double* __restrict__ A, con
         if (k0 > 0) {
             // diagonal block: factored by the look-ahead; rows below from A
             load_panel(N, A, k0, nk, nk, rows + 16, rows, P, nullptr);
-            if (tid == 0) s_next = 1;
+            if (tid == 0) {
+                s_next = 1;
+                s_d0 = 0;
+            }
             __syncthreads();
         }
         if (s_bad) {
@@ -660,10 +666,19 @@ __device__ __forceinline__ void cholesky_body(int N, double* __restrict__ A, con
                 __builtin_amdgcn_s_setprio(3);
                 trail_block(N, k0, nk, rows, 0, 0, src, A, dq, P, Dn);
                 wave_sync();
+                if (lane == 0) __hip_atomic_store(&s_d0, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 const int bad = factor_diag(min(CH_NB, m), Dn, Iv,
                                             ILg + (size_t)((k0 + nk) / CH_NB) * IV_DOUBLES, cb, dd, ds);
                 if (lane == 0) s_bad = bad;
                 __builtin_amdgcn_s_setprio(0);
+            }
+            if (wave == NW / 2) {
+                // the wave that shares wave 0's SIMD keeps off the matrix unit
+                // until the next diagonal block is formed (bounded wait)
+                for (int spin = 0; spin < 4096; spin++) {
+                    if (__hip_atomic_load(&s_d0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) break;
+                    __builtin_amdgcn_s_sleep(1);
+                }
             }
             for (;;) {
                 int g = 0;
