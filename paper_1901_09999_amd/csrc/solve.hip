@@ -782,16 +782,18 @@ __global__ __launch_bounds__(CH_THREADS) void k_resolve(int N, const double* __r
 // Phase 1: one pixel per thread, e kept in LDS; phase 2: one wave per column,
 // the lanes striding over the pixels (coalesced), then a wave sum.
 constexpr int RES_MAXPIX = (2 * PSFM_RMAX + 1) * (2 * PSFM_RMAX + 1);
+constexpr int RES_T = 1024;        // threads of k_resid (one workgroup per stamp)
 
-__global__ __launch_bounds__(256) void k_resid(int n, int nb, int ns, int N, int npix,
-                                               const float* __restrict__ design,
-                                               const double* __restrict__ G,
-                                               const double* __restrict__ a,
-                                               const uint8_t* __restrict__ fitted,
-                                               double* __restrict__ gt, double* __restrict__ chi2,
-                                               const SolveState* st) {
+__global__ __launch_bounds__(RES_T) void k_resid(int n, int nb, int ns, int N, int npix,
+                                                 const float* __restrict__ design,
+                                                 const double* __restrict__ G,
+                                                 const double* __restrict__ a,
+                                                 const uint8_t* __restrict__ fitted,
+                                                 double* __restrict__ gt, double* __restrict__ chi2,
+                                                 const SolveState* st) {
     if (st->done) return;
     const int s = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int NWV = RES_T / 64, CPW = (64 + NWV - 1) / NWV;   // columns per wave, max
     const int L = nb + 1;
     __shared__ double alpha[64];
     __shared__ float ebuf[RES_MAXPIX];
@@ -812,41 +814,73 @@ __global__ __launch_bounds__(256) void k_resid(int n, int nb, int ns, int N, int
     }
     __syncthreads();
     const float* D = design + (size_t)s * (nb + 2) * npix;
+    // 1. residual per pixel, e = d~ - sum_c alpha_c A~_c: four partial sums,
+    //    the columns' loads of a group of eight issued together
     double chi = 0.0;
-    for (int p = tid; p < npix; p += 256) {
-        double e = (double)D[(size_t)(nb + 1) * npix + p];
-        for (int c = 0; c < L; c++) e -= alpha[c] * (double)D[(size_t)c * npix + p];
+    for (int p = tid; p < npix; p += RES_T) {
+        double e4[4] = {(double)D[(size_t)(nb + 1) * npix + p], 0.0, 0.0, 0.0};
+        int c = 0;
+        for (; c + 8 <= L; c += 8) {
+            float dv[8];
+#pragma unroll
+            for (int k = 0; k < 8; k++) dv[k] = D[(size_t)(c + k) * npix + p];
+#pragma unroll
+            for (int k = 0; k < 8; k++) e4[k & 3] -= alpha[c + k] * (double)dv[k];
+        }
+        for (; c < L; c++) e4[c & 3] -= alpha[c] * (double)D[(size_t)c * npix + p];
+        const double e = (e4[0] + e4[1]) + (e4[2] + e4[3]);
         chi += e * e;
         ebuf[p] = (float)e;
     }
     chi = psfm_block_sum(chi, red);     // also orders ebuf before phase 2
-    for (int c = wave; c < L; c += 4) {
-        const float* Dc = D + (size_t)c * npix;
-        double acc = 0.0;
-        for (int p = lane; p < npix; p += 64) acc += (double)Dc[p] * (double)ebuf[p];
-        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-        if (lane == 0) gt[(size_t)c * n + s] = acc;
+    // 2. g_c = sum_p A~_c(p) e(p): wave w takes the columns w, w + NWV, ...,
+    //    every lane one pixel of each at a time (all the wave's column loads
+    //    for a pixel issued together)
+    double acc[CPW];
+#pragma unroll
+    for (int k = 0; k < CPW; k++) acc[k] = 0.0;
+#pragma unroll 4
+    for (int p = lane; p < npix; p += 64) {
+        const double e = (double)ebuf[p];
+        float dv[CPW];
+#pragma unroll
+        for (int k = 0; k < CPW; k++) {
+            const int c = wave + NWV * k;
+            dv[k] = D[(size_t)(c < L ? c : 0) * npix + p];
+        }
+#pragma unroll
+        for (int k = 0; k < CPW; k++) acc[k] += (double)dv[k] * e;
+    }
+#pragma unroll
+    for (int k = 0; k < CPW; k++) {
+        double v = acc[k];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        const int c = wave + NWV * k;
+        if (lane == 0 && c < L) gt[(size_t)c * n + s] = v;
     }
     if (tid == 0) chi2[s] = chi;
 }
 
 // g[(i,q)] = sum_used g_q(c_k) g_k[i], g[N-1] = sum_used g_k[nb]: the
 // right-hand side of the correction, assembled like b.
-__global__ void k_assemble_vec(int n, int nb, int ns, int N, const double* __restrict__ gt,
-                               const double* __restrict__ G, const uint8_t* __restrict__ used,
-                               double* __restrict__ gv, const SolveState* st) {
+__global__ __launch_bounds__(64) void k_assemble_vec(int n, int nb, int ns, int N,
+                                                    const double* __restrict__ gt,
+                                                    const double* __restrict__ G,
+                                                    const uint8_t* __restrict__ used,
+                                                    double* __restrict__ gv, const SolveState* st) {
+    // one wave per unknown t, its lanes over the stamps, fixed-order wave sum
     if (st->done) return;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= N) return;
+    const int t = blockIdx.x, lane = threadIdx.x;
     const int i = (t == N - 1) ? nb : t / ns;
     const int q = (t == N - 1) ? -1 : t - (t / ns) * ns;
     double acc = 0.0;
-    for (int k = 0; k < n; k++) {
+    for (int k = lane; k < n; k += 64) {
         const double u = used[k] ? 1.0 : 0.0;
         const double w = q < 0 ? u : u * G[(size_t)k * ns + q];
         acc += w * gt[(size_t)i * n + k];
     }
-    gv[t] = acc;
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane == 0) gv[t] = acc;
 }
 
 // chi2_s = e_s - 2 alpha^T b_s + alpha^T M_s alpha for every fitted stamp
@@ -1633,14 +1667,14 @@ static int solve_impl(const psfm_context* ctx, int W, int H, const int32_t* stam
         if (mixed && n_stamps > 0) {
             // 16-bit sums: refine against FP32 pixel residuals, then chi2 from pixels
             for (int k = 0; k < cf.refine; k++) {
-                hipLaunchKernelGGL(k_resid, dim3(n_stamps), dim3(256), 0, st, n_stamps, nb, ns, N,
+                hipLaunchKernelGGL(k_resid, dim3(n_stamps), dim3(RES_T), 0, st, n_stamps, nb, ns, N,
                                    npix, stamp_design, G, coeffs, fitted, gt, stamp_chi2, state);
-                hipLaunchKernelGGL(k_assemble_vec, dim3((N + 255) / 256), dim3(256), 0, st, n_stamps,
+                hipLaunchKernelGGL(k_assemble_vec, dim3(N), dim3(64), 0, st, n_stamps,
                                    nb, ns, N, gt, G, used, gv, state);
                 hipLaunchKernelGGL(k_resolve, dim3(1), dim3(CH_THREADS), lds, st, N, M, ILg, Dg, gv,
                                    coeffs, state);
             }
-            hipLaunchKernelGGL(k_resid, dim3(n_stamps), dim3(256), 0, st, n_stamps, nb, ns, N, npix,
+            hipLaunchKernelGGL(k_resid, dim3(n_stamps), dim3(RES_T), 0, st, n_stamps, nb, ns, N, npix,
                                stamp_design, G, coeffs, fitted, gt, stamp_chi2, state);
         } else if (n_stamps > 0) {
             hipLaunchKernelGGL(k_chi2_clip, dim3(n_stamps), dim3(64), 0, st, n_stamps, nb, ns, N,
