@@ -108,11 +108,11 @@ __global__ void k_transpose_sums_b(const PairDesc* __restrict__ pairs, int L) {
     transpose_sums_body(p.n, L, p.Ms, p.bs, p.Mt, p.bt, blockIdx.x, gridDim.x);
 }
 
-// One item per (i, j, s) of the per-stamp index space, 32 items per
-// workgroup; the stamps are split over 8 threads per item (stamp-major
-// sums, so consecutive stamps are consecutive words) and the partial sums
-// are added in LDS in a fixed order.
-constexpr int ASM_ITEMS = 32, ASM_CHUNKS = 8;
+// One item per (i, j, s) of the per-stamp index space, 8 items per
+// workgroup; the stamps are split over the 32 lanes of a half-wave per item
+// (stamp-major sums, so consecutive stamps are consecutive words) and the
+// partial sums are added by shuffles in a fixed order.
+constexpr int ASM_ITEMS = 8, ASM_CHUNKS = 32;
 
 template <int NS>
 __device__ void assemble_body(int n, int nb, int N, const double* __restrict__ Mt,
@@ -120,7 +120,6 @@ __device__ void assemble_body(int n, int nb, int N, const double* __restrict__ M
                               const uint8_t* __restrict__ used, double* __restrict__ M,
                               double* __restrict__ b, const SolveState* st, const int bid) {
     if (st->done) return;
-    __shared__ double red[ASM_ITEMS][ASM_CHUNKS][NS];
     const int L = nb + 1;
     const int chunk = threadIdx.x % ASM_CHUNKS, li = threadIdx.x / ASM_CHUNKS;
     const int t = bid * ASM_ITEMS + li;
@@ -162,16 +161,16 @@ __device__ void assemble_body(int n, int nb, int N, const double* __restrict__ M
             acc[0] += ((i == nb) ? u : u * g[s]) * brow[k];
         }
     }
-#pragma unroll
-    for (int q = 0; q < NS; q++) red[li][chunk][q] = acc[q];
-    __syncthreads();
-    if (chunk != 0 || kind == 0) return;
+    // the item's 32 lanes (one half-wave) add their partial sums in a fixed
+    // butterfly order
 #pragma unroll
     for (int q = 0; q < NS; q++) {
-        double v = 0.0;
-        for (int c = 0; c < ASM_CHUNKS; c++) v += red[li][c][q];
+        double v = acc[q];
+#pragma unroll
+        for (int o = ASM_CHUNKS / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
         acc[q] = v;
     }
+    if (chunk != 0 || kind == 0) return;
     if (kind == 1) {
         const int row = (i == nb) ? N - 1 : i * NS + s;
         if (j == nb) {
