@@ -84,26 +84,49 @@ __global__ void k_solve_init_b(const PairDesc* __restrict__ pairs, int min_stamp
 
 // Stamp-major copy of the stamp sums: Mt[ij][k] = M_k[ij], bt[i][k] = b_k[i],
 // so that the assembly reads each (i, j) entry of all stamps contiguously.
+// Tiles of 32 stamps x 64 entries go through LDS, so that both the reads
+// (along the entries of a stamp) and the writes (along the stamps of an
+// entry) are contiguous; workgroup bid, bid + nblk, ... take the tiles.
+constexpr int TS_K = 32, TS_R = 64;
 __device__ void transpose_sums_body(int n, int L, const double* __restrict__ Ms,
                                     const double* __restrict__ bs, double* __restrict__ Mt,
                                     double* __restrict__ bt, int bid, int nblk) {
-    const int LL = L * L;
-    for (size_t e = (size_t)bid * blockDim.x + threadIdx.x; e < (size_t)n * (LL + L);
-         e += (size_t)nblk * blockDim.x) {
-        const int k = (int)(e % n);
-        const size_t r = e / n;
-        if (r < (size_t)LL) Mt[r * n + k] = Ms[(size_t)k * LL + r];
-        else bt[(r - LL) * n + k] = bs[(size_t)k * L + (r - LL)];
+    __shared__ double tile[TS_K][TS_R + 1];
+    const int LL = L * L, R = LL + L;
+    const int tk = (n + TS_K - 1) / TS_K, tr = (R + TS_R - 1) / TS_R;
+    const int tid = threadIdx.x;
+    for (int tb = bid; tb < tk * tr; tb += nblk) {
+        const int k0 = (tb % tk) * TS_K, r0 = (tb / tk) * TS_R;
+        __syncthreads();                        // the previous tile's writes are done
+#pragma unroll
+        for (int m = 0; m < TS_K * TS_R / 256; m++) {
+            const int kk = tid / TS_R + (256 / TS_R) * m, rr = tid % TS_R;
+            const int k = k0 + kk, r = r0 + rr;
+            double v = 0.0;
+            if (k < n && r < R) v = r < LL ? Ms[(size_t)k * LL + r] : bs[(size_t)k * L + (r - LL)];
+            tile[kk][rr] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < TS_K * TS_R / 256; m++) {
+            const int rr = tid / TS_K + (256 / TS_K) * m, kk = tid % TS_K;
+            const int k = k0 + kk, r = r0 + rr;
+            if (k < n && r < R) {
+                if (r < LL) Mt[(size_t)r * n + k] = tile[kk][rr];
+                else bt[(size_t)(r - LL) * n + k] = tile[kk][rr];
+            }
+        }
     }
 }
 
-__global__ void k_transpose_sums(int n, int L, const double* __restrict__ Ms,
-                                 const double* __restrict__ bs, double* __restrict__ Mt,
-                                 double* __restrict__ bt) {
+__global__ __launch_bounds__(256) void k_transpose_sums(int n, int L, const double* __restrict__ Ms,
+                                                        const double* __restrict__ bs,
+                                                        double* __restrict__ Mt,
+                                                        double* __restrict__ bt) {
     transpose_sums_body(n, L, Ms, bs, Mt, bt, blockIdx.x, gridDim.x);
 }
 
-__global__ void k_transpose_sums_b(const PairDesc* __restrict__ pairs, int L) {
+__global__ __launch_bounds__(256) void k_transpose_sums_b(const PairDesc* __restrict__ pairs, int L) {
     const PairDesc& p = pairs[blockIdx.y];
     transpose_sums_body(p.n, L, p.Ms, p.bs, p.Mt, p.bt, blockIdx.x, gridDim.x);
 }
@@ -1556,7 +1579,7 @@ int batch_solve(const psfm_context* ctx, const PairDesc* pairs, const int* stamp
     const int nt = std::max(std::max(max_n, max_N), 1);
     hipLaunchKernelGGL(k_solve_init_b, dim3((nt + 255) / 256, n_pairs), dim3(256), 0, st, pairs,
                        cf.min_stamps);
-    hipLaunchKernelGGL(k_transpose_sums_b, dim3(64, n_pairs), dim3(256), 0, st, pairs, L);
+    hipLaunchKernelGGL(k_transpose_sums_b, dim3(256, n_pairs), dim3(256), 0, st, pairs, L);
     PSFM_HIP_CHECK(hipGetLastError());
     for (int it = 0; it < cf.max_iter; it++) {
 #define PSFM_ASM_B(NSV)                                                                          \
@@ -1630,8 +1653,11 @@ static int solve_impl(const psfm_context* ctx, int W, int H, const int32_t* stam
                        G, stamp_chi2, coeffs, state);
     PSFM_HIP_CHECK(hipGetLastError());
     const int nthreads_asm = L * L * ns + L * ns;
-    if (n_stamps > 0)
-        hipLaunchKernelGGL(k_transpose_sums, dim3(256), dim3(256), 0, st, n_stamps, L, stamp_M, stamp_b, Mt, bt);
+    if (n_stamps > 0) {
+        const int tiles = (n_stamps + TS_K - 1) / TS_K * ((L * L + L + TS_R - 1) / TS_R);
+        hipLaunchKernelGGL(k_transpose_sums, dim3(std::min(tiles, 1024)), dim3(256), 0, st, n_stamps, L,
+                           stamp_M, stamp_b, Mt, bt);
+    }
     if (prior && n_stamps > 0) {
         // completed predictions, then (warm start -> kernel-sum clip) rounds
         hipLaunchKernelGGL(k_prior_chi2, dim3(n_stamps), dim3(64), 0, st, nb, stamp_M, stamp_b, stamp_e,
