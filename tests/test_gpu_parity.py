@@ -240,6 +240,16 @@ def test_ragged_shapes(W, H, P, h, r, S):
     assert np.array_equal(_np(cm), cm_r)
     assert np.max(np.abs(_np(var) - var_r) / np.maximum(np.abs(var_r), 1e-30)) < 1e-5
     assert np.max(np.abs(_np(cov) - cov_r)) < 1e-12
+    # the difference on the oracle's convolved planes (widths that are not a
+    # multiple of 4 take the one-pixel-per-thread subtraction)
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    sub = ctx.subtract(at, d["I2"], d["V2"], d["M2"], t(conv_r), t(var_r), t(cm_r), t(cov_r))
+    torch.cuda.synchronize()
+    D, VD, MD, CD = O.subtract(cfg, a, pair.I2, pair.V2, pair.M2, conv_r, var_r, cm_r, cov_r)
+    assert np.max(np.abs(_np(sub["diff"]) - D) / np.maximum(np.abs(np.nan_to_num(pair.I2)), 1)) < 1e-6
+    assert np.array_equal(_np(sub["diff_var"]), VD)
+    assert np.array_equal(_np(sub["diff_mask"]), MD)
+    assert np.max(np.abs(_np(sub["cov_diff"]) - CD)) < 1e-12
 
 
 def test_too_few_stamps_and_empty():
