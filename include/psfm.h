@@ -300,6 +300,20 @@ int psfm_propagate_variance(const psfm_context* ctx, const double* coeffs, const
                             psfm_fit_stats* stats, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * psfm_convolve_image and psfm_propagate_variance of the same pair in one
+ * call (Section 4.2, Eqs. 12-13; Sections 3.4, 3.5, 4.3): every output tile
+ * realises its patch kernel once and forms both I' (with out_mask) and V'.
+ * Arguments, layouts and results are those of the two calls (I and V share
+ * the mask M and the pitch); the outputs are bit-identical to theirs.  The
+ * workspace is psfm_propagate_variance's.
+ */
+int psfm_convolve_pair(const psfm_context* ctx, const double* coeffs, const float* I,
+                       const float* V, const uint8_t* M, int W, int H, int64_t pitch,
+                       const double* cov_in, int cov_in_half, float* out, uint8_t* out_mask,
+                       float* var_out, double* cov_out, int cov_out_half, psfm_fit_stats* stats,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/*
  * Difference image (Section 4.3; sign: science minus matched reference):
  *   diff = I2 - conv - d0, diff_var = V2 + conv_var,
  *   diff_mask = (M2 != 0 ? PSFM_MASK_BAD : 0) | conv_mask,

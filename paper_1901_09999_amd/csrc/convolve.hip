@@ -389,6 +389,99 @@ int dispatch_conv(const float* src, const uint8_t* M, int W, int H, int64_t pitc
     }
 }
 
+// Image and variance convolution of one tile in one workgroup: the patch
+// kernel and its statistics are realised once (both tap sets), then the
+// halo of I (with the mask bits) gives I' and its mask, and the halo of V
+// (same buffer, after every wave is done with I) gives V'.  The arithmetic
+// of each plane is that of k_conv_tile<H_, 0> and <H_, 1>.
+template <int H_>
+__global__ __launch_bounds__(256) void k_conv_pair_tile(
+    const float* __restrict__ I, const float* __restrict__ V, const uint8_t* __restrict__ M, int W,
+    int H, int64_t pitch, int P, const double* __restrict__ a, BasisArgs B, double bad_frac,
+    const double* __restrict__ cov_in, int c_in, float* __restrict__ out,
+    uint8_t* __restrict__ out_mask, float* __restrict__ var_out) {
+    constexpr int KW = 2 * H_ + 1;
+    constexpr int T = KW * KW;
+    constexpr int HW = TILE + 2 * H_;
+    constexpr int NWB = (HW + 31) / 32 + 1;
+    static_assert(sizeof(float) * HW * HW >= sizeof(RealiseLds) + sizeof(double) * T,
+                  "kernel scratch must fit in the halo buffer");
+    __shared__ __align__(16) float halo[HW * HW];
+    __shared__ __align__(16) float tapsK[T + 4];
+    __shared__ __align__(16) float tapsV[T + 4];
+    __shared__ uint32_t badw[HW][NWB];
+    __shared__ double ring[H_ + 1];
+    __shared__ double red[16];
+    __shared__ int s_rb;
+    __shared__ double s_f;
+    const int tid = threadIdx.x;
+    const PatchGeom g = patch_geom(W, H, P);
+    const int px = blockIdx.x / g.tpp, sx = blockIdx.x % g.tpp;
+    const int py = blockIdx.y / g.tpp, sy = blockIdx.y % g.tpp;
+    const int X0 = px * P + sx * TILE, Y0 = py * P + sy * TILE;
+    const int X1 = min(min(X0 + TILE, (px + 1) * P), W);
+    const int Y1 = min(min(Y0 + TILE, (py + 1) * P), H);
+    if (X0 >= X1 || Y0 >= Y1) return;
+
+    patch_taps<H_>(B, a, W, H, P, px, py, bad_frac, cov_in, c_in, halo, tapsK, tapsV, ring, red,
+                   &s_rb, &s_f);
+    const int lx = tid & 63;
+    const int r0 = (tid >> 6) * 16;
+    const int gx = X0 + lx;
+    float acc[16];
+    {
+        const int anybad = load_halo<H_, true>(I, M, W, H, pitch, X0, Y0, halo, badw);
+        conv16<H_>(halo, tapsK, lx, r0, acc);
+        uint32_t bad16 = 0, poor16 = 0;
+        if (anybad) mask16<H_>(badw, s_rb, lx, r0, &bad16, &poor16);
+        if (gx < X1) {
+#pragma unroll
+            for (int j = 0; j < 16; j++) {
+                const int gy = Y0 + r0 + j;
+                if (gy < Y1) {
+                    out[(int64_t)gy * pitch + gx] = acc[j];
+                    out_mask[(int64_t)gy * pitch + gx] = ((bad16 >> j) & 1u) ? PSFM_MASK_CONV_BAD
+                                                         : ((poor16 >> j) & 1u) ? PSFM_MASK_CONV_POOR
+                                                                                : 0;
+                }
+            }
+        }
+    }
+    __syncthreads();                       // every wave is done with the image halo
+    load_halo<H_, false>(V, M, W, H, pitch, X0, Y0, halo, badw);
+    conv16<H_>(halo, tapsV, lx, r0, acc);
+    if (gx < X1) {
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+            const int gy = Y0 + r0 + j;
+            if (gy < Y1) var_out[(int64_t)gy * pitch + gx] = acc[j];
+        }
+    }
+}
+
+int dispatch_conv_pair(const float* I, const float* V, const uint8_t* M, int W, int H,
+                       int64_t pitch, int P, const double* a, const BasisArgs& B, double bad_frac,
+                       const double* cov_in, int c_in, float* out, uint8_t* out_mask,
+                       float* var_out, hipStream_t st) {
+    const PatchGeom g = patch_geom(W, H, P);
+    const dim3 grid(g.npx * g.tpp, g.npy * g.tpp);
+    switch (B.h) {
+#define PSFM_CP_CASE(HH)                                                                             \
+    case HH:                                                                                         \
+        hipLaunchKernelGGL((k_conv_pair_tile<HH>), grid, dim3(256), 0, st, I, V, M, W, H, pitch, P,  \
+                           a, B, bad_frac, cov_in, c_in, out, out_mask, var_out);                    \
+        break;
+        PSFM_CP_CASE(1) PSFM_CP_CASE(2) PSFM_CP_CASE(3) PSFM_CP_CASE(4) PSFM_CP_CASE(5)
+        PSFM_CP_CASE(6) PSFM_CP_CASE(7) PSFM_CP_CASE(8) PSFM_CP_CASE(9) PSFM_CP_CASE(10)
+        PSFM_CP_CASE(11) PSFM_CP_CASE(12) PSFM_CP_CASE(13) PSFM_CP_CASE(14) PSFM_CP_CASE(15)
+        PSFM_CP_CASE(16)
+#undef PSFM_CP_CASE
+        default: return PSFM_ERR_UNSUPPORTED;
+    }
+    PSFM_HIP_CHECK(hipGetLastError());
+    return PSFM_OK;
+}
+
 // Normalised autocorrelation of the kernel realised at the centre of cell j
 // of the 3 x 3 partition:
 //   A(e) = sum_u K(u) K(u + e) / sum_u K(u)^2,   |e_x|, |e_y| <= 2h,
@@ -903,6 +996,30 @@ extern "C" int psfm_convolve_image(const psfm_context* ctx, const double* coeffs
                             0, out, out_mask, st);
 }
 
+// The covariance pseudo-matrix part of the variance propagation: samples at
+// the centres of the 3 x 3 partition, their mean, normalised and cropped.
+static int cov_pseudo(const psfm_context* ctx, const double* coeffs, int W, int H,
+                      const double* cov_in, int cov_in_half, double* cov_out, int cov_out_half,
+                      psfm_fit_stats* stats, void* ws, hipStream_t st) {
+    psfm::Carver c(ws);
+    const int Rmax = 2 * ctx->h + 32;
+    double* samples = c.take<double>((size_t)PSFM_COV_SAMPLES * (2 * Rmax + 1) * (2 * Rmax + 1));
+    double* avg = c.take<double>((size_t)(2 * Rmax + 1) * (2 * Rmax + 1));
+    const int E = 4 * ctx->h + 1;
+    double* autoc = c.take<double>((size_t)PSFM_COV_SAMPLES * E * E);
+    const int R = 2 * ctx->h + cov_in_half, Rw = 2 * R + 1;
+    // uncorrelated input: the samples are the autocorrelation itself
+    hipLaunchKernelGGL(k_cov_auto, dim3(PSFM_COV_SAMPLES, E), dim3(256), 0, st, coeffs,
+                       basis_args(ctx), W, H, cov_in ? autoc : samples);
+    if (cov_in)
+        hipLaunchKernelGGL(k_cov_mix, dim3(PSFM_COV_SAMPLES, (Rw * Rw + 255) / 256), dim3(256), 0, st,
+                           autoc, ctx->h, cov_in, cov_in_half, samples);
+    hipLaunchKernelGGL(k_cov_finish, dim3(1), dim3(1024), 0, st, samples, R, avg, cov_out,
+                       cov_out_half, stats);
+    PSFM_HIP_CHECK(hipGetLastError());
+    return PSFM_OK;
+}
+
 extern "C" int psfm_propagate_variance(const psfm_context* ctx, const double* coeffs,
                                        const float* V, const uint8_t* M, int W, int H,
                                        int64_t pitch, const double* cov_in, int cov_in_half,
@@ -917,27 +1034,33 @@ extern "C" int psfm_propagate_variance(const psfm_context* ctx, const double* co
     if (!cov_in) cov_in_half = 0;
     if (!ws || ws_bytes < psfm::conv_workspace(ctx, W, H)) return PSFM_ERR_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
-    psfm::Carver c(ws);
-    const int Rmax = 2 * ctx->h + 32;
-    double* samples = c.take<double>((size_t)PSFM_COV_SAMPLES * (2 * Rmax + 1) * (2 * Rmax + 1));
-    double* avg = c.take<double>((size_t)(2 * Rmax + 1) * (2 * Rmax + 1));
-    const int E = 4 * ctx->h + 1;
-    double* autoc = c.take<double>((size_t)PSFM_COV_SAMPLES * E * E);
     const psfm_config& cf = ctx->cfg;
     rc = dispatch_conv<1>(V, M, W, H, pitch, cf.patch, coeffs, basis_args(ctx), cf.bad_frac, cov_in,
                           cov_in_half, var_out, nullptr, st);
     if (rc) return rc;
-    const int R = 2 * ctx->h + cov_in_half, Rw = 2 * R + 1;
-    // uncorrelated input: the samples are the autocorrelation itself
-    hipLaunchKernelGGL(k_cov_auto, dim3(PSFM_COV_SAMPLES, E), dim3(256), 0, st, coeffs,
-                       basis_args(ctx), W, H, cov_in ? autoc : samples);
-    if (cov_in)
-        hipLaunchKernelGGL(k_cov_mix, dim3(PSFM_COV_SAMPLES, (Rw * Rw + 255) / 256), dim3(256), 0, st,
-                           autoc, ctx->h, cov_in, cov_in_half, samples);
-    hipLaunchKernelGGL(k_cov_finish, dim3(1), dim3(1024), 0, st, samples, R, avg, cov_out,
-                       cov_out_half, stats);
-    PSFM_HIP_CHECK(hipGetLastError());
-    return PSFM_OK;
+    return cov_pseudo(ctx, coeffs, W, H, cov_in, cov_in_half, cov_out, cov_out_half, stats, ws, st);
+}
+
+extern "C" int psfm_convolve_pair(const psfm_context* ctx, const double* coeffs, const float* I,
+                                  const float* V, const uint8_t* M, int W, int H, int64_t pitch,
+                                  const double* cov_in, int cov_in_half, float* out,
+                                  uint8_t* out_mask, float* var_out, double* cov_out,
+                                  int cov_out_half, psfm_fit_stats* stats, void* ws,
+                                  size_t ws_bytes, void* stream) {
+    int rc = check_image_args(ctx, W, H, pitch);
+    if (rc) return rc;
+    if (!coeffs || !I || !V || !M || !out || !out_mask || !var_out || !cov_out ||
+        cov_out_half < 0 || cov_in_half < 0)
+        return PSFM_ERR_INVALID_ARG;
+    if (cov_in_half > 32 || cov_out_half > 2 * ctx->h + 64) return PSFM_ERR_UNSUPPORTED;
+    if (!cov_in) cov_in_half = 0;
+    if (!ws || ws_bytes < psfm::conv_workspace(ctx, W, H)) return PSFM_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    const psfm_config& cf = ctx->cfg;
+    rc = dispatch_conv_pair(I, V, M, W, H, pitch, cf.patch, coeffs, basis_args(ctx), cf.bad_frac,
+                            cov_in, cov_in_half, out, out_mask, var_out, st);
+    if (rc) return rc;
+    return cov_pseudo(ctx, coeffs, W, H, cov_in, cov_in_half, cov_out, cov_out_half, stats, ws, st);
 }
 
 extern "C" int psfm_subtract(const psfm_context* ctx, const double* coeffs, const float* I2,

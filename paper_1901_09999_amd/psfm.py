@@ -116,6 +116,7 @@ def lib():
             "psfm_solve": (i, [P, i, i, P, i, P, P, P, P, P, P, P, P, P, P, sz, P]),
             "psfm_convolve_image": (i, [P, P, P, P, i, i, i64, P, P, P, sz, P]),
             "psfm_propagate_variance": (i, [P, P, P, P, i, i, i64, P, i, P, P, i, P, P, sz, P]),
+            "psfm_convolve_pair": (i, [P, P, P, P, P, i, i, i64, P, i, P, P, P, P, i, P, P, sz, P]),
             "psfm_subtract": (i, [P, P, P, P, P, P, P, P, i, i, i64, P, i, P, i, P, P, P, P, i, P,
                                   sz, P]),
             "psfm_status_string": (C.c_char_p, [i]),
@@ -335,6 +336,25 @@ class Context:
                "psfm_propagate_variance")
         return out, cov_out
 
+    def convolve_pair(self, coeffs, I, V, M, cov_in=None, c_out=10, stats=None, out=None,
+                      out_mask=None, var_out=None, cov_out=None):
+        """psfm_convolve_pair: convolve_image and propagate_variance in one call
+        (one patch-kernel realisation per tile); returns (conv, conv_mask, var, cov)."""
+        H, W = I.shape
+        out = torch.empty_like(I) if out is None else out
+        out_mask = torch.empty_like(M) if out_mask is None else out_mask
+        var_out = torch.empty_like(V) if var_out is None else var_out
+        if cov_out is None:
+            cov_out = torch.empty((2 * c_out + 1, 2 * c_out + 1), dtype=torch.float64,
+                                  device=self.device)
+        c_in = 0 if cov_in is None else (cov_in.shape[0] - 1) // 2
+        ws = self.workspace(W, H, 0)
+        _check(lib().psfm_convolve_pair(self._h, _ptr(coeffs), _ptr(I), _ptr(V), _ptr(M), W, H, W,
+                                        _ptr(cov_in), c_in, _ptr(out), _ptr(out_mask), _ptr(var_out),
+                                        _ptr(cov_out), c_out, _ptr(stats), _ptr(ws), ws.numel(),
+                                        _stream()), "psfm_convolve_pair")
+        return out, out_mask, var_out, cov_out
+
     def subtract(self, coeffs, I2, V2, M2, conv, conv_var, conv_mask, cov_conv, cov2=None,
                  c_d=None, out=None):
         H, W = I2.shape
@@ -362,9 +382,10 @@ class Context:
         fit = self.fit_stamps(I1, M1, I2, V2, M2, stamps, out=b["fit"])
         b["flags_in"].copy_(fit["flags"])
         sol = self.solve(W, H, stamps, fit, flags=b["flags_in"], out=b["sol"], flags_inplace=True)
-        conv, cmask = self.convolve_image(sol["coeffs"], I1, M1, out=b["conv"], out_mask=b["conv_mask"])
-        var, cov = self.propagate_variance(sol["coeffs"], V1, M1, c_out=c_out, stats=sol["stats"],
-                                           out=b["var"], cov_out=b["cov"])
+        conv, cmask, var, cov = self.convolve_pair(sol["coeffs"], I1, V1, M1, c_out=c_out,
+                                                   stats=sol["stats"], out=b["conv"],
+                                                   out_mask=b["conv_mask"], var_out=b["var"],
+                                                   cov_out=b["cov"])
         sub = self.subtract(sol["coeffs"], I2, V2, M2, conv, var, cmask, cov, out=b["sub"])
         return dict(fit=fit, sol=sol, conv=conv, conv_mask=cmask, var=var, cov=cov, **sub)
 
@@ -535,7 +556,8 @@ def exported_symbols() -> Sequence[str]:
     return ["psfm_config_default", "psfm_create", "psfm_destroy", "psfm_n_basis", "psfm_n_spatial",
             "psfm_n_unknowns", "psfm_stamp_dim", "psfm_workspace_bytes", "psfm_stamp_design_floats",
             "psfm_fit_stamps",
-            "psfm_solve", "psfm_convolve_image", "psfm_propagate_variance", "psfm_subtract",
+            "psfm_solve", "psfm_convolve_image", "psfm_propagate_variance", "psfm_convolve_pair",
+            "psfm_subtract",
             "psfm_status_string", "psfm_batch_workspace_bytes", "psfm_batch_plan",
             "psfm_batch_run", "psfm_batch_run_stage", "psfm_batch_set_tuning", "psfm_batch_graph_capture",
             "psfm_batch_graph_launch", "psfm_batch_destroy", "psfm_wall_clock_hz",

@@ -364,3 +364,45 @@ def test_cholesky_solve_matches_oracle():
     _, info2 = psfm.cholesky_solve(torch.from_numpy(M2).cuda(), torch.from_numpy(b).cuda())
     torch.cuda.synchronize()
     assert int(_np(info2)[0]) == info_o2 == 101
+
+
+@pytest.mark.parametrize("W,H,P,h,c_in", [(2048, 2048, 64, 10, 0), (300, 217, 64, 5, 1),
+                                          (161, 190, 50, 3, 2)])
+def test_convolve_pair_equals_separate_calls(W, H, P, h, c_in):
+    """psfm_convolve_pair (one patch realisation per tile for both planes) is
+    bit-identical to psfm_convolve_image + psfm_propagate_variance, with an
+    uncorrelated or a correlated input, on full and ragged tilings."""
+    torch, psfm = hip()
+    base = synth.WORKLOADS["pair2048"]
+    wl = base if W == 2048 else synth.scaled(base, f"cp{W}x{H}", W, H, n_sources=max(40, W * H // 600),
+                                             n_stamps=20, kernel_half=h, patch=P)
+    pair = synth.make_pair(wl, 31 + W)
+    cfg = O.Config.from_workload(wl)
+    ctx = _ctx(wl)
+    d = psfm.to_device(pair)
+    rng = np.random.default_rng(W)
+    a = np.zeros(cfg.n_unknowns)
+    a[0] = 1.0
+    a[: cfg.n_unknowns - 1] += 0.02 * rng.standard_normal(cfg.n_unknowns - 1)
+    a[-1] = 2.0
+    at = torch.from_numpy(a).cuda()
+    cin = None
+    if c_in:
+        q = rng.uniform(0.0, 1.0, (2 * c_in + 1, 2 * c_in + 1))
+        cin_np = np.array([[np.sum(q[max(0, -dy):q.shape[0] - max(0, dy), max(0, -dx):q.shape[1] - max(0, dx)] *
+                                   q[max(0, dy):q.shape[0] - max(0, -dy), max(0, dx):q.shape[1] - max(0, -dx)])
+                            for dx in range(-c_in, c_in + 1)] for dy in range(-c_in, c_in + 1)])
+        cin = torch.from_numpy(cin_np / cin_np[c_in, c_in]).cuda()
+    print(f"{W}x{H} P={P} h={h} c_in={c_in}", flush=True)
+    s1 = torch.zeros(psfm.STATS_BYTES, dtype=torch.uint8, device="cuda")
+    s2 = torch.zeros(psfm.STATS_BYTES, dtype=torch.uint8, device="cuda")
+    conv, cm = ctx.convolve_image(at, d["I1"], d["M1"])
+    var, cov = ctx.propagate_variance(at, d["V1"], d["M1"], cov_in=cin, c_out=12, stats=s1)
+    conv2, cm2, var2, cov2 = ctx.convolve_pair(at, d["I1"], d["V1"], d["M1"], cov_in=cin, c_out=12,
+                                               stats=s2)
+    torch.cuda.synchronize()
+    assert np.array_equal(_np(conv2), _np(conv))
+    assert np.array_equal(_np(cm2), _np(cm))
+    assert np.array_equal(_np(var2), _np(var))
+    assert np.array_equal(_np(cov2), _np(cov))
+    assert psfm.read_stats(s2)["cov_discarded_frac"] == psfm.read_stats(s1)["cov_discarded_frac"]
