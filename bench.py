@@ -412,22 +412,30 @@ def main():
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
+        # the timed steps carry no events of their own (a timing event between
+        # stages idles the GPU for a few microseconds)
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        start.record()
+        for k in range(steps):
+            step()
+        stop.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        gpu_ms = float(start.elapsed_time(stop)) / steps
+        # stage split: the same number of steps again, with an event after each stage
         NS = 4      # stages: fit, solve, convolve (image + variance + pseudo-matrix), subtract
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(NS)] for _ in range(steps)]
-        start = torch.cuda.Event(enable_timing=True)
-        t0 = time.perf_counter()
         start.record()
         for k in range(steps):
             step(evs[k])
         torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
         stage = np.zeros(NS)
         for k in range(steps):
             prev = start if k == 0 else evs[k - 1][NS - 1]
             marks = [prev] + evs[k]
             stage += [marks[i].elapsed_time(marks[i + 1]) for i in range(NS)]
         stage /= steps
-        gpu_ms = float(start.elapsed_time(evs[-1][NS - 1])) / steps
         stats = psfm.read_stats(bufs["sol"]["stats"])
         # the image convolution alone (its own launches, HIP events), for its roofline
         s = bufs["sol"]

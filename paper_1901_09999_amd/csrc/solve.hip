@@ -284,13 +284,6 @@ __device__ __forceinline__ void load_panel(int N, const double* __restrict__ S, 
     }
 }
 
-// The stored inverse of panel p's 32 x 32 diagonal block into Iv (LDS,
-// row stride CH_PS).
-__device__ __forceinline__ void load_inverse(const double* __restrict__ ILg, int p, double* Iv) {
-    for (int e = threadIdx.x; e < IV_DOUBLES; e += CH_THREADS)
-        Iv[(e >> 5) * CH_PS + (e & 31)] = ILg[(size_t)p * IV_DOUBLES + e];
-}
-
 // z <- Iv z over the panel's unknowns (forward substitution through the
 // diagonal block), by the first 32 lanes of wave 0.
 __device__ __forceinline__ void diag_forward(int k0, int nk, const double* Iv, double* zb) {
@@ -306,55 +299,158 @@ __device__ __forceinline__ void diag_forward(int k0, int nk, const double* Iv, d
     if (lane < nk) zb[k0 + lane] = z;
 }
 
-// Back substitution L^T w = z with the factor in the lower triangle of A and
-// the stored diagonal-block inverses; z (LDS) is overwritten by w.  Per
-// panel, in reverse: rhs = z_p - L_below^T w_below (all threads), then
-// w_p = Iv^T rhs (wave 0).  P, Iv, part are LDS scratch of the caller.
-__device__ __forceinline__ void back_subst(int N, const double* __restrict__ A, const double* __restrict__ ILg,
-                           double* zb, double* P, double* Iv, double* part) {
+// The stored diagonal-block inverses of an N-unknown factor into P when
+// they fit there (returns whether they did).
+__device__ __forceinline__ bool stage_inverses(int N, const double* __restrict__ ILg, double* P) {
+    const int np = (N + CH_NB - 1) / CH_NB;
+    const bool staged = np * IV_DOUBLES <= (max(N, CH_NB) + 16) * CH_PS;
+    if (staged) {
+        constexpr int CHUNK = 8;        // loads in flight per thread
+        const int total = np * IV_DOUBLES;
+        for (int e0 = threadIdx.x; e0 < total; e0 += CH_THREADS * CHUNK) {
+            double v[CHUNK];
+#pragma unroll
+            for (int u = 0; u < CHUNK; u++) v[u] = ILg[min(e0 + CH_THREADS * u, total - 1)];
+#pragma unroll
+            for (int u = 0; u < CHUNK; u++)
+                if (e0 + CH_THREADS * u < total) P[e0 + CH_THREADS * u] = v[u];
+        }
+    }
+    __syncthreads();
+    return staged;
+}
+
+// The LDS copy of panel q's stored inverse: in place when all of them were
+// staged, else loaded into the head of P (which always holds one).  Every
+// thread of the workgroup calls it, after a barrier that follows the
+// previous step's reads.
+__device__ __forceinline__ const double* step_inverse(int q, bool staged, const double* __restrict__ ILg,
+                                                      double* P) {
+    if (staged) return P + q * IV_DOUBLES;
+    for (int e = threadIdx.x; e < IV_DOUBLES; e += CH_THREADS) P[e] = ILg[(size_t)q * IV_DOUBLES + e];
+    __syncthreads();
+    return P;
+}
+
+// Row (TRANS = false) or column (TRANS = true) `lane` of a 32 x 32 inverse
+// in LDS times z[0..31]; four independent FP64 chains.
+template <bool TRANS>
+__device__ __forceinline__ double iv_dot(const double* __restrict__ iv, const double* z, int lane) {
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < CH_NB; k++) s4[k & 3] += iv[TRANS ? k * CH_NB + lane : lane * CH_NB + k] * z[k];
+    return (s4[0] + s4[1]) + (s4[2] + s4[3]);
+}
+
+// Forward substitution L z = z (z in LDS, overwritten) with a stored factor,
+// right-looking: z_q = Iv_q z_q (wave 0), then every row below the panel
+// takes it out, z_i -= sum_t L(i, q0 + t) z_(q0 + t) (one thread per row).
+// The rows of the next panel are loaded during this panel's update (two
+// register sets, the step loop unrolled by two so that they swap without a
+// copy), so that no load stands in front of wave 0's z_q, the serial chain.
+// Inverses as in back_subst.
+__device__ __forceinline__ void forward_subst(int N, const double* __restrict__ A,
+                                              const double* __restrict__ ILg, double* zb, double* P,
+                                              bool staged, double* wq) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    constexpr int NPART = CH_THREADS / 32;
-    for (int k0 = ((N - 1) / CH_NB) * CH_NB; k0 >= 0; k0 -= CH_NB) {
-        const int nk = min(CH_NB, N - k0);
-        const int rows = N - k0;
-        load_panel(N, A, k0, nk, nk, rows, rows, P, nullptr);
-        load_inverse(ILg, k0 / CH_NB, Iv);
-        __syncthreads();
-        {
-            const int c = tid & 31, w = tid >> 5;
-            double a0 = 0.0, a1 = 0.0;
-            if (c < nk) {
-                int i = nk + w;
-                for (; i + NPART < rows; i += 2 * NPART) {
-                    a0 += P[i * CH_PS + c] * zb[k0 + i];
-                    a1 += P[(i + NPART) * CH_PS + c] * zb[k0 + i + NPART];
-                }
-                if (i < rows) a0 += P[i * CH_PS + c] * zb[k0 + i];
+    const int np = (N + CH_NB - 1) / CH_NB;
+    // row q0 + nk + tid's nk entries of panel q (zeros beyond nk); a wave
+    // with no row below the panel issues no loads (the vector memory
+    // pipeline, not the bytes, bounds these steps)
+    auto load_row = [&](int q, double* lv) {
+        const int q0 = q * CH_NB, nk = min(CH_NB, N - q0);
+        const bool need = wave * 64 < N - q0 - nk;
+        const double* row = A + (size_t)min(q0 + nk + tid, N - 1) * N + q0;
+#pragma unroll
+        for (int t = 0; t < CH_NB; t++) {
+            if (need && t < nk) lv[t] = row[t];
+            else lv[t] = 0.0;
+        }
+    };
+    auto step = [&](int q, const double* lv, double* ln) {
+        const int q0 = q * CH_NB, nk = min(CH_NB, N - q0);
+        const int i = q0 + nk + tid;
+        const double* iv = step_inverse(q, staged, ILg, P);
+        if (wave == 0) {
+            double z = 0.0;
+            if (lane < CH_NB) {
+                z = iv_dot<false>(iv, zb + q0, lane);
+                wq[lane] = z;
             }
-            part[c * NPART + w] = a0 + a1;
+            wave_sync();
+            if (lane < nk) zb[q0 + lane] = z;
         }
         __syncthreads();
-        if (wave == 0) {
-            double v = 0.0;
-            if (lane < nk) {
-                double p4[4] = {0.0, 0.0, 0.0, 0.0};
+        if (q + 1 < np) load_row(q + 1, ln);
+        if (i < N) {
+            double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int w = 0; w < NPART; w++) p4[w & 3] += part[lane * NPART + w];
-                v = zb[k0 + lane] - ((p4[0] + p4[1]) + (p4[2] + p4[3]));
-            }
-            if (lane < CH_NB) zb[k0 + lane] = v;
-            wave_sync();
+            for (int t = 0; t < CH_NB; t++) s4[t & 3] += lv[t] * wq[t];
+            zb[i] -= (s4[0] + s4[1]) + (s4[2] + s4[3]);
+        }
+        __syncthreads();
+    };
+    double la[CH_NB], lb[CH_NB];
+    load_row(0, la);
+    for (int q = 0; q < np; q += 2) {
+        step(q, la, lb);
+        if (q + 1 < np) step(q + 1, lb, la);
+    }
+}
+
+// Back substitution L^T w = z with the factor in the lower triangle of A and
+// the stored diagonal-block inverses; z (LDS) is overwritten by w.  Panels in
+// reverse, right-looking: w_q = Iv_q^T z_q (wave 0), then the block row of L
+// left of the diagonal block takes w_q out of every earlier unknown,
+// z_c -= sum_t L(q0 + t, c) w_t (one thread per column c).  The block row
+// of the next panel is loaded during this panel's update, as in
+// forward_subst.  The inverses are read from P (staged there by
+// stage_inverses, or one per step).  wq (>= CH_NB doubles) is LDS scratch of
+// the caller.
+static_assert(CH_NMAX <= CH_THREADS, "one thread per unknown left of a panel");
+__device__ __forceinline__ void back_subst(int N, const double* __restrict__ A, const double* __restrict__ ILg,
+                           double* zb, double* P, bool staged, double* wq) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int np = (N + CH_NB - 1) / CH_NB;
+    // column tid of panel q's block row (zeros in rows beyond nk); a wave
+    // with no column left of the panel issues no loads
+    auto load_col = [&](int q, double* lv) {
+        const int q0 = q * CH_NB, nk = min(CH_NB, N - q0);
+        const bool need = wave * 64 < q0;
+        const double* col = A + (size_t)q0 * N + min(tid, max(q0 - 1, 0));
+#pragma unroll
+        for (int t = 0; t < CH_NB; t++) {
+            if (need && t < nk) lv[t] = col[(size_t)t * N];
+            else lv[t] = 0.0;
+        }
+    };
+    auto step = [&](int q, const double* lv, double* ln) {
+        const int q0 = q * CH_NB, nk = min(CH_NB, N - q0);
+        const double* iv = step_inverse(q, staged, ILg, P);
+        if (wave == 0) {
             double wv = 0.0;
             if (lane < CH_NB) {
-                double s4[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int i = 0; i < CH_NB; i++) s4[i & 3] += Iv[i * CH_PS + lane] * zb[k0 + i];
-                wv = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+                wv = iv_dot<true>(iv, zb + q0, lane);
+                wq[lane] = wv;
             }
             wave_sync();
-            if (lane < nk) zb[k0 + lane] = wv;
+            if (lane < nk) zb[q0 + lane] = wv;
         }
         __syncthreads();
+        if (q > 0) load_col(q - 1, ln);
+        if (tid < q0) {
+            double s4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int t = 0; t < CH_NB; t++) s4[t & 3] += lv[t] * wq[t];
+            zb[tid] -= (s4[0] + s4[1]) + (s4[2] + s4[3]);
+        }
+        __syncthreads();
+    };
+    double la[CH_NB], lb[CH_NB];
+    load_col(np - 1, la);
+    for (int q = np - 1; q >= 0; q -= 2) {
+        step(q, la, lb);
+        if (q - 1 >= 0) step(q - 1, lb, la);
     }
 }
 
@@ -715,7 +811,10 @@ __device__ __forceinline__ void cholesky_body(int N, double* __restrict__ A, con
         }
         __syncthreads();
     }
-    back_subst(N, A, ILg, zb, P, Iv, Dn);
+    {
+        const bool staged = stage_inverses(N, ILg, P);
+        back_subst(N, A, ILg, zb, P, staged, Dn);
+    }
     for (int i = tid; i < N; i += CH_THREADS) x[i] = Dq[i] * zb[i];
 }
 
@@ -761,31 +860,15 @@ __device__ __forceinline__ void resolve_body(int N, const double* __restrict__ A
     extern __shared__ double P[];
     __shared__ double zb[CH_NMAX + 32];
     __shared__ double Dq[CH_NMAX];
-    __shared__ double Iv[CH_NB * CH_PS];
-    __shared__ double part[CH_NB * (CH_THREADS / 32)];
-    const int tid = threadIdx.x, wave = tid >> 6;
+    __shared__ double wq[CH_NB];
+    const int tid = threadIdx.x;
     for (int i = tid; i < N + 32; i += CH_THREADS) {
         zb[i] = i < N ? Dg[i] * g[i] : 0.0;
         if (i < N) Dq[i] = Dg[i];
     }
-    // forward substitution L z = D g, panel by panel
-    for (int k0 = 0; k0 < N; k0 += CH_NB) {
-        const int nk = min(CH_NB, N - k0);
-        const int rows = N - k0;
-        load_panel(N, A, k0, nk, nk, rows, rows, P, nullptr);
-        load_inverse(ILg, k0 / CH_NB, Iv);
-        __syncthreads();
-        if (wave == 0) diag_forward(k0, nk, Iv, zb);
-        __syncthreads();
-        for (int i = nk + tid; i < rows; i += CH_THREADS) {
-            double s4[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int c = 0; c < CH_NB; c++) s4[c & 3] += P[i * CH_PS + c] * zb[k0 + c];
-            zb[k0 + i] -= (s4[0] + s4[1]) + (s4[2] + s4[3]);
-        }
-        __syncthreads();
-    }
-    back_subst(N, A, ILg, zb, P, Iv, part);
+    const bool staged = stage_inverses(N, ILg, P);    // (its barrier also orders zb)
+    forward_subst(N, A, ILg, zb, P, staged, wq);      // L z = D g
+    back_subst(N, A, ILg, zb, P, staged, wq);
     for (int i = tid; i < N; i += CH_THREADS) x[i] += Dq[i] * zb[i];
 }
 
