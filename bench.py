@@ -399,7 +399,9 @@ def main():
         def step(ev=None):
             f = ctx.fit_stamps(d["I1"], d["M1"], d["I2"], d["V2"], d["M2"], d["stamps"], out=bufs["fit"])
             if ev: ev[0].record()
-            s = ctx.solve(W, H, d["stamps"], f, out=bufs["sol"])
+            # the fit rewrites every stamp's flags, so the solve marks its
+            # rejections in them (no copy)
+            s = ctx.solve(W, H, d["stamps"], f, flags=f["flags"], out=bufs["sol"], flags_inplace=True)
             if ev: ev[1].record()
             ctx.convolve_pair(s["coeffs"], d["I1"], d["V1"], d["M1"], c_out=wl.cov_half,
                               stats=s["stats"], out=bufs["conv"], out_mask=bufs["conv_mask"],

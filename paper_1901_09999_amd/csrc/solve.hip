@@ -65,23 +65,6 @@ __device__ void solve_init_body(int n, int N, int ns, int S, int W, int H, int m
     }
 }
 
-__global__ void k_solve_init(int n, int N, int ns, int S, int W, int H, int min_stamps,
-                             const int32_t* __restrict__ xy, const int32_t* __restrict__ flags,
-                             uint8_t* __restrict__ used, uint8_t* __restrict__ fitted,
-                             double* __restrict__ G, double* __restrict__ chi2,
-                             double* __restrict__ coeffs, SolveState* st) {
-    solve_init_body(n, N, ns, S, W, H, min_stamps, xy, flags, used, fitted, G, chi2, coeffs, st,
-                    blockIdx.x);
-}
-
-// Batched forms: blockIdx.y is the pair (uneven pairs leave blocks idle).
-__global__ void k_solve_init_b(const PairDesc* __restrict__ pairs, int min_stamps) {
-    const PairDesc& p = pairs[blockIdx.y];
-    if ((int)blockIdx.x * (int)blockDim.x >= max(max(p.n, p.N), 1)) return;
-    solve_init_body(p.n, p.N, p.ns, p.S, p.W, p.H, min_stamps, p.xy, p.flags, p.used, p.fitted,
-                    p.G, p.chi2, p.coeffs, p.st, blockIdx.x);
-}
-
 // Stamp-major copy of the stamp sums: Mt[ij][k] = M_k[ij], bt[i][k] = b_k[i],
 // so that the assembly reads each (i, j) entry of all stamps contiguously.
 // Tiles of 32 stamps x 64 entries go through LDS, so that both the reads
@@ -119,16 +102,37 @@ __device__ void transpose_sums_body(int n, int L, const double* __restrict__ Ms,
     }
 }
 
-__global__ __launch_bounds__(256) void k_transpose_sums(int n, int L, const double* __restrict__ Ms,
-                                                        const double* __restrict__ bs,
-                                                        double* __restrict__ Mt,
-                                                        double* __restrict__ bt) {
-    transpose_sums_body(n, L, Ms, bs, Mt, bt, blockIdx.x, gridDim.x);
+// The two independent set-up steps of a solve in one launch: workgroups
+// below n_init initialise the state, the spatial terms and the stamp masks,
+// the others transpose the stamp sums.
+__global__ __launch_bounds__(256) void k_solve_prep(int n_init, int n, int N, int ns, int S, int W, int H,
+                                                    int min_stamps, int L,
+                                                    const int32_t* __restrict__ xy,
+                                                    const int32_t* __restrict__ flags,
+                                                    uint8_t* __restrict__ used, uint8_t* __restrict__ fitted,
+                                                    double* __restrict__ G, double* __restrict__ chi2,
+                                                    double* __restrict__ coeffs, SolveState* st,
+                                                    const double* __restrict__ Ms,
+                                                    const double* __restrict__ bs,
+                                                    double* __restrict__ Mt, double* __restrict__ bt) {
+    const int bid = blockIdx.x;
+    if (bid < n_init)
+        solve_init_body(n, N, ns, S, W, H, min_stamps, xy, flags, used, fitted, G, chi2, coeffs, st, bid);
+    else
+        transpose_sums_body(n, L, Ms, bs, Mt, bt, bid - n_init, gridDim.x - n_init);
 }
 
-__global__ __launch_bounds__(256) void k_transpose_sums_b(const PairDesc* __restrict__ pairs, int L) {
+__global__ __launch_bounds__(256) void k_solve_prep_b(const PairDesc* __restrict__ pairs, int n_init,
+                                                      int min_stamps, int L) {
     const PairDesc& p = pairs[blockIdx.y];
-    transpose_sums_body(p.n, L, p.Ms, p.bs, p.Mt, p.bt, blockIdx.x, gridDim.x);
+    const int bid = blockIdx.x;
+    if (bid < n_init) {
+        if (bid * (int)blockDim.x >= max(max(p.n, p.N), 1)) return;
+        solve_init_body(p.n, p.N, p.ns, p.S, p.W, p.H, min_stamps, p.xy, p.flags, p.used, p.fitted,
+                        p.G, p.chi2, p.coeffs, p.st, bid);
+    } else {
+        transpose_sums_body(p.n, L, p.Ms, p.bs, p.Mt, p.bt, bid - n_init, gridDim.x - n_init);
+    }
 }
 
 // One item per (i, j, s) of the per-stamp index space, 8 items per
@@ -137,7 +141,9 @@ __global__ __launch_bounds__(256) void k_transpose_sums_b(const PairDesc* __rest
 // partial sums are added by shuffles in a fixed order.
 constexpr int ASM_ITEMS = 8, ASM_CHUNKS = 32;
 
-template <int NS>
+// R: stamps per batch of loads.  R > 1 shortens a latency-bound assembly
+// (one pair); the batch, bound by throughput, keeps R = 1 for occupancy.
+template <int NS, int R>
 __device__ void assemble_body(int n, int nb, int N, const double* __restrict__ Mt,
                               const double* __restrict__ bt, const double* __restrict__ G,
                               const uint8_t* __restrict__ used, double* __restrict__ M,
@@ -164,16 +170,33 @@ __device__ void assemble_body(int n, int nb, int N, const double* __restrict__ M
         kind = (i == nb && s != 0) ? 0 : 2;
     }
     if (kind == 1) {
+        // the stamp sums, masks and g_s of R of the lane's stamps are loaded
+        // together (the stamp sums come from L2 or HBM; the spatial terms,
+        // read in the sum, are a few KB that stay in L1); summed in stamp order
         const double* mrow = Mt + (size_t)ij * n;
-        for (int k = chunk; k < n; k += ASM_CHUNKS) {
-            const double* g = G + (size_t)k * NS;            // spatial terms of stamp k
-            const double u = used[k] ? 1.0 : 0.0;
-            const double gm = ((i == nb) ? u : u * g[s]) * mrow[k];
-            if (j == nb) {
-                acc[0] += gm;
-            } else {
+        for (int k0 = chunk; k0 < n; k0 += R * ASM_CHUNKS) {
+            double gs[R], mv[R];
+            uint8_t uv[R];
 #pragma unroll
-                for (int q = 0; q < NS; q++) acc[q] += g[q] * gm;
+            for (int r = 0; r < R; r++) {
+                const int k = min(k0 + r * ASM_CHUNKS, n - 1);
+                gs[r] = G[(size_t)k * NS + s];
+                uv[r] = used[k];
+                mv[r] = mrow[k];
+            }
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                const int k = k0 + r * ASM_CHUNKS;
+                if (k >= n) break;
+                const double u = uv[r] ? 1.0 : 0.0;
+                const double gm = ((i == nb) ? u : u * gs[r]) * mv[r];
+                if (j == nb) {
+                    acc[0] += gm;
+                } else {
+                    const double* g = G + (size_t)k * NS;    // spatial terms of stamp k
+#pragma unroll
+                    for (int q = 0; q < NS; q++) acc[q] += g[q] * gm;
+                }
             }
         }
     } else if (kind == 2) {
@@ -213,7 +236,7 @@ __global__ __launch_bounds__(256) void k_assemble(int n, int nb, int N, const do
                                                   const double* __restrict__ G, const uint8_t* __restrict__ used,
                                                   double* __restrict__ M, double* __restrict__ b,
                                                   const SolveState* st) {
-    assemble_body<NS>(n, nb, N, Mt, bt, G, used, M, b, st, blockIdx.x);
+    assemble_body<NS, (NS <= 6 ? 4 : NS <= 10 ? 2 : 1)>(n, nb, N, Mt, bt, G, used, M, b, st, blockIdx.x);
 }
 
 // Batched: only the pairs with NS spatial terms take part in this launch.
@@ -222,7 +245,7 @@ __global__ __launch_bounds__(256) void k_assemble_b(const PairDesc* __restrict__
     const PairDesc& p = pairs[blockIdx.y];
     const int L = nb + 1;
     if (p.ns != NS || (int)blockIdx.x * ASM_ITEMS >= L * L * NS + L * NS) return;
-    assemble_body<NS>(p.n, nb, p.N, p.Mt, p.bt, p.G, p.used, p.A, p.b, p.st, blockIdx.x);
+    assemble_body<NS, 1>(p.n, nb, p.N, p.Mt, p.bt, p.G, p.used, p.A, p.b, p.st, blockIdx.x);
 }
 
 
@@ -1660,9 +1683,9 @@ int batch_solve(const psfm_context* ctx, const PairDesc* pairs, const int* stamp
     int rc = solve_lds_grant(lds);
     if (rc) return rc;
     const int nt = std::max(std::max(max_n, max_N), 1);
-    hipLaunchKernelGGL(k_solve_init_b, dim3((nt + 255) / 256, n_pairs), dim3(256), 0, st, pairs,
-                       cf.min_stamps);
-    hipLaunchKernelGGL(k_transpose_sums_b, dim3(256, n_pairs), dim3(256), 0, st, pairs, L);
+    const int n_init = (nt + 255) / 256;
+    hipLaunchKernelGGL(k_solve_prep_b, dim3(n_init + 256, n_pairs), dim3(256), 0, st, pairs, n_init,
+                       cf.min_stamps, L);
     PSFM_HIP_CHECK(hipGetLastError());
     for (int it = 0; it < cf.max_iter; it++) {
 #define PSFM_ASM_B(NSV)                                                                          \
@@ -1731,16 +1754,13 @@ static int solve_impl(const psfm_context* ctx, int W, int H, const int32_t* stam
     int rc = psfm::solve_lds_grant(lds);
     if (rc) return rc;
     const int nt = std::max(n_stamps, N);
-    hipLaunchKernelGGL(k_solve_init, dim3((nt + 255) / 256), dim3(256), 0, st, n_stamps, N, ns,
-                       cf.spatial_order, W, H, cf.min_stamps, stamp_xy, stamp_flags, used, fitted,
-                       G, stamp_chi2, coeffs, state);
+    const int n_init = (nt + 255) / 256;
+    const int tiles = n_stamps > 0 ? (n_stamps + TS_K - 1) / TS_K * ((L * L + L + TS_R - 1) / TS_R) : 0;
+    hipLaunchKernelGGL(k_solve_prep, dim3(n_init + std::min(tiles, 1024)), dim3(256), 0, st, n_init,
+                       n_stamps, N, ns, cf.spatial_order, W, H, cf.min_stamps, L, stamp_xy, stamp_flags,
+                       used, fitted, G, stamp_chi2, coeffs, state, stamp_M, stamp_b, Mt, bt);
     PSFM_HIP_CHECK(hipGetLastError());
     const int nthreads_asm = L * L * ns + L * ns;
-    if (n_stamps > 0) {
-        const int tiles = (n_stamps + TS_K - 1) / TS_K * ((L * L + L + TS_R - 1) / TS_R);
-        hipLaunchKernelGGL(k_transpose_sums, dim3(std::min(tiles, 1024)), dim3(256), 0, st, n_stamps, L,
-                           stamp_M, stamp_b, Mt, bt);
-    }
     if (prior && n_stamps > 0) {
         // completed predictions, then (warm start -> kernel-sum clip) rounds
         hipLaunchKernelGGL(k_prior_chi2, dim3(n_stamps), dim3(64), 0, st, nb, stamp_M, stamp_b, stamp_e,
