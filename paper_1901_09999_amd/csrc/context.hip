@@ -24,7 +24,7 @@ int check_hip(hipError_t e) {
     return PSFM_ERR_HIP;
 }
 
-int fit_bands(const psfm_context* ctx) { return (2 * ctx->r + 1 + PSFM_FIT_BR - 1) / PSFM_FIT_BR; }
+int fit_bands(const psfm_context* ctx) { return (2 * ctx->r + 1 + ctx->fit_br - 1) / ctx->fit_br; }
 
 int n_patches(const psfm_context* ctx, int W, int H) {
     const int P = ctx->cfg.patch;
@@ -92,6 +92,10 @@ int psfm_create(const psfm_config* cfg, psfm_context** out) {
     ctx->L = nb + 1;
     ctx->h = c.half_width;
     ctx->r = c.stamp_half;
+    // fit band: 9 rows up to 41-row stamps (r <= 20: two workgroups' LDS per CU and
+    // short bands, e.g. 9+9+9+9+5 rows at r = 20), 11 rows beyond (fewer bands
+    // per stamp when the stamps are many and large: 11+11+11+11+5 at r = 24)
+    ctx->fit_br = c.stamp_half <= 20 ? PSFM_FIT_BR_SMALL : PSFM_FIT_BR_LARGE;
     ctx->KW = 2 * c.half_width + 1;
     ctx->T = ctx->KW * ctx->KW;
     const int h = ctx->h, KW = ctx->KW, T = ctx->T;

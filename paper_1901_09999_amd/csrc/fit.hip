@@ -1,6 +1,7 @@
 // Per-stamp normal equations (Section 2, Eqs. 3-6 with c = 0, p = 0).
 //
-// One workgroup handles one band of PSFM_FIT_BR rows of one stamp:
+// One workgroup handles one band of BR rows of one stamp (BR a template
+// constant; the context picks 9 or 11 by stamp size):
 //   1. the band's input window of I1 (band rows + 2h halo rows, stamp width
 //      + 2h columns) is read from HBM into LDS, masked/non-finite pixels
 //      become zeros and raise the stamp flags (validity, Section 3.3);
@@ -47,7 +48,6 @@ __device__ __forceinline__ floatx4 mfma16(u16x8 a, u16x8 b, floatx4 c) {
                                                        __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
-constexpr int BR = PSFM_FIT_BR;
 constexpr int SEG = 12;          // stamp pixels per row-pass item
 constexpr int AT_STRIDE = 80;    // LDS row stride of the weighted block (bank spread)
 constexpr int GC = PSFM_GRAM_COLS;
@@ -57,7 +57,7 @@ struct FitLds {
     int win, col, R, At, sw, dt, psi, z, fac, rf, cf, total;  // float offsets
 };
 
-__host__ __device__ inline FitLds fit_lds_layout(int h, int r, int nb, int nf) {
+__host__ __device__ inline FitLds fit_lds_layout(int h, int r, int nb, int nf, int BR) {
     const int WC = 2 * r + 1 + 2 * h;
     const int npad = (2 * r + 1 + 3) / 4 * 4;
     FitLds L;
@@ -100,8 +100,8 @@ struct FitArgs {
     float* design;     // 16-bit modes: [stamp][nb + 2][(2r+1)^2] FP32 block, column-major
 };
 
-// One band of one stamp (item = stamp * nbands + band).
-template <int H_, int PREC>
+// One band of BR rows of one stamp (item = stamp * nbands + band).
+template <int H_, int PREC, int BR>
 __device__ void fit_band_body(const FitArgs& a, const int item, float* __restrict__ lds) {
     const float* __restrict__ I1 = a.I1;
     const uint8_t* __restrict__ M1 = a.M1;
@@ -131,7 +131,7 @@ __device__ void fit_band_body(const FitArgs& a, const int item, float* __restric
     const int NPX = 2 * r + 1;
     const int WC = NPX + 2 * H_;
     const int npad = (NPX + 3) / 4 * 4;
-    const FitLds Lo = fit_lds_layout(H_, r, nb, nf);
+    const FitLds Lo = fit_lds_layout(H_, r, nb, nf, BR);
     float* win = lds + Lo.win;
     float* colb = lds + Lo.col;
     float* Rb = lds + Lo.R;
@@ -414,15 +414,15 @@ __device__ void fit_band_body(const FitArgs& a, const int item, float* __restric
     if (tid == 0) band_flags[item] = 0;
 }
 
-template <int H_, int PREC>
+template <int H_, int PREC, int BR>
 __global__ __launch_bounds__(256) void k_fit_band(FitArgs a) {
     extern __shared__ float lds[];
-    fit_band_body<H_, PREC>(a, blockIdx.x, lds);
+    fit_band_body<H_, PREC, BR>(a, blockIdx.x, lds);
 }
 
 // All bands of all stamps of all pairs of a batch; item_pair maps the
 // flattened band index to its pair.
-template <int H_>
+template <int H_, int BR>
 __global__ __launch_bounds__(256) void k_fit_band_b(const PairDesc* __restrict__ pairs,
                                                     const int* __restrict__ item_pair, FitArgs base) {
     extern __shared__ float lds[];
@@ -439,7 +439,7 @@ __global__ __launch_bounds__(256) void k_fit_band_b(const PairDesc* __restrict__
     a.xy = pd.xy;
     a.part = pd.part;
     a.band_flags = pd.bflags;
-    fit_band_body<H_, PSFM_PREC_FP32>(a, blockIdx.x - pd.band_off, lds);
+    fit_band_body<H_, PSFM_PREC_FP32, BR>(a, blockIdx.x - pd.band_off, lds);
 }
 
 // Sum of the band partials of each stamp in FP64 and scatter to M_s, b_s, e_s.
@@ -528,41 +528,58 @@ FitArgs base_fit_args(const psfm_context* ctx) {
     return a;
 }
 
-template <int H_>
+template <int H_, int BR>
 int set_fit_lds(size_t lds) {
     static size_t granted = 0;      // dynamic LDS granted so far (all forms)
     if (lds > granted) {
-        PSFM_HIP_CHECK(hipFuncSetAttribute((const void*)k_fit_band<H_, PSFM_PREC_FP32>,
+        PSFM_HIP_CHECK(hipFuncSetAttribute((const void*)k_fit_band<H_, PSFM_PREC_FP32, BR>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        PSFM_HIP_CHECK(hipFuncSetAttribute((const void*)k_fit_band<H_, PSFM_PREC_FP16>,
+        PSFM_HIP_CHECK(hipFuncSetAttribute((const void*)k_fit_band<H_, PSFM_PREC_FP16, BR>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        PSFM_HIP_CHECK(hipFuncSetAttribute((const void*)k_fit_band<H_, PSFM_PREC_BF16>,
+        PSFM_HIP_CHECK(hipFuncSetAttribute((const void*)k_fit_band<H_, PSFM_PREC_BF16, BR>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        PSFM_HIP_CHECK(hipFuncSetAttribute((const void*)k_fit_band_b<H_>,
+        PSFM_HIP_CHECK(hipFuncSetAttribute((const void*)k_fit_band_b<H_, BR>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         granted = lds;
     }
     return PSFM_OK;
 }
 
+// The band height is a compile-time constant of the kernels (the column
+// pass keeps one accumulator per band row in registers); the context picks
+// one of the instantiated heights.
 template <int H_>
-int launch_fit(const psfm_context* ctx, const FitArgs& a, int n_items, const PairDesc* pairs,
-               const int* item_pair, hipStream_t st) {
-    const FitLds Lo = fit_lds_layout(H_, ctx->r, ctx->nb, ctx->nf);
+int set_fit_lds_ctx(const psfm_context* ctx, size_t lds) {
+    return ctx->fit_br == PSFM_FIT_BR_SMALL ? set_fit_lds<H_, PSFM_FIT_BR_SMALL>(lds)
+                                            : set_fit_lds<H_, PSFM_FIT_BR_LARGE>(lds);
+}
+
+template <int H_, int BR>
+int launch_fit_br(const psfm_context* ctx, const FitArgs& a, int n_items, const PairDesc* pairs,
+                  const int* item_pair, hipStream_t st) {
+    const FitLds Lo = fit_lds_layout(H_, ctx->r, ctx->nb, ctx->nf, BR);
     const size_t lds = (size_t)Lo.total * sizeof(float);
-    int rc = set_fit_lds<H_>(lds);
+    int rc = set_fit_lds<H_, BR>(lds);
     if (rc) return rc;
     const int prec = ctx->cfg.precision;
     if (pairs)
-        hipLaunchKernelGGL(k_fit_band_b<H_>, dim3(n_items), dim3(256), lds, st, pairs, item_pair, a);
+        hipLaunchKernelGGL((k_fit_band_b<H_, BR>), dim3(n_items), dim3(256), lds, st, pairs, item_pair, a);
     else if (prec == PSFM_PREC_FP16)
-        hipLaunchKernelGGL((k_fit_band<H_, PSFM_PREC_FP16>), dim3(n_items), dim3(256), lds, st, a);
+        hipLaunchKernelGGL((k_fit_band<H_, PSFM_PREC_FP16, BR>), dim3(n_items), dim3(256), lds, st, a);
     else if (prec == PSFM_PREC_BF16)
-        hipLaunchKernelGGL((k_fit_band<H_, PSFM_PREC_BF16>), dim3(n_items), dim3(256), lds, st, a);
+        hipLaunchKernelGGL((k_fit_band<H_, PSFM_PREC_BF16, BR>), dim3(n_items), dim3(256), lds, st, a);
     else
-        hipLaunchKernelGGL((k_fit_band<H_, PSFM_PREC_FP32>), dim3(n_items), dim3(256), lds, st, a);
+        hipLaunchKernelGGL((k_fit_band<H_, PSFM_PREC_FP32, BR>), dim3(n_items), dim3(256), lds, st, a);
     PSFM_HIP_CHECK(hipGetLastError());
     return PSFM_OK;
+}
+
+template <int H_>
+int launch_fit(const psfm_context* ctx, const FitArgs& a, int n_items, const PairDesc* pairs,
+               const int* item_pair, hipStream_t st) {
+    return ctx->fit_br == PSFM_FIT_BR_SMALL
+               ? launch_fit_br<H_, PSFM_FIT_BR_SMALL>(ctx, a, n_items, pairs, item_pair, st)
+               : launch_fit_br<H_, PSFM_FIT_BR_LARGE>(ctx, a, n_items, pairs, item_pair, st);
 }
 
 int dispatch_fit(const psfm_context* ctx, const FitArgs& a, int n_items, const PairDesc* pairs,
@@ -584,7 +601,7 @@ int dispatch_fit(const psfm_context* ctx, const FitArgs& a, int n_items, const P
 namespace psfm {
 
 size_t fit_lds_bytes(const psfm_context* ctx) {
-    return (size_t)fit_lds_layout(ctx->h, ctx->r, ctx->nb, ctx->nf).total * sizeof(float);
+    return (size_t)fit_lds_layout(ctx->h, ctx->r, ctx->nb, ctx->nf, ctx->fit_br).total * sizeof(float);
 }
 
 // Grants the fit kernels their dynamic LDS (done ahead of a graph capture).
@@ -592,7 +609,7 @@ int fit_prepare(const psfm_context* ctx) {
     const size_t lds = fit_lds_bytes(ctx);
     switch (ctx->h) {
 #define PSFM_FIT_PREP(HH) \
-    case HH: return set_fit_lds<HH>(lds);
+    case HH: return set_fit_lds_ctx<HH>(ctx, lds);
         PSFM_FIT_PREP(1) PSFM_FIT_PREP(2) PSFM_FIT_PREP(3) PSFM_FIT_PREP(4) PSFM_FIT_PREP(5)
         PSFM_FIT_PREP(6) PSFM_FIT_PREP(7) PSFM_FIT_PREP(8) PSFM_FIT_PREP(9) PSFM_FIT_PREP(10)
         PSFM_FIT_PREP(11) PSFM_FIT_PREP(12) PSFM_FIT_PREP(13) PSFM_FIT_PREP(14) PSFM_FIT_PREP(15)
