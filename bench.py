@@ -4,8 +4,10 @@ One step = one whole pass of the path over synthetic input already resident
 in HBM.
 
 Default workload (one pair):
-    psfm_fit_stamps -> psfm_solve (with rejection) -> psfm_convolve_pair
-    (psfm_convolve_image + psfm_propagate_variance in one call) -> psfm_subtract
+    psfm_fit_stamps -> psfm_solve (with rejection) -> psfm_match_pair
+    (psfm_convolve_image + psfm_propagate_variance + psfm_subtract in one pass
+    over the output tiles; the difference image, its variance, mask and
+    covariance pseudo-matrix are the products)
 on a 2048 x 2048 FP32 pair, science PSF sigma 1.4 -> 2.6 px across the field
 with ellipticity up to 0.2, 2000 sources, 10% mask, 21 x 21 kernel with the
 49-term ISIS basis x spatial order 2 (295 unknowns), 100 stamps of 41 x 41,
@@ -403,13 +405,11 @@ def main():
             # rejections in them (no copy)
             s = ctx.solve(W, H, d["stamps"], f, flags=f["flags"], out=bufs["sol"], flags_inplace=True)
             if ev: ev[1].record()
-            ctx.convolve_pair(s["coeffs"], d["I1"], d["V1"], d["M1"], c_out=wl.cov_half,
-                              stats=s["stats"], out=bufs["conv"], out_mask=bufs["conv_mask"],
-                              var_out=bufs["var"], cov_out=bufs["cov"])
+            # convolutions of I1 and V1 and the difference in one pass over the
+            # tiles (the convolved planes are not stored: the difference is the product)
+            ctx.match(s["coeffs"], d["I1"], d["V1"], d["M1"], d["I2"], d["V2"], d["M2"],
+                      c_out=wl.cov_half, stats=s["stats"], out=bufs["sub"], cov_conv=bufs["cov"])
             if ev: ev[2].record()
-            ctx.subtract(s["coeffs"], d["I2"], d["V2"], d["M2"], bufs["conv"], bufs["var"],
-                         bufs["conv_mask"], bufs["cov"], out=bufs["sub"])
-            if ev: ev[3].record()
 
         for _ in range(warmup):
             step()
@@ -426,7 +426,7 @@ def main():
         wall = time.perf_counter() - t0
         gpu_ms = float(start.elapsed_time(stop)) / steps
         # stage split: the same number of steps again, with an event after each stage
-        NS = 4      # stages: fit, solve, convolve (image + variance + pseudo-matrix), subtract
+        NS = 3      # stages: fit, solve, apply (convolutions, pseudo-matrices, difference)
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(NS)] for _ in range(steps)]
         start.record()
         for k in range(steps):
@@ -474,7 +474,7 @@ def main():
                      avg_launch_us=round(conv_us, 2), algorithmic_flops_per_launch=flops,
                      launches_per_step=0,
                      note="timed in launches of its own; the step forms the image and variance "
-                          "planes in one fused tile kernel (k_conv_pair_tile)")
+                          "planes and the difference in one fused tile kernel (k_match_tile)")
     Nu = wl.n_unknowns
     g = torch.Generator(device="cuda")
     g.manual_seed(5)
@@ -530,7 +530,7 @@ def main():
                    "width": W, "height": H, "n_stamps": n, "unknowns": wl.n_unknowns,
                    "parallelism": "single GPU"},
         "stages_ms": {k: round(float(v), 4) for k, v in
-                      zip(["fit", "solve", "convolve+variance", "subtract"], stage)},
+                      zip(["fit", "solve", "apply"], stage)},
         "gpu_ms_per_step": round(gpu_ms, 4),
         "fit": {"chi2_dof": stats["chi2_dof"], "kernel_sum_centre": stats["kernel_sum_centre"],
                 "n_used": stats["n_used"], "n_iter": stats["n_iter"]},
@@ -543,7 +543,7 @@ def main():
                           "value": round(W * H / 1e6 / (o["ms_per_step"] * 1e-3), 2),
                           "ms_per_step": round(o["ms_per_step"], 4),
                           "stages_ms": {k: round(float(v), 4) for k, v in
-                                        zip(["fit", "solve", "convolve+variance", "subtract"],
+                                        zip(["fit", "solve", "apply"],
                                             o["stage"])},
                           "fit": {"chi2_dof": o["stats"]["chi2_dof"],
                                   "kernel_sum_centre": o["stats"]["kernel_sum_centre"],

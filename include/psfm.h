@@ -331,6 +331,29 @@ int psfm_subtract(const psfm_context* ctx, const double* coeffs, const float* I2
                   void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * psfm_convolve_pair and psfm_subtract of one pair in one pass (Section 4.2,
+ * Eqs. 12-13; Sections 3.4, 3.5, 4.3): every output tile realises its patch
+ * kernel once, forms I' and V' in registers and writes the difference image
+ * (diff, diff_var, diff_mask as psfm_subtract defines them, bit-identical to
+ * that call) without storing and reading back the convolved planes.
+ * I1, V1 share the mask M1; all planes share W, H and pitch.  conv and
+ * conv_mask (both or neither) and conv_var are optional (NULL: not written).
+ * cov1 / cov1_half are psfm_propagate_variance's cov_in, cov_conv its
+ * cov_out (always written: C_D needs it), cov2 / cov_diff as in
+ * psfm_subtract; the variance means of C_D are summed per 64 x 64 tile
+ * (equal to psfm_subtract's up to summation order).  Workspace:
+ * psfm_workspace_bytes().  Errors as the two calls.
+ */
+int psfm_match_pair(const psfm_context* ctx, const double* coeffs, const float* I1,
+                    const float* V1, const uint8_t* M1, const float* I2, const float* V2,
+                    const uint8_t* M2, int W, int H, int64_t pitch, const double* cov1,
+                    int cov1_half, const double* cov2, int cov2_half, float* conv,
+                    uint8_t* conv_mask, float* conv_var, double* cov_conv, int cov_conv_half,
+                    float* diff, float* diff_var, uint8_t* diff_mask, double* cov_diff,
+                    int cov_diff_half, psfm_fit_stats* stats, void* ws, size_t ws_bytes,
+                    void* stream);
+
+/*
  * Batched matching of many independent image pairs: the whole path of the
  * calls above (fit, solve with rejection, image and variance convolution,
  * covariance pseudo-matrix, difference) for every pair of a batch, with each

@@ -252,10 +252,12 @@ size_t psfm_workspace_bytes(const psfm_context* ctx, int W, int H, int n_stamps)
     size_t s = psfm::solve_workspace(ctx, n_stamps);
     size_t c = psfm::conv_workspace(ctx, W, H);
     size_t d = psfm::subtract_workspace(ctx, W, H);
+    size_t e = psfm::match_workspace(ctx, W, H);
     size_t m = b;
     if (s > m) m = s;
     if (c > m) m = c;
     if (d > m) m = d;
+    if (e > m) m = e;
     return psfm::align_up(m, 256) + 256;
 }
 

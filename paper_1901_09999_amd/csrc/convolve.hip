@@ -750,12 +750,122 @@ __global__ __launch_bounds__(256) void k_subtract_cov(const double* __restrict__
     cov_diff_body(partials, nblk, cov2, c2, covc, cc, covd, cd);
 }
 
-// Fused apply for every pair of a batch: per 64 x 64 tile (flattened over
-// all pairs, pair after pair, visited by a grid-stride loop) the patch
-// kernel is realised once; I' = K (x) I1 with its BAD/POOR mask, then
-// D = I2 - I' - d0; V' = f K^2 (x) V1, then V_D = V2 + V'.  The tile's
-// variance sums go to the pair's partials; the workgroup that finishes a
-// pair's last tile forms that pair's C_D and stamps its completion time.
+// One 64 x 64 tile t of a pair of the fused apply: the patch kernel is
+// realised once; I' = K (x) I1 with its BAD/POOR mask, then D = I2 - I' - d0;
+// V' = f K^2 (x) V1, then V_D = V2 + V' (I' and V' are stored only where the
+// pair asks for them).  The tile's variance sums (sum V2, n2, sum V', n') go
+// to p.sub_part[4 t].  All threads of the workgroup call it.
+template <int H_>
+__device__ __forceinline__ void match_tile(const PairDesc& p, const int t, const BasisArgs& B0, int P,
+                                           double bad_frac, float* halo, float* tapsK, float* tapsV,
+                                           uint32_t (*badw)[(TILE + 2 * H_ + 31) / 32 + 1],
+                                           double* ring, double* red, int* s_rb, double* s_f) {
+    const int tid = threadIdx.x;
+    const int lx = tid & 63;
+    const int r0 = (tid >> 6) * 16;
+    const int W = p.W, H = p.H;
+    const int64_t pitch = p.pitch;
+    const PatchGeom g = patch_geom(W, H, P);
+    const int tx = t % p.ntx, ty = t / p.ntx;
+    const int px = tx / g.tpp, sx = tx % g.tpp;
+    const int py = ty / g.tpp, sy = ty % g.tpp;
+    const int X0 = px * P + sx * TILE, Y0 = py * P + sy * TILE;
+    const int X1 = min(min(X0 + TILE, (px + 1) * P), W);
+    const int Y1 = min(min(Y0 + TILE, (py + 1) * P), H);
+    double s2 = 0.0, n2 = 0.0, sc = 0.0, nc = 0.0;
+    if (X0 < X1 && Y0 < Y1) {
+        BasisArgs B = B0;
+        B.ns = p.ns;
+        B.S = p.S;
+        patch_taps<H_>(B, p.coeffs, W, H, P, px, py, bad_frac, p.cov1, p.cov1_half, halo, tapsK,
+                       tapsV, ring, red, s_rb, s_f);
+        const int anybad = load_halo<H_, true>(p.I1, p.M1, W, H, pitch, X0, Y0, halo, badw);
+        float acc[16];
+        conv16<H_>(halo, tapsK, lx, r0, acc);
+        uint32_t bad16 = 0, poor16 = 0;
+        if (anybad) mask16<H_>(badw, *s_rb, lx, r0, &bad16, &poor16);
+        const double d0 = p.coeffs[p.N - 1];
+        const int gx = X0 + lx;
+        // the target image's mask, values and variance of the 16 outputs,
+        // loaded together (clamped addresses outside the tile)
+        uint8_t m2v[16];
+        float i2v[16], v2v[16];
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+            const int gy = Y0 + r0 + j;
+            const int64_t o = (gx < X1 && gy < Y1) ? (int64_t)gy * pitch + gx : 0;
+            m2v[j] = p.M2[o];
+            i2v[j] = p.I2[o];
+            v2v[j] = p.V2[o];
+        }
+        uint32_t m2bits = 0;
+        if (gx < X1) {
+#pragma unroll
+            for (int j = 0; j < 16; j++) {
+                const int gy = Y0 + r0 + j;
+                if (gy < Y1) {
+                    const int64_t o = (int64_t)gy * pitch + gx;
+                    const uint8_t cm = ((bad16 >> j) & 1u) ? PSFM_MASK_CONV_BAD
+                                       : ((poor16 >> j) & 1u) ? PSFM_MASK_CONV_POOR : 0;
+                    if (p.conv) {
+                        p.conv[o] = acc[j];
+                        p.conv_mask[o] = cm;
+                    }
+                    if (m2v[j]) {
+                        m2bits |= 1u << j;
+                        p.diff[o] = 0.0f;
+                        p.diff_mask[o] = (uint8_t)(PSFM_MASK_BAD | cm);
+                    } else {
+                        p.diff[o] = (float)((double)i2v[j] - (double)acc[j] - d0);
+                        p.diff_mask[o] = cm;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        load_halo<H_, false>(p.V1, p.M1, W, H, pitch, X0, Y0, halo, badw);
+        conv16<H_>(halo, tapsV, lx, r0, acc);
+        if (gx < X1) {
+#pragma unroll
+            for (int j = 0; j < 16; j++) {
+                const int gy = Y0 + r0 + j;
+                if (gy < Y1) {
+                    const int64_t o = (int64_t)gy * pitch + gx;
+                    const float cv = acc[j];
+                    if (p.var) p.var[o] = cv;
+                    if ((m2bits >> j) & 1u) {
+                        p.diff_var[o] = 0.0f;
+                    } else {
+                        const float v2 = v2v[j];
+                        p.diff_var[o] = (float)((double)v2 + (double)cv);
+                        s2 += v2;
+                        n2 += 1.0;
+                    }
+                    if (!((bad16 | poor16) >> j & 1u)) {
+                        sc += cv;
+                        nc += 1.0;
+                    }
+                }
+            }
+        }
+    }
+    s2 = psfm_block_sum(s2, red);
+    n2 = psfm_block_sum(n2, red);
+    sc = psfm_block_sum(sc, red);
+    nc = psfm_block_sum(nc, red);
+    if (tid == 0) {
+        double* q = p.sub_part + 4 * (size_t)t;
+        q[0] = s2;
+        q[1] = n2;
+        q[2] = sc;
+        q[3] = nc;
+    }
+}
+
+// Fused apply for every pair of a batch: the tiles of all pairs (flattened,
+// pair after pair, visited by a grid-stride loop) go through match_tile; the
+// workgroup that finishes a pair's last tile forms that pair's C_D and
+// stamps its completion time.
 template <int H_>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_match_tiles_b(const PairDesc* __restrict__ pairs,
                                                        const int* __restrict__ tile_pair,
@@ -777,107 +887,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     __shared__ double s_f;
     __shared__ int s_last;
     const int tid = threadIdx.x;
-    const int lx = tid & 63;
-    const int r0 = (tid >> 6) * 16;
     for (int item = blockIdx.x; item < n_tiles; item += gridDim.x) {
         const PairDesc& p = pairs[tile_pair[item]];
-        const int W = p.W, H = p.H;
-        const int64_t pitch = p.pitch;
         const int t = item - p.tile_off;
-        const PatchGeom g = patch_geom(W, H, P);
-        const int tx = t % p.ntx, ty = t / p.ntx;
-        const int px = tx / g.tpp, sx = tx % g.tpp;
-        const int py = ty / g.tpp, sy = ty % g.tpp;
-        const int X0 = px * P + sx * TILE, Y0 = py * P + sy * TILE;
-        const int X1 = min(min(X0 + TILE, (px + 1) * P), W);
-        const int Y1 = min(min(Y0 + TILE, (py + 1) * P), H);
-        double s2 = 0.0, n2 = 0.0, sc = 0.0, nc = 0.0;
-        if (X0 < X1 && Y0 < Y1) {
-            BasisArgs B = B0;
-            B.ns = p.ns;
-            B.S = p.S;
-            patch_taps<H_>(B, p.coeffs, W, H, P, px, py, bad_frac, p.cov1, p.cov1_half, halo, tapsK,
-                           tapsV, ring, red, &s_rb, &s_f);
-            const int anybad = load_halo<H_, true>(p.I1, p.M1, W, H, pitch, X0, Y0, halo, badw);
-            float acc[16];
-            conv16<H_>(halo, tapsK, lx, r0, acc);
-            uint32_t bad16 = 0, poor16 = 0;
-            if (anybad) mask16<H_>(badw, s_rb, lx, r0, &bad16, &poor16);
-            const double d0 = p.coeffs[p.N - 1];
-            const int gx = X0 + lx;
-            // the target image's mask, values and variance of the 16 outputs,
-            // loaded together (clamped addresses outside the tile)
-            uint8_t m2v[16];
-            float i2v[16], v2v[16];
-#pragma unroll
-            for (int j = 0; j < 16; j++) {
-                const int gy = Y0 + r0 + j;
-                const int64_t o = (gx < X1 && gy < Y1) ? (int64_t)gy * pitch + gx : 0;
-                m2v[j] = p.M2[o];
-                i2v[j] = p.I2[o];
-                v2v[j] = p.V2[o];
-            }
-            uint32_t m2bits = 0;
-            if (gx < X1) {
-#pragma unroll
-                for (int j = 0; j < 16; j++) {
-                    const int gy = Y0 + r0 + j;
-                    if (gy < Y1) {
-                        const int64_t o = (int64_t)gy * pitch + gx;
-                        const uint8_t cm = ((bad16 >> j) & 1u) ? PSFM_MASK_CONV_BAD
-                                           : ((poor16 >> j) & 1u) ? PSFM_MASK_CONV_POOR : 0;
-                        if (p.conv) {
-                            p.conv[o] = acc[j];
-                            p.conv_mask[o] = cm;
-                        }
-                        if (m2v[j]) {
-                            m2bits |= 1u << j;
-                            p.diff[o] = 0.0f;
-                            p.diff_mask[o] = (uint8_t)(PSFM_MASK_BAD | cm);
-                        } else {
-                            p.diff[o] = (float)((double)i2v[j] - (double)acc[j] - d0);
-                            p.diff_mask[o] = cm;
-                        }
-                    }
-                }
-            }
-            __syncthreads();
-            load_halo<H_, false>(p.V1, p.M1, W, H, pitch, X0, Y0, halo, badw);
-            conv16<H_>(halo, tapsV, lx, r0, acc);
-            if (gx < X1) {
-#pragma unroll
-                for (int j = 0; j < 16; j++) {
-                    const int gy = Y0 + r0 + j;
-                    if (gy < Y1) {
-                        const int64_t o = (int64_t)gy * pitch + gx;
-                        const float cv = acc[j];
-                        if (p.var) p.var[o] = cv;
-                        if ((m2bits >> j) & 1u) {
-                            p.diff_var[o] = 0.0f;
-                        } else {
-                            const float v2 = v2v[j];
-                            p.diff_var[o] = (float)((double)v2 + (double)cv);
-                            s2 += v2;
-                            n2 += 1.0;
-                        }
-                        if (!((bad16 | poor16) >> j & 1u)) {
-                            sc += cv;
-                            nc += 1.0;
-                        }
-                    }
-                }
-            }
-        }
-        s2 = psfm_block_sum(s2, red);
-        n2 = psfm_block_sum(n2, red);
-        sc = psfm_block_sum(sc, red);
-        nc = psfm_block_sum(nc, red);
+        match_tile<H_>(p, t, B0, P, bad_frac, halo, tapsK, tapsV, badw, ring, red, &s_rb, &s_f);
         if (tid == 0) {
-            double* q = p.sub_part + 4 * (size_t)t;
-            q[0] = s2;
-            q[1] = n2;
-            q[2] = sc;
-            q[3] = nc;
             __threadfence();
             const unsigned prev = atomicAdd(p.tiles_done, 1u);
             s_last = prev + 1 == (unsigned)(p.ntx * p.nty);
@@ -894,6 +908,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         }
         __syncthreads();
     }
+}
+
+// The fused apply of one pair (psfm_match_pair): one workgroup per tile, the
+// pair's description by value; C_D follows in k_subtract_cov.
+template <int H_>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_match_tile(PairDesc p, BasisArgs B0, int P,
+                                                                                          double bad_frac) {
+    constexpr int KW = 2 * H_ + 1;
+    constexpr int T = KW * KW;
+    constexpr int HW = TILE + 2 * H_;
+    constexpr int NWB = (HW + 31) / 32 + 1;
+    __shared__ __align__(16) float halo[HW * HW];
+    __shared__ __align__(16) float tapsK[T + 4];
+    __shared__ __align__(16) float tapsV[T + 4];
+    __shared__ uint32_t badw[HW][NWB];
+    __shared__ double ring[H_ + 1];
+    __shared__ double red[16];
+    __shared__ int s_rb;
+    __shared__ double s_f;
+    match_tile<H_>(p, blockIdx.x, B0, P, bad_frac, halo, tapsK, tapsV, badw, ring, red, &s_rb, &s_f);
 }
 
 constexpr int SUB_BLOCKS = 1024;
@@ -916,6 +950,13 @@ size_t subtract_workspace(const psfm_context*, int, int) {
     Carver c(nullptr);
     c.take<double>(4 * SUB_BLOCKS);
     return c.off;
+}
+
+// psfm_match_pair: the pseudo-matrix scratch, then the tiles' variance sums.
+size_t match_workspace(const psfm_context* ctx, int W, int H) {
+    const PatchGeom g = patch_geom(W, H, ctx->cfg.patch);
+    return align_up(conv_workspace(ctx, W, H), 256) +
+           sizeof(double) * 4 * (size_t)(g.npx * g.tpp) * (g.npy * g.tpp);
 }
 
 int cov_sample_side(const psfm_context* ctx, int c_in) { return 2 * (2 * ctx->h + c_in) + 1; }
@@ -1093,6 +1134,79 @@ extern "C" int psfm_subtract(const psfm_context* ctx, const double* coeffs, cons
                            W, H, pitch, coeffs + (ctx->N - 1), diff, diff_var, diff_mask, partials);
     PSFM_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(k_subtract_cov, dim3(1), dim3(256), 0, st, partials, nblk, cov2, cov2_half,
+                       cov_conv, cov_conv_half, cov_diff, cov_diff_half);
+    PSFM_HIP_CHECK(hipGetLastError());
+    return PSFM_OK;
+}
+
+template <int H_>
+static void launch_match_tile(const PairDesc& p, const BasisArgs& B, int P, double bad_frac, int n_tiles,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(k_match_tile<H_>, dim3(n_tiles), dim3(256), 0, st, p, B, P, bad_frac);
+}
+
+extern "C" int psfm_match_pair(const psfm_context* ctx, const double* coeffs, const float* I1,
+                               const float* V1, const uint8_t* M1, const float* I2, const float* V2,
+                               const uint8_t* M2, int W, int H, int64_t pitch, const double* cov1,
+                               int cov1_half, const double* cov2, int cov2_half, float* conv,
+                               uint8_t* conv_mask, float* conv_var, double* cov_conv,
+                               int cov_conv_half, float* diff, float* diff_var, uint8_t* diff_mask,
+                               double* cov_diff, int cov_diff_half, psfm_fit_stats* stats, void* ws,
+                               size_t ws_bytes, void* stream) {
+    int rc = check_image_args(ctx, W, H, pitch);
+    if (rc) return rc;
+    if (!coeffs || !I1 || !V1 || !M1 || !I2 || !V2 || !M2 || !cov_conv || !diff || !diff_var ||
+        !diff_mask || !cov_diff || (conv == nullptr) != (conv_mask == nullptr) || cov1_half < 0 ||
+        cov2_half < 0 || cov_conv_half < 0 || cov_diff_half < 0)
+        return PSFM_ERR_INVALID_ARG;
+    if (cov1_half > 32 || cov_conv_half > 2 * ctx->h + 64) return PSFM_ERR_UNSUPPORTED;
+    if (!cov1) cov1_half = 0;
+    if (!ws || ws_bytes < psfm::match_workspace(ctx, W, H)) return PSFM_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    const psfm_config& cf = ctx->cfg;
+    const PatchGeom g = patch_geom(W, H, cf.patch);
+    PairDesc p{};
+    p.I1 = I1;
+    p.V1 = V1;
+    p.M1 = M1;
+    p.I2 = I2;
+    p.V2 = V2;
+    p.M2 = M2;
+    p.W = W;
+    p.H = H;
+    p.pitch = pitch;
+    p.N = ctx->N;
+    p.ns = ctx->ns;
+    p.S = cf.spatial_order;
+    p.coeffs = const_cast<double*>(coeffs);
+    p.cov1 = cov1;
+    p.cov1_half = cov1_half;
+    p.conv = conv;
+    p.conv_mask = conv_mask;
+    p.var = conv_var;
+    p.diff = diff;
+    p.diff_var = diff_var;
+    p.diff_mask = diff_mask;
+    p.ntx = g.npx * g.tpp;
+    p.nty = g.npy * g.tpp;
+    p.sub_part = reinterpret_cast<double*>(static_cast<char*>(ws) +
+                                           psfm::align_up(psfm::conv_workspace(ctx, W, H), 256));
+    const int n_tiles = p.ntx * p.nty;
+    const BasisArgs B = basis_args(ctx);
+    switch (ctx->h) {
+#define PSFM_M1_CASE(HH) \
+    case HH: launch_match_tile<HH>(p, B, cf.patch, cf.bad_frac, n_tiles, st); break;
+        PSFM_M1_CASE(1) PSFM_M1_CASE(2) PSFM_M1_CASE(3) PSFM_M1_CASE(4) PSFM_M1_CASE(5)
+        PSFM_M1_CASE(6) PSFM_M1_CASE(7) PSFM_M1_CASE(8) PSFM_M1_CASE(9) PSFM_M1_CASE(10)
+        PSFM_M1_CASE(11) PSFM_M1_CASE(12) PSFM_M1_CASE(13) PSFM_M1_CASE(14) PSFM_M1_CASE(15)
+        PSFM_M1_CASE(16)
+#undef PSFM_M1_CASE
+        default: return PSFM_ERR_UNSUPPORTED;
+    }
+    PSFM_HIP_CHECK(hipGetLastError());
+    rc = cov_pseudo(ctx, coeffs, W, H, cov1, cov1_half, cov_conv, cov_conv_half, stats, ws, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_subtract_cov, dim3(1), dim3(256), 0, st, p.sub_part, n_tiles, cov2, cov2_half,
                        cov_conv, cov_conv_half, cov_diff, cov_diff_half);
     PSFM_HIP_CHECK(hipGetLastError());
     return PSFM_OK;

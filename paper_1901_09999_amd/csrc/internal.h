@@ -145,6 +145,7 @@ size_t fit_workspace(const psfm_context* ctx, int n_stamps);
 size_t solve_workspace(const psfm_context* ctx, int n_stamps);
 size_t conv_workspace(const psfm_context* ctx, int W, int H);
 size_t subtract_workspace(const psfm_context* ctx, int W, int H);
+size_t match_workspace(const psfm_context* ctx, int W, int H);
 
 int fit_bands(const psfm_context* ctx);
 int n_patches(const psfm_context* ctx, int W, int H);

@@ -406,3 +406,59 @@ def test_convolve_pair_equals_separate_calls(W, H, P, h, c_in):
     assert np.array_equal(_np(var2), _np(var))
     assert np.array_equal(_np(cov2), _np(cov))
     assert psfm.read_stats(s2)["cov_discarded_frac"] == psfm.read_stats(s1)["cov_discarded_frac"]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("W,H,P,h,c_in", [(2048, 2048, 64, 10, 0), (300, 217, 64, 5, 1),
+                                          (161, 190, 50, 3, 2)])
+def test_match_pair_equals_separate_calls(W, H, P, h, c_in):
+    """psfm_match_pair (convolutions and difference in one pass over the
+    tiles) gives psfm_convolve_pair + psfm_subtract's difference image
+    bit for bit, with or without the convolved planes written, with
+    uncorrelated or correlated inputs, on full and ragged tilings; C_D's
+    variance means are summed per tile, so it agrees to rounding."""
+    torch, psfm = hip()
+    base = synth.WORKLOADS["pair2048"]
+    wl = base if W == 2048 else synth.scaled(base, f"mp{W}x{H}", W, H, n_sources=max(40, W * H // 600),
+                                             n_stamps=20, kernel_half=h, patch=P)
+    pair = synth.make_pair(wl, 57 + W)
+    cfg = O.Config.from_workload(wl)
+    ctx = _ctx(wl)
+    d = psfm.to_device(pair)
+    rng = np.random.default_rng(W + 1)
+    a = np.zeros(cfg.n_unknowns)
+    a[0] = 1.0
+    a[: cfg.n_unknowns - 1] += 0.02 * rng.standard_normal(cfg.n_unknowns - 1)
+    a[-1] = 2.0
+    at = torch.from_numpy(a).cuda()
+    cin = c2 = None
+    if c_in:
+        def corr(c):
+            q = rng.uniform(0.0, 1.0, (2 * c + 1, 2 * c + 1))
+            m = np.array([[np.sum(q[max(0, -dy):q.shape[0] - max(0, dy), max(0, -dx):q.shape[1] - max(0, dx)] *
+                                  q[max(0, dy):q.shape[0] - max(0, -dy), max(0, dx):q.shape[1] - max(0, -dx)])
+                           for dx in range(-c, c + 1)] for dy in range(-c, c + 1)])
+            return torch.from_numpy(m / m[c, c]).cuda()
+        cin, c2 = corr(c_in), corr(c_in + 1)
+    print(f"{W}x{H} P={P} h={h} c_in={c_in}", flush=True)
+    conv, cm, var, cov = ctx.convolve_pair(at, d["I1"], d["V1"], d["M1"], cov_in=cin, c_out=12)
+    ref = ctx.subtract(at, d["I2"], d["V2"], d["M2"], conv, var, cm, cov, cov2=c2)
+    conv_f = torch.full_like(conv, -1.0)
+    cm_f = torch.full_like(cm, 7)
+    var_f = torch.full_like(var, -1.0)
+    full = ctx.match(at, d["I1"], d["V1"], d["M1"], d["I2"], d["V2"], d["M2"], cov1=cin, cov2=c2,
+                     c_out=12, conv=conv_f, conv_mask=cm_f, conv_var=var_f)
+    bare = ctx.match(at, d["I1"], d["V1"], d["M1"], d["I2"], d["V2"], d["M2"], cov1=cin, cov2=c2,
+                     c_out=12)
+    torch.cuda.synchronize()
+    assert np.array_equal(_np(conv_f), _np(conv))
+    assert np.array_equal(_np(cm_f), _np(cm))
+    assert np.array_equal(_np(var_f), _np(var))
+    for r in (full, bare):
+        assert np.array_equal(_np(r["cov"]), _np(cov))
+        for k in ("diff", "diff_var", "diff_mask"):
+            assert np.array_equal(_np(r[k]), _np(ref[k])), k
+        cd, cd_ref = _np(r["cov_diff"]), _np(ref["cov_diff"])
+        assert cd.shape == cd_ref.shape
+        assert np.max(np.abs(cd - cd_ref)) <= 1e-12 * np.max(np.abs(cd_ref))
+
