@@ -365,28 +365,31 @@ __device__ __forceinline__ double iv_dot(const double* __restrict__ iv, const do
     return (s4[0] + s4[1]) + (s4[2] + s4[3]);
 }
 
-// Forward substitution L z = z (z in LDS, overwritten) with a stored factor,
+// Forward substitution L z = z (z in LDS, overwritten) with a stored factor
+// (its entries below the diagonal blocks from the transposed copy LT),
 // right-looking: z_q = Iv_q z_q (wave 0), then every row below the panel
 // takes it out, z_i -= sum_t L(i, q0 + t) z_(q0 + t) (one thread per row).
 // The rows of the next panel are loaded during this panel's update (two
 // register sets, the step loop unrolled by two so that they swap without a
 // copy), so that no load stands in front of wave 0's z_q, the serial chain.
 // Inverses as in back_subst.
-__device__ __forceinline__ void forward_subst(int N, const double* __restrict__ A,
+__device__ __forceinline__ void forward_subst(int N, const double* __restrict__ LT,
                                               const double* __restrict__ ILg, double* zb, double* P,
                                               bool staged, double* wq) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int np = (N + CH_NB - 1) / CH_NB;
-    // row q0 + nk + tid's nk entries of panel q (zeros beyond nk); a wave
-    // with no row below the panel issues no loads (the vector memory
-    // pipeline, not the bytes, bounds these steps)
+    // row q0 + nk + tid's nk entries of panel q from the transposed factor
+    // (LT[c][i] = L(i, c): consecutive rows are consecutive words, so a load
+    // instruction touches a few cache lines, not one per lane; zeros beyond
+    // nk); a wave with no row below the panel issues no loads (the vector
+    // memory pipeline, not the bytes, bounds these steps)
     auto load_row = [&](int q, double* lv) {
         const int q0 = q * CH_NB, nk = min(CH_NB, N - q0);
         const bool need = wave * 64 < N - q0 - nk;
-        const double* row = A + (size_t)min(q0 + nk + tid, N - 1) * N + q0;
+        const double* col = LT + (size_t)q0 * N + min(q0 + nk + tid, N - 1);
 #pragma unroll
         for (int t = 0; t < CH_NB; t++) {
-            if (need && t < nk) lv[t] = row[t];
+            if (need && t < nk) lv[t] = col[(size_t)t * N];
             else lv[t] = 0.0;
         }
     };
@@ -688,7 +691,8 @@ __device__ __forceinline__ void trail_block(int N, int k0, int nk, int rows, int
 __device__ __forceinline__ void cholesky_body(int N, double* __restrict__ A, const double* __restrict__ S,
                               const double* __restrict__ b,
                               double* __restrict__ x, double* __restrict__ ILg,
-                              double* __restrict__ Dg, SolveState* st) {
+                              double* __restrict__ Dg, SolveState* st,
+                              double* __restrict__ LT = nullptr) {
     if (st->done) return;
     extern __shared__ double P[];        // panel [max(N, 32) + 16][CH_PS]
     __shared__ double Dq[CH_NMAX];
@@ -796,6 +800,14 @@ __device__ __forceinline__ void cholesky_body(int N, double* __restrict__ A, con
             for (int i = nk + tr; i < rows; i += TR)
                 if (tc < nk) A[(k0 + i) * N + k0 + tc] = P[i * CH_PS + tc];
         }
+        if (LT) {
+            // the same entries transposed, LT[c][i] = L(i, c), for the
+            // refinement's forward substitution (coalesced reads there)
+            const int ti = tid & 63;
+            for (int c = tid >> 6; c < nk; c += CH_THREADS / 64)
+                for (int i = nk + ti; i < rows; i += 64)
+                    LT[(size_t)(k0 + c) * N + k0 + i] = P[i * CH_PS + c];
+        }
         // ---- trailing update, with the next diagonal block first (wave 0)
         if (m > 0) {
             const int mt = (m + 31) / 32;
@@ -851,7 +863,8 @@ __global__ __launch_bounds__(CH_THREADS) void k_cholesky(int N, double* __restri
                                                          double* __restrict__ ILg,
                                                          double* __restrict__ Dg, SolveState* st,
                                                          const double* __restrict__ Msrc,
-                                                         int* __restrict__ info) {
+                                                         int* __restrict__ info,
+                                                         double* __restrict__ LT) {
     if (OWN) {
         if (threadIdx.x == 0) {
             st->done = 0;
@@ -859,7 +872,7 @@ __global__ __launch_bounds__(CH_THREADS) void k_cholesky(int N, double* __restri
         }
         __syncthreads();
     }
-    cholesky_body(N, A, OWN ? Msrc : A, b, x, ILg, Dg, st);
+    cholesky_body(N, A, OWN ? Msrc : A, b, x, ILg, Dg, st, LT);
     if (OWN) {
         __syncthreads();
         if (threadIdx.x == 0) *info = st->info;
@@ -876,7 +889,8 @@ __global__ __launch_bounds__(CH_THREADS) void k_cholesky_b(const PairDesc* __res
 // lower triangle in A, 1/sqrt(diag M) in Dg, the diagonal-block inverses in
 // ILg); x += d.  One workgroup.  This is the correction step of the
 // iterative refinement of the 16-bit modes.
-__device__ __forceinline__ void resolve_body(int N, const double* __restrict__ A, const double* __restrict__ ILg,
+__device__ __forceinline__ void resolve_body(int N, const double* __restrict__ A, const double* __restrict__ LT,
+                             const double* __restrict__ ILg,
                              const double* __restrict__ Dg, const double* __restrict__ g,
                              double* __restrict__ x, const SolveState* st) {
     if (st->done) return;
@@ -890,17 +904,18 @@ __device__ __forceinline__ void resolve_body(int N, const double* __restrict__ A
         if (i < N) Dq[i] = Dg[i];
     }
     const bool staged = stage_inverses(N, ILg, P);    // (its barrier also orders zb)
-    forward_subst(N, A, ILg, zb, P, staged, wq);      // L z = D g
+    forward_subst(N, LT, ILg, zb, P, staged, wq);     // L z = D g
     back_subst(N, A, ILg, zb, P, staged, wq);
     for (int i = tid; i < N; i += CH_THREADS) x[i] += Dq[i] * zb[i];
 }
 
 __global__ __launch_bounds__(CH_THREADS) void k_resolve(int N, const double* __restrict__ A,
+                                                        const double* __restrict__ LT,
                                                         const double* __restrict__ ILg,
                                                         const double* __restrict__ Dg,
                                                         const double* __restrict__ g,
                                                         double* __restrict__ x, const SolveState* st) {
-    resolve_body(N, A, ILg, Dg, g, x, st);
+    resolve_body(N, A, LT, ILg, Dg, g, x, st);
 }
 
 // Pixel residuals of every fitted stamp at the current coefficients, from
@@ -1646,6 +1661,8 @@ size_t solve_workspace(const psfm_context* ctx, int n) {
     c.take<double>(ctx->N);                          // prior: warm start
     c.take<double>(1);
     c.take<int>(2);
+    if (ctx->cfg.precision != PSFM_PREC_FP32)
+        c.take<double>((size_t)ctx->N * ctx->N);     // transposed factor (refinement)
     return c.off;
 }
 
@@ -1748,6 +1765,7 @@ static int solve_impl(const psfm_context* ctx, int W, int H, const int32_t* stam
     double* a0 = c.take<double>(ctx->N);
     double* pdof = c.take<double>(1);
     int* pcounts = c.take<int>(2);
+    double* LT = mixed ? c.take<double>((size_t)ctx->N * ctx->N) : nullptr;   // transposed factor
     const int nb = ctx->nb, ns = ctx->ns, N = ctx->N, L = ctx->L;
     const int npix = (2 * ctx->r + 1) * (2 * ctx->r + 1);
     const psfm_config& cf = ctx->cfg;
@@ -1791,7 +1809,8 @@ static int solve_impl(const psfm_context* ctx, int W, int H, const int32_t* stam
             default: return PSFM_ERR_UNSUPPORTED;
         }
         hipLaunchKernelGGL(k_cholesky<false>, dim3(1), dim3(CH_THREADS), lds, st, N, M, b, coeffs, ILg,
-                           mixed ? Dg : nullptr, state, nullptr, nullptr);
+                           mixed ? Dg : nullptr, state, nullptr, nullptr,
+                           mixed && n_stamps > 0 ? LT : nullptr);
         if (mixed && n_stamps > 0) {
             // 16-bit sums: refine against FP32 pixel residuals, then chi2 from pixels
             for (int k = 0; k < cf.refine; k++) {
@@ -1799,8 +1818,8 @@ static int solve_impl(const psfm_context* ctx, int W, int H, const int32_t* stam
                                    npix, stamp_design, G, coeffs, fitted, gt, stamp_chi2, state);
                 hipLaunchKernelGGL(k_assemble_vec, dim3(N), dim3(64), 0, st, n_stamps,
                                    nb, ns, N, gt, G, used, gv, state);
-                hipLaunchKernelGGL(k_resolve, dim3(1), dim3(CH_THREADS), lds, st, N, M, ILg, Dg, gv,
-                                   coeffs, state);
+                hipLaunchKernelGGL(k_resolve, dim3(1), dim3(CH_THREADS), lds, st, N, M, LT, ILg, Dg,
+                                   gv, coeffs, state);
             }
             hipLaunchKernelGGL(k_resid, dim3(n_stamps), dim3(RES_T), 0, st, n_stamps, nb, ns, N, npix,
                                stamp_design, G, coeffs, fitted, gt, stamp_chi2, state);
@@ -1880,7 +1899,7 @@ extern "C" int psfm_cholesky_solve(int n, const double* M, const double* b, doub
     double* A = c.take<double>((size_t)n * n);
     double* ILg = c.take<double>(psfm::solve_il_doubles(n));
     hipLaunchKernelGGL(k_cholesky<true>, dim3(1), dim3(CH_THREADS), lds, st, n, A, b, x, ILg, nullptr,
-                       state, M, info);
+                       state, M, info, nullptr);
     PSFM_HIP_CHECK(hipGetLastError());
     return PSFM_OK;
 }
