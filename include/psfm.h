@@ -259,7 +259,7 @@ int psfm_solve_stamps(const psfm_context* ctx, int n_stamps, const double* stamp
  * an excluded stamp whose chi2_s / npix_s at the solution lies within the
  * method's clip threshold is restored, and the rejection loop resumes from
  * the restored set (up to max_iter more solutions), so the least-squares
- * solution and the method's own clip remain the judge.  Same arguments as
+ * solution and the method's own clip have the final word.  Same arguments as
  * psfm_solve.
  */
 int psfm_solve_prior(const psfm_context* ctx, int W, int H, const int32_t* stamp_xy, int n_stamps,

@@ -4,7 +4,7 @@ A small CNN predicts each stamp's kernel from the stamp pair; it is trained
 on single-star stamp pairs whose targets are the kernels the method itself
 solves for each stamp (psfm_fit_stamps + psfm_solve_stamps).  In use, its
 predictions feed psfm_solve_prior: a warm start and a rejection prior, with
-the full least-squares solve as the fallback and the judge.
+the full least-squares solve as the fallback and the final word.
 
 This module only marshals: the network's forward, loss gradient and Adam
 steps run in the library's FP16 kernels (psfm_cnn_*).

@@ -4,7 +4,7 @@ A network is trained on the GPU (stamp pairs in crowded cells, kernels
 solved by the method), then used on spatially varying pairs with 10%
 variable sources.  The full method (three solutions) is checked against the
 FP64 oracle at the whole-path target; the gain is measured at an equal solve
-budget, and the fallback keeps the least-squares solution the judge.
+budget, and the fallback leaves the final word to the least-squares solution.
 """
 import numpy as np
 import pytest
