@@ -724,13 +724,13 @@ __device__ void cov_diff_body(const double* __restrict__ partials, int nparts,
                               int cd) {
     __shared__ double red[16];
     double v[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int b = threadIdx.x; b < nparts; b += 256)
+    for (int b = threadIdx.x; b < nparts; b += blockDim.x)
         for (int k = 0; k < 4; k++) v[k] += partials[4 * b + k];
     for (int k = 0; k < 4; k++) v[k] = psfm_block_sum(v[k], red);
     const double v2 = v[1] > 0.0 ? v[0] / v[1] : 0.0;
     const double vc = v[3] > 0.0 ? v[2] / v[3] : 0.0;
     const int Dw = 2 * cd + 1;
-    for (int e = threadIdx.x; e < Dw * Dw; e += 256) {
+    for (int e = threadIdx.x; e < Dw * Dw; e += blockDim.x) {
         const int dy = e / Dw - cd, dx = e % Dw - cd;
         double a2 = 0.0, ac = 0.0;
         if (cov2) {
@@ -748,6 +748,20 @@ __global__ __launch_bounds__(256) void k_subtract_cov(const double* __restrict__
                                                       const double* __restrict__ covc, int cc,
                                                       double* __restrict__ covd, int cd) {
     cov_diff_body(partials, nblk, cov2, c2, covc, cc, covd, cd);
+}
+
+// psfm_match_pair's last step: the convolved image's pseudo-matrix C' from
+// the samples, then C_D from the tiles' variance sums and C' (one launch).
+__global__ __launch_bounds__(1024) void k_cov_finish_diff(const double* __restrict__ samples, int R,
+                                                         double* __restrict__ avg,
+                                                         double* __restrict__ cov_out, int c_out,
+                                                         psfm_fit_stats* stats,
+                                                         const double* __restrict__ partials,
+                                                         int nparts, const double* __restrict__ cov2,
+                                                         int c2, double* __restrict__ covd, int cd) {
+    cov_finish_body(samples, R, avg, cov_out, c_out, stats);
+    __syncthreads();       // C' (global, this workgroup's writes) before its use
+    cov_diff_body(partials, nparts, cov2, c2, cov_out, c_out, covd, cd);
 }
 
 // One 64 x 64 tile t of a pair of the fused apply: the patch kernel is
@@ -1039,9 +1053,13 @@ extern "C" int psfm_convolve_image(const psfm_context* ctx, const double* coeffs
 
 // The covariance pseudo-matrix part of the variance propagation: samples at
 // the centres of the 3 x 3 partition, their mean, normalised and cropped.
+// With covd given, C_D follows in the same launch as C' (psfm_match_pair):
+// from the tiles' variance sums parts[nparts][4] and cov2.
 static int cov_pseudo(const psfm_context* ctx, const double* coeffs, int W, int H,
                       const double* cov_in, int cov_in_half, double* cov_out, int cov_out_half,
-                      psfm_fit_stats* stats, void* ws, hipStream_t st) {
+                      psfm_fit_stats* stats, void* ws, hipStream_t st,
+                      const double* parts = nullptr, int nparts = 0, const double* cov2 = nullptr,
+                      int c2 = 0, double* covd = nullptr, int cd = 0) {
     psfm::Carver c(ws);
     const int Rmax = 2 * ctx->h + 32;
     double* samples = c.take<double>((size_t)PSFM_COV_SAMPLES * (2 * Rmax + 1) * (2 * Rmax + 1));
@@ -1055,8 +1073,12 @@ static int cov_pseudo(const psfm_context* ctx, const double* coeffs, int W, int 
     if (cov_in)
         hipLaunchKernelGGL(k_cov_mix, dim3(PSFM_COV_SAMPLES, (Rw * Rw + 255) / 256), dim3(256), 0, st,
                            autoc, ctx->h, cov_in, cov_in_half, samples);
-    hipLaunchKernelGGL(k_cov_finish, dim3(1), dim3(1024), 0, st, samples, R, avg, cov_out,
-                       cov_out_half, stats);
+    if (covd)
+        hipLaunchKernelGGL(k_cov_finish_diff, dim3(1), dim3(1024), 0, st, samples, R, avg, cov_out,
+                           cov_out_half, stats, parts, nparts, cov2, c2, covd, cd);
+    else
+        hipLaunchKernelGGL(k_cov_finish, dim3(1), dim3(1024), 0, st, samples, R, avg, cov_out,
+                           cov_out_half, stats);
     PSFM_HIP_CHECK(hipGetLastError());
     return PSFM_OK;
 }
@@ -1204,10 +1226,6 @@ extern "C" int psfm_match_pair(const psfm_context* ctx, const double* coeffs, co
         default: return PSFM_ERR_UNSUPPORTED;
     }
     PSFM_HIP_CHECK(hipGetLastError());
-    rc = cov_pseudo(ctx, coeffs, W, H, cov1, cov1_half, cov_conv, cov_conv_half, stats, ws, st);
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_subtract_cov, dim3(1), dim3(256), 0, st, p.sub_part, n_tiles, cov2, cov2_half,
-                       cov_conv, cov_conv_half, cov_diff, cov_diff_half);
-    PSFM_HIP_CHECK(hipGetLastError());
-    return PSFM_OK;
+    return cov_pseudo(ctx, coeffs, W, H, cov1, cov1_half, cov_conv, cov_conv_half, stats, ws, st,
+                      p.sub_part, n_tiles, cov2, cov2_half, cov_diff, cov_diff_half);
 }
