@@ -447,7 +447,7 @@ __device__ void fit_reduce_body(const double* __restrict__ part, const int* __re
                                 int nbands, int nb, int npix, double* __restrict__ Ms,
                                 double* __restrict__ bs, double* __restrict__ es,
                                 int32_t* __restrict__ npix_out, int32_t* __restrict__ flags_out,
-                                const int s) {
+                                const int s, const int q, const int nq) {
     const int tid = threadIdx.x;
     const int L = nb + 1;
     __shared__ int s_fl;
@@ -462,9 +462,11 @@ __device__ void fit_reduce_body(const double* __restrict__ part, const int* __re
     double* M = Ms + (size_t)s * L * L;
     double* bv = bs + (size_t)s * L;
     const double* P0 = part + (size_t)s * nbands * GC * GC;
-    // four entries per thread at a time, their band partials loaded together
-    // (clamped index beyond L * L); each sum runs over the bands in order
-    for (int e0 = tid; e0 < L * L; e0 += 4 * 256) {
+    // workgroup q of the stamp's nq takes entries [1024 q, 1024 (q + 1)), and
+    // so on every nq-th chunk: four entries per thread, their band partials
+    // loaded together (clamped index beyond L * L); each sum runs over the
+    // bands in order
+    for (int e0 = 4 * 256 * q + tid; e0 < L * L; e0 += 4 * 256 * nq) {
         double v[4] = {0.0, 0.0, 0.0, 0.0};
         int off[4];
 #pragma unroll
@@ -484,14 +486,14 @@ __device__ void fit_reduce_body(const double* __restrict__ part, const int* __re
         for (int u = 0; u < 4; u++)
             if (e0 + 256 * u < L * L) M[e0 + 256 * u] = v[u];
     }
-    for (int i = tid; i <= L; i += 256) {
+    for (int i = tid; q == nq - 1 && i <= L; i += 256) {
         double v = 0.0;
         if (!fl)
             for (int b = 0; b < nbands; b++) v += P0[(size_t)b * GC * GC + (nb + 1) * GC + i];
         if (i < L) bv[i] = v;
         else es[s] = v;
     }
-    if (tid == 0) {
+    if (tid == 0 && q == 0) {
         npix_out[s] = fl ? 0 : npix;
         flags_out[s] = fl;
     }
@@ -503,15 +505,19 @@ __global__ __launch_bounds__(256) void k_fit_reduce(const double* __restrict__ p
                                                     double* __restrict__ bs, double* __restrict__ es,
                                                     int32_t* __restrict__ npix_out,
                                                     int32_t* __restrict__ flags_out) {
-    fit_reduce_body(part, band_flags, nbands, nb, npix, Ms, bs, es, npix_out, flags_out, blockIdx.x);
+    fit_reduce_body(part, band_flags, nbands, nb, npix, Ms, bs, es, npix_out, flags_out, blockIdx.x,
+                    blockIdx.y, gridDim.y);
 }
+
+// Workgroups per stamp of the reduction: one 1024-entry chunk of L x L each.
+inline int reduce_parts(const psfm_context* ctx) { return (ctx->L * ctx->L + 1023) / 1024; }
 
 __global__ __launch_bounds__(256) void k_fit_reduce_b(const PairDesc* __restrict__ pairs,
                                                       const int* __restrict__ stamp_pair, int nbands,
                                                       int nb, int npix) {
     const PairDesc& pd = pairs[stamp_pair[blockIdx.x]];
     fit_reduce_body(pd.part, pd.bflags, nbands, nb, npix, pd.Ms, pd.bs, pd.es, pd.npix, pd.flags,
-                    blockIdx.x - pd.stamp_off);
+                    blockIdx.x - pd.stamp_off, blockIdx.y, gridDim.y);
 }
 
 FitArgs base_fit_args(const psfm_context* ctx) {
@@ -627,8 +633,8 @@ int batch_fit(const psfm_context* ctx, const PairDesc* pairs, const int* item_pa
     int rc = dispatch_fit(ctx, base_fit_args(ctx), n_items, pairs, item_pair, st);
     if (rc) return rc;
     const int npix = (2 * ctx->r + 1) * (2 * ctx->r + 1);
-    hipLaunchKernelGGL(k_fit_reduce_b, dim3(n_stamps), dim3(256), 0, st, pairs, stamp_pair,
-                       fit_bands(ctx), ctx->nb, npix);
+    hipLaunchKernelGGL(k_fit_reduce_b, dim3(n_stamps, reduce_parts(ctx)), dim3(256), 0, st, pairs,
+                       stamp_pair, fit_bands(ctx), ctx->nb, npix);
     PSFM_HIP_CHECK(hipGetLastError());
     return PSFM_OK;
 }
@@ -681,7 +687,7 @@ extern "C" int psfm_fit_stamps(const psfm_context* ctx, const float* I1, const u
     int rc = dispatch_fit(ctx, a, n_stamps * a.nbands, nullptr, nullptr, st);
     if (rc != PSFM_OK) return rc;
     const int npix = (2 * ctx->r + 1) * (2 * ctx->r + 1);
-    hipLaunchKernelGGL(k_fit_reduce, dim3(n_stamps), dim3(256), 0, st, part, bflags,
+    hipLaunchKernelGGL(k_fit_reduce, dim3(n_stamps, reduce_parts(ctx)), dim3(256), 0, st, part, bflags,
                        psfm::fit_bands(ctx), ctx->nb, npix, stamp_M, stamp_b, stamp_e, stamp_npix,
                        stamp_flags);
     PSFM_HIP_CHECK(hipGetLastError());
