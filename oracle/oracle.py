@@ -3,9 +3,6 @@
 TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke`` and
 the CPU-baseline leg of ``bench.py``; never by the product path.  The arithmetic
 lives in the C file; this module only marshals numpy arrays.
-
-Stored expected values under ``tests/golden`` come from :mod:`oracle.make_golden`,
-which calls only this module.
 """
 from __future__ import annotations
 

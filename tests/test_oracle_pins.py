@@ -539,3 +539,223 @@ def test_matched_filter_noise_statistic(orc):
     # ignoring the covariance (variance only) under-predicts the noise badly
     z0 = F[sl] / np.sqrt(var[sl].astype(np.float64) * (m ** 2).sum())
     assert z0.std() > 1.5
+
+
+def test_difference_noise_statistic(orc):
+    """Section 4.3 (image combination) checked with the Section 4.4 statistic
+    on the difference image itself: two independent correlated-noise images of
+    known variance and pseudo-matrix; image 1 is convolved with a matching
+    kernel (its pseudo-matrix propagated), then subtracted from image 2.  The
+    matched-filter output of D divided by sqrt(V_D * sum m(u) m(u') C_D(u-u'))
+    has unit standard deviation (paper: within 6%).  Dropping either variance
+    term, or averaging the two pseudo-matrices without the variance weights,
+    moves the statistic far outside that band, so each part of V_D and C_D is
+    pinned."""
+    cfg = O.Config(S=0)
+    kb = O.basis(cfg)
+    a = np.zeros(cfg.n_unknowns)
+    a[0] = 1.0
+    a[term_index(cfg, 1, 0, 0)] = 1.0               # K = unit-sum Gaussian, sigma 1.5
+    W = H = 768
+    g1 = np.array([[0.0, 0.3, 0.0], [0.2, 1.0, 0.4], [0.0, 0.1, 0.0]])
+    g2 = np.array([[0.1, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 0.3]])
+
+    def pseudo(g):                                   # normalised autocorrelation, 5 x 5
+        c = signal.correlate2d(g, g, mode="full")
+        return c / c[2, 2]
+
+    rng = np.random.default_rng(2024)
+    s1, s2 = 16.0, 4.0
+    I1 = conv_same(rng.standard_normal((H, W)) * s1, g1).astype(np.float32)
+    I2 = conv_same(rng.standard_normal((H, W)) * s2, g2).astype(np.float32)
+    V1 = np.full((H, W), s1 * s1 * (g1 ** 2).sum(), np.float32)
+    V2 = np.full((H, W), s2 * s2 * (g2 ** 2).sum(), np.float32)
+    Z = np.zeros((H, W), np.uint8)
+    C1, C2 = pseudo(g1), pseudo(g2)
+    conv, cm = O.convolve_image(cfg, a, I1, Z, kb=kb)
+    R = 2 * cfg.h + 2
+    var, cov, disc = O.propagate_variance(cfg, a, V1, Z, cov_in=C1, c_in=2, c_out=R, kb=kb)
+    assert disc < 1e-15                              # nothing cropped at c_out = 2h + c_in
+    D, VD, MD, CD = O.subtract(cfg, a, I2, V2, Z, conv, var, cm, cov, cov2=C2)
+    c = CD.shape[0] // 2
+    assert c == R and abs(CD[c, c] - 1.0) < 1e-12
+    hm = 6
+    m = gauss_img(2 * hm + 1, 2 * hm + 1, hm, hm, 2.0)
+    m /= m.sum()
+    mm = signal.correlate2d(m, m, mode="full")
+    sl = (slice(40, H - 40), slice(40, W - 40))
+    F = signal.fftconvolve(D.astype(np.float64), m, mode="same")[sl]
+
+    def stat(Cm, Vm):
+        f = (mm * Cm[c - 2 * hm:c + 2 * hm + 1, c - 2 * hm:c + 2 * hm + 1]).sum()
+        return (F / np.sqrt(Vm[sl].astype(np.float64) * f)).std()
+
+    assert abs(stat(CD, VD) - 1.0) < 0.03
+    # the two inputs' variances are comparable, so each term of V_D matters
+    vc = float(var[sl].mean())
+    assert 0.3 < float(V2[0, 0]) / vc < 3.0
+    assert stat(CD, var) > 1.15 and stat(CD, V2) > 1.15
+    # the variance-weighted average of the pseudo-matrices is what holds
+    C2p = np.zeros_like(CD)
+    C2p[c - 2:c + 3, c - 2:c + 3] = C2
+    assert stat(0.5 * (C2p + cov), VD) > 1.08
+    # where image 2 is masked the difference carries no value and is flagged
+    M2 = Z.copy()
+    M2[100:104, 200:260] = 1
+    D2, VD2, MD2, _ = O.subtract(cfg, a, I2, V2, M2, conv, var, cm, cov, cov2=C2)
+    assert (D2[M2 != 0] == 0).all() and (VD2[M2 != 0] == 0).all()
+    assert (MD2[M2 != 0] & O.MASK_BAD).all() and (MD2[M2 == 0] == MD[M2 == 0]).all()
+
+
+def test_convolve_region_equals_full_image(orc):
+    """The rectangle form computes every pixel exactly as the full-image
+    convolution and variance propagation (which the brute-force map tests
+    pin): full rectangle and off-origin rectangles that cut patches, with
+    masks, a correlated input, spatial variation and patches smaller than the
+    image."""
+    cfg = O.Config(sigmas=(0.8, 1.6, 2.5), degrees=(2, 2, 0), h=4, S=2, P=16)
+    W, H = 75, 58
+    rng = np.random.default_rng(31)
+    I = rng.normal(100, 10, (H, W)).astype(np.float32)
+    V = rng.uniform(50, 150, (H, W)).astype(np.float32)
+    M = np.zeros((H, W), np.uint8)
+    M[20:23, 30] = 1
+    M[50, 5:9] = 4
+    I[M != 0] = np.nan
+    V[M != 0] = np.nan
+    a = rng.normal(0, 0.2, cfg.n_unknowns)
+    a[0] = 1.0
+    q = np.array([[0.1, 0.3, 0.05], [0.2, 1.0, 0.25], [0.0, 0.15, 0.1]])
+    Cin = signal.correlate2d(q, q, mode="full")[1:4, 1:4]
+    Cin = Cin / Cin[1, 1]
+    full, fm = O.convolve_image(cfg, a, I, M)
+    fvar, _, _ = O.propagate_variance(cfg, a, V, M, cov_in=Cin, c_in=1, c_out=2)
+    for rect in [(0, 0, W, H), (13, 7, 61, 50), (40, 33, W, H), (0, 45, 17, H), (70, 0, 71, 1)]:
+        x0, y0, x1, y1 = rect
+        out, om, var = O.convolve_region(cfg, a, I, V, M, rect, cov_in=Cin, c_in=1)
+        assert np.array_equal(out, full[y0:y1, x0:x1])
+        assert np.array_equal(om, fm[y0:y1, x0:x1])
+        assert np.array_equal(var, fvar[y0:y1, x0:x1])
+    # either plane alone
+    out, om, var = O.convolve_region(cfg, a, I, None, M, (13, 7, 61, 50))
+    assert var is None and np.array_equal(out, full[7:50, 13:61])
+    out, om, var = O.convolve_region(cfg, a, None, V, M, (13, 7, 61, 50), cov_in=Cin, c_in=1)
+    assert out is None and np.array_equal(var, fvar[7:50, 13:61])
+
+
+def _clip_problem(q_values, npix=100):
+    """Per-stamp sums with b_s = 0 and M_s = I: the solution is a = 0 and each
+    stamp's chi2 is e_s, so the clip statistic q_s = e_s / npix_s is set by
+    hand (small basis: N = 10 unknowns)."""
+    cfg = O.Config(sigmas=(0.8, 1.5), degrees=(2, 1), h=2, r=2, S=0, max_iter=3, min_stamps=3)
+    n = len(q_values)
+    L = cfg.n_basis + 1
+    fit = dict(M=np.repeat(np.eye(L)[None], n, axis=0), b=np.zeros((n, L)),
+               e=np.asarray(q_values, np.float64) * npix, npix=np.full(n, npix, np.int32),
+               flags=np.zeros(n, np.int32))
+    stamps = np.array([[10 + s, 10] for s in range(n)], np.int32)
+    return cfg, fit, stamps
+
+
+def test_clip_statistic_population_sigma_strict(orc):
+    """Rejection reading (Sections 3.3, 3.6): reject q_s > mean + 3 std with
+    the population std over the used stamps and a strict inequality.
+    Nine zeros and one 10: mean 1, population std 3, threshold exactly 10 --
+    the 10 is kept (a >= test would drop it).  Ten zeros and one 11: mean 1,
+    population std sqrt(10) = 3.162, threshold 10.49 < 11 -- dropped (the
+    sample std sqrt(11) = 3.317 would give 10.95 and still drop it); nine
+    zeros, one 1 and one 8: the population threshold 7.69 < 8 drops the 8,
+    while the sample std (threshold 8.02) would keep it."""
+    cfg, fit, st_xy = _clip_problem([0.0] * 9 + [10.0])
+    ret, a, chi2, fl, st = O.solve(cfg, 100, 100, st_xy, fit)
+    assert ret == 0 and np.all(a == 0) and st["n_iter"] == 1
+    assert st["n_rejected"] == 0 and not (fl & O.STAMP_REJECTED).any()
+    cfg, fit, st_xy = _clip_problem([0.0] * 10 + [11.0])
+    ret, a, chi2, fl, st = O.solve(cfg, 100, 100, st_xy, fit)
+    assert ret == 0 and st["n_rejected"] == 1 and fl[10] & O.STAMP_REJECTED
+    assert st["n_iter"] == 2                        # second solution changes nothing
+    qs = [0.0] * 9 + [1.0, 8.0]
+    m = np.mean(qs)
+    assert m + 3 * np.std(qs) < 8.0 < m + 3 * np.std(qs, ddof=1)
+    cfg, fit, st_xy = _clip_problem(qs)
+    ret, a, chi2, fl, st = O.solve(cfg, 100, 100, st_xy, fit)
+    assert ret == 0 and st["n_rejected"] == 1 and fl[10] & O.STAMP_REJECTED
+
+
+def test_clip_iterations_and_min_stamps(orc):
+    """A second-round clip (the threshold moves once the first outlier is
+    gone) is applied within the solution budget, and a clip that would leave
+    fewer than min_stamps stamps is not applied."""
+    qs = [1.0] * 12 + [3.0, 40.0]
+    cfg, fit, st_xy = _clip_problem(qs)
+    ret, a, chi2, fl, st = O.solve(cfg, 100, 100, st_xy, fit)
+    # round 1 drops the 40; round 2 (mean 1.15, std 0.53, threshold 2.74) drops the 3
+    assert ret == 0 and st["n_iter"] == 3 and st["n_rejected"] == 2
+    assert fl[12] & O.STAMP_REJECTED and fl[13] & O.STAMP_REJECTED
+    cfg1 = O.Config(**{**cfg.__dict__, "max_iter": 2})
+    ret, a, chi2, fl, st = O.solve(cfg1, 100, 100, st_xy, fit)
+    assert st["n_iter"] == 2 and st["n_rejected"] == 1 and not fl[12] & O.STAMP_REJECTED
+    cfg3 = O.Config(**{**cfg.__dict__, "min_stamps": 14})
+    ret, a, chi2, fl, st = O.solve(cfg3, 100, 100, st_xy, fit)
+    assert ret == 0 and st["n_rejected"] == 0 and st["n_used"] == 14
+
+
+def test_chi2_per_dof_is_lstsq_residual(orc):
+    """chi2/dof = |residual|^2 / (rows - N) of the stacked weighted
+    least-squares problem (Section 3.6 quality measure, no softening)."""
+    cfg, W, H, I1, I2, V2, Z = _tiny_problem(seed=8)
+    stamps = np.array([[6, 6], [7, 8], [5, 7]], np.int32)
+    fit = O.fit_stamps(cfg, I1, Z, I2, V2, Z, stamps)
+    cfg1 = O.Config(**{**cfg.__dict__, "max_iter": 1})
+    ret, a, chi2, fl, st = O.solve(cfg1, W, H, stamps, fit)
+    assert ret == 0
+    kb = O.basis(cfg)
+    Ai = [conv_same(I1.astype(np.float64), kb[i]) for i in range(cfg.n_basis)]
+    r = cfg.r
+    rows, rhs = [], []
+    for xc, yc in stamps:
+        sl = (slice(yc - r, yc + r + 1), slice(xc - r, xc + r + 1))
+        A = np.stack([x[sl].ravel() for x in Ai] + [np.ones((2 * r + 1) ** 2)], axis=1)
+        sw = 1.0 / np.sqrt(V2[sl].astype(np.float64).ravel())
+        rows.append(sw[:, None] * A)
+        rhs.append(sw * I2[sl].astype(np.float64).ravel())
+    A = np.vstack(rows)
+    d = np.concatenate(rhs)
+    ls, res, rank, _ = np.linalg.lstsq(A, d, rcond=None)
+    assert rank == cfg.n_unknowns
+    dof = A.shape[0] - cfg.n_unknowns
+    assert st["dof"] == dof == 3 * 25 - 10
+    assert abs(st["chi2"] - res[0]) < 1e-8 * res[0]
+    assert abs(st["chi2_dof"] - res[0] / dof) < 1e-8 * res[0] / dof
+
+
+def test_bad_radius_closed_forms(orc):
+    """BAD/POOR radius (Section 3.4) on kernels whose squared-weight profile is
+    known in closed form: a delta has radius 0; a flat (2h+1)^2 kernel keeps
+    ((2r+1)/(2h+1))^2 of its squared weight inside box r; a separable kernel
+    g(u) g(v) keeps F(r)^2, F the 1-D inside fraction of g^2 -- so the radius
+    is the smallest r with F(r)^2 > 0.8 (one-dimensional sums only)."""
+    h = 10
+    K = np.zeros((2 * h + 1, 2 * h + 1))
+    K[h, h] = 2.5
+    assert O.bad_radius(K, h, 0.2) == 0
+    K = np.full((2 * h + 1, 2 * h + 1), 0.3)
+    rb = min(r for r in range(h + 1) if (2 * r + 1) ** 2 > 0.8 * (2 * h + 1) ** 2)
+    assert rb == 9 and O.bad_radius(K, h, 0.2) == rb
+    assert O.bad_radius(K, h, 0.5) == min(r for r in range(h + 1)
+                                          if (2 * r + 1) ** 2 > 0.5 * (2 * h + 1) ** 2)
+    u = np.arange(-h, h + 1, dtype=np.float64)
+    for s in (0.7, 1.5, 3.0, 6.0):
+        g = np.exp(-u * u / (2 * s * s)) * (1 + 0.1 * u)
+        F = np.array([(g[h - r:h + r + 1] ** 2).sum() for r in range(h + 1)]) / (g ** 2).sum()
+        expect = next((r for r in range(h + 1) if F[r] ** 2 > 0.8), h)
+        assert O.bad_radius(np.outer(g, g), h, 0.2) == expect
+    # "drops below" is strict: exactly half of the squared weight outside box 0
+    # (centre 2, four neighbours 1: 4 of 8) does not meet a 0.5 fraction
+    K = np.zeros((2 * h + 1, 2 * h + 1))
+    K[h, h] = 2.0
+    K[h - 1, h] = K[h + 1, h] = K[h, h - 1] = K[h, h + 1] = 1.0
+    assert O.bad_radius(K, h, 0.5) == 1 and O.bad_radius(K, h, 0.5000001) == 0
+    # a Gaussian of sigma 3 needs a wider radius than one of sigma 0.7
+    assert O.bad_radius(np.outer(np.exp(-u * u / 18), np.exp(-u * u / 18)), h, 0.2) > \
+        O.bad_radius(np.outer(np.exp(-u * u / 0.98), np.exp(-u * u / 0.98)), h, 0.2)
