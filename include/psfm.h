@@ -354,6 +354,33 @@ int psfm_match_pair(const psfm_context* ctx, const double* coeffs, const float* 
                     void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * psfm_match_pair without a workspace argument.  Its scratch (covariance
+ * samples and per-tile variance sums) lives in a static device array of
+ * PSFM_STATIC_SCRATCH_BYTES on each device, held until the process ends;
+ * the call allocates nothing.  Arguments, results and errors are those of
+ * psfm_match_pair (bit-identical outputs, same kernels), plus
+ * PSFM_ERR_WORKSPACE, returned before anything is launched, when the image
+ * needs more scratch than the array holds: about 1 MB of covariance samples
+ * at h = 10 (1.6 MB at h = 16) plus 32 bytes per 64 x 64 output tile, i.e.
+ * images up to about 20000 x 20000 px at h = 10 with 64-px patches (smaller
+ * patches mean more tiles).  Every call on a device shares that device's
+ * array and leaves its contents behind: calls that overlap on one device
+ * (several streams or host threads) race and must be serialised by the
+ * caller.
+ */
+#define PSFM_STATIC_SCRATCH_BYTES ((size_t)4 << 20)
+int psfm_match_pair_static(const psfm_context* ctx, const double* coeffs, const float* I1,
+                           const float* V1, const uint8_t* M1, const float* I2, const float* V2,
+                           const uint8_t* M2, int W, int H, int64_t pitch, const double* cov1,
+                           int cov1_half, const double* cov2, int cov2_half, float* conv,
+                           uint8_t* conv_mask, float* conv_var, double* cov_conv,
+                           int cov_conv_half, float* diff, float* diff_var, uint8_t* diff_mask,
+                           double* cov_diff, int cov_diff_half, psfm_fit_stats* stats,
+                           void* stream);
+
+/*
  * Batched matching of many independent image pairs: the whole path of the
  * calls above (fit, solve with rejection, image and variance convolution,
  * covariance pseudo-matrix, difference) for every pair of a batch, with each

@@ -1167,14 +1167,16 @@ static void launch_match_tile(const PairDesc& p, const BasisArgs& B, int P, doub
     hipLaunchKernelGGL(k_match_tile<H_>, dim3(n_tiles), dim3(256), 0, st, p, B, P, bad_frac);
 }
 
-extern "C" int psfm_match_pair(const psfm_context* ctx, const double* coeffs, const float* I1,
-                               const float* V1, const uint8_t* M1, const float* I2, const float* V2,
-                               const uint8_t* M2, int W, int H, int64_t pitch, const double* cov1,
-                               int cov1_half, const double* cov2, int cov2_half, float* conv,
-                               uint8_t* conv_mask, float* conv_var, double* cov_conv,
-                               int cov_conv_half, float* diff, float* diff_var, uint8_t* diff_mask,
-                               double* cov_diff, int cov_diff_half, psfm_fit_stats* stats, void* ws,
-                               size_t ws_bytes, void* stream) {
+// psfm_match_pair with its scratch at `ws` (psfm_match_pair: the caller's
+// workspace; psfm_match_pair_static: the library's static device array).
+int psfm::match_pair_ws(const psfm_context* ctx, const double* coeffs, const float* I1,
+                        const float* V1, const uint8_t* M1, const float* I2, const float* V2,
+                        const uint8_t* M2, int W, int H, int64_t pitch, const double* cov1,
+                        int cov1_half, const double* cov2, int cov2_half, float* conv,
+                        uint8_t* conv_mask, float* conv_var, double* cov_conv, int cov_conv_half,
+                        float* diff, float* diff_var, uint8_t* diff_mask, double* cov_diff,
+                        int cov_diff_half, psfm_fit_stats* stats, void* ws, size_t ws_bytes,
+                        void* stream) {
     int rc = check_image_args(ctx, W, H, pitch);
     if (rc) return rc;
     if (!coeffs || !I1 || !V1 || !M1 || !I2 || !V2 || !M2 || !cov_conv || !diff || !diff_var ||
@@ -1228,4 +1230,18 @@ extern "C" int psfm_match_pair(const psfm_context* ctx, const double* coeffs, co
     PSFM_HIP_CHECK(hipGetLastError());
     return cov_pseudo(ctx, coeffs, W, H, cov1, cov1_half, cov_conv, cov_conv_half, stats, ws, st,
                       p.sub_part, n_tiles, cov2, cov2_half, cov_diff, cov_diff_half);
+}
+
+extern "C" int psfm_match_pair(const psfm_context* ctx, const double* coeffs, const float* I1,
+                               const float* V1, const uint8_t* M1, const float* I2, const float* V2,
+                               const uint8_t* M2, int W, int H, int64_t pitch, const double* cov1,
+                               int cov1_half, const double* cov2, int cov2_half, float* conv,
+                               uint8_t* conv_mask, float* conv_var, double* cov_conv,
+                               int cov_conv_half, float* diff, float* diff_var, uint8_t* diff_mask,
+                               double* cov_diff, int cov_diff_half, psfm_fit_stats* stats, void* ws,
+                               size_t ws_bytes, void* stream) {
+    return psfm::match_pair_ws(ctx, coeffs, I1, V1, M1, I2, V2, M2, W, H, pitch, cov1, cov1_half,
+                               cov2, cov2_half, conv, conv_mask, conv_var, cov_conv, cov_conv_half,
+                               diff, diff_var, diff_mask, cov_diff, cov_diff_half, stats, ws,
+                               ws_bytes, stream);
 }

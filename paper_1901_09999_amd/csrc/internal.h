@@ -147,6 +147,14 @@ size_t conv_workspace(const psfm_context* ctx, int W, int H);
 size_t subtract_workspace(const psfm_context* ctx, int W, int H);
 size_t match_workspace(const psfm_context* ctx, int W, int H);
 
+int match_pair_ws(const psfm_context* ctx, const double* coeffs, const float* I1, const float* V1,
+                  const uint8_t* M1, const float* I2, const float* V2, const uint8_t* M2, int W,
+                  int H, int64_t pitch, const double* cov1, int cov1_half, const double* cov2,
+                  int cov2_half, float* conv, uint8_t* conv_mask, float* conv_var,
+                  double* cov_conv, int cov_conv_half, float* diff, float* diff_var,
+                  uint8_t* diff_mask, double* cov_diff, int cov_diff_half, psfm_fit_stats* stats,
+                  void* ws, size_t ws_bytes, void* stream);
+
 int fit_bands(const psfm_context* ctx);
 int n_patches(const psfm_context* ctx, int W, int H);
 

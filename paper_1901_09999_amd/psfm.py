@@ -121,6 +121,8 @@ def lib():
                                   sz, P]),
             "psfm_match_pair": (i, [P, P, P, P, P, P, P, P, i, i, i64, P, i, P, i, P, P, P, P, i,
                                     P, P, P, P, i, P, P, sz, P]),
+            "psfm_match_pair_static": (i, [P, P, P, P, P, P, P, P, i, i, i64, P, i, P, i, P, P, P,
+                                           P, i, P, P, P, P, i, P, P]),
             "psfm_status_string": (C.c_char_p, [i]),
             "psfm_batch_workspace_bytes": (sz, [P, C.POINTER(CPair), i]),
             "psfm_batch_plan": (i, [P, C.POINTER(CPair), i, C.POINTER(CTuning), P, sz, P, P,
@@ -403,6 +405,32 @@ class Context:
                                      _ptr(ws), ws.numel(), _stream()), "psfm_match_pair")
         return dict(out, cov=cov_conv)
 
+    def match_static(self, coeffs, I1, V1, M1, I2, V2, M2, cov1=None, cov2=None, c_out=10,
+                     c_d=None, stats=None, out=None, cov_conv=None, conv=None, conv_mask=None,
+                     conv_var=None):
+        """psfm_match_pair_static: :meth:`match` with the library's static
+        device scratch instead of a workspace (the call allocates nothing when
+        every output is given)."""
+        H, W = I1.shape
+        c1 = 0 if cov1 is None else (cov1.shape[0] - 1) // 2
+        c2 = 0 if cov2 is None else (cov2.shape[0] - 1) // 2
+        cd = max(c_out, c2) if c_d is None else c_d
+        if cov_conv is None:
+            cov_conv = torch.empty((2 * c_out + 1, 2 * c_out + 1), dtype=torch.float64,
+                                   device=self.device)
+        if out is None:
+            out = dict(diff=torch.empty_like(I2), diff_var=torch.empty_like(V2),
+                       diff_mask=torch.empty_like(M2),
+                       cov_diff=torch.empty((2 * cd + 1, 2 * cd + 1), dtype=torch.float64,
+                                            device=self.device))
+        _check(lib().psfm_match_pair_static(
+            self._h, _ptr(coeffs), _ptr(I1), _ptr(V1), _ptr(M1), _ptr(I2), _ptr(V2), _ptr(M2), W,
+            H, W, _ptr(cov1), c1, _ptr(cov2), c2, _ptr(conv), _ptr(conv_mask), _ptr(conv_var),
+            _ptr(cov_conv), c_out, _ptr(out["diff"]), _ptr(out["diff_var"]),
+            _ptr(out["diff_mask"]), _ptr(out["cov_diff"]), cd, _ptr(stats), _stream()),
+            "psfm_match_pair_static")
+        return dict(out, cov=cov_conv)
+
     def match_pair(self, I1, V1, M1, I2, V2, M2, stamps, c_out=10, bufs=None):
         """The whole hot path: fit -> solve -> convolve -> variance -> subtract.
         ``bufs`` (from :meth:`alloc_pair`) avoids allocations in a timed loop."""
@@ -584,7 +612,7 @@ def exported_symbols() -> Sequence[str]:
             "psfm_n_unknowns", "psfm_stamp_dim", "psfm_workspace_bytes", "psfm_stamp_design_floats",
             "psfm_fit_stamps",
             "psfm_solve", "psfm_convolve_image", "psfm_propagate_variance", "psfm_convolve_pair",
-            "psfm_subtract", "psfm_match_pair",
+            "psfm_subtract", "psfm_match_pair", "psfm_match_pair_static",
             "psfm_status_string", "psfm_batch_workspace_bytes", "psfm_batch_plan",
             "psfm_batch_run", "psfm_batch_run_stage", "psfm_batch_set_tuning", "psfm_batch_graph_capture",
             "psfm_batch_graph_launch", "psfm_batch_destroy", "psfm_wall_clock_hz",
