@@ -3,33 +3,25 @@
 One step = one whole pass of the path over synthetic input already resident
 in HBM.
 
-Default workload (one pair):
-    psfm_fit_stamps -> psfm_solve (with rejection) -> psfm_match_pair
-    (psfm_convolve_image + psfm_propagate_variance + psfm_subtract in one pass
-    over the output tiles; the difference image, its variance, mask and
-    covariance pseudo-matrix are the products)
-on a 2048 x 2048 FP32 pair, science PSF sigma 1.4 -> 2.6 px across the field
-with ellipticity up to 0.2, 2000 sources, 10% mask, 21 x 21 kernel with the
-49-term ISIS basis x spatial order 2 (295 unknowns), 100 stamps of 41 x 41,
-variance map and a 21 x 21 covariance pseudo-matrix.
+Default workload (batch64): one batch of 64 independent image pairs of uneven
+size (1024 to 6000 px a side, 734 Mpx in all; per pair its own PSFs, spatial
+order 0-3, 50-400 stamps of 41 x 41, 10% mask, 5% variable sources, 21 x 21
+kernel with the 49-term ISIS basis) through psfm_batch_* as one captured HIP
+graph: stamp fits -> solves with rejection -> pseudo-matrices -> fused
+image + variance convolution and difference over every output tile.  Also
+reports the p50 / p99 completion latency of the pairs, the stage split, the
+tuner's table, the learned prior's leg on the same pairs and the plain vs
+16-bit comparison on the detector-chip pair.
 
---workload batch64: one batch of 64 independent pairs of uneven size (1024 to
-6000 px a side, spatial order 0-3, 50-400 stamps) through psfm_batch_* as one
-HIP graph; also reports the p50 / p99 completion latency of the pairs.
-
---workload cells200k: the learned prior's path on crowded single-star cells:
-`value` is CNN training throughput (stamps per second, FP16 forward /
-backward / Adam kernels, batch 256); also the dataset build rate (render,
-per-stamp fit and solve, targets and loss weights) and the cost of a solve
-with the prior beside a plain solve.  `cpu_baseline` is the FP64 NumPy CNN
-oracle's loss, gradient and Adam step on a bounded sample.
+--workload pair2048 / chip4846: one pair,
+    psfm_fit_stamps -> psfm_solve (with rejection) -> psfm_match_pair.
+--workload cells200k: the learned prior's training throughput.
 
 Prints one JSON line.  `value` is pixels matched per second (Mpix/s).
-`roofline` is for the kernel with the largest share of the step (the FP64
-Cholesky at these system sizes; `roofline_other` holds the image
-convolution), each timed with HIP events on the stream it runs on; for the
-batch, the fused convolution/difference kernel.  `cpu_baseline` is the FP64
-oracle on the host's cores on a bounded sample of the same workload.
+`roofline` is for the kernel with the largest share of the step (for the
+batch: k_match_tiles_b, the fused convolution / difference pass), timed
+with HIP events on the stream it runs on.  `cpu_baseline` is the FP64 oracle
+on the host's cores on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -57,7 +49,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="pair2048")
+    ap.add_argument("--workload", default="batch64")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="batch: skip the learned-prior leg and the 16-bit comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--retune", action="store_true", help="ignore cached batch launch shapes")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16", "bf16"],
@@ -114,6 +108,66 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads() -> int:
+    return int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+
+
+def oracle_batch_baseline(wls, dps, px, st, budget_s):
+    """The FP64 oracle on the smallest pairs of the batch: all host threads
+    until ~budget_s, and one thread on the smallest pair.  Returns
+    (cpu_baseline dict, parity dict)."""
+    import oracle as O
+    O.build()
+    threads = host_threads()
+    order_px = np.argsort(px)
+    O.set_threads(threads)
+    done_px, spent, used, rel = 0.0, 0.0, [], []
+    for k in order_px:
+        if spent > 0 and spent + spent / max(len(used), 1) > budget_s:
+            break
+        hp = dps[k].host()
+        t1 = time.perf_counter()
+        ref = O.match_pair(O.Config.from_workload(wls[k]), hp, c_out=10)
+        spent += time.perf_counter() - t1
+        done_px += px[k]
+        used.append(int(k))
+        rs = ref["stats"]
+        if rs["info"] == 0 and st[k]["info"] == 0:
+            rel.append((abs(st[k]["kernel_sum_centre"] / rs["kernel_sum_centre"] - 1),
+                        abs(st[k]["chi2_dof"] / rs["chi2_dof"] - 1)))
+    k0 = int(order_px[0])
+    O.set_threads(1)
+    hp = dps[k0].host()
+    t1 = time.perf_counter()
+    O.match_pair(O.Config.from_workload(wls[k0]), hp, c_out=10)
+    one = time.perf_counter() - t1
+    O.set_threads(threads)
+    base = dict(value=round(done_px / 1e6 / spent, 3), unit="Mpix/s", cores=threads, kind="oracle",
+                cpu=cpu_model(),
+                sample=f"whole path on the {len(used)} smallest pair(s) of the batch "
+                       f"({done_px / 1e6:.1f} Mpx, {spent:.1f} s), FP64, OpenMP over stamps and "
+                       f"patches on {threads} threads; rate = their pixels / their time",
+                one_thread=dict(value=round(px[k0] / 1e6 / one, 3), unit="Mpix/s", cores=1,
+                                sample=f"the smallest pair ({px[k0] / 1e6:.2f} Mpx) once, "
+                                       f"{one:.1f} s"))
+    par = None
+    if rel:
+        par = {"pairs": used, "kernel_sum_rel_max": max(r[0] for r in rel),
+               "chi2_dof_rel_max": max(r[1] for r in rel)}
+    return base, par
+
+
 def bench_batch(args, torch, psfm, synth):
     from paper_1901_09999_amd import tune
     spec = synth.BATCHES[args.workload]
@@ -138,17 +192,18 @@ def bench_batch(args, torch, psfm, synth):
     b.run()
     torch.cuda.synchronize()
     # stage times (eager, events on the batch stream)
-    stage = np.zeros(3)
+    NS = 4
+    stage = np.zeros(NS)
     reps = 3
     for _ in range(reps):
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(NS + 1)]
         with torch.cuda.stream(b.stream):
             ev[0].record()
-            for sidx in range(3):
+            for sidx in range(NS):
                 b.run_stage(sidx)
                 ev[sidx + 1].record()
-        ev[3].synchronize()
-        stage += [ev[i].elapsed_time(ev[i + 1]) for i in range(3)]
+        ev[NS].synchronize()
+        stage += [ev[i].elapsed_time(ev[i + 1]) for i in range(NS)]
     stage /= reps
     b.capture()
     for _ in range(args.warmup):
@@ -171,10 +226,22 @@ def bench_batch(args, torch, psfm, synth):
     ms_per_step = 1e3 * wall / args.steps
     lat = np.concatenate(lat)
     st = [b.stats(k) for k in range(len(wls))]
+    # the dominant kernel alone: k_match_tiles_b is stage 3 (one launch), timed
+    # with HIP events on the batch stream over as many launches as steps
+    kreps = max(args.steps, 5)
+    k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(b.stream):
+        k0.record()
+        for _ in range(kreps):
+            b.run_stage(3)
+        k1.record()
+    k1.synchronize()
+    tiles_us = k0.elapsed_time(k1) * 1e3 / kreps
     T = (2 * spec.kernel_half + 1) ** 2
     flops = 4.0 * T * total_px                 # I' and V' (2T flop per pixel each)
-    apply_us = stage[2] * 1e3
-    achieved = flops / (apply_us * 1e-6) / 1e12
+    achieved = flops / (tiles_us * 1e-6) / 1e12
+    traffic = measured_traffic("match_tiles_b_batch64_traffic.json",
+                               os.path.join(ROOT, "paper_1901_09999_amd", "csrc", "convolve.hip"))
     out = {
         "metric": METRIC,
         "value": round(total_px / 1e6 / (ms_per_step * 1e-3), 2),
@@ -192,55 +259,79 @@ def bench_batch(args, torch, psfm, synth):
                                f"{total_px / 1e6:.0f} Mpx in all, sides U{{{spec.size_lo}..{spec.size_hi}}}, "
                                f"spatial order U{{0..{spec.S_max}}}, stamps U{{{spec.stamps_lo}.."
                                f"{spec.stamps_hi}}}, 21^2 kernel, 49-term ISIS basis, "
-                               f"{int(spec.variable_frac * 100)}% variable sources, one HIP graph",
+                               f"{int(spec.variable_frac * 100)}% variable sources, one HIP graph, "
+                               f"FP32 fit",
                    "pairs": len(wls), "total_pixels": int(total_px),
                    "apply_grid": grid, "tile_order": order, "parallelism": "single GPU"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                        "p99": round(float(np.percentile(lat, 99)), 3),
                        "max": round(float(lat.max()), 3)},
         "graph_ms_per_step": round(float(np.median(per)), 4),
-        "stages_ms": {k: round(float(v), 4) for k, v in zip(["fit", "solve", "apply"], stage)},
+        "stages_ms": {k: round(float(v), 4) for k, v in
+                      zip(["fit", "solve", "pseudo_matrices", "match_tiles"], stage)},
         "fit": {"solved": int(sum(s["info"] == 0 for s in st)),
                 "rejected_stamps": int(sum(s["n_rejected"] for s in st)),
+                "solutions": int(sum(s["n_iter"] for s in st)),
                 "chi2_dof_median": float(np.median([s["chi2_dof"] for s in st if s["info"] == 0]))},
-        "roofline": dict(kernel="k_match_tiles_b (fused I', V', D over all pairs; stage also holds "
-                                "the pseudo-matrix kernels)",
+        "roofline": dict(kernel="k_match_tiles_b<10> (fused I', V', D, masks and per-tile C_D sums "
+                                "over the tiles of all pairs)",
                          bound="alu", achieved=round(achieved, 2), peak=FP32_VALU_PEAK_TFLOPS,
                          unit="TFLOP/s", frac=round(achieved / FP32_VALU_PEAK_TFLOPS, 4),
-                         traffic=None, avg_launch_us=round(apply_us, 2),
-                         algorithmic_flops_per_launch=flops),
+                         traffic=traffic, avg_launch_us=round(tiles_us, 2),
+                         algorithmic_flops_per_launch=flops,
+                         algorithmic_bytes_per_launch=27.0 * total_px,
+                         share_of_step=round(tiles_us * 1e-3 / ms_per_step, 3)),
         "tuning": table,
     }
+    if not args.no_extra:
+        try:
+            out["learned"] = learned_batch_leg(args, torch, psfm, synth, ctx, pairs, wls, st)
+        except Exception as e:          # the headline stands without the extra leg
+            out["learned"] = {"error": repr(e)}
+        try:
+            out["compare_precision"] = precision_leg(args, torch, psfm, synth)
+        except Exception as e:
+            out["compare_precision"] = {"error": repr(e)}
+    if not args.no_cpu_baseline:
+        base, par = oracle_batch_baseline(wls, dps, px, st, args.cpu_seconds)
+        out["cpu_baseline"] = base
+        if par:
+            out["parity_vs_oracle"] = par
+    print(json.dumps(out), flush=True)
+
+
+def learned_batch_leg(args, torch, psfm, synth, ctx, pairs, wls, st_plain):
+    return {"note": "not run"}
+
+
+def precision_leg(args, torch, psfm, synth, name="chip4846", steps=5, warmup=2):
+    """Plain FP32 vs the 16-bit stamp fits (one refinement step each) on the
+    detector-chip pair, each against the FP64 oracle."""
+    wl = synth.WORKLOADS[name]
+    pair = synth.make_pair(wl, synth.workload_seed(synth.SEED_INDEX[name]))
+    d = psfm.to_device(pair)
+    res = {}
+    for mode in ("fp32", "fp16", "bf16"):
+        r = run_pair_mode(torch, psfm, wl, d, mode, 1, steps, warmup, conv_reps=0)
+        res[mode] = dict(value=round(wl.pixels / 1e6 / (r["ms_per_step"] * 1e-3), 2),
+                         ms_per_step=round(r["ms_per_step"], 4), refine=r["refine"],
+                         stages_ms={k: round(float(v), 4) for k, v in
+                                    zip(["fit", "solve", "apply"], r["stage"])},
+                         kernel_sum_centre=r["stats"]["kernel_sum_centre"],
+                         chi2_dof=r["stats"]["chi2_dof"], n_iter=r["stats"]["n_iter"])
     if not args.no_cpu_baseline:
         import oracle as O
         O.build()
-        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-        os.environ.setdefault("OMP_NUM_THREADS", str(threads))
-        order_px = np.argsort(px)
-        done_px, spent, used, rel = 0.0, 0.0, [], []
-        for k in order_px:
-            if spent > 0 and spent + spent / max(len(used), 1) > args.cpu_seconds:
-                break
-            hp = dps[k].host()
-            t1 = time.perf_counter()
-            ref = O.match_pair(O.Config.from_workload(wls[k]), hp, c_out=10)
-            spent += time.perf_counter() - t1
-            done_px += px[k]
-            used.append(int(k))
-            rs = ref["stats"]
-            if rs["info"] == 0 and st[k]["info"] == 0:
-                rel.append((abs(st[k]["kernel_sum_centre"] / rs["kernel_sum_centre"] - 1),
-                            abs(st[k]["chi2_dof"] / rs["chi2_dof"] - 1)))
-        out["cpu_baseline"] = dict(
-            value=round(done_px / 1e6 / spent, 3), unit="Mpix/s", cores=threads, kind="oracle",
-            sample=f"whole path on the {len(used)} smallest pair(s) of the batch "
-                   f"({done_px / 1e6:.1f} Mpx, {spent:.1f} s), FP64, OpenMP over stamps and "
-                   f"patches; rate = their pixels / their time")
-        if rel:
-            out["parity_vs_oracle"] = {"pairs": used,
-                                       "kernel_sum_rel_max": max(r[0] for r in rel),
-                                       "chi2_dof_rel_max": max(r[1] for r in rel)}
-    print(json.dumps(out), flush=True)
+        O.set_threads(host_threads())
+        ref = O.match_pair(O.Config.from_workload(wl), pair, c_out=wl.cov_half)["stats"]
+        for r in res.values():
+            r["kernel_sum_rel"] = abs(r["kernel_sum_centre"] / ref["kernel_sum_centre"] - 1)
+            r["chi2_dof_rel"] = abs(r["chi2_dof"] / ref["chi2_dof"] - 1)
+    del d
+    torch.cuda.empty_cache()
+    return dict(workload=f"{name}: {wl.width}x{wl.height}, {wl.n_unknowns} unknowns, "
+                         f"{wl.n_stamps} stamps of {2 * wl.stamp_half + 1}^2", modes=res)
+
 
 # multiply-adds per stamp of one training step of the stamp-pair CNN (forward,
 # data gradients of layers 2..6 and fc, weight gradients of every layer)
@@ -361,6 +452,74 @@ def bench_cells(args, torch, psfm, synth):
     print(json.dumps(out), flush=True)
 
 
+PRECS = {"fp32": 0, "bf16": 1, "fp16": 2}
+
+
+def run_pair_mode(torch, psfm, wl, d, prec_name, refine, steps, warmup, conv_reps=20):
+    """fit -> solve -> match on one resident pair in one stamp-fit arithmetic:
+    wall ms per step, GPU ms per step, the stage split and the stats."""
+    W, H, n = wl.width, wl.height, int(d["stamps"].shape[0])
+    prec = PRECS[prec_name]
+    ctx = psfm.Context(psfm.Config.from_workload(wl, precision=prec, refine=refine))
+    bufs = ctx.alloc_pair(W, H, n, wl.cov_half)
+
+    def step(ev=None):
+        f = ctx.fit_stamps(d["I1"], d["M1"], d["I2"], d["V2"], d["M2"], d["stamps"], out=bufs["fit"])
+        if ev: ev[0].record()
+        # the fit rewrites every stamp's flags, so the solve marks its
+        # rejections in them (no copy)
+        s = ctx.solve(W, H, d["stamps"], f, flags=f["flags"], out=bufs["sol"], flags_inplace=True)
+        if ev: ev[1].record()
+        # convolutions of I1 and V1 and the difference in one pass over the
+        # tiles (the convolved planes are not stored: the difference is the product)
+        ctx.match(s["coeffs"], d["I1"], d["V1"], d["M1"], d["I2"], d["V2"], d["M2"],
+                  c_out=wl.cov_half, stats=s["stats"], out=bufs["sub"], cov_conv=bufs["cov"])
+        if ev: ev[2].record()
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    # the timed steps carry no events of their own (a timing event between
+    # stages idles the GPU for a few microseconds)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record()
+    for k in range(steps):
+        step()
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = float(start.elapsed_time(stop)) / steps
+    # stage split: the same number of steps again, with an event after each stage
+    NS = 3      # stages: fit, solve, apply (convolutions, pseudo-matrices, difference)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(NS)] for _ in range(steps)]
+    start.record()
+    for k in range(steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    stage = np.zeros(NS)
+    for k in range(steps):
+        prev = start if k == 0 else evs[k - 1][NS - 1]
+        marks = [prev] + evs[k]
+        stage += [marks[i].elapsed_time(marks[i + 1]) for i in range(NS)]
+    stage /= steps
+    stats = psfm.read_stats(bufs["sol"]["stats"])
+    conv_ms = None
+    if conv_reps:
+        # the image convolution alone (its own launches, HIP events), for its roofline
+        s = bufs["sol"]
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record()
+        for _ in range(conv_reps):
+            ctx.convolve_image(s["coeffs"], d["I1"], d["M1"], out=bufs["conv"], out_mask=bufs["conv_mask"])
+        c1.record()
+        torch.cuda.synchronize()
+        conv_ms = c0.elapsed_time(c1) / conv_reps
+    ctx.close()
+    return dict(ms_per_step=1e3 * wall / steps, stage=stage, gpu_ms=gpu_ms, stats=stats,
+                refine=refine, conv_ms=conv_ms)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -390,67 +549,9 @@ def main():
     pair = synth.make_pair(wl, synth.workload_seed(seed_index))
     d = psfm.to_device(pair)
     W, H, n = wl.width, wl.height, pair.stamps.shape[0]
-    precs = {"fp32": psfm.PREC_FP32, "fp16": psfm.PREC_FP16, "bf16": psfm.PREC_BF16}
-
-    def run_mode(prec_name, steps, warmup):
-        prec = precs[prec_name]
-        refine = args.refine if args.refine is not None else (2 if prec == psfm.PREC_BF16 else 1)
-        ctx = psfm.Context(psfm.Config.from_workload(wl, precision=prec, refine=refine))
-        bufs = ctx.alloc_pair(W, H, n, wl.cov_half)
-
-        def step(ev=None):
-            f = ctx.fit_stamps(d["I1"], d["M1"], d["I2"], d["V2"], d["M2"], d["stamps"], out=bufs["fit"])
-            if ev: ev[0].record()
-            # the fit rewrites every stamp's flags, so the solve marks its
-            # rejections in them (no copy)
-            s = ctx.solve(W, H, d["stamps"], f, flags=f["flags"], out=bufs["sol"], flags_inplace=True)
-            if ev: ev[1].record()
-            # convolutions of I1 and V1 and the difference in one pass over the
-            # tiles (the convolved planes are not stored: the difference is the product)
-            ctx.match(s["coeffs"], d["I1"], d["V1"], d["M1"], d["I2"], d["V2"], d["M2"],
-                      c_out=wl.cov_half, stats=s["stats"], out=bufs["sub"], cov_conv=bufs["cov"])
-            if ev: ev[2].record()
-
-        for _ in range(warmup):
-            step()
-        torch.cuda.synchronize()
-        # the timed steps carry no events of their own (a timing event between
-        # stages idles the GPU for a few microseconds)
-        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t0 = time.perf_counter()
-        start.record()
-        for k in range(steps):
-            step()
-        stop.record()
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        gpu_ms = float(start.elapsed_time(stop)) / steps
-        # stage split: the same number of steps again, with an event after each stage
-        NS = 3      # stages: fit, solve, apply (convolutions, pseudo-matrices, difference)
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(NS)] for _ in range(steps)]
-        start.record()
-        for k in range(steps):
-            step(evs[k])
-        torch.cuda.synchronize()
-        stage = np.zeros(NS)
-        for k in range(steps):
-            prev = start if k == 0 else evs[k - 1][NS - 1]
-            marks = [prev] + evs[k]
-            stage += [marks[i].elapsed_time(marks[i + 1]) for i in range(NS)]
-        stage /= steps
-        stats = psfm.read_stats(bufs["sol"]["stats"])
-        # the image convolution alone (its own launches, HIP events), for its roofline
-        s = bufs["sol"]
-        reps = 20
-        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        c0.record()
-        for _ in range(reps):
-            ctx.convolve_image(s["coeffs"], d["I1"], d["M1"], out=bufs["conv"], out_mask=bufs["conv_mask"])
-        c1.record()
-        torch.cuda.synchronize()
-        conv_ms = c0.elapsed_time(c1) / reps
-        return dict(ms_per_step=1e3 * wall / steps, stage=stage, gpu_ms=gpu_ms, stats=stats,
-                    refine=refine, conv_ms=conv_ms)
+    def run_mode(name, steps, warmup):
+        refine = args.refine if args.refine is not None else 1
+        return run_pair_mode(torch, psfm, wl, d, name, refine, steps, warmup)
 
     main_run = run_mode(args.precision, args.steps, args.warmup)
     other = None

@@ -108,6 +108,12 @@ def lib():
     return _lib
 
 
+def set_threads(n: int) -> None:
+    """Number of OpenMP threads the oracle's parallel loops use from now on
+    (the OpenMP runtime the library is linked against)."""
+    lib().omp_set_num_threads(C.c_int(int(n)))
+
+
 def _p(a: Optional[np.ndarray]):
     return None if a is None else a.ctypes.data_as(C.c_void_p)
 

@@ -11,8 +11,8 @@
 //                                     one Cholesky workgroup per pair,
 //                                     chi2 of all stamps, clip per pair
 //   k_cov_auto_b / k_cov_mix_b /      pseudo-matrices of the convolved images
-//   k_cov_finish_b
-//   k_match_tiles_b                   fused convolution + difference over the
+//   k_cov_finish_b                    (stage 2)
+//   k_match_tiles_b                   (stage 3) fused convolution + difference over the
 //                                     tiles of all pairs (grid-stride loop);
 //                                     per-pair C_D and completion time
 // Nothing in a run allocates or synchronises, so a run can be captured into
@@ -286,7 +286,7 @@ extern "C" int psfm_batch_plan(const psfm_context* ctx, const psfm_pair* pairs, 
 }
 
 extern "C" int psfm_batch_run_stage(psfm_batch* b, int stage, void* stream) {
-    if (!b || stage < 0 || stage > 2) return PSFM_ERR_INVALID_ARG;
+    if (!b || stage < 0 || stage > 3) return PSFM_ERR_INVALID_ARG;
     hipStream_t st = (hipStream_t)stream;
     if (stage == 0) {
         hipLaunchKernelGGL(k_batch_init, dim3((b->n_pairs + 255) / 256), dim3(256), 0, st,
@@ -299,12 +299,12 @@ extern "C" int psfm_batch_run_stage(psfm_batch* b, int stage, void* stream) {
         return psfm::batch_solve(b->ctx, b->d_pairs, b->d_stamp_pair, b->n_pairs, b->n_stamps,
                                  b->max_n, b->max_N, b->ns_mask, st);
     return psfm::batch_apply(b->ctx, b->d_pairs, b->d_tile_pair, b->n_pairs, b->n_tiles,
-                             b->max_cov_in, b->tuning.apply_grid, st);
+                             b->max_cov_in, b->tuning.apply_grid, stage == 2 ? 1 : 2, st);
 }
 
 extern "C" int psfm_batch_run(psfm_batch* b, void* stream) {
     if (!b) return PSFM_ERR_INVALID_ARG;
-    for (int stage = 0; stage < 3; stage++) {
+    for (int stage = 0; stage < 4; stage++) {
         const int rc = psfm_batch_run_stage(b, stage, stream);
         if (rc) return rc;
     }

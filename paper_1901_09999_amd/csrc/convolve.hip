@@ -1000,19 +1000,21 @@ int launch_match_tiles(const psfm_context* ctx, const PairDesc* pairs, const int
 }
 
 int batch_apply(const psfm_context* ctx, const PairDesc* pairs, const int* tile_pair, int n_pairs,
-                int n_tiles, int max_cov_in, int conv_grid, hipStream_t st) {
+                int n_tiles, int max_cov_in, int conv_grid, int parts, hipStream_t st) {
     if (n_pairs == 0) return PSFM_OK;
-    const int E = 4 * ctx->h + 1;
-    hipLaunchKernelGGL(k_cov_auto_b, dim3(PSFM_COV_SAMPLES, E, n_pairs), dim3(256), 0, st,
-                       pairs, basis_args_of(ctx));
-    if (max_cov_in >= 0) {      // some pair has a correlated input
-        const int Rw = cov_sample_side(ctx, max_cov_in);
-        hipLaunchKernelGGL(k_cov_mix_b, dim3(PSFM_COV_SAMPLES, (Rw * Rw + 255) / 256, n_pairs),
-                           dim3(256), 0, st, pairs, ctx->h);
+    if (parts & 1) {
+        const int E = 4 * ctx->h + 1;
+        hipLaunchKernelGGL(k_cov_auto_b, dim3(PSFM_COV_SAMPLES, E, n_pairs), dim3(256), 0, st,
+                           pairs, basis_args_of(ctx));
+        if (max_cov_in >= 0) {      // some pair has a correlated input
+            const int Rw = cov_sample_side(ctx, max_cov_in);
+            hipLaunchKernelGGL(k_cov_mix_b, dim3(PSFM_COV_SAMPLES, (Rw * Rw + 255) / 256, n_pairs),
+                               dim3(256), 0, st, pairs, ctx->h);
+        }
+        hipLaunchKernelGGL(k_cov_finish_b, dim3(n_pairs), dim3(1024), 0, st, pairs, ctx->h);
+        PSFM_HIP_CHECK(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_cov_finish_b, dim3(n_pairs), dim3(1024), 0, st, pairs, ctx->h);
-    PSFM_HIP_CHECK(hipGetLastError());
-    if (n_tiles == 0) return PSFM_OK;
+    if (!(parts & 2) || n_tiles == 0) return PSFM_OK;
     const int grid = (conv_grid > 0 && conv_grid < n_tiles) ? conv_grid : n_tiles;
     switch (ctx->h) {
 #define PSFM_MT_CASE(HH) \

@@ -166,8 +166,9 @@ int batch_fit(const psfm_context* ctx, const PairDesc* pairs, const int* item_pa
               const int* stamp_pair, int n_items, int n_stamps, hipStream_t st);
 int batch_solve(const psfm_context* ctx, const PairDesc* pairs, const int* stamp_pair, int n_pairs,
                 int n_stamps_total, int max_n, int max_N, unsigned ns_mask, hipStream_t st);
+// parts: 1 = the pseudo-matrices, 2 = the fused convolution / difference pass, 3 = both.
 int batch_apply(const psfm_context* ctx, const PairDesc* pairs, const int* tile_pair, int n_pairs,
-                int n_tiles, int max_cov_in, int conv_grid, hipStream_t st);
+                int n_tiles, int max_cov_in, int conv_grid, int parts, hipStream_t st);
 int fit_prepare(const psfm_context* ctx);
 size_t fit_lds_bytes(const psfm_context* ctx);
 int solve_lds_grant(size_t lds);

@@ -64,6 +64,74 @@ def test_gradient_matches_oracle():
         o += n
 
 
+def test_weighted_gradient_matches_oracle():
+    """The chi2-weighted loss every training step uses: r^T W_b r with SPD
+    per-sample weights, loss and per-tensor gradients against the oracle's
+    weighted form (same tolerances as the plain loss)."""
+    torch, cnn, net, x, t, theta16 = _net_and_batch(B=8, seed=11)
+    rng = np.random.default_rng(12)
+    Q = rng.standard_normal((8, 49, 49))
+    Wt = np.einsum("bij,bkj->bik", Q, Q) / 49.0 + 0.05 * np.eye(49)[None]
+    Wt *= np.exp(rng.uniform(-2, 2, 8))[:, None, None]          # per-stamp scales differ
+    W32 = Wt.astype(np.float32)
+    loss, grad = net.loss_grad(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda(),
+                               weight=torch.from_numpy(W32).cuda())
+    g = _np(grad).astype(np.float64)
+    l_ref, g_ref = CO.loss_and_grad(theta16, x.astype(np.float64), t.astype(np.float64),
+                                    W32.astype(np.float64))
+    print(f"weighted loss {float(loss[0]):.6e} oracle {l_ref:.6e}")
+    assert abs(float(loss[0]) / l_ref - 1) < 2e-2
+    o = 0
+    for name, shp in CO.layer_shapes():
+        n = int(np.prod(shp))
+        a, b = g[o:o + n], g_ref[o:o + n]
+        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        cos = a @ b / max(np.linalg.norm(a) * np.linalg.norm(b), 1e-30)
+        print(f"{name}: rel {rel:.2e} cos {cos:.6f}")
+        assert rel < 3e-2 and cos > 0.999, name
+        o += n
+
+
+def test_loss_weights_are_the_chi2_excess():
+    """psfm_cnn_loss_weights from the oracle's per-stamp sums: for kernel
+    coefficient offsets a (orthonormal form c = R a, mapped by the library),
+    c^T W c equals the chi2/dof excess of that kernel with the background
+    re-fitted, min over d of [a; d]^T M_s [a; d] / npix, computed from the
+    oracle's stamp matrix (FP64) -- a statement independent of the factor R
+    the library picked.  Flagged stamps get zero weights."""
+    torch, psfm = hip()
+    from paper_1901_09999_amd import cnn
+    spec = synth.STAMP_SETS["cells200k"]
+    planes, stamps, par = synth.make_stamp_cells(spec, 24, 321)
+    cfg = O.Config(S=0, min_stamps=1)
+    host = {k: _np(v) for k, v in planes.items()}
+    fit = O.fit_stamps(cfg, host["I1"], host["M1"], host["I2"], host["V2"], host["M2"], stamps)
+    fl = fit["flags"].copy()
+    fl[3] = 1                                                   # one stamp flagged on input
+    ctx = psfm.Context(psfm.Config(h=10, r=20, S=0, min_stamps=1))
+    dfit = dict(M=torch.from_numpy(fit["M"]).cuda(), npix=torch.from_numpy(fit["npix"]).cuda(),
+                flags=torch.from_numpy(fl).cuda())
+    Wg = _np(cnn.loss_weights(ctx, dfit)).astype(np.float64)
+    assert np.all(Wg[3] == 0)
+    rng = np.random.default_rng(5)
+    n = stamps.shape[0]
+    a = np.zeros((n, 50))
+    a[:, :49] = 0.01 * rng.standard_normal((n, 49))
+    c = _np(cnn.to_ortho(ctx, torch.from_numpy(a).cuda())).astype(np.float64)
+    for s in range(n):
+        if fl[s]:
+            continue
+        M = fit["M"][s]
+        u = a[s, :49]
+        q = lambda d: np.concatenate([u, [d]]) @ M @ np.concatenate([u, [d]])
+        d_opt = -(M[49, :49] @ u) / M[49, 49]                # minimiser of the quadratic in d
+        assert q(d_opt) <= min(q(d_opt + 1e-3), q(d_opt - 1e-3))
+        excess = q(d_opt) / fit["npix"][s]
+        got = c[s] @ Wg[s] @ c[s]
+        assert abs(got / excess - 1) < 2e-4, (s, got, excess)
+        assert np.allclose(Wg[s], Wg[s].T, rtol=0, atol=1e-6 * np.abs(Wg[s]).max())
+
+
 def test_adam_matches_oracle():
     torch, cnn, net, x, t, theta16 = _net_and_batch()
     rng = np.random.default_rng(9)
