@@ -54,6 +54,9 @@ def parse():
                     help="batch: skip the learned-prior leg and the 16-bit comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--retune", action="store_true", help="ignore cached batch launch shapes")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="batch: skip the launch-shape search (one workgroup per tile, smallest "
+                         "pair first; for profiling runs)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16", "bf16"],
                     help="arithmetic of the stamp fit for the reported value")
     ap.add_argument("--refine", type=int, default=None, help="refinement steps of 16-bit modes")
@@ -186,7 +189,10 @@ def bench_batch(args, torch, psfm, synth):
     pairs = [dict(I1=d.I1, V1=d.V1, M1=d.M1, I2=d.I2, V2=d.V2, M2=d.M2,
                   stamps=torch.from_numpy(d.stamps.astype(np.int32)).cuda(),
                   S=d.workload.spatial_order) for d in dps]
-    grid, order, table = tune.choose(ctx, pairs, c_out=10, log=log, use_cache=not args.retune)
+    if args.no_tune:
+        grid, order, table = 0, 1, []
+    else:
+        grid, order, table = tune.choose(ctx, pairs, c_out=10, log=log, use_cache=not args.retune)
     log(f"tuned: apply_grid {grid}, order {order}")
     b = psfm.Batch(ctx, pairs, c_out=10, apply_grid=grid, order=order)
     b.run()
