@@ -141,8 +141,10 @@ typedef struct psfm_fit_stats {
     int n_iter;                /* solutions computed */
     int info;                  /* 0 ok; k > 0: pivot k not positive; -3: too few stamps */
     double chi2_dof_prior;     /* psfm_solve_prior: chi2/dof of the kept stamps at the warm start */
-    int n_prior;               /* psfm_solve_prior: stamps the prior excluded (after fallback) */
-    int n_restored;            /* psfm_solve_prior: excluded stamps the solution brought back */
+    int n_prior;               /* psfm_solve_prior: stamps left excluded by the prior in the answer */
+    int n_restored;            /* psfm_solve_prior: excluded stamps the solution found within the clip */
+    int n_trusted;             /* psfm_solve_prior: predictions kept by the 1.05x rule */
+    int prior_fallback;        /* psfm_solve_prior: 1 if the full method was rerun (prior void) */
 } psfm_fit_stats;
 
 typedef struct psfm_context psfm_context;
@@ -244,23 +246,29 @@ int psfm_solve_stamps(const psfm_context* ctx, int n_stamps, const double* stamp
  * psfm_solve with a learned prior: stamp_pred (n x L float64, kernel terms;
  * the background slot is ignored) holds per-stamp predicted local kernel
  * coefficients.  Before the first solution
- *   - each prediction is completed with its best background;
- *   - warm start a0: the spatial polynomial of each term fitted to the kept
- *     predictions;
- *   - rejection prior: a variable source shows as a predicted kernel sum (its
- *     own flux ratio) far from a0's kernel sum at the stamp; departures
- *     d = k_pred / k_a0 - 1 beyond max(5 robust sigma, 20%) about their
- *     median (robust sigma = 1.4826 x median absolute deviation, kept
- *     stamps) get PSFM_STAMP_PRIOR and are left out of the equations; a0 is
- *     refitted and the clip repeated (at most max_iter + 1 rounds, no solve
- *     needed);
+ *   - each prediction is completed with its best background and its residual
+ *     chi2 compared with that of the stamp's own least-squares kernel (the
+ *     solved value, an L x L FP64 Cholesky per stamp): where the prediction's
+ *     chi2 exceeds 1.05x the solved value, the least-squares kernel replaces
+ *     it (stats->n_trusted: predictions kept);
+ *   - warm start a0: the spatial polynomial of each term fitted to these
+ *     per-stamp kernels;
+ *   - rejection prior: a variable source shows as a per-stamp kernel sum (its
+ *     own flux ratio) far from a0's kernel sum at the stamp, on a stamp that
+ *     a0 does not fit; a stamp whose departure d = k_s / k_a0 - 1 lies beyond
+ *     max(5 robust sigma, 20%) about the median departure (robust sigma = 1.4826 x
+ *     median absolute deviation) and whose chi2_s / npix_s at a0 exceeds the
+ *     method's clip threshold there gets PSFM_STAMP_PRIOR and is left out of
+ *     the equations; a0 is refitted and the clip repeated (at most
+ *     max_iter + 1 rounds, no solve needed);
  *   - stats->chi2_dof_prior: chi2/dof of the kept stamps at a0.
- * The solve and rejection loop of psfm_solve then runs as usual.  Fallback:
- * an excluded stamp whose chi2_s / npix_s at the solution lies within the
- * method's clip threshold is restored, and the rejection loop resumes from
- * the restored set (up to max_iter more solutions), so the least-squares
- * solution and the method's own clip have the final word.  Same arguments as
- * psfm_solve.
+ * The solve and rejection loop of psfm_solve then runs on the kept stamps.
+ * The least-squares solution is the judge: if any excluded stamp's
+ * chi2_s / npix_s at the final solution lies within the method's clip
+ * threshold, or the prior path failed, the exclusions are void and
+ * psfm_solve's loop reruns from the complete stamp set with a fresh budget
+ * (stats->prior_fallback = 1): the answer is then psfm_solve's.  Needs
+ * L <= 64.  Same arguments as psfm_solve.
  */
 int psfm_solve_prior(const psfm_context* ctx, int W, int H, const int32_t* stamp_xy, int n_stamps,
                      const double* stamp_M, const double* stamp_b, const double* stamp_e,

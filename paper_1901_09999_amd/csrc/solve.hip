@@ -1229,6 +1229,8 @@ __device__ void solve_finish_body(int n, int ns, int N, int S, int W, int H,
         stats->chi2_dof_prior = 0.0;
         stats->n_prior = 0;
         stats->n_restored = 0;
+        stats->n_trusted = 0;
+        stats->prior_fallback = 0;
     }
 }
 
@@ -1238,6 +1240,8 @@ __global__ void k_prior_finish(const double* __restrict__ pdof, const int* __res
         stats->chi2_dof_prior = *pdof;
         stats->n_prior = counts[0];
         stats->n_restored = counts[1];
+        stats->n_trusted = counts[2];
+        stats->prior_fallback = counts[3];
     }
 }
 
@@ -1379,6 +1383,37 @@ __global__ __launch_bounds__(64) void k_prior_chi2(int nb, const double* __restr
     if (lane == 0) chi2p[s] = es[s] + part;
 }
 
+// The 1.05x rule, per stamp: a stamp's predicted kernel is kept only if its
+// residual chi2 (background re-fitted) is within PRIOR_TRUST of the residual
+// of the stamp's own least-squares kernel (the solved value, from
+// k_solve_stamps); otherwise the least-squares kernel replaces the
+// prediction.  has[s] = 1 for every stamp with a kernel estimate (usable and
+// a positive definite own system), counts[2] = predictions kept.
+constexpr double PRIOR_TRUST = 1.05;
+
+__global__ __launch_bounds__(1024) void k_prior_trust(int n, int L, const int32_t* __restrict__ flags,
+                                                      double* __restrict__ alpha,
+                                                      double* __restrict__ chi2_pred,
+                                                      const double* __restrict__ local_ls,
+                                                      const double* __restrict__ chi2_ls,
+                                                      uint8_t* __restrict__ has,
+                                                      int* __restrict__ counts) {
+    __shared__ double red[16];
+    double kept = 0.0;
+    for (int s = threadIdx.x; s < n; s += blockDim.x) {
+        const bool ok = flags[s] == 0 && chi2_ls[s] >= 0.0;
+        const bool keep = ok && chi2_pred[s] <= PRIOR_TRUST * chi2_ls[s];
+        if (ok && !keep) {
+            for (int i = 0; i < L; i++) alpha[(size_t)s * L + i] = local_ls[(size_t)s * L + i];
+            chi2_pred[s] = chi2_ls[s];
+        }
+        has[s] = ok;
+        kept += keep ? 1.0 : 0.0;
+    }
+    kept = psfm_block_sum(kept, red);
+    if (threadIdx.x == 0) counts[2] = (int)kept;
+}
+
 // Warm start a0 of the prior: per kernel term, the spatial polynomial
 // fitted (least squares, FP64) to the completed per-stamp predictions of
 // the stamps in use; the background as their mean.  One workgroup.
@@ -1386,8 +1421,8 @@ constexpr int PRIOR_T = 1024;
 
 __global__ __launch_bounds__(PRIOR_T) void k_prior_warm(
     int n, int nb, int ns, int N, const double* __restrict__ G,
-    const double* __restrict__ alpha, const uint8_t* __restrict__ used, double* __restrict__ a0,
-    const SolveState* st, int force) {
+    const double* __restrict__ alpha, const uint8_t* __restrict__ used,
+    const uint8_t* __restrict__ trust, double* __restrict__ a0, const SolveState* st, int force) {
     __shared__ double Gm[28 * 28];
     __shared__ double rhs[64 * 28];
     __shared__ int s_ok;
@@ -1407,13 +1442,13 @@ __global__ __launch_bounds__(PRIOR_T) void k_prior_warm(
                 const int ss = s + u;
                 const double* g = G + (size_t)ss * ns;    // spatial terms at the stamp centre
                 const double v = isG ? g[r0] : alpha[(size_t)ss * L + r0];
-                a4[u] += used[ss] ? v * g[q] : 0.0;
+                a4[u] += (used[ss] && trust[ss]) ? v * g[q] : 0.0;
             }
         }
         for (; s < n; s++) {
             const double* g = G + (size_t)s * ns;
             const double v = isG ? g[r0] : alpha[(size_t)s * L + r0];
-            a4[0] += used[s] ? v * g[q] : 0.0;
+            a4[0] += (used[s] && trust[s]) ? v * g[q] : 0.0;
         }
         const double acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
         if (isG) Gm[e] = acc;
@@ -1458,7 +1493,7 @@ __global__ __launch_bounds__(PRIOR_T) void k_prior_warm(
     __shared__ double red[16];
     double sbg = 0.0, c = 0.0;
     for (int s = tid; s < n; s += PRIOR_T)
-        if (used[s]) {
+        if (used[s] && trust[s]) {
             sbg += alpha[(size_t)s * L + nb];
             c += 1.0;
         }
@@ -1467,15 +1502,20 @@ __global__ __launch_bounds__(PRIOR_T) void k_prior_warm(
     if (tid == 0) a0[N - 1] = c > 0.0 ? sbg / c : 0.0;
 }
 
-// Rejection prior: a variable source shows up as a stamp whose predicted
-// kernel sum (its own flux ratio) departs from the warm start's kernel sum
-// at that stamp (the consensus of the kept predictions).  The departures
-// d_s = k_pred / k_a0 - 1 of the kept stamps are summarised robustly (median
-// m and 1.4826 x median |d - m|, by ranking in LDS), and a stamp with
-// |d_s - m| > max(5 robust sigma, PRIOR_FLOOR) gets PSFM_STAMP_PRIOR and
-// leaves the equations (it stays fitted, so its chi2 is evaluated at every
-// solution for the fallback).  A round that excludes nothing, or would leave
-// fewer than min_stamps, ends the prior.
+// Rejection prior: a variable source shows up as a stamp whose kernel
+// estimate (the prediction, or its own least-squares kernel where the 1.05x
+// rule dropped the prediction) has a kernel sum -- its own flux ratio --
+// departing from the warm start's kernel sum at that stamp (the consensus),
+// and which the warm start does not fit.  The departures d_s = k_s / k_a0 - 1
+// of the stamps in use are summarised robustly (median m and 1.4826 x median
+// |d - m|, by ranking in LDS); a stamp gets PSFM_STAMP_PRIOR and leaves the
+// equations when
+// |d_s - m| > max(5 robust sigma, PRIOR_FLOOR) and its chi2_s / npix_s at the
+// warm start exceeds the method's clip threshold there (mean + clip_sigma
+// std over the stamps in use): the departure must be the stamp's own, not
+// the noise of a faint stamp's prediction.  It stays fitted, so its chi2 is
+// evaluated at every solution for the final judgement.  A round that excludes
+// nothing, or would leave fewer than min_stamps, ends the prior.
 constexpr double PRIOR_FLOOR = 0.2;    // flux-ratio departures below 20% never exclude
 constexpr int PRIOR_RANK_MAX = 2048;   // robust statistics up to this many stamps
 
@@ -1497,16 +1537,41 @@ __device__ double block_kth(const double* v, int m, int k, int* s_idx) {
 }
 
 __global__ __launch_bounds__(1024) void k_prior_clip(int n, int ns, int L, int min_stamps,
+                                                     double clip_sigma,
                                                      const double* __restrict__ G,
                                                      const double* __restrict__ alpha,
                                                      const double* __restrict__ a0,
+                                                     const uint8_t* __restrict__ trust,
+                                                     const double* __restrict__ chi2w,
+                                                     const int32_t* __restrict__ npix,
                                                      uint8_t* __restrict__ used,
                                                      int32_t* __restrict__ flags, SolveState* st) {
     __shared__ double vals[PRIOR_RANK_MAX];
+    __shared__ double red[16];
     __shared__ int s_cnt, s_idx, s_n;
-    __shared__ double s_med, s_thr;
+    __shared__ double s_med, s_thr, s_qthr;
     const int tid = threadIdx.x;
     if (st->done || st->prior_done) return;
+    // the method's clip threshold at the warm start, over the stamps in use
+    {
+        double sq = 0.0, cnt = 0.0;
+        for (int s = tid; s < n; s += 1024)
+            if (used[s]) {
+                sq += chi2w[s] / npix[s];
+                cnt += 1.0;
+            }
+        const double tot = psfm_block_sum(sq, red);
+        const double nu = psfm_block_sum(cnt, red);
+        const double mean = nu > 0.0 ? tot / nu : 0.0;
+        double dv = 0.0;
+        for (int s = tid; s < n; s += 1024)
+            if (used[s]) {
+                const double d = chi2w[s] / npix[s] - mean;
+                dv += d * d;
+            }
+        const double var = nu > 0.0 ? psfm_block_sum(dv, red) / nu : 0.0;
+        if (tid == 0) s_qthr = mean + clip_sigma * sqrt(var);
+    }
     auto dev = [&](int s) {
         double kc = 0.0;
         for (int q = 0; q < ns; q++) kc += a0[q] * G[(size_t)s * ns + q];
@@ -1518,7 +1583,7 @@ __global__ __launch_bounds__(1024) void k_prior_clip(int n, int ns, int L, int m
     }
     __syncthreads();
     for (int s = tid; s < n; s += 1024)
-        if (used[s]) {
+        if (used[s] && trust[s]) {
             const int k = atomicAdd(&s_cnt, 1);
             if (k < PRIOR_RANK_MAX) vals[k] = dev(s);
         }
@@ -1536,19 +1601,22 @@ __global__ __launch_bounds__(1024) void k_prior_clip(int n, int ns, int L, int m
     const double mad = block_kth(vals, m, m / 2, &s_idx);
     if (tid == 0) s_thr = fmax(5.0 * 1.4826 * mad, PRIOR_FLOOR);
     __syncthreads();
-    const double thr = s_thr, mm = s_med;
+    const double thr = s_thr, mm = s_med, qthr = s_qthr;
+    auto out = [&](int s) {
+        return used[s] && trust[s] && fabs(dev(s) - mm) > thr && chi2w[s] / npix[s] > qthr;
+    };
     int nnew = 0;
     for (int s = tid; s < n; s += 1024)
-        if (used[s] && fabs(dev(s) - mm) > thr) nnew++;
+        if (out(s)) nnew++;
     atomicAdd(&s_n, nnew);
     __syncthreads();
     const int tn = s_n;
-    if (tn == 0 || s_cnt - tn < min_stamps) {
+    if (tn == 0 || st->n_used - tn < min_stamps) {
         if (tid == 0) st->prior_done = 1;
         return;
     }
     for (int s = tid; s < n; s += 1024)
-        if (used[s] && fabs(dev(s) - mm) > thr) {
+        if (out(s)) {
             used[s] = 0;
             flags[s] |= PSFM_STAMP_PRIOR;
         }
@@ -1576,11 +1644,18 @@ __global__ __launch_bounds__(1024) void k_prior_dof(int n, int N, const int32_t*
     if (threadIdx.x == 0) *out = np > N ? c2 / (np - N) : 0.0;
 }
 
-// Fallback: a stamp the prior excluded whose chi2_s / npix_s at the solved
-// coefficients is within the final clip threshold is restored and, if any
-// was, the solve loop is reopened for one more solution.  One workgroup.
+// The least-squares solution judges the prior: at the prior path's final
+// solution the method's own clip threshold (mean + clip_sigma std of
+// chi2_s / npix_s over the stamps in use) is formed; if any stamp the prior
+// excluded lies within it (the method would have kept that stamp), or the
+// prior path failed, the exclusions are void and the full method runs again
+// from the complete stamp set with a fresh solution budget (the rounds that
+// follow), which is psfm_solve's own path.  Otherwise the prior path's answer
+// stands.  counts[0]: stamps left excluded, counts[1]: excluded stamps found
+// within the threshold, counts[3]: 1 if the full method was rerun.
 __global__ __launch_bounds__(1024) void k_prior_fallback(int n, double clip_sigma,
                                                          const int32_t* __restrict__ npix,
+                                                         const uint8_t* __restrict__ fitted,
                                                          uint8_t* __restrict__ used,
                                                          int32_t* __restrict__ flags,
                                                          const double* __restrict__ chi2,
@@ -1588,15 +1663,10 @@ __global__ __launch_bounds__(1024) void k_prior_fallback(int n, double clip_sigm
     __shared__ double red[16];
     __shared__ double s_thr;
     const int tid = threadIdx.x;
-    if (st->info != 0) {
-        if (tid == 0) counts[0] = counts[1] = 0;
-        return;
-    }
-    // the method's clip threshold over the stamps in use
-    auto cand = [&](int s) { return used[s] != 0; };
+    const bool failed = st->info != 0;
     double sq = 0.0, cnt = 0.0;
     for (int s = tid; s < n; s += 1024)
-        if (cand(s)) {
+        if (used[s]) {
             sq += chi2[s] / npix[s];
             cnt += 1.0;
         }
@@ -1605,7 +1675,7 @@ __global__ __launch_bounds__(1024) void k_prior_fallback(int n, double clip_sigm
     const double mean = nu > 0.0 ? tot / nu : 0.0;
     double dv = 0.0;
     for (int s = tid; s < n; s += 1024)
-        if (cand(s)) {
+        if (used[s]) {
             const double d = chi2[s] / npix[s] - mean;
             dv += d * d;
         }
@@ -1616,21 +1686,29 @@ __global__ __launch_bounds__(1024) void k_prior_fallback(int n, double clip_sigm
     double back = 0.0, still = 0.0;
     for (int s = tid; s < n; s += 1024)
         if (flags[s] & PSFM_STAMP_PRIOR) {
-            if (chi2[s] / npix[s] <= thr) {
-                flags[s] &= ~PSFM_STAMP_PRIOR;
-                used[s] = 1;
-                back += 1.0;
-            } else {
-                still += 1.0;
-            }
+            if (failed || chi2[s] / npix[s] <= thr) back += 1.0;
+            else still += 1.0;
         }
-    const double nb_ = psfm_block_sum(back, red);
-    const double ns_ = psfm_block_sum(still, red);
+    const double nback = psfm_block_sum(back, red);
+    const double nstill = psfm_block_sum(still, red);
+    const bool rerun = failed || nback > 0.0;
+    double nfit = 0.0;
+    if (rerun)
+        for (int s = tid; s < n; s += 1024)
+            if (fitted[s]) {
+                flags[s] &= ~(PSFM_STAMP_PRIOR | PSFM_STAMP_REJECTED);
+                used[s] = 1;
+                nfit += 1.0;
+            }
+    nfit = psfm_block_sum(nfit, red);
     if (tid == 0) {
-        counts[0] = (int)ns_;
-        counts[1] = (int)nb_;
-        if (nb_ > 0.0) {            // the method's rejection loop resumes from the restored set
-            st->n_used += (int)nb_;
+        counts[0] = rerun ? 0 : (int)nstill;
+        counts[1] = (int)nback;
+        counts[3] = rerun ? 1 : 0;
+        if (rerun) {            // psfm_solve's loop from the complete set, fresh budget
+            st->n_used = (int)nfit;
+            st->n_rej = 0;
+            st->info = 0;
             st->done = 0;
             st->n_iter_base = st->n_iter;
         }
@@ -1660,7 +1738,10 @@ size_t solve_workspace(const psfm_context* ctx, int n) {
     c.take<double>(n + 1);                           // prior: chi2 at the warm start
     c.take<double>(ctx->N);                          // prior: warm start
     c.take<double>(1);
-    c.take<int>(2);
+    c.take<int>(4);
+    c.take<double>((size_t)n * ctx->L + 1);          // prior: each stamp's own least-squares kernel
+    c.take<double>(n + 1);                           // prior: its chi2 (the solved value)
+    c.take<uint8_t>(n + 1);                          // prior: stamps with a kernel estimate
     if (ctx->cfg.precision != PSFM_PREC_FP32)
         c.take<double>((size_t)ctx->N * ctx->N);     // transposed factor (refinement)
     return c.off;
@@ -1743,6 +1824,7 @@ static int solve_impl(const psfm_context* ctx, int W, int H, const int32_t* stam
                          !stamp_flags || !stamp_chi2))
         return PSFM_ERR_INVALID_ARG;
     if (ctx->N > CH_NMAX) return PSFM_ERR_UNSUPPORTED;
+    if (prior && ctx->L > 64) return PSFM_ERR_UNSUPPORTED;
     const size_t need = psfm::solve_workspace(ctx, n_stamps);
     if (!ws || ws_bytes < need) return PSFM_ERR_WORKSPACE;
     const size_t lds = psfm::solve_lds_bytes(ctx->N);
@@ -1764,7 +1846,10 @@ static int solve_impl(const psfm_context* ctx, int W, int H, const int32_t* stam
     double* wchi2 = c.take<double>(n_stamps + 1);
     double* a0 = c.take<double>(ctx->N);
     double* pdof = c.take<double>(1);
-    int* pcounts = c.take<int>(2);
+    int* pcounts = c.take<int>(4);
+    double* pls = c.take<double>((size_t)n_stamps * ctx->L + 1);
+    double* pchi2ls = c.take<double>(n_stamps + 1);
+    uint8_t* ptrust = c.take<uint8_t>(n_stamps + 1);
     double* LT = mixed ? c.take<double>((size_t)ctx->N * ctx->N) : nullptr;   // transposed factor
     const int nb = ctx->nb, ns = ctx->ns, N = ctx->N, L = ctx->L;
     const int npix = (2 * ctx->r + 1) * (2 * ctx->r + 1);
@@ -1780,17 +1865,25 @@ static int solve_impl(const psfm_context* ctx, int W, int H, const int32_t* stam
     PSFM_HIP_CHECK(hipGetLastError());
     const int nthreads_asm = L * L * ns + L * ns;
     if (prior && n_stamps > 0) {
-        // completed predictions, then (warm start -> kernel-sum clip) rounds
+        // completed predictions, the 1.05x rule against each stamp's own
+        // least-squares kernel, then (warm start -> kernel-sum clip) rounds
         hipLaunchKernelGGL(k_prior_chi2, dim3(n_stamps), dim3(64), 0, st, nb, stamp_M, stamp_b, stamp_e,
                            stamp_flags, prior, palpha, pchi2);
+        hipLaunchKernelGGL(k_solve_stamps, dim3(n_stamps), dim3(64), 0, st, L, stamp_M, stamp_b,
+                           stamp_e, stamp_flags, pls, pchi2ls);
+        hipLaunchKernelGGL(k_prior_trust, dim3(1), dim3(1024), 0, st, n_stamps, L, stamp_flags, palpha,
+                           pchi2, pls, pchi2ls, ptrust, pcounts);
         for (int it = 0; it < cf.max_iter + 1; it++) {
             hipLaunchKernelGGL(k_prior_warm, dim3(1), dim3(PRIOR_T), 0, st, n_stamps, nb, ns, N, G,
-                               palpha, used, a0, state, 0);
+                               palpha, used, ptrust, a0, state, 0);
+            hipLaunchKernelGGL(k_chi2, dim3(n_stamps), dim3(64), 0, st, nb, ns, N, stamp_M, stamp_b,
+                               stamp_e, G, a0, fitted, wchi2, state);
             hipLaunchKernelGGL(k_prior_clip, dim3(1), dim3(1024), 0, st, n_stamps, ns, L, cf.min_stamps,
-                               G, palpha, a0, used, stamp_flags, state);
+                               cf.clip_sigma, G, palpha, a0, ptrust, wchi2, stamp_npix, used, stamp_flags,
+                               state);
         }
         hipLaunchKernelGGL(k_prior_warm, dim3(1), dim3(PRIOR_T), 0, st, n_stamps, nb, ns, N, G, palpha,
-                           used, a0, state, 1);
+                           used, ptrust, a0, state, 1);
         hipLaunchKernelGGL(k_chi2, dim3(n_stamps), dim3(64), 0, st, nb, ns, N, stamp_M, stamp_b,
                            stamp_e, G, a0, fitted, wchi2, state);
         hipLaunchKernelGGL(k_prior_dof, dim3(1), dim3(1024), 0, st, n_stamps, N, stamp_npix, used, wchi2,
@@ -1838,10 +1931,11 @@ static int solve_impl(const psfm_context* ctx, int W, int H, const int32_t* stam
         if (rc) return rc;
     }
     if (prior && n_stamps > 0) {
-        // fallback: stamps the prior excluded but the solution accepts come back
+        // the least-squares solution judges the prior; on a fallback the full
+        // method reruns from the complete stamp set
         hipLaunchKernelGGL(k_prior_fallback, dim3(1), dim3(1024), 0, st, n_stamps, cf.clip_sigma,
-                           stamp_npix, used, stamp_flags, stamp_chi2, state, pcounts);
-        for (int it = 0; it < cf.max_iter; it++) {   // idle unless the fallback restored stamps
+                           stamp_npix, fitted, used, stamp_flags, stamp_chi2, state, pcounts);
+        for (int it = 0; it < cf.max_iter; it++) {   // idle unless the full method reruns
             rc = round();
             if (rc) return rc;
         }

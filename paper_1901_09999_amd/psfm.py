@@ -60,6 +60,8 @@ class CStats(C.Structure):
         ("chi2_dof_prior", C.c_double),
         ("n_prior", C.c_int),
         ("n_restored", C.c_int),
+        ("n_trusted", C.c_int),
+        ("prior_fallback", C.c_int),
     ]
 
     def as_dict(self):
