@@ -306,8 +306,93 @@ def bench_batch(args, torch, psfm, synth):
     print(json.dumps(out), flush=True)
 
 
-def learned_batch_leg(args, torch, psfm, synth, ctx, pairs, wls, st_plain):
-    return {"note": "not run"}
+def learned_batch_leg(args, torch, psfm, synth, ctx_b, pairs, wls, st_plain):
+    """The learned prior on the batch's pairs: the network is trained on the
+    GPU (200k method-solved stamp pairs), then every pair runs the
+    single-pair path twice -- fit -> solve -> match, and fit -> predict ->
+    solve with the prior -> match -- each timed with HIP events (one warm-up
+    run first).  Both legs are sequential single-pair calls, so their Mpix/s
+    compare with each other, not with the captured batch."""
+    from paper_1901_09999_amd import cnn
+    t0 = time.perf_counter()
+    net, rep = cnn.fit_prior(n=200_000, seed=11, epochs=8, n_val=10_000)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    ctxs = {}
+    acc = dict(px=0.0, plain_ms=0.0, prior_ms=0.0, plain_solve_ms=0.0, prior_solve_ms=0.0,
+               predict_ms=0.0, sol_plain=0, sol_prior=0, excluded=0, fallbacks=0, trusted=0,
+               stamps=0)
+    dchi, dks = [], []
+    for k, q in enumerate(pairs):
+        S = int(q["S"])
+        if S not in ctxs:
+            ctxs[S] = psfm.Context(psfm.Config(h=ctx_b.cfg.h, r=ctx_b.cfg.r, S=S))
+        ctx = ctxs[S]
+        H, W = q["I1"].shape
+        n = int(q["stamps"].shape[0])
+        bufs = ctx.alloc_pair(W, H, n, 10)
+
+        def leg(use_prior, ev):
+            f = ctx.fit_stamps(q["I1"], q["M1"], q["I2"], q["V2"], q["M2"], q["stamps"], out=bufs["fit"])
+            ev[0].record()
+            pred = None
+            if use_prior:
+                pred = cnn.predict_local(ctx, net, q["I1"], q["M1"], q["I2"], q["M2"], q["stamps"])
+            ev[1].record()
+            s = ctx.solve(W, H, q["stamps"], f, flags=f["flags"], out=bufs["sol"], flags_inplace=True,
+                          prior=pred)
+            ev[2].record()
+            ctx.match(s["coeffs"], q["I1"], q["V1"], q["M1"], q["I2"], q["V2"], q["M2"], c_out=10,
+                      stats=s["stats"], out=bufs["sub"], cov_conv=bufs["cov"])
+            ev[3].record()
+            return s
+
+        res = {}
+        for use_prior in (False, True):
+            for rep_i in range(2):                  # warm-up, then the timed run
+                ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+                ev[4].record()
+                s = leg(use_prior, ev[:4])
+                ev[3].synchronize()
+            st = psfm.read_stats(s["stats"])
+            res[use_prior] = dict(total=ev[4].elapsed_time(ev[3]), predict=ev[0].elapsed_time(ev[1]),
+                                  solve=ev[1].elapsed_time(ev[2]), st=st)
+        a, b = res[False], res[True]
+        acc["px"] += W * H
+        acc["plain_ms"] += a["total"]
+        acc["prior_ms"] += b["total"]
+        acc["plain_solve_ms"] += a["solve"]
+        acc["prior_solve_ms"] += b["solve"]
+        acc["predict_ms"] += b["predict"]
+        acc["sol_plain"] += a["st"]["n_iter"]
+        acc["sol_prior"] += b["st"]["n_iter"]
+        acc["excluded"] += b["st"]["n_prior"]
+        acc["fallbacks"] += b["st"]["prior_fallback"]
+        acc["trusted"] += b["st"]["n_trusted"]
+        acc["stamps"] += n
+        if a["st"]["info"] == 0 and b["st"]["info"] == 0:
+            dchi.append(b["st"]["chi2_dof"] / a["st"]["chi2_dof"] - 1)
+            dks.append(abs(b["st"]["kernel_sum_centre"] / a["st"]["kernel_sum_centre"] - 1))
+        del bufs
+    for c in ctxs.values():
+        c.close()
+    return dict(
+        train=dict(seconds=round(t_train, 1), stamps=rep["n_train"], epochs=rep["epochs"],
+                   train_stamps_per_s=rep["train_samples_per_s"],
+                   within_1p05=round(rep["within_1p05"], 3),
+                   kernel_sum_err_median=round(rep["kernel_sum_err_median"], 4)),
+        pairs=len(pairs),
+        plain_sequential_mpix_s=round(acc["px"] / 1e3 / acc["plain_ms"], 1),
+        learned_sequential_mpix_s=round(acc["px"] / 1e3 / acc["prior_ms"], 1),
+        solve_ms=dict(plain=round(acc["plain_solve_ms"], 3), prior=round(acc["prior_solve_ms"], 3),
+                      predict=round(acc["predict_ms"], 3)),
+        solutions=dict(plain=acc["sol_plain"], prior=acc["sol_prior"]),
+        stamps=acc["stamps"], predictions_kept_by_1p05_rule=acc["trusted"],
+        excluded_by_prior=acc["excluded"], fallbacks=acc["fallbacks"],
+        chi2_dof_change_median=float(np.median(dchi)) if dchi else None,
+        chi2_dof_change_max=float(np.max(dchi)) if dchi else None,
+        pairs_with_lower_chi2_dof=int(sum(x < 0 for x in dchi)),
+        kernel_sum_change_max=float(np.max(dks)) if dks else None)
 
 
 def precision_leg(args, torch, psfm, synth, name="chip4846", steps=5, warmup=2):

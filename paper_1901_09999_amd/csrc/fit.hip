@@ -20,7 +20,10 @@
 //      bands of each stamp and scatters M_s, b_s, e_s.
 // 16-bit modes (PSFM_PREC_FP16 / _BF16): the weighted row block is rounded to
 // 16 bits, stored column-major, and folded in with v_mfma_f32_16x16x32_{f16,
-// bf16} (FP32 accumulation, FP64 per row as above); the FP32 block itself
+// bf16} (FP32 accumulation, FP64 per row as above); in BF16 the block is
+// split into hi + lo BF16 parts and the Gram is that of hi + lo (four
+// products, ~16 significant bits, still positive semi-definite); the FP32
+// block itself
 // (terms, sqrt(w), d~) is written to the stamp design for the refinement of
 // the solution, which recomputes residuals from it.
 #include "internal.h"
@@ -57,7 +60,8 @@ struct FitLds {
     int win, col, R, At, sw, dt, psi, z, fac, rf, cf, total;  // float offsets
 };
 
-__host__ __device__ inline FitLds fit_lds_layout(int h, int r, int nb, int nf, int BR) {
+// split: room for two 16-bit blocks (the BF16 mode's hi and lo parts).
+__host__ __device__ inline FitLds fit_lds_layout(int h, int r, int nb, int nf, int BR, bool split) {
     const int WC = 2 * r + 1 + 2 * h;
     const int npad = (2 * r + 1 + 3) / 4 * 4;
     FitLds L;
@@ -66,7 +70,8 @@ __host__ __device__ inline FitLds fit_lds_layout(int h, int r, int nb, int nf, i
     L.win = o;  o += a4((BR + 2 * h) * WC);
     L.col = o;  o += a4(nf * BR * WC + SEG + 2 * h + 4);   // slack for the last row-pass loads
     L.R = o;    o += a4(npad * nb);
-    L.At = o;   o += a4(npad * AT_STRIDE > GC * A16S / 2 ? npad * AT_STRIDE : GC * A16S / 2);
+    const int blk16 = split ? GC * A16S : GC * A16S / 2;     // floats
+    L.At = o;   o += a4(npad * AT_STRIDE > blk16 ? npad * AT_STRIDE : blk16);
     L.sw = o;   o += BR * (2 * r + 1);
     L.dt = o;   o += BR * (2 * r + 1);
     L.psi = o;  o += 64;
@@ -131,7 +136,7 @@ __device__ void fit_band_body(const FitArgs& a, const int item, float* __restric
     const int NPX = 2 * r + 1;
     const int WC = NPX + 2 * H_;
     const int npad = (NPX + 3) / 4 * 4;
-    const FitLds Lo = fit_lds_layout(H_, r, nb, nf, BR);
+    const FitLds Lo = fit_lds_layout(H_, r, nb, nf, BR, PREC == PSFM_PREC_BF16);
     float* win = lds + Lo.win;
     float* colb = lds + Lo.col;
     float* Rb = lds + Lo.R;
@@ -347,6 +352,7 @@ __device__ void fit_band_body(const FitArgs& a, const int item, float* __restric
         // 3b'. the same block, rounded to 16 bits, column-major A16[c][x]
         //      (pixels padded to a multiple of 32); FP32 values to the design
         unsigned short* A16 = reinterpret_cast<unsigned short*>(At);
+        unsigned short* A16lo = A16 + GC * A16S;      // BF16: the remainders v - hi
         const int kp = (NPX + 31) / 32 * 32;
         float* dsg = a.design + (size_t)s * (nb + 2) * (NPX * NPX) + (size_t)(y_l0 + br) * NPX;
         for (int e = tid; e < GC * kp; e += 256) {
@@ -360,13 +366,47 @@ __device__ void fit_band_body(const FitArgs& a, const int item, float* __restric
                 else if (c == nb + 1) v = dtb[br * NPX + x];
                 if (c < nb + 2) dsg[(size_t)c * (NPX * NPX) + x] = v;
             }
-            A16[c * A16S + x] = to16<PREC>(v);
+            const unsigned short hi = to16<PREC>(v);
+            A16[c * A16S + x] = hi;
+            if constexpr (PREC == PSFM_PREC_BF16)
+                A16lo[c * A16S + x] = to16<PREC>(v - (float)__builtin_bit_cast(__bf16, hi));
         }
         __syncthreads();
         // 3c'. Gram blocks, K = 32 pixels per instruction (same wave blocks)
         for (int ks = 0; ks < kp / 32; ks++) {
             const unsigned short* colp = A16 + (lane & 15) * A16S + 32 * ks + 8 * (lane >> 4);
             auto ld = [&](int b) { return *reinterpret_cast<const u16x8*>(colp + 16 * b * A16S); };
+            if constexpr (PREC == PSFM_PREC_BF16) {
+                // x y = (hi_x + lo_x)(hi_y + lo_y), all four BF16 products with FP32
+                // sums: the Gram of the 16-bit-significand block hi + lo, so it
+                // stays positive semi-definite (dropping lo lo would not)
+                auto ll = [&](int b) {
+                    return *reinterpret_cast<const u16x8*>(colp + GC * A16S + 16 * b * A16S);
+                };
+                auto m3 = [&](floatx4 c, int bx, int by) {
+                    const u16x8 xh = ld(bx), yh = ld(by), xl = ll(bx), yl = ll(by);
+                    c = mfma16<PREC>(xh, yh, c);
+                    c = mfma16<PREC>(xh, yl, c);
+                    c = mfma16<PREC>(xl, yh, c);
+                    return mfma16<PREC>(xl, yl, c);
+                };
+                if (wave == 0) {
+                    acc[0] = m3(acc[0], 0, 0);
+                    acc[1] = m3(acc[1], 1, 0);
+                    acc[2] = m3(acc[2], 1, 1);
+                } else if (wave == 1) {
+                    acc[0] = m3(acc[0], 2, 0);
+                    acc[1] = m3(acc[1], 2, 1);
+                    acc[2] = m3(acc[2], 2, 2);
+                } else if (wave == 2) {
+                    acc[0] = m3(acc[0], 3, 0);
+                    acc[1] = m3(acc[1], 3, 1);
+                } else {
+                    acc[0] = m3(acc[0], 3, 2);
+                    acc[1] = m3(acc[1], 3, 3);
+                }
+                continue;
+            }
             if (wave == 0) {
                 const u16x8 a0 = ld(0), a1 = ld(1);
                 acc[0] = mfma16<PREC>(a0, a0, acc[0]);
@@ -563,7 +603,8 @@ int set_fit_lds_ctx(const psfm_context* ctx, size_t lds) {
 template <int H_, int BR>
 int launch_fit_br(const psfm_context* ctx, const FitArgs& a, int n_items, const PairDesc* pairs,
                   const int* item_pair, hipStream_t st) {
-    const FitLds Lo = fit_lds_layout(H_, ctx->r, ctx->nb, ctx->nf, BR);
+    const FitLds Lo = fit_lds_layout(H_, ctx->r, ctx->nb, ctx->nf, BR,
+                                     ctx->cfg.precision == PSFM_PREC_BF16 && !pairs);
     const size_t lds = (size_t)Lo.total * sizeof(float);
     int rc = set_fit_lds<H_, BR>(lds);
     if (rc) return rc;
@@ -607,7 +648,8 @@ int dispatch_fit(const psfm_context* ctx, const FitArgs& a, int n_items, const P
 namespace psfm {
 
 size_t fit_lds_bytes(const psfm_context* ctx) {
-    return (size_t)fit_lds_layout(ctx->h, ctx->r, ctx->nb, ctx->nf, ctx->fit_br).total * sizeof(float);
+    return (size_t)fit_lds_layout(ctx->h, ctx->r, ctx->nb, ctx->nf, ctx->fit_br,
+                                  ctx->cfg.precision == PSFM_PREC_BF16).total * sizeof(float);
 }
 
 // Grants the fit kernels their dynamic LDS (done ahead of a graph capture).

@@ -4,17 +4,18 @@ FP64 oracle.
 
 Tolerances:
   * 16-bit Gram: each design entry is rounded once (unit roundoff 2^-11 for
-    FP16, 2^-8 for BF16) before FP32-accumulated products, so every Gram entry
-    stays within ~2 u of sqrt(M_ii M_jj): 2e-3 (FP16) and 1.6e-2 (BF16);
+    FP16; BF16 hi + lo keeps ~2^-16) before FP32-accumulated products, so
+    every Gram entry stays within ~2 u of sqrt(M_ii M_jj): 2e-3 in both;
   * the cached FP32 design reproduces the FP32-mode Gram as exactly as that
     Gram matches the oracle (2e-5 of sqrt(M_ii M_jj));
   * FP16 after one refinement step meets the whole-path targets as FP32
     does: kernel sum within 1e-4 relative, chi2/dof within 1% (the solution is
     refined against FP32 residuals; the 16-bit Gram only preconditions the
     correction);
-  * BF16 converges more slowly: on the 2048^2 pair two steps leave the kernel
-    sum at ~1.4e-4 (measured), so it is held to 3e-4 there; on the detector
-    chip it meets 1e-4.
+  * BF16 takes the Gram of a hi + lo split of the block (four BF16
+    products, ~16 significant bits), held to the FP16 mode's 2e-3 per entry;
+    with the one refinement step the workload prescribes it meets the same
+    whole-path targets on the 2048^2 pair and the detector chip.
 """
 import functools
 
@@ -45,7 +46,7 @@ def _run(psfm, torch, wl, pair, **kw):
     return ctx, d, r
 
 
-@pytest.mark.parametrize("prec,tol", [(2, 2e-3), (1, 1.6e-2)])
+@pytest.mark.parametrize("prec,tol", [(2, 2e-3), (1, 2e-3)])
 def test_sixteen_bit_gram_and_design(prec, tol):
     torch, psfm = hip()
     wl, pair = pair_for("pair2048", SEED1)
@@ -74,7 +75,7 @@ def test_sixteen_bit_gram_and_design(prec, tol):
     assert np.max(np.abs(bd - _np(f32["b"])[ok]) / (Mb * ebd[:, None])) < 2e-5
 
 
-@pytest.mark.parametrize("prec,refine,ktol", [(2, 1, 1e-4), (1, 2, 3e-4)])
+@pytest.mark.parametrize("prec,refine,ktol", [(2, 1, 1e-4), (1, 1, 1e-4)])
 def test_sixteen_bit_whole_path(prec, refine, ktol):
     torch, psfm = hip()
     wl, pair = pair_for("pair2048", SEED1)
@@ -131,7 +132,7 @@ def test_detector_chip_full_size(prec):
     torch, psfm = hip()
     wl, pair, cfg, a_ref, rs = _chip()
     print(f"chip4846 precision {prec}: {pair.stamps.shape[0]} stamps", flush=True)
-    ctx, d, r = _run(psfm, torch, wl, pair, precision=prec, refine=1 if prec != 1 else 2)
+    ctx, d, r = _run(psfm, torch, wl, pair, precision=prec, refine=1)
     st = psfm.read_stats(r["sol"]["stats"])
     ks = abs(st["kernel_sum_centre"] / rs["kernel_sum_centre"] - 1)
     cd = abs(st["chi2_dof"] / rs["chi2_dof"] - 1)
