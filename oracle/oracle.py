@@ -23,6 +23,28 @@ STAMP_INVALID, STAMP_REJECTED, STAMP_NONFINITE = 1, 2, 4
 MASK_BAD, MASK_CONV_BAD, MASK_CONV_POOR = 1, 2, 4
 
 
+STAMP_RESERVE = 32
+CUT_FEW_STAMPS, CUT_MEAN_DEV, CUT_RMS_DEV, CUT_MOMENT1, CUT_MOMENT2, CUT_DECONV = 1, 2, 4, 8, 16, 32
+
+
+class OrcQuality(C.Structure):
+    _fields_ = [
+        ("dev_mean", C.c_double),
+        ("dev_rms", C.c_double),
+        ("kernel_sum", C.c_double),
+        ("mom_x", C.c_double),
+        ("mom_y", C.c_double),
+        ("mom_xx", C.c_double),
+        ("mom_yy", C.c_double),
+        ("deconv_max", C.c_double),
+        ("n_used", C.c_int),
+        ("cut_flags", C.c_int),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class OrcConfig(C.Structure):
     _fields_ = [
         ("n_gauss", C.c_int),
@@ -100,6 +122,12 @@ def lib():
                                     i]),
             "orc_convolve_region": (None, [cfgp, P, P, P, P, P, i, i, i64, P, i, i, i, i, i, P, P,
                                            P]),
+            "orc_fit_norm": (None, [cfgp, P, P, P, i, i, i64, P, i, P, P]),
+            "orc_norm_solve": (i, [i, P, P, P, P]),
+            "orc_solve_norm": (i, [cfgp, i, i, P, i, P, P, P, P, P, P, P, P, P,
+                                   C.POINTER(OrcStats), C.POINTER(C.c_int)]),
+            "orc_quality_eval": (None, [cfgp, P, P, P, P, P, i, i, i64, P, i, P, d, P,
+                                        C.POINTER(OrcQuality)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(_lib, name)
@@ -353,3 +381,58 @@ def match_pair(cfg: Config, pair, c_out: int = 10):
     out.update(conv=conv, conv_mask=cmask, var=var, cov=cov, cov_discarded=disc, diff=D,
                diff_var=VD, diff_mask=MD, cov_diff=CD)
     return out
+
+
+# ---------------------------------------------------------------- the paper's
+# normalisation and quality mode (Sections 3.2, 3.3, 3.6, 3.7)
+
+def fit_norm(cfg: Config, I1, I2, stamps, flags, kb=None):
+    """Per-stamp unweighted sums [n, 5]: npix, sum A0, sum I2, sum A0^2, sum A0 I2."""
+    kb = basis(cfg) if kb is None else kb
+    I1, I2 = _c(I1, np.float32), _c(I2, np.float32)
+    H, W = I1.shape
+    xy = _c(stamps, np.int32).reshape(-1, 2)
+    n = xy.shape[0]
+    out = np.zeros((n, 5))
+    lib().orc_fit_norm(C.byref(cfg.c()), _p(kb), _p(I1), _p(I2), W, H, W, _p(xy), n,
+                       _p(_c(flags, np.int32)), _p(out))
+    return out
+
+
+def norm_solve(norm, used):
+    """(ret, b0, d0) from the stamp totals of the stamps in use."""
+    norm = _c(norm, np.float64)
+    b0, d0 = C.c_double(0.0), C.c_double(0.0)
+    ret = lib().orc_norm_solve(norm.shape[0], _p(norm), _p(_c(used, np.uint8)), C.byref(b0),
+                               C.byref(d0))
+    return ret, b0.value, d0.value
+
+
+def solve_norm(cfg: Config, W, H, stamps, fit, norm, flags=None, group=None):
+    """Paper's normalisation mode.  Returns (ret, coeffs, chi2, flags, stats, n_replaced)."""
+    xy = _c(stamps, np.int32).reshape(-1, 2)
+    n = xy.shape[0]
+    fl = _c(fit["flags"] if flags is None else flags, np.int32).copy()
+    a = np.zeros(cfg.n_unknowns); chi2 = np.zeros(n)
+    st = OrcStats()
+    nrep = C.c_int(0)
+    ret = lib().orc_solve_norm(C.byref(cfg.c()), W, H, _p(xy), n, _p(_c(fit["M"], np.float64)),
+                               _p(_c(fit["b"], np.float64)), _p(_c(fit["e"], np.float64)),
+                               _p(_c(fit["npix"], np.int32)), _p(_c(norm, np.float64)),
+                               _p(None if group is None else _c(group, np.int32)), _p(fl), _p(a),
+                               _p(chi2), C.byref(st), C.byref(nrep))
+    return ret, a, chi2, fl, st.as_dict(), nrep.value
+
+
+def quality(cfg: Config, a, I1, I2, V2, stamps, flags, soft=0.0, kb=None):
+    """Quality record and per-stamp deviations of a solution (Section 3.6)."""
+    kb = basis(cfg) if kb is None else kb
+    I1, I2, V2 = (_c(x, np.float32) for x in (I1, I2, V2))
+    H, W = I1.shape
+    xy = _c(stamps, np.int32).reshape(-1, 2)
+    n = xy.shape[0]
+    dev = np.zeros(n)
+    q = OrcQuality()
+    lib().orc_quality_eval(C.byref(cfg.c()), _p(kb), _p(_c(a, np.float64)), _p(I1), _p(I2), _p(V2), W,
+                           H, W, _p(xy), n, _p(_c(flags, np.int32)), float(soft), _p(dev), C.byref(q))
+    return q.as_dict(), dev

@@ -760,3 +760,310 @@ void orc_subtract(const orc_config* c, const double* a, const float* I2, const f
             cov_diff[(dy + cd) * Dw + (dx + cd)] = (v2 + vc) > 0.0 ? (v2 * a2 + vc * ac) / (v2 + vc) : 0.0;
         }
 }
+
+/* ------------------------------------------------------------------------
+ * The paper's normalisation and quality mode (Sections 3.2, 3.3, 3.6, 3.7).
+ */
+
+#define ORC_STAMP_RESERVE 32   /* candidate held back to replace a rejected stamp */
+
+/*
+ * Unweighted sums of one stamp for the separate normalisation (Section 3.2,
+ * sigma(x, y) = 1).  With A0 = k0 (x) I1 the flux-carrying column (the
+ * unit-sum term the other terms were made zero-sum against):
+ *   norm[5 s + 0] = npix,  [1] = sum A0,  [2] = sum I2,
+ *   [3] = sum A0^2,        [4] = sum A0 I2
+ * over the stamp pixels; zeros for stamps flagged on input (any bit except
+ * ORC_STAMP_RESERVE, whose sums are kept for a later replacement).
+ */
+void orc_fit_norm(const orc_config* c, const double* kb, const float* I1, const float* I2, int W,
+                  int H, int64_t pitch, const int32_t* xy, int n, const int32_t* flags,
+                  double* norm) {
+    const int h = c->h, r = c->r, K = 2 * h + 1;
+    (void)W;
+    (void)H;
+#pragma omp parallel for schedule(dynamic)
+    for (int s = 0; s < n; s++) {
+        double* o = norm + 5 * (size_t)s;
+        for (int k = 0; k < 5; k++) o[k] = 0.0;
+        if (flags[s] & ~ORC_STAMP_RESERVE) continue;
+        const int xc = xy[2 * s], yc = xy[2 * s + 1];
+        for (int y = yc - r; y <= yc + r; y++)
+            for (int x = xc - r; x <= xc + r; x++) {
+                double a0 = 0.0;
+                for (int v = -h; v <= h; v++)
+                    for (int u = -h; u <= h; u++)
+                        a0 += kb[(v + h) * K + (u + h)] * (double)I1[(int64_t)(y - v) * pitch + (x - u)];
+                const double d = (double)I2[(int64_t)y * pitch + x];
+                o[0] += 1.0;
+                o[1] += a0;
+                o[2] += d;
+                o[3] += a0 * a0;
+                o[4] += a0 * d;
+            }
+    }
+}
+
+/*
+ * Normalisation b0 and background difference d0, spatially constant, from
+ * the stamps in use (Section 3.2).  Reading: only b0 and d0 add flux, the
+ * zero-sum terms move flux within a stamp, so over each stamp's aperture
+ * the totals obey T2_s = b0 T1_s + d0 npix_s; b0 and d0 are the unweighted
+ * least-squares fit of that relation over the stamps (sigma = 1, as in
+ * aperture photometry).  Returns 0, or 1 if the 2 x 2 system is singular.
+ */
+int orc_norm_solve(int n, const double* norm, const uint8_t* used, double* b0, double* d0) {
+    double saa = 0.0, san = 0.0, snn = 0.0, sad = 0.0, snd = 0.0;
+    for (int s = 0; s < n; s++) {
+        if (!used[s]) continue;
+        const double np = norm[5 * s], t1 = norm[5 * s + 1], t2 = norm[5 * s + 2];
+        saa += t1 * t1;
+        san += t1 * np;
+        snn += np * np;
+        sad += t1 * t2;
+        snd += np * t2;
+    }
+    const double det = saa * snn - san * san;
+    if (!(det > 1e-12 * saa * snn)) {
+        *b0 = 0.0;
+        *d0 = 0.0;
+        return 1;
+    }
+    *b0 = (sad * snn - san * snd) / det;
+    *d0 = (saa * snd - san * sad) / det;
+    return 0;
+}
+
+/*
+ * Solution in the paper's normalisation mode (Sections 3.2, 3.3): at each
+ * iteration b0 and d0 come from orc_norm_solve over the stamps in use; the
+ * weighted equations of the other unknowns are then solved with b0 and d0
+ * held: unknown 0 (term 0, spatial term 0) = b0, the higher spatial terms of
+ * term 0 = 0 (the normalisation is spatially constant), the background =
+ * d0, and for the free unknowns f
+ *     M_ff a_f = b_f - M_fc a_c
+ * (c the held unknowns), solved by orc_cholesky_solve.  The rejection is
+ * orc_solve's.  Replacement (Section 3.3, "removed (and replaced, if
+ * possible)"): with group non-NULL, each stamp rejected in a round is
+ * replaced by the lowest-index stamp of the same group (group >= 0) that is
+ * held in reserve (flags == ORC_STAMP_RESERVE on input); it enters the next
+ * solution.  stats as orc_solve, with dof = sum npix - (free unknowns + 2);
+ * *n_replaced counts replacements.  Returns 0, -3, -4, or -5 (singular
+ * normalisation).
+ */
+int orc_solve_norm(const orc_config* c, int W, int H, const int32_t* xy, int n, const double* Ms,
+                   const double* bs, const double* es, const int32_t* npix, const double* norm,
+                   const int32_t* group, int32_t* flags, double* coeffs, double* chi2,
+                   orc_stats* st, int* n_replaced) {
+    const int nb = orc_n_basis(c), ns = orc_n_spatial(c), N = nb * ns + 1, L = nb + 1;
+    uint8_t* used = (uint8_t*)calloc(n > 0 ? n : 1, 1);
+    uint8_t* fitted = (uint8_t*)calloc(n > 0 ? n : 1, 1);
+    uint8_t* held = (uint8_t*)calloc(N, 1);
+    int* fidx = (int*)malloc(sizeof(int) * N);
+    double* M = (double*)malloc(sizeof(double) * (size_t)N * N);
+    double* b = (double*)malloc(sizeof(double) * N);
+    double* Mf = (double*)malloc(sizeof(double) * (size_t)N * N);
+    double* bf = (double*)malloc(sizeof(double) * N);
+    double* af = (double*)malloc(sizeof(double) * N);
+    int ret = 0, iter = 0, n_rej = 0, n_rep = 0;
+    memset(st, 0, sizeof(*st));
+    for (int s = 0; s < n; s++) {
+        used[s] = flags[s] == 0;
+        fitted[s] = used[s];
+        chi2[s] = 0.0;
+    }
+    for (int t = 0; t < ns; t++) held[0 * ns + t] = 1;
+    held[N - 1] = 1;
+    int nf = 0;
+    for (int i = 0; i < N; i++)
+        if (!held[i]) fidx[nf++] = i;
+    for (int i = 0; i < N; i++) coeffs[i] = 0.0;
+    for (;;) {
+        int n_used = 0;
+        for (int s = 0; s < n; s++) n_used += used[s];
+        if (n_used < c->min_stamps) { ret = -3; st->info = -3; break; }
+        double b0, d0;
+        if (orc_norm_solve(n, norm, used, &b0, &d0)) { ret = -5; st->info = -5; break; }
+        orc_assemble(c, W, H, xy, n, Ms, bs, used, M, b);
+        for (int i = 0; i < N; i++) coeffs[i] = 0.0;
+        coeffs[0] = b0;
+        coeffs[N - 1] = d0;
+        for (int p = 0; p < nf; p++) {
+            const int i = fidx[p];
+            double t = b[i];
+            for (int j = 0; j < N; j++)
+                if (held[j]) t -= M[(size_t)i * N + j] * coeffs[j];
+            bf[p] = t;
+            for (int q = 0; q < nf; q++) Mf[(size_t)p * nf + q] = M[(size_t)i * N + fidx[q]];
+        }
+        int info = orc_cholesky_solve(nf, Mf, bf, af);
+        if (info) { ret = -4; st->info = fidx[info - 1] + 1; break; }
+        for (int p = 0; p < nf; p++) coeffs[fidx[p]] = af[p];
+        iter++;
+        for (int s = 0; s < n; s++)
+            chi2[s] = fitted[s] ? orc_stamp_chi2(c, coeffs, W, H, xy[2 * s], xy[2 * s + 1],
+                                                  Ms + (size_t)s * L * L, bs + (size_t)s * L, es[s])
+                                : 0.0;
+        if (iter >= c->max_iter) break;
+        double mean = 0.0, var = 0.0;
+        for (int s = 0; s < n; s++)
+            if (used[s]) mean += chi2[s] / npix[s];
+        mean /= n_used;
+        for (int s = 0; s < n; s++)
+            if (used[s]) {
+                const double dq = chi2[s] / npix[s] - mean;
+                var += dq * dq;
+            }
+        const double thr = mean + c->clip_sigma * sqrt(var / n_used);
+        int n_new = 0;
+        for (int s = 0; s < n; s++)
+            if (used[s] && chi2[s] / npix[s] > thr) n_new++;
+        if (n_new == 0 || n_used - n_new < c->min_stamps) break;
+        for (int s = 0; s < n; s++)
+            if (used[s] && chi2[s] / npix[s] > thr) {
+                used[s] = 0;
+                flags[s] |= ORC_STAMP_REJECTED;
+                n_rej++;
+                if (group && group[s] >= 0)
+                    for (int q = 0; q < n; q++)
+                        if (group[q] == group[s] && flags[q] == ORC_STAMP_RESERVE) {
+                            flags[q] = 0;
+                            used[q] = 1;
+                            fitted[q] = 1;
+                            n_rep++;
+                            break;
+                        }
+            }
+    }
+    st->n_iter = iter;
+    st->n_rejected = n_rej;
+    *n_replaced = n_rep;
+    if (ret != 0)
+        for (int i = 0; i < N; i++) coeffs[i] = 0.0;
+    if (ret == 0) {
+        double c2 = 0.0, np = 0.0;
+        int nu = 0;
+        for (int s = 0; s < n; s++)
+            if (used[s]) { c2 += chi2[s]; np += npix[s]; nu++; }
+        st->chi2 = c2;
+        st->dof = np - (nf + 2);
+        st->chi2_dof = c2 / (np - (nf + 2));
+        st->n_used = nu;
+        st->kernel_sum_centre = coeffs[0];
+    }
+    free(used); free(fitted); free(held); free(fidx); free(M); free(b); free(Mf); free(bf);
+    free(af);
+    return ret;
+}
+
+/* Quality record of a subtraction (Sections 3.6 and 3.7). */
+typedef struct {
+    double dev_mean, dev_rms;         /* normalised mean deviation, r.m.s. deviation */
+    double kernel_sum, mom_x, mom_y, mom_xx, mom_yy, deconv_max;
+    int n_used, cut_flags;
+} orc_quality;
+
+/* cut bits (Section 3.7's recommended cuts) */
+#define ORC_CUT_FEW_STAMPS 1     /* number of stamps used < 3 */
+#define ORC_CUT_MEAN_DEV   2     /* normalised mean deviation > 0.5 */
+#define ORC_CUT_RMS_DEV    4     /* normalised r.m.s. deviation > 0.3 */
+#define ORC_CUT_MOMENT1    8     /* a first moment (x, y) of the kernel > 0.5 in size */
+#define ORC_CUT_MOMENT2   16     /* a second moment (xx, yy) of the kernel < 0 */
+#define ORC_CUT_DECONV    32     /* maximum deconvolution fraction > 1.03 */
+
+/*
+ * Quality of a solution (Section 3.6).
+ * Per used stamp (flags == 0), the residual of the solution applied there --
+ * the kernel realised at the stamp centre convolved with I1 plus the
+ * background, subtracted from I2 -- divided by the variance softened with a
+ * scaled flux:  dev_s = (1/npix) sum (I2 - m)^2 / (V2 + soft |m|),
+ * m = K_s (x) I1 + d0 (reading: "a scaled version of the flux" is soft
+ * times the model flux of the pixel; soft = 0 gives chi2_s / npix_s).
+ * dev[s] receives dev_s (0 for unused stamps).  Over the used stamps:
+ * dev_mean = mean(dev_s) - 1 (excess over pure noise) and dev_rms =
+ * population std of dev_s (readings of the "normalised" mean and r.m.s.
+ * deviations).  At the image centre: the kernel sum, first moments
+ * (sum u K / sum K, sum v K / sum K), second central moments, and the
+ * maximum over radii rho = 0 .. ceil(h sqrt 2) of the deconvolution
+ * fraction sum_{u^2 + v^2 <= rho^2} K / sum K.  cut_flags: the bits above.
+ */
+void orc_quality_eval(const orc_config* c, const double* kb, const double* a, const float* I1,
+                      const float* I2, const float* V2, int W, int H, int64_t pitch,
+                      const int32_t* xy, int n, const int32_t* flags, double soft, double* dev,
+                      orc_quality* q) {
+    const int h = c->h, r = c->r, Kw = 2 * h + 1, T = Kw * Kw, N = orc_n_unknowns(c);
+    const double d0 = a[N - 1];
+#pragma omp parallel for schedule(dynamic)
+    for (int s = 0; s < n; s++) {
+        dev[s] = 0.0;
+        if (flags[s]) continue;
+        const int xc = xy[2 * s], yc = xy[2 * s + 1];
+        double* K = (double*)malloc(sizeof(double) * T);
+        orc_kernel_at(c, kb, a, xc, yc, W, H, K);
+        double acc = 0.0;
+        int np = 0;
+        for (int y = yc - r; y <= yc + r; y++)
+            for (int x = xc - r; x <= xc + r; x++) {
+                double m = d0;
+                for (int v = -h; v <= h; v++)
+                    for (int u = -h; u <= h; u++)
+                        m += K[(v + h) * Kw + (u + h)] * (double)I1[(int64_t)(y - v) * pitch + (x - u)];
+                const double res = (double)I2[(int64_t)y * pitch + x] - m;
+                acc += res * res / ((double)V2[(int64_t)y * pitch + x] + soft * fabs(m));
+                np++;
+            }
+        dev[s] = acc / np;
+        free(K);
+    }
+    double sm = 0.0, sv = 0.0;
+    int nu = 0;
+    for (int s = 0; s < n; s++)
+        if (!flags[s]) { sm += dev[s]; nu++; }
+    const double mean = nu ? sm / nu : 0.0;
+    for (int s = 0; s < n; s++)
+        if (!flags[s]) sv += (dev[s] - mean) * (dev[s] - mean);
+    q->n_used = nu;
+    q->dev_mean = nu ? mean - 1.0 : 0.0;
+    q->dev_rms = nu ? sqrt(sv / nu) : 0.0;
+    double* K = (double*)malloc(sizeof(double) * T);
+    orc_kernel_at(c, kb, a, 0.5 * (W - 1), 0.5 * (H - 1), W, H, K);
+    double s0 = 0.0, su = 0.0, sv1 = 0.0;
+    for (int v = -h; v <= h; v++)
+        for (int u = -h; u <= h; u++) {
+            const double k = K[(v + h) * Kw + (u + h)];
+            s0 += k;
+            su += u * k;
+            sv1 += v * k;
+        }
+    q->kernel_sum = s0;
+    q->mom_x = su / s0;
+    q->mom_y = sv1 / s0;
+    double sxx = 0.0, syy = 0.0;
+    for (int v = -h; v <= h; v++)
+        for (int u = -h; u <= h; u++) {
+            const double k = K[(v + h) * Kw + (u + h)];
+            sxx += (u - q->mom_x) * (u - q->mom_x) * k;
+            syy += (v - q->mom_y) * (v - q->mom_y) * k;
+        }
+    q->mom_xx = sxx / s0;
+    q->mom_yy = syy / s0;
+    const int rmax = (int)ceil(h * sqrt(2.0));
+    double best = -1e300;
+    for (int rho = 0; rho <= rmax; rho++) {
+        double e = 0.0;
+        for (int v = -h; v <= h; v++)
+            for (int u = -h; u <= h; u++)
+                if (u * u + v * v <= rho * rho) e += K[(v + h) * Kw + (u + h)];
+        if (e / s0 > best) best = e / s0;
+    }
+    q->deconv_max = best;
+    free(K);
+    int f = 0;
+    if (q->n_used < 3) f |= ORC_CUT_FEW_STAMPS;
+    if (q->dev_mean > 0.5) f |= ORC_CUT_MEAN_DEV;
+    if (q->dev_rms > 0.3) f |= ORC_CUT_RMS_DEV;
+    if (fabs(q->mom_x) > 0.5 || fabs(q->mom_y) > 0.5) f |= ORC_CUT_MOMENT1;
+    if (q->mom_xx < 0.0 || q->mom_yy < 0.0) f |= ORC_CUT_MOMENT2;
+    if (q->deconv_max > 1.03) f |= ORC_CUT_DECONV;
+    q->cut_flags = f;
+}
