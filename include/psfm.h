@@ -64,7 +64,8 @@ typedef enum {
     PSFM_ERR_NOT_PD = -4,        /* (device) normal matrix not positive definite */
     PSFM_ERR_HIP = -5,           /* a HIP runtime call failed */
     PSFM_ERR_WORKSPACE = -6,     /* workspace missing or smaller than required */
-    PSFM_ERR_UNSUPPORTED = -7    /* configuration outside what the kernels support */
+    PSFM_ERR_UNSUPPORTED = -7,   /* configuration outside what the kernels support */
+    PSFM_ERR_NORM_SINGULAR = -8  /* (device) stamp totals do not determine b0 and d0 */
 } psfm_status;
 
 /* Stamp flag bits (stamp_flags). */
@@ -73,6 +74,7 @@ typedef enum {
 #define PSFM_STAMP_NONFINITE 4   /* non-finite pixel, or variance not finite and > 0 */
 #define PSFM_STAMP_EXCLUDED  8   /* excluded by the caller before psfm_solve */
 #define PSFM_STAMP_PRIOR    16   /* excluded before the first solution by the learned prior */
+#define PSFM_STAMP_RESERVE  32   /* held back to replace a rejected stamp (psfm_solve_norm) */
 
 /* Output mask bits. */
 #define PSFM_MASK_BAD       1    /* masked in the input (difference image: image 2) */
@@ -145,6 +147,7 @@ typedef struct psfm_fit_stats {
     int n_restored;            /* psfm_solve_prior: excluded stamps the solution found within the clip */
     int n_trusted;             /* psfm_solve_prior: predictions kept by the 1.05x rule */
     int prior_fallback;        /* psfm_solve_prior: 1 if the full method was rerun (prior void) */
+    int n_replaced;            /* psfm_solve_norm: reserve stamps brought in for rejected ones */
 } psfm_fit_stats;
 
 typedef struct psfm_context psfm_context;
@@ -217,6 +220,87 @@ int psfm_solve(const psfm_context* ctx, int W, int H, const int32_t* stamp_xy, i
                const int32_t* stamp_npix, int32_t* stamp_flags, const float* stamp_design,
                double* coeffs, double* stamp_chi2, psfm_fit_stats* stats, void* ws,
                size_t ws_bytes, void* stream);
+
+/*
+ * The paper's normalisation and quality mode (Sections 3.2, 3.3, 3.6, 3.7).
+ *
+ * psfm_fit_norm: the unweighted sums of each stamp for the separate
+ * normalisation (Section 3.2, sigma(x, y) = 1): with A0 = k_0 (x) I1 the
+ * flux-carrying column,
+ *   stamp_norm[5 s + 0..4] = npix, sum A0, sum I2, sum A0^2, sum A0 I2
+ * over the stamp's (2r+1)^2 pixels (FP64).  Stamps whose flags hold any bit
+ * other than PSFM_STAMP_RESERVE get zeros (reserves keep their sums for a
+ * later replacement).  stamp_flags: psfm_fit_stamps' flags (plus
+ * PSFM_STAMP_RESERVE set by the caller on the reserves).  Stamp footprints
+ * must lie inside the image (psfm_fit_stamps flags those that do not).
+ */
+int psfm_fit_norm(const psfm_context* ctx, const float* I1, const float* I2, int W, int H,
+                  int64_t pitch, const int32_t* stamp_xy, int n_stamps,
+                  const int32_t* stamp_flags, double* stamp_norm, void* stream);
+
+/*
+ * psfm_solve in the paper's normalisation mode (Section 3.2): at every
+ * solution b0 and d0 are found first, spatially constant and unweighted,
+ * from the stamp totals of the stamps in use (only they add flux; the other
+ * terms move flux within a stamp): the least-squares fit of
+ * sum I2 = b0 sum A0 + d0 npix over the stamps.  The weighted equations of
+ * the other unknowns are then solved with them held (term 0 = b0 at spatial
+ * term 0 and 0 at the others, background = d0).  Rejection as psfm_solve;
+ * replacement (Section 3.3): with stamp_group (n int32, nullable; group id
+ * >= 0 per stamp, e.g. the subregion the stamp was chosen in), each stamp
+ * rejected in a round is replaced by the lowest-index stamp of its group
+ * whose flags are exactly PSFM_STAMP_RESERVE (stats->n_replaced counts
+ * them).  stats->dof = sum npix - (free unknowns + 2); kernel_sum_centre =
+ * b0; info PSFM_ERR_NORM_SINGULAR if the totals cannot separate b0 from d0.
+ * FP32 stamp fits only.  Workspace: psfm_workspace_bytes().
+ */
+int psfm_solve_norm(const psfm_context* ctx, int W, int H, const int32_t* stamp_xy, int n_stamps,
+                    const double* stamp_M, const double* stamp_b, const double* stamp_e,
+                    const int32_t* stamp_npix, const double* stamp_norm,
+                    const int32_t* stamp_group, int32_t* stamp_flags, double* coeffs,
+                    double* stamp_chi2, psfm_fit_stats* stats, void* ws, size_t ws_bytes,
+                    void* stream);
+
+/* Quality record of a solution (device memory, written by psfm_quality). */
+typedef struct psfm_quality {
+    double dev_mean;     /* normalised mean deviation: mean of dev_s over used stamps, minus 1 */
+    double dev_rms;      /* normalised r.m.s. deviation: population std of dev_s */
+    double kernel_sum;   /* kernel realised at the image centre: sum, */
+    double mom_x, mom_y; /* first moments (pixels), */
+    double mom_xx, mom_yy; /* second central moments, */
+    double deconv_max;   /* maximum deconvolution fraction */
+    int n_used;          /* stamps used */
+    int cut_flags;       /* PSFM_CUT_* bits raised */
+} psfm_quality;
+
+/* The bad-subtraction cuts the paper recommends (Section 3.7). */
+#define PSFM_CUT_FEW_STAMPS 1    /* stamps used < 3 */
+#define PSFM_CUT_MEAN_DEV   2    /* normalised mean deviation > 0.5 */
+#define PSFM_CUT_RMS_DEV    4    /* normalised r.m.s. deviation > 0.3 */
+#define PSFM_CUT_MOMENT1    8    /* |first moment| (x or y) > 0.5 */
+#define PSFM_CUT_MOMENT2   16    /* second moment (xx or yy) < 0 */
+#define PSFM_CUT_DECONV    32    /* maximum deconvolution fraction > 1.03 */
+
+/*
+ * Quality of a solution (Section 3.6).  For each stamp with stamp_flags 0,
+ * the residual of the solution applied at the stamp (the kernel realised at
+ * its centre convolved with I1, plus the background d0) divided by the
+ * variance softened with a scaled flux:
+ *   stamp_dev[s] = (1/npix) sum (I2 - m)^2 / (V2 + soft |m|),  m the model,
+ * (0 for the other stamps; soft = 0 gives chi2_s / npix_s).  Over the used
+ * stamps, *quality gets the normalised mean and r.m.s. deviations; for the
+ * kernel realised at the image centre its sum, first moments sum u K / sum K
+ * and sum v K / sum K, second central moments, and the maximum over radii
+ * rho = 0 .. ceil(h sqrt 2) of the deconvolution fraction
+ * sum_{u^2 + v^2 <= rho^2} K / sum K; and the PSFM_CUT_* bits.  coeffs:
+ * N float64 (any mode).  stamp_dev: n float64 (device); quality: device.
+ * Used stamps' footprints must lie inside the image (as psfm_fit_stamps'
+ * valid stamps do); others are skipped.
+ */
+int psfm_quality_eval(const psfm_context* ctx, const double* coeffs, const float* I1,
+                      const float* I2, const float* V2, int W, int H, int64_t pitch,
+                      const int32_t* stamp_xy, int n_stamps, const int32_t* stamp_flags,
+                      double soft, double* stamp_dev, psfm_quality* quality, void* stream);
 
 /*
  * The dense solve of psfm_solve on its own (Section 2: the normal equations

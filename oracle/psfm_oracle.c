@@ -848,7 +848,7 @@ int orc_norm_solve(int n, const double* norm, const uint8_t* used, double* b0, d
  * replaced by the lowest-index stamp of the same group (group >= 0) that is
  * held in reserve (flags == ORC_STAMP_RESERVE on input); it enters the next
  * solution.  stats as orc_solve, with dof = sum npix - (free unknowns + 2);
- * *n_replaced counts replacements.  Returns 0, -3, -4, or -5 (singular
+ * *n_replaced counts replacements.  Returns 0, -3, -4, or -8 (singular
  * normalisation).
  */
 int orc_solve_norm(const orc_config* c, int W, int H, const int32_t* xy, int n, const double* Ms,
@@ -883,7 +883,7 @@ int orc_solve_norm(const orc_config* c, int W, int H, const int32_t* xy, int n, 
         for (int s = 0; s < n; s++) n_used += used[s];
         if (n_used < c->min_stamps) { ret = -3; st->info = -3; break; }
         double b0, d0;
-        if (orc_norm_solve(n, norm, used, &b0, &d0)) { ret = -5; st->info = -5; break; }
+        if (orc_norm_solve(n, norm, used, &b0, &d0)) { ret = -8; st->info = -8; break; }
         orc_assemble(c, W, H, xy, n, Ms, bs, used, M, b);
         for (int i = 0; i < N; i++) coeffs[i] = 0.0;
         coeffs[0] = b0;

@@ -277,6 +277,7 @@ const char* psfm_status_string(int status) {
         case PSFM_ERR_HIP: return "HIP runtime error";
         case PSFM_ERR_WORKSPACE: return "workspace missing or too small";
         case PSFM_ERR_UNSUPPORTED: return "configuration not supported by the kernels";
+        case PSFM_ERR_NORM_SINGULAR: return "normalisation undetermined by the stamp totals";
         default: return "unknown status";
     }
 }

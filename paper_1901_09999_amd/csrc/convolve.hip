@@ -1247,3 +1247,235 @@ extern "C" int psfm_match_pair(const psfm_context* ctx, const double* coeffs, co
                                diff, diff_var, diff_mask, cov_diff, cov_diff_half, stats, ws,
                                ws_bytes, stream);
 }
+
+// ---------------------------------------------------------------- the paper's
+// normalisation and quality mode (Sections 3.2, 3.3, 3.6, 3.7)
+
+namespace {
+
+constexpr int NW_MAX = 2 * PSFM_RMAX + 1 + 2 * PSFM_HMAX;   // window side, stamp + kernel halo
+constexpr int NQ_T = 256;
+
+// Loads the (2r+1+2h)^2 window of I1 around stamp centre (xc, yc) into LDS.
+__device__ void load_stamp_window(const float* __restrict__ I1, int64_t pitch, int xc, int yc, int r,
+                                  int h, float* win) {
+    const int R = r + h, WW = 2 * R + 1;
+    for (int e = threadIdx.x; e < WW * WW; e += blockDim.x) {
+        const int wy = e / WW, wx = e - wy * WW;
+        win[e] = I1[(int64_t)(yc - R + wy) * pitch + (xc - R + wx)];
+    }
+}
+
+__device__ bool stamp_inside(int xc, int yc, int R, int W, int H) {
+    return xc - R >= 0 && yc - R >= 0 && xc + R < W && yc + R < H;
+}
+
+// Unweighted stamp sums for the separate normalisation: npix, sum A0,
+// sum I2, sum A0^2, sum A0 I2 with A0 = k_0 (x) I1 (FP64), one workgroup per
+// stamp; stamps flagged with anything but PSFM_STAMP_RESERVE get zeros.
+__global__ __launch_bounds__(NQ_T) void k_fit_norm(const double* __restrict__ k0,
+                                                   const float* __restrict__ I1,
+                                                   const float* __restrict__ I2, int W, int H,
+                                                   int64_t pitch, const int32_t* __restrict__ xy,
+                                                   const int32_t* __restrict__ flags, int r, int h,
+                                                   double* __restrict__ norm) {
+    __shared__ float win[NW_MAX * NW_MAX];
+    __shared__ double taps[(2 * PSFM_HMAX + 1) * (2 * PSFM_HMAX + 1)];
+    __shared__ double red[16];
+    const int s = blockIdx.x, tid = threadIdx.x;
+    const int xc = xy[2 * s], yc = xy[2 * s + 1];
+    const int KW = 2 * h + 1, NPX = 2 * r + 1, WW = NPX + 2 * h;
+    double* out = norm + 5 * (size_t)s;
+    if ((flags[s] & ~PSFM_STAMP_RESERVE) || !stamp_inside(xc, yc, r + h, W, H)) {
+        if (tid < 5) out[tid] = 0.0;
+        return;
+    }
+    for (int t = tid; t < KW * KW; t += NQ_T) taps[t] = k0[t];
+    load_stamp_window(I1, pitch, xc, yc, r, h, win);
+    __syncthreads();
+    double s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0, cnt = 0.0;
+    for (int p = tid; p < NPX * NPX; p += NQ_T) {
+        const int y = p / NPX, x = p - y * NPX;
+        double a0 = 0.0;
+        for (int v = -h; v <= h; v++) {
+            const float* row = win + (size_t)(y + h - v) * WW + (x + h);
+            const double* tr = taps + (v + h) * KW + h;
+            for (int u = -h; u <= h; u++) a0 += tr[u] * (double)row[-u];
+        }
+        const double d = (double)I2[(int64_t)(yc - r + y) * pitch + (xc - r + x)];
+        s1 += a0;
+        s2 += d;
+        s3 += a0 * a0;
+        s4 += a0 * d;
+        cnt += 1.0;
+    }
+    cnt = psfm_block_sum(cnt, red);
+    s1 = psfm_block_sum(s1, red);
+    s2 = psfm_block_sum(s2, red);
+    s3 = psfm_block_sum(s3, red);
+    s4 = psfm_block_sum(s4, red);
+    if (tid == 0) {
+        out[0] = cnt;
+        out[1] = s1;
+        out[2] = s2;
+        out[3] = s3;
+        out[4] = s4;
+    }
+}
+
+// Softened deviation of each used stamp: the kernel realised at the stamp
+// centre (FP64), the model m = K (x) I1 + d0 per stamp pixel, and
+// dev_s = (1/npix) sum (I2 - m)^2 / (V2 + soft |m|).  One workgroup per stamp.
+__global__ __launch_bounds__(NQ_T) void k_stamp_dev(BasisArgs B, const double* __restrict__ a,
+                                                    const float* __restrict__ I1,
+                                                    const float* __restrict__ I2,
+                                                    const float* __restrict__ V2, int W, int H,
+                                                    int64_t pitch, const int32_t* __restrict__ xy,
+                                                    const int32_t* __restrict__ flags, int r,
+                                                    double soft, double* __restrict__ dev) {
+    __shared__ RealiseLds sh;
+    __shared__ double Kd[(2 * PSFM_HMAX + 1) * (2 * PSFM_HMAX + 1)];
+    __shared__ float win[NW_MAX * NW_MAX];
+    __shared__ double red[16];
+    const int s = blockIdx.x, tid = threadIdx.x, h = B.h;
+    const int xc = xy[2 * s], yc = xy[2 * s + 1];
+    const int KW = 2 * h + 1, NPX = 2 * r + 1, WW = NPX + 2 * h;
+    if (flags[s] || !stamp_inside(xc, yc, r + h, W, H)) {
+        if (tid == 0) dev[s] = 0.0;
+        return;
+    }
+    realise_kernel(B, a, xc, yc, W, H, sh, Kd);
+    load_stamp_window(I1, pitch, xc, yc, r, h, win);
+    __syncthreads();
+    const double d0 = a[B.nb * B.ns];
+    double acc = 0.0;
+    for (int p = tid; p < NPX * NPX; p += NQ_T) {
+        const int y = p / NPX, x = p - y * NPX;
+        double m = d0;
+        for (int v = -h; v <= h; v++) {
+            const float* row = win + (size_t)(y + h - v) * WW + (x + h);
+            const double* kr = Kd + (v + h) * KW + h;
+            for (int u = -h; u <= h; u++) m += kr[u] * (double)row[-u];
+        }
+        const int64_t o = (int64_t)(yc - r + y) * pitch + (xc - r + x);
+        const double res = (double)I2[o] - m;
+        acc += res * res / ((double)V2[o] + soft * fabs(m));
+    }
+    acc = psfm_block_sum(acc, red);
+    if (tid == 0) dev[s] = acc / (double)(NPX * NPX);
+}
+
+// Aggregates: normalised mean and r.m.s. deviation over the used stamps; the
+// kernel at the image centre (sum, moments, maximum deconvolution fraction
+// over circular radii); the cut bits.  One workgroup.
+__global__ __launch_bounds__(NQ_T) void k_quality_finish(BasisArgs B, const double* __restrict__ a,
+                                                         int W, int H, int n,
+                                                         const int32_t* __restrict__ flags,
+                                                         const double* __restrict__ dev,
+                                                         psfm_quality* __restrict__ q) {
+    __shared__ RealiseLds sh;
+    __shared__ double Kd[(2 * PSFM_HMAX + 1) * (2 * PSFM_HMAX + 1)];
+    __shared__ double red[16];
+    __shared__ double enc[64];
+    const int tid = threadIdx.x, h = B.h, KW = 2 * h + 1, T = KW * KW;
+    double sm = 0.0, cnt = 0.0;
+    for (int s = tid; s < n; s += NQ_T)
+        if (!flags[s]) {
+            sm += dev[s];
+            cnt += 1.0;
+        }
+    sm = psfm_block_sum(sm, red);
+    cnt = psfm_block_sum(cnt, red);
+    const double mean = cnt > 0.0 ? sm / cnt : 0.0;
+    double sv = 0.0;
+    for (int s = tid; s < n; s += NQ_T)
+        if (!flags[s]) sv += (dev[s] - mean) * (dev[s] - mean);
+    sv = psfm_block_sum(sv, red);
+    realise_kernel(B, a, 0.5 * (W - 1), 0.5 * (H - 1), W, H, sh, Kd);
+    double s0 = 0.0, su = 0.0, sv1 = 0.0;
+    for (int t = tid; t < T; t += NQ_T) {
+        const int v = t / KW - h, u = t % KW - h;
+        s0 += Kd[t];
+        su += u * Kd[t];
+        sv1 += v * Kd[t];
+    }
+    s0 = psfm_block_sum(s0, red);
+    su = psfm_block_sum(su, red);
+    sv1 = psfm_block_sum(sv1, red);
+    const double mx = su / s0, my = sv1 / s0;
+    double sxx = 0.0, syy = 0.0;
+    for (int t = tid; t < T; t += NQ_T) {
+        const int v = t / KW - h, u = t % KW - h;
+        sxx += (u - mx) * (u - mx) * Kd[t];
+        syy += (v - my) * (v - my) * Kd[t];
+    }
+    sxx = psfm_block_sum(sxx, red);
+    syy = psfm_block_sum(syy, red);
+    const int rmax = (int)ceil(h * sqrt(2.0));
+    if (tid <= rmax) {                 // enclosed sum within radius tid
+        double e = 0.0;
+        for (int t = 0; t < T; t++) {
+            const int v = t / KW - h, u = t % KW - h;
+            if (u * u + v * v <= tid * tid) e += Kd[t];
+        }
+        enc[tid] = e / s0;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double best = enc[0];
+        for (int k = 1; k <= rmax; k++) best = fmax(best, enc[k]);
+        psfm_quality r;
+        r.n_used = (int)cnt;
+        r.dev_mean = cnt > 0.0 ? mean - 1.0 : 0.0;
+        r.dev_rms = cnt > 0.0 ? sqrt(sv / cnt) : 0.0;
+        r.kernel_sum = s0;
+        r.mom_x = mx;
+        r.mom_y = my;
+        r.mom_xx = sxx / s0;
+        r.mom_yy = syy / s0;
+        r.deconv_max = best;
+        int f = 0;
+        if (r.n_used < 3) f |= PSFM_CUT_FEW_STAMPS;
+        if (r.dev_mean > 0.5) f |= PSFM_CUT_MEAN_DEV;
+        if (r.dev_rms > 0.3) f |= PSFM_CUT_RMS_DEV;
+        if (fabs(r.mom_x) > 0.5 || fabs(r.mom_y) > 0.5) f |= PSFM_CUT_MOMENT1;
+        if (r.mom_xx < 0.0 || r.mom_yy < 0.0) f |= PSFM_CUT_MOMENT2;
+        if (r.deconv_max > 1.03) f |= PSFM_CUT_DECONV;
+        r.cut_flags = f;
+        *q = r;
+    }
+}
+
+}  // namespace
+
+extern "C" int psfm_fit_norm(const psfm_context* ctx, const float* I1, const float* I2, int W, int H,
+                             int64_t pitch, const int32_t* stamp_xy, int n_stamps,
+                             const int32_t* stamp_flags, double* stamp_norm, void* stream) {
+    if (!ctx || n_stamps < 0) return PSFM_ERR_INVALID_ARG;
+    if (W < 1 || H < 1 || pitch < W) return PSFM_ERR_SHAPE;
+    if (n_stamps == 0) return PSFM_OK;
+    if (!I1 || !I2 || !stamp_xy || !stamp_flags || !stamp_norm) return PSFM_ERR_INVALID_ARG;
+    hipLaunchKernelGGL(k_fit_norm, dim3(n_stamps), dim3(NQ_T), 0, (hipStream_t)stream, ctx->kb64, I1, I2,
+                       W, H, pitch, stamp_xy, stamp_flags, ctx->r, ctx->h, stamp_norm);
+    PSFM_HIP_CHECK(hipGetLastError());
+    return PSFM_OK;
+}
+
+extern "C" int psfm_quality_eval(const psfm_context* ctx, const double* coeffs, const float* I1,
+                                 const float* I2, const float* V2, int W, int H, int64_t pitch,
+                                 const int32_t* stamp_xy, int n_stamps, const int32_t* stamp_flags,
+                                 double soft, double* stamp_dev, psfm_quality* quality, void* stream) {
+    if (!ctx || n_stamps < 0 || !coeffs || !quality || !(soft >= 0.0)) return PSFM_ERR_INVALID_ARG;
+    if (W < 1 || H < 1 || pitch < W) return PSFM_ERR_SHAPE;
+    if (n_stamps > 0 && (!I1 || !I2 || !V2 || !stamp_xy || !stamp_flags || !stamp_dev))
+        return PSFM_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    const BasisArgs B = basis_args(ctx);
+    if (n_stamps > 0)
+        hipLaunchKernelGGL(k_stamp_dev, dim3(n_stamps), dim3(NQ_T), 0, st, B, coeffs, I1, I2, V2, W, H,
+                           pitch, stamp_xy, stamp_flags, ctx->r, soft, stamp_dev);
+    hipLaunchKernelGGL(k_quality_finish, dim3(1), dim3(NQ_T), 0, st, B, coeffs, W, H, n_stamps,
+                       stamp_flags, stamp_dev, quality);
+    PSFM_HIP_CHECK(hipGetLastError());
+    return PSFM_OK;
+}

@@ -51,6 +51,7 @@ struct SolveState {
     int prior_done;   // rejection prior converged (psfm_solve_prior)
     int n_iter_base;  // solutions before the current rejection loop (fallback restart)
     int chi2_done;    // stamps whose chi2 is in (k_chi2_clip); zero between launches
+    int n_rep;        // stamps brought in from the reserve (psfm_solve_norm)
 };
 
 // Everything the kernels need about one image pair: inputs, outputs, the

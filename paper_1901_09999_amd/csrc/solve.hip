@@ -56,6 +56,7 @@ __device__ void solve_init_body(int n, int N, int ns, int S, int W, int H, int m
             st->n_used = cnt;
             st->n_iter = 0;
             st->n_rej = 0;
+            st->n_rep = 0;
             st->prior_done = 0;
             st->n_iter_base = 0;
             st->chi2_done = 0;
@@ -1187,7 +1188,7 @@ __global__ __launch_bounds__(64) void k_chi2_clip(int n, int nb, int ns, int N,
     clip_body(n, max_iter, min_stamps, clip_sigma, npix, used, flags, chi2, st);
 }
 
-__device__ void solve_finish_body(int n, int ns, int N, int S, int W, int H,
+__device__ void solve_finish_body(int n, int ns, int N, int n_par, int S, int W, int H,
                                   const int32_t* __restrict__ npix,
                                   const uint8_t* __restrict__ used,
                                   const double* __restrict__ chi2, double* __restrict__ coeffs,
@@ -1214,8 +1215,8 @@ __device__ void solve_finish_body(int n, int ns, int N, int S, int W, int H,
         stats->info = info;
         if (info == 0) {
             stats->chi2 = c2;
-            stats->dof = np - N;
-            stats->chi2_dof = c2 / (np - N);
+            stats->dof = np - n_par;
+            stats->chi2_dof = c2 / (np - n_par);
             stats->n_used = (int)nu;
             // term 0's spatial polynomial at the image centre
             stats->kernel_sum_centre = psfm_spatial_dot(S, 0.5 * (W - 1), 0.5 * (H - 1), W, H, coeffs);
@@ -1231,6 +1232,7 @@ __device__ void solve_finish_body(int n, int ns, int N, int S, int W, int H,
         stats->n_restored = 0;
         stats->n_trusted = 0;
         stats->prior_fallback = 0;
+        stats->n_replaced = st->n_rep;
     }
 }
 
@@ -1245,16 +1247,16 @@ __global__ void k_prior_finish(const double* __restrict__ pdof, const int* __res
     }
 }
 
-__global__ void k_solve_finish(int n, int ns, int N, int S, int W, int H,
+__global__ void k_solve_finish(int n, int ns, int N, int n_par, int S, int W, int H,
                                const int32_t* __restrict__ npix, const uint8_t* __restrict__ used,
                                const double* __restrict__ chi2, double* __restrict__ coeffs,
                                const SolveState* st, psfm_fit_stats* stats) {
-    solve_finish_body(n, ns, N, S, W, H, npix, used, chi2, coeffs, st, stats);
+    solve_finish_body(n, ns, N, n_par, S, W, H, npix, used, chi2, coeffs, st, stats);
 }
 
 __global__ void k_solve_finish_b(const PairDesc* __restrict__ pairs) {
     const PairDesc& p = pairs[blockIdx.x];
-    solve_finish_body(p.n, p.ns, p.N, p.S, p.W, p.H, p.npix, p.used, p.chi2, p.coeffs, p.st,
+    solve_finish_body(p.n, p.ns, p.N, p.N, p.S, p.W, p.H, p.npix, p.used, p.chi2, p.coeffs, p.st,
                       p.stats);
 }
 
@@ -1715,6 +1717,162 @@ __global__ __launch_bounds__(1024) void k_prior_fallback(int n, double clip_sigm
     }
 }
 
+// ---- the paper's normalisation mode (Sections 3.2, 3.3)
+
+// b0 and d0, spatially constant, from the stamps in use: the unweighted
+// least-squares fit of the stamp totals T2_s = b0 T1_s + d0 npix_s (only the
+// normalisation and the background add flux; the zero-sum terms move it
+// within a stamp).  hv[0] = b0, hv[1] = d0; a singular 2 x 2 system fails the
+// solve with info PSFM_ERR_NORM_SINGULAR.  One workgroup.
+__global__ __launch_bounds__(1024) void k_norm_solve(int n, const double* __restrict__ norm,
+                                                     const uint8_t* __restrict__ used,
+                                                     double* __restrict__ hv, SolveState* st) {
+    if (st->done) return;
+    __shared__ double red[16];
+    double saa = 0.0, san = 0.0, snn = 0.0, sad = 0.0, snd = 0.0;
+    for (int s = threadIdx.x; s < n; s += blockDim.x)
+        if (used[s]) {
+            const double np = norm[5 * (size_t)s], t1 = norm[5 * (size_t)s + 1],
+                         t2 = norm[5 * (size_t)s + 2];
+            saa += t1 * t1;
+            san += t1 * np;
+            snn += np * np;
+            sad += t1 * t2;
+            snd += np * t2;
+        }
+    saa = block_sum(saa, red);
+    san = block_sum(san, red);
+    snn = block_sum(snn, red);
+    sad = block_sum(sad, red);
+    snd = block_sum(snd, red);
+    if (threadIdx.x == 0) {
+        const double det = saa * snn - san * san;
+        if (!(det > 1e-12 * saa * snn)) {
+            hv[0] = hv[1] = 0.0;
+            st->info = PSFM_ERR_NORM_SINGULAR;
+            st->done = 1;
+        } else {
+            hv[0] = (sad * snn - san * snd) / det;
+            hv[1] = (saa * snd - san * sad) / det;
+        }
+    }
+}
+
+// Holds the normalisation (term 0: b0 at spatial term 0, zero at the others)
+// and the background (d0) in the assembled equations: their columns move to
+// the right-hand side with their values, their rows and columns become those
+// of the identity, so the factorisation returns them unchanged and solves
+// M_ff a_f = b_f - M_fc a_c for the free unknowns.  One workgroup.
+__global__ __launch_bounds__(1024) void k_hold(int N, int ns, double* __restrict__ M,
+                                               double* __restrict__ b,
+                                               const double* __restrict__ hv,
+                                               const SolveState* st) {
+    if (st->done) return;
+    const double b0 = hv[0], d0 = hv[1];
+    auto held = [&](int i) { return i < ns || i == N - 1; };
+    for (int i = threadIdx.x; i < N; i += blockDim.x)
+        if (!held(i)) b[i] -= M[(size_t)i * N] * b0 + M[(size_t)i * N + N - 1] * d0;
+    __syncthreads();
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+        const int i = e / N, j = e - i * N;
+        if (held(i) || held(j)) M[e] = i == j ? 1.0 : 0.0;
+    }
+    for (int i = threadIdx.x; i < N; i += blockDim.x)
+        if (held(i)) b[i] = i == 0 ? b0 : (i == N - 1 ? d0 : 0.0);
+}
+
+// The method's sigma-clip (as clip_body) with replacement (Section 3.3): each
+// stamp rejected in this round is replaced by a reserve of its group (a stamp
+// whose flags are exactly PSFM_STAMP_RESERVE with the same group id >= 0),
+// the group's reserves taken in index order.  newrej / act: scratch flags.
+__global__ __launch_bounds__(1024) void k_clip_replace(int n, int max_iter, int min_stamps,
+                                                       double clip_sigma,
+                                                       const int32_t* __restrict__ npix,
+                                                       const int32_t* __restrict__ group,
+                                                       uint8_t* __restrict__ used,
+                                                       uint8_t* __restrict__ fitted,
+                                                       int32_t* __restrict__ flags,
+                                                       const double* __restrict__ chi2,
+                                                       uint8_t* __restrict__ newrej,
+                                                       uint8_t* __restrict__ act, SolveState* st) {
+    if (st->done) return;
+    __shared__ double red[16];
+    __shared__ double s_thr;
+    const int tid = threadIdx.x;
+    for (int s = tid; s < n; s += blockDim.x) newrej[s] = 0;
+    __syncthreads();
+    if (tid == 0) st->n_iter += 1;
+    __syncthreads();
+    if (st->n_iter - st->n_iter_base >= max_iter) {
+        if (tid == 0) st->done = 1;
+        return;
+    }
+    double sq = 0.0, cnt = 0.0;
+    for (int s = tid; s < n; s += blockDim.x)
+        if (used[s]) {
+            sq += chi2[s] / npix[s];
+            cnt += 1.0;
+        }
+    const double tot = block_sum(sq, red);
+    const double nu = block_sum(cnt, red);
+    const double mean = tot / nu;
+    double dv = 0.0;
+    for (int s = tid; s < n; s += blockDim.x)
+        if (used[s]) {
+            const double d = chi2[s] / npix[s] - mean;
+            dv += d * d;
+        }
+    const double var = block_sum(dv, red) / nu;
+    if (tid == 0) s_thr = mean + clip_sigma * sqrt(var);
+    __syncthreads();
+    const double thr = s_thr;
+    double nnew = 0.0;
+    for (int s = tid; s < n; s += blockDim.x)
+        if (used[s] && chi2[s] / npix[s] > thr) nnew += 1.0;
+    const double tnew = block_sum(nnew, red);
+    if (tnew == 0.0 || nu - tnew < (double)min_stamps) {
+        if (tid == 0) st->done = 1;
+        return;
+    }
+    for (int s = tid; s < n; s += blockDim.x)
+        if (used[s] && chi2[s] / npix[s] > thr) {
+            used[s] = 0;
+            flags[s] |= PSFM_STAMP_REJECTED;
+            newrej[s] = 1;
+        }
+    __syncthreads();
+    double nact = 0.0;
+    if (group) {
+        // reserve q of group g comes in if fewer of g's reserves precede it
+        // than g lost stamps in this round
+        for (int q = tid; q < n; q += blockDim.x) {
+            act[q] = 0;
+            const int g = group[q];
+            if (flags[q] != PSFM_STAMP_RESERVE || g < 0) continue;
+            int lost = 0, before = 0;
+            for (int s = 0; s < n; s++) {
+                lost += newrej[s] && group[s] == g;
+                before += s < q && flags[s] == PSFM_STAMP_RESERVE && group[s] == g;
+            }
+            act[q] = before < lost;
+        }
+        __syncthreads();
+        for (int q = tid; q < n; q += blockDim.x)
+            if (act[q]) {
+                flags[q] = 0;
+                used[q] = 1;
+                fitted[q] = 1;
+                nact += 1.0;
+            }
+    }
+    nact = block_sum(nact, red);
+    if (tid == 0) {
+        st->n_rej += (int)tnew;
+        st->n_used += (int)nact - (int)tnew;
+        st->n_rep += (int)nact;
+    }
+}
+
 }  // namespace
 
 namespace psfm {
@@ -1742,6 +1900,9 @@ size_t solve_workspace(const psfm_context* ctx, int n) {
     c.take<double>((size_t)n * ctx->L + 1);          // prior: each stamp's own least-squares kernel
     c.take<double>(n + 1);                           // prior: its chi2 (the solved value)
     c.take<uint8_t>(n + 1);                          // prior: stamps with a kernel estimate
+    c.take<double>(2);                               // normalisation mode: b0, d0
+    c.take<uint8_t>(n + 1);                          // normalisation mode: rejected this round
+    c.take<uint8_t>(n + 1);                          // normalisation mode: reserves to bring in
     if (ctx->cfg.precision != PSFM_PREC_FP32)
         c.take<double>((size_t)ctx->N * ctx->N);     // transposed factor (refinement)
     return c.off;
@@ -1850,6 +2011,9 @@ static int solve_impl(const psfm_context* ctx, int W, int H, const int32_t* stam
     double* pls = c.take<double>((size_t)n_stamps * ctx->L + 1);
     double* pchi2ls = c.take<double>(n_stamps + 1);
     uint8_t* ptrust = c.take<uint8_t>(n_stamps + 1);
+    c.take<double>(2);
+    c.take<uint8_t>(n_stamps + 1);
+    c.take<uint8_t>(n_stamps + 1);
     double* LT = mixed ? c.take<double>((size_t)ctx->N * ctx->N) : nullptr;   // transposed factor
     const int nb = ctx->nb, ns = ctx->ns, N = ctx->N, L = ctx->L;
     const int npix = (2 * ctx->r + 1) * (2 * ctx->r + 1);
@@ -1940,7 +2104,7 @@ static int solve_impl(const psfm_context* ctx, int W, int H, const int32_t* stam
             if (rc) return rc;
         }
     }
-    hipLaunchKernelGGL(k_solve_finish, dim3(1), dim3(1024), 0, st, n_stamps, ns, N,
+    hipLaunchKernelGGL(k_solve_finish, dim3(1), dim3(1024), 0, st, n_stamps, ns, N, N,
                        cf.spatial_order, W, H, stamp_npix, used, stamp_chi2, coeffs, state, stats);
     if (prior && n_stamps > 0)
         hipLaunchKernelGGL(k_prior_finish, dim3(1), dim3(64), 0, st, pdof, pcounts, stats);
@@ -2009,6 +2173,90 @@ extern "C" int psfm_solve_stamps(const psfm_context* ctx, int n_stamps, const do
     if (ctx->L > 64) return PSFM_ERR_UNSUPPORTED;
     hipLaunchKernelGGL(k_solve_stamps, dim3(n_stamps), dim3(64), 0, (hipStream_t)stream, ctx->L,
                        stamp_M, stamp_b, stamp_e, stamp_flags, local, stamp_chi2);
+    PSFM_HIP_CHECK(hipGetLastError());
+    return PSFM_OK;
+}
+
+extern "C" int psfm_solve_norm(const psfm_context* ctx, int W, int H, const int32_t* stamp_xy,
+                               int n_stamps, const double* stamp_M, const double* stamp_b,
+                               const double* stamp_e, const int32_t* stamp_npix,
+                               const double* stamp_norm, const int32_t* stamp_group,
+                               int32_t* stamp_flags, double* coeffs, double* stamp_chi2,
+                               psfm_fit_stats* stats, void* ws, size_t ws_bytes, void* stream) {
+    if (!ctx || n_stamps < 0 || !coeffs || !stats) return PSFM_ERR_INVALID_ARG;
+    if (ctx->cfg.precision != PSFM_PREC_FP32) return PSFM_ERR_UNSUPPORTED;
+    if (W < 1 || H < 1) return PSFM_ERR_SHAPE;
+    if (n_stamps > 0 && (!stamp_xy || !stamp_M || !stamp_b || !stamp_e || !stamp_npix ||
+                         !stamp_norm || !stamp_flags || !stamp_chi2))
+        return PSFM_ERR_INVALID_ARG;
+    if (ctx->N > CH_NMAX) return PSFM_ERR_UNSUPPORTED;
+    const size_t need = psfm::solve_workspace(ctx, n_stamps);
+    if (!ws || ws_bytes < need) return PSFM_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t lds = psfm::solve_lds_bytes(ctx->N);
+    const int nb = ctx->nb, ns = ctx->ns, N = ctx->N, L = ctx->L;
+    psfm::Carver c(ws);
+    SolveState* state = c.take<SolveState>(1);
+    uint8_t* used = c.take<uint8_t>(n_stamps + 1);
+    uint8_t* fitted = c.take<uint8_t>(n_stamps + 1);
+    double* G = c.take<double>((size_t)n_stamps * ns + 1);
+    double* M = c.take<double>((size_t)N * N);
+    double* b = c.take<double>(N);
+    double* ILg = c.take<double>(psfm::solve_il_doubles(N));
+    double* Mt = c.take<double>((size_t)n_stamps * L * L + 1);
+    double* bt = c.take<double>((size_t)n_stamps * L + 1);
+    c.take<double>(N);
+    c.take<double>((size_t)n_stamps * L + 1);
+    c.take<double>(N);
+    c.take<double>((size_t)n_stamps * L + 1);
+    c.take<double>(n_stamps + 1);
+    c.take<double>(n_stamps + 1);
+    c.take<double>(N);
+    c.take<double>(1);
+    c.take<int>(4);
+    c.take<double>((size_t)n_stamps * L + 1);
+    c.take<double>(n_stamps + 1);
+    c.take<uint8_t>(n_stamps + 1);
+    double* hv = c.take<double>(2);
+    uint8_t* newrej = c.take<uint8_t>(n_stamps + 1);
+    uint8_t* act = c.take<uint8_t>(n_stamps + 1);
+    const psfm_config& cf = ctx->cfg;
+    int rc = psfm::solve_lds_grant(lds);
+    if (rc) return rc;
+    const int nt = std::max(n_stamps, N);
+    const int n_init = (nt + 255) / 256;
+    const int tiles = n_stamps > 0 ? (n_stamps + TS_K - 1) / TS_K * ((L * L + L + TS_R - 1) / TS_R) : 0;
+    hipLaunchKernelGGL(k_solve_prep, dim3(n_init + std::min(tiles, 1024)), dim3(256), 0, st, n_init,
+                       n_stamps, N, ns, cf.spatial_order, W, H, cf.min_stamps, L, stamp_xy, stamp_flags,
+                       used, fitted, G, stamp_chi2, coeffs, state, stamp_M, stamp_b, Mt, bt);
+    PSFM_HIP_CHECK(hipGetLastError());
+    const int nthreads_asm = L * L * ns + L * ns;
+    const dim3 ag((nthreads_asm + ASM_ITEMS - 1) / ASM_ITEMS);
+    for (int it = 0; it < cf.max_iter; it++) {
+        hipLaunchKernelGGL(k_norm_solve, dim3(1), dim3(1024), 0, st, n_stamps, stamp_norm, used, hv, state);
+        switch (ns) {
+#define PSFM_ASM_CASE(NSV) \
+    case NSV: hipLaunchKernelGGL(k_assemble<NSV>, ag, dim3(256), 0, st, n_stamps, nb, N, Mt, bt, G, used, M, b, state); break;
+            PSFM_ASM_CASE(1) PSFM_ASM_CASE(3) PSFM_ASM_CASE(6) PSFM_ASM_CASE(10) PSFM_ASM_CASE(15)
+            PSFM_ASM_CASE(21) PSFM_ASM_CASE(28)
+#undef PSFM_ASM_CASE
+            default: return PSFM_ERR_UNSUPPORTED;
+        }
+        hipLaunchKernelGGL(k_hold, dim3(1), dim3(1024), 0, st, N, ns, M, b, hv, state);
+        hipLaunchKernelGGL(k_cholesky<false>, dim3(1), dim3(CH_THREADS), lds, st, N, M, b, coeffs, ILg,
+                           nullptr, state, nullptr, nullptr, nullptr);
+        if (n_stamps > 0) {
+            hipLaunchKernelGGL(k_chi2, dim3(n_stamps), dim3(64), 0, st, nb, ns, N, stamp_M, stamp_b,
+                               stamp_e, G, coeffs, fitted, stamp_chi2, state);
+            hipLaunchKernelGGL(k_clip_replace, dim3(1), dim3(1024), 0, st, n_stamps, cf.max_iter,
+                               cf.min_stamps, cf.clip_sigma, stamp_npix, stamp_group, used, fitted,
+                               stamp_flags, stamp_chi2, newrej, act, state);
+        }
+        PSFM_HIP_CHECK(hipGetLastError());
+    }
+    // fitted parameters: the free unknowns plus b0 and d0
+    hipLaunchKernelGGL(k_solve_finish, dim3(1), dim3(1024), 0, st, n_stamps, ns, N, N - ns + 1,
+                       cf.spatial_order, W, H, stamp_npix, used, stamp_chi2, coeffs, state, stats);
     PSFM_HIP_CHECK(hipGetLastError());
     return PSFM_OK;
 }

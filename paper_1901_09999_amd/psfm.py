@@ -62,6 +62,7 @@ class CStats(C.Structure):
         ("n_restored", C.c_int),
         ("n_trusted", C.c_int),
         ("prior_fallback", C.c_int),
+        ("n_replaced", C.c_int),
     ]
 
     def as_dict(self):
@@ -69,6 +70,30 @@ class CStats(C.Structure):
 
 
 STATS_BYTES = C.sizeof(CStats)
+
+STAMP_RESERVE = 32
+CUT_FEW_STAMPS, CUT_MEAN_DEV, CUT_RMS_DEV, CUT_MOMENT1, CUT_MOMENT2, CUT_DECONV = 1, 2, 4, 8, 16, 32
+
+
+class CQuality(C.Structure):
+    _fields_ = [
+        ("dev_mean", C.c_double),
+        ("dev_rms", C.c_double),
+        ("kernel_sum", C.c_double),
+        ("mom_x", C.c_double),
+        ("mom_y", C.c_double),
+        ("mom_xx", C.c_double),
+        ("mom_yy", C.c_double),
+        ("deconv_max", C.c_double),
+        ("n_used", C.c_int),
+        ("cut_flags", C.c_int),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+QUALITY_BYTES = C.sizeof(CQuality)
 
 
 class CPair(C.Structure):
@@ -125,6 +150,9 @@ def lib():
                                     P, P, P, P, i, P, P, sz, P]),
             "psfm_match_pair_static": (i, [P, P, P, P, P, P, P, P, i, i, i64, P, i, P, i, P, P, P,
                                            P, i, P, P, P, P, i, P, P]),
+            "psfm_fit_norm": (i, [P, P, P, i, i, i64, P, i, P, P, P]),
+            "psfm_solve_norm": (i, [P, i, i, P, i, P, P, P, P, P, P, P, P, P, P, P, sz, P]),
+            "psfm_quality_eval": (i, [P, P, P, P, P, i, i, i64, P, i, P, C.c_double, P, P, P]),
             "psfm_status_string": (C.c_char_p, [i]),
             "psfm_batch_workspace_bytes": (sz, [P, C.POINTER(CPair), i]),
             "psfm_batch_plan": (i, [P, C.POINTER(CPair), i, C.POINTER(CTuning), P, sz, P, P,
@@ -316,6 +344,46 @@ class Context:
                                 _ptr(out["chi2"]), _ptr(out["stats"]), _ptr(ws), ws.numel(),
                                 _stream()), "psfm_solve")
         return out
+
+    # ------------------------------------------- the paper's normalisation mode
+    def fit_norm(self, I1, I2, stamps, flags, out=None):
+        """psfm_fit_norm: per-stamp unweighted sums [n, 5] (npix, sum A0,
+        sum I2, sum A0^2, sum A0 I2)."""
+        H, W = I1.shape
+        n = stamps.shape[0]
+        out = torch.empty((max(n, 1), 5), dtype=torch.float64, device=self.device) if out is None else out
+        _check(lib().psfm_fit_norm(self._h, _ptr(I1), _ptr(I2), W, H, W, _ptr(stamps), n, _ptr(flags),
+                                   _ptr(out), _stream()), "psfm_fit_norm")
+        return out[:n]
+
+    def solve_norm(self, W, H, stamps, fit, norm, flags=None, group=None, out=None):
+        """psfm_solve_norm (b0, d0 from stamp totals, held; replacement from
+        ``group`` reserves).  Stamp flags are updated in a copy."""
+        n = stamps.shape[0]
+        dev = self.device
+        fl = (fit["flags"] if flags is None else flags).clone()
+        if out is None:
+            out = dict(coeffs=torch.empty(self.N, dtype=torch.float64, device=dev),
+                       chi2=torch.empty(max(n, 1), dtype=torch.float64, device=dev),
+                       stats=torch.zeros(STATS_BYTES, dtype=torch.uint8, device=dev))
+        out["flags"] = fl
+        ws = self.workspace(W, H, n)
+        _check(lib().psfm_solve_norm(self._h, W, H, _ptr(stamps), n, _ptr(fit["M"]), _ptr(fit["b"]),
+                                     _ptr(fit["e"]), _ptr(fit["npix"]), _ptr(norm), _ptr(group), _ptr(fl),
+                                     _ptr(out["coeffs"]), _ptr(out["chi2"]), _ptr(out["stats"]), _ptr(ws),
+                                     ws.numel(), _stream()), "psfm_solve_norm")
+        return out
+
+    def quality(self, coeffs, I1, I2, V2, stamps, flags, soft=0.0):
+        """psfm_quality_eval: (quality tensor, per-stamp deviations)."""
+        H, W = I1.shape
+        n = stamps.shape[0]
+        dev = torch.empty(max(n, 1), dtype=torch.float64, device=self.device)
+        q = torch.zeros(QUALITY_BYTES, dtype=torch.uint8, device=self.device)
+        _check(lib().psfm_quality_eval(self._h, _ptr(coeffs), _ptr(I1), _ptr(I2), _ptr(V2), W, H, W,
+                                       _ptr(stamps), n, _ptr(flags), float(soft), _ptr(dev), _ptr(q),
+                                       _stream()), "psfm_quality_eval")
+        return q, dev[:n]
 
     def convolve_image(self, coeffs, I, M, out=None, out_mask=None):
         H, W = I.shape
@@ -598,6 +666,11 @@ def cholesky_solve(M: torch.Tensor, b: torch.Tensor, x: Optional[torch.Tensor] =
     return x, info
 
 
+def read_quality(q: torch.Tensor) -> dict:
+    raw = bytes(q.cpu().numpy().tobytes())
+    return CQuality.from_buffer_copy(raw[:QUALITY_BYTES]).as_dict()
+
+
 def read_stats(stats: torch.Tensor) -> dict:
     raw = bytes(stats.cpu().numpy().tobytes())
     return CStats.from_buffer_copy(raw[:STATS_BYTES]).as_dict()
@@ -620,6 +693,7 @@ def exported_symbols() -> Sequence[str]:
             "psfm_batch_run", "psfm_batch_run_stage", "psfm_batch_set_tuning", "psfm_batch_graph_capture",
             "psfm_batch_graph_launch", "psfm_batch_destroy", "psfm_wall_clock_hz",
             "psfm_solve_stamps", "psfm_solve_prior", "psfm_cholesky_workspace_bytes",
+            "psfm_fit_norm", "psfm_solve_norm", "psfm_quality_eval",
             "psfm_cholesky_solve", "psfm_cnn_param_count",
             "psfm_cnn_workspace_bytes", "psfm_cnn_forward", "psfm_cnn_loss_grad",
             "psfm_cnn_loss_weights", "psfm_cnn_adam",

@@ -76,7 +76,11 @@ def test_host_argument_checks(lib):
                                None) == -1
     assert lib.psfm_solve(None, 10, 10, None, 1, *([None] * 9), None, 0, None) == -1
     assert lib.psfm_convolve_image(None, None, None, None, 10, 10, 10, None, None, None, 0, None) == -1
-    for code in range(-7, 1):
+    assert lib.psfm_fit_norm(None, None, None, 10, 10, 10, None, 1, None, None, None) == -1
+    assert lib.psfm_solve_norm(None, 10, 10, None, 1, *([None] * 10), None, 0, None) == -1
+    assert lib.psfm_quality_eval(None, None, None, None, None, 10, 10, 10, None, 1, None, 0.0, None,
+                                 None, None) == -1
+    for code in range(-8, 1):
         assert lib.psfm_status_string(code).decode()
 
 
