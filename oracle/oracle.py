@@ -128,6 +128,9 @@ def lib():
                                    C.POINTER(OrcStats), C.POINTER(C.c_int)]),
             "orc_quality_eval": (None, [cfgp, P, P, P, P, P, i, i, i64, P, i, P, d, P,
                                         C.POINTER(OrcQuality)]),
+            "orc_bin": (None, [P, P, P, i, i, i64, i, P, i, P, P, P, P, i, P]),
+            "orc_resample_cov": (None, [P, i, d, P, i]),
+            "orc_add_images": (None, [d, P, P, P, P, i, d, P, P, P, P, i, i, i, i64, P, P, P, P, i]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(_lib, name)
@@ -436,3 +439,45 @@ def quality(cfg: Config, a, I1, I2, V2, stamps, flags, soft=0.0, kb=None):
     lib().orc_quality_eval(C.byref(cfg.c()), _p(kb), _p(_c(a, np.float64)), _p(I1), _p(I2), _p(V2), W,
                            H, W, _p(xy), n, _p(_c(flags, np.int32)), float(soft), _p(dev), C.byref(q))
     return q.as_dict(), dev
+
+
+# ------------------------------------------------ noise-model operations
+# beyond convolution (Section 4.3)
+
+def bin_image(I, V, M, B, cov_in=None, c_out=4):
+    """Integer binning: (Ib, Vb, Mb, cov_b, discarded)."""
+    I, V = _c(I, np.float32), _c(V, np.float32)
+    M = _c(M, np.uint8)
+    H, W = I.shape
+    Wb, Hb = W // B, H // B
+    Ib = np.zeros((Hb, Wb), np.float32); Vb = np.zeros((Hb, Wb), np.float32)
+    Mb = np.zeros((Hb, Wb), np.uint8); cov = np.zeros((2 * c_out + 1, 2 * c_out + 1))
+    c_in = 0 if cov_in is None else (np.asarray(cov_in).shape[0] - 1) // 2
+    disc = C.c_double(0.0)
+    lib().orc_bin(_p(I), _p(V), _p(M), W, H, W, B,
+                  _p(None if cov_in is None else _c(cov_in, np.float64)), c_in, _p(Ib), _p(Vb), _p(Mb),
+                  _p(cov), c_out, C.byref(disc))
+    return Ib, Vb, Mb, cov, disc.value
+
+
+def resample_cov(cov_in, scale, c_out):
+    cov_in = _c(cov_in, np.float64)
+    out = np.zeros((2 * c_out + 1, 2 * c_out + 1))
+    lib().orc_resample_cov(_p(cov_in), (cov_in.shape[0] - 1) // 2, float(scale), _p(out), c_out)
+    return out
+
+
+def add_images(alpha, Ia, Va, Ma, Ca, beta, Ib, Vb, Mb, Cb, cs):
+    """S = alpha Ia + beta Ib with variance, mask and pseudo-matrix."""
+    Ia, Va, Ib, Vb = (_c(x, np.float32) for x in (Ia, Va, Ib, Vb))
+    Ma, Mb = _c(Ma, np.uint8), _c(Mb, np.uint8)
+    H, W = Ia.shape
+    S = np.zeros((H, W), np.float32); VS = np.zeros((H, W), np.float32)
+    MS = np.zeros((H, W), np.uint8); CS = np.zeros((2 * cs + 1, 2 * cs + 1))
+    ca = 0 if Ca is None else (np.asarray(Ca).shape[0] - 1) // 2
+    cb = 0 if Cb is None else (np.asarray(Cb).shape[0] - 1) // 2
+    lib().orc_add_images(float(alpha), _p(Ia), _p(Va), _p(Ma),
+                         _p(None if Ca is None else _c(Ca, np.float64)), ca, float(beta), _p(Ib), _p(Vb),
+                         _p(Mb), _p(None if Cb is None else _c(Cb, np.float64)), cb, W, H, W, _p(S),
+                         _p(VS), _p(MS), _p(CS), cs)
+    return S, VS, MS, CS

@@ -1067,3 +1067,159 @@ void orc_quality_eval(const orc_config* c, const double* kb, const double* a, co
     if (q->deconv_max > 1.03) f |= ORC_CUT_DECONV;
     q->cut_flags = f;
 }
+
+/* ------------------------------------------------------------------------
+ * Noise-model operations beyond convolution (Section 4.3, "Use in practise").
+ */
+
+/*
+ * Binning by an integer factor B (Section 4.3): a convolution with a
+ * constant B x B kernel followed by a change of scale.  Output pixel (X, Y)
+ * of the (W / B) x (H / B) image (partial blocks at the right and bottom
+ * edges dropped) is the sum over its block; pixels masked in the input
+ * contribute nothing and set the output mask (OR of the block's masks).
+ * With the box kernel k = 1 the convolution rules give
+ *     raw(D) = sum_{u,u' in block} C_in(D + u - u')  (pseudo-matrix of the sum),
+ *     V_b = f * sum_block V,   f = raw(0) / B^2  (covariance factor moved in),
+ * and the change of scale samples the pseudo-matrix at multiples of B:
+ *     C_b(D) = raw(B D) / raw(0),  |D| <= c_out per axis.
+ * cov_in: (2 c_in + 1)^2, NULL = uncorrelated.  Output planes have pitch
+ * W / B.  *discarded: share of sum |raw(B D) / raw(0)| cut off by the crop.
+ */
+void orc_bin(const float* I, const float* V, const uint8_t* Mk, int W, int H, int64_t pitch, int B,
+             const double* cov_in, int c_in, float* Ib, float* Vb, uint8_t* Mb, double* cov_out,
+             int c_out, double* discarded) {
+    const int Wb = W / B, Hb = H / B, Cw = 2 * c_in + 1;
+    /* raw pseudo-matrix of the block sum at fine offsets |D| <= (B-1) + c_in */
+    const int R = B - 1 + c_in, Rw = 2 * R + 1;
+    double* raw = (double*)calloc((size_t)Rw * Rw, sizeof(double));
+    for (int dy = -R; dy <= R; dy++)
+        for (int dx = -R; dx <= R; dx++) {
+            double s = 0.0;
+            for (int v = 0; v < B; v++)
+                for (int u = 0; u < B; u++)
+                    for (int v2 = 0; v2 < B; v2++)
+                        for (int u2 = 0; u2 < B; u2++) {
+                            const int wx = dx + u - u2, wy = dy + v - v2;
+                            if (wx < -c_in || wx > c_in || wy < -c_in || wy > c_in) continue;
+                            s += cov_in ? cov_in[(wy + c_in) * Cw + (wx + c_in)]
+                                        : (wx == 0 && wy == 0 ? 1.0 : 0.0);
+                        }
+            raw[(dy + R) * Rw + (dx + R)] = s;
+        }
+    const double raw0 = raw[R * Rw + R];
+    const double f = raw0 / ((double)B * B);
+    for (int Y = 0; Y < Hb; Y++)
+        for (int X = 0; X < Wb; X++) {
+            double si = 0.0, sv = 0.0;
+            uint8_t m = 0;
+            for (int v = 0; v < B; v++)
+                for (int u = 0; u < B; u++) {
+                    const int64_t o = (int64_t)(B * Y + v) * pitch + (B * X + u);
+                    if (Mk[o]) {
+                        m = 1;
+                    } else {
+                        si += I[o];
+                        sv += V[o];
+                    }
+                }
+            Ib[(int64_t)Y * Wb + X] = (float)si;
+            Vb[(int64_t)Y * Wb + X] = (float)(f * sv);
+            Mb[(int64_t)Y * Wb + X] = m;
+        }
+    /* coarse pseudo-matrix: raw at multiples of B, normalised to the centre */
+    const int Rc = R / B, Ow = 2 * c_out + 1;
+    double tot = 0.0, kept = 0.0;
+    for (int DY = -Rc; DY <= Rc; DY++)
+        for (int DX = -Rc; DX <= Rc; DX++) tot += fabs(raw[(B * DY + R) * Rw + (B * DX + R)] / raw0);
+    for (int DY = -c_out; DY <= c_out; DY++)
+        for (int DX = -c_out; DX <= c_out; DX++) {
+            double val = 0.0;
+            if (abs(DX) <= Rc && abs(DY) <= Rc) val = raw[(B * DY + R) * Rw + (B * DX + R)] / raw0;
+            cov_out[(DY + c_out) * Ow + (DX + c_out)] = val;
+            kept += fabs(val);
+        }
+    if (discarded) *discarded = tot > 0.0 ? (tot - kept) / tot : 0.0;
+    free(raw);
+}
+
+/*
+ * Resampling of a pseudo-matrix to a new pixel scale (Section 4.3): an
+ * output pixel spans `scale` input pixels, so output offset D samples the
+ * input pseudo-matrix at scale * D by bilinear interpolation (zero beyond
+ * its extent).  The centre stays 1 (zero offset is a grid point); the
+ * off-centre entries are then scaled together so that their sum -- the
+ * total covariance excluding the variance -- equals the input's.
+ * cov_in (2 c_in + 1)^2 with centre 1; cov_out (2 c_out + 1)^2.
+ */
+void orc_resample_cov(const double* cov_in, int c_in, double scale, double* cov_out, int c_out) {
+    const int Cw = 2 * c_in + 1, Ow = 2 * c_out + 1;
+    double tin = 0.0, tout = 0.0;
+    for (int t = 0; t < Cw * Cw; t++)
+        if (t != c_in * Cw + c_in) tin += cov_in[t];
+    for (int DY = -c_out; DY <= c_out; DY++)
+        for (int DX = -c_out; DX <= c_out; DX++) {
+            const double x = scale * DX, y = scale * DY;
+            const double fx = floor(x), fy = floor(y);
+            const double tx = x - fx, ty = y - fy;
+            double val = 0.0;
+            for (int j = 0; j < 2; j++)
+                for (int i = 0; i < 2; i++) {
+                    const int px = (int)fx + i, py = (int)fy + j;
+                    if (px < -c_in || px > c_in || py < -c_in || py > c_in) continue;
+                    const double w = (i ? tx : 1.0 - tx) * (j ? ty : 1.0 - ty);
+                    val += w * cov_in[(py + c_in) * Cw + (px + c_in)];
+                }
+            cov_out[(DY + c_out) * Ow + (DX + c_out)] = val;
+            if (DX != 0 || DY != 0) tout += val;
+        }
+    const double a = tout != 0.0 ? tin / tout : 0.0;
+    for (int DY = -c_out; DY <= c_out; DY++)
+        for (int DX = -c_out; DX <= c_out; DX++)
+            if (DX != 0 || DY != 0) cov_out[(DY + c_out) * Ow + (DX + c_out)] *= a;
+}
+
+/*
+ * Weighted sum of two images (Section 4.3, adding or subtracting images):
+ *     S = alpha Ia + beta Ib,  V_S = alpha^2 Va + beta^2 Vb,
+ *     mask_S = mask_a | mask_b (S and V_S are 0 where it is set),
+ *     C_S = (wa Ca + wb Cb) / (wa + wb),  wa = alpha^2 mean(Va),
+ *     wb = beta^2 mean(Vb)
+ * with the means over each image's unmasked pixels (the weights of the
+ * weighted average are the average variances of the two terms).  Ca, Cb
+ * ((2 ca + 1)^2, (2 cb + 1)^2; NULL = uncorrelated) are zero-padded or
+ * cropped to (2 cs + 1)^2.
+ */
+void orc_add_images(double alpha, const float* Ia, const float* Va, const uint8_t* Ma,
+                    const double* Ca, int ca, double beta, const float* Ib, const float* Vb,
+                    const uint8_t* Mb, const double* Cb, int cb, int W, int H, int64_t pitch,
+                    float* S, float* VS, uint8_t* MS, double* CS, int cs) {
+    double sa = 0.0, sb = 0.0;
+    long na = 0, nbp = 0;
+    for (int y = 0; y < H; y++)
+        for (int x = 0; x < W; x++) {
+            const int64_t o = (int64_t)y * pitch + x;
+            if (!Ma[o]) { sa += Va[o]; na++; }
+            if (!Mb[o]) { sb += Vb[o]; nbp++; }
+            const uint8_t m = (uint8_t)(Ma[o] | Mb[o]);
+            MS[o] = m;
+            if (m) {
+                S[o] = 0.0f;
+                VS[o] = 0.0f;
+            } else {
+                S[o] = (float)(alpha * (double)Ia[o] + beta * (double)Ib[o]);
+                VS[o] = (float)(alpha * alpha * (double)Va[o] + beta * beta * (double)Vb[o]);
+            }
+        }
+    const double wa = alpha * alpha * (na ? sa / na : 0.0), wb = beta * beta * (nbp ? sb / nbp : 0.0);
+    const int Sw = 2 * cs + 1;
+    for (int dy = -cs; dy <= cs; dy++)
+        for (int dx = -cs; dx <= cs; dx++) {
+            double va, vb;
+            if (Ca) va = (abs(dx) <= ca && abs(dy) <= ca) ? Ca[(dy + ca) * (2 * ca + 1) + (dx + ca)] : 0.0;
+            else va = (dx == 0 && dy == 0) ? 1.0 : 0.0;
+            if (Cb) vb = (abs(dx) <= cb && abs(dy) <= cb) ? Cb[(dy + cb) * (2 * cb + 1) + (dx + cb)] : 0.0;
+            else vb = (dx == 0 && dy == 0) ? 1.0 : 0.0;
+            CS[(dy + cs) * Sw + (dx + cs)] = (wa + wb) > 0.0 ? (wa * va + wb * vb) / (wa + wb) : 0.0;
+        }
+}
