@@ -473,6 +473,54 @@ int psfm_match_pair_static(const psfm_context* ctx, const double* coeffs, const 
                            void* stream);
 
 /*
+ * Noise-model operations beyond convolution (Section 4.3).  These need no
+ * context.  Pseudo-matrices are (2c + 1)^2 float64 arrays centred on zero
+ * offset, NULL meaning the uncorrelated (unit centre) one.
+ *
+ * psfm_bin_image: binning by an integer factor B (1..64) as a convolution
+ * with a constant B x B kernel followed by a change of scale.  Output pixel
+ * (X, Y) of the (W / B) x (H / B) planes (partial blocks at the right and
+ * bottom edges dropped; pitch_b in elements) holds the sum of the block's
+ * unmasked pixels, Mb = 1 if any pixel of the block is masked, and
+ *   Vb = f * (sum of the block's unmasked variances),  f = raw(0) / B^2,
+ *   raw(D) = sum_{u, u' in block} C_in(D + u - u'),
+ * the covariance factor of the block sum moved into the variance map; the
+ * pseudo-matrix of the binned image is raw sampled at multiples of B,
+ * cov_out(D) = raw(B D) / raw(0), cropped or zero-padded to cov_out_half
+ * (*discarded, device, nullable: share of its sum |.| cut off).
+ */
+int psfm_bin_image(const float* I, const float* V, const uint8_t* M, int W, int H, int64_t pitch,
+                   int B, const double* cov_in, int cov_in_half, float* Ib, float* Vb, uint8_t* Mb,
+                   int64_t pitch_b, double* cov_out, int cov_out_half, double* discarded,
+                   void* stream);
+
+/*
+ * psfm_resample_cov: a pseudo-matrix carried to a new pixel scale (an output
+ * pixel spans `scale` input pixels, scale > 0): output offset D takes the
+ * bilinear interpolation of cov_in at scale * D (zero beyond its extent);
+ * the centre stays cov_in's (1), and the off-centre entries are scaled
+ * together so that their sum -- the total covariance excluding the variance
+ * -- equals cov_in's.  Both device arrays, half-sizes up to 256.
+ */
+int psfm_resample_cov(const double* cov_in, int cov_in_half, double scale, double* cov_out,
+                      int cov_out_half, void* stream);
+
+/*
+ * psfm_add_images: S = alpha Ia + beta Ib (adding or subtracting images),
+ * V_S = alpha^2 Va + beta^2 Vb, MS = Ma | Mb (S = V_S = 0 where it is
+ * non-zero), and cov_s = (wa cov_a + wb cov_b) / (wa + wb) with the weights
+ * wa = alpha^2 mean(Va), wb = beta^2 mean(Vb), each mean over that input's
+ * unmasked pixels; inputs zero-padded or cropped to cov_s_half.  All planes
+ * W x H with `pitch`.  ws: device scratch of PSFM_ADD_WORKSPACE_BYTES.
+ */
+#define PSFM_ADD_WORKSPACE_BYTES 32768
+int psfm_add_images(double alpha, const float* Ia, const float* Va, const uint8_t* Ma,
+                    const double* cov_a, int cov_a_half, double beta, const float* Ib,
+                    const float* Vb, const uint8_t* Mb, const double* cov_b, int cov_b_half, int W,
+                    int H, int64_t pitch, float* S, float* VS, uint8_t* MS, double* cov_s,
+                    int cov_s_half, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * Batched matching of many independent image pairs: the whole path of the
  * calls above (fit, solve with rejection, image and variance convolution,
  * covariance pseudo-matrix, difference) for every pair of a batch, with each

@@ -153,6 +153,10 @@ def lib():
             "psfm_fit_norm": (i, [P, P, P, i, i, i64, P, i, P, P, P]),
             "psfm_solve_norm": (i, [P, i, i, P, i, P, P, P, P, P, P, P, P, P, P, P, sz, P]),
             "psfm_quality_eval": (i, [P, P, P, P, P, i, i, i64, P, i, P, C.c_double, P, P, P]),
+            "psfm_bin_image": (i, [P, P, P, i, i, i64, i, P, i, P, P, P, i64, P, i, P, P]),
+            "psfm_resample_cov": (i, [P, i, C.c_double, P, i, P]),
+            "psfm_add_images": (i, [C.c_double, P, P, P, P, i, C.c_double, P, P, P, P, i, i, i, i64, P,
+                                    P, P, P, i, P, sz, P]),
             "psfm_status_string": (C.c_char_p, [i]),
             "psfm_batch_workspace_bytes": (sz, [P, C.POINTER(CPair), i]),
             "psfm_batch_plan": (i, [P, C.POINTER(CPair), i, C.POINTER(CTuning), P, sz, P, P,
@@ -666,6 +670,50 @@ def cholesky_solve(M: torch.Tensor, b: torch.Tensor, x: Optional[torch.Tensor] =
     return x, info
 
 
+ADD_WORKSPACE_BYTES = 32768
+
+
+def bin_image(I, V, M, B, cov_in=None, c_out=4):
+    """psfm_bin_image: (Ib, Vb, Mb, cov_b, discarded) on the device."""
+    H, W = I.shape
+    Wb, Hb = W // B, H // B
+    dev = I.device
+    Ib = torch.empty((Hb, Wb), dtype=torch.float32, device=dev)
+    Vb = torch.empty((Hb, Wb), dtype=torch.float32, device=dev)
+    Mb = torch.empty((Hb, Wb), dtype=torch.uint8, device=dev)
+    cov = torch.empty((2 * c_out + 1, 2 * c_out + 1), dtype=torch.float64, device=dev)
+    disc = torch.zeros(1, dtype=torch.float64, device=dev)
+    c_in = 0 if cov_in is None else (cov_in.shape[0] - 1) // 2
+    _check(lib().psfm_bin_image(_ptr(I), _ptr(V), _ptr(M), W, H, W, B, _ptr(cov_in), c_in, _ptr(Ib),
+                                _ptr(Vb), _ptr(Mb), Wb, _ptr(cov), c_out, _ptr(disc), _stream()),
+           "psfm_bin_image")
+    return Ib, Vb, Mb, cov, disc
+
+
+def resample_cov(cov_in, scale, c_out):
+    out = torch.empty((2 * c_out + 1, 2 * c_out + 1), dtype=torch.float64, device=cov_in.device)
+    _check(lib().psfm_resample_cov(_ptr(cov_in), (cov_in.shape[0] - 1) // 2, float(scale), _ptr(out),
+                                   c_out, _stream()), "psfm_resample_cov")
+    return out
+
+
+def add_images(alpha, Ia, Va, Ma, cov_a, beta, Ib, Vb, Mb, cov_b, cs, out=None, ws=None):
+    """psfm_add_images: dict(S, VS, MS, cov)."""
+    H, W = Ia.shape
+    dev = Ia.device
+    if out is None:
+        out = dict(S=torch.empty_like(Ia), VS=torch.empty_like(Va), MS=torch.empty_like(Ma),
+                   cov=torch.empty((2 * cs + 1, 2 * cs + 1), dtype=torch.float64, device=dev))
+    ws = torch.empty(ADD_WORKSPACE_BYTES, dtype=torch.uint8, device=dev) if ws is None else ws
+    ca = 0 if cov_a is None else (cov_a.shape[0] - 1) // 2
+    cb = 0 if cov_b is None else (cov_b.shape[0] - 1) // 2
+    _check(lib().psfm_add_images(float(alpha), _ptr(Ia), _ptr(Va), _ptr(Ma), _ptr(cov_a), ca, float(beta),
+                                 _ptr(Ib), _ptr(Vb), _ptr(Mb), _ptr(cov_b), cb, W, H, W, _ptr(out["S"]),
+                                 _ptr(out["VS"]), _ptr(out["MS"]), _ptr(out["cov"]), cs, _ptr(ws),
+                                 ws.numel(), _stream()), "psfm_add_images")
+    return out
+
+
 def read_quality(q: torch.Tensor) -> dict:
     raw = bytes(q.cpu().numpy().tobytes())
     return CQuality.from_buffer_copy(raw[:QUALITY_BYTES]).as_dict()
@@ -693,7 +741,8 @@ def exported_symbols() -> Sequence[str]:
             "psfm_batch_run", "psfm_batch_run_stage", "psfm_batch_set_tuning", "psfm_batch_graph_capture",
             "psfm_batch_graph_launch", "psfm_batch_destroy", "psfm_wall_clock_hz",
             "psfm_solve_stamps", "psfm_solve_prior", "psfm_cholesky_workspace_bytes",
-            "psfm_fit_norm", "psfm_solve_norm", "psfm_quality_eval",
+            "psfm_fit_norm", "psfm_solve_norm", "psfm_quality_eval", "psfm_bin_image",
+            "psfm_resample_cov", "psfm_add_images",
             "psfm_cholesky_solve", "psfm_cnn_param_count",
             "psfm_cnn_workspace_bytes", "psfm_cnn_forward", "psfm_cnn_loss_grad",
             "psfm_cnn_loss_weights", "psfm_cnn_adam",
