@@ -131,6 +131,11 @@ def lib():
             "orc_bin": (None, [P, P, P, i, i, i64, i, P, i, P, P, P, P, i, P]),
             "orc_resample_cov": (None, [P, i, d, P, i]),
             "orc_add_images": (None, [d, P, P, P, P, i, d, P, P, P, P, i, i, i, i64, P, P, P, P, i]),
+            "orc_envelope_psf": (d, [P, i, i, P]),
+            "orc_render_target": (None, [P, i, d, i, i, i64, P]),
+            "orc_stack_reject": (None, [i, P, P, P, i64, i, i, i64, d, P]),
+            "orc_trace_mask": (None, [cfgp, P, P, P, i, i, i64, d, P]),
+            "orc_stack_combine": (None, [i, P, P, P, i64, i, i, i64, P, i, P, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(_lib, name)
@@ -481,3 +486,54 @@ def add_images(alpha, Ia, Va, Ma, Ca, beta, Ib, Vb, Mb, Cb, cs):
                          _p(Mb), _p(None if Cb is None else _c(Cb, np.float64)), cb, W, H, W, _p(S),
                          _p(VS), _p(MS), _p(CS), cs)
     return S, VS, MS, CS
+
+
+# ---------------------------------------------- PSF homogenisation (Section 5)
+
+def envelope_psf(params, half):
+    """(sigma_env, envelope image) from n x 3 (sigma_major, sigma_minor, angle)."""
+    params = _c(params, np.float64).reshape(-1, 3)
+    env = np.zeros((2 * half + 1, 2 * half + 1))
+    s = lib().orc_envelope_psf(_p(params), params.shape[0], half, _p(env))
+    return s, env
+
+
+def render_target(src, sigma, W, H):
+    src = _c(src, np.float64).reshape(-1, 3)
+    out = np.zeros((H, W), np.float32)
+    lib().orc_render_target(_p(src), src.shape[0], float(sigma), W, H, W, _p(out))
+    return out
+
+
+def stack_reject(I, V, M, nsigma):
+    """I, V, M: [n, H, W]; returns outlier flags [n, H, W] (uint8)."""
+    I, V = _c(I, np.float32), _c(V, np.float32)
+    M = _c(M, np.uint8)
+    n, H, W = I.shape
+    out = np.zeros((n, H, W), np.uint8)
+    lib().orc_stack_reject(n, _p(I), _p(V), _p(M), H * W, W, H, W, float(nsigma), _p(out))
+    return out
+
+
+def trace_mask(cfg: Config, a, outl, frac, kb=None):
+    kb = basis(cfg) if kb is None else kb
+    outl = _c(outl, np.uint8)
+    H, W = outl.shape
+    bad = np.zeros((H, W), np.uint8)
+    lib().orc_trace_mask(C.byref(cfg.c()), _p(kb), _p(_c(a, np.float64)), _p(outl), W, H, W,
+                         float(frac), _p(bad))
+    return bad
+
+
+def stack_combine(I, V, M, covs):
+    """I, V, M: [n, H, W]; covs [n, Cw, Cw].  Returns (S, VS, MS, CS, weights)."""
+    I, V = _c(I, np.float32), _c(V, np.float32)
+    M = _c(M, np.uint8)
+    covs = _c(covs, np.float64)
+    n, H, W = I.shape
+    ck = (covs.shape[1] - 1) // 2
+    S = np.zeros((H, W), np.float32); VS = np.zeros((H, W), np.float32)
+    MS = np.zeros((H, W), np.uint8); CS = np.zeros((2 * ck + 1, 2 * ck + 1)); w = np.zeros(n)
+    lib().orc_stack_combine(n, _p(I), _p(V), _p(M), H * W, W, H, W, _p(covs), ck, _p(S), _p(VS),
+                            _p(MS), _p(CS), _p(w))
+    return S, VS, MS, CS, w

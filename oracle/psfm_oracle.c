@@ -1223,3 +1223,216 @@ void orc_add_images(double alpha, const float* Ia, const float* Va, const uint8_
             CS[(dy + cs) * Sw + (dx + cs)] = (wa + wb) > 0.0 ? (wa * va + wb * vb) / (wa + wb) : 0.0;
         }
 }
+
+/* ------------------------------------------------------------------------
+ * PSF homogenisation for stacking (Section 5.1).
+ */
+
+/*
+ * Envelope PSF (Section 5.1): each input PSF, an elliptical Gaussian
+ * (params[3 k + 0..2] = sigma_major, sigma_minor, angle), is realised in a
+ * circular version with a common peak of 1 -- reading: the circular Gaussian
+ * of the major-axis width, so that it contains the input PSF -- on the grid
+ * |u|, |v| <= half; env[] receives the pixel-by-pixel maximum over the
+ * inputs, and the envelope model is the circular Gaussian of peak 1 fitted
+ * to it by least squares over its width: golden-section search of
+ * sum (env - exp(-r^2 / 2 s^2))^2 over s in [0.1, 2 max sigma_major] to a
+ * bracket of 1e-10 px.  Returns the fitted width.
+ */
+static double env_misfit(const double* env, int half, double s) {
+    const int Ew = 2 * half + 1;
+    double q = 0.0;
+    for (int v = -half; v <= half; v++)
+        for (int u = -half; u <= half; u++) {
+            const double d = env[(v + half) * Ew + (u + half)] - exp(-(double)(u * u + v * v) / (2.0 * s * s));
+            q += d * d;
+        }
+    return q;
+}
+
+double orc_envelope_psf(const double* params, int n, int half, double* env) {
+    const int Ew = 2 * half + 1;
+    double smax = 0.0;
+    for (int k = 0; k < n; k++)
+        if (params[3 * k] > smax) smax = params[3 * k];
+    for (int v = -half; v <= half; v++)
+        for (int u = -half; u <= half; u++) {
+            double m = 0.0;
+            for (int k = 0; k < n; k++) {
+                const double s = params[3 * k];
+                const double g = exp(-(double)(u * u + v * v) / (2.0 * s * s));
+                if (g > m) m = g;
+            }
+            env[(v + half) * Ew + (u + half)] = m;
+        }
+    const double gr = 0.5 * (sqrt(5.0) - 1.0);
+    double a = 0.1, b = 2.0 * smax;
+    double c = b - gr * (b - a), d = a + gr * (b - a);
+    double fc = env_misfit(env, half, c), fd = env_misfit(env, half, d);
+    while (b - a > 1e-10) {
+        if (fc < fd) {
+            b = d; d = c; fd = fc;
+            c = b - gr * (b - a);
+            fc = env_misfit(env, half, c);
+        } else {
+            a = c; c = d; fc = fd;
+            d = a + gr * (b - a);
+            fd = env_misfit(env, half, d);
+        }
+    }
+    return 0.5 * (a + b);
+}
+
+/*
+ * Fake target image (Section 5.1): the envelope PSF, a circular Gaussian of
+ * width sigma and unit flux sampled at pixel centres, placed at the known
+ * source positions with their fluxes (src[3 s + 0..2] = x, y, flux), each
+ * within a box of half-width ceil(6 sigma) + 1 around floor(x), floor(y);
+ * sums in source order.
+ */
+void orc_render_target(const double* src, int n, double sigma, int W, int H, int64_t pitch,
+                       float* out) {
+    const int rad = (int)ceil(6.0 * sigma) + 1;
+    double* acc = (double*)calloc((size_t)W * H, sizeof(double));
+    const double norm = 1.0 / (2.0 * 3.14159265358979323846 * sigma * sigma);
+    for (int s = 0; s < n; s++) {
+        const double x0 = src[3 * s], y0 = src[3 * s + 1], f = src[3 * s + 2];
+        const int xi = (int)floor(x0), yi = (int)floor(y0);
+        for (int y = yi - rad; y <= yi + rad; y++)
+            for (int x = xi - rad; x <= xi + rad; x++) {
+                if (x < 0 || x >= W || y < 0 || y >= H) continue;
+                const double dx = x - x0, dy = y - y0;
+                acc[(size_t)y * W + x] += f * norm * exp(-(dx * dx + dy * dy) / (2.0 * sigma * sigma));
+            }
+    }
+    for (int y = 0; y < H; y++)
+        for (int x = 0; x < W; x++) out[(int64_t)y * pitch + x] = (float)acc[(size_t)y * W + x];
+    free(acc);
+}
+
+/*
+ * Outlier pixels across n PSF-homogenised inputs (Section 5.1); plane k of
+ * each array starts at k * plane (elements).  At each pixel the inputs not
+ * masked there are compared with their median (the mean of the two middle
+ * values for an even count); input k is an outlier if
+ * |I_k - median| > nsigma sqrt(V_k).  Fewer than 3 unmasked inputs: none is.
+ * out[k] = 1 for outliers, else 0.
+ */
+static int cmp_double(const void* a, const void* b) {
+    const double x = *(const double*)a, y = *(const double*)b;
+    return (x > y) - (x < y);
+}
+
+void orc_stack_reject(int n, const float* I, const float* V, const uint8_t* Mk, int64_t plane,
+                      int W, int H, int64_t pitch, double nsigma, uint8_t* out) {
+    double vals[64];
+    for (int y = 0; y < H; y++)
+        for (int x = 0; x < W; x++) {
+            const int64_t o = (int64_t)y * pitch + x;
+            int m = 0;
+            for (int k = 0; k < n; k++) {
+                out[k * plane + o] = 0;
+                if (!Mk[k * plane + o]) vals[m++] = I[k * plane + o];
+            }
+            if (m < 3) continue;
+            qsort(vals, m, sizeof(double), cmp_double);
+            const double med = (m % 2) ? vals[m / 2] : 0.5 * (vals[m / 2 - 1] + vals[m / 2]);
+            for (int k = 0; k < n; k++) {
+                const int64_t q = k * plane + o;
+                if (Mk[q]) continue;
+                if (fabs((double)I[q] - med) > nsigma * sqrt((double)V[q])) out[q] = 1;
+            }
+        }
+}
+
+/*
+ * Back from outliers on a convolved image to bad pixels of the original
+ * (Section 5.1): the outlier mask is correlated with the magnitude of the
+ * kernel applied there -- the matched filter, the adjoint of the
+ * convolution, so pixel x collects the outlier flags of the convolved pixels
+ * x + u it contributed to with weight |K_p(u)| -- and x is bad if that
+ * collects at least frac of sum |K_p|; K_p is the patch kernel of x's
+ * patch.  Outside the image counts as no outlier.
+ */
+void orc_trace_mask(const orc_config* c, const double* kb, const double* a, const uint8_t* outl,
+                    int W, int H, int64_t pitch, double frac, uint8_t* bad) {
+    const int h = c->h, Kw = 2 * h + 1, T = Kw * Kw, np = orc_n_patches(c, W, H);
+#pragma omp parallel for schedule(dynamic)
+    for (int p = 0; p < np; p++) {
+        int x0, x1, y0, y1;
+        patch_bounds(W, H, c->P, p, &x0, &x1, &y0, &y1);
+        double* K = (double*)malloc(sizeof(double) * T);
+        orc_patch_kernel(c, kb, a, W, H, p, K);
+        double tot = 0.0;
+        for (int t = 0; t < T; t++) tot += fabs(K[t]);
+        for (int y = y0; y < y1; y++)
+            for (int x = x0; x < x1; x++) {
+                double s = 0.0;
+                for (int v = -h; v <= h; v++)
+                    for (int u = -h; u <= h; u++) {
+                        const int xx = x + u, yy = y + v;
+                        if (xx < 0 || xx >= W || yy < 0 || yy >= H) continue;
+                        if (outl[(int64_t)yy * pitch + xx]) s += fabs(K[(v + h) * Kw + (u + h)]);
+                    }
+                bad[(int64_t)y * pitch + x] = s >= frac * tot && s > 0.0;
+            }
+        free(K);
+    }
+}
+
+/*
+ * Weighted combination of n homogenised inputs (Section 5.2): weights
+ * w_k = 1 / mean(V_k) over each input's pixels with mask 0 (reading of
+ * "weights set to the mean variance": inverse-variance weights);
+ *     S = sum_k w_k I_k / sum_k w_k,  V_S = sum_k w_k^2 V_k / (sum_k w_k)^2
+ * over the inputs with mask 0 at the pixel; none: S = V_S = 0, MS = 1.
+ * Pseudo-matrix: the variance-weighted average of the inputs' (each
+ * (2 ck + 1)^2, all the same size, in one array of n (2 ck + 1)^2 values)
+ * with weights w_k^2 mean(V_k).  weights_out (nullable) receives the w_k.
+ */
+void orc_stack_combine(int n, const float* I, const float* V, const uint8_t* Mk, int64_t plane,
+                       int W, int H, int64_t pitch, const double* C, int ck, float* S, float* VS,
+                       uint8_t* MS, double* CS, double* weights_out) {
+    double w[64], vbar[64];
+    for (int k = 0; k < n; k++) {
+        double sv = 0.0;
+        long cnt = 0;
+        for (int y = 0; y < H; y++)
+            for (int x = 0; x < W; x++) {
+                const int64_t q = k * plane + (int64_t)y * pitch + x;
+                if (!Mk[q]) { sv += V[q]; cnt++; }
+            }
+        vbar[k] = cnt ? sv / cnt : 0.0;
+        w[k] = vbar[k] > 0.0 ? 1.0 / vbar[k] : 0.0;
+        if (weights_out) weights_out[k] = w[k];
+    }
+    for (int y = 0; y < H; y++)
+        for (int x = 0; x < W; x++) {
+            const int64_t o = (int64_t)y * pitch + x;
+            double sw = 0.0, si = 0.0, sv = 0.0;
+            for (int k = 0; k < n; k++) {
+                const int64_t q = k * plane + o;
+                if (Mk[q]) continue;
+                sw += w[k];
+                si += w[k] * (double)I[q];
+                sv += w[k] * w[k] * (double)V[q];
+            }
+            if (sw > 0.0) {
+                S[o] = (float)(si / sw);
+                VS[o] = (float)(sv / (sw * sw));
+                MS[o] = 0;
+            } else {
+                S[o] = 0.0f;
+                VS[o] = 0.0f;
+                MS[o] = 1;
+            }
+        }
+    const int Cw = 2 * ck + 1;
+    double tw = 0.0;
+    for (int k = 0; k < n; k++) tw += w[k] * w[k] * vbar[k];
+    for (int t = 0; t < Cw * Cw; t++) {
+        double s = 0.0;
+        for (int k = 0; k < n; k++) s += w[k] * w[k] * vbar[k] * C[(size_t)k * Cw * Cw + t];
+        CS[t] = tw > 0.0 ? s / tw : 0.0;
+    }
+}
