@@ -521,6 +521,82 @@ int psfm_add_images(double alpha, const float* Ia, const float* Va, const uint8_
                     int cov_s_half, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * PSF homogenisation for stacking (Section 5.1): every input is matched to a
+ * fake target image with one common PSF, the envelope of the inputs' PSFs,
+ * so that all inputs share that PSF; outliers among the homogenised inputs
+ * are traced back to pixels of the originals; the inputs are then combined
+ * (Section 5.2).  Up to PSFM_STACK_MAX_INPUTS inputs; n planes of one array
+ * start at multiples of `plane` elements (bytes for masks), each W x H with
+ * `pitch`.  No context is needed except by psfm_trace_mask.
+ *
+ * psfm_envelope_psf: params (device) holds n elliptical Gaussian PSFs as
+ * (sigma_major, sigma_minor, angle) triples.  Each is taken in its circular
+ * version of peak 1 and width sigma_major (containing the input PSF); env
+ * (device, (2 half + 1)^2 float64, row-major, offsets -half..half, half
+ * 1..64) receives their pixel-wise maximum, and *sigma (device) the width of
+ * the circular peak-1 Gaussian fitted to it by least squares (golden-section
+ * search over [0.1, 2 max sigma_major] to a bracket of 1e-10 px).
+ */
+#define PSFM_STACK_MAX_INPUTS 64
+int psfm_envelope_psf(const double* params, int n, int half, double* env, double* sigma,
+                      void* stream);
+
+/*
+ * psfm_render_target: the fake target image, a circular Gaussian of width
+ * sigma (host, 0 < sigma <= 1000) and unit flux sampled at pixel centres,
+ * placed at each source of src (device, n (x, y, flux) float64 triples,
+ * pixel coordinates) with its flux, over the box of half-width
+ * ceil(6 sigma) + 1 around (floor(x), floor(y)); every pixel sums its
+ * sources in index order in float64 and stores float32 in out (device,
+ * W x H with pitch).  Sources with |x| or |y| >= 1e9 (or NaN) are skipped.
+ * ws: device scratch of psfm_render_workspace_bytes(n, W, H, sigma) bytes
+ * (0 for invalid arguments).
+ */
+size_t psfm_render_workspace_bytes(int n, int W, int H, double sigma);
+int psfm_render_target(const double* src, int n, double sigma, int W, int H, int64_t pitch,
+                       float* out, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * psfm_stack_reject: outlier pixels among n homogenised inputs (1..64).  At
+ * each pixel the inputs with M = 0 there are compared with their median (the
+ * mean of the two middle values for an even count, in float64); input k is
+ * an outlier if |I_k - median| > nsigma sqrt(V_k).  out[k] (device, n planes
+ * like I) = 1 for outliers, else 0 (always 0 where fewer than 3 inputs are
+ * unmasked, and for masked inputs).
+ */
+int psfm_stack_reject(int n, const float* I, const float* V, const uint8_t* M, int64_t plane, int W,
+                      int H, int64_t pitch, double nsigma, uint8_t* out, void* stream);
+
+/*
+ * psfm_trace_mask: outliers found on an image convolved with the context's
+ * kernel (coeffs: the solution, device) traced back to the pixels of the
+ * input that produced them.  In patch p, pixel x collects |K_p(u)| over the
+ * outlier pixels x + u it contributes to (the matched filter of the
+ * convolution; outside the image counts as no outlier) and bad = 1 where
+ * that sum is positive and at least frac (>= 0) times sum |K_p|, else 0.
+ * outliers and bad: device W x H bytes with pitch.
+ */
+int psfm_trace_mask(const psfm_context* ctx, const double* coeffs, const uint8_t* outliers, int W,
+                    int H, int64_t pitch, double frac, uint8_t* bad, void* stream);
+
+/*
+ * psfm_stack_combine (Section 5.2): weights w_k = 1 / mean(V_k) over each
+ * input's pixels with M = 0 (0 if it has none); at each pixel, over the
+ * inputs unmasked there,
+ *   S = sum w_k I_k / sum w_k,   V_S = sum w_k^2 V_k / (sum w_k)^2,
+ * MS = 0; where none is unmasked S = V_S = 0 and MS = 1.  cov (device,
+ * nullable if cov_s is NULL) holds the n inputs' pseudo-matrices, each
+ * (2 cov_half + 1)^2; cov_s (device, nullable) receives their average with
+ * weights w_k^2 mean(V_k).  weights (device, nullable) receives the w_k.
+ * ws: device scratch of PSFM_STACK_WORKSPACE_BYTES.
+ */
+#define PSFM_STACK_WORKSPACE_BYTES 262656
+int psfm_stack_combine(int n, const float* I, const float* V, const uint8_t* M, int64_t plane, int W,
+                       int H, int64_t pitch, const double* cov, int cov_half, float* S, float* VS,
+                       uint8_t* MS, double* cov_s, double* weights, void* ws, size_t ws_bytes,
+                       void* stream);
+
+/*
  * Batched matching of many independent image pairs: the whole path of the
  * calls above (fit, solve with rejection, image and variance convolution,
  * covariance pseudo-matrix, difference) for every pair of a batch, with each

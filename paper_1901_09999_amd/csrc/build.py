@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 SOURCES = ["context.hip", "fit.hip", "solve.hip", "convolve.hip", "batch.hip", "cnn.hip",
-           "noalloc.hip", "noise.hip"]
+           "noalloc.hip", "noise.hip", "stack.hip"]
 LIB = os.path.join(PKG, "libpsfm.so")
 OBJDIR = os.path.join(ROOT, "_build")
 

@@ -1446,6 +1446,80 @@ __global__ __launch_bounds__(NQ_T) void k_quality_finish(BasisArgs B, const doub
     }
 }
 
+// Outliers on a convolved image traced back to pixels of its input
+// (Section 5.1): one workgroup per 64 x 64 tile of a patch.  The outlier
+// flags of the tile and its h-halo are bit-packed in LDS; a tile without any
+// writes zeros.  Otherwise |K_p| in FP64 (K_p realised at the patch centre)
+// with its total summed in tap order, and each pixel x adds |K_p(u, v)| over
+// the flagged pixels x + (u, v), rows then columns in increasing order, the
+// pixel being marked when the sum is positive and at least frac sum |K_p|.
+constexpr int TR_HW = TILE + 2 * PSFM_HMAX;
+constexpr int TR_NWB = (TR_HW + 31) / 32 + 1;
+
+__global__ __launch_bounds__(256) void k_trace_tile(const uint8_t* __restrict__ outl, int W, int H,
+                                                    int64_t pitch, int P, const double* __restrict__ a,
+                                                    BasisArgs B, double frac, uint8_t* __restrict__ bad) {
+    __shared__ RealiseLds sh;
+    __shared__ double Kd[(2 * PSFM_HMAX + 1) * (2 * PSFM_HMAX + 1)];
+    __shared__ uint32_t badw[TR_HW][TR_NWB];
+    __shared__ double s_thr;
+    const int h = B.h, KW = 2 * h + 1, T = KW * KW, HW = TILE + 2 * h, tid = threadIdx.x;
+    const PatchGeom g = patch_geom(W, H, P);
+    const int px = blockIdx.x / g.tpp, sx = blockIdx.x % g.tpp;
+    const int py = blockIdx.y / g.tpp, sy = blockIdx.y % g.tpp;
+    const int X0 = px * P + sx * TILE, Y0 = py * P + sy * TILE;
+    const int X1 = min(min(X0 + TILE, (px + 1) * P), W);
+    const int Y1 = min(min(Y0 + TILE, (py + 1) * P), H);
+    if (X0 >= X1 || Y0 >= Y1) return;
+    for (int e = tid; e < TR_HW * TR_NWB; e += 256) (&badw[0][0])[e] = 0u;
+    __syncthreads();
+    int any = 0;
+    for (int e = tid; e < HW * HW; e += 256) {
+        const int hy = e / HW, hx = e - hy * HW;
+        const int gy = Y0 - h + hy, gx = X0 - h + hx;
+        if (gx >= 0 && gx < W && gy >= 0 && gy < H && outl[(int64_t)gy * pitch + gx]) {
+            any = 1;
+            atomicOr(&badw[hy][hx >> 5], 1u << (hx & 31));
+        }
+    }
+    any = __syncthreads_or(any);
+    if (any) {
+        const int x0 = px * P, x1 = min(x0 + P, W), y0 = py * P, y1 = min(y0 + P, H);
+        realise_kernel(B, a, 0.5 * (x0 + x1 - 1), 0.5 * (y0 + y1 - 1), W, H, sh, Kd);
+        for (int t = tid; t < T; t += 256) Kd[t] = fabs(Kd[t]);
+        __syncthreads();
+        if (tid == 0) {
+            double tot = 0.0;
+            for (int t = 0; t < T; t++) tot += Kd[t];
+            s_thr = frac * tot;
+        }
+        __syncthreads();
+    }
+    const double thr = any ? s_thr : 0.0;
+    const uint64_t kmask = (1ull << KW) - 1ull;
+    for (int e = tid; e < TILE * TILE; e += 256) {
+        const int ly = e >> 6, lx = e & 63;
+        const int gx = X0 + lx, gy = Y0 + ly;
+        if (gx >= X1 || gy >= Y1) continue;
+        uint8_t f = 0;
+        if (any) {
+            double s = 0.0;
+            const int w = lx >> 5, shf = lx & 31;
+            for (int v = 0; v < KW; v++) {
+                const uint32_t* bw = badw[ly + v];
+                uint64_t bits = (((uint64_t)bw[w] | ((uint64_t)bw[w + 1] << 32)) >> shf) & kmask;
+                while (bits) {
+                    const int u = __builtin_ctzll(bits);
+                    bits &= bits - 1ull;
+                    s += Kd[v * KW + u];
+                }
+            }
+            f = (s >= thr && s > 0.0) ? 1 : 0;
+        }
+        bad[(int64_t)gy * pitch + gx] = f;
+    }
+}
+
 }  // namespace
 
 extern "C" int psfm_fit_norm(const psfm_context* ctx, const float* I1, const float* I2, int W, int H,
@@ -1476,6 +1550,18 @@ extern "C" int psfm_quality_eval(const psfm_context* ctx, const double* coeffs, 
                            pitch, stamp_xy, stamp_flags, ctx->r, soft, stamp_dev);
     hipLaunchKernelGGL(k_quality_finish, dim3(1), dim3(NQ_T), 0, st, B, coeffs, W, H, n_stamps,
                        stamp_flags, stamp_dev, quality);
+    PSFM_HIP_CHECK(hipGetLastError());
+    return PSFM_OK;
+}
+
+extern "C" int psfm_trace_mask(const psfm_context* ctx, const double* coeffs, const uint8_t* outliers,
+                               int W, int H, int64_t pitch, double frac, uint8_t* bad, void* stream) {
+    int rc = check_image_args(ctx, W, H, pitch);
+    if (rc) return rc;
+    if (!coeffs || !outliers || !bad || !(frac >= 0.0)) return PSFM_ERR_INVALID_ARG;
+    const PatchGeom g = patch_geom(W, H, ctx->cfg.patch);
+    hipLaunchKernelGGL(k_trace_tile, dim3(g.npx * g.tpp, g.npy * g.tpp), dim3(256), 0, (hipStream_t)stream,
+                       outliers, W, H, pitch, ctx->cfg.patch, coeffs, basis_args(ctx), frac, bad);
     PSFM_HIP_CHECK(hipGetLastError());
     return PSFM_OK;
 }

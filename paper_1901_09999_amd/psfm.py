@@ -157,6 +157,12 @@ def lib():
             "psfm_resample_cov": (i, [P, i, C.c_double, P, i, P]),
             "psfm_add_images": (i, [C.c_double, P, P, P, P, i, C.c_double, P, P, P, P, i, i, i, i64, P,
                                     P, P, P, i, P, sz, P]),
+            "psfm_envelope_psf": (i, [P, i, i, P, P, P]),
+            "psfm_render_workspace_bytes": (sz, [i, i, i, C.c_double]),
+            "psfm_render_target": (i, [P, i, C.c_double, i, i, i64, P, P, sz, P]),
+            "psfm_stack_reject": (i, [i, P, P, P, i64, i, i, i64, C.c_double, P, P]),
+            "psfm_trace_mask": (i, [P, P, P, i, i, i64, C.c_double, P, P]),
+            "psfm_stack_combine": (i, [i, P, P, P, i64, i, i, i64, P, i, P, P, P, P, P, P, sz, P]),
             "psfm_status_string": (C.c_char_p, [i]),
             "psfm_batch_workspace_bytes": (sz, [P, C.POINTER(CPair), i]),
             "psfm_batch_plan": (i, [P, C.POINTER(CPair), i, C.POINTER(CTuning), P, sz, P, P,
@@ -714,6 +720,74 @@ def add_images(alpha, Ia, Va, Ma, cov_a, beta, Ib, Vb, Mb, cov_b, cs, out=None, 
     return out
 
 
+STACK_WORKSPACE_BYTES = 262656
+STACK_MAX_INPUTS = 64
+
+
+def envelope_psf(params, half):
+    """psfm_envelope_psf: params (n, 3) float64 (sigma_major, sigma_minor,
+    angle) on the device -> (sigma (1,), env (2 half + 1)^2)."""
+    dev = params.device
+    env = torch.empty((2 * half + 1, 2 * half + 1), dtype=torch.float64, device=dev)
+    sig = torch.empty(1, dtype=torch.float64, device=dev)
+    _check(lib().psfm_envelope_psf(_ptr(params), params.shape[0], half, _ptr(env), _ptr(sig), _stream()),
+           "psfm_envelope_psf")
+    return sig, env
+
+
+def render_target(src, sigma, W, H, out=None, ws=None):
+    """psfm_render_target: src (n, 3) float64 (x, y, flux) on the device."""
+    n = src.shape[0]
+    dev = src.device
+    need = int(lib().psfm_render_workspace_bytes(n, W, H, float(sigma)))
+    if need == 0:
+        raise PsfmError("psfm_render_workspace_bytes: invalid arguments")
+    out = torch.empty((H, W), dtype=torch.float32, device=dev) if out is None else out
+    ws = torch.empty(need, dtype=torch.uint8, device=dev) if ws is None else ws
+    _check(lib().psfm_render_target(_ptr(src), n, float(sigma), W, H, W, _ptr(out), _ptr(ws), ws.numel(),
+                                    _stream()), "psfm_render_target")
+    return out
+
+
+def stack_reject(I, V, M, nsigma, out=None):
+    """psfm_stack_reject on (n, H, W) planes."""
+    n, H, W = I.shape
+    out = torch.empty_like(M) if out is None else out
+    _check(lib().psfm_stack_reject(n, _ptr(I), _ptr(V), _ptr(M), H * W, W, H, W, float(nsigma), _ptr(out),
+                                   _stream()), "psfm_stack_reject")
+    return out
+
+
+def trace_mask(ctx, coeffs, outliers, frac, out=None):
+    """psfm_trace_mask: the input pixels behind the outliers of a convolved image."""
+    H, W = outliers.shape
+    out = torch.empty_like(outliers) if out is None else out
+    _check(lib().psfm_trace_mask(ctx.handle, _ptr(coeffs), _ptr(outliers), W, H, W, float(frac), _ptr(out),
+                                 _stream()), "psfm_trace_mask")
+    return out
+
+
+def stack_combine(I, V, M, cov=None, out=None, ws=None):
+    """psfm_stack_combine on (n, H, W) planes; cov (n, 2c + 1, 2c + 1) or
+    None.  Returns dict(S, VS, MS, cov, weights)."""
+    n, H, W = I.shape
+    dev = I.device
+    ck = 0 if cov is None else (cov.shape[1] - 1) // 2
+    if out is None:
+        out = dict(S=torch.empty((H, W), dtype=torch.float32, device=dev),
+                   VS=torch.empty((H, W), dtype=torch.float32, device=dev),
+                   MS=torch.empty((H, W), dtype=torch.uint8, device=dev),
+                   cov=None if cov is None else torch.empty((2 * ck + 1,) * 2, dtype=torch.float64,
+                                                            device=dev),
+                   weights=torch.empty(n, dtype=torch.float64, device=dev))
+    ws = torch.empty(STACK_WORKSPACE_BYTES, dtype=torch.uint8, device=dev) if ws is None else ws
+    _check(lib().psfm_stack_combine(n, _ptr(I), _ptr(V), _ptr(M), H * W, W, H, W, _ptr(cov), ck,
+                                    _ptr(out["S"]), _ptr(out["VS"]), _ptr(out["MS"]), _ptr(out["cov"]),
+                                    _ptr(out["weights"]), _ptr(ws), ws.numel(), _stream()),
+           "psfm_stack_combine")
+    return out
+
+
 def read_quality(q: torch.Tensor) -> dict:
     raw = bytes(q.cpu().numpy().tobytes())
     return CQuality.from_buffer_copy(raw[:QUALITY_BYTES]).as_dict()
@@ -743,6 +817,8 @@ def exported_symbols() -> Sequence[str]:
             "psfm_solve_stamps", "psfm_solve_prior", "psfm_cholesky_workspace_bytes",
             "psfm_fit_norm", "psfm_solve_norm", "psfm_quality_eval", "psfm_bin_image",
             "psfm_resample_cov", "psfm_add_images",
+            "psfm_envelope_psf", "psfm_render_workspace_bytes", "psfm_render_target",
+            "psfm_stack_reject", "psfm_trace_mask", "psfm_stack_combine",
             "psfm_cholesky_solve", "psfm_cnn_param_count",
             "psfm_cnn_workspace_bytes", "psfm_cnn_forward", "psfm_cnn_loss_grad",
             "psfm_cnn_loss_weights", "psfm_cnn_adam",

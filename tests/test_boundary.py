@@ -80,6 +80,19 @@ def test_host_argument_checks(lib):
     assert lib.psfm_solve_norm(None, 10, 10, None, 1, *([None] * 10), None, 0, None) == -1
     assert lib.psfm_quality_eval(None, None, None, None, None, 10, 10, 10, None, 1, None, 0.0, None,
                                  None, None) == -1
+    assert lib.psfm_trace_mask(None, None, None, 10, 10, 10, 0.5, None, None) == -1
+
+
+def test_stack_host_argument_checks(lib):
+    """Homogenisation entry points reject bad arguments before any launch."""
+    assert lib.psfm_envelope_psf(None, 1, 5, None, None, None) == -1
+    assert lib.psfm_render_workspace_bytes(10, 0, 10, 1.0) == 0
+    assert lib.psfm_render_workspace_bytes(10, 10, 10, -1.0) == 0
+    assert lib.psfm_render_workspace_bytes(10, 64, 64, 2.0) > 0
+    assert lib.psfm_render_target(None, 0, 1.0, 10, 10, 10, None, None, 0, None) == -1
+    assert lib.psfm_stack_reject(0, None, None, None, 100, 10, 10, 10, 3.0, None, None) == -1
+    assert lib.psfm_stack_combine(0, *([None] * 3), 100, 10, 10, 10, None, 0, *([None] * 6), 0,
+                                  None) == -1
     for code in range(-8, 1):
         assert lib.psfm_status_string(code).decode()
 
