@@ -12,15 +12,15 @@
 //      zero-sum fix-up A_i = psi_i R_i - z_i A_0, the weighting by sqrt(1/V2)
 //      and the extra columns sqrt(w) (background) and sqrt(w) * I2 (target);
 //      the 64-column weighted row block is then folded into the Gram
-//      G = A~^T A~ with v_mfma_f32_16x16x4f32 (10 lower 16x16 blocks, spread
-//      over the 4 waves);
-//      The MFMA accumulators (FP32) are flushed into FP64 registers after
-//      every stamp row, so FP32 sums never span more than 2r+1 pixels;
+//      G = A~^T A~ with v_mfma_f64_16x16x4f64 on the FP32 values (10 lower
+//      16x16 blocks, spread over the 4 waves): exact products, FP64 sums over
+//      the band, so the Gram of the FP32 block stays positive semi-definite
+//      to FP64 rounding even for the 1e10-condition Grams of bright stars;
 //   4. the band's partial Gram is written in FP64; a second kernel adds the
 //      bands of each stamp and scatters M_s, b_s, e_s.
 // 16-bit modes (PSFM_PREC_FP16 / _BF16): the weighted row block is rounded to
 // 16 bits, stored column-major, and folded in with v_mfma_f32_16x16x32_{f16,
-// bf16} (FP32 accumulation, FP64 per row as above); in BF16 the block is
+// bf16} (FP32 accumulation within a stamp row, rows added in FP64); in BF16 the block is
 // split into hi + lo BF16 parts and the Gram is that of hi + lo (four
 // products, ~16 significant bits, still positive semi-definite); the FP32
 // block itself
@@ -31,6 +31,7 @@
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
@@ -259,13 +260,12 @@ __device__ void fit_band_body(const FitArgs& a, const int item, float* __restric
 
     // ---- 3. rows of the band
     const int lane = tid & 63, wave = tid >> 6;
-    floatx4 acc[3];
-    double acc64[3][4];
+    floatx4 acc[3];            // 16-bit modes: FP32 MFMA sums of one stamp row
+    doublex4 accd[3];          // FP64 sums of the band
 #pragma unroll
     for (int q = 0; q < 3; q++) {
         acc[q] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int e = 0; e < 4; e++) acc64[q][e] = 0.0;
+        accd[q] = doublex4{0.0, 0.0, 0.0, 0.0};
     }
     const int nseg = (NPX + SEG - 1) / SEG;
     // row-pass item of this thread (the usual case: nb * nseg <= 256), its
@@ -326,26 +326,30 @@ __device__ void fit_band_body(const FitArgs& a, const int item, float* __restric
         __syncthreads();
         // 3c. Gram blocks on MFMA.  Wave blocks (bm, bn): w0 (0,0)(1,0)(1,1);
         // w1 (2,0)(2,1)(2,2); w2 (3,0)(3,1); w3 (3,2)(3,3).
+        //     The FP32 values enter v_mfma_f64_16x16x4f64 as FP64: every
+        //     product is exact and the sums run in FP64 over the whole band,
+        //     so the Gram is that of the FP32 block to FP64 rounding (and
+        //     positive semi-definite to it), whatever its condition.
         for (int ks = 0; ks < npad / 4; ks++) {
             const float* rowp = At + (4 * ks + (lane >> 4)) * AT_STRIDE + (lane & 15);
             if (wave == 0) {
-                const float a0 = rowp[0], a1 = rowp[16];
-                acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, a0, acc[0], 0, 0, 0);
-                acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, a0, acc[1], 0, 0, 0);
-                acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, a1, acc[2], 0, 0, 0);
+                const double a0 = rowp[0], a1 = rowp[16];
+                accd[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a0, accd[0], 0, 0, 0);
+                accd[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a0, accd[1], 0, 0, 0);
+                accd[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a1, accd[2], 0, 0, 0);
             } else if (wave == 1) {
-                const float a0 = rowp[0], a1 = rowp[16], a2 = rowp[32];
-                acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, a0, acc[0], 0, 0, 0);
-                acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, a1, acc[1], 0, 0, 0);
-                acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, a2, acc[2], 0, 0, 0);
+                const double a0 = rowp[0], a1 = rowp[16], a2 = rowp[32];
+                accd[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, a0, accd[0], 0, 0, 0);
+                accd[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, a1, accd[1], 0, 0, 0);
+                accd[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, a2, accd[2], 0, 0, 0);
             } else if (wave == 2) {
-                const float a0 = rowp[0], a1 = rowp[16], a3 = rowp[48];
-                acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a3, a0, acc[0], 0, 0, 0);
-                acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a3, a1, acc[1], 0, 0, 0);
+                const double a0 = rowp[0], a1 = rowp[16], a3 = rowp[48];
+                accd[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a3, a0, accd[0], 0, 0, 0);
+                accd[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a3, a1, accd[1], 0, 0, 0);
             } else {
-                const float a2 = rowp[32], a3 = rowp[48];
-                acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a3, a2, acc[0], 0, 0, 0);
-                acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a3, a3, acc[1], 0, 0, 0);
+                const double a2 = rowp[32], a3 = rowp[48];
+                accd[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a3, a2, accd[0], 0, 0, 0);
+                accd[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a3, a3, accd[1], 0, 0, 0);
             }
         }
         } else {
@@ -428,18 +432,22 @@ __device__ void fit_band_body(const FitArgs& a, const int item, float* __restric
             }
         }
         }
-        // FP32 MFMA sums cover one stamp row; rows are added in FP64.
+        // 16-bit modes: the FP32 MFMA sums cover one stamp row; rows are
+        // added in FP64.
+        if constexpr (PREC != PSFM_PREC_FP32) {
 #pragma unroll
-        for (int q = 0; q < 3; q++) {
+            for (int q = 0; q < 3; q++) {
 #pragma unroll
-            for (int e = 0; e < 4; e++) acc64[q][e] += (double)acc[q][e];
-            acc[q] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+                for (int e = 0; e < 4; e++) accd[q][e] += (double)acc[q][e];
+                acc[q] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            }
         }
         // Rb may be rewritten only after every wave finished 3b (barrier above);
         // At is rewritten after the barrier that follows the next row pass.
     }
 
-    // ---- 4. partial Gram out: rows 16 bm + 4 (lane / 16) + q, column 16 bn + lane % 16
+    // ---- 4. partial Gram out, column 16 bn + lane % 16; row 16 bm + (lane / 16) + 4 e
+    //         from the FP64 MFMA, 16 bm + 4 (lane / 16) + e from the FP32 ones
     double* G = part + (size_t)item * GC * GC;
     const int bms[4][3] = {{0, 1, 1}, {2, 2, 2}, {3, 3, -1}, {3, 3, -1}};
     const int bns[4][3] = {{0, 0, 1}, {0, 1, 2}, {0, 1, -1}, {2, 3, -1}};
@@ -449,7 +457,11 @@ __device__ void fit_band_body(const FitArgs& a, const int item, float* __restric
         if (bm < 0) continue;
         const int col = 16 * bn + (lane & 15);
 #pragma unroll
-        for (int e = 0; e < 4; e++) G[(16 * bm + 4 * (lane >> 4) + e) * GC + col] = acc64[q][e];
+        for (int e = 0; e < 4; e++) {
+            const int row = PREC == PSFM_PREC_FP32 ? 16 * bm + (lane >> 4) + 4 * e
+                                                   : 16 * bm + 4 * (lane >> 4) + e;
+            G[row * GC + col] = accd[q][e];
+        }
     }
     if (tid == 0) band_flags[item] = 0;
 }
