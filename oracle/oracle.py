@@ -136,6 +136,12 @@ def lib():
             "orc_stack_reject": (None, [i, P, P, P, i64, i, i, i64, d, P]),
             "orc_trace_mask": (None, [cfgp, P, P, P, i, i, i64, d, P]),
             "orc_stack_combine": (None, [i, P, P, P, i64, i, i, i64, P, i, P, P, P, P, P]),
+            "orc_dual_unknowns": (i, [cfgp]),
+            "orc_fit_dual": (None, [cfgp, P, P, P, P, P, P, i, i, i64, P, i, P, P, P, P, P]),
+            "orc_penalty_q": (None, [cfgp, P, P]),
+            "orc_solve_dual": (i, [cfgp, P, i, i, P, i, P, P, P, P, P, d, P, P, C.POINTER(OrcStats)]),
+            "orc_dual_kernels": (None, [cfgp, P, P, d, d, i, i, P, P]),
+            "orc_dual_apply": (None, [cfgp, P, P, P, P, P, P, P, P, i, i, i64, P, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(_lib, name)
@@ -537,3 +543,68 @@ def stack_combine(I, V, M, covs):
     lib().orc_stack_combine(n, _p(I), _p(V), _p(M), H * W, W, H, W, _p(covs), ck, _p(S), _p(VS),
                             _p(MS), _p(CS), _p(w))
     return S, VS, MS, CS, w
+
+
+# ---------------------------------------------------------------- two kernels
+
+def dual_unknowns(cfg: Config) -> int:
+    return (2 * cfg.n_basis - 1) * cfg.n_spatial + 1
+
+
+def fit_dual(cfg: Config, I1, M1, I2, V2, M2, stamps, kb=None):
+    """Per-stamp sums of the two-kernel form: dict(M [n,L2,L2], b [n,L2], e, npix, flags), L2 = 2 nb."""
+    kb = basis(cfg) if kb is None else kb
+    I1, I2, V2 = (_c(a, np.float32) for a in (I1, I2, V2))
+    M1, M2 = _c(M1, np.uint8), _c(M2, np.uint8)
+    H, W = I1.shape
+    xy = _c(stamps, np.int32).reshape(-1, 2)
+    n = xy.shape[0]
+    L = 2 * cfg.n_basis
+    Ms = np.zeros((n, L, L)); bs = np.zeros((n, L)); es = np.zeros(n)
+    npix = np.zeros(n, dtype=np.int32); flags = np.zeros(n, dtype=np.int32)
+    lib().orc_fit_dual(C.byref(cfg.c()), _p(kb), _p(I1), _p(M1), _p(I2), _p(V2), _p(M2), W, H, W,
+                       _p(xy), n, _p(Ms), _p(bs), _p(es), _p(npix), _p(flags))
+    return dict(M=Ms, b=bs, e=es, npix=npix, flags=flags)
+
+
+def penalty_q(cfg: Config, kb=None) -> np.ndarray:
+    kb = basis(cfg) if kb is None else kb
+    Q = np.zeros(cfg.n_basis)
+    lib().orc_penalty_q(C.byref(cfg.c()), _p(kb), _p(Q))
+    return Q
+
+
+def solve_dual(cfg: Config, W, H, stamps, fit, phi, flags=None, kb=None):
+    """Two-kernel solution with rejection.  Returns (ret, coeffs, chi2, flags, stats)."""
+    kb = basis(cfg) if kb is None else kb
+    xy = _c(stamps, np.int32).reshape(-1, 2)
+    n = xy.shape[0]
+    fl = _c(fit["flags"] if flags is None else flags, np.int32).copy()
+    a = np.zeros(dual_unknowns(cfg)); chi2 = np.zeros(n)
+    st = OrcStats()
+    ret = lib().orc_solve_dual(C.byref(cfg.c()), _p(kb), W, H, _p(xy), n, _p(_c(fit["M"], np.float64)),
+                               _p(_c(fit["b"], np.float64)), _p(_c(fit["e"], np.float64)),
+                               _p(_c(fit["npix"], np.int32)), _p(fl), float(phi), _p(a), _p(chi2),
+                               C.byref(st))
+    return ret, a, chi2, fl, st.as_dict()
+
+
+def dual_kernels(cfg: Config, a, x, y, W, H, kb=None):
+    kb = basis(cfg) if kb is None else kb
+    K = 2 * cfg.h + 1
+    K1 = np.zeros((K, K)); K2 = np.zeros((K, K))
+    lib().orc_dual_kernels(C.byref(cfg.c()), _p(kb), _p(_c(a, np.float64)), float(x), float(y), W, H,
+                           _p(K1), _p(K2))
+    return K1, K2
+
+
+def dual_apply(cfg: Config, a, I1, V1, M1, I2, V2, M2, kb=None):
+    """(D, V_D, mask_D) of the two-kernel form."""
+    kb = basis(cfg) if kb is None else kb
+    I1, V1, I2, V2 = (_c(x, np.float32) for x in (I1, V1, I2, V2))
+    M1, M2 = _c(M1, np.uint8), _c(M2, np.uint8)
+    H, W = I1.shape
+    D = np.zeros((H, W), np.float32); VD = np.zeros((H, W), np.float32); MD = np.zeros((H, W), np.uint8)
+    lib().orc_dual_apply(C.byref(cfg.c()), _p(kb), _p(_c(a, np.float64)), _p(I1), _p(V1), _p(M1), _p(I2),
+                         _p(V2), _p(M2), W, H, W, _p(D), _p(VD), _p(MD))
+    return D, VD, MD

@@ -1436,3 +1436,339 @@ void orc_stack_combine(int n, const float* I, const float* V, const uint8_t* Mk,
         CS[t] = tw > 0.0 ? s / tw : 0.0;
     }
 }
+
+/* ------------------------------------------------------------------------
+ * Matching both images to a common PSF (Section 2, Eqs. 1-4 with the
+ * penalty of Eq. 9).
+ *
+ * Unknowns a = (b, c, d0): b the nb kernel terms of K1 with their spatial
+ * polynomials (b[i * ns + s], exactly the single form's kernel unknowns),
+ * c the zero-sum terms i = 1..nb-1 of the kernel applied to I2, with the
+ * same spatial polynomials (c[(i - 1) * ns + s] at offset nb ns), and the
+ * constant background d0 last: N2 = (2 nb - 1) ns + 1.  Model of I2:
+ *     sum_i b_i g k_i (x) I1 + sum_{i>=1} c_i g k_i (x) I2 + d0,
+ * so that K1 (x) I1 + d0 = K2 (x) I2 with K2 = delta - sum_{i>=1} c_i g k_i
+ * (unit sum, as every k_i with i >= 1 sums to zero).
+ */
+
+int orc_dual_unknowns(const orc_config* c) {
+    return (2 * orc_n_basis(c) - 1) * orc_n_spatial(c) + 1;
+}
+
+/*
+ * Per-stamp sums of the two-kernel form: columns A = (k_i (x) I1 for
+ * i = 0..nb-1, k_i (x) I2 for i = 1..nb-1, 1), L2 = 2 nb, weights 1 / V2:
+ * M_s = A^T W A (L2 x L2), b_s = A^T W I2, e_s = I2^T W I2 over the stamp
+ * pixels.  Validity as for the single form, with I2 (and its mask) now
+ * also required over the convolution footprint [x-r-h, x+r+h]^2.
+ */
+void orc_fit_dual(const orc_config* c, const double* kb, const float* I1, const uint8_t* M1,
+                  const float* I2, const float* V2, const uint8_t* M2, int W, int H,
+                  int64_t pitch, const int32_t* xy, int n, double* Ms, double* bs, double* es,
+                  int32_t* npix, int32_t* flags) {
+    const int nb = orc_n_basis(c), L = 2 * nb, h = c->h, r = c->r, K = 2 * h + 1, T = K * K;
+#pragma omp parallel for schedule(dynamic)
+    for (int s = 0; s < n; s++) {
+        const int xc = xy[2 * s], yc = xy[2 * s + 1], R = r + h;
+        double* M = Ms + (size_t)s * L * L;
+        double* b = bs + (size_t)s * L;
+        int flag = 0;
+        memset(M, 0, sizeof(double) * L * L);
+        memset(b, 0, sizeof(double) * L);
+        es[s] = 0.0;
+        npix[s] = 0;
+        if (xc - R < 0 || yc - R < 0 || xc + R >= W || yc + R >= H) {
+            flag |= ORC_STAMP_INVALID;
+        } else {
+            for (int y = yc - R; y <= yc + R; y++)
+                for (int x = xc - R; x <= xc + R; x++)
+                    if (M1[y * pitch + x] || M2[y * pitch + x]) flag |= ORC_STAMP_INVALID;
+            if (!flag) {
+                for (int y = yc - R; y <= yc + R; y++)
+                    for (int x = xc - R; x <= xc + R; x++)
+                        if (!isfinite(I1[y * pitch + x]) || !isfinite(I2[y * pitch + x]))
+                            flag |= ORC_STAMP_NONFINITE;
+                for (int y = yc - r; y <= yc + r; y++)
+                    for (int x = xc - r; x <= xc + r; x++) {
+                        const float v2 = V2[y * pitch + x];
+                        if (!isfinite(v2) || !(v2 > 0.0f)) flag |= ORC_STAMP_NONFINITE;
+                    }
+            }
+        }
+        flags[s] = flag;
+        if (flag) continue;
+        double* A = (double*)malloc(sizeof(double) * L);
+        for (int y = yc - r; y <= yc + r; y++) {
+            for (int x = xc - r; x <= xc + r; x++) {
+                for (int i = 0; i < nb; i++) {
+                    const double* ki = kb + (size_t)i * T;
+                    double a1 = 0.0, a2 = 0.0;
+                    for (int v = -h; v <= h; v++)
+                        for (int u = -h; u <= h; u++) {
+                            const int64_t o = (int64_t)(y - v) * pitch + (x - u);
+                            const double k = ki[(v + h) * K + (u + h)];
+                            a1 += k * (double)I1[o];
+                            a2 += k * (double)I2[o];
+                        }
+                    A[i] = a1;
+                    if (i >= 1) A[nb + i - 1] = a2;
+                }
+                A[L - 1] = 1.0;
+                const double w = 1.0 / (double)V2[y * pitch + x];
+                const double d = (double)I2[y * pitch + x];
+                for (int i = 0; i < L; i++) {
+                    for (int j = 0; j < L; j++) M[i * L + j] += w * A[i] * A[j];
+                    b[i] += w * A[i] * d;
+                }
+                es[s] += w * d * d;
+            }
+        }
+        npix[s] = (2 * r + 1) * (2 * r + 1);
+        free(A);
+    }
+}
+
+/*
+ * Penalty weights of the basis (Eq. 9 without Phi): Q_i = sum_{u,v}
+ * (u^2 + v^2)^2 k_i(u, v)^2, i = 0..nb-1.
+ */
+void orc_penalty_q(const orc_config* c, const double* kb, double* Q) {
+    const int nb = orc_n_basis(c), h = c->h, K = 2 * h + 1;
+    for (int i = 0; i < nb; i++) {
+        double q = 0.0;
+        for (int v = -h; v <= h; v++)
+            for (int u = -h; u <= h; u++) {
+                const double r2 = (double)(u * u + v * v);
+                const double k = kb[(size_t)i * K * K + (v + h) * K + (u + h)];
+                q += r2 * r2 * k * k;
+            }
+        Q[i] = q;
+    }
+}
+
+/* Local coefficients of the two-kernel form at (x, y): alpha[0..nb-1] the
+   b-terms, alpha[nb + i - 1] the c-term of basis i, alpha[2 nb - 1] = d0. */
+static void dual_local(const orc_config* c, const double* a, double x, double y, int W, int H,
+                       double* alpha) {
+    const int nb = orc_n_basis(c), ns = orc_n_spatial(c), nt = 2 * nb - 1;
+    double g[64];
+    orc_spatial(c->S, x, y, W, H, g);
+    for (int i = 0; i < nt; i++) {
+        double v = 0.0;
+        for (int s = 0; s < ns; s++) v += a[i * ns + s] * g[s];
+        alpha[i] = v;
+    }
+    alpha[nt] = a[nt * ns];
+}
+
+/*
+ * Solution of the two-kernel form with rejection (the single form's loop
+ * and readings), the assembly over the 2 nb - 1 spatially varying columns,
+ * and the penalty of Eq. 9 on the diagonal: unknown j of basis term i
+ * (b-terms i >= 1 and every c-term; not b_0, the normalisation, nor d0)
+ * gets P_j = Phi Q_i.  Reading of "neither negligible nor dominant":
+ * Phi = phi * (sum over penalised j of M_jj) / (sum over penalised j of
+ * Q_i(j)), recomputed at every assembly, so that the penalties add the
+ * fraction phi (>= 0) to the total diagonal of the penalised unknowns.
+ * The per-stamp chi2 (rejection, chi2/dof) is the data term alone.
+ * kernel_sum_centre is K1's sum at the image centre (b_0 there).
+ */
+int orc_solve_dual(const orc_config* c, const double* kb, int W, int H, const int32_t* xy, int n,
+                   const double* Ms, const double* bs, const double* es, const int32_t* npix,
+                   int32_t* flags, double phi, double* coeffs, double* chi2, orc_stats* st) {
+    const int nb = orc_n_basis(c), ns = orc_n_spatial(c), nt = 2 * nb - 1, N = nt * ns + 1,
+              L = 2 * nb;
+    uint8_t* used = (uint8_t*)calloc(n > 0 ? n : 1, 1);
+    uint8_t* fitted = (uint8_t*)calloc(n > 0 ? n : 1, 1);
+    double* M = (double*)malloc(sizeof(double) * (size_t)N * N);
+    double* b = (double*)malloc(sizeof(double) * N);
+    double* Q = (double*)malloc(sizeof(double) * nb);
+    double* alpha = (double*)malloc(sizeof(double) * L);
+    double g[64];
+    orc_penalty_q(c, kb, Q);
+    int ret = 0, iter = 0, n_rej = 0;
+    memset(st, 0, sizeof(*st));
+    for (int s = 0; s < n; s++) {
+        used[s] = flags[s] == 0;
+        fitted[s] = used[s];
+        chi2[s] = 0.0;
+    }
+    for (int i = 0; i < N; i++) coeffs[i] = 0.0;
+    for (;;) {
+        int n_used = 0;
+        for (int s = 0; s < n; s++) n_used += used[s];
+        if (n_used < c->min_stamps) { ret = -3; st->info = -3; break; }
+        /* assembly: M[(i,s),(j,t)] = sum g_s g_t M_s[i][j], the background unexpanded */
+        memset(M, 0, sizeof(double) * (size_t)N * N);
+        memset(b, 0, sizeof(double) * N);
+        for (int k = 0; k < n; k++) {
+            if (!used[k]) continue;
+            orc_spatial(c->S, xy[2 * k], xy[2 * k + 1], W, H, g);
+            const double* Mk = Ms + (size_t)k * L * L;
+            const double* bk = bs + (size_t)k * L;
+            for (int i = 0; i < nt; i++)
+                for (int sa = 0; sa < ns; sa++) {
+                    const int row = i * ns + sa;
+                    for (int j = 0; j < nt; j++)
+                        for (int t = 0; t < ns; t++)
+                            M[(size_t)row * N + j * ns + t] += g[sa] * g[t] * Mk[i * L + j];
+                    M[(size_t)row * N + N - 1] += g[sa] * Mk[i * L + nt];
+                    M[(size_t)(N - 1) * N + row] += g[sa] * Mk[nt * L + i];
+                    b[row] += g[sa] * bk[i];
+                }
+            M[(size_t)(N - 1) * N + N - 1] += Mk[nt * L + nt];
+            b[N - 1] += bk[nt];
+        }
+        /* penalty */
+        double dsum = 0.0, qsum = 0.0;
+        for (int i = 1; i < nt; i++) {
+            const double qi = Q[i < nb ? i : i - nb + 1];
+            for (int sa = 0; sa < ns; sa++) {
+                dsum += M[(size_t)(i * ns + sa) * N + i * ns + sa];
+                qsum += qi;
+            }
+        }
+        const double Phi = qsum > 0.0 ? phi * dsum / qsum : 0.0;
+        for (int i = 1; i < nt; i++) {
+            const double qi = Q[i < nb ? i : i - nb + 1];
+            for (int sa = 0; sa < ns; sa++) M[(size_t)(i * ns + sa) * N + i * ns + sa] += Phi * qi;
+        }
+        int info = orc_cholesky_solve(N, M, b, coeffs);
+        if (info) { ret = -4; st->info = info; break; }
+        iter++;
+        for (int k = 0; k < n; k++) {
+            chi2[k] = 0.0;
+            if (!fitted[k]) continue;
+            dual_local(c, coeffs, xy[2 * k], xy[2 * k + 1], W, H, alpha);
+            const double* Mk = Ms + (size_t)k * L * L;
+            const double* bk = bs + (size_t)k * L;
+            double q = 0.0, lin = 0.0;
+            for (int i = 0; i < L; i++) {
+                double t = 0.0;
+                for (int j = 0; j < L; j++) t += Mk[i * L + j] * alpha[j];
+                q += alpha[i] * t;
+                lin += alpha[i] * bk[i];
+            }
+            chi2[k] = es[k] - 2.0 * lin + q;
+        }
+        if (iter >= c->max_iter) break;
+        double mean = 0.0, var = 0.0;
+        for (int k = 0; k < n; k++)
+            if (used[k]) mean += chi2[k] / npix[k];
+        mean /= n_used;
+        for (int k = 0; k < n; k++)
+            if (used[k]) {
+                const double dq = chi2[k] / npix[k] - mean;
+                var += dq * dq;
+            }
+        const double thr = mean + c->clip_sigma * sqrt(var / n_used);
+        int n_new = 0;
+        for (int k = 0; k < n; k++)
+            if (used[k] && chi2[k] / npix[k] > thr) n_new++;
+        if (n_new == 0 || n_used - n_new < c->min_stamps) break;
+        for (int k = 0; k < n; k++)
+            if (used[k] && chi2[k] / npix[k] > thr) {
+                used[k] = 0;
+                flags[k] |= ORC_STAMP_REJECTED;
+                n_rej++;
+            }
+    }
+    st->n_iter = iter;
+    st->n_rejected = n_rej;
+    if (ret != 0)
+        for (int i = 0; i < N; i++) coeffs[i] = 0.0;
+    if (ret == 0) {
+        double c2 = 0.0, np = 0.0;
+        int nu = 0;
+        for (int k = 0; k < n; k++)
+            if (used[k]) { c2 += chi2[k]; np += npix[k]; nu++; }
+        st->chi2 = c2;
+        st->dof = np - N;
+        st->chi2_dof = c2 / (np - N);
+        st->n_used = nu;
+        dual_local(c, coeffs, 0.5 * (W - 1), 0.5 * (H - 1), W, H, alpha);
+        st->kernel_sum_centre = alpha[0];
+    }
+    free(used);
+    free(fitted);
+    free(M);
+    free(b);
+    free(Q);
+    free(alpha);
+    return ret;
+}
+
+/* K1 = sum_i b_i(x, y) k_i and K2 = delta - sum_{i>=1} c_i(x, y) k_i at
+   (x, y), each (2h+1)^2 in the basis layout. */
+void orc_dual_kernels(const orc_config* c, const double* kb, const double* a, double x, double y,
+                      int W, int H, double* K1, double* K2) {
+    const int nb = orc_n_basis(c), h = c->h, Kw = 2 * h + 1, T = Kw * Kw;
+    double* alpha = (double*)malloc(sizeof(double) * 2 * nb);
+    dual_local(c, a, x, y, W, H, alpha);
+    for (int t = 0; t < T; t++) {
+        double k1 = 0.0, k2 = 0.0;
+        for (int i = 0; i < nb; i++) k1 += alpha[i] * kb[(size_t)i * T + t];
+        for (int i = 1; i < nb; i++) k2 += alpha[nb + i - 1] * kb[(size_t)i * T + t];
+        K1[t] = k1;
+        K2[t] = (t == h * Kw + h ? 1.0 : 0.0) - k2;
+    }
+    free(alpha);
+}
+
+/*
+ * The two-kernel difference image: in each patch (kernels realised at the
+ * patch centre, Section 3.5),
+ *     D = K2 (x) I2~ - K1 (x) I1~ - d0,   V_D = K1^2 (x) V1~ + K2^2 (x) V2~,
+ * with ~ meaning zero where masked or outside the image (the inputs are
+ * taken as uncorrelated); mask: CONV_BAD if a masked or outside pixel of
+ * I1 lies within K1's BAD radius or one of I2 within K2's, else CONV_POOR
+ * if one of either lies within h (Section 3.4).
+ */
+void orc_dual_apply(const orc_config* c, const double* kb, const double* a, const float* I1,
+                    const float* V1, const uint8_t* M1, const float* I2, const float* V2,
+                    const uint8_t* M2, int W, int H, int64_t pitch, float* D, float* VD,
+                    uint8_t* MD) {
+    const int h = c->h, Kw = 2 * h + 1, T = Kw * Kw, np = orc_n_patches(c, W, H);
+    const double d0 = a[orc_dual_unknowns(c) - 1];
+#pragma omp parallel for schedule(dynamic)
+    for (int p = 0; p < np; p++) {
+        int x0, x1, y0, y1;
+        double* K1 = (double*)malloc(sizeof(double) * T);
+        double* K2 = (double*)malloc(sizeof(double) * T);
+        patch_bounds(W, H, c->P, p, &x0, &x1, &y0, &y1);
+        orc_dual_kernels(c, kb, a, 0.5 * (x0 + x1 - 1), 0.5 * (y0 + y1 - 1), W, H, K1, K2);
+        const int rb1 = orc_bad_radius(K1, h, c->bad_frac), rb2 = orc_bad_radius(K2, h, c->bad_frac);
+        for (int y = y0; y < y1; y++)
+            for (int x = x0; x < x1; x++) {
+                double s1 = 0.0, s2 = 0.0, v1 = 0.0, v2 = 0.0;
+                int dm1 = h + 1, dm2 = h + 1;
+                for (int v = -h; v <= h; v++)
+                    for (int u = -h; u <= h; u++) {
+                        const int xx = x - u, yy = y - v;
+                        const int t = (v + h) * Kw + (u + h);
+                        const int dd = abs(u) > abs(v) ? abs(u) : abs(v);
+                        const int in = xx >= 0 && xx < W && yy >= 0 && yy < H;
+                        const int64_t o = (int64_t)yy * pitch + xx;
+                        if (in && !M1[o]) {
+                            s1 += K1[t] * (double)I1[o];
+                            v1 += K1[t] * K1[t] * (double)V1[o];
+                        } else if (dd < dm1) {
+                            dm1 = dd;
+                        }
+                        if (in && !M2[o]) {
+                            s2 += K2[t] * (double)I2[o];
+                            v2 += K2[t] * K2[t] * (double)V2[o];
+                        } else if (dd < dm2) {
+                            dm2 = dd;
+                        }
+                    }
+                const int64_t o = (int64_t)y * pitch + x;
+                D[o] = (float)(s2 - s1 - d0);
+                VD[o] = (float)(v1 + v2);
+                MD[o] = (dm1 <= rb1 || dm2 <= rb2) ? ORC_MASK_CONV_BAD
+                        : (dm1 <= h || dm2 <= h) ? ORC_MASK_CONV_POOR : 0;
+            }
+        free(K1);
+        free(K2);
+    }
+}

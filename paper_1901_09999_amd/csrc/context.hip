@@ -57,12 +57,6 @@ void psfm_config_default(psfm_config* cfg) {
     cfg->refine = 1;
 }
 
-static double ipow(double x, int n) {
-    double r = 1.0;
-    for (int k = 0; k < n; k++) r *= x;
-    return r;
-}
-
 int psfm_create(const psfm_config* cfg, psfm_context** out) {
     if (!cfg || !out) return PSFM_ERR_INVALID_ARG;
     *out = nullptr;
@@ -107,54 +101,56 @@ int psfm_create(const psfm_config* cfg, psfm_context** out) {
     std::vector<double> psi64(nb);
     std::vector<int> rowf(nb), colf(nb);
     std::vector<float> psi(nb), z(nb);
-    int foff = 0;
-    for (int j = 0; j < c.n_gauss; j++) {
-        const double s2 = 2.0 * c.sigma[j] * c.sigma[j];
-        for (int e = 0; e <= c.degree[j]; e++)
-            for (int t = -h; t <= h; t++) {
-                const double f = ipow(t, e) * std::exp(-(double)t * t / s2);
-                fac64[(size_t)(foff + e) * KW + (t + h)] = f;
-                fac[(size_t)(foff + e) * KW + (t + h)] = (float)f;
-            }
-        foff += c.degree[j] + 1;
-    }
-    int i = 0;
-    foff = 0;
-    std::vector<double> raw(T);
-    for (int j = 0; j < c.n_gauss; j++) {
-        const double s2 = 2.0 * c.sigma[j] * c.sigma[j];
-        for (int d = 0; d <= c.degree[j]; d++) {
-            for (int p = d; p >= 0; p--) {
-                const int q = d - p;
-                double sum = 0.0, sabs = 0.0;
-                for (int v = -h; v <= h; v++)
-                    for (int u = -h; u <= h; u++) {
-                        const double val = ipow(u, p) * ipow(v, q) * std::exp(-(double)(u * u + v * v) / s2);
-                        raw[(v + h) * KW + (u + h)] = val;
-                        sum += val;
-                        sabs += std::fabs(val);
-                    }
-                double* ki = kb.data() + (size_t)i * T;
-                double norm;
-                bool sub_k0 = false;
-                if (i == 0) {
-                    norm = 1.0 / sum;
-                } else if (p % 2 == 0 && q % 2 == 0) {
-                    norm = 1.0 / sum;
-                    sub_k0 = true;
-                } else {
-                    norm = 1.0 / sabs;
+    // The basis is separable: term (j, p, q) is f_{j,p}(u) f_{j,q}(v) with
+    // f_{j,e}(t) = t^e exp(-t^2 / 2 s_j^2).  Its 2-D sum and absolute sum are
+    // products of the factors' 1-D sums, which give the normalisation psi_i
+    // (unit sum for the even-even terms, unit absolute sum for the others);
+    // the even-even terms i >= 1 then have k_0 (unit sum) subtracted, so
+    // that every term but k_0 sums to zero.
+    std::vector<double> sum1((size_t)nf), abs1((size_t)nf);
+    {
+        int f = 0;
+        for (int j = 0; j < c.n_gauss; j++) {
+            const double inv2s2 = 0.5 / (c.sigma[j] * c.sigma[j]);
+            for (int e = 0; e <= c.degree[j]; e++, f++) {
+                double s1 = 0.0, a1 = 0.0;
+                for (int t = -h; t <= h; t++) {
+                    double mono = 1.0;
+                    for (int k = 0; k < e; k++) mono *= (double)t;
+                    const double v = mono * std::exp(-(double)(t * t) * inv2s2);
+                    fac64[(size_t)f * KW + (t + h)] = v;
+                    fac[(size_t)f * KW + (t + h)] = (float)v;
+                    s1 += v;
+                    a1 += std::fabs(v);
                 }
-                for (int t = 0; t < T; t++) ki[t] = raw[t] * norm - (sub_k0 ? kb[t] : 0.0);
-                rowf[i] = foff + p;
-                colf[i] = foff + q;
-                psi[i] = (float)norm;
-                psi64[i] = norm;
-                z[i] = sub_k0 ? 1.0f : 0.0f;
-                i++;
+                sum1[f] = s1;
+                abs1[f] = a1;
             }
         }
-        foff += c.degree[j] + 1;
+    }
+    {
+        int i = 0, f0 = 0;
+        for (int j = 0; j < c.n_gauss; j++) {
+            for (int d = 0; d <= c.degree[j]; d++)
+                for (int p = d; p >= 0; p--, i++) {
+                    const int fu = f0 + p, fv = f0 + (d - p);
+                    const bool even = (p % 2 == 0) && ((d - p) % 2 == 0);
+                    const double nrm = even ? 1.0 / (sum1[fu] * sum1[fv]) : 1.0 / (abs1[fu] * abs1[fv]);
+                    const bool zs = even && i > 0;
+                    rowf[i] = fu;
+                    colf[i] = fv;
+                    psi64[i] = nrm;
+                    psi[i] = (float)nrm;
+                    z[i] = zs ? 1.0f : 0.0f;
+                    double* ki = kb.data() + (size_t)i * T;
+                    for (int v = 0; v < KW; v++)
+                        for (int u = 0; u < KW; u++) {
+                            const double sep = nrm * fac64[(size_t)fu * KW + u] * fac64[(size_t)fv * KW + v];
+                            ki[v * KW + u] = zs ? sep - kb[v * KW + u] : sep;
+                        }
+                }
+            f0 += c.degree[j] + 1;
+        }
     }
 
     // R: upper Cholesky factor of the basis Gram G_ij = sum_t k_i(t) k_j(t), so
