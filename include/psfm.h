@@ -521,6 +521,72 @@ int psfm_add_images(double alpha, const float* Ia, const float* Va, const uint8_
                     int cov_s_half, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Matching both images to a common PSF (Section 2, Eqs. 1-4, with the
+ * penalty of Eq. 9): I2 is modelled as K1 (x) I1 plus sum c_i g_i k_i (x) I2
+ * plus the background, so that K1 (x) I1 + d0 = K2 (x) I2 with
+ * K2 = delta - sum_{i>=1} c_i g_i k_i (unit sum: every k_i with i >= 1 sums
+ * to zero); neither image has to be deconvolved, e.g. when their PSFs are
+ * elongated along different axes.  The context's basis, h, r, patch, spatial
+ * order and rejection settings apply; its precision does not (FP32 design,
+ * FP64 Gram).
+ *
+ * Unknowns (psfm_dual_unknowns, N2 = (2 nb - 1) ns + 1, float64): the b-terms
+ * b[i * ns + s] (i < nb, the single form's kernel unknowns), the c-terms of
+ * basis i = 1..nb-1 at offset nb ns, c[(i - 1) * ns + s], and d0 last.  Stamp
+ * matrices are L2 = 2 nb wide: columns k_i (x) I1 (i < nb), k_i (x) I2
+ * (1 <= i < nb), then the background.  Supported while 2 nb + 1 <= 128 and
+ * N2 <= 496 (the 49-term basis: spatial order 0 or 1).
+ *
+ * psfm_dual_workspace_bytes: device scratch for either call below (0 for
+ * invalid arguments).
+ */
+size_t psfm_dual_workspace_bytes(const psfm_context* ctx, int width, int height, int n_stamps);
+int psfm_dual_unknowns(const psfm_context* ctx);
+
+/*
+ * psfm_fit_dual: per-stamp sums of the two-kernel form, weights 1 / V2:
+ * stamp_M (n x L2 x L2), stamp_b (n x L2), stamp_e, stamp_npix, stamp_flags,
+ * as psfm_fit_stamps.  Validity as there, plus I2 and M2 over the whole
+ * convolution footprint (I2 is convolved): a masked pixel there makes the
+ * stamp INVALID, a non-finite one NONFINITE.
+ */
+int psfm_fit_dual(const psfm_context* ctx, const float* I1, const uint8_t* M1, const float* I2,
+                  const float* V2, const uint8_t* M2, int W, int H, int64_t pitch,
+                  const int32_t* stamp_xy, int n_stamps, double* stamp_M, double* stamp_b,
+                  double* stamp_e, int32_t* stamp_npix, int32_t* stamp_flags, void* ws,
+                  size_t ws_bytes, void* stream);
+
+/*
+ * psfm_solve_dual: the solution with rejection (as psfm_solve) of the
+ * two-kernel form, with the penalty P = Phi Q_i, Q_i = sum (u^2 + v^2)^2
+ * k_i(u, v)^2, on the diagonal of every b-term i >= 1 and every c-term (not
+ * b_0, the normalisation, nor d0).  Phi is unspecified in the paper beyond
+ * "neither negligible nor dominant": here Phi = phi (sum of the penalised
+ * unknowns' diagonal) / (sum of their Q_i), recomputed at each assembly, so
+ * the penalties add the fraction phi (>= 0) to that diagonal.  The stamp
+ * chi2 (rejection, chi2/dof) is the data term alone; kernel_sum_centre is
+ * K1's sum at the image centre.  coeffs: N2 float64.
+ */
+int psfm_solve_dual(const psfm_context* ctx, int W, int H, const int32_t* stamp_xy, int n_stamps,
+                    const double* stamp_M, const double* stamp_b, const double* stamp_e,
+                    const int32_t* stamp_npix, int32_t* stamp_flags, double phi, double* coeffs,
+                    double* stamp_chi2, psfm_fit_stats* stats, void* ws, size_t ws_bytes,
+                    void* stream);
+
+/*
+ * psfm_dual_subtract: the difference image of the two-kernel form, kernels
+ * realised at each patch centre: D = K2 (x) I2 - K1 (x) I1 - d0,
+ * V_D = K1^2 (x) V1 + K2^2 (x) V2 (inputs taken as uncorrelated), masked or
+ * outside pixels read as 0; diff_mask CONV_BAD within K1's BAD radius of a
+ * masked or outside I1 pixel or within K2's of one of I2, else CONV_POOR
+ * within h of either.  D and V_D are written everywhere.
+ */
+int psfm_dual_subtract(const psfm_context* ctx, const double* coeffs, const float* I1,
+                       const float* V1, const uint8_t* M1, const float* I2, const float* V2,
+                       const uint8_t* M2, int W, int H, int64_t pitch, float* diff,
+                       float* diff_var, uint8_t* diff_mask, void* stream);
+
+/*
  * PSF homogenisation for stacking (Section 5.1): every input is matched to a
  * fake target image with one common PSF, the envelope of the inputs' PSFs,
  * so that all inputs share that PSF; outliers among the homogenised inputs

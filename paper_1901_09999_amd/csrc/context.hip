@@ -183,6 +183,19 @@ int psfm_create(const psfm_config* cfg, psfm_context** out) {
         }
     }
 
+    // penalty weights of the two-kernel form (Eq. 9 without Phi):
+    // Q_i = sum_{u,v} (u^2 + v^2)^2 k_i(u, v)^2
+    std::vector<double> penq(nb);
+    for (int t = 0; t < nb; t++) {
+        double q = 0.0;
+        for (int v = -h; v <= h; v++)
+            for (int u = -h; u <= h; u++) {
+                const double rr = (double)(u * u + v * v), k = kb[(size_t)t * T + (v + h) * KW + (u + h)];
+                q += rr * rr * k * k;
+            }
+        penq[t] = q;
+    }
+
     // one device block for all tables
     psfm::Carver layout(nullptr);
     double* d_kb = layout.take<double>(kb.size());
@@ -194,6 +207,7 @@ int psfm_create(const psfm_config* cfg, psfm_context** out) {
     double* d_fac64 = layout.take<double>(fac64.size());
     double* d_psi64 = layout.take<double>(nb);
     double* d_R = layout.take<double>(R.size());
+    double* d_penq = layout.take<double>(nb);
     const size_t bytes = layout.off;
     char* blk = nullptr;
     if (hipMalloc(&blk, bytes) != hipSuccess) {
@@ -211,6 +225,7 @@ int psfm_create(const psfm_config* cfg, psfm_context** out) {
     ctx->fac64 = rebase(d_fac64);
     ctx->psi64 = rebase(d_psi64);
     ctx->kgram_R = rebase(d_R);
+    ctx->penq = rebase(d_penq);
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipMemcpy(ctx->kb64, kb.data(), kb.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ctx->fac, fac.data(), fac.size() * sizeof(float), hipMemcpyHostToDevice);
@@ -221,6 +236,7 @@ int psfm_create(const psfm_config* cfg, psfm_context** out) {
     if (e == hipSuccess) e = hipMemcpy(ctx->fac64, fac64.data(), fac64.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ctx->psi64, psi64.data(), nb * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ctx->kgram_R, R.data(), R.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ctx->penq, penq.data(), nb * sizeof(double), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(blk);
         delete ctx;
@@ -256,6 +272,15 @@ size_t psfm_workspace_bytes(const psfm_context* ctx, int W, int H, int n_stamps)
     if (e > m) m = e;
     return psfm::align_up(m, 256) + 256;
 }
+
+size_t psfm_dual_workspace_bytes(const psfm_context* ctx, int W, int H, int n_stamps) {
+    if (!ctx || W < 1 || H < 1 || n_stamps < 0) return 0;
+    size_t f = psfm::dual_fit_workspace(ctx, n_stamps);
+    size_t s = psfm::dual_solve_workspace(ctx, n_stamps);
+    return psfm::align_up(f > s ? f : s, 256) + 256;
+}
+
+int psfm_dual_unknowns(const psfm_context* ctx) { return ctx ? psfm::dual_unknowns(ctx) : -1; }
 
 size_t psfm_stamp_design_floats(const psfm_context* ctx, int n_stamps) {
     if (!ctx || n_stamps < 0 || ctx->cfg.precision == PSFM_PREC_FP32) return 0;

@@ -57,8 +57,11 @@ struct RealiseLds {
 //   K = sum_i gamma_i f_{rowf_i}(u) f_{colf_i}(v),
 //   gamma_i = alpha_i psi_i (i >= 1),  gamma_0 = psi_0 (alpha_0 - sum_i z_i alpha_i).
 // Kd receives [(v+h)*KW + (u+h)].  All threads of the block call it.
+// skip0: term 0 takes no coefficient (the sum over the zero-sum terms only,
+// as in the kernel applied to I2 in the two-kernel form; a then points
+// ns coefficients before that kernel's first term).
 __device__ void realise_kernel(const BasisArgs& B, const double* __restrict__ a, double x, double y,
-                               int W, int H, RealiseLds& sh, double* Kd) {
+                               int W, int H, RealiseLds& sh, double* Kd, bool skip0 = false) {
     const int KW = 2 * B.h + 1, T = KW * KW, tid = threadIdx.x, nb = B.nb, ns = B.ns;
     for (int e = tid; e < B.nf * KW; e += blockDim.x) sh.F[e] = B.fac64[e];
     if (tid < 64) {
@@ -88,6 +91,7 @@ __device__ void realise_kernel(const BasisArgs& B, const double* __restrict__ a,
                 }
             }
         }
+        if (skip0 && tid == 0) al = 0.0;
         // c0 = sum_(i >= 1) z_i alpha_i: fixed-order butterfly over the wave
         double c0 = tid >= 1 && tid < nb ? zi * al : 0.0;
 #pragma unroll
@@ -1446,6 +1450,124 @@ __global__ __launch_bounds__(NQ_T) void k_quality_finish(BasisArgs B, const doub
     }
 }
 
+// The two-kernel difference image (Section 2): one workgroup per 64 x 64
+// tile of a patch.  K1 (the b-terms) and K2 = delta - sum c_i k_i (the
+// c-terms, realised with term 0 left out) are realised in FP64 at the patch
+// centre with their BAD radii; FP32 taps of K1, K1^2, K2, K2^2.  The halos of
+// I1, I2 (with their mask bits), V1 and V2 go through the tile buffer in
+// turn; D = K2 (x) I2 - K1 (x) I1 - d0 and V_D = K1^2 (x) V1 + K2^2 (x) V2
+// (uncorrelated inputs), the mask BAD within either kernel's BAD radius of
+// its image's masked or outside pixels, else POOR within h of either.
+template <int H_>
+__global__ __launch_bounds__(256) void k_dual_tile(
+    const float* __restrict__ I1, const float* __restrict__ V1, const uint8_t* __restrict__ M1,
+    const float* __restrict__ I2, const float* __restrict__ V2, const uint8_t* __restrict__ M2, int W,
+    int H, int64_t pitch, int P, const double* __restrict__ a, BasisArgs B, int c_off, int N2,
+    double bad_frac, float* __restrict__ D, float* __restrict__ VD, uint8_t* __restrict__ MD) {
+    constexpr int KW = 2 * H_ + 1;
+    constexpr int T = KW * KW;
+    constexpr int HW = TILE + 2 * H_;
+    constexpr int NWB = (HW + 31) / 32 + 1;
+    static_assert(sizeof(float) * HW * HW >= sizeof(RealiseLds) + sizeof(double) * T,
+                  "kernel scratch must fit in the halo buffer");
+    __shared__ __align__(16) float halo[HW * HW];
+    __shared__ __align__(16) float tK1[T + 4];
+    __shared__ __align__(16) float tV1[T + 4];
+    __shared__ __align__(16) float tK2[T + 4];
+    __shared__ __align__(16) float tV2[T + 4];
+    __shared__ uint32_t badw[HW][NWB];
+    __shared__ double ring[H_ + 1];
+    __shared__ double red[16];
+    __shared__ int s_rb1, s_rb2;
+    __shared__ double s_f;
+    const int tid = threadIdx.x;
+    const PatchGeom g = patch_geom(W, H, P);
+    const int px = blockIdx.x / g.tpp, sx = blockIdx.x % g.tpp;
+    const int py = blockIdx.y / g.tpp, sy = blockIdx.y % g.tpp;
+    const int X0 = px * P + sx * TILE, Y0 = py * P + sy * TILE;
+    const int X1 = min(min(X0 + TILE, (px + 1) * P), W);
+    const int Y1 = min(min(Y0 + TILE, (py + 1) * P), H);
+    if (X0 >= X1 || Y0 >= Y1) return;
+    {
+        RealiseLds& sh = *reinterpret_cast<RealiseLds*>(halo);
+        double* Kd = reinterpret_cast<double*>(reinterpret_cast<char*>(halo) + sizeof(RealiseLds));
+        const int x0 = px * P, x1 = min(x0 + P, W), y0 = py * P, y1 = min(y0 + P, H);
+        const double xc = 0.5 * (x0 + x1 - 1), yc = 0.5 * (y0 + y1 - 1);
+        realise_kernel(B, a, xc, yc, W, H, sh, Kd);
+        kernel_stats(Kd, H_, bad_frac, nullptr, 0, ring, red, &s_rb1, &s_f);
+        for (int t = tid; t < T; t += 256) {
+            const int uu = t / KW, vv = t - uu * KW;     // column-major
+            const double k = Kd[vv * KW + uu];
+            tK1[t] = (float)k;
+            tV1[t] = (float)(k * k);
+        }
+        __syncthreads();
+        realise_kernel(B, a + c_off, xc, yc, W, H, sh, Kd, true);
+        for (int t = tid; t < T; t += 256) Kd[t] = (t == H_ * KW + H_ ? 1.0 : 0.0) - Kd[t];
+        __syncthreads();
+        kernel_stats(Kd, H_, bad_frac, nullptr, 0, ring, red, &s_rb2, &s_f);
+        for (int t = tid; t < T; t += 256) {
+            const int uu = t / KW, vv = t - uu * KW;
+            const double k = Kd[vv * KW + uu];
+            tK2[t] = (float)k;
+            tV2[t] = (float)(k * k);
+        }
+        __syncthreads();
+    }
+    const int lx = tid & 63;
+    const int r0 = (tid >> 6) * 16;
+    float acc1[16], acc2[16], accv[16];
+    uint32_t bad = 0, poor = 0;
+    {
+        const int anybad = load_halo<H_, true>(I1, M1, W, H, pitch, X0, Y0, halo, badw);
+        conv16<H_>(halo, tK1, lx, r0, acc1);
+        if (anybad) mask16<H_>(badw, s_rb1, lx, r0, &bad, &poor);
+    }
+    __syncthreads();
+    {
+        const int anybad = load_halo<H_, true>(I2, M2, W, H, pitch, X0, Y0, halo, badw);
+        conv16<H_>(halo, tK2, lx, r0, acc2);
+        if (anybad) {
+            uint32_t b2 = 0, p2 = 0;
+            mask16<H_>(badw, s_rb2, lx, r0, &b2, &p2);
+            bad |= b2;
+            poor |= p2;
+        }
+    }
+    __syncthreads();
+    load_halo<H_, false>(V1, M1, W, H, pitch, X0, Y0, halo, badw);
+    conv16<H_>(halo, tV1, lx, r0, accv);
+    __syncthreads();
+    float accv2[16];
+    load_halo<H_, false>(V2, M2, W, H, pitch, X0, Y0, halo, badw);
+    conv16<H_>(halo, tV2, lx, r0, accv2);
+    const double d0 = a[N2 - 1];
+    const int gx = X0 + lx;
+    if (gx < X1) {
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+            const int gy = Y0 + r0 + j;
+            if (gy < Y1) {
+                const int64_t o = (int64_t)gy * pitch + gx;
+                D[o] = (float)((double)acc2[j] - (double)acc1[j] - d0);
+                VD[o] = accv[j] + accv2[j];
+                MD[o] = ((bad >> j) & 1u) ? PSFM_MASK_CONV_BAD : ((poor >> j) & 1u) ? PSFM_MASK_CONV_POOR : 0;
+            }
+        }
+    }
+}
+
+template <int H_>
+int launch_dual(const float* I1, const float* V1, const uint8_t* M1, const float* I2, const float* V2,
+                const uint8_t* M2, int W, int H, int64_t pitch, int P, const double* a, const BasisArgs& B,
+                int c_off, int N2, double bad_frac, float* D, float* VD, uint8_t* MD, hipStream_t st) {
+    const PatchGeom g = patch_geom(W, H, P);
+    hipLaunchKernelGGL((k_dual_tile<H_>), dim3(g.npx * g.tpp, g.npy * g.tpp), dim3(256), 0, st, I1, V1, M1,
+                       I2, V2, M2, W, H, pitch, P, a, B, c_off, N2, bad_frac, D, VD, MD);
+    PSFM_HIP_CHECK(hipGetLastError());
+    return PSFM_OK;
+}
+
 // Outliers on a convolved image traced back to pixels of its input
 // (Section 5.1): one workgroup per 64 x 64 tile of a patch.  The outlier
 // flags of the tile and its h-halo are bit-packed in LDS; a tile without any
@@ -1564,4 +1686,29 @@ extern "C" int psfm_trace_mask(const psfm_context* ctx, const double* coeffs, co
                        outliers, W, H, pitch, ctx->cfg.patch, coeffs, basis_args(ctx), frac, bad);
     PSFM_HIP_CHECK(hipGetLastError());
     return PSFM_OK;
+}
+
+extern "C" int psfm_dual_subtract(const psfm_context* ctx, const double* coeffs, const float* I1,
+                                  const float* V1, const uint8_t* M1, const float* I2, const float* V2,
+                                  const uint8_t* M2, int W, int H, int64_t pitch, float* diff,
+                                  float* diff_var, uint8_t* diff_mask, void* stream) {
+    int rc = check_image_args(ctx, W, H, pitch);
+    if (rc) return rc;
+    if (!coeffs || !I1 || !V1 || !M1 || !I2 || !V2 || !M2 || !diff || !diff_var || !diff_mask)
+        return PSFM_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    const psfm_config& cf = ctx->cfg;
+    const BasisArgs B = basis_args(ctx);
+    const int c_off = (ctx->nb - 1) * ctx->ns, N2 = psfm::dual_unknowns(ctx);
+    switch (ctx->h) {
+#define PSFM_DUAL_CASE(HH) \
+    case HH: return launch_dual<HH>(I1, V1, M1, I2, V2, M2, W, H, pitch, cf.patch, coeffs, B, c_off, N2, \
+                                    cf.bad_frac, diff, diff_var, diff_mask, st);
+        PSFM_DUAL_CASE(1) PSFM_DUAL_CASE(2) PSFM_DUAL_CASE(3) PSFM_DUAL_CASE(4) PSFM_DUAL_CASE(5)
+        PSFM_DUAL_CASE(6) PSFM_DUAL_CASE(7) PSFM_DUAL_CASE(8) PSFM_DUAL_CASE(9) PSFM_DUAL_CASE(10)
+        PSFM_DUAL_CASE(11) PSFM_DUAL_CASE(12) PSFM_DUAL_CASE(13) PSFM_DUAL_CASE(14) PSFM_DUAL_CASE(15)
+        PSFM_DUAL_CASE(16)
+#undef PSFM_DUAL_CASE
+        default: return PSFM_ERR_UNSUPPORTED;
+    }
 }

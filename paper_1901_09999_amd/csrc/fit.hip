@@ -56,6 +56,9 @@ constexpr int SEG = 12;          // stamp pixels per row-pass item
 constexpr int AT_STRIDE = 80;    // LDS row stride of the weighted block (bank spread)
 constexpr int GC = PSFM_GRAM_COLS;
 constexpr int A16S = 104;        // LDS column stride (halves) of the 16-bit block: up to 96 pixels
+// Band mode that only writes the FP32 weighted block to the stamp design (no
+// Gram): the two-kernel form's passes over I1 and over I2.
+constexpr int PREC_DESIGN = 16;
 
 struct FitLds {
     int win, col, R, At, sw, dt, psi, z, fac, rf, cf, total;  // float offsets
@@ -370,12 +373,15 @@ __device__ void fit_band_body(const FitArgs& a, const int item, float* __restric
                 else if (c == nb + 1) v = dtb[br * NPX + x];
                 if (c < nb + 2) dsg[(size_t)c * (NPX * NPX) + x] = v;
             }
-            const unsigned short hi = to16<PREC>(v);
-            A16[c * A16S + x] = hi;
-            if constexpr (PREC == PSFM_PREC_BF16)
-                A16lo[c * A16S + x] = to16<PREC>(v - (float)__builtin_bit_cast(__bf16, hi));
+            if constexpr (PREC != PREC_DESIGN) {
+                const unsigned short hi = to16<PREC>(v);
+                A16[c * A16S + x] = hi;
+                if constexpr (PREC == PSFM_PREC_BF16)
+                    A16lo[c * A16S + x] = to16<PREC>(v - (float)__builtin_bit_cast(__bf16, hi));
+            }
         }
         __syncthreads();
+        if constexpr (PREC != PREC_DESIGN) {
         // 3c'. Gram blocks, K = 32 pixels per instruction (same wave blocks)
         for (int ks = 0; ks < kp / 32; ks++) {
             const unsigned short* colp = A16 + (lane & 15) * A16S + 32 * ks + 8 * (lane >> 4);
@@ -432,9 +438,10 @@ __device__ void fit_band_body(const FitArgs& a, const int item, float* __restric
             }
         }
         }
+        }
         // 16-bit modes: the FP32 MFMA sums cover one stamp row; rows are
         // added in FP64.
-        if constexpr (PREC != PSFM_PREC_FP32) {
+        if constexpr (PREC != PSFM_PREC_FP32 && PREC != PREC_DESIGN) {
 #pragma unroll
             for (int q = 0; q < 3; q++) {
 #pragma unroll
@@ -448,6 +455,10 @@ __device__ void fit_band_body(const FitArgs& a, const int item, float* __restric
 
     // ---- 4. partial Gram out, column 16 bn + lane % 16; row 16 bm + (lane / 16) + 4 e
     //         from the FP64 MFMA, 16 bm + 4 (lane / 16) + e from the FP32 ones
+    if constexpr (PREC == PREC_DESIGN) {
+        if (tid == 0) band_flags[item] = 0;
+        return;
+    }
     double* G = part + (size_t)item * GC * GC;
     const int bms[4][3] = {{0, 1, 1}, {2, 2, 2}, {3, 3, -1}, {3, 3, -1}};
     const int bns[4][3] = {{0, 0, 1}, {0, 1, 2}, {0, 1, -1}, {2, 3, -1}};
@@ -572,6 +583,115 @@ __global__ __launch_bounds__(256) void k_fit_reduce_b(const PairDesc* __restrict
                     blockIdx.x - pd.stamp_off, blockIdx.y, gridDim.y);
 }
 
+// Per-stamp sums of the two-kernel form (Section 2, Eqs. 3-6 with the I2
+// columns): one workgroup per stamp over the two FP32 designs of the
+// design-only band passes (over I1, and over I2 in its place).  Columns, in
+// the order of the stamp matrix: k_i (x) I1 for i < nb (design 1), k_i (x) I2
+// for 1 <= i < nb (design 2), sqrt(w), then sqrt(w) I2 (design 1); chunks of
+// GD_KC pixels go through LDS and the lower 16 x 16 blocks of their Gram
+// accumulate on v_mfma_f64_16x16x4f64 (exact products of the FP32 values,
+// FP64 sums), blocks q = wave + 4 j.
+constexpr int GD_KC = 32;               // stamp pixels per LDS chunk
+constexpr int GD_COLS = 128;            // 2 nb + 1 <= 125 columns (nb <= 62)
+constexpr int GD_STRIDE = GD_COLS + 4;  // LDS row stride (floats)
+constexpr int GD_JMAX = 9;              // blocks per wave: 36 lower blocks / 4 waves
+
+__global__ __launch_bounds__(256) void k_gram_dual(const float* __restrict__ d1,
+                                                   const float* __restrict__ d2,
+                                                   const int* __restrict__ bf1,
+                                                   const int* __restrict__ bf2, int nbands, int nb,
+                                                   int npix, double* __restrict__ Ms,
+                                                   double* __restrict__ bs, double* __restrict__ es,
+                                                   int32_t* __restrict__ npix_out,
+                                                   int32_t* __restrict__ flags_out) {
+    __shared__ float Tb[GD_KC * GD_STRIDE];
+    __shared__ int s_fl;
+    const int s = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int L = 2 * nb, Lx = L + 1, nblk = (Lx + 15) / 16, ntri = nblk * (nblk + 1) / 2;
+    if (tid < 64) {
+        int f = 0;
+        for (int b = tid; b < nbands; b += 64) f |= bf1[s * nbands + b] | bf2[s * nbands + b];
+        for (int o = 32; o > 0; o >>= 1) f |= __shfl_xor(f, o);
+        if (tid == 0) s_fl = (f & PSFM_STAMP_INVALID) ? PSFM_STAMP_INVALID : f;
+    }
+    __syncthreads();
+    const int fl = s_fl;
+    double* M = Ms + (size_t)s * L * L;
+    double* bv = bs + (size_t)s * L;
+    if (fl) {
+        for (int e = tid; e < L * L; e += 256) M[e] = 0.0;
+        for (int e = tid; e < L; e += 256) bv[e] = 0.0;
+        if (tid == 0) {
+            es[s] = 0.0;
+            npix_out[s] = 0;
+            flags_out[s] = fl;
+        }
+        return;
+    }
+    const size_t dstride = (size_t)(nb + 2) * npix;
+    const float* D1 = d1 + (size_t)s * dstride;
+    const float* D2 = d2 + (size_t)s * dstride;
+    int bmq[GD_JMAX], bnq[GD_JMAX];
+    doublex4 acc[GD_JMAX];
+#pragma unroll
+    for (int j = 0; j < GD_JMAX; j++) {
+        const int q = wave + 4 * j;
+        int bm = 0;
+        while ((bm + 1) * (bm + 2) / 2 <= q) bm++;
+        bmq[j] = q < ntri ? bm : -1;
+        bnq[j] = q - bm * (bm + 1) / 2;
+        acc[j] = doublex4{0.0, 0.0, 0.0, 0.0};
+    }
+    for (int x0 = 0; x0 < npix; x0 += GD_KC) {
+        __syncthreads();
+        for (int e = tid; e < GD_COLS * GD_KC; e += 256) {
+            const int c = e / GD_KC, x = e - c * GD_KC, px = x0 + x;
+            float v = 0.0f;
+            if (px < npix && c < Lx) {
+                const float* col = c < nb ? D1 + (size_t)c * npix
+                                   : c < L - 1 ? D2 + (size_t)(c - nb + 1) * npix
+                                   : D1 + (size_t)(nb + c - (L - 1)) * npix;
+                v = col[px];
+            }
+            Tb[x * GD_STRIDE + c] = v;
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int ks = 0; ks < GD_KC / 4; ks++) {
+            const float* rowp = Tb + (4 * ks + (lane >> 4)) * GD_STRIDE + (lane & 15);
+#pragma unroll
+            for (int j = 0; j < GD_JMAX; j++) {
+                if (bmq[j] < 0) continue;
+                const double av = rowp[16 * bmq[j]], bw = rowp[16 * bnq[j]];
+                acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bw, acc[j], 0, 0, 0);
+            }
+        }
+    }
+    // D row 16 bm + (lane / 16) + 4 e, column 16 bn + lane % 16
+#pragma unroll
+    for (int j = 0; j < GD_JMAX; j++) {
+        if (bmq[j] < 0) continue;
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const int i = 16 * bmq[j] + (lane >> 4) + 4 * e, jj = 16 * bnq[j] + (lane & 15);
+            if (i >= Lx || jj >= Lx || jj > i) continue;
+            const double v = acc[j][e];
+            if (i < L) {
+                M[(size_t)i * L + jj] = v;
+                M[(size_t)jj * L + i] = v;
+            } else if (jj < L) {
+                bv[jj] = v;
+            } else {
+                es[s] = v;
+            }
+        }
+    }
+    if (tid == 0) {
+        npix_out[s] = npix;
+        flags_out[s] = 0;
+    }
+}
+
 FitArgs base_fit_args(const psfm_context* ctx) {
     FitArgs a{};
     a.r = ctx->r;
@@ -598,6 +718,8 @@ int set_fit_lds(size_t lds) {
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         PSFM_HIP_CHECK(hipFuncSetAttribute((const void*)k_fit_band_b<H_, BR>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        PSFM_HIP_CHECK(hipFuncSetAttribute((const void*)k_fit_band<H_, PREC_DESIGN, BR>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         granted = lds;
     }
     return PSFM_OK;
@@ -614,14 +736,15 @@ int set_fit_lds_ctx(const psfm_context* ctx, size_t lds) {
 
 template <int H_, int BR>
 int launch_fit_br(const psfm_context* ctx, const FitArgs& a, int n_items, const PairDesc* pairs,
-                  const int* item_pair, hipStream_t st) {
+                  const int* item_pair, int prec, hipStream_t st) {
     const FitLds Lo = fit_lds_layout(H_, ctx->r, ctx->nb, ctx->nf, BR,
-                                     ctx->cfg.precision == PSFM_PREC_BF16 && !pairs);
+                                     prec == PSFM_PREC_BF16 && !pairs);
     const size_t lds = (size_t)Lo.total * sizeof(float);
     int rc = set_fit_lds<H_, BR>(lds);
     if (rc) return rc;
-    const int prec = ctx->cfg.precision;
-    if (pairs)
+    if (prec == PREC_DESIGN)
+        hipLaunchKernelGGL((k_fit_band<H_, PREC_DESIGN, BR>), dim3(n_items), dim3(256), lds, st, a);
+    else if (pairs)
         hipLaunchKernelGGL((k_fit_band_b<H_, BR>), dim3(n_items), dim3(256), lds, st, pairs, item_pair, a);
     else if (prec == PSFM_PREC_FP16)
         hipLaunchKernelGGL((k_fit_band<H_, PSFM_PREC_FP16, BR>), dim3(n_items), dim3(256), lds, st, a);
@@ -635,17 +758,19 @@ int launch_fit_br(const psfm_context* ctx, const FitArgs& a, int n_items, const 
 
 template <int H_>
 int launch_fit(const psfm_context* ctx, const FitArgs& a, int n_items, const PairDesc* pairs,
-               const int* item_pair, hipStream_t st) {
+               const int* item_pair, int prec, hipStream_t st) {
     return ctx->fit_br == PSFM_FIT_BR_SMALL
-               ? launch_fit_br<H_, PSFM_FIT_BR_SMALL>(ctx, a, n_items, pairs, item_pair, st)
-               : launch_fit_br<H_, PSFM_FIT_BR_LARGE>(ctx, a, n_items, pairs, item_pair, st);
+               ? launch_fit_br<H_, PSFM_FIT_BR_SMALL>(ctx, a, n_items, pairs, item_pair, prec, st)
+               : launch_fit_br<H_, PSFM_FIT_BR_LARGE>(ctx, a, n_items, pairs, item_pair, prec, st);
 }
 
+// prec: the context's precision, or PREC_DESIGN for a design-only pass.
 int dispatch_fit(const psfm_context* ctx, const FitArgs& a, int n_items, const PairDesc* pairs,
-                 const int* item_pair, hipStream_t st) {
+                 const int* item_pair, hipStream_t st, int prec = -1) {
+    if (prec < 0) prec = ctx->cfg.precision;
     switch (ctx->h) {
 #define PSFM_FIT_CASE(HH) \
-    case HH: return launch_fit<HH>(ctx, a, n_items, pairs, item_pair, st);
+    case HH: return launch_fit<HH>(ctx, a, n_items, pairs, item_pair, prec, st);
         PSFM_FIT_CASE(1) PSFM_FIT_CASE(2) PSFM_FIT_CASE(3) PSFM_FIT_CASE(4) PSFM_FIT_CASE(5)
         PSFM_FIT_CASE(6) PSFM_FIT_CASE(7) PSFM_FIT_CASE(8) PSFM_FIT_CASE(9) PSFM_FIT_CASE(10)
         PSFM_FIT_CASE(11) PSFM_FIT_CASE(12) PSFM_FIT_CASE(13) PSFM_FIT_CASE(14) PSFM_FIT_CASE(15)
@@ -691,6 +816,18 @@ int batch_fit(const psfm_context* ctx, const PairDesc* pairs, const int* item_pa
                        stamp_pair, fit_bands(ctx), ctx->nb, npix);
     PSFM_HIP_CHECK(hipGetLastError());
     return PSFM_OK;
+}
+
+// The two-kernel fit: both designs and both passes' band flags.
+size_t dual_fit_workspace(const psfm_context* ctx, int n_stamps) {
+    Carver c(nullptr);
+    const size_t npix = (size_t)(2 * ctx->r + 1) * (2 * ctx->r + 1);
+    const size_t nbl = (size_t)n_stamps * fit_bands(ctx);
+    c.take<float>((size_t)n_stamps * (ctx->nb + 2) * npix);
+    c.take<float>((size_t)n_stamps * (ctx->nb + 2) * npix);
+    c.take<int>(nbl);
+    c.take<int>(nbl);
+    return c.off;
 }
 
 size_t fit_workspace(const psfm_context* ctx, int n_stamps) {
@@ -744,6 +881,57 @@ extern "C" int psfm_fit_stamps(const psfm_context* ctx, const float* I1, const u
     hipLaunchKernelGGL(k_fit_reduce, dim3(n_stamps, reduce_parts(ctx)), dim3(256), 0, st, part, bflags,
                        psfm::fit_bands(ctx), ctx->nb, npix, stamp_M, stamp_b, stamp_e, stamp_npix,
                        stamp_flags);
+    PSFM_HIP_CHECK(hipGetLastError());
+    return PSFM_OK;
+}
+
+extern "C" int psfm_fit_dual(const psfm_context* ctx, const float* I1, const uint8_t* M1,
+                             const float* I2, const float* V2, const uint8_t* M2, int W, int H,
+                             int64_t pitch, const int32_t* stamp_xy, int n_stamps, double* stamp_M,
+                             double* stamp_b, double* stamp_e, int32_t* stamp_npix,
+                             int32_t* stamp_flags, void* ws, size_t ws_bytes, void* stream) {
+    if (!ctx || n_stamps < 0) return PSFM_ERR_INVALID_ARG;
+    if (W < 1 || H < 1 || pitch < W) return PSFM_ERR_SHAPE;
+    if (n_stamps == 0) return PSFM_OK;
+    if (!I1 || !M1 || !I2 || !V2 || !M2 || !stamp_xy || !stamp_M || !stamp_b || !stamp_e ||
+        !stamp_npix || !stamp_flags)
+        return PSFM_ERR_INVALID_ARG;
+    if (2 * ctx->nb + 1 > GD_COLS) return PSFM_ERR_UNSUPPORTED;
+    if (psfm::fit_lds_bytes(ctx) > 160 * 1024 - 1024) return PSFM_ERR_UNSUPPORTED;
+    if (!ws || ws_bytes < psfm::dual_fit_workspace(ctx, n_stamps)) return PSFM_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    const int npix = (2 * ctx->r + 1) * (2 * ctx->r + 1);
+    const size_t dsz = (size_t)n_stamps * (ctx->nb + 2) * npix;
+    psfm::Carver c(ws);
+    float* d1 = c.take<float>(dsz);
+    float* d2 = c.take<float>(dsz);
+    const size_t nbl = (size_t)n_stamps * psfm::fit_bands(ctx);
+    int* bf1 = c.take<int>(nbl);
+    int* bf2 = c.take<int>(nbl);
+    FitArgs a = base_fit_args(ctx);
+    a.I1 = I1;
+    a.M1 = M1;
+    a.I2 = I2;
+    a.V2 = V2;
+    a.M2 = M2;
+    a.W = W;
+    a.H = H;
+    a.pitch = pitch;
+    a.xy = stamp_xy;
+    a.part = nullptr;
+    a.band_flags = bf1;
+    a.design = d1;
+    int rc = dispatch_fit(ctx, a, n_stamps * a.nbands, nullptr, nullptr, st, PREC_DESIGN);
+    if (rc != PSFM_OK) return rc;
+    // the I2 columns: the same pass with I2 (and its mask) as the convolved image
+    a.I1 = I2;
+    a.M1 = M2;
+    a.band_flags = bf2;
+    a.design = d2;
+    rc = dispatch_fit(ctx, a, n_stamps * a.nbands, nullptr, nullptr, st, PREC_DESIGN);
+    if (rc != PSFM_OK) return rc;
+    hipLaunchKernelGGL(k_gram_dual, dim3(n_stamps), dim3(256), 0, st, d1, d2, bf1, bf2, a.nbands, ctx->nb,
+                       npix, stamp_M, stamp_b, stamp_e, stamp_npix, stamp_flags);
     PSFM_HIP_CHECK(hipGetLastError());
     return PSFM_OK;
 }

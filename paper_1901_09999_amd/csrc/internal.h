@@ -38,6 +38,7 @@ struct psfm_context {
     double* psi64;    // [nb] normalisations in FP64
     double* kgram_R;  // [nb][nb] upper factor R of B^T B (B = taps as columns): |B a| = |R a|
     bool kgram_ok;    // false if the basis taps are (nearly) dependent: no R
+    double* penq;     // [nb] penalty weights sum (u^2 + v^2)^2 k_i^2 (two-kernel form)
     void* dev_block;  // single allocation backing all of the above
 };
 
@@ -143,7 +144,10 @@ struct Carver {
 
 // Per-call workspace needs (bytes).
 size_t fit_workspace(const psfm_context* ctx, int n_stamps);
+size_t dual_fit_workspace(const psfm_context* ctx, int n_stamps);
 size_t solve_workspace(const psfm_context* ctx, int n_stamps);
+size_t dual_solve_workspace(const psfm_context* ctx, int n_stamps);
+int dual_unknowns(const psfm_context* ctx);
 size_t conv_workspace(const psfm_context* ctx, int W, int H);
 size_t subtract_workspace(const psfm_context* ctx, int W, int H);
 size_t match_workspace(const psfm_context* ctx, int W, int H);

@@ -1037,22 +1037,22 @@ __device__ void chi2_body(int nb, int ns, int N, const double* __restrict__ Ms,
     if (st->done) return;
     const int lane = threadIdx.x;
     if (!fitted[s]) return;
-    __shared__ double alpha[64];
-    const int L = nb + 1;
-    if (lane < L) {
+    __shared__ double alpha[128];
+    const int L = nb + 1;     // up to 128 (the two-kernel form); rows lane and lane + 64
+    for (int r = lane; r < L; r += 64) {
         double al;
-        if (lane < nb) {
+        if (r < nb) {
             al = 0.0;
-            for (int q = 0; q < ns; q++) al += a[lane * ns + q] * G[(size_t)s * ns + q];
+            for (int q = 0; q < ns; q++) al += a[r * ns + q] * G[(size_t)s * ns + q];
         } else {
             al = a[N - 1];
         }
-        alpha[lane] = al;
+        alpha[r] = al;
     }
     wave_sync();
     double part = 0.0;
-    if (lane < L) {
-        const double* Mc = Ms + (size_t)s * L * L + lane;
+    for (int r = lane; r < L; r += 64) {
+        const double* Mc = Ms + (size_t)s * L * L + r;
         double u0 = 0.0, u1 = 0.0, u2 = 0.0, u3 = 0.0;
         int i = 0;
         for (; i + 3 < L; i += 4) {
@@ -1062,8 +1062,8 @@ __device__ void chi2_body(int nb, int ns, int N, const double* __restrict__ Ms,
             u3 += alpha[i + 3] * Mc[(size_t)(i + 3) * L];
         }
         for (; i < L; i++) u0 += alpha[i] * Mc[(size_t)i * L];
-        const double al = alpha[lane];
-        part = al * ((u0 + u1) + (u2 + u3)) - 2.0 * al * bs[(size_t)s * L + lane];
+        const double al = alpha[r];
+        part += al * ((u0 + u1) + (u2 + u3)) - 2.0 * al * bs[(size_t)s * L + r];
     }
     for (int o = 32; o > 0; o >>= 1) part += __shfl_down(part, o);
     if (lane == 0) chi2[s] = es[s] + part;
@@ -1186,6 +1186,32 @@ __global__ __launch_bounds__(64) void k_chi2_clip(int n, int nb, int ns, int N,
     if (threadIdx.x == 0)
         __hip_atomic_store(&st->chi2_done, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     clip_body(n, max_iter, min_stamps, clip_sigma, npix, used, flags, chi2, st);
+}
+
+// Penalty of the two-kernel form (Eq. 9): unknowns of the spatially varying
+// columns i = 1 .. nt - 1 (b-terms i < nb, c-terms of basis i - nb + 1 above),
+// every spatial term, get Phi Q_i on the diagonal, with
+// Phi = phi (sum of their diagonal) / (sum of their Q_i), summed in a fixed
+// order over the workgroup.
+__global__ __launch_bounds__(1024) void k_penalty(int N, int ns, int nt, int nb,
+                                                  const double* __restrict__ Q, double phi,
+                                                  double* __restrict__ M, const SolveState* st) {
+    __shared__ double red[16];
+    if (st->done) return;
+    const int np = (nt - 1) * ns;
+    double dsum = 0.0, qsum = 0.0;
+    for (int e = threadIdx.x; e < np; e += blockDim.x) {
+        const int j = ns + e, i = j / ns;
+        dsum += M[(size_t)j * N + j];
+        qsum += Q[i < nb ? i : i - nb + 1];
+    }
+    dsum = block_sum(dsum, red);
+    qsum = block_sum(qsum, red);
+    const double Phi = qsum > 0.0 ? phi * dsum / qsum : 0.0;
+    for (int e = threadIdx.x; e < np; e += blockDim.x) {
+        const int j = ns + e, i = j / ns;
+        M[(size_t)j * N + j] += Phi * Q[i < nb ? i : i - nb + 1];
+    }
 }
 
 __device__ void solve_finish_body(int n, int ns, int N, int n_par, int S, int W, int H,
@@ -1972,11 +1998,15 @@ int batch_solve(const psfm_context* ctx, const PairDesc* pairs, const int* stamp
 
 // Shared launch sequence of psfm_solve and psfm_solve_prior (prior: the
 // per-stamp predicted local coefficients, or null).
+// penq (nullable): penalty weights of the two-kernel form, whose view of the
+// context (nb = 2 nb - 1 spatially varying columns) ctx then is; pen_nb is
+// the basis size they index.
 static int solve_impl(const psfm_context* ctx, int W, int H, const int32_t* stamp_xy, int n_stamps,
                       const double* stamp_M, const double* stamp_b, const double* stamp_e,
                       const int32_t* stamp_npix, int32_t* stamp_flags, const float* stamp_design,
                       const double* prior, double* coeffs, double* stamp_chi2,
-                      psfm_fit_stats* stats, void* ws, size_t ws_bytes, hipStream_t st) {
+                      psfm_fit_stats* stats, void* ws, size_t ws_bytes, hipStream_t st,
+                      const double* penq = nullptr, double phi = 0.0, int pen_nb = 0) {
     if (!ctx || n_stamps < 0 || !coeffs || !stats) return PSFM_ERR_INVALID_ARG;
     const bool mixed = ctx->cfg.precision != PSFM_PREC_FP32;
     if (mixed && n_stamps > 0 && !stamp_design) return PSFM_ERR_INVALID_ARG;
@@ -2065,6 +2095,9 @@ static int solve_impl(const psfm_context* ctx, int W, int H, const int32_t* stam
 #undef PSFM_ASM_CASE
             default: return PSFM_ERR_UNSUPPORTED;
         }
+        if (penq)
+            hipLaunchKernelGGL(k_penalty, dim3(1), dim3(1024), 0, st, N, ns, nb, pen_nb, penq, phi, M,
+                               state);
         hipLaunchKernelGGL(k_cholesky<false>, dim3(1), dim3(CH_THREADS), lds, st, N, M, b, coeffs, ILg,
                            mixed ? Dg : nullptr, state, nullptr, nullptr,
                            mixed && n_stamps > 0 ? LT : nullptr);
@@ -2259,4 +2292,36 @@ extern "C" int psfm_solve_norm(const psfm_context* ctx, int W, int H, const int3
                        cf.spatial_order, W, H, stamp_npix, used, stamp_chi2, coeffs, state, stats);
     PSFM_HIP_CHECK(hipGetLastError());
     return PSFM_OK;
+}
+
+// The two-kernel form's view of the context: its 2 nb - 1 spatially varying
+// columns take the place of the nb basis terms (stamp matrices 2 nb wide).
+static psfm_context dual_view(const psfm_context* ctx) {
+    psfm_context d = *ctx;
+    d.nb = 2 * ctx->nb - 1;
+    d.L = 2 * ctx->nb;
+    d.N = d.nb * ctx->ns + 1;
+    d.cfg.precision = PSFM_PREC_FP32;
+    return d;
+}
+
+namespace psfm {
+size_t dual_solve_workspace(const psfm_context* ctx, int n_stamps) {
+    const psfm_context d = dual_view(ctx);
+    return solve_workspace(&d, n_stamps);
+}
+int dual_unknowns(const psfm_context* ctx) { return (2 * ctx->nb - 1) * ctx->ns + 1; }
+}  // namespace psfm
+
+extern "C" int psfm_solve_dual(const psfm_context* ctx, int W, int H, const int32_t* stamp_xy,
+                               int n_stamps, const double* stamp_M, const double* stamp_b,
+                               const double* stamp_e, const int32_t* stamp_npix, int32_t* stamp_flags,
+                               double phi, double* coeffs, double* stamp_chi2, psfm_fit_stats* stats,
+                               void* ws, size_t ws_bytes, void* stream) {
+    if (!ctx || !(phi >= 0.0)) return PSFM_ERR_INVALID_ARG;
+    const psfm_context d = dual_view(ctx);
+    if (d.L > 128) return PSFM_ERR_UNSUPPORTED;
+    return solve_impl(&d, W, H, stamp_xy, n_stamps, stamp_M, stamp_b, stamp_e, stamp_npix, stamp_flags,
+                      nullptr, nullptr, coeffs, stamp_chi2, stats, ws, ws_bytes, (hipStream_t)stream,
+                      ctx->penq, phi, ctx->nb);
 }

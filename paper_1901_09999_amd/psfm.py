@@ -157,6 +157,11 @@ def lib():
             "psfm_resample_cov": (i, [P, i, C.c_double, P, i, P]),
             "psfm_add_images": (i, [C.c_double, P, P, P, P, i, C.c_double, P, P, P, P, i, i, i, i64, P,
                                     P, P, P, i, P, sz, P]),
+            "psfm_dual_workspace_bytes": (sz, [P, i, i, i]),
+            "psfm_dual_unknowns": (i, [P]),
+            "psfm_fit_dual": (i, [P, P, P, P, P, P, i, i, i64, P, i, P, P, P, P, P, P, sz, P]),
+            "psfm_solve_dual": (i, [P, i, i, P, i, P, P, P, P, P, C.c_double, P, P, P, P, sz, P]),
+            "psfm_dual_subtract": (i, [P, P, P, P, P, P, P, P, i, i, i64, P, P, P, P]),
             "psfm_envelope_psf": (i, [P, i, i, P, P, P]),
             "psfm_render_workspace_bytes": (sz, [i, i, i, C.c_double]),
             "psfm_render_target": (i, [P, i, C.c_double, i, i, i64, P, P, sz, P]),
@@ -394,6 +399,63 @@ class Context:
                                        _ptr(stamps), n, _ptr(flags), float(soft), _ptr(dev), _ptr(q),
                                        _stream()), "psfm_quality_eval")
         return q, dev[:n]
+
+    # ------------------------------------------------- both images to a common PSF
+    @property
+    def N2(self) -> int:
+        return lib().psfm_dual_unknowns(self._h)
+
+    def dual_workspace(self, W: int, H: int, n_stamps: int) -> torch.Tensor:
+        need = lib().psfm_dual_workspace_bytes(self._h, W, H, n_stamps)
+        if need == 0:
+            raise PsfmError("invalid workspace request")
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def fit_dual(self, I1, M1, I2, V2, M2, stamps):
+        """psfm_fit_dual: dict(M [n, 2nb, 2nb], b, e, npix, flags)."""
+        H, W = I1.shape
+        n = stamps.shape[0]
+        L = 2 * self.nb
+        dev = self.device
+        out = dict(M=torch.empty((n, L, L), dtype=torch.float64, device=dev),
+                   b=torch.empty((n, L), dtype=torch.float64, device=dev),
+                   e=torch.empty(n, dtype=torch.float64, device=dev),
+                   npix=torch.empty(n, dtype=torch.int32, device=dev),
+                   flags=torch.empty(n, dtype=torch.int32, device=dev))
+        ws = self.dual_workspace(W, H, n)
+        _check(lib().psfm_fit_dual(self._h, _ptr(I1), _ptr(M1), _ptr(I2), _ptr(V2), _ptr(M2), W, H, W,
+                                   _ptr(stamps), n, _ptr(out["M"]), _ptr(out["b"]), _ptr(out["e"]),
+                                   _ptr(out["npix"]), _ptr(out["flags"]), _ptr(ws), ws.numel(),
+                                   _stream()), "psfm_fit_dual")
+        return out
+
+    def solve_dual(self, W, H, stamps, fit, phi, flags=None):
+        """psfm_solve_dual: dict(coeffs [N2], chi2, stats, flags)."""
+        n = stamps.shape[0]
+        dev = self.device
+        fl = (fit["flags"] if flags is None else flags).clone()
+        out = dict(coeffs=torch.empty(self.N2, dtype=torch.float64, device=dev),
+                   chi2=torch.empty(max(n, 1), dtype=torch.float64, device=dev),
+                   stats=torch.zeros(STATS_BYTES, dtype=torch.uint8, device=dev), flags=fl)
+        ws = self.dual_workspace(W, H, n)
+        _check(lib().psfm_solve_dual(self._h, W, H, _ptr(stamps), n, _ptr(fit["M"]), _ptr(fit["b"]),
+                                     _ptr(fit["e"]), _ptr(fit["npix"]), _ptr(fl), float(phi),
+                                     _ptr(out["coeffs"]), _ptr(out["chi2"]), _ptr(out["stats"]), _ptr(ws),
+                                     ws.numel(), _stream()), "psfm_solve_dual")
+        return out
+
+    def dual_subtract(self, coeffs, I1, V1, M1, I2, V2, M2):
+        """psfm_dual_subtract: (D, V_D, mask_D)."""
+        H, W = I1.shape
+        D = torch.empty_like(I1)
+        VD = torch.empty_like(V1)
+        MD = torch.empty_like(M1)
+        _check(lib().psfm_dual_subtract(self._h, _ptr(coeffs), _ptr(I1), _ptr(V1), _ptr(M1), _ptr(I2),
+                                        _ptr(V2), _ptr(M2), W, H, W, _ptr(D), _ptr(VD), _ptr(MD),
+                                        _stream()), "psfm_dual_subtract")
+        return D, VD, MD
 
     def convolve_image(self, coeffs, I, M, out=None, out_mask=None):
         H, W = I.shape
@@ -817,6 +879,8 @@ def exported_symbols() -> Sequence[str]:
             "psfm_solve_stamps", "psfm_solve_prior", "psfm_cholesky_workspace_bytes",
             "psfm_fit_norm", "psfm_solve_norm", "psfm_quality_eval", "psfm_bin_image",
             "psfm_resample_cov", "psfm_add_images",
+            "psfm_dual_workspace_bytes", "psfm_dual_unknowns", "psfm_fit_dual", "psfm_solve_dual",
+            "psfm_dual_subtract",
             "psfm_envelope_psf", "psfm_render_workspace_bytes", "psfm_render_target",
             "psfm_stack_reject", "psfm_trace_mask", "psfm_stack_combine",
             "psfm_cholesky_solve", "psfm_cnn_param_count",
