@@ -274,7 +274,7 @@ def bench_batch(args, torch, psfm, synth):
                        "max": round(float(lat.max()), 3)},
         "graph_ms_per_step": round(float(np.median(per)), 4),
         "stages_ms": {k: round(float(v), 4) for k, v in
-                      zip(["fit", "solve", "pseudo_matrices", "match_tiles"], stage)},
+                      zip(["fit", "solve", "patch_kernels_pseudo_matrices", "match_tiles"], stage)},
         "fit": {"solved": int(sum(s["info"] == 0 for s in st)),
                 "rejected_stamps": int(sum(s["n_rejected"] for s in st)),
                 "solutions": int(sum(s["n_iter"] for s in st)),

@@ -742,9 +742,11 @@ int psfm_batch_plan(const psfm_context* ctx, const psfm_pair* pairs, int n_pairs
 int psfm_batch_run(psfm_batch* batch, void* stream);
 
 /* One stage of psfm_batch_run: 0 = start time and stamp fits, 1 = solve
-   loop, 2 = pseudo-matrices of the convolved images, 3 = the fused
-   convolution / difference pass (one launch).  Running stages 0, 1, 2, 3 in
-   order is psfm_batch_run (for timing stages). */
+   loop, 2 = the patch kernels of every pair (FP32 taps and BAD radii kept in
+   the workspace) and the pseudo-matrices of the convolved images, 3 = the
+   fused convolution / difference pass (one launch, reading the taps of
+   stage 2).  Running stages 0, 1, 2, 3 in order is psfm_batch_run (for
+   timing stages). */
 int psfm_batch_run_stage(psfm_batch* batch, int stage, void* stream);
 
 /* Changes the apply grid of a plan (tuning->order is fixed at plan time).

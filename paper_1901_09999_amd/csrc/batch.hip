@@ -10,6 +10,8 @@
 //   solve loop (max_iter rounds)      assembly per spatial order,
 //                                     one Cholesky workgroup per pair,
 //                                     chi2 of all stamps, clip per pair
+//   k_realise_b                       patch kernels of all pairs: FP32 taps and
+//                                     BAD radii for the tile pass (stage 2)
 //   k_cov_auto_b / k_cov_mix_b /      pseudo-matrices of the convolved images
 //   k_cov_finish_b                    (stage 2)
 //   k_match_tiles_b                   (stage 3) fused convolution + difference over the
@@ -28,7 +30,7 @@
 struct psfm_batch {
     const psfm_context* ctx;
     int n_pairs;
-    int n_items, n_stamps, n_tiles;
+    int n_items, n_stamps, n_tiles, n_patches;
     int max_n, max_N, max_cov_in;
     unsigned ns_mask;
     psfm_batch_tuning tuning;
@@ -36,6 +38,7 @@ struct psfm_batch {
     int* d_item_pair;
     int* d_stamp_pair;
     int* d_tile_pair;
+    int* d_patch_pair;
     unsigned* d_counters;
     uint64_t* times;
     hipGraph_t graph;
@@ -53,7 +56,7 @@ __global__ void k_batch_init(unsigned* __restrict__ counters, int n_pairs, uint6
 int n_spatial_of(int S) { return (S + 1) * (S + 2) / 2; }
 
 struct PairSizes {
-    int nbands, ns, N, L, ntx, nty, Rw, cov_in;
+    int nbands, ns, N, L, ntx, nty, npatch, Rw, cov_in;
 };
 
 PairSizes sizes_of(const psfm_context* ctx, const psfm_pair& q) {
@@ -66,6 +69,7 @@ PairSizes sizes_of(const psfm_context* ctx, const psfm_pair& q) {
     const int tpp = (P + PSFM_TILE - 1) / PSFM_TILE;
     z.ntx = (q.width + P - 1) / P * tpp;
     z.nty = (q.height + P - 1) / P * tpp;
+    z.npatch = ((q.width + P - 1) / P) * ((q.height + P - 1) / P);
     z.cov_in = q.cov1 ? q.cov1_half : 0;
     z.Rw = psfm::cov_sample_side(ctx, z.cov_in);
     return z;
@@ -93,10 +97,11 @@ struct Layout {
     int* item_pair;
     int* stamp_pair;
     int* tile_pair;
+    int* patch_pair;
     unsigned* counters;
     std::vector<PairDesc> desc;
     size_t bytes;
-    int n_items = 0, n_stamps = 0, n_tiles = 0;
+    int n_items = 0, n_stamps = 0, n_tiles = 0, n_patches = 0;
 };
 
 void lay_out(const psfm_context* ctx, const psfm_pair* q, const int* order, int n, void* base,
@@ -107,14 +112,16 @@ void lay_out(const psfm_context* ctx, const psfm_pair* q, const int* order, int 
         Lo.n_items += q[k].n_stamps * z.nbands;
         Lo.n_stamps += q[k].n_stamps;
         Lo.n_tiles += z.ntx * z.nty;
+        Lo.n_patches += z.npatch;
     }
     Lo.pairs = c.take<PairDesc>(n);
     Lo.item_pair = c.take<int>(Lo.n_items + 1);
     Lo.stamp_pair = c.take<int>(Lo.n_stamps + 1);
     Lo.tile_pair = c.take<int>(Lo.n_tiles + 1);
+    Lo.patch_pair = c.take<int>(Lo.n_patches + 1);
     Lo.counters = c.take<unsigned>(n + 1);
     Lo.desc.assign(n, PairDesc{});
-    int band_off = 0, stamp_off = 0, tile_off = 0;
+    int band_off = 0, stamp_off = 0, tile_off = 0, patch_off = 0;
     // fit and solve lists follow the given order; tiles follow `order`
     for (int k = 0; k < n; k++) {
         const psfm_pair& p = q[k];
@@ -173,6 +180,9 @@ void lay_out(const psfm_context* ctx, const psfm_pair* q, const int* order, int 
                             : nullptr;
         d.cov_avg = c.take<double>((size_t)z.Rw * z.Rw);
         d.sub_part = c.take<double>((size_t)4 * z.ntx * z.nty);
+        d.ptaps = c.take<float>((size_t)z.npatch * psfm::patch_taps_floats(ctx->h));
+        d.patch_off = patch_off;
+        patch_off += z.npatch;
         d.tiles_done = Lo.counters + k;
         d.t_done = nullptr;
         d.band_off = band_off;
@@ -232,7 +242,7 @@ extern "C" int psfm_batch_plan(const psfm_context* ctx, const psfm_pair* pairs, 
     lay_out(ctx, pairs, order.data(), n_pairs, ws, Lo);
     // work lists (host) -> workspace
     std::vector<int> item_pair(Lo.n_items + 1, 0), stamp_pair(Lo.n_stamps + 1, 0),
-        tile_pair(Lo.n_tiles + 1, 0);
+        tile_pair(Lo.n_tiles + 1, 0), patch_pair(Lo.n_patches + 1, 0);
     int max_n = 0, max_N = 0, max_cov_in = -1;   // -1: no pair has a correlated input
     unsigned ns_mask = 0;
     for (int k = 0; k < n_pairs; k++) {
@@ -241,6 +251,8 @@ extern "C" int psfm_batch_plan(const psfm_context* ctx, const psfm_pair* pairs, 
         for (int i = 0; i < d.n * nbands; i++) item_pair[d.band_off + i] = k;
         for (int i = 0; i < d.n; i++) stamp_pair[d.stamp_off + i] = k;
         for (int i = 0; i < d.ntx * d.nty; i++) tile_pair[d.tile_off + i] = k;
+        const PairSizes z = sizes_of(ctx, pairs[k]);
+        for (int i = 0; i < z.npatch; i++) patch_pair[d.patch_off + i] = k;
         max_n = std::max(max_n, d.n);
         max_N = std::max(max_N, d.N);
         max_cov_in = std::max(max_cov_in, d.cov1 ? d.cov1_half : -1);
@@ -257,6 +269,8 @@ extern "C" int psfm_batch_plan(const psfm_context* ctx, const psfm_pair* pairs, 
                                   hipMemcpyHostToDevice, st));
     PSFM_HIP_CHECK(hipMemcpyAsync(Lo.tile_pair, tile_pair.data(), sizeof(int) * tile_pair.size(),
                                   hipMemcpyHostToDevice, st));
+    PSFM_HIP_CHECK(hipMemcpyAsync(Lo.patch_pair, patch_pair.data(), sizeof(int) * patch_pair.size(),
+                                  hipMemcpyHostToDevice, st));
     PSFM_HIP_CHECK(hipStreamSynchronize(st));
     // grant dynamic LDS now, so that a later capture launches only kernels
     int rc = psfm::fit_prepare(ctx);
@@ -270,6 +284,7 @@ extern "C" int psfm_batch_plan(const psfm_context* ctx, const psfm_pair* pairs, 
     b->n_items = Lo.n_items;
     b->n_stamps = Lo.n_stamps;
     b->n_tiles = Lo.n_tiles;
+    b->n_patches = Lo.n_patches;
     b->max_n = max_n;
     b->max_N = max_N;
     b->max_cov_in = max_cov_in;
@@ -279,6 +294,7 @@ extern "C" int psfm_batch_plan(const psfm_context* ctx, const psfm_pair* pairs, 
     b->d_item_pair = Lo.item_pair;
     b->d_stamp_pair = Lo.stamp_pair;
     b->d_tile_pair = Lo.tile_pair;
+    b->d_patch_pair = Lo.patch_pair;
     b->d_counters = Lo.counters;
     b->times = times;
     *out = b;
@@ -299,7 +315,8 @@ extern "C" int psfm_batch_run_stage(psfm_batch* b, int stage, void* stream) {
         return psfm::batch_solve(b->ctx, b->d_pairs, b->d_stamp_pair, b->n_pairs, b->n_stamps,
                                  b->max_n, b->max_N, b->ns_mask, st);
     return psfm::batch_apply(b->ctx, b->d_pairs, b->d_tile_pair, b->n_pairs, b->n_tiles,
-                             b->max_cov_in, b->tuning.apply_grid, stage == 2 ? 1 : 2, st);
+                             b->d_patch_pair, b->n_patches, b->max_cov_in, b->tuning.apply_grid,
+                             stage == 2 ? 1 : 2, st);
 }
 
 extern "C" int psfm_batch_run(psfm_batch* b, void* stream) {

@@ -35,6 +35,13 @@ __host__ __device__ inline PatchGeom patch_geom(int W, int H, int P) {
     return g;
 }
 
+// Orders a wave's LDS writes before its other lanes' reads.
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Basis tables as kernel arguments.
 struct BasisArgs {
     const double* fac64;   // [nf][KW]
@@ -119,8 +126,11 @@ __device__ void realise_kernel(const BasisArgs& B, const double* __restrict__ a,
 __device__ void kernel_stats(const double* Kd, int h, double bad_frac, const double* __restrict__ cov_in,
                              int c_in, double* ring, double* red, int* rb_out, double* f_out) {
     const int KW = 2 * h + 1, T = KW * KW, tid = threadIdx.x;
+    // the sums over the taps are formed by wave 0 alone (lane l: taps l,
+    // l + 64, ...), so that they do not depend on the workgroup size
     double s2 = 0.0;
-    for (int t = tid; t < T; t += blockDim.x) s2 += Kd[t] * Kd[t];
+    if (tid < 64)
+        for (int t = tid; t < T; t += 64) s2 += Kd[t] * Kd[t];
     const double sumk2 = psfm_block_sum(s2, red);
     if (tid <= h) {   // squared weight on the ring max(|u|,|v|) = tid
         const int rr = tid;
@@ -138,7 +148,7 @@ __device__ void kernel_stats(const double* Kd, int h, double bad_frac, const dou
     if (cov_in) {
         const int Cw = 2 * c_in + 1;
         double r0 = 0.0;
-        for (int t = tid; t < T; t += blockDim.x) {
+        for (int t = tid; tid < 64 && t < T; t += 64) {
             const int v = t / KW - h, u = t % KW - h;
             double q = 0.0;
             for (int wy = -c_in; wy <= c_in; wy++)
@@ -773,7 +783,10 @@ __global__ __launch_bounds__(1024) void k_cov_finish_diff(const double* __restri
 // V' = f K^2 (x) V1, then V_D = V2 + V' (I' and V' are stored only where the
 // pair asks for them).  The tile's variance sums (sum V2, n2, sum V', n') go
 // to p.sub_part[4 t].  All threads of the workgroup call it.
-template <int H_>
+// PRE: the patch taps come from p.ptaps (realised for the whole batch by
+// k_realise_b), so the tile kernel carries no realisation code (and its
+// registers); otherwise the tile realises its patch kernel itself.
+template <int H_, bool PRE>
 __device__ __forceinline__ void match_tile(const PairDesc& p, const int t, const BasisArgs& B0, int P,
                                            double bad_frac, float* halo, float* tapsK, float* tapsV,
                                            uint32_t (*badw)[(TILE + 2 * H_ + 31) / 32 + 1],
@@ -792,11 +805,23 @@ __device__ __forceinline__ void match_tile(const PairDesc& p, const int t, const
     const int Y1 = min(min(Y0 + TILE, (py + 1) * P), H);
     double s2 = 0.0, n2 = 0.0, sc = 0.0, nc = 0.0;
     if (X0 < X1 && Y0 < Y1) {
-        BasisArgs B = B0;
-        B.ns = p.ns;
-        B.S = p.S;
-        patch_taps<H_>(B, p.coeffs, W, H, P, px, py, bad_frac, p.cov1, p.cov1_half, halo, tapsK,
-                       tapsV, ring, red, s_rb, s_f);
+        if constexpr (PRE) {
+            // realised by k_realise_b for the whole batch
+            constexpr int T = (2 * H_ + 1) * (2 * H_ + 1);
+            const float* src = p.ptaps + (size_t)(py * g.npx + px) * psfm::patch_taps_floats(H_);
+            for (int e = tid; e < T; e += 256) {
+                tapsK[e] = src[e];
+                tapsV[e] = src[T + e];
+            }
+            if (tid == 0) *s_rb = __float_as_int(src[2 * T]);
+            __syncthreads();
+        } else {
+            BasisArgs B = B0;
+            B.ns = p.ns;
+            B.S = p.S;
+            patch_taps<H_>(B, p.coeffs, W, H, P, px, py, bad_frac, p.cov1, p.cov1_half, halo, tapsK,
+                           tapsV, ring, red, s_rb, s_f);
+        }
         const int anybad = load_halo<H_, true>(p.I1, p.M1, W, H, pitch, X0, Y0, halo, badw);
         float acc[16];
         conv16<H_>(halo, tapsK, lx, r0, acc);
@@ -880,6 +905,140 @@ __device__ __forceinline__ void match_tile(const PairDesc& p, const int t, const
     }
 }
 
+// Patch kernels of every pair of a batch, one wave per patch (four per
+// workgroup, which share the basis factors in LDS): the arithmetic of
+// realise_kernel and kernel_stats for one workgroup (the same operations in
+// the same order, their tap sums being wave-0 sums there), then the FP32
+// taps K and f K^2 and the BAD radius to p.ptaps for the tile pass.
+constexpr int RB_WAVES = 4;
+
+template <int H_>
+__global__ __launch_bounds__(256) void k_realise_b(const PairDesc* __restrict__ pairs,
+                                                   const int* __restrict__ patch_pair, int n_patches,
+                                                   BasisArgs B0, int P, double bad_frac) {
+    constexpr int KW = 2 * H_ + 1;
+    constexpr int T = KW * KW;
+    __shared__ double F[32 * KW];
+    __shared__ int rf[64], cf[64];
+    __shared__ double gam[RB_WAVES][64];
+    __shared__ double Kd[RB_WAVES][T];
+    __shared__ double ring[RB_WAVES][H_ + 1];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nb = B0.nb;
+    for (int e = tid; e < B0.nf * KW; e += 256) F[e] = B0.fac64[e];
+    if (tid < nb) {
+        rf[tid] = B0.rowf[tid];
+        cf[tid] = B0.colf[tid];
+    }
+    __syncthreads();
+    const int q = blockIdx.x * RB_WAVES + w;
+    if (q >= n_patches) return;                 // the whole wave; no barrier follows
+    const PairDesc& p = pairs[patch_pair[q]];
+    const int ql = q - p.patch_off;
+    const int W = p.W, H = p.H, ns = p.ns;
+    const PatchGeom g = patch_geom(W, H, P);
+    const int px = ql % g.npx, py = ql / g.npx;
+    const int x0 = px * P, x1 = min(x0 + P, W), y0 = py * P, y1 = min(y0 + P, H);
+    const double x = 0.5 * (x0 + x1 - 1), y = 0.5 * (y0 + y1 - 1);
+    {
+        const int i = lane < nb ? lane : 0;
+        double cv[28];
+#pragma unroll
+        for (int k = 0; k < 28; k++) cv[k] = p.coeffs[i * ns + (k < ns ? k : 0)];
+        const double zi = (double)B0.z[i], ps = B0.psi64[i];
+        const double xt = W > 1 ? (2.0 * x - (W - 1)) / (double)(W - 1) : 0.0;
+        const double yt = H > 1 ? (2.0 * y - (H - 1)) / (double)(H - 1) : 0.0;
+        double al = 0.0;
+#pragma unroll
+        for (int d = 0; d <= 6; d++) {
+            if (d <= p.S) {
+#pragma unroll
+                for (int l = d; l >= 0; l--) {
+                    double v = 1.0;
+#pragma unroll
+                    for (int k = 0; k < l; k++) v *= xt;
+#pragma unroll
+                    for (int k = 0; k < d - l; k++) v *= yt;
+                    al += cv[d * (d + 1) / 2 + (d - l)] * v;
+                }
+            }
+        }
+        double c0 = lane >= 1 && lane < nb ? zi * al : 0.0;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) c0 += __shfl_xor(c0, o);
+        if (lane < nb) gam[w][lane] = (lane == 0 ? al - c0 : al) * ps;
+    }
+    wave_sync_lds();
+    double* K = Kd[w];
+    for (int t = lane; t < T; t += 64) {
+        const int v = t / KW, u = t - v * KW;
+        double k4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (int j = 0; j < nb; j++) k4[j & 3] += gam[w][j] * F[rf[j] * KW + u] * F[cf[j] * KW + v];
+        K[t] = (k4[0] + k4[1]) + (k4[2] + k4[3]);
+    }
+    wave_sync_lds();
+    // kernel_stats' sums: lane partials over taps lane + 64 j, then the
+    // workgroup sum's shuffle-down tree (its lane-0 value)
+    double s2 = 0.0;
+    for (int t = lane; t < T; t += 64) s2 += K[t] * K[t];
+    for (int o = 32; o > 0; o >>= 1) s2 += __shfl_down(s2, o);
+    const double sumk2 = __shfl(s2, 0);
+    if (lane <= H_) {
+        const int rr = lane;
+        double sr = 0.0;
+        for (int v = -rr; v <= rr; v++) {
+            const int step = (v == -rr || v == rr || rr == 0) ? 1 : 2 * rr;
+            for (int u = -rr; u <= rr; u += step) {
+                const double k = K[(v + H_) * KW + (u + H_)];
+                sr += k * k;
+            }
+        }
+        ring[w][rr] = sr;
+    }
+    double f = 1.0;
+    if (p.cov1) {
+        const int c_in = p.cov1_half, Cw = 2 * c_in + 1;
+        const double* cov_in = p.cov1;
+        double r0 = 0.0;
+        for (int t = lane; t < T; t += 64) {
+            const int v = t / KW - H_, u = t % KW - H_;
+            double qq = 0.0;
+            for (int wy = -c_in; wy <= c_in; wy++)
+                for (int wx = -c_in; wx <= c_in; wx++) {
+                    const int u2 = u - wx, v2 = v - wy;
+                    if (u2 < -H_ || u2 > H_ || v2 < -H_ || v2 > H_) continue;
+                    qq += cov_in[(wy + c_in) * Cw + (wx + c_in)] * K[(v2 + H_) * KW + (u2 + H_)];
+                }
+            r0 += K[t] * qq;
+        }
+        for (int o = 32; o > 0; o >>= 1) r0 += __shfl_down(r0, o);
+        const double raw0 = __shfl(r0, 0);
+        f = sumk2 > 0.0 ? raw0 / sumk2 : 0.0;
+    }
+    wave_sync_lds();
+    int rb = H_;
+    {
+        double outside = 0.0;
+        for (int rr = 0; rr <= H_; rr++) outside += ring[w][rr];
+        const double tot = outside;
+        for (int rr = 0; rr <= H_; rr++) {
+            outside -= ring[w][rr];
+            if (outside < bad_frac * tot) {
+                rb = rr;
+                break;
+            }
+        }
+    }
+    float* dst = p.ptaps + (size_t)ql * psfm::patch_taps_floats(H_);
+    for (int t = lane; t < T; t += 64) {
+        const int uu = t / KW, vv = t - uu * KW;     // column-major
+        const double k = K[vv * KW + uu];
+        dst[t] = (float)k;
+        dst[T + t] = (float)(f * k * k);
+    }
+    if (lane == 0) dst[2 * T] = __int_as_float(rb);
+}
+
 // Fused apply for every pair of a batch: the tiles of all pairs (flattened,
 // pair after pair, visited by a grid-stride loop) go through match_tile; the
 // workgroup that finishes a pair's last tile forms that pair's C_D and
@@ -905,10 +1064,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     __shared__ double s_f;
     __shared__ int s_last;
     const int tid = threadIdx.x;
-    for (int item = blockIdx.x; item < n_tiles; item += gridDim.x) {
+    for (int it = blockIdx.x; it < n_tiles; it += gridDim.x) {
+        // one workgroup per tile: workgroups go to the 8 XCDs in turn, so
+        // XCD x takes the x-th contiguous eighth of the tile list, where
+        // neighbouring tiles share their halo rows in that XCD's L2
+        int item = it;
+        if ((int)gridDim.x == n_tiles) {
+            const int x = it & 7, k = it >> 3, q = n_tiles >> 3, r = n_tiles & 7;
+            item = x * q + (x < r ? x : r) + k;
+        }
         const PairDesc& p = pairs[tile_pair[item]];
         const int t = item - p.tile_off;
-        match_tile<H_>(p, t, B0, P, bad_frac, halo, tapsK, tapsV, badw, ring, red, &s_rb, &s_f);
+        match_tile<H_, true>(p, t, B0, P, bad_frac, halo, tapsK, tapsV, badw, ring, red, &s_rb, &s_f);
         if (tid == 0) {
             __threadfence();
             const unsigned prev = atomicAdd(p.tiles_done, 1u);
@@ -945,7 +1112,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     __shared__ double red[16];
     __shared__ int s_rb;
     __shared__ double s_f;
-    match_tile<H_>(p, blockIdx.x, B0, P, bad_frac, halo, tapsK, tapsV, badw, ring, red, &s_rb, &s_f);
+    match_tile<H_, false>(p, blockIdx.x, B0, P, bad_frac, halo, tapsK, tapsV, badw, ring, red, &s_rb, &s_f);
 }
 
 constexpr int SUB_BLOCKS = 1024;
@@ -1003,9 +1170,30 @@ int launch_match_tiles(const psfm_context* ctx, const PairDesc* pairs, const int
     return PSFM_OK;
 }
 
+template <int H_>
+void launch_realise_b(const psfm_context* ctx, const PairDesc* pairs, const int* patch_pair,
+                      int n_patches, hipStream_t st) {
+    hipLaunchKernelGGL(k_realise_b<H_>, dim3((n_patches + RB_WAVES - 1) / RB_WAVES), dim3(256), 0, st,
+                       pairs, patch_pair, n_patches, basis_args_of(ctx), ctx->cfg.patch, ctx->cfg.bad_frac);
+}
+
 int batch_apply(const psfm_context* ctx, const PairDesc* pairs, const int* tile_pair, int n_pairs,
-                int n_tiles, int max_cov_in, int conv_grid, int parts, hipStream_t st) {
+                int n_tiles, const int* patch_pair, int n_patches, int max_cov_in, int conv_grid,
+                int parts, hipStream_t st) {
     if (n_pairs == 0) return PSFM_OK;
+    if ((parts & 1) && patch_pair && n_patches > 0) {
+        switch (ctx->h) {
+#define PSFM_RB_CASE(HH) \
+    case HH: launch_realise_b<HH>(ctx, pairs, patch_pair, n_patches, st); break;
+            PSFM_RB_CASE(1) PSFM_RB_CASE(2) PSFM_RB_CASE(3) PSFM_RB_CASE(4) PSFM_RB_CASE(5)
+            PSFM_RB_CASE(6) PSFM_RB_CASE(7) PSFM_RB_CASE(8) PSFM_RB_CASE(9) PSFM_RB_CASE(10)
+            PSFM_RB_CASE(11) PSFM_RB_CASE(12) PSFM_RB_CASE(13) PSFM_RB_CASE(14) PSFM_RB_CASE(15)
+            PSFM_RB_CASE(16)
+#undef PSFM_RB_CASE
+            default: return PSFM_ERR_UNSUPPORTED;
+        }
+        PSFM_HIP_CHECK(hipGetLastError());
+    }
     if (parts & 1) {
         const int E = 4 * ctx->h + 1;
         hipLaunchKernelGGL(k_cov_auto_b, dim3(PSFM_COV_SAMPLES, E, n_pairs), dim3(256), 0, st,

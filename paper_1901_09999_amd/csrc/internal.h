@@ -114,12 +114,15 @@ struct PairDesc {
     double* cov_auto;                // kernel autocorrelation (correlated input only)
     double* cov_avg;
     double* sub_part;                // [tiles][4] variance sums of the tiles
+    float* ptaps;                    // batch: per patch, FP32 taps K, f K^2 and the BAD radius
+                                     // (psfm::patch_taps_floats each); null: realised per tile
     unsigned int* tiles_done;        // tiles finished (batch completion counter)
     uint64_t* t_done;                // completion time stamp (nullable)
     // offsets in the flattened work lists of a batch
     int band_off;
     int stamp_off;
     int tile_off;
+    int patch_off;         // first patch of the pair in the batch's patch list
     int ntx, nty;
 };
 
@@ -173,7 +176,10 @@ int batch_solve(const psfm_context* ctx, const PairDesc* pairs, const int* stamp
                 int n_stamps_total, int max_n, int max_N, unsigned ns_mask, hipStream_t st);
 // parts: 1 = the pseudo-matrices, 2 = the fused convolution / difference pass, 3 = both.
 int batch_apply(const psfm_context* ctx, const PairDesc* pairs, const int* tile_pair, int n_pairs,
-                int n_tiles, int max_cov_in, int conv_grid, int parts, hipStream_t st);
+                int n_tiles, const int* patch_pair, int n_patches, int max_cov_in, int conv_grid,
+                int parts, hipStream_t st);
+// floats per patch in PairDesc::ptaps: K and f K^2 (column-major), the BAD radius
+__host__ __device__ inline int patch_taps_floats(int h) { return 2 * (2 * h + 1) * (2 * h + 1) + 4; }
 int fit_prepare(const psfm_context* ctx);
 size_t fit_lds_bytes(const psfm_context* ctx);
 int solve_lds_grant(size_t lds);

@@ -701,8 +701,8 @@ class Batch:
         torch.cuda.current_stream().wait_stream(self.stream)
 
     def run_stage(self, stage: int):
-        """One stage (0 fit, 1 solve, 2 pseudo-matrices, 3 fused convolution /
-        difference pass) on the current stream."""
+        """One stage (0 fit, 1 solve, 2 patch kernels and pseudo-matrices,
+        3 fused convolution / difference pass) on the current stream."""
         _check(lib().psfm_batch_run_stage(self._h, stage, _stream()), "psfm_batch_run_stage")
 
     def capture(self):
