@@ -10,8 +10,10 @@ kernel with the 49-term ISIS basis) through psfm_batch_* as one captured HIP
 graph: stamp fits -> solves with rejection -> pseudo-matrices -> fused
 image + variance convolution and difference over every output tile.  Also
 reports the p50 / p99 completion latency of the pairs, the stage split, the
-tuner's table, the learned prior's leg on the same pairs and the plain vs
-16-bit comparison on the detector-chip pair.
+tuner's table, the learned prior's leg on the same pairs, the plain vs
+16-bit comparison on the detector-chip pair and the paper's other modes
+(two kernels with the penalty, normalisation and quality, homogenisation
+for stacking, binning and addition) on 2048^2 images.
 
 --workload pair2048 / chip4846: one pair,
     psfm_fit_stamps -> psfm_solve (with rejection) -> psfm_match_pair.
@@ -298,6 +300,10 @@ def bench_batch(args, torch, psfm, synth):
             out["compare_precision"] = precision_leg(args, torch, psfm, synth)
         except Exception as e:
             out["compare_precision"] = {"error": repr(e)}
+        try:
+            out["modes"] = modes_leg(args, torch, psfm, synth)
+        except Exception as e:
+            out["modes"] = {"error": repr(e)}
     if not args.no_cpu_baseline:
         base, par = oracle_batch_baseline(wls, dps, px, st, args.cpu_seconds)
         out["cpu_baseline"] = base
@@ -393,6 +399,145 @@ def learned_batch_leg(args, torch, psfm, synth, ctx_b, pairs, wls, st_plain):
         chi2_dof_change_max=float(np.max(dchi)) if dchi else None,
         pairs_with_lower_chi2_dof=int(sum(x < 0 for x in dchi)),
         kernel_sum_change_max=float(np.max(dks)) if dks else None)
+
+
+def modes_leg(args, torch, psfm, synth, W=2048, H=2048, reps=3):
+    """The paper's other modes, each on 2048^2 synthetic images resident in
+    HBM, timed with HIP events over `reps` calls after one warm-up:
+    both images matched to a common PSF (psfm_fit_dual -> psfm_solve_dual ->
+    psfm_dual_subtract, penalty 0.02) beside the single kernel on the same
+    orthogonally elongated pair; the normalisation and quality mode (fit,
+    unweighted b0/d0 sums, held solve, quality record, match); PSF
+    homogenisation of three inputs (envelope, fake target, three matchings,
+    outlier rejection, trace-back, stack); binning and image addition
+    (HBM-bound: achieved GB/s of their algorithmic bytes)."""
+    dev = "cuda"
+    rng = np.random.default_rng(5)
+    n_src = 3000
+    xs = rng.uniform(0, W, n_src)
+    ys = rng.uniform(0, H, n_src)
+    fl = np.exp(rng.uniform(np.log(1e3), np.log(1e5), n_src))
+
+    def image(psf, theta, seed):
+        m = synth._render_torch(torch, W, H, xs, ys, fl, psf, theta, dev).reshape(H, W).double() + 100.0
+        g = torch.Generator(device=dev)
+        g.manual_seed(seed)
+        var = m.abs() + 1.0
+        img = m + var.sqrt() * torch.randn((H, W), generator=g, device=dev, dtype=torch.float64)
+        return img.float().contiguous(), var.float().contiguous()
+
+    Z = torch.zeros((H, W), dtype=torch.uint8, device=dev)
+    R = 30
+    st = [(int(xs[i]), int(ys[i])) for i in np.argsort(-fl)
+          if R <= xs[i] < W - R and R <= ys[i] < H - R][:200]
+    stamps = torch.tensor(st, dtype=torch.int32, device=dev)
+
+    def timed(fn):
+        out = fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            out = fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps, out
+
+    res = {}
+    # (1) two kernels vs one on orthogonally elongated PSFs
+    I1, V1 = image(synth.PsfField(1.8, 1.8, 0.45), 0.0, 1)
+    I2, V2 = image(synth.PsfField(1.8, 1.8, 0.45), np.pi / 2, 2)
+    ctx = psfm.Context(psfm.Config(S=1))
+
+    def dual():
+        f = ctx.fit_dual(I1, Z, I2, V2, Z, stamps)
+        s = ctx.solve_dual(W, H, stamps, f, 0.02)
+        ctx.dual_subtract(s["coeffs"], I1, V1, Z, I2, V2, Z)
+        return s
+
+    def single():
+        f = ctx.fit_stamps(I1, Z, I2, V2, Z, stamps)
+        s = ctx.solve(W, H, stamps, f)
+        ctx.match(s["coeffs"], I1, V1, Z, I2, V2, Z, stats=s["stats"])
+        return s
+
+    ms_d, sd = timed(dual)
+    ms_s, ss = timed(single)
+    a, b = psfm.read_stats(sd["stats"]), psfm.read_stats(ss["stats"])
+    res["two_kernels"] = dict(mpix_s=round(W * H / 1e3 / ms_d, 1), ms=round(ms_d, 3),
+                              unknowns=ctx.N2, chi2_dof=a["chi2_dof"],
+                              single_kernel=dict(mpix_s=round(W * H / 1e3 / ms_s, 1), ms=round(ms_s, 3),
+                                                 unknowns=ctx.N, chi2_dof=b["chi2_dof"]))
+    # (2) the paper's normalisation and quality mode on a plain pair
+    J1, U1 = image(synth.PsfField(1.4, 1.4, 0.0), 0.0, 3)
+    J2, U2 = image(synth.PsfField(2.0, 2.2, 0.2), 0.3, 4)
+
+    def paper_mode():
+        f = ctx.fit_stamps(J1, Z, J2, U2, Z, stamps)
+        nrm = ctx.fit_norm(J1, J2, stamps, f["flags"])
+        s = ctx.solve_norm(W, H, stamps, f, nrm)
+        q = ctx.quality(s["coeffs"], J1, J2, U2, stamps, s["flags"], soft=0.1)[0]
+        ctx.match(s["coeffs"], J1, U1, Z, J2, U2, Z, stats=s["stats"])
+        return s, q
+
+    ms_p, (sp, qp) = timed(paper_mode)
+    qd = psfm.read_quality(qp)
+    res["normalisation_quality_mode"] = dict(mpix_s=round(W * H / 1e3 / ms_p, 1), ms=round(ms_p, 3),
+                                             chi2_dof=psfm.read_stats(sp["stats"])["chi2_dof"],
+                                             cut_flags=int(qd.get("cut_flags", -1)))
+    # (3) homogenisation of three inputs to their envelope, outliers, stack
+    psfs = [(synth.PsfField(1.5, 1.5, 0.2), 0.2), (synth.PsfField(1.8, 1.8, 0.1), 1.1),
+            (synth.PsfField(1.3, 1.3, 0.3), 2.0)]
+    ins = [image(p_, th, 10 + k) for k, (p_, th) in enumerate(psfs)]
+    params = []
+    for p_, th in psfs:
+        sa, sb = p_.params(np.array([W / 2.0]), np.array([H - 1.0]), W, H)
+        params.append((float(sa[0]), float(sb[0]), th))
+    params_d = torch.tensor(params, dtype=torch.float64, device=dev)
+    src_d = torch.tensor(np.stack([xs, ys, fl], axis=1), dtype=torch.float64, device=dev)
+    hctx = psfm.Context(psfm.Config(S=1, max_iter=2))
+
+    def homogenise():
+        sig, _ = psfm.envelope_psf(params_d, 15)
+        target = psfm.render_target(src_d, float(sig[0]), W, H)
+        conv, var, co = [], [], []
+        for img, v in ins:
+            f = hctx.fit_stamps(img, Z, target, v, Z, stamps)
+            s = hctx.solve(W, H, stamps, f)
+            conv.append(hctx.convolve_image(s["coeffs"], img, Z)[0])
+            var.append(hctx.propagate_variance(s["coeffs"], v, Z)[0])
+            co.append(s["coeffs"])
+        Ic, Vc = torch.stack(conv), torch.stack(var)
+        Mc = torch.zeros((3, H, W), dtype=torch.uint8, device=dev)
+        outl = psfm.stack_reject(Ic, Vc, Mc, 5.0)
+        for k in range(3):
+            psfm.trace_mask(hctx, co[k], outl[k], 0.8)
+        return psfm.stack_combine(Ic, Vc, Mc)
+
+    ms_h, _ = timed(homogenise)
+    res["homogenisation"] = dict(inputs=3, mpix_s=round(3 * W * H / 1e3 / ms_h, 1), ms=round(ms_h, 3))
+    # (4) binning and addition (HBM-bound)
+    B4 = 4096
+    gb = torch.Generator(device=dev)
+    gb.manual_seed(7)
+    Ib = torch.randn((B4, B4), generator=gb, device=dev).float()
+    Vb = torch.rand((B4, B4), generator=gb, device=dev).float() + 1.0
+    Mb = torch.zeros((B4, B4), dtype=torch.uint8, device=dev)
+    ms_b, _ = timed(lambda: psfm.bin_image(Ib, Vb, Mb, 2, c_out=4))
+    ms_a, _ = timed(lambda: psfm.add_images(0.7, Ib, Vb, Mb, None, 1.3, Ib, Vb, Mb, None, 3))
+    px = B4 * B4
+    bin_bytes = 9 * px + 9 * px / 4              # I, V, M read; binned planes written
+    add_bytes = 18 * px + 9 * px                 # two inputs read, S, V_S, M_S written
+    res["noise_ops"] = dict(
+        image=f"{B4}x{B4}",
+        bin2=dict(ms=round(ms_b, 4), gb_s=round(bin_bytes / ms_b / 1e6, 1),
+                  hbm_frac=round(bin_bytes / ms_b / 1e6 / HBM_PEAK_GBS, 3)),
+        add=dict(ms=round(ms_a, 4), gb_s=round(add_bytes / ms_a / 1e6, 1),
+                 hbm_frac=round(add_bytes / ms_a / 1e6 / HBM_PEAK_GBS, 3)))
+    ctx.close()
+    hctx.close()
+    torch.cuda.empty_cache()
+    return res
 
 
 def precision_leg(args, torch, psfm, synth, name="chip4846", steps=5, warmup=2):
