@@ -59,6 +59,9 @@ constexpr int A16S = 104;        // LDS column stride (halves) of the 16-bit blo
 // Band mode that only writes the FP32 weighted block to the stamp design (no
 // Gram): the two-kernel form's passes over I1 and over I2.
 constexpr int PREC_DESIGN = 16;
+// Gram entries per lane in rows 48 .. nb+1 (on the VALU): at most 904 for
+// nb + 2 = 64 columns, over 4 x 256 lane slots
+constexpr int GX_MAX = 4;
 
 struct FitLds {
     int win, col, R, At, sw, dt, psi, z, fac, rf, cf, total;  // float offsets
@@ -270,6 +273,36 @@ __device__ void fit_band_body(const FitArgs& a, const int item, float* __restric
         acc[q] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
         accd[q] = doublex4{0.0, 0.0, 0.0, 0.0};
     }
+    // FP32 mode: the Gram rows 48 .. nb+1 on the VALU of waves 2 and 3 --
+    // entry e = (tid - 128) + 128 j of the row-major lower triangle of those
+    // rows, (er[j], ec[j]), summed in ex[j]
+    int er[GX_MAX], ec[GX_MAX], nxl = 0;
+    double ex[GX_MAX];
+    {
+        // entry e = ((tid + 128) % 256) + 256 j of the row-major lower
+        // triangle of rows 48 .. nb+1: waves 2 and 3 (one MFMA block each)
+        // take the first 128, waves 0 and 1 any beyond
+        const int R1 = nb + 1;
+        const int E = R1 >= 48 ? (R1 + 1) * (R1 + 2) / 2 - 48 * 49 / 2 : 0;
+        const int l2 = (tid + 128) & 255;
+#pragma unroll
+        for (int j = 0; j < GX_MAX; j++) {
+            ex[j] = 0.0;
+            er[j] = 0;
+            ec[j] = 0;
+            const int e = l2 + 256 * j;
+            if (PREC == PSFM_PREC_FP32 && e < E) {
+                int r = 48, rem = e;
+                while (rem >= r + 1) {
+                    rem -= r + 1;
+                    r++;
+                }
+                er[j] = r;
+                ec[j] = rem;
+                nxl = j + 1;
+            }
+        }
+    }
     const int nseg = (NPX + SEG - 1) / SEG;
     // row-pass item of this thread (the usual case: nb * nseg <= 256), its
     // taps held in registers across the rows
@@ -327,32 +360,37 @@ __device__ void fit_band_body(const FitArgs& a, const int item, float* __restric
             }
         }
         __syncthreads();
-        // 3c. Gram blocks on MFMA.  Wave blocks (bm, bn): w0 (0,0)(1,0)(1,1);
-        // w1 (2,0)(2,1)(2,2); w2 (3,0)(3,1); w3 (3,2)(3,3).
-        //     The FP32 values enter v_mfma_f64_16x16x4f64 as FP64: every
-        //     product is exact and the sums run in FP64 over the whole band,
-        //     so the Gram is that of the FP32 block to FP64 rounding (and
-        //     positive semi-definite to it), whatever its condition.
+        // 3c. The Gram of the block.  The FP32 values enter
+        //     v_mfma_f64_16x16x4f64 as FP64: every product is exact and the
+        //     sums run in FP64 over the whole band, so the Gram is that of
+        //     the FP32 block to FP64 rounding (and positive semi-definite to
+        //     it), whatever its condition.  Rows 0..47 in six 16 x 16 blocks
+        //     (bm, bn): w0 (0,0)(1,1); w1 (1,0)(2,2); w2 (2,0); w3 (2,1);
+        //     rows 48 .. nb+1 (the last terms, sqrt(w), d~: three rows of the
+        //     49-term basis, not worth a block row of MFMA) on the FP64 VALU,
+        //     entries (er[j], ec[j]) of each lane.
         for (int ks = 0; ks < npad / 4; ks++) {
             const float* rowp = At + (4 * ks + (lane >> 4)) * AT_STRIDE + (lane & 15);
             if (wave == 0) {
                 const double a0 = rowp[0], a1 = rowp[16];
                 accd[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a0, accd[0], 0, 0, 0);
-                accd[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a0, accd[1], 0, 0, 0);
-                accd[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a1, accd[2], 0, 0, 0);
+                accd[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a1, accd[1], 0, 0, 0);
             } else if (wave == 1) {
                 const double a0 = rowp[0], a1 = rowp[16], a2 = rowp[32];
-                accd[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, a0, accd[0], 0, 0, 0);
-                accd[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, a1, accd[1], 0, 0, 0);
-                accd[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, a2, accd[2], 0, 0, 0);
-            } else if (wave == 2) {
-                const double a0 = rowp[0], a1 = rowp[16], a3 = rowp[48];
-                accd[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a3, a0, accd[0], 0, 0, 0);
-                accd[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a3, a1, accd[1], 0, 0, 0);
+                accd[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a0, accd[0], 0, 0, 0);
+                accd[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, a2, accd[1], 0, 0, 0);
             } else {
-                const double a2 = rowp[32], a3 = rowp[48];
-                accd[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a3, a2, accd[0], 0, 0, 0);
-                accd[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a3, a3, accd[1], 0, 0, 0);
+                const double a2 = rowp[32], ab = rowp[wave == 2 ? 0 : 16];
+                accd[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, ab, accd[0], 0, 0, 0);
+            }
+            const float* xr = At + 4 * ks * AT_STRIDE;
+#pragma unroll
+            for (int j = 0; j < GX_MAX; j++) {
+                if (j < nxl) {
+#pragma unroll
+                    for (int q = 0; q < 4; q++)
+                        ex[j] = fma((double)xr[q * AT_STRIDE + er[j]], (double)xr[q * AT_STRIDE + ec[j]], ex[j]);
+                }
             }
         }
         } else {
@@ -460,11 +498,22 @@ __device__ void fit_band_body(const FitArgs& a, const int item, float* __restric
         return;
     }
     double* G = part + (size_t)item * GC * GC;
-    const int bms[4][3] = {{0, 1, 1}, {2, 2, 2}, {3, 3, -1}, {3, 3, -1}};
-    const int bns[4][3] = {{0, 0, 1}, {0, 1, 2}, {0, 1, -1}, {2, 3, -1}};
+    // blocks (bm, bn) of each wave: the FP32 mode's six below row 48, the
+    // 16-bit modes' ten
+    const int bms32[4][3] = {{0, 1, -1}, {1, 2, -1}, {2, -1, -1}, {2, -1, -1}};
+    const int bns32[4][3] = {{0, 1, -1}, {0, 2, -1}, {0, -1, -1}, {1, -1, -1}};
+    const int bms16[4][3] = {{0, 1, 1}, {2, 2, 2}, {3, 3, -1}, {3, 3, -1}};
+    const int bns16[4][3] = {{0, 0, 1}, {0, 1, 2}, {0, 1, -1}, {2, 3, -1}};
+    const bool six = PREC == PSFM_PREC_FP32;
+    if constexpr (PREC == PSFM_PREC_FP32) {
+#pragma unroll
+        for (int j = 0; j < GX_MAX; j++)
+            if (j < nxl) G[er[j] * GC + ec[j]] = ex[j];
+    }
 #pragma unroll
     for (int q = 0; q < 3; q++) {
-        const int bm = bms[wave][q], bn = bns[wave][q];
+        const int bm = six ? bms32[wave][q] : bms16[wave][q];
+        const int bn = six ? bns32[wave][q] : bns16[wave][q];
         if (bm < 0) continue;
         const int col = 16 * bn + (lane & 15);
 #pragma unroll

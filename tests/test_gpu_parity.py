@@ -63,6 +63,32 @@ def test_fit_stamps_parity(name):
     assert np.max(np.abs(_np(fit["b"]) - ref["b"]) / den) < 2e-5
 
 
+@pytest.mark.parametrize("degrees", [(6, 4, 2), (6, 6, 2), (4, 2, 2), (9, 2)])
+def test_fit_stamps_basis_sizes(degrees):
+    """Every part of the fit's Gram: bases of 49, 62 (the largest: 64 Gram
+    columns), 27 and 61 terms (the rows beyond 47 are summed outside the
+    MFMA blocks, by one to four lane slots each)."""
+    torch, psfm = hip()
+    wl, pair = pair_for("pair512", SEEDS["pair512"], 384, 320, n_stamps=30)
+    sig = (0.7, 1.5, 3.0)[:len(degrees)]
+    cfg = O.Config.from_workload(wl, sigmas=sig, degrees=degrees)
+    ctx = _ctx(wl, sigmas=sig, degrees=degrees)
+    assert ctx.nb == cfg.n_basis
+    d = psfm.to_device(pair)
+    fit = ctx.fit_stamps(d["I1"], d["M1"], d["I2"], d["V2"], d["M2"], d["stamps"])
+    ref = O.fit_stamps(cfg, pair.I1, pair.M1, pair.I2, pair.V2, pair.M2, pair.stamps)
+    assert np.array_equal(_np(fit["flags"]), ref["flags"])
+    err = norm_err_M(_np(fit["M"]), ref["M"])
+    print(f"degrees {degrees} ({ctx.nb} terms): Gram normalised error {err:.3e}")
+    assert err < 2e-5
+    Md = np.sqrt(np.einsum("sii->si", ref["M"]))
+    den = Md * np.sqrt(np.maximum(ref["e"], 1e-300))[:, None]
+    den[den == 0] = 1
+    assert np.max(np.abs(_np(fit["b"]) - ref["b"]) / den) < 2e-5
+    ok = ref["e"] > 0
+    assert np.max(np.abs(_np(fit["e"])[ok] - ref["e"][ok]) / ref["e"][ok]) < 1e-5
+
+
 @pytest.mark.parametrize("name", ["pair512", "pair2048"])
 def test_solve_parity_same_sums(name):
     torch, psfm = hip()
