@@ -823,25 +823,24 @@ __device__ __forceinline__ void match_tile(const PairDesc& p, const int t, const
                            tapsV, ring, red, s_rb, s_f);
         }
         const int anybad = load_halo<H_, true>(p.I1, p.M1, W, H, pitch, X0, Y0, halo, badw);
+        const int gx = X0 + lx;
+        // the target image's mask, values and variance of the 16 outputs,
+        // loaded together (clamped addresses outside the tile) and early: their
+        // latency passes under the image convolution
+        uint32_t m2bits = 0;
+        float i2v[16];
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+            const int gy = Y0 + r0 + j;
+            const int64_t o = (gx < X1 && gy < Y1) ? (int64_t)gy * pitch + gx : 0;
+            m2bits |= (p.M2[o] != 0 ? 1u : 0u) << j;
+            i2v[j] = p.I2[o];
+        }
         float acc[16];
         conv16<H_>(halo, tapsK, lx, r0, acc);
         uint32_t bad16 = 0, poor16 = 0;
         if (anybad) mask16<H_>(badw, *s_rb, lx, r0, &bad16, &poor16);
         const double d0 = p.coeffs[p.N - 1];
-        const int gx = X0 + lx;
-        // the target image's mask, values and variance of the 16 outputs,
-        // loaded together (clamped addresses outside the tile)
-        uint8_t m2v[16];
-        float i2v[16], v2v[16];
-#pragma unroll
-        for (int j = 0; j < 16; j++) {
-            const int gy = Y0 + r0 + j;
-            const int64_t o = (gx < X1 && gy < Y1) ? (int64_t)gy * pitch + gx : 0;
-            m2v[j] = p.M2[o];
-            i2v[j] = p.I2[o];
-            v2v[j] = p.V2[o];
-        }
-        uint32_t m2bits = 0;
         if (gx < X1) {
 #pragma unroll
             for (int j = 0; j < 16; j++) {
@@ -854,8 +853,7 @@ __device__ __forceinline__ void match_tile(const PairDesc& p, const int t, const
                         p.conv[o] = acc[j];
                         p.conv_mask[o] = cm;
                     }
-                    if (m2v[j]) {
-                        m2bits |= 1u << j;
+                    if ((m2bits >> j) & 1u) {
                         p.diff[o] = 0.0f;
                         p.diff_mask[o] = (uint8_t)(PSFM_MASK_BAD | cm);
                     } else {
@@ -867,6 +865,12 @@ __device__ __forceinline__ void match_tile(const PairDesc& p, const int t, const
         }
         __syncthreads();
         load_halo<H_, false>(p.V1, p.M1, W, H, pitch, X0, Y0, halo, badw);
+        float v2v[16];                 // the target's variance, under the variance convolution
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+            const int gy = Y0 + r0 + j;
+            v2v[j] = p.V2[(gx < X1 && gy < Y1) ? (int64_t)gy * pitch + gx : 0];
+        }
         conv16<H_>(halo, tapsV, lx, r0, acc);
         if (gx < X1) {
 #pragma unroll
@@ -892,16 +896,14 @@ __device__ __forceinline__ void match_tile(const PairDesc& p, const int t, const
             }
         }
     }
-    s2 = psfm_block_sum(s2, red);
-    n2 = psfm_block_sum(n2, red);
-    sc = psfm_block_sum(sc, red);
-    nc = psfm_block_sum(nc, red);
+    double sums[4] = {s2, n2, sc, nc};
+    psfm_block_sum4(sums, red);
     if (tid == 0) {
         double* q = p.sub_part + 4 * (size_t)t;
-        q[0] = s2;
-        q[1] = n2;
-        q[2] = sc;
-        q[3] = nc;
+        q[0] = sums[0];
+        q[1] = sums[1];
+        q[2] = sums[2];
+        q[3] = sums[3];
     }
 }
 

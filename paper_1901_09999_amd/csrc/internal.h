@@ -233,6 +233,28 @@ __device__ __forceinline__ double psfm_spatial_dot(int S, double x, double y, in
     return acc;
 }
 
+// Four psfm_block_sum's in one pass (the same sums, one set of barriers);
+// `red` holds >= 4 * (waves) doubles.  Results in v[0..3] of every thread.
+__device__ __forceinline__ void psfm_block_sum4(double v[4], double* red) {
+#pragma unroll
+    for (int k = 0; k < 4; k++)
+        for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_down(v[k], o);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < 4; k++) red[4 * wave + k] = v[k];
+    __syncthreads();
+    const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        double s = 0.0;
+        for (int w = 0; w < nw; w++) s += red[4 * w + k];
+        v[k] = s;
+    }
+    __syncthreads();
+}
+
 // Fixed-order sum over a workgroup of up to 1024 threads (deterministic).
 // Every thread of the block must call it; `red` holds >= 16 doubles in LDS.
 __device__ __forceinline__ double psfm_block_sum(double v, double* red) {
