@@ -805,16 +805,15 @@ __device__ __forceinline__ void match_tile(const PairDesc& p, const int t, const
     const int Y1 = min(min(Y0 + TILE, (py + 1) * P), H);
     double s2 = 0.0, n2 = 0.0, sc = 0.0, nc = 0.0;
     if (X0 < X1 && Y0 < Y1) {
+        // batch: the patch taps (realised by k_realise_b) are loaded into
+        // registers first, so that their latency passes under the halo loads
+        constexpr int T = (2 * H_ + 1) * (2 * H_ + 1);
+        constexpr int NT = (2 * T + 1 + 255) / 256;
+        float tk[NT];
         if constexpr (PRE) {
-            // realised by k_realise_b for the whole batch
-            constexpr int T = (2 * H_ + 1) * (2 * H_ + 1);
             const float* src = p.ptaps + (size_t)(py * g.npx + px) * psfm::patch_taps_floats(H_);
-            for (int e = tid; e < T; e += 256) {
-                tapsK[e] = src[e];
-                tapsV[e] = src[T + e];
-            }
-            if (tid == 0) *s_rb = __float_as_int(src[2 * T]);
-            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < NT; k++) tk[k] = src[min(tid + 256 * k, 2 * T)];
         } else {
             BasisArgs B = B0;
             B.ns = p.ns;
@@ -823,6 +822,16 @@ __device__ __forceinline__ void match_tile(const PairDesc& p, const int t, const
                            tapsV, ring, red, s_rb, s_f);
         }
         const int anybad = load_halo<H_, true>(p.I1, p.M1, W, H, pitch, X0, Y0, halo, badw);
+        if constexpr (PRE) {
+#pragma unroll
+            for (int k = 0; k < NT; k++) {
+                const int e = tid + 256 * k;
+                if (e < T) tapsK[e] = tk[k];
+                else if (e < 2 * T) tapsV[e - T] = tk[k];
+                else if (e == 2 * T) *s_rb = __float_as_int(tk[k]);
+            }
+            __syncthreads();
+        }
         const int gx = X0 + lx;
         // the target image's mask, values and variance of the 16 outputs,
         // loaded together (clamped addresses outside the tile) and early: their
