@@ -107,7 +107,7 @@ def lib():
             "orc_spatial": (None, [i, d, d, i, i, P]),
             "orc_local_coeffs": (None, [cfgp, P, d, d, i, i, P]),
             "orc_kernel_at": (None, [cfgp, P, P, d, d, i, i, P]),
-            "orc_fit_stamps": (None, [cfgp, P, P, P, P, P, P, i, i, i64, P, i, P, P, P, P, P]),
+            "orc_fit_stamps": (None, [cfgp, P, P, P, P, P, P, i, i, i64, P, i, P, P, P, P, P, P]),
             "orc_assemble": (None, [cfgp, i, i, P, i, P, P, P, P, P]),
             "orc_cholesky_solve": (i, [i, P, P, P]),
             "orc_stamp_chi2": (d, [cfgp, P, i, i, i, i, P, P, d]),
@@ -137,7 +137,7 @@ def lib():
             "orc_trace_mask": (None, [cfgp, P, P, P, i, i, i64, d, P]),
             "orc_stack_combine": (None, [i, P, P, P, i64, i, i, i64, P, i, P, P, P, P, P]),
             "orc_dual_unknowns": (i, [cfgp]),
-            "orc_fit_dual": (None, [cfgp, P, P, P, P, P, P, i, i, i64, P, i, P, P, P, P, P]),
+            "orc_fit_dual": (None, [cfgp, P, P, P, P, P, P, i, i, i64, P, i, P, P, P, P, P, P]),
             "orc_penalty_q": (None, [cfgp, P, P]),
             "orc_solve_dual": (i, [cfgp, P, i, i, P, i, P, P, P, P, P, d, P, P, C.POINTER(OrcStats)]),
             "orc_dual_kernels": (None, [cfgp, P, P, d, d, i, i, P, P]),
@@ -243,10 +243,12 @@ def kernel_at(cfg: Config, a: np.ndarray, x: float, y: float, W: int, H: int,
     return K
 
 
-def fit_stamps(cfg: Config, I1, M1, I2, V2, M2, stamps, kb=None):
-    """Per-stamp sums: returns dict(M [n,L,L], b [n,L], e [n], npix [n], flags [n])."""
+def fit_stamps(cfg: Config, I1, M1, I2, V2, M2, stamps, kb=None, V1=None):
+    """Per-stamp sums: returns dict(M [n,L,L], b [n,L], e [n], npix [n], flags [n]).
+    With V1 the weights are 1 / (V1 + V2), else 1 / V2."""
     kb = basis(cfg) if kb is None else kb
     I1, I2, V2 = (_c(a, np.float32) for a in (I1, I2, V2))
+    V1 = None if V1 is None else _c(V1, np.float32)
     M1, M2 = _c(M1, np.uint8), _c(M2, np.uint8)
     H, W = I1.shape
     xy = _c(stamps, np.int32).reshape(-1, 2)
@@ -255,7 +257,7 @@ def fit_stamps(cfg: Config, I1, M1, I2, V2, M2, stamps, kb=None):
     Ms = np.zeros((n, L, L)); bs = np.zeros((n, L)); es = np.zeros(n)
     npix = np.zeros(n, dtype=np.int32); flags = np.zeros(n, dtype=np.int32)
     lib().orc_fit_stamps(C.byref(cfg.c()), _p(kb), _p(I1), _p(M1), _p(I2), _p(V2), _p(M2), W, H,
-                         W, _p(xy), n, _p(Ms), _p(bs), _p(es), _p(npix), _p(flags))
+                         W, _p(xy), n, _p(Ms), _p(bs), _p(es), _p(npix), _p(flags), _p(V1))
     return dict(M=Ms, b=bs, e=es, npix=npix, flags=flags)
 
 
@@ -551,10 +553,12 @@ def dual_unknowns(cfg: Config) -> int:
     return (2 * cfg.n_basis - 1) * cfg.n_spatial + 1
 
 
-def fit_dual(cfg: Config, I1, M1, I2, V2, M2, stamps, kb=None):
-    """Per-stamp sums of the two-kernel form: dict(M [n,L2,L2], b [n,L2], e, npix, flags), L2 = 2 nb."""
+def fit_dual(cfg: Config, I1, M1, I2, V2, M2, stamps, kb=None, V1=None):
+    """Per-stamp sums of the two-kernel form: dict(M [n,L2,L2], b [n,L2], e, npix, flags), L2 = 2 nb.
+    With V1 the weights are 1 / (V1 + V2), else 1 / V2."""
     kb = basis(cfg) if kb is None else kb
     I1, I2, V2 = (_c(a, np.float32) for a in (I1, I2, V2))
+    V1 = None if V1 is None else _c(V1, np.float32)
     M1, M2 = _c(M1, np.uint8), _c(M2, np.uint8)
     H, W = I1.shape
     xy = _c(stamps, np.int32).reshape(-1, 2)
@@ -563,7 +567,7 @@ def fit_dual(cfg: Config, I1, M1, I2, V2, M2, stamps, kb=None):
     Ms = np.zeros((n, L, L)); bs = np.zeros((n, L)); es = np.zeros(n)
     npix = np.zeros(n, dtype=np.int32); flags = np.zeros(n, dtype=np.int32)
     lib().orc_fit_dual(C.byref(cfg.c()), _p(kb), _p(I1), _p(M1), _p(I2), _p(V2), _p(M2), W, H, W,
-                       _p(xy), n, _p(Ms), _p(bs), _p(es), _p(npix), _p(flags))
+                       _p(xy), n, _p(Ms), _p(bs), _p(es), _p(npix), _p(flags), _p(V1))
     return dict(M=Ms, b=bs, e=es, npix=npix, flags=flags)
 
 

@@ -181,18 +181,24 @@ void orc_kernel_at(const orc_config* c, const double* kb, const double* a, doubl
  *     A_i(x, y) = sum_{u,v} k_i(u, v) I1(x - u, y - v)     (i < nb)
  *     A_nb      = 1                                        (constant background)
  *     w = 1 / V2(x, y),  d = I2(x, y)
+ * (or w = 1 / (V1 + V2) when V1 is given: the variance of the convolved
+ * image counted as well, the sum taken in float as the images are stored)
  * and the stamp accumulates M_s = sum w A A^T (L x L, L = nb + 1),
  * b_s = sum w A d and e_s = sum w d^2.
  * Validity (Section 3.3): a stamp whose convolution footprint
  * [x-r-h, x+r+h]^2 leaves the image or holds a masked I1 pixel, or whose
  * stamp [x-r, x+r]^2 holds a masked I2 pixel, is flagged INVALID; a stamp
- * holding a non-finite I1/I2 value or a variance that is not finite and
- * positive is flagged NONFINITE.  Flagged stamps get zero sums.
+ * holding a non-finite I1/I2 value or a weight variance that is not finite
+ * and positive is flagged NONFINITE.  Flagged stamps get zero sums.
  */
+static float weight_var(const float* V1, const float* V2, int64_t o) {
+    return V1 ? V2[o] + V1[o] : V2[o];
+}
+
 void orc_fit_stamps(const orc_config* c, const double* kb, const float* I1, const uint8_t* M1,
                     const float* I2, const float* V2, const uint8_t* M2, int W, int H,
                     int64_t pitch, const int32_t* xy, int n, double* Ms, double* bs, double* es,
-                    int32_t* npix, int32_t* flags) {
+                    int32_t* npix, int32_t* flags, const float* V1) {
     const int nb = orc_n_basis(c), L = nb + 1, h = c->h, r = c->r, K = 2 * h + 1,
               T = K * K;
 #pragma omp parallel for schedule(dynamic)
@@ -220,7 +226,7 @@ void orc_fit_stamps(const orc_config* c, const double* kb, const float* I1, cons
                         if (!isfinite(I1[y * pitch + x])) flag |= ORC_STAMP_NONFINITE;
                 for (int y = yc - r; y <= yc + r; y++)
                     for (int x = xc - r; x <= xc + r; x++) {
-                        const float v2 = V2[y * pitch + x];
+                        const float v2 = weight_var(V1, V2, y * pitch + x);
                         if (!isfinite(I2[y * pitch + x]) || !isfinite(v2) || !(v2 > 0.0f))
                             flag |= ORC_STAMP_NONFINITE;
                     }
@@ -242,7 +248,7 @@ void orc_fit_stamps(const orc_config* c, const double* kb, const float* I1, cons
                     A[i] = acc;
                 }
                 A[nb] = 1.0;
-                const double w = 1.0 / (double)V2[y * pitch + x];
+                const double w = 1.0 / (double)weight_var(V1, V2, y * pitch + x);
                 const double d = (double)I2[y * pitch + x];
                 for (int i = 0; i < L; i++) {
                     for (int j = 0; j < L; j++) M[i * L + j] += w * A[i] * A[j];
@@ -1457,7 +1463,8 @@ int orc_dual_unknowns(const orc_config* c) {
 
 /*
  * Per-stamp sums of the two-kernel form: columns A = (k_i (x) I1 for
- * i = 0..nb-1, k_i (x) I2 for i = 1..nb-1, 1), L2 = 2 nb, weights 1 / V2:
+ * i = 0..nb-1, k_i (x) I2 for i = 1..nb-1, 1), L2 = 2 nb, weights 1 / V2
+ * (1 / (V1 + V2) when V1 is given, as in orc_fit_stamps):
  * M_s = A^T W A (L2 x L2), b_s = A^T W I2, e_s = I2^T W I2 over the stamp
  * pixels.  Validity as for the single form, with I2 (and its mask) now
  * also required over the convolution footprint [x-r-h, x+r+h]^2.
@@ -1465,7 +1472,7 @@ int orc_dual_unknowns(const orc_config* c) {
 void orc_fit_dual(const orc_config* c, const double* kb, const float* I1, const uint8_t* M1,
                   const float* I2, const float* V2, const uint8_t* M2, int W, int H,
                   int64_t pitch, const int32_t* xy, int n, double* Ms, double* bs, double* es,
-                  int32_t* npix, int32_t* flags) {
+                  int32_t* npix, int32_t* flags, const float* V1) {
     const int nb = orc_n_basis(c), L = 2 * nb, h = c->h, r = c->r, K = 2 * h + 1, T = K * K;
 #pragma omp parallel for schedule(dynamic)
     for (int s = 0; s < n; s++) {
@@ -1490,7 +1497,7 @@ void orc_fit_dual(const orc_config* c, const double* kb, const float* I1, const 
                             flag |= ORC_STAMP_NONFINITE;
                 for (int y = yc - r; y <= yc + r; y++)
                     for (int x = xc - r; x <= xc + r; x++) {
-                        const float v2 = V2[y * pitch + x];
+                        const float v2 = weight_var(V1, V2, y * pitch + x);
                         if (!isfinite(v2) || !(v2 > 0.0f)) flag |= ORC_STAMP_NONFINITE;
                     }
             }
@@ -1514,7 +1521,7 @@ void orc_fit_dual(const orc_config* c, const double* kb, const float* I1, const 
                     if (i >= 1) A[nb + i - 1] = a2;
                 }
                 A[L - 1] = 1.0;
-                const double w = 1.0 / (double)V2[y * pitch + x];
+                const double w = 1.0 / (double)weight_var(V1, V2, y * pitch + x);
                 const double d = (double)I2[y * pitch + x];
                 for (int i = 0; i < L; i++) {
                     for (int j = 0; j < L; j++) M[i * L + j] += w * A[i] * A[j];

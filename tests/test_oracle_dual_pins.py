@@ -56,11 +56,13 @@ def _stamps(xs, ys, W, H, R, n):
     return np.array(keep[:n], dtype=np.int32)
 
 
-def test_penalised_solution_is_ridge_least_squares(orc):
+@pytest.mark.parametrize("with_v1", [False, True])
+def test_penalised_solution_is_ridge_least_squares(orc, with_v1):
     """One solution (no rejection) of the oracle equals the minimiser of
     sum w (A a - I2)^2 + sum P_j a_j^2 with A built here: for every stamp
     pixel, the columns g_s(stamp) k_i (x) I1, g_s(stamp) k_i (x) I2 (i >= 1)
-    and 1, and P_j = Phi Q_i on the b-terms i >= 1 and all c-terms."""
+    and 1, and P_j = Phi Q_i on the b-terms i >= 1 and all c-terms; w is
+    1 / V2, or 1 / (V1 + V2) when V1 is given."""
     cfg = O.Config(sigmas=(0.8, 1.6), degrees=(2, 1), h=4, r=5, S=1, max_iter=1)
     W = H = 90
     I1, V1, I2, V2, xs, ys = _pair(W, H, 40, 3)
@@ -68,7 +70,7 @@ def test_penalised_solution_is_ridge_least_squares(orc):
     st = _stamps(xs, ys, W, H, cfg.r + cfg.h, 14)
     kb = O.basis(cfg)
     nb, ns = cfg.n_basis, cfg.n_spatial
-    fit = O.fit_dual(cfg, I1, Z, I2, V2, Z, st)
+    fit = O.fit_dual(cfg, I1, Z, I2, V2, Z, st, V1=V1 if with_v1 else None)
     assert np.all(fit["flags"] == 0)
     phi = 0.05
     ret, a, chi2, fl, stats = O.solve_dual(cfg, W, H, st, fit, phi)
@@ -84,7 +86,7 @@ def test_penalised_solution_is_ridge_least_squares(orc):
                 row += [g[s] * c2[i][y, x] for i in range(1, nb) for s in range(ns)]
                 row.append(1.0)
                 rows.append(row)
-                ws.append(1.0 / float(V2[y, x]))
+                ws.append(1.0 / (float(V2[y, x]) + (float(V1[y, x]) if with_v1 else 0.0)))
                 ds.append(float(I2[y, x]))
     A = np.array(rows)
     w = np.array(ws)

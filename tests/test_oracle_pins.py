@@ -323,6 +323,35 @@ def test_normal_equations_bruteforce(orc):
         assert abs(chi2[s] - (res ** 2).sum()) < 1e-8 * max(1.0, chi2[s])
 
 
+def test_normal_equations_summed_variance_weights(orc):
+    """Weights 1 / (V1 + V2) (both images' noise): the sums are numpy's
+    weighted products with those weights, not the 1 / V2 ones; a stamp whose
+    summed variance is not finite and positive is flagged NONFINITE."""
+    cfg, W, H, I1, I2, V2, Z = _tiny_problem()
+    V1 = np.random.default_rng(9).uniform(20, 80, (H, W)).astype(np.float32)
+    stamps = np.array([[6, 6], [7, 8]], np.int32)
+    fit = O.fit_stamps(cfg, I1, Z, I2, V2, Z, stamps, V1=V1)
+    fit0 = O.fit_stamps(cfg, I1, Z, I2, V2, Z, stamps)
+    kb = O.basis(cfg)
+    Ai = [conv_same(I1.astype(np.float64), kb[i]) for i in range(cfg.n_basis)]
+    r = cfg.r
+    for s, (xc, yc) in enumerate(stamps):
+        sl = (slice(yc - r, yc + r + 1), slice(xc - r, xc + r + 1))
+        A = np.stack([x[sl].ravel() for x in Ai] + [np.ones((2 * r + 1) ** 2)], axis=1)
+        w = 1.0 / (V1[sl] + V2[sl]).astype(np.float64).ravel()   # variances added as stored (float)
+        d = I2[sl].astype(np.float64).ravel()
+        assert np.allclose(fit["M"][s], A.T @ (w[:, None] * A), rtol=1e-12)
+        assert np.allclose(fit["b"][s], A.T @ (w * d), rtol=1e-12)
+        assert abs(fit["e"][s] - (w * d * d).sum()) < 1e-10 * fit["e"][s]
+        assert not np.allclose(fit["M"][s], fit0["M"][s], rtol=1e-2)
+    V1b = V1.copy()
+    V1b[9, 10] = -V2[9, 10]                     # sum 0 inside the stamp of (8, 8) only
+    V1b[4, 4] = np.nan                          # inside the stamp of (4, 4) only (r = 2)
+    st = np.array([[8, 8], [4, 4], [9, 6]], np.int32)
+    fb = O.fit_stamps(cfg, I1, Z, I2, V2, Z, st, V1=V1b)
+    assert list(fb["flags"]) == [4, 4, 0]
+
+
 def test_stamp_validity_flags(orc):
     cfg, W, H, I1, I2, V2, Z = _tiny_problem()
     M1 = Z.copy(); M1[2, 11] = 1         # only inside the footprint of (7, 6) (r + h = 4)
