@@ -176,15 +176,9 @@ def oracle_batch_baseline(wls, dps, px, st, budget_s):
 def bench_batch(args, torch, psfm, synth):
     from paper_1901_09999_amd import tune
     spec = synth.BATCHES[args.workload]
-    seed_index = synth.SEED_INDEX[args.workload]
-    wls = [synth.batch_pair_workload(spec, k, seed_index) for k in range(spec.n_pairs)]
     t0 = time.perf_counter()
-    dps = []
-    for k, wl in enumerate(wls):
-        dps.append(synth.make_pair_device(wl, synth.workload_seed(seed_index, k)))
-        if k % 16 == 15:
-            torch.cuda.synchronize()
-            log(f"generated {k + 1}/{len(wls)} pairs ({time.perf_counter() - t0:.1f} s)")
+    wls, dps = synth.make_batch_device(args.workload,
+                                       log=lambda s: log(f"{s} ({time.perf_counter() - t0:.1f} s)"))
     px = np.array([wl.pixels for wl in wls], dtype=np.float64)
     total_px = float(px.sum())
     ctx = psfm.Context(psfm.Config(h=spec.kernel_half, r=spec.stamp_half, S=0))
@@ -192,10 +186,12 @@ def bench_batch(args, torch, psfm, synth):
                   stamps=torch.from_numpy(d.stamps.astype(np.int32)).cuda(),
                   S=d.workload.spatial_order) for d in dps]
     if args.no_tune:
-        grid, order, table = 0, 1, []
+        grid, order, band, table = 0, 1, 0, []
     else:
-        grid, order, table = tune.choose(ctx, pairs, c_out=10, log=log, use_cache=not args.retune)
-    log(f"tuned: apply_grid {grid}, order {order}")
+        tu = tune.choose(ctx, pairs, c_out=10, log=log, use_cache=not args.retune)
+        grid, order, band, table = tu["apply_grid"], tu["order"], tu["fit_band_rows"], tu["table"]
+        ctx = tune.context_for(ctx, band)
+    log(f"tuned: apply_grid {grid}, order {order}, fit band rows {band}")
     b = psfm.Batch(ctx, pairs, c_out=10, apply_grid=grid, order=order)
     b.run()
     torch.cuda.synchronize()
@@ -270,7 +266,8 @@ def bench_batch(args, torch, psfm, synth):
                                f"{int(spec.variable_frac * 100)}% variable sources, one HIP graph, "
                                f"FP32 fit",
                    "pairs": len(wls), "total_pixels": int(total_px),
-                   "apply_grid": grid, "tile_order": order, "parallelism": "single GPU"},
+                   "apply_grid": grid, "tile_order": order, "fit_band_rows": band,
+                   "parallelism": "single GPU"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                        "p99": round(float(np.percentile(lat, 99)), 3),
                        "max": round(float(lat.max()), 3)},

@@ -29,7 +29,8 @@
  *     is the default stream).  Host-detectable argument errors are returned
  *     before anything is launched.  Numerical failures found on the device
  *     (too few stamps, a matrix that is not positive definite) are written to
- *     psfm_fit_stats.info; the call itself still returns PSFM_OK.
+ *     psfm_fit_stats.info; the call itself still returns PSFM_OK (unless the
+ *     config's flags hold PSFM_SYNC, see there).
  *   - Calls allocate nothing: scratch memory is the caller's workspace `ws`
  *     (device memory of at least psfm_workspace_bytes() bytes, 256-byte
  *     aligned).  Concurrent calls need separate workspaces.  A context is
@@ -82,7 +83,8 @@ typedef enum {
 #define PSFM_MASK_CONV_POOR 4    /* masked input within the kernel footprint only */
 
 /* Arithmetic of the stamp fit (the normal equations of Section 2, Eq. 6).
-   FP32: FP32 basis convolution, FP32-MFMA Gram, per-row FP64 sums.
+   FP32: FP32 basis convolution, the Gram of the FP32 weighted block on FP64
+   MFMA (exact products, FP64 sums).
    BF16 / FP16: the same FP32 design rounded to 16 bits for a 16-bit MFMA
    Gram (FP32 accumulation, per-row FP64 sums); psfm_solve then refines each
    FP64 Cholesky solution `refine` times against residuals recomputed in
@@ -105,7 +107,8 @@ typedef enum {
  *   spatial_order, in coordinates scaled to [-1, 1] over the image, ordered by
  *   degree then l descending; evaluated at stamp centres for the fit and at
  *   patch centres for the application.
- *   Stamps are (2 stamp_half + 1)^2 pixels; the weights are 1 / V2.
+ *   Stamps are (2 stamp_half + 1)^2 pixels; the weights are 1 / V2, or
+ *   1 / (V1 + V2) (weight_mode).
  *   Rejection (Sections 3.3, 3.6): after each solution the used stamps with
  *   chi2_s / npix_s > mean + clip_sigma * std (population, over used stamps)
  *   are rejected and the equations re-solved, at most max_iter solutions; a
@@ -129,7 +132,34 @@ typedef struct psfm_config {
     double bad_frac;       /* BAD/POOR fraction (default 0.2) */
     int precision;         /* PSFM_PREC_* */
     int refine;            /* refinement steps of the 16-bit modes (0..4, default 1) */
+    int weight_mode;       /* PSFM_WEIGHT_*: fit weights 1 / V2 (default) or 1 / (V1 + V2) */
+    int ortho_basis;       /* 1: psfm_solve works in the orthonormalised basis (FP32 only) */
+    int flags;             /* PSFM_SYNC or 0 */
+    int fit_band_rows;     /* stamp rows per fit workgroup: 0 = chosen from r, or 9 or 11 */
 } psfm_config;
+
+/* weight_mode.  The fit's pixel weights are the inverse variance of the
+   target image alone (PSFM_WEIGHT_V2, Section 2's sigma^2 = V2), or of the
+   two images' variances added (PSFM_WEIGHT_V1V2: the convolved image's noise
+   counted with unit kernel weight); the second needs V1 in the fit calls. */
+#define PSFM_WEIGHT_V2   0
+#define PSFM_WEIGHT_V1V2 1
+
+/* ortho_basis.  The normal equations are ill-conditioned because the basis
+   terms overlap (Section 3.1's Gaussians share their centre).  With
+   ortho_basis = 1, psfm_solve and psfm_solve_prior map each stamp's sums to
+   the basis whose taps are orthonormal (k' = k R^-1, R the upper Cholesky
+   factor of the taps' Gram matrix; background unchanged), solve there, and
+   map the coefficients back (a = R^-1 c per spatial term) before the
+   residuals, the clip and the statistics, which are basis-independent.  FP32
+   precision only; the other solves and the batch return PSFM_ERR_UNSUPPORTED. */
+
+/* flags.  PSFM_SYNC: psfm_solve, psfm_solve_prior, psfm_solve_norm and
+   psfm_solve_dual wait for the stream after their launches and return the
+   device-detected status (PSFM_ERR_TOO_FEW_STAMPS, PSFM_ERR_NOT_PD,
+   PSFM_ERR_NORM_SINGULAR) besides writing it to stats->info.  Such calls
+   synchronise the stream and cannot be captured into a graph. */
+#define PSFM_SYNC 1
 
 /* Quality record of a fit (device memory, written by the library). */
 typedef struct psfm_fit_stats {
@@ -154,7 +184,8 @@ typedef struct psfm_context psfm_context;
 
 /* Fills *cfg with the defaults: 3 Gaussians (0.7, 1.5, 3.0 px) x degrees
    (6, 4, 2) = 49 terms, h = 10, S = 0, r = 20, P = 64, clip 3, 3 solutions,
-   3 stamps, bad_frac 0.2, FP32, 1 refinement step (16-bit modes only). */
+   3 stamps, bad_frac 0.2, FP32, 1 refinement step (16-bit modes only),
+   weights 1 / V2, the basis as defined, no flags, fit band rows from r. */
 void psfm_config_default(psfm_config* cfg);
 
 /* Validates cfg, builds the basis tables (FP64 on the host) and uploads them
@@ -187,16 +218,19 @@ size_t psfm_stamp_design_floats(const psfm_context* ctx, int n_stamps);
  * or, for a stamp failing the validity test of Section 3.3 (footprint
  * [x-r-h, x+r+h]^2 outside the image or masked in M1; stamp masked in M2;
  * non-finite or non-positive data), the flag bits and zero sums.
- * Arithmetic: FP32 separable basis convolution, FP32 MFMA Gram, per-band
- * partial sums added in FP64 (16-bit Gram in the BF16 / FP16 modes, see
- * PSFM_PREC_*).  Inputs: I1, M1 (convolved image), I2, V2, M2 (target), all
- * W x H with `pitch`.  Outputs are float64/int32 device arrays of n_stamps
+ * Arithmetic: FP32 separable basis convolution, the Gram of the FP32
+ * weighted block on FP64 MFMA, per-band partial sums added in FP64 (16-bit
+ * Gram in the BF16 / FP16 modes, see PSFM_PREC_*).  Inputs: I1, M1 (convolved
+ * image), I2, V2, M2 (target), all W x H with `pitch`; V1 (the convolved
+ * image's variance) is read only with weight_mode PSFM_WEIGHT_V1V2 (then the
+ * weight is 1 / (V1 + V2), added in FP32, and a stamp whose sum is not finite
+ * and positive is NONFINITE), else it may be NULL.  Outputs are float64/int32 device arrays of n_stamps
  * entries (stamp_M n*L*L, stamp_b n*L).  stamp_design (16-bit modes only,
  * else may be NULL; psfm_stamp_design_floats floats): per stamp the FP32
  * weighted design, column-major [term 0..nb-1, sqrt(w), sqrt(w) I2][pixel].
  */
-int psfm_fit_stamps(const psfm_context* ctx, const float* I1, const uint8_t* M1, const float* I2,
-                    const float* V2, const uint8_t* M2, int W, int H, int64_t pitch,
+int psfm_fit_stamps(const psfm_context* ctx, const float* I1, const float* V1, const uint8_t* M1,
+                    const float* I2, const float* V2, const uint8_t* M2, int W, int H, int64_t pitch,
                     const int32_t* stamp_xy, int n_stamps, double* stamp_M, double* stamp_b,
                     double* stamp_e, int32_t* stamp_npix, int32_t* stamp_flags,
                     float* stamp_design, void* ws, size_t ws_bytes, void* stream);
@@ -544,14 +578,15 @@ size_t psfm_dual_workspace_bytes(const psfm_context* ctx, int width, int height,
 int psfm_dual_unknowns(const psfm_context* ctx);
 
 /*
- * psfm_fit_dual: per-stamp sums of the two-kernel form, weights 1 / V2:
+ * psfm_fit_dual: per-stamp sums of the two-kernel form, weights 1 / V2 (or
+ * 1 / (V1 + V2) with weight_mode PSFM_WEIGHT_V1V2, V1 then required):
  * stamp_M (n x L2 x L2), stamp_b (n x L2), stamp_e, stamp_npix, stamp_flags,
  * as psfm_fit_stamps.  Validity as there, plus I2 and M2 over the whole
  * convolution footprint (I2 is convolved): a masked pixel there makes the
  * stamp INVALID, a non-finite one NONFINITE.
  */
-int psfm_fit_dual(const psfm_context* ctx, const float* I1, const uint8_t* M1, const float* I2,
-                  const float* V2, const uint8_t* M2, int W, int H, int64_t pitch,
+int psfm_fit_dual(const psfm_context* ctx, const float* I1, const float* V1, const uint8_t* M1,
+                  const float* I2, const float* V2, const uint8_t* M2, int W, int H, int64_t pitch,
                   const int32_t* stamp_xy, int n_stamps, double* stamp_M, double* stamp_b,
                   double* stamp_e, int32_t* stamp_npix, int32_t* stamp_flags, void* ws,
                   size_t ws_bytes, void* stream);

@@ -224,7 +224,7 @@ extern "C" int psfm_batch_plan(const psfm_context* ctx, const psfm_pair* pairs, 
         if (rc) return rc;
     }
     if (psfm::fit_lds_bytes(ctx) > 160 * 1024 - 1024) return PSFM_ERR_UNSUPPORTED;
-    if (ctx->cfg.precision != PSFM_PREC_FP32) return PSFM_ERR_UNSUPPORTED;
+    if (ctx->cfg.precision != PSFM_PREC_FP32 || ctx->cfg.ortho_basis) return PSFM_ERR_UNSUPPORTED;
     psfm_batch_tuning tu{0, 0};
     if (tuning) tu = *tuning;
     if (tu.apply_grid < 0 || tu.order < 0 || tu.order > 2) return PSFM_ERR_INVALID_ARG;

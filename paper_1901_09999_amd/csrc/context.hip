@@ -76,6 +76,13 @@ int psfm_create(const psfm_config* cfg, psfm_context** out) {
         nb + 2 > PSFM_GRAM_COLS || nf > 32 || c.precision < PSFM_PREC_FP32 ||
         c.precision > PSFM_PREC_FP16 || c.refine < 0 || c.refine > 4)
         return PSFM_ERR_UNSUPPORTED;
+    if (c.weight_mode != PSFM_WEIGHT_V2 && c.weight_mode != PSFM_WEIGHT_V1V2)
+        return PSFM_ERR_INVALID_ARG;
+    if (c.ortho_basis != 0 && c.ortho_basis != 1) return PSFM_ERR_INVALID_ARG;
+    if (c.flags & ~PSFM_SYNC) return PSFM_ERR_INVALID_ARG;
+    if (c.fit_band_rows != 0 && c.fit_band_rows != PSFM_FIT_BR_SMALL &&
+        c.fit_band_rows != PSFM_FIT_BR_LARGE)
+        return PSFM_ERR_UNSUPPORTED;
 
     psfm_context* ctx = new psfm_context();
     ctx->cfg = c;
@@ -88,8 +95,10 @@ int psfm_create(const psfm_config* cfg, psfm_context** out) {
     ctx->r = c.stamp_half;
     // fit band: 9 rows up to 41-row stamps (r <= 20: two workgroups' LDS per CU and
     // short bands, e.g. 9+9+9+9+5 rows at r = 20), 11 rows beyond (fewer bands
-    // per stamp when the stamps are many and large: 11+11+11+11+5 at r = 24)
-    ctx->fit_br = c.stamp_half <= 20 ? PSFM_FIT_BR_SMALL : PSFM_FIT_BR_LARGE;
+    // per stamp when the stamps are many and large: 11+11+11+11+5 at r = 24);
+    // a caller (a tuner) may pick either height instead
+    ctx->fit_br = c.fit_band_rows ? c.fit_band_rows
+                                  : c.stamp_half <= 20 ? PSFM_FIT_BR_SMALL : PSFM_FIT_BR_LARGE;
     ctx->KW = 2 * c.half_width + 1;
     ctx->T = ctx->KW * ctx->KW;
     const int h = ctx->h, KW = ctx->KW, T = ctx->T;

@@ -97,6 +97,8 @@ struct FitArgs {
     const float* I2;
     const float* V2;
     const uint8_t* M2;
+    const float* V1;   // weight 1 / (V1 + V2) when wmode is PSFM_WEIGHT_V1V2
+    int wmode;
     int W, H;
     int64_t pitch;
     const int32_t* xy;
@@ -210,7 +212,8 @@ __device__ void fit_band_body(const FitArgs& a, const int item, float* __restric
         for (int e = tid; e < nbr * NPX; e += 256) {
             const int br = e / NPX, x = e - br * NPX;
             const int64_t o = (int64_t)(yc - r + y_l0 + br) * pitch + (xc - r + x);
-            const float i2 = I2[o], v2 = V2[o];
+            const float i2 = I2[o];
+            const float v2 = a.wmode == PSFM_WEIGHT_V1V2 ? V2[o] + a.V1[o] : V2[o];
             float sw = 0.0f, dt = 0.0f;
             if (M2[o]) {
                 fl |= PSFM_STAMP_INVALID;
@@ -545,6 +548,7 @@ __global__ __launch_bounds__(256) void k_fit_band_b(const PairDesc* __restrict__
     a.I2 = pd.I2;
     a.V2 = pd.V2;
     a.M2 = pd.M2;
+    a.V1 = pd.V1;
     a.W = pd.W;
     a.H = pd.H;
     a.pitch = pd.pitch;
@@ -752,6 +756,7 @@ FitArgs base_fit_args(const psfm_context* ctx) {
     a.zf = ctx->term_z;
     a.nb = ctx->nb;
     a.nf = ctx->nf;
+    a.wmode = ctx->cfg.weight_mode;
     return a;
 }
 
@@ -889,8 +894,9 @@ size_t fit_workspace(const psfm_context* ctx, int n_stamps) {
 
 }  // namespace psfm
 
-extern "C" int psfm_fit_stamps(const psfm_context* ctx, const float* I1, const uint8_t* M1,
-                               const float* I2, const float* V2, const uint8_t* M2, int W, int H,
+extern "C" int psfm_fit_stamps(const psfm_context* ctx, const float* I1, const float* V1,
+                               const uint8_t* M1, const float* I2, const float* V2,
+                               const uint8_t* M2, int W, int H,
                                int64_t pitch, const int32_t* stamp_xy, int n_stamps,
                                double* stamp_M, double* stamp_b, double* stamp_e,
                                int32_t* stamp_npix, int32_t* stamp_flags, float* stamp_design,
@@ -903,6 +909,7 @@ extern "C" int psfm_fit_stamps(const psfm_context* ctx, const float* I1, const u
     if (!I1 || !M1 || !I2 || !V2 || !M2 || !stamp_xy || !stamp_M || !stamp_b || !stamp_e ||
         !stamp_npix || !stamp_flags)
         return PSFM_ERR_INVALID_ARG;
+    if (ctx->cfg.weight_mode == PSFM_WEIGHT_V1V2 && !V1) return PSFM_ERR_INVALID_ARG;
     if (psfm::fit_lds_bytes(ctx) > 160 * 1024 - 1024) return PSFM_ERR_UNSUPPORTED;
     const size_t need = psfm::fit_workspace(ctx, n_stamps);
     if (!ws || ws_bytes < need) return PSFM_ERR_WORKSPACE;
@@ -917,6 +924,7 @@ extern "C" int psfm_fit_stamps(const psfm_context* ctx, const float* I1, const u
     a.I2 = I2;
     a.V2 = V2;
     a.M2 = M2;
+    a.V1 = V1;
     a.W = W;
     a.H = H;
     a.pitch = pitch;
@@ -934,8 +942,9 @@ extern "C" int psfm_fit_stamps(const psfm_context* ctx, const float* I1, const u
     return PSFM_OK;
 }
 
-extern "C" int psfm_fit_dual(const psfm_context* ctx, const float* I1, const uint8_t* M1,
-                             const float* I2, const float* V2, const uint8_t* M2, int W, int H,
+extern "C" int psfm_fit_dual(const psfm_context* ctx, const float* I1, const float* V1,
+                             const uint8_t* M1, const float* I2, const float* V2,
+                             const uint8_t* M2, int W, int H,
                              int64_t pitch, const int32_t* stamp_xy, int n_stamps, double* stamp_M,
                              double* stamp_b, double* stamp_e, int32_t* stamp_npix,
                              int32_t* stamp_flags, void* ws, size_t ws_bytes, void* stream) {
@@ -945,6 +954,7 @@ extern "C" int psfm_fit_dual(const psfm_context* ctx, const float* I1, const uin
     if (!I1 || !M1 || !I2 || !V2 || !M2 || !stamp_xy || !stamp_M || !stamp_b || !stamp_e ||
         !stamp_npix || !stamp_flags)
         return PSFM_ERR_INVALID_ARG;
+    if (ctx->cfg.weight_mode == PSFM_WEIGHT_V1V2 && !V1) return PSFM_ERR_INVALID_ARG;
     if (2 * ctx->nb + 1 > GD_COLS) return PSFM_ERR_UNSUPPORTED;
     if (psfm::fit_lds_bytes(ctx) > 160 * 1024 - 1024) return PSFM_ERR_UNSUPPORTED;
     if (!ws || ws_bytes < psfm::dual_fit_workspace(ctx, n_stamps)) return PSFM_ERR_WORKSPACE;
@@ -963,6 +973,7 @@ extern "C" int psfm_fit_dual(const psfm_context* ctx, const float* I1, const uin
     a.I2 = I2;
     a.V2 = V2;
     a.M2 = M2;
+    a.V1 = V1;
     a.W = W;
     a.H = H;
     a.pitch = pitch;

@@ -1931,6 +1931,10 @@ size_t solve_workspace(const psfm_context* ctx, int n) {
     c.take<uint8_t>(n + 1);                          // normalisation mode: reserves to bring in
     if (ctx->cfg.precision != PSFM_PREC_FP32)
         c.take<double>((size_t)ctx->N * ctx->N);     // transposed factor (refinement)
+    if (ctx->cfg.ortho_basis) {
+        c.take<double>((size_t)n * ctx->L * ctx->L + 1);   // stamp sums in the orthonormal basis
+        c.take<double>((size_t)n * ctx->L + 1);
+    }
     return c.off;
 }
 
@@ -2001,6 +2005,76 @@ int batch_solve(const psfm_context* ctx, const PairDesc* pairs, const int* stamp
 // penq (nullable): penalty weights of the two-kernel form, whose view of the
 // context (nb = 2 nb - 1 spatially varying columns) ctx then is; pen_nb is
 // the basis size they index.
+// ---- orthonormalised basis (ortho_basis)
+// The taps of the basis terms, as columns of B, have the Gram B^T B = R^T R
+// (R upper, from the context); the terms k' = k R^-1 are orthonormal.  With
+// T = blockdiag(R^-1, 1) (background unchanged) a stamp's sums become
+// M' = T^T M T and b' = T^T b.  One wave per stamp: lane j first takes column
+// j of [M | b] through the forward substitution with R^T (X = R^-T [M | b]),
+// then lane i takes row i of X through the substitution with R from the
+// right (M' = X R^-1).  L <= 63, so the L + 1 columns fit one wave.
+__global__ __launch_bounds__(64) void k_ortho_stamps(const double* __restrict__ Rm, int nb, int L,
+                                                     const double* __restrict__ Ms,
+                                                     const double* __restrict__ bs,
+                                                     double* __restrict__ Mo,
+                                                     double* __restrict__ bo) {
+    __shared__ double X[64 * 65];                 // X[i * 65 + j]: row i, column j (b at j = L)
+    const int s = blockIdx.x, t = threadIdx.x;
+    const double* M = Ms + (size_t)s * L * L;
+    if (t <= L) {
+        const int j = t;
+        auto src = [&](int i) { return j < L ? M[(size_t)i * L + j] : bs[(size_t)s * L + i]; };
+        for (int i = 0; i < nb; i++) {
+            double v = src(i);
+            for (int k = 0; k < i; k++) v -= Rm[k * nb + i] * X[k * 65 + j];
+            X[i * 65 + j] = v / Rm[i * nb + i];
+        }
+        for (int i = nb; i < L; i++) X[i * 65 + j] = src(i);
+    }
+    __syncthreads();
+    if (t < L) {
+        const int i = t;
+        double* Y = X + i * 65;                   // row i, overwritten left to right
+        for (int j = 0; j < nb; j++) {
+            double v = Y[j];
+            for (int k = 0; k < j; k++) v -= Y[k] * Rm[k * nb + j];
+            Y[j] = v / Rm[j * nb + j];
+        }
+        double* out = Mo + (size_t)s * L * L + (size_t)i * L;
+        for (int j = 0; j < L; j++) out[j] = Y[j];
+        bo[(size_t)s * L + i] = Y[L];
+    }
+}
+
+// Coefficients back from the orthonormalised basis after a solution:
+// a_(i, p) = sum_j (R^-1)_ij c_(j, p) for each spatial term p (back
+// substitution R a = c, in place from the last term up), the background
+// unchanged.  Skipped when this round's factorization did not run or failed
+// (the state is then done), so that the coefficients are mapped once per
+// solution.  One thread per spatial term.
+__global__ __launch_bounds__(64) void k_ortho_coeffs(const double* __restrict__ Rm, int nb, int ns,
+                                                     double* __restrict__ x,
+                                                     const SolveState* __restrict__ st) {
+    if (st->done) return;
+    const int p = threadIdx.x;
+    if (p >= ns) return;
+    for (int i = nb - 1; i >= 0; i--) {
+        double v = x[i * ns + p];
+        for (int k = i + 1; k < nb; k++) v -= Rm[i * nb + k] * x[k * ns + p];
+        x[i * ns + p] = v / Rm[i * nb + i];
+    }
+}
+
+// PSFM_SYNC: wait for the stream, then return the status the device wrote.
+static int sync_status(const psfm_context* ctx, const psfm_fit_stats* stats, hipStream_t st) {
+    if (!(ctx->cfg.flags & PSFM_SYNC)) return PSFM_OK;
+    int info = 0;
+    PSFM_HIP_CHECK(hipMemcpyAsync(&info, &stats->info, sizeof(int), hipMemcpyDeviceToHost, st));
+    PSFM_HIP_CHECK(hipStreamSynchronize(st));
+    if (info > 0) return PSFM_ERR_NOT_PD;
+    return info;   // 0, PSFM_ERR_TOO_FEW_STAMPS or PSFM_ERR_NORM_SINGULAR
+}
+
 static int solve_impl(const psfm_context* ctx, int W, int H, const int32_t* stamp_xy, int n_stamps,
                       const double* stamp_M, const double* stamp_b, const double* stamp_e,
                       const int32_t* stamp_npix, int32_t* stamp_flags, const float* stamp_design,
@@ -2016,6 +2090,8 @@ static int solve_impl(const psfm_context* ctx, int W, int H, const int32_t* stam
         return PSFM_ERR_INVALID_ARG;
     if (ctx->N > CH_NMAX) return PSFM_ERR_UNSUPPORTED;
     if (prior && ctx->L > 64) return PSFM_ERR_UNSUPPORTED;
+    const bool ortho = ctx->cfg.ortho_basis != 0;
+    if (ortho && (mixed || penq || ctx->L > 63)) return PSFM_ERR_UNSUPPORTED;
     const size_t need = psfm::solve_workspace(ctx, n_stamps);
     if (!ws || ws_bytes < need) return PSFM_ERR_WORKSPACE;
     const size_t lds = psfm::solve_lds_bytes(ctx->N);
@@ -2045,6 +2121,8 @@ static int solve_impl(const psfm_context* ctx, int W, int H, const int32_t* stam
     c.take<uint8_t>(n_stamps + 1);
     c.take<uint8_t>(n_stamps + 1);
     double* LT = mixed ? c.take<double>((size_t)ctx->N * ctx->N) : nullptr;   // transposed factor
+    double* Mo = ortho ? c.take<double>((size_t)n_stamps * ctx->L * ctx->L + 1) : nullptr;
+    double* bo = ortho ? c.take<double>((size_t)n_stamps * ctx->L + 1) : nullptr;
     const int nb = ctx->nb, ns = ctx->ns, N = ctx->N, L = ctx->L;
     const int npix = (2 * ctx->r + 1) * (2 * ctx->r + 1);
     const psfm_config& cf = ctx->cfg;
@@ -2053,9 +2131,14 @@ static int solve_impl(const psfm_context* ctx, int W, int H, const int32_t* stam
     const int nt = std::max(n_stamps, N);
     const int n_init = (nt + 255) / 256;
     const int tiles = n_stamps > 0 ? (n_stamps + TS_K - 1) / TS_K * ((L * L + L + TS_R - 1) / TS_R) : 0;
+    if (ortho && n_stamps > 0)
+        hipLaunchKernelGGL(k_ortho_stamps, dim3(n_stamps), dim3(64), 0, st, ctx->kgram_R, nb, L, stamp_M,
+                           stamp_b, Mo, bo);
+    // the assembly reads the (mapped) sums; the residuals read the originals
     hipLaunchKernelGGL(k_solve_prep, dim3(n_init + std::min(tiles, 1024)), dim3(256), 0, st, n_init,
                        n_stamps, N, ns, cf.spatial_order, W, H, cf.min_stamps, L, stamp_xy, stamp_flags,
-                       used, fitted, G, stamp_chi2, coeffs, state, stamp_M, stamp_b, Mt, bt);
+                       used, fitted, G, stamp_chi2, coeffs, state, ortho ? Mo : stamp_M,
+                       ortho ? bo : stamp_b, Mt, bt);
     PSFM_HIP_CHECK(hipGetLastError());
     const int nthreads_asm = L * L * ns + L * ns;
     if (prior && n_stamps > 0) {
@@ -2101,6 +2184,8 @@ static int solve_impl(const psfm_context* ctx, int W, int H, const int32_t* stam
         hipLaunchKernelGGL(k_cholesky<false>, dim3(1), dim3(CH_THREADS), lds, st, N, M, b, coeffs, ILg,
                            mixed ? Dg : nullptr, state, nullptr, nullptr,
                            mixed && n_stamps > 0 ? LT : nullptr);
+        if (ortho)
+            hipLaunchKernelGGL(k_ortho_coeffs, dim3(1), dim3(64), 0, st, ctx->kgram_R, nb, ns, coeffs, state);
         if (mixed && n_stamps > 0) {
             // 16-bit sums: refine against FP32 pixel residuals, then chi2 from pixels
             for (int k = 0; k < cf.refine; k++) {
@@ -2142,7 +2227,7 @@ static int solve_impl(const psfm_context* ctx, int W, int H, const int32_t* stam
     if (prior && n_stamps > 0)
         hipLaunchKernelGGL(k_prior_finish, dim3(1), dim3(64), 0, st, pdof, pcounts, stats);
     PSFM_HIP_CHECK(hipGetLastError());
-    return PSFM_OK;
+    return sync_status(ctx, stats, st);
 }
 
 extern "C" int psfm_solve(const psfm_context* ctx, int W, int H, const int32_t* stamp_xy,
@@ -2217,7 +2302,7 @@ extern "C" int psfm_solve_norm(const psfm_context* ctx, int W, int H, const int3
                                int32_t* stamp_flags, double* coeffs, double* stamp_chi2,
                                psfm_fit_stats* stats, void* ws, size_t ws_bytes, void* stream) {
     if (!ctx || n_stamps < 0 || !coeffs || !stats) return PSFM_ERR_INVALID_ARG;
-    if (ctx->cfg.precision != PSFM_PREC_FP32) return PSFM_ERR_UNSUPPORTED;
+    if (ctx->cfg.precision != PSFM_PREC_FP32 || ctx->cfg.ortho_basis) return PSFM_ERR_UNSUPPORTED;
     if (W < 1 || H < 1) return PSFM_ERR_SHAPE;
     if (n_stamps > 0 && (!stamp_xy || !stamp_M || !stamp_b || !stamp_e || !stamp_npix ||
                          !stamp_norm || !stamp_flags || !stamp_chi2))
@@ -2291,7 +2376,7 @@ extern "C" int psfm_solve_norm(const psfm_context* ctx, int W, int H, const int3
     hipLaunchKernelGGL(k_solve_finish, dim3(1), dim3(1024), 0, st, n_stamps, ns, N, N - ns + 1,
                        cf.spatial_order, W, H, stamp_npix, used, stamp_chi2, coeffs, state, stats);
     PSFM_HIP_CHECK(hipGetLastError());
-    return PSFM_OK;
+    return sync_status(ctx, stats, st);
 }
 
 // The two-kernel form's view of the context: its 2 nb - 1 spatially varying
@@ -2319,6 +2404,7 @@ extern "C" int psfm_solve_dual(const psfm_context* ctx, int W, int H, const int3
                                double phi, double* coeffs, double* stamp_chi2, psfm_fit_stats* stats,
                                void* ws, size_t ws_bytes, void* stream) {
     if (!ctx || !(phi >= 0.0)) return PSFM_ERR_INVALID_ARG;
+    if (ctx->cfg.ortho_basis) return PSFM_ERR_UNSUPPORTED;
     const psfm_context d = dual_view(ctx);
     if (d.L > 128) return PSFM_ERR_UNSUPPORTED;
     return solve_impl(&d, W, H, stamp_xy, n_stamps, stamp_M, stamp_b, stamp_e, stamp_npix, stamp_flags,

@@ -22,6 +22,8 @@ MAX_GAUSS = 8
 STAMP_INVALID, STAMP_REJECTED, STAMP_NONFINITE, STAMP_EXCLUDED, STAMP_PRIOR = 1, 2, 4, 8, 16
 MASK_BAD, MASK_CONV_BAD, MASK_CONV_POOR = 1, 2, 4
 PREC_FP32, PREC_BF16, PREC_FP16 = 0, 1, 2
+WEIGHT_V2, WEIGHT_V1V2 = 0, 1     # fit weights 1 / V2 or 1 / (V1 + V2)
+SYNC = 1                          # config flag: solves wait and return the device status
 
 
 class PsfmError(RuntimeError):
@@ -43,6 +45,10 @@ class CConfig(C.Structure):
         ("bad_frac", C.c_double),
         ("precision", C.c_int),
         ("refine", C.c_int),
+        ("weight_mode", C.c_int),
+        ("ortho_basis", C.c_int),
+        ("flags", C.c_int),
+        ("fit_band_rows", C.c_int),
     ]
 
 
@@ -139,7 +145,7 @@ def lib():
             "psfm_stamp_dim": (i, [P]),
             "psfm_workspace_bytes": (sz, [P, i, i, i]),
             "psfm_stamp_design_floats": (sz, [P, i]),
-            "psfm_fit_stamps": (i, [P, P, P, P, P, P, i, i, i64, P, i, P, P, P, P, P, P, P, sz, P]),
+            "psfm_fit_stamps": (i, [P, P, P, P, P, P, P, i, i, i64, P, i, P, P, P, P, P, P, P, sz, P]),
             "psfm_solve": (i, [P, i, i, P, i, P, P, P, P, P, P, P, P, P, P, sz, P]),
             "psfm_convolve_image": (i, [P, P, P, P, i, i, i64, P, P, P, sz, P]),
             "psfm_propagate_variance": (i, [P, P, P, P, i, i, i64, P, i, P, P, i, P, P, sz, P]),
@@ -159,7 +165,7 @@ def lib():
                                     P, P, P, i, P, sz, P]),
             "psfm_dual_workspace_bytes": (sz, [P, i, i, i]),
             "psfm_dual_unknowns": (i, [P]),
-            "psfm_fit_dual": (i, [P, P, P, P, P, P, i, i, i64, P, i, P, P, P, P, P, P, sz, P]),
+            "psfm_fit_dual": (i, [P, P, P, P, P, P, P, i, i, i64, P, i, P, P, P, P, P, P, sz, P]),
             "psfm_solve_dual": (i, [P, i, i, P, i, P, P, P, P, P, C.c_double, P, P, P, P, sz, P]),
             "psfm_dual_subtract": (i, [P, P, P, P, P, P, P, P, i, i, i64, P, P, P, P]),
             "psfm_envelope_psf": (i, [P, i, i, P, P, P]),
@@ -235,6 +241,10 @@ class Config:
     bad_frac: float = 0.2
     precision: int = PREC_FP32
     refine: int = 1
+    weight_mode: int = 0          # WEIGHT_V2 or WEIGHT_V1V2
+    ortho_basis: int = 0
+    flags: int = 0                # SYNC or 0
+    fit_band_rows: int = 0        # 0 (from r), 9 or 11
 
     @classmethod
     def from_workload(cls, wl, **kw):
@@ -252,6 +262,8 @@ class Config:
         c.half_width, c.spatial_order, c.stamp_half, c.patch = self.h, self.S, self.r, self.P
         c.clip_sigma, c.max_iter, c.min_stamps = self.clip_sigma, self.max_iter, self.min_stamps
         c.bad_frac, c.precision, c.refine = self.bad_frac, self.precision, self.refine
+        c.weight_mode, c.ortho_basis = self.weight_mode, self.ortho_basis
+        c.flags, c.fit_band_rows = self.flags, self.fit_band_rows
         return c
 
 
@@ -295,7 +307,8 @@ class Context:
         return self._ws
 
     # ------------------------------------------------------------------ calls
-    def fit_stamps(self, I1, M1, I2, V2, M2, stamps, out=None):
+    def fit_stamps(self, I1, M1, I2, V2, M2, stamps, out=None, V1=None):
+        """psfm_fit_stamps (V1 is read with weight_mode WEIGHT_V1V2 only)."""
         H, W = I1.shape
         n = stamps.shape[0]
         L = self.L
@@ -308,8 +321,8 @@ class Context:
                        flags=torch.empty(n, dtype=torch.int32, device=dev),
                        design=self.design_buffer(n))
         ws = self.workspace(W, H, n)
-        _check(lib().psfm_fit_stamps(self._h, _ptr(I1), _ptr(M1), _ptr(I2), _ptr(V2), _ptr(M2), W, H,
-                                     W, _ptr(stamps), n, _ptr(out["M"]), _ptr(out["b"]),
+        _check(lib().psfm_fit_stamps(self._h, _ptr(I1), _ptr(V1), _ptr(M1), _ptr(I2), _ptr(V2),
+                                     _ptr(M2), W, H, W, _ptr(stamps), n, _ptr(out["M"]), _ptr(out["b"]),
                                      _ptr(out["e"]), _ptr(out["npix"]), _ptr(out["flags"]),
                                      _ptr(out.get("design")), _ptr(ws), ws.numel(), _stream()),
                "psfm_fit_stamps")
@@ -413,7 +426,7 @@ class Context:
             self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
         return self._ws
 
-    def fit_dual(self, I1, M1, I2, V2, M2, stamps):
+    def fit_dual(self, I1, M1, I2, V2, M2, stamps, V1=None):
         """psfm_fit_dual: dict(M [n, 2nb, 2nb], b, e, npix, flags)."""
         H, W = I1.shape
         n = stamps.shape[0]
@@ -425,7 +438,8 @@ class Context:
                    npix=torch.empty(n, dtype=torch.int32, device=dev),
                    flags=torch.empty(n, dtype=torch.int32, device=dev))
         ws = self.dual_workspace(W, H, n)
-        _check(lib().psfm_fit_dual(self._h, _ptr(I1), _ptr(M1), _ptr(I2), _ptr(V2), _ptr(M2), W, H, W,
+        _check(lib().psfm_fit_dual(self._h, _ptr(I1), _ptr(V1), _ptr(M1), _ptr(I2), _ptr(V2), _ptr(M2),
+                                   W, H, W,
                                    _ptr(stamps), n, _ptr(out["M"]), _ptr(out["b"]), _ptr(out["e"]),
                                    _ptr(out["npix"]), _ptr(out["flags"]), _ptr(ws), ws.numel(),
                                    _stream()), "psfm_fit_dual")
@@ -578,7 +592,7 @@ class Context:
         ``bufs`` (from :meth:`alloc_pair`) avoids allocations in a timed loop."""
         H, W = I1.shape
         b = self.alloc_pair(W, H, stamps.shape[0], c_out) if bufs is None else bufs
-        fit = self.fit_stamps(I1, M1, I2, V2, M2, stamps, out=b["fit"])
+        fit = self.fit_stamps(I1, M1, I2, V2, M2, stamps, out=b["fit"], V1=V1)
         b["flags_in"].copy_(fit["flags"])
         sol = self.solve(W, H, stamps, fit, flags=b["flags_in"], out=b["sol"], flags_inplace=True)
         sub = self.match(sol["coeffs"], I1, V1, M1, I2, V2, M2, c_out=c_out, stats=sol["stats"],

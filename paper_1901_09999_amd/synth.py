@@ -487,6 +487,23 @@ def make_pair_device(wl: Workload, seed: int, device="cuda", n_stamps: Optional[
                       M2, stamps, xs, ys, fluxes, seed)
 
 
+def make_batch_device(name: str = "batch64", log=None):
+    """The pairs of batch ``name`` rendered on the GPU, each from its own
+    seed: returns (workloads, device pairs)."""
+    import torch
+
+    spec = BATCHES[name]
+    seed_index = SEED_INDEX[name]
+    wls = [batch_pair_workload(spec, k, seed_index) for k in range(spec.n_pairs)]
+    dps = []
+    for k, wl in enumerate(wls):
+        dps.append(make_pair_device(wl, workload_seed(seed_index, k)))
+        if log and k % 16 == 15:
+            torch.cuda.synchronize()
+            log(f"generated {k + 1}/{len(wls)} pairs")
+    return wls, dps
+
+
 # --------------------------------------------------------------------------
 # Single-star stamp pairs for the learned prior (one star per 64 x 64 cell).
 

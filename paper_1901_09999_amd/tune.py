@@ -1,14 +1,21 @@
 """Launch-shape choice for batched matching.
 
-The fused apply kernel of a batch visits the 64 x 64 tiles of every pair;
-its grid (one workgroup per tile, or a grid-stride loop over a fixed number
-of workgroups) and the order of the pairs in the tile list (as given,
-smallest first, largest first) are chosen by timing each candidate on the
-batch itself.  Results are cached as JSON, keyed by the device and the shape
-of the batch, so a later plan of the same shape skips the search.
+Two tile shapes and two launch parameters are chosen by timing each
+candidate on the batch itself:
+  * the stamp fit's band height (stamp rows per workgroup, 9 or 11: the
+    kernels are built for both), timed on the fit stage alone;
+  * the fused apply kernel's grid (one workgroup per 64 x 64 tile, or a
+    grid-stride loop over a fixed number of workgroups) and the order of the
+    pairs in its tile list (as given, smallest first, largest first), timed
+    on the whole batch.
+The two searches are separate because the band height changes only the fit
+and the apply parameters only the tile pass.  Results are cached as JSON,
+keyed by the device and the shape of the batch, so a later plan of the same
+shape skips the search.
 """
 from __future__ import annotations
 
+import dataclasses
 import hashlib
 import json
 import os
@@ -21,6 +28,7 @@ from . import psfm
 
 DEFAULT_GRIDS = (0, 256, 512, 1024, 2048)
 DEFAULT_ORDERS = (0, 1, 2)
+DEFAULT_BAND_ROWS = (9, 11)
 
 
 def cache_path() -> str:
@@ -71,16 +79,57 @@ def _time_runs(b: psfm.Batch, reps: int) -> float:
     return best
 
 
+def _time_stage(b: psfm.Batch, stage: int, reps: int) -> float:
+    b.run()                                   # warm (and every stage's inputs in place)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(b.stream):
+            e0.record()
+            b.run_stage(stage)
+            e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    return best
+
+
+def context_for(ctx: psfm.Context, fit_band_rows: int) -> psfm.Context:
+    """ctx itself, or a context of the same configuration with the given fit band height."""
+    if ctx.cfg.fit_band_rows == fit_band_rows:
+        return ctx
+    return psfm.Context(dataclasses.replace(ctx.cfg, fit_band_rows=fit_band_rows), ctx.device)
+
+
 def choose(ctx: psfm.Context, pairs: Sequence[dict], c_out: int = 10,
            grids: Sequence[int] = DEFAULT_GRIDS, orders: Sequence[int] = DEFAULT_ORDERS,
-           reps: int = 2, use_cache: bool = True, log=None) -> Tuple[int, int, List[dict]]:
-    """Returns (apply_grid, order, table of timings in ms)."""
+           band_rows: Sequence[int] = DEFAULT_BAND_ROWS, reps: int = 2, use_cache: bool = True,
+           log=None) -> dict:
+    """Returns dict(apply_grid, order, fit_band_rows, table of timings in ms)."""
     key = batch_key(ctx, pairs)
     if use_cache:
         rec = _load().get(key)
-        if rec:
-            return rec["apply_grid"], rec["order"], rec["table"]
+        if rec and "fit_band_rows" in rec:
+            return rec
     table = []
+    fit_ms = {}
+    for br in band_rows:
+        try:
+            c = context_for(ctx, br)
+        except psfm.PsfmError:                # that band's LDS does not fit this basis
+            continue
+        b = psfm.Batch(c, pairs, c_out=c_out)
+        ms = _time_stage(b, 0, reps)
+        fit_ms[br] = ms
+        table.append(dict(fit_band_rows=br, stage="fit", ms=round(ms, 4)))
+        if log:
+            log(f"tune: fit band rows {br}: {ms:.3f} ms")
+        b.close()
+        del b
+        if c is not ctx:
+            c.close()
+        torch.cuda.empty_cache()
+    best_br = min(fit_ms, key=fit_ms.get) if fit_ms else ctx.cfg.fit_band_rows
     for order in orders:
         b = psfm.Batch(ctx, pairs, c_out=c_out, order=order)
         for g in grids:
@@ -92,7 +141,8 @@ def choose(ctx: psfm.Context, pairs: Sequence[dict], c_out: int = 10,
         b.close()
         del b
         torch.cuda.empty_cache()
-    best = min(table, key=lambda t: t["ms"])
-    _store(key, dict(apply_grid=best["apply_grid"], order=best["order"], table=table,
-                     when=time.strftime("%Y-%m-%dT%H:%M:%S")))
-    return best["apply_grid"], best["order"], table
+    best = min((t for t in table if "apply_grid" in t), key=lambda t: t["ms"])
+    rec = dict(apply_grid=best["apply_grid"], order=best["order"], fit_band_rows=best_br,
+               table=table, when=time.strftime("%Y-%m-%dT%H:%M:%S"))
+    _store(key, rec)
+    return rec

@@ -70,9 +70,14 @@ def test_host_argument_checks(lib):
     lib.psfm_config_default(C.byref(bad))
     bad.refine = 5
     assert lib.psfm_create(C.byref(bad), C.byref(h)) == -7
+    for field, value, code in (("weight_mode", 2, -1), ("ortho_basis", 2, -1), ("flags", 2, -1),
+                               ("fit_band_rows", 10, -7)):
+        lib.psfm_config_default(C.byref(bad))
+        setattr(bad, field, value)
+        assert lib.psfm_create(C.byref(bad), C.byref(h)) == code, field
     assert lib.psfm_stamp_design_floats(None, 4) == 0
     assert lib.psfm_workspace_bytes(None, 10, 10, 1) == 0
-    assert lib.psfm_fit_stamps(None, *([None] * 5), 10, 10, 10, None, 1, *([None] * 6), None, 0,
+    assert lib.psfm_fit_stamps(None, *([None] * 6), 10, 10, 10, None, 1, *([None] * 6), None, 0,
                                None) == -1
     assert lib.psfm_solve(None, 10, 10, None, 1, *([None] * 9), None, 0, None) == -1
     assert lib.psfm_convolve_image(None, None, None, None, 10, 10, 10, None, None, None, 0, None) == -1

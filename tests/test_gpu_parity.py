@@ -1,10 +1,11 @@
 """Parity of the HIP path (called through the C interface) with the FP64 oracle.
 
 Tolerances follow from the arithmetic of the HIP kernels:
-  * per-stamp Gram (FP32 separable basis convolution, FP32 MFMA accumulation
-    over <= 12 x 49 pixels per band, bands added in FP64): every entry within
-    2e-5 of sqrt(M_ii M_jj) (Cauchy-Schwarz scale of the entry), e_s within
-    1e-5 relative;
+  * per-stamp Gram (FP32 separable basis convolution of the FP32 weighted
+    block, its products summed on FP64 MFMA over <= 11 rows of a stamp per
+    band, bands added in FP64): every entry within 2e-5 of sqrt(M_ii M_jj)
+    (Cauchy-Schwarz scale of the entry; the FP32 design's rounding sets it),
+    e_s within 1e-5 relative;
   * solve from identical stamp sums (both FP64): kernel sum and chi2/dof
     within 1e-9 relative; coefficients within 1e-5 of max|a| (the equations
     have condition numbers near 1e8, so raw coefficients are only pinned to
