@@ -154,8 +154,6 @@ void lay_out(const psfm_context* ctx, const psfm_pair* q, const int* order, int 
         d.used = c.take<uint8_t>(ns_st + 1);
         d.fitted = c.take<uint8_t>(ns_st + 1);
         d.G = c.take<double>((size_t)ns_st * z.ns + 1);
-        d.Mt = c.take<double>((size_t)ns_st * z.L * z.L + 1);
-        d.bt = c.take<double>((size_t)ns_st * z.L + 1);
         d.A = c.take<double>((size_t)z.N * z.N);
         d.b = c.take<double>(z.N);
         d.ILg = c.take<double>(psfm::solve_il_doubles(z.N));

@@ -86,8 +86,6 @@ struct PairDesc {
     uint8_t* used;
     uint8_t* fitted;
     double* G;
-    double* Mt;
-    double* bt;
     double* A;
     double* b;
     double* ILg;

@@ -66,188 +66,225 @@ __device__ void solve_init_body(int n, int N, int ns, int S, int W, int H, int m
     }
 }
 
-// Stamp-major copy of the stamp sums: Mt[ij][k] = M_k[ij], bt[i][k] = b_k[i],
-// so that the assembly reads each (i, j) entry of all stamps contiguously.
-// Tiles of 32 stamps x 64 entries go through LDS, so that both the reads
-// (along the entries of a stamp) and the writes (along the stamps of an
-// entry) are contiguous; workgroup bid, bid + nblk, ... take the tiles.
-constexpr int TS_K = 32, TS_R = 64;
-__device__ void transpose_sums_body(int n, int L, const double* __restrict__ Ms,
-                                    const double* __restrict__ bs, double* __restrict__ Mt,
-                                    double* __restrict__ bt, int bid, int nblk) {
-    __shared__ double tile[TS_K][TS_R + 1];
-    const int LL = L * L, R = LL + L;
-    const int tk = (n + TS_K - 1) / TS_K, tr = (R + TS_R - 1) / TS_R;
-    const int tid = threadIdx.x;
-    for (int tb = bid; tb < tk * tr; tb += nblk) {
-        const int k0 = (tb % tk) * TS_K, r0 = (tb / tk) * TS_R;
-        __syncthreads();                        // the previous tile's writes are done
-#pragma unroll
-        for (int m = 0; m < TS_K * TS_R / 256; m++) {
-            const int kk = tid / TS_R + (256 / TS_R) * m, rr = tid % TS_R;
-            const int k = k0 + kk, r = r0 + rr;
-            double v = 0.0;
-            if (k < n && r < R) v = r < LL ? Ms[(size_t)k * LL + r] : bs[(size_t)k * L + (r - LL)];
-            tile[kk][rr] = v;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int m = 0; m < TS_K * TS_R / 256; m++) {
-            const int rr = tid / TS_K + (256 / TS_K) * m, kk = tid % TS_K;
-            const int k = k0 + kk, r = r0 + rr;
-            if (k < n && r < R) {
-                if (r < LL) Mt[(size_t)r * n + k] = tile[kk][rr];
-                else bt[(size_t)(r - LL) * n + k] = tile[kk][rr];
-            }
-        }
-    }
-}
-
-// The two independent set-up steps of a solve in one launch: workgroups
-// below n_init initialise the state, the spatial terms and the stamp masks,
-// the others transpose the stamp sums.
-__global__ __launch_bounds__(256) void k_solve_prep(int n_init, int n, int N, int ns, int S, int W, int H,
-                                                    int min_stamps, int L,
-                                                    const int32_t* __restrict__ xy,
+// Set-up of a solve: the state, the spatial terms and the stamp masks.
+__global__ __launch_bounds__(256) void k_solve_prep(int n, int N, int ns, int S, int W, int H,
+                                                    int min_stamps, const int32_t* __restrict__ xy,
                                                     const int32_t* __restrict__ flags,
                                                     uint8_t* __restrict__ used, uint8_t* __restrict__ fitted,
                                                     double* __restrict__ G, double* __restrict__ chi2,
-                                                    double* __restrict__ coeffs, SolveState* st,
-                                                    const double* __restrict__ Ms,
-                                                    const double* __restrict__ bs,
-                                                    double* __restrict__ Mt, double* __restrict__ bt) {
-    const int bid = blockIdx.x;
-    if (bid < n_init)
-        solve_init_body(n, N, ns, S, W, H, min_stamps, xy, flags, used, fitted, G, chi2, coeffs, st, bid);
-    else
-        transpose_sums_body(n, L, Ms, bs, Mt, bt, bid - n_init, gridDim.x - n_init);
+                                                    double* __restrict__ coeffs, SolveState* st) {
+    solve_init_body(n, N, ns, S, W, H, min_stamps, xy, flags, used, fitted, G, chi2, coeffs, st, blockIdx.x);
 }
 
-__global__ __launch_bounds__(256) void k_solve_prep_b(const PairDesc* __restrict__ pairs, int n_init,
-                                                      int min_stamps, int L) {
+__global__ __launch_bounds__(256) void k_solve_prep_b(const PairDesc* __restrict__ pairs, int min_stamps) {
     const PairDesc& p = pairs[blockIdx.y];
-    const int bid = blockIdx.x;
-    if (bid < n_init) {
-        if (bid * (int)blockDim.x >= max(max(p.n, p.N), 1)) return;
-        solve_init_body(p.n, p.N, p.ns, p.S, p.W, p.H, min_stamps, p.xy, p.flags, p.used, p.fitted,
-                        p.G, p.chi2, p.coeffs, p.st, bid);
-    } else {
-        transpose_sums_body(p.n, L, p.Ms, p.bs, p.Mt, p.bt, bid - n_init, gridDim.x - n_init);
-    }
+    if ((int)blockIdx.x * (int)blockDim.x >= max(max(p.n, p.N), 1)) return;
+    solve_init_body(p.n, p.N, p.ns, p.S, p.W, p.H, min_stamps, p.xy, p.flags, p.used, p.fitted, p.G,
+                    p.chi2, p.coeffs, p.st, blockIdx.x);
 }
 
-// One item per (i, j, s) of the per-stamp index space, 8 items per
-// workgroup; the stamps are split over the 32 lanes of a half-wave per item
-// (stamp-major sums, so consecutive stamps are consecutive words) and the
-// partial sums are added by shuffles in a fixed order.
-constexpr int ASM_ITEMS = 8, ASM_CHUNKS = 32;
+// Assembly of the normal equations (Section 2): row (i, p) of M (the
+// background row last) is sum over the used stamps s of
+// g_s[p] M_s[i][(j, q)] g_s[q].  The rows (i, p) of one term i all read the
+// same M_s[i][.], so one workgroup forms a group of PB of them (the
+// background row alone in the last group).  Its ASM_WAVES waves each take a
+// fixed share of the stamps, in order; lane j keeps the group's entries
+// (j, q) for every q in registers, reading M_s[i][j] (consecutive lanes,
+// consecutive words); the values every lane needs (the stamps' spatial
+// terms and masks) are loaded one per lane for ASM_UNROLL stamps at a time
+// and passed through the wave's own LDS slots (read back as broadcasts).
+// b's entries are summed per lane (lane r: stamp k0 + r) and reduced at the
+// end.  Each stamp sum is read once per group and no transposed copy is
+// needed.  The waves' partial sums are added in wave order, so the result
+// does not depend on the launch.  JC: columns per lane (L <= 64 JC).
+constexpr int ASM_WAVES = 4;
+constexpr int ASM_UNROLL = 8;
 
-// R: stamps per batch of loads.  R > 1 shortens a latency-bound assembly
-// (one pair); the batch, bound by throughput, keeps R = 1 for occupancy.
-template <int NS, int R>
-__device__ void assemble_body(int n, int nb, int N, const double* __restrict__ Mt,
-                              const double* __restrict__ bt, const double* __restrict__ G,
-                              const uint8_t* __restrict__ used, double* __restrict__ M,
-                              double* __restrict__ b, const SolveState* st, const int bid) {
-    if (st->done) return;
-    const int L = nb + 1;
-    const int chunk = threadIdx.x % ASM_CHUNKS, li = threadIdx.x / ASM_CHUNKS;
-    const int t = bid * ASM_ITEMS + li;
-    const int nm = L * L * NS;
-    double acc[NS];
+// rows per group (a divisor of NS).  One: groups of several rows share the
+// loads of M_s[i][.], but their accumulators overflow the registers of a
+// lane at the occupancy that hides the loads' latency.
+template <int NS>
+struct AsmRows {
+    static constexpr int value = 1;
+    static_assert(NS % value == 0, "a group holds whole rows");
+};
+
+template <int NS>
+__host__ __device__ constexpr int asm_groups(int nb) { return nb * (NS / AsmRows<NS>::value) + 1; }
+
+template <int NS, int JC>
+__device__ void assemble_group(int n, int nb, int N, const double* __restrict__ Ms,
+                               const double* __restrict__ bs, const double* __restrict__ G,
+                               const uint8_t* __restrict__ used, double* __restrict__ M,
+                               double* __restrict__ b, const SolveState* st, int grp) {
+    constexpr int PB = AsmRows<NS>::value;
+    const int NG = asm_groups<NS>(nb);
+    if (st->done || grp >= NG) return;                 // uniform over the workgroup
+    const int L = nb + 1, j = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool bg = grp == NG - 1;
+    const int i = bg ? nb : grp / (NS / PB), p0 = bg ? 0 : (grp % (NS / PB)) * PB;
+    const size_t LL = (size_t)L * L;
+    const double* mrow = Ms + (size_t)i * L;
+    constexpr int GV = (ASM_UNROLL * NS + 63) / 64;
+    const int k_lo = (int)((long long)n * wave / ASM_WAVES);
+    const int k_hi = (int)((long long)n * (wave + 1) / ASM_WAVES);
+    __shared__ double bcast[ASM_WAVES][ASM_UNROLL * (NS + PB)];   // per wave: g_s, then g_s[p] u_s
+    double* gsh = bcast[wave];
+    double acc[PB][JC][NS];
+    double bacc[PB];
 #pragma unroll
-    for (int q = 0; q < NS; q++) acc[q] = 0.0;
-    int kind = 0, i = 0, j = 0, s = 0, ij = 0;
-    if (t < nm) {
-        s = t % NS;
-        ij = t / NS;
-        i = ij / L;
-        j = ij - i * L;
-        kind = (i == nb && s != 0) ? 0 : 1;
-    } else if (t < nm + L * NS) {
-        const int e = t - nm;
-        i = e / NS;
-        s = e - i * NS;
-        kind = (i == nb && s != 0) ? 0 : 2;
+    for (int t = 0; t < PB; t++) {
+        bacc[t] = 0.0;
+#pragma unroll
+        for (int c = 0; c < JC; c++)
+#pragma unroll
+            for (int q = 0; q < NS; q++) acc[t][c][q] = 0.0;
     }
-    if (kind == 1) {
-        // the stamp sums, masks and g_s of R of the lane's stamps are loaded
-        // together (the stamp sums come from L2 or HBM; the spatial terms,
-        // read in the sum, are a few KB that stay in L1); summed in stamp order
-        const double* mrow = Mt + (size_t)ij * n;
-        for (int k0 = chunk; k0 < n; k0 += R * ASM_CHUNKS) {
-            double gs[R], mv[R];
-            uint8_t uv[R];
+    for (int k0 = k_lo; k0 < k_hi; k0 += ASM_UNROLL) {
+        // lane e < ASM_UNROLL NS: spatial term e % NS of stamp k0 + e / NS;
+        // lane r < ASM_UNROLL: stamp k0 + r's mask, b_s[i] and g_s[p0 + t]
+        double gv[GV];
 #pragma unroll
-            for (int r = 0; r < R; r++) {
-                const int k = min(k0 + r * ASM_CHUNKS, n - 1);
-                gs[r] = G[(size_t)k * NS + s];
-                uv[r] = used[k];
-                mv[r] = mrow[k];
-            }
+        for (int t = 0; t < GV; t++) {
+            const int e = j + 64 * t;
+            gv[t] = (e < ASM_UNROLL * NS && k0 * NS + e < k_hi * NS) ? G[(size_t)k0 * NS + e] : 0.0;
+        }
+        const int kr = min(k0 + min(j, ASM_UNROLL - 1), k_hi - 1);
+        const double uv = (j < ASM_UNROLL && k0 + j < k_hi && used[kr]) ? 1.0 : 0.0;
+        const double bvv = bs[(size_t)kr * L + i];
+        double gpv[PB];
 #pragma unroll
-            for (int r = 0; r < R; r++) {
-                const int k = k0 + r * ASM_CHUNKS;
-                if (k >= n) break;
-                const double u = uv[r] ? 1.0 : 0.0;
-                const double gm = ((i == nb) ? u : u * gs[r]) * mv[r];
-                if (j == nb) {
-                    acc[0] += gm;
-                } else {
-                    const double* g = G + (size_t)k * NS;    // spatial terms of stamp k
+        for (int t = 0; t < PB; t++) {
+            gpv[t] = bg ? (t == 0 ? uv : 0.0) : uv * G[(size_t)kr * NS + p0 + t];
+            bacc[t] = fma(gpv[t], bvv, bacc[t]);
+        }
+        double mv[JC][ASM_UNROLL];
 #pragma unroll
-                    for (int q = 0; q < NS; q++) acc[q] += g[q] * gm;
+        for (int c = 0; c < JC; c++)
+#pragma unroll
+            for (int r = 0; r < ASM_UNROLL; r++)
+                mv[c][r] = mrow[(size_t)min(k0 + r, k_hi - 1) * LL + min(j + 64 * c, L - 1)];
+        wave_sync();                                  // the previous chunk's reads are done
+#pragma unroll
+        for (int t = 0; t < GV; t++)
+            if (j + 64 * t < ASM_UNROLL * NS) gsh[j + 64 * t] = gv[t];
+        if (j < ASM_UNROLL) {
+#pragma unroll
+            for (int t = 0; t < PB; t++) gsh[ASM_UNROLL * NS + j * PB + t] = gpv[t];
+        }
+        wave_sync();
+#pragma unroll
+        for (int r = 0; r < ASM_UNROLL; r++) {
+            double g[NS], gp[PB];
+#pragma unroll
+            for (int q = 0; q < NS; q++) g[q] = gsh[r * NS + q];
+#pragma unroll
+            for (int t = 0; t < PB; t++) gp[t] = gsh[ASM_UNROLL * NS + r * PB + t];   // 0: unused, k >= k_hi
+#pragma unroll
+            for (int c = 0; c < JC; c++) {
+#pragma unroll
+                for (int t = 0; t < PB; t++) {
+                    const double w = gp[t] * mv[c][r];
+                    if (j + 64 * c < nb) {
+#pragma unroll
+                        for (int q = 0; q < NS; q++) acc[t][c][q] = fma(g[q], w, acc[t][c][q]);
+                    } else {
+                        acc[t][c][0] += w;
+                    }
                 }
             }
         }
-    } else if (kind == 2) {
-        const double* brow = bt + (size_t)i * n;
-        for (int k = chunk; k < n; k += ASM_CHUNKS) {
-            const double* g = G + (size_t)k * NS;
-            const double u = used[k] ? 1.0 : 0.0;
-            acc[0] += ((i == nb) ? u : u * g[s]) * brow[k];
-        }
     }
-    // the item's 32 lanes (one half-wave) add their partial sums in a fixed
-    // butterfly order
+    // b's entries: the lanes' sums in a fixed butterfly order
 #pragma unroll
-    for (int q = 0; q < NS; q++) {
-        double v = acc[q];
+    for (int t = 0; t < PB; t++)
 #pragma unroll
-        for (int o = ASM_CHUNKS / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
-        acc[q] = v;
-    }
-    if (chunk != 0 || kind == 0) return;
-    if (kind == 1) {
-        const int row = (i == nb) ? N - 1 : i * NS + s;
-        if (j == nb) {
-            M[(size_t)row * N + N - 1] = acc[0];
-        } else {
+        for (int o = 32; o > 0; o >>= 1) bacc[t] += __shfl_xor(bacc[t], o);
+    // the waves' partial sums, added in wave order by wave 0, one row at a time
+    __shared__ double part[ASM_WAVES - 1][JC * NS][64];
 #pragma unroll
-            for (int q = 0; q < NS; q++) M[(size_t)row * N + j * NS + q] = acc[q];
+    for (int t = 0; t < PB; t++) {
+        if (wave > 0) {
+#pragma unroll
+            for (int c = 0; c < JC; c++)
+#pragma unroll
+                for (int q = 0; q < NS; q++) part[wave - 1][c * NS + q][j] = acc[t][c][q];
         }
-    } else {
-        b[(i == nb) ? N - 1 : i * NS + s] = acc[0];
+        __syncthreads();
+        if (wave == 0) {
+#pragma unroll
+            for (int w = 0; w < ASM_WAVES - 1; w++)
+#pragma unroll
+                for (int c = 0; c < JC; c++)
+#pragma unroll
+                    for (int q = 0; q < NS; q++) acc[t][c][q] += part[w][c * NS + q][j];
+        }
+        __syncthreads();
+    }
+    __shared__ double bpart[ASM_WAVES][PB];
+    if (j == 0) {
+#pragma unroll
+        for (int t = 0; t < PB; t++) bpart[wave][t] = bacc[t];
+    }
+    __syncthreads();
+    if (wave > 0) return;
+#pragma unroll
+    for (int t = 0; t < PB; t++) {
+        if (bg && t > 0) continue;                    // the background group has one row
+        const int row = bg ? N - 1 : i * NS + p0 + t;
+#pragma unroll
+        for (int c = 0; c < JC; c++) {
+            const int jc = j + 64 * c;
+            if (jc < nb) {
+#pragma unroll
+                for (int q = 0; q < NS; q++) M[(size_t)row * N + jc * NS + q] = acc[t][c][q];
+            } else if (jc == nb) {
+                M[(size_t)row * N + N - 1] = acc[t][c][0];
+            }
+        }
+        if (j == 0) {
+            double bsum = bpart[0][t];
+#pragma unroll
+            for (int w = 1; w < ASM_WAVES; w++) bsum += bpart[w][t];
+            b[row] = bsum;
+        }
     }
 }
 
-template <int NS>
-__global__ __launch_bounds__(256) void k_assemble(int n, int nb, int N, const double* __restrict__ Mt,
-                                                  const double* __restrict__ bt,
-                                                  const double* __restrict__ G, const uint8_t* __restrict__ used,
-                                                  double* __restrict__ M, double* __restrict__ b,
-                                                  const SolveState* st) {
-    assemble_body<NS, (NS <= 6 ? 4 : NS <= 10 ? 2 : 1)>(n, nb, N, Mt, bt, G, used, M, b, st, blockIdx.x);
+// The groups that share a term i (and so read the same M_s[i][.] of every
+// stamp) are kept together on one XCD, whose L2 then serves the repeated
+// reads: workgroup slot x of a launch whose width is a multiple of 8 runs on
+// XCD x % 8, and XCD c takes the c-th of eight contiguous runs of groups.
+// -1 for the slots beyond the groups.
+__device__ __forceinline__ int xcd_item(int x, int n_items) {
+    const int c = x & 7, k = x >> 3, q = n_items >> 3, r = n_items & 7;
+    return k < q + (c < r) ? c * q + min(c, r) + k : -1;
+}
+
+template <int NS, int JC>
+__global__ __launch_bounds__(64 * ASM_WAVES) void k_assemble(int n, int nb, int N,
+                                                             const double* __restrict__ Ms,
+                                                             const double* __restrict__ bs,
+                                                             const double* __restrict__ G,
+                                                             const uint8_t* __restrict__ used,
+                                                             double* __restrict__ M, double* __restrict__ b,
+                                                             const SolveState* st) {
+    const int grp = xcd_item(blockIdx.x, asm_groups<NS>(nb));
+    if (grp >= 0) assemble_group<NS, JC>(n, nb, N, Ms, bs, G, used, M, b, st, grp);
 }
 
 // Batched: only the pairs with NS spatial terms take part in this launch.
 template <int NS>
-__global__ __launch_bounds__(256) void k_assemble_b(const PairDesc* __restrict__ pairs, int nb) {
+__global__ __launch_bounds__(64 * ASM_WAVES) void k_assemble_b(const PairDesc* __restrict__ pairs, int nb) {
     const PairDesc& p = pairs[blockIdx.y];
-    const int L = nb + 1;
-    if (p.ns != NS || (int)blockIdx.x * ASM_ITEMS >= L * L * NS + L * NS) return;
-    assemble_body<NS, 1>(p.n, nb, p.N, p.Mt, p.bt, p.G, p.used, p.A, p.b, p.st, blockIdx.x);
+    const int grp = xcd_item(blockIdx.x, asm_groups<NS>(nb));
+    if (p.ns != NS || grp < 0) return;
+    assemble_group<NS, 1>(p.n, nb, p.N, p.Ms, p.bs, p.G, p.used, p.A, p.b, p.st, grp);
 }
+
+// Launch width of an assembly: the groups, rounded up to a multiple of 8 (see xcd_item).
+template <int NS>
+int asm_width(int nb) { return (asm_groups<NS>(nb) + 7) / 8 * 8; }
 
 
 __device__ __forceinline__ double block_sum(double v, double* red) { return psfm_block_sum(v, red); }
@@ -1912,8 +1949,6 @@ size_t solve_workspace(const psfm_context* ctx, int n) {
     c.take<double>((size_t)ctx->N * ctx->N);
     c.take<double>(ctx->N);
     c.take<double>(psfm::solve_il_doubles(ctx->N));
-    c.take<double>((size_t)n * ctx->L * ctx->L + 1);
-    c.take<double>((size_t)n * ctx->L + 1);
     c.take<double>(ctx->N);                          // 1 / sqrt(diag M)
     c.take<double>((size_t)n * ctx->L + 1);          // residual gradients, stamp-major
     c.take<double>(ctx->N);                          // assembled correction right-hand side
@@ -1967,22 +2002,19 @@ int batch_solve(const psfm_context* ctx, const PairDesc* pairs, const int* stamp
                 int n_stamps_total, int max_n, int max_N, unsigned ns_mask, hipStream_t st) {
     if (n_pairs == 0) return PSFM_OK;
     const psfm_config& cf = ctx->cfg;
-    const int nb = ctx->nb, L = ctx->L;
+    const int nb = ctx->nb;
     const size_t lds = solve_lds_bytes(max_N);
     int rc = solve_lds_grant(lds);
     if (rc) return rc;
     const int nt = std::max(std::max(max_n, max_N), 1);
     const int n_init = (nt + 255) / 256;
-    hipLaunchKernelGGL(k_solve_prep_b, dim3(n_init + 256, n_pairs), dim3(256), 0, st, pairs, n_init,
-                       cf.min_stamps, L);
+    hipLaunchKernelGGL(k_solve_prep_b, dim3(n_init, n_pairs), dim3(256), 0, st, pairs, cf.min_stamps);
     PSFM_HIP_CHECK(hipGetLastError());
     for (int it = 0; it < cf.max_iter; it++) {
 #define PSFM_ASM_B(NSV)                                                                          \
-        if (ns_mask & (1u << NSV)) {                                                             \
-            const int items = L * L * NSV + L * NSV;                                             \
-            hipLaunchKernelGGL(k_assemble_b<NSV>, dim3((items + ASM_ITEMS - 1) / ASM_ITEMS, n_pairs), \
-                               dim3(256), 0, st, pairs, nb);                                      \
-        }
+        if (ns_mask & (1u << NSV))                                                               \
+            hipLaunchKernelGGL(k_assemble_b<NSV>, dim3(asm_width<NSV>(nb), n_pairs),              \
+                               dim3(64 * ASM_WAVES), 0, st, pairs, nb);
         PSFM_ASM_B(1) PSFM_ASM_B(3) PSFM_ASM_B(6) PSFM_ASM_B(10) PSFM_ASM_B(15) PSFM_ASM_B(21)
         PSFM_ASM_B(28)
 #undef PSFM_ASM_B
@@ -2103,8 +2135,6 @@ static int solve_impl(const psfm_context* ctx, int W, int H, const int32_t* stam
     double* M = c.take<double>((size_t)ctx->N * ctx->N);
     double* b = c.take<double>(ctx->N);
     double* ILg = c.take<double>(psfm::solve_il_doubles(ctx->N));
-    double* Mt = c.take<double>((size_t)n_stamps * ctx->L * ctx->L + 1);
-    double* bt = c.take<double>((size_t)n_stamps * ctx->L + 1);
     double* Dg = c.take<double>(ctx->N);
     double* gt = c.take<double>((size_t)n_stamps * ctx->L + 1);
     double* gv = c.take<double>(ctx->N);
@@ -2130,17 +2160,15 @@ static int solve_impl(const psfm_context* ctx, int W, int H, const int32_t* stam
     if (rc) return rc;
     const int nt = std::max(n_stamps, N);
     const int n_init = (nt + 255) / 256;
-    const int tiles = n_stamps > 0 ? (n_stamps + TS_K - 1) / TS_K * ((L * L + L + TS_R - 1) / TS_R) : 0;
     if (ortho && n_stamps > 0)
         hipLaunchKernelGGL(k_ortho_stamps, dim3(n_stamps), dim3(64), 0, st, ctx->kgram_R, nb, L, stamp_M,
                            stamp_b, Mo, bo);
     // the assembly reads the (mapped) sums; the residuals read the originals
-    hipLaunchKernelGGL(k_solve_prep, dim3(n_init + std::min(tiles, 1024)), dim3(256), 0, st, n_init,
-                       n_stamps, N, ns, cf.spatial_order, W, H, cf.min_stamps, L, stamp_xy, stamp_flags,
-                       used, fitted, G, stamp_chi2, coeffs, state, ortho ? Mo : stamp_M,
-                       ortho ? bo : stamp_b, Mt, bt);
+    const double* Ma = ortho ? Mo : stamp_M;
+    const double* ba = ortho ? bo : stamp_b;
+    hipLaunchKernelGGL(k_solve_prep, dim3(n_init), dim3(256), 0, st, n_stamps, N, ns, cf.spatial_order, W,
+                       H, cf.min_stamps, stamp_xy, stamp_flags, used, fitted, G, stamp_chi2, coeffs, state);
     PSFM_HIP_CHECK(hipGetLastError());
-    const int nthreads_asm = L * L * ns + L * ns;
     if (prior && n_stamps > 0) {
         // completed predictions, the 1.05x rule against each stamp's own
         // least-squares kernel, then (warm start -> kernel-sum clip) rounds
@@ -2169,14 +2197,23 @@ static int solve_impl(const psfm_context* ctx, int W, int H, const int32_t* stam
     }
     // one round: assembly, solution (+ refinement), chi2, clip
     auto round = [&]() -> int {
-        const dim3 ag((nthreads_asm + ASM_ITEMS - 1) / ASM_ITEMS);
-        switch (ns) {
+        if (L > 64) {            // the two-kernel form's stamp matrices (up to 128 wide)
+            switch (ns) {
 #define PSFM_ASM_CASE(NSV) \
-    case NSV: hipLaunchKernelGGL(k_assemble<NSV>, ag, dim3(256), 0, st, n_stamps, nb, N, Mt, bt, G, used, M, b, state); break;
-            PSFM_ASM_CASE(1) PSFM_ASM_CASE(3) PSFM_ASM_CASE(6) PSFM_ASM_CASE(10) PSFM_ASM_CASE(15)
-            PSFM_ASM_CASE(21) PSFM_ASM_CASE(28)
+    case NSV: hipLaunchKernelGGL((k_assemble<NSV, 2>), dim3(asm_width<NSV>(nb)), dim3(64 * ASM_WAVES), 0, st, n_stamps, nb, N, Ma, ba, G, used, M, b, state); break;
+                PSFM_ASM_CASE(1) PSFM_ASM_CASE(3) PSFM_ASM_CASE(6)
 #undef PSFM_ASM_CASE
-            default: return PSFM_ERR_UNSUPPORTED;
+                default: return PSFM_ERR_UNSUPPORTED;
+            }
+        } else {
+            switch (ns) {
+#define PSFM_ASM_CASE(NSV) \
+    case NSV: hipLaunchKernelGGL((k_assemble<NSV, 1>), dim3(asm_width<NSV>(nb)), dim3(64 * ASM_WAVES), 0, st, n_stamps, nb, N, Ma, ba, G, used, M, b, state); break;
+                PSFM_ASM_CASE(1) PSFM_ASM_CASE(3) PSFM_ASM_CASE(6) PSFM_ASM_CASE(10) PSFM_ASM_CASE(15)
+                PSFM_ASM_CASE(21) PSFM_ASM_CASE(28)
+#undef PSFM_ASM_CASE
+                default: return PSFM_ERR_UNSUPPORTED;
+            }
         }
         if (penq)
             hipLaunchKernelGGL(k_penalty, dim3(1), dim3(1024), 0, st, N, ns, nb, pen_nb, penq, phi, M,
@@ -2321,8 +2358,6 @@ extern "C" int psfm_solve_norm(const psfm_context* ctx, int W, int H, const int3
     double* M = c.take<double>((size_t)N * N);
     double* b = c.take<double>(N);
     double* ILg = c.take<double>(psfm::solve_il_doubles(N));
-    double* Mt = c.take<double>((size_t)n_stamps * L * L + 1);
-    double* bt = c.take<double>((size_t)n_stamps * L + 1);
     c.take<double>(N);
     c.take<double>((size_t)n_stamps * L + 1);
     c.take<double>(N);
@@ -2343,18 +2378,14 @@ extern "C" int psfm_solve_norm(const psfm_context* ctx, int W, int H, const int3
     if (rc) return rc;
     const int nt = std::max(n_stamps, N);
     const int n_init = (nt + 255) / 256;
-    const int tiles = n_stamps > 0 ? (n_stamps + TS_K - 1) / TS_K * ((L * L + L + TS_R - 1) / TS_R) : 0;
-    hipLaunchKernelGGL(k_solve_prep, dim3(n_init + std::min(tiles, 1024)), dim3(256), 0, st, n_init,
-                       n_stamps, N, ns, cf.spatial_order, W, H, cf.min_stamps, L, stamp_xy, stamp_flags,
-                       used, fitted, G, stamp_chi2, coeffs, state, stamp_M, stamp_b, Mt, bt);
+    hipLaunchKernelGGL(k_solve_prep, dim3(n_init), dim3(256), 0, st, n_stamps, N, ns, cf.spatial_order, W,
+                       H, cf.min_stamps, stamp_xy, stamp_flags, used, fitted, G, stamp_chi2, coeffs, state);
     PSFM_HIP_CHECK(hipGetLastError());
-    const int nthreads_asm = L * L * ns + L * ns;
-    const dim3 ag((nthreads_asm + ASM_ITEMS - 1) / ASM_ITEMS);
     for (int it = 0; it < cf.max_iter; it++) {
         hipLaunchKernelGGL(k_norm_solve, dim3(1), dim3(1024), 0, st, n_stamps, stamp_norm, used, hv, state);
         switch (ns) {
 #define PSFM_ASM_CASE(NSV) \
-    case NSV: hipLaunchKernelGGL(k_assemble<NSV>, ag, dim3(256), 0, st, n_stamps, nb, N, Mt, bt, G, used, M, b, state); break;
+    case NSV: hipLaunchKernelGGL((k_assemble<NSV, 1>), dim3(asm_width<NSV>(nb)), dim3(64 * ASM_WAVES), 0, st, n_stamps, nb, N, stamp_M, stamp_b, G, used, M, b, state); break;
             PSFM_ASM_CASE(1) PSFM_ASM_CASE(3) PSFM_ASM_CASE(6) PSFM_ASM_CASE(10) PSFM_ASM_CASE(15)
             PSFM_ASM_CASE(21) PSFM_ASM_CASE(28)
 #undef PSFM_ASM_CASE
