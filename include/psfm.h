@@ -859,6 +859,28 @@ int psfm_cnn_targets(const psfm_context* ctx, const double* local, int n_stamps,
 int psfm_cnn_local_coeffs(const psfm_context* ctx, const float* ortho, int n_stamps,
                           double* local, void* stream);
 
+/* Training-set standardisation of the prior's targets.  Per component c,
+   mu[c] and sd[c] (the unbiased standard deviation, floored at 1e-12) over
+   the first n_stats rows of target (n x 49 FP32); then for all n rows
+   z = (target - mu) / sd, and the loss weights carried into z coordinates,
+   wz = diag(sd) W diag(sd) divided by its mean diagonal (trace / 49, the
+   trace floored at 1e-30), so that every stamp counts alike in the loss.
+   weight, wz: n x 49 x 49 FP32.  Requires 2 <= n_stats <= n. */
+int psfm_cnn_standardize(const float* target, const float* weight, int n, int n_stats,
+                         float* mu, float* sd, float* z, float* wz, void* stream);
+
+/* Folds the standardisation into the network: fc2's weight rows times sd,
+   its bias sd * b + mu (FP32 master and FP16 copy), so that the network
+   returns the coefficients themselves. */
+int psfm_cnn_fold_output(float* w32, uint16_t* w16, const float* mu, const float* sd, void* stream);
+
+/* Per-sample excess r^T W r, r = pred - target (n x 49 FP32), W = weight[s]
+   (49 x 49): with the weights of psfm_cnn_loss_weights, the chi2/dof excess
+   of the predicted kernel.  pred rows pred_stride (49, or 0: the same row,
+   e.g. a constant predictor, for every sample) apart.  exc: n FP32. */
+int psfm_cnn_excess(const float* pred, int pred_stride, const float* target, const float* weight,
+                    int n, float* exc, void* stream);
+
 /* Human-readable text of a psfm_status value (static storage). */
 const char* psfm_status_string(int status);
 

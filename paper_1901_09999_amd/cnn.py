@@ -101,14 +101,10 @@ class Net:
                                    _stream()), "psfm_cnn_adam")
 
     def fold_output(self, mu: torch.Tensor, sd: torch.Tensor):
-        """Make the network output sd * z + mu directly (z its current output):
-        fc2 rows scaled by sd, bias sd * b + mu; FP16 copy refreshed."""
-        o_w = self.w32.numel() - OUT - OUT * 128
-        W2 = self.w32[o_w:o_w + OUT * 128].view(OUT, 128)
-        b2 = self.w32[o_w + OUT * 128:]
-        W2.mul_(sd[:, None].to(W2.dtype))
-        b2.mul_(sd.to(b2.dtype)).add_(mu.to(b2.dtype))
-        self.w16.copy_(self.w32.to(torch.float16))
+        """psfm_cnn_fold_output: make the network output sd * z + mu directly
+        (z its current output)."""
+        _check(lib().psfm_cnn_fold_output(_ptr(self.w32), _ptr(self.w16), _ptr(mu.contiguous()),
+                                          _ptr(sd.contiguous()), _stream()), "psfm_cnn_fold_output")
 
     def state(self) -> dict:
         return dict(w32=self.w32.cpu().numpy(), m=self.m.cpu().numpy(), v=self.v.cpu().numpy(),
@@ -194,36 +190,46 @@ def make_dataset(n: int, seed: int, spec: synth.StampSetSpec = synth.STAMP_SETS[
                 params={k: np.concatenate([p[k] for p in params])[ok.cpu().numpy()] for k in params[0]})
 
 
-def standardize(data: dict, rows=None) -> dict:
-    """Training view of a dataset: targets z = (c - mu) / sd per component
-    (mu, sd over ``rows``), and the chi2/dof-excess weights carried into z
+def standardize(data: dict, n_stats: Optional[int] = None) -> dict:
+    """Training view of a dataset (psfm_cnn_standardize): targets
+    z = (c - mu) / sd per component (mu, sd over the first ``n_stats`` rows,
+    all by default), and the chi2/dof-excess weights carried into z
     coordinates, W_z = diag(sd) W diag(sd), each divided by its mean
     eigenvalue (trace / 49) so that every stamp counts alike while its well
     constrained kernel directions dominate its term."""
-    T = data["target"] if rows is None else data["target"][rows]
-    mu, sd = T.mean(0), T.std(0).clamp_min(1e-12)
-    z = ((data["target"] - mu) / sd).contiguous()
-    Wz = data["weight"] * sd[None, :, None] * sd[None, None, :]
-    tr = torch.diagonal(Wz, dim1=1, dim2=2).sum(1).clamp_min(1e-30)
-    Wz = (Wz / (tr / OUT)[:, None, None]).contiguous()
+    T, W = data["target"].contiguous(), data["weight"].contiguous()
+    n = T.shape[0]
+    n_stats = n if n_stats is None else n_stats
+    mu = torch.empty(OUT, dtype=torch.float32, device=T.device)
+    sd = torch.empty_like(mu)
+    z = torch.empty_like(T)
+    Wz = torch.empty_like(W)
+    _check(lib().psfm_cnn_standardize(_ptr(T), _ptr(W), n, n_stats, _ptr(mu), _ptr(sd), _ptr(z), _ptr(Wz),
+                                      _stream()), "psfm_cnn_standardize")
     return dict(x=data["x"], target=z, weight=Wz, mu=mu, sd=sd)
 
 
-def evaluate_constant(c: torch.Tensor, target, weight=None) -> float:
-    """The loss of predicting the constant c for every sample."""
-    r = c[None, :] - target
-    if weight is None:
-        return float((r * r).mean())
-    return float(torch.einsum("bi,bij,bj->", r, weight, r)) / r.numel()
+def quad_excess(pred, target, weight) -> torch.Tensor:
+    """psfm_cnn_excess: r^T W r per sample, r = pred - target; ``pred`` is
+    n x 49 or one row of 49 shared by every sample."""
+    target, weight, pred = target.contiguous(), weight.contiguous(), pred.contiguous()
+    n = target.shape[0]
+    exc = torch.empty(n, dtype=torch.float32, device=target.device)
+    _check(lib().psfm_cnn_excess(_ptr(pred), 0 if pred.dim() == 1 else OUT, _ptr(target), _ptr(weight),
+                                 n, _ptr(exc), _stream()), "psfm_cnn_excess")
+    return exc
+
+
+def evaluate_constant(c: torch.Tensor, target, weight) -> float:
+    """The weighted loss of predicting the constant c for every sample."""
+    return float(quad_excess(c.to(torch.float32), target, weight).double().sum()) / target.numel()
 
 
 def excess(net: Net, x, target, weight, batch: int = 1024) -> np.ndarray:
     """Per-stamp chi2/dof excess r^T W r of the network's predicted kernels
     (r the orthonormal-coefficient error, W the stamp's loss weight)."""
-    out = []
-    for s in range(0, x.shape[0], batch):
-        r = net.forward(x[s:s + batch]) - target[s:s + batch]
-        out.append(torch.einsum("bi,bij,bj->b", r, weight[s:s + batch], r))
+    out = [quad_excess(net.forward(x[s:s + batch]), target[s:s + batch], weight[s:s + batch])
+           for s in range(0, x.shape[0], batch)]
     return torch.cat(out).cpu().numpy()
 
 
@@ -284,15 +290,14 @@ def fit_prior(n: int = 200_000, seed: int = 4, epochs: int = 6, batch: int = 256
     t_data = time.perf_counter() - t0
     m = data["x"].shape[0]
     tr_rows, val_rows = slice(0, m - n_val), slice(m - n_val, m)
-    view = standardize(data, tr_rows)
+    view = standardize(data, m - n_val)
     net = Net(seed=seed)
     train_view = {k: view[k][tr_rows] for k in ("x", "target", "weight")}
     hist = train(net, train_view, epochs=epochs, batch=batch, lr=lr, val_frac=0.02, seed=seed, log=log)
     net.fold_output(view["mu"], view["sd"])
     xv, tv, wv = data["x"][val_rows], data["target"][val_rows], data["weight"][val_rows]
     exc = excess(net, xv, tv, wv)
-    r0 = (view["mu"][None, :] - tv)
-    exc_mean = torch.einsum("bi,bij,bj->b", r0, wv, r0).cpu().numpy()
+    exc_mean = quad_excess(view["mu"], tv, wv).cpu().numpy()
     ctx = psfm.Context(psfm.Config(h=10, r=20, S=0, min_stamps=1))
     pred = to_local(ctx, net.forward(xv)).cpu().numpy()
     ks = np.abs(pred[:, 0] / data["local"][val_rows][:, 0].cpu().numpy() - 1)

@@ -673,6 +673,91 @@ int forward_into(const __half* w, const __half* x, int B, const Acts& A, hipStre
     return PSFM_OK;
 }
 
+// ---- training-set statistics and per-sample transforms of the loss
+
+// Per output component c (one workgroup each): the mean and the unbiased
+// standard deviation of target[0..n_stats)[c], two passes with FP64 sums in
+// a fixed order; sd floored at 1e-12.
+__global__ __launch_bounds__(256) void k_col_stats(const float* __restrict__ target, int n_stats,
+                                                   float* __restrict__ mu, float* __restrict__ sd) {
+    __shared__ double red[16];
+    const int c = blockIdx.x;
+    double s = 0.0;
+    for (int r = threadIdx.x; r < n_stats; r += blockDim.x) s += target[(size_t)r * NOUT + c];
+    const double m = psfm_block_sum(s, red) / n_stats;
+    double q = 0.0;
+    for (int r = threadIdx.x; r < n_stats; r += blockDim.x) {
+        const double d = target[(size_t)r * NOUT + c] - m;
+        q += d * d;
+    }
+    const double var = psfm_block_sum(q, red) / (n_stats - 1);
+    if (threadIdx.x == 0) {
+        mu[c] = (float)m;
+        sd[c] = fmaxf((float)sqrt(var), 1e-12f);
+    }
+}
+
+// One wave per sample: z = (target - mu) / sd, and the sample's weight
+// carried into z coordinates, diag(sd) W diag(sd), divided by its mean
+// diagonal (trace / 49, the trace floored at 1e-30).
+__global__ __launch_bounds__(64) void k_standardize(const float* __restrict__ target,
+                                                    const float* __restrict__ weight,
+                                                    const float* __restrict__ mu,
+                                                    const float* __restrict__ sd,
+                                                    float* __restrict__ z, float* __restrict__ wz) {
+    const int s = blockIdx.x, l = threadIdx.x;
+    const float* W = weight + (size_t)s * NOUT * NOUT;
+    float* Wo = wz + (size_t)s * NOUT * NOUT;
+    if (l < NOUT) z[(size_t)s * NOUT + l] = (target[(size_t)s * NOUT + l] - mu[l]) / sd[l];
+    double t = l < NOUT ? (double)(W[l * NOUT + l] * sd[l] * sd[l]) : 0.0;
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+    const float mean_diag = (float)(fmax(t, 1e-30) / NOUT);
+    for (int e = l; e < NOUT * NOUT; e += 64) {
+        const int i = e / NOUT, j = e - i * NOUT;
+        Wo[e] = W[e] * sd[i] * sd[j] / mean_diag;
+    }
+}
+
+// The output layer rescaled so that the network returns sd * out + mu: fc2's
+// weight rows times sd, its bias sd * b + mu; the FP16 copy of those
+// parameters refreshed.
+__global__ __launch_bounds__(256) void k_fold_output(float* __restrict__ w32, __half* __restrict__ w16,
+                                                     const float* __restrict__ mu,
+                                                     const float* __restrict__ sd) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < NOUT * HID + NOUT;
+         e += gridDim.x * blockDim.x) {
+        float v;
+        if (e < NOUT * HID) {
+            v = w32[OFF_F2W + e] * sd[e / HID];
+            w32[OFF_F2W + e] = v;
+            w16[OFF_F2W + e] = __float2half(v);
+        } else {
+            const int o = e - NOUT * HID;
+            v = sd[o] * w32[OFF_F2B + o] + mu[o];
+            w32[OFF_F2B + o] = v;
+            w16[OFF_F2B + o] = __float2half(v);
+        }
+    }
+}
+
+// One wave per sample: r^T W r with r = pred - target (FP64 sums).
+__global__ __launch_bounds__(64) void k_quad_excess(const float* __restrict__ pred, int pred_stride,
+                                                    const float* __restrict__ target,
+                                                    const float* __restrict__ weight,
+                                                    float* __restrict__ exc) {
+    const int s = blockIdx.x, l = threadIdx.x;
+    const float r = l < NOUT ? pred[(size_t)s * pred_stride + l] - target[(size_t)s * NOUT + l] : 0.0f;
+    const float* W = weight + (size_t)s * NOUT * NOUT;
+    double wr = 0.0;                                   // (W r)_l
+    for (int j = 0; j < NOUT; j++) {
+        const float rj = __shfl(r, j);
+        if (l < NOUT) wr += (double)W[l * NOUT + j] * rj;
+    }
+    double q = (double)r * wr;
+    for (int o = 32; o > 0; o >>= 1) q += __shfl_xor(q, o);
+    if (l == 0) exc[s] = (float)q;
+}
+
 }  // namespace
 
 extern "C" size_t psfm_cnn_param_count(void) { return NPARAM; }
@@ -794,6 +879,37 @@ extern "C" int psfm_cnn_local_coeffs(const psfm_context* ctx, const float* ortho
     if (n_stamps == 0) return PSFM_OK;
     hipLaunchKernelGGL(k_ortho_to_coeff, dim3(n_stamps), dim3(64), 0, (hipStream_t)stream,
                        ctx->kgram_R, ctx->nb, ctx->L, ortho, local);
+    PSFM_HIP_CHECK(hipGetLastError());
+    return PSFM_OK;
+}
+
+extern "C" int psfm_cnn_standardize(const float* target, const float* weight, int n, int n_stats,
+                                    float* mu, float* sd, float* z, float* wz, void* stream) {
+    if (!target || !weight || !mu || !sd || !z || !wz || n_stats < 2 || n_stats > n)
+        return PSFM_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_col_stats, dim3(NOUT), dim3(256), 0, st, target, n_stats, mu, sd);
+    hipLaunchKernelGGL(k_standardize, dim3(n), dim3(64), 0, st, target, weight, mu, sd, z, wz);
+    PSFM_HIP_CHECK(hipGetLastError());
+    return PSFM_OK;
+}
+
+extern "C" int psfm_cnn_fold_output(float* w32, uint16_t* w16, const float* mu, const float* sd,
+                                    void* stream) {
+    if (!w32 || !w16 || !mu || !sd) return PSFM_ERR_INVALID_ARG;
+    hipLaunchKernelGGL(k_fold_output, dim3((NOUT * HID + NOUT + 255) / 256), dim3(256), 0,
+                       (hipStream_t)stream, w32, reinterpret_cast<__half*>(w16), mu, sd);
+    PSFM_HIP_CHECK(hipGetLastError());
+    return PSFM_OK;
+}
+
+extern "C" int psfm_cnn_excess(const float* pred, int pred_stride, const float* target,
+                               const float* weight, int n, float* exc, void* stream) {
+    if (n < 0 || (pred_stride != 0 && pred_stride != NOUT)) return PSFM_ERR_INVALID_ARG;
+    if (n == 0) return PSFM_OK;
+    if (!pred || !target || !weight || !exc) return PSFM_ERR_INVALID_ARG;
+    hipLaunchKernelGGL(k_quad_excess, dim3(n), dim3(64), 0, (hipStream_t)stream, pred, pred_stride,
+                       target, weight, exc);
     PSFM_HIP_CHECK(hipGetLastError());
     return PSFM_OK;
 }

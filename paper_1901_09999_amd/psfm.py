@@ -199,6 +199,9 @@ def lib():
             "psfm_cnn_stamp_inputs": (i, [P, P, P, P, i, i, i64, P, i, P, P, P]),
             "psfm_cnn_targets": (i, [P, P, i, P, P]),
             "psfm_cnn_local_coeffs": (i, [P, P, i, P, P]),
+            "psfm_cnn_standardize": (i, [P, P, i, i, P, P, P, P, P]),
+            "psfm_cnn_fold_output": (i, [P, P, P, P, P]),
+            "psfm_cnn_excess": (i, [P, i, P, P, i, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -900,4 +903,5 @@ def exported_symbols() -> Sequence[str]:
             "psfm_cholesky_solve", "psfm_cnn_param_count",
             "psfm_cnn_workspace_bytes", "psfm_cnn_forward", "psfm_cnn_loss_grad",
             "psfm_cnn_loss_weights", "psfm_cnn_adam",
-            "psfm_cnn_stamp_inputs", "psfm_cnn_targets", "psfm_cnn_local_coeffs"]
+            "psfm_cnn_stamp_inputs", "psfm_cnn_targets", "psfm_cnn_local_coeffs",
+            "psfm_cnn_standardize", "psfm_cnn_fold_output", "psfm_cnn_excess"]

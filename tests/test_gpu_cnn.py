@@ -213,7 +213,7 @@ def test_training_reduces_validation_loss():
     data = cnn.make_dataset(12288, 2024, chunk=12288)
     n = data["x"].shape[0]
     tr, val = slice(0, n - 1024), slice(n - 1024, n)
-    view = cnn.standardize(data, tr)
+    view = cnn.standardize(data, n - 1024)
     net = cnn.Net(seed=1)
     xv, zv, wv = view["x"][val], view["target"][val], view["weight"][val]
     before = cnn.evaluate(net, xv, zv, 512, wv)
@@ -231,3 +231,48 @@ def test_training_reduces_validation_loss():
     ks = np.abs(pred[:, 0] / _np(data["local"][val])[:, 0] - 1)
     print(f"median kernel-sum error of the predictions {np.median(ks):.3e}")
     assert np.median(ks) < 0.1
+
+
+def test_standardize_fold_and_excess_against_numpy():
+    """psfm_cnn_standardize (column statistics over a prefix of the rows,
+    z-scores and the weights carried into z coordinates), psfm_cnn_excess
+    (r^T W r per sample, also for a constant predictor) and
+    psfm_cnn_fold_output (the folded network returns sd * out + mu) against
+    FP64 numpy on random SPD weights.  FP32 data with FP64 sums: 1e-5
+    relative; the folded output layer, rounded to FP16 again: 1e-2 of the output
+    scale."""
+    torch, psfm = hip()
+    from paper_1901_09999_amd import cnn
+    rng = np.random.default_rng(3)
+    n, n_stats = 300, 250
+    T = (rng.normal(0, 1, (n, 49)) * rng.uniform(0.1, 5, 49) + rng.normal(0, 3, 49)).astype(np.float32)
+    A = rng.normal(size=(n, 49, 49))
+    W = (A @ A.transpose(0, 2, 1) / 49).astype(np.float32)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    v = cnn.standardize(dict(x=None, target=t(T), weight=t(W)), n_stats)
+    T64, W64 = T.astype(np.float64), W.astype(np.float64)
+    mu, sd = T64[:n_stats].mean(0), T64[:n_stats].std(0, ddof=1)
+    assert np.allclose(_np(v["mu"]), mu, rtol=1e-5, atol=1e-6)
+    assert np.allclose(_np(v["sd"]), sd, rtol=1e-5)
+    z = (T64 - mu) / sd
+    assert np.max(np.abs(_np(v["target"]) - z)) < 1e-5 * np.max(np.abs(z))
+    Wz = W64 * sd[None, :, None] * sd[None, None, :]
+    Wz /= (np.einsum("sii->s", Wz) / 49)[:, None, None]
+    assert np.max(np.abs(_np(v["weight"]) - Wz)) < 1e-5 * np.max(np.abs(Wz))
+    P = rng.normal(size=(n, 49)).astype(np.float32)
+    r = P.astype(np.float64) - T64
+    ref = np.einsum("bi,bij,bj->b", r, W64, r)
+    assert np.allclose(_np(cnn.quad_excess(t(P), t(T), t(W))), ref, rtol=1e-5)
+    c = P[0]
+    rc = c.astype(np.float64)[None, :] - T64
+    refc = np.einsum("bi,bij,bj->b", rc, W64, rc)
+    assert np.allclose(_np(cnn.quad_excess(t(c), t(T), t(W))), refc, rtol=1e-5)
+    assert abs(cnn.evaluate_constant(t(c), t(T), t(W)) / (refc.sum() / T.size) - 1) < 1e-5
+    # the folded network
+    net = cnn.Net(seed=2)
+    x = t(rng.standard_normal((16, 2, 41, 41)).astype(np.float16))
+    out0 = _np(net.forward(x)).astype(np.float64)
+    net.fold_output(v["mu"], v["sd"])
+    out1 = _np(net.forward(x)).astype(np.float64)
+    expect = out0 * _np(v["sd"]) + _np(v["mu"])
+    assert np.max(np.abs(out1 - expect)) < 1e-2 * np.max(np.abs(expect))
