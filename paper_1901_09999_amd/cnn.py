@@ -222,7 +222,8 @@ def quad_excess(pred, target, weight) -> torch.Tensor:
 
 def evaluate_constant(c: torch.Tensor, target, weight) -> float:
     """The weighted loss of predicting the constant c for every sample."""
-    return float(quad_excess(c.to(torch.float32), target, weight).double().sum()) / target.numel()
+    exc = quad_excess(c.to(torch.float32), target, weight).cpu().numpy()
+    return float(np.sum(exc, dtype=np.float64)) / target.numel()
 
 
 def excess(net: Net, x, target, weight, batch: int = 1024) -> np.ndarray:
