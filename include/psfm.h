@@ -135,7 +135,7 @@ typedef struct psfm_config {
     int weight_mode;       /* PSFM_WEIGHT_*: fit weights 1 / V2 (default) or 1 / (V1 + V2) */
     int ortho_basis;       /* 1: psfm_solve works in the orthonormalised basis (FP32 only) */
     int flags;             /* PSFM_SYNC or 0 */
-    int fit_band_rows;     /* stamp rows per fit workgroup: 0 = chosen from r, or 9 or 11 */
+    int fit_band_rows;     /* stamp rows per fit workgroup: 0 = chosen from r, or 7, 9 or 11 */
 } psfm_config;
 
 /* weight_mode.  The fit's pixel weights are the inverse variance of the

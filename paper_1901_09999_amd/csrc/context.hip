@@ -80,8 +80,8 @@ int psfm_create(const psfm_config* cfg, psfm_context** out) {
         return PSFM_ERR_INVALID_ARG;
     if (c.ortho_basis != 0 && c.ortho_basis != 1) return PSFM_ERR_INVALID_ARG;
     if (c.flags & ~PSFM_SYNC) return PSFM_ERR_INVALID_ARG;
-    if (c.fit_band_rows != 0 && c.fit_band_rows != PSFM_FIT_BR_SMALL &&
-        c.fit_band_rows != PSFM_FIT_BR_LARGE)
+    if (c.fit_band_rows != 0 && c.fit_band_rows != PSFM_FIT_BR_SHORT &&
+        c.fit_band_rows != PSFM_FIT_BR_MID && c.fit_band_rows != PSFM_FIT_BR_TALL)
         return PSFM_ERR_UNSUPPORTED;
 
     psfm_context* ctx = new psfm_context();
@@ -93,12 +93,13 @@ int psfm_create(const psfm_config* cfg, psfm_context** out) {
     ctx->L = nb + 1;
     ctx->h = c.half_width;
     ctx->r = c.stamp_half;
-    // fit band: 9 rows up to 41-row stamps (r <= 20: two workgroups' LDS per CU and
-    // short bands, e.g. 9+9+9+9+5 rows at r = 20), 11 rows beyond (fewer bands
-    // per stamp when the stamps are many and large: 11+11+11+11+5 at r = 24);
-    // a caller (a tuner) may pick either height instead
+    // fit band: 7 rows up to 41-row stamps (r <= 20: three workgroups' LDS per CU
+    // at h = 10, which hides the band's latencies better than fewer, taller
+    // bands: 7+7+7+7+7+6 rows at r = 20), 11 rows beyond (fewer bands per stamp
+    // when the stamps are large: 11+11+11+11+5 at r = 24); a caller (a tuner)
+    // may pick any of the three heights instead
     ctx->fit_br = c.fit_band_rows ? c.fit_band_rows
-                                  : c.stamp_half <= 20 ? PSFM_FIT_BR_SMALL : PSFM_FIT_BR_LARGE;
+                                  : c.stamp_half <= 20 ? PSFM_FIT_BR_SHORT : PSFM_FIT_BR_TALL;
     ctx->KW = 2 * c.half_width + 1;
     ctx->T = ctx->KW * ctx->KW;
     const int h = ctx->h, KW = ctx->KW, T = ctx->T;

@@ -74,11 +74,16 @@ __host__ __device__ inline FitLds fit_lds_layout(int h, int r, int nb, int nf, i
     FitLds L;
     int o = 0;
     auto a4 = [](int x) { return (x + 3) / 4 * 4; };   // 16-byte aligned regions
-    L.win = o;  o += a4((BR + 2 * h) * WC);
     L.col = o;  o += a4(nf * BR * WC + SEG + 2 * h + 4);   // slack for the last row-pass loads
+    // The window is dead once the column pass is done, so it shares its
+    // space with the row loop's buffers (at seven-row bands, r = 20, h = 10,
+    // this keeps a workgroup under a third of the CU's LDS: three per CU).
+    const int u0 = o;
+    L.win = u0;
     L.R = o;    o += a4(npad * nb);
     const int blk16 = split ? GC * A16S : GC * A16S / 2;     // floats
     L.At = o;   o += a4(npad * AT_STRIDE > blk16 ? npad * AT_STRIDE : blk16);
+    if (o < u0 + a4((BR + 2 * h) * WC)) o = u0 + a4((BR + 2 * h) * WC);
     L.sw = o;   o += BR * (2 * r + 1);
     L.dt = o;   o += BR * (2 * r + 1);
     L.psi = o;  o += 64;
@@ -784,8 +789,11 @@ int set_fit_lds(size_t lds) {
 // one of the instantiated heights.
 template <int H_>
 int set_fit_lds_ctx(const psfm_context* ctx, size_t lds) {
-    return ctx->fit_br == PSFM_FIT_BR_SMALL ? set_fit_lds<H_, PSFM_FIT_BR_SMALL>(lds)
-                                            : set_fit_lds<H_, PSFM_FIT_BR_LARGE>(lds);
+    switch (ctx->fit_br) {
+        case PSFM_FIT_BR_SHORT: return set_fit_lds<H_, PSFM_FIT_BR_SHORT>(lds);
+        case PSFM_FIT_BR_MID: return set_fit_lds<H_, PSFM_FIT_BR_MID>(lds);
+        default: return set_fit_lds<H_, PSFM_FIT_BR_TALL>(lds);
+    }
 }
 
 template <int H_, int BR>
@@ -813,9 +821,14 @@ int launch_fit_br(const psfm_context* ctx, const FitArgs& a, int n_items, const 
 template <int H_>
 int launch_fit(const psfm_context* ctx, const FitArgs& a, int n_items, const PairDesc* pairs,
                const int* item_pair, int prec, hipStream_t st) {
-    return ctx->fit_br == PSFM_FIT_BR_SMALL
-               ? launch_fit_br<H_, PSFM_FIT_BR_SMALL>(ctx, a, n_items, pairs, item_pair, prec, st)
-               : launch_fit_br<H_, PSFM_FIT_BR_LARGE>(ctx, a, n_items, pairs, item_pair, prec, st);
+    switch (ctx->fit_br) {
+        case PSFM_FIT_BR_SHORT:
+            return launch_fit_br<H_, PSFM_FIT_BR_SHORT>(ctx, a, n_items, pairs, item_pair, prec, st);
+        case PSFM_FIT_BR_MID:
+            return launch_fit_br<H_, PSFM_FIT_BR_MID>(ctx, a, n_items, pairs, item_pair, prec, st);
+        default:
+            return launch_fit_br<H_, PSFM_FIT_BR_TALL>(ctx, a, n_items, pairs, item_pair, prec, st);
+    }
 }
 
 // prec: the context's precision, or PREC_DESIGN for a design-only pass.

@@ -13,8 +13,9 @@
 #define PSFM_HMAX 16          // largest supported kernel half width
 #define PSFM_RMAX 32          // largest supported stamp half width
 #define PSFM_GRAM_COLS 64     // Gram width: nb terms + sqrt(w) + d~ (+ zero padding)
-#define PSFM_FIT_BR_SMALL 9   // fit bands (stamp rows per workgroup): the two heights
-#define PSFM_FIT_BR_LARGE 11  // the fit kernels are built for
+#define PSFM_FIT_BR_SHORT 7   // fit bands (stamp rows per workgroup): the three heights
+#define PSFM_FIT_BR_MID 9     // the fit kernels are built for
+#define PSFM_FIT_BR_TALL 11
 #define PSFM_TILE 64          // output tile side of the image convolution
 #define PSFM_COV_SAMPLES 9    // 3 x 3 kernels for the image pseudo-matrix
 
@@ -26,7 +27,7 @@ struct psfm_context {
     int L;      // per-stamp matrix side (nb + 1)
     int nf;     // distinct 1-D factors (Gaussian j, power e)
     int h, r, KW, T;
-    int fit_br;       // stamp rows per fit workgroup (band): PSFM_FIT_BR_SMALL or _LARGE
+    int fit_br;       // stamp rows per fit workgroup (band): PSFM_FIT_BR_SHORT, _MID or _TALL
     // device tables
     double* kb64;     // [nb][T] full basis taps, FP64 (row v major: [(v+h)*KW + (u+h)])
     float* fac;       // [nf][KW] 1-D factors e-th power x Gaussian j, at offsets -h..h

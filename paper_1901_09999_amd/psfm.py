@@ -247,7 +247,7 @@ class Config:
     weight_mode: int = 0          # WEIGHT_V2 or WEIGHT_V1V2
     ortho_basis: int = 0
     flags: int = 0                # SYNC or 0
-    fit_band_rows: int = 0        # 0 (from r), 9 or 11
+    fit_band_rows: int = 0        # 0 (from r), 7, 9 or 11
 
     @classmethod
     def from_workload(cls, wl, **kw):

@@ -2,8 +2,8 @@
 
 Two tile shapes and two launch parameters are chosen by timing each
 candidate on the batch itself:
-  * the stamp fit's band height (stamp rows per workgroup, 9 or 11: the
-    kernels are built for both), timed on the fit stage alone;
+  * the stamp fit's band height (stamp rows per workgroup, 7, 9 or 11: the
+    kernels are built for all three), timed on the fit stage alone;
   * the fused apply kernel's grid (one workgroup per 64 x 64 tile, or a
     grid-stride loop over a fixed number of workgroups) and the order of the
     pairs in its tile list (as given, smallest first, largest first), timed
@@ -28,7 +28,7 @@ from . import psfm
 
 DEFAULT_GRIDS = (0, 256, 512, 1024, 2048)
 DEFAULT_ORDERS = (0, 1, 2)
-DEFAULT_BAND_ROWS = (9, 11)
+DEFAULT_BAND_ROWS = (7, 9, 11)
 
 
 def cache_path() -> str:

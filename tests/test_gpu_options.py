@@ -141,7 +141,7 @@ def test_sync_returns_device_status():
     assert psfm.read_stats(sol["stats"])["info"] == 1
 
 
-@pytest.mark.parametrize("rows", [9, 11])
+@pytest.mark.parametrize("rows", [7, 9, 11])
 def test_fit_band_rows_parity(rows):
     torch, psfm = hip()
     wl, pair = pair_for("pair512", SEED)
@@ -169,9 +169,9 @@ def test_tuner_choices(tmp_path, monkeypatch):
     ctx = psfm.Context(psfm.Config.from_workload(pairs_h[0][0], S=0))
     dev = [dict(psfm.to_device(p), S=wl.spatial_order) for wl, p in pairs_h]
     rec = tune.choose(ctx, dev, c_out=10, grids=(0, 256), orders=(0, 1), reps=1, use_cache=False)
-    assert rec["fit_band_rows"] in (9, 11) and rec["apply_grid"] in (0, 256) and rec["order"] in (0, 1)
+    assert rec["fit_band_rows"] in (7, 9, 11) and rec["apply_grid"] in (0, 256) and rec["order"] in (0, 1)
     fits = [t for t in rec["table"] if t.get("stage") == "fit"]
-    assert sorted(t["fit_band_rows"] for t in fits) == [9, 11]
+    assert sorted(t["fit_band_rows"] for t in fits) == [7, 9, 11]
     best = min(fits, key=lambda t: t["ms"])
     assert best["fit_band_rows"] == rec["fit_band_rows"]
     assert tune.choose(ctx, dev, c_out=10, use_cache=True)["when"] == rec["when"]     # cached
