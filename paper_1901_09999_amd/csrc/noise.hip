@@ -122,9 +122,34 @@ __global__ __launch_bounds__(NB_T) void k_resample_cov(const double* __restrict_
 
 constexpr int ADD_BLOCKS = 1024;
 
+// One output pixel of the sum (and its share of the variance means).
+__device__ __forceinline__ void add_pixel(double alpha, double beta, float ia, float va, uint8_t ma,
+                                          float ib, float vb, uint8_t mb, float& s, float& vs,
+                                          uint8_t& ms, double& sa, double& na, double& sb, double& nb) {
+    if (!ma) {
+        sa += va;
+        na += 1.0;
+    }
+    if (!mb) {
+        sb += vb;
+        nb += 1.0;
+    }
+    ms = (uint8_t)(ma | mb);
+    if (ms) {
+        s = 0.0f;
+        vs = 0.0f;
+    } else {
+        s = (float)(alpha * (double)ia + beta * (double)ib);
+        vs = (float)(alpha * alpha * (double)va + beta * beta * (double)vb);
+    }
+}
+
 // S = alpha Ia + beta Ib, V_S = alpha^2 Va + beta^2 Vb, mask_S = mask_a |
 // mask_b (S = V_S = 0 there); per workgroup the unmasked variance sums and
-// counts of both inputs (partials[4 b + 0..3], FP64).  Grid-stride over rows.
+// counts of both inputs (partials[4 b + 0..3], FP64).  Grid-stride over rows;
+// with V4 (rows 16-byte aligned) four pixels per thread through 16-byte
+// loads and stores (the masks as 4-byte words), the row's remainder one by one.
+template <bool V4>
 __global__ __launch_bounds__(NB_T) void k_add_images(double alpha, const float* __restrict__ Ia,
                                                      const float* __restrict__ Va,
                                                      const uint8_t* __restrict__ Ma, double beta,
@@ -136,29 +161,35 @@ __global__ __launch_bounds__(NB_T) void k_add_images(double alpha, const float* 
                                                      double* __restrict__ partials) {
     __shared__ double red[16];
     double sa = 0.0, na = 0.0, sb = 0.0, nb = 0.0;
-    for (int y = blockIdx.x; y < H; y += gridDim.x)
-        for (int x = threadIdx.x; x < W; x += NB_T) {
-            const int64_t o = (int64_t)y * pitch + x;
-            const uint8_t ma = Ma[o], mb = Mb[o];
-            const float va = Va[o], vb = Vb[o];
-            if (!ma) {
-                sa += va;
-                na += 1.0;
-            }
-            if (!mb) {
-                sb += vb;
-                nb += 1.0;
-            }
-            const uint8_t m = (uint8_t)(ma | mb);
-            MS[o] = m;
-            if (m) {
-                S[o] = 0.0f;
-                VS[o] = 0.0f;
-            } else {
-                S[o] = (float)(alpha * (double)Ia[o] + beta * (double)Ib[o]);
-                VS[o] = (float)(alpha * alpha * (double)va + beta * beta * (double)vb);
+    const int W4 = V4 ? W / 4 * 4 : 0;
+    for (int y = blockIdx.x; y < H; y += gridDim.x) {
+        const int64_t row = (int64_t)y * pitch;
+        if constexpr (V4) {
+            for (int x = 4 * threadIdx.x; x < W4; x += 4 * NB_T) {
+                const int64_t o = row + x;
+                const float4 ia = *reinterpret_cast<const float4*>(Ia + o);
+                const float4 va = *reinterpret_cast<const float4*>(Va + o);
+                const float4 ib = *reinterpret_cast<const float4*>(Ib + o);
+                const float4 vb = *reinterpret_cast<const float4*>(Vb + o);
+                const uchar4 ma = *reinterpret_cast<const uchar4*>(Ma + o);
+                const uchar4 mb = *reinterpret_cast<const uchar4*>(Mb + o);
+                float4 s, vs;
+                uchar4 ms;
+                add_pixel(alpha, beta, ia.x, va.x, ma.x, ib.x, vb.x, mb.x, s.x, vs.x, ms.x, sa, na, sb, nb);
+                add_pixel(alpha, beta, ia.y, va.y, ma.y, ib.y, vb.y, mb.y, s.y, vs.y, ms.y, sa, na, sb, nb);
+                add_pixel(alpha, beta, ia.z, va.z, ma.z, ib.z, vb.z, mb.z, s.z, vs.z, ms.z, sa, na, sb, nb);
+                add_pixel(alpha, beta, ia.w, va.w, ma.w, ib.w, vb.w, mb.w, s.w, vs.w, ms.w, sa, na, sb, nb);
+                *reinterpret_cast<float4*>(S + o) = s;
+                *reinterpret_cast<float4*>(VS + o) = vs;
+                *reinterpret_cast<uchar4*>(MS + o) = ms;
             }
         }
+        for (int x = W4 + threadIdx.x; x < W; x += NB_T) {
+            const int64_t o = row + x;
+            add_pixel(alpha, beta, Ia[o], Va[o], Ma[o], Ib[o], Vb[o], Mb[o], S[o], VS[o], MS[o], sa, na,
+                      sb, nb);
+        }
+    }
     sa = psfm_block_sum(sa, red);
     na = psfm_block_sum(na, red);
     sb = psfm_block_sum(sb, red);
@@ -179,16 +210,18 @@ __global__ __launch_bounds__(NB_T) void k_add_cov(double alpha, const double* __
                                                   const double* __restrict__ partials, int nblk,
                                                   double* __restrict__ CS, int cs) {
     __shared__ double s_w[2];
+    __shared__ double red[16];
+    // thread t: blocks t, t + NB_T, ... (loads independent of each other),
+    // then the fixed-order workgroup sums
+    double q[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblk; b += NB_T) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) q[k] += partials[4 * b + k];
+    }
+    psfm_block_sum4(q, red);
     if (threadIdx.x == 0) {
-        double sa = 0.0, na = 0.0, sb = 0.0, nb = 0.0;
-        for (int b = 0; b < nblk; b++) {
-            sa += partials[4 * b];
-            na += partials[4 * b + 1];
-            sb += partials[4 * b + 2];
-            nb += partials[4 * b + 3];
-        }
-        s_w[0] = alpha * alpha * (na > 0.0 ? sa / na : 0.0);
-        s_w[1] = beta * beta * (nb > 0.0 ? sb / nb : 0.0);
+        s_w[0] = alpha * alpha * (q[1] > 0.0 ? q[0] / q[1] : 0.0);
+        s_w[1] = beta * beta * (q[3] > 0.0 ? q[2] / q[3] : 0.0);
     }
     __syncthreads();
     const double wa = s_w[0], wb = s_w[1];
@@ -247,8 +280,16 @@ extern "C" int psfm_add_images(double alpha, const float* Ia, const float* Va, c
     hipStream_t st = (hipStream_t)stream;
     double* partials = static_cast<double*>(ws);
     const int nblk = H < ADD_BLOCKS ? H : ADD_BLOCKS;
-    hipLaunchKernelGGL(k_add_images, dim3(nblk), dim3(NB_T), 0, st, alpha, Ia, Va, Ma, beta, Ib, Vb, Mb, W,
-                       H, pitch, S, VS, MS, partials);
+    auto al16 = [](const void* ptr) { return ((uintptr_t)ptr & 15) == 0; };
+    auto al4 = [](const void* ptr) { return ((uintptr_t)ptr & 3) == 0; };
+    const bool v4 = (pitch & 3) == 0 && al16(Ia) && al16(Va) && al16(Ib) && al16(Vb) && al16(S) &&
+                    al16(VS) && al4(Ma) && al4(Mb) && al4(MS);
+    if (v4)
+        hipLaunchKernelGGL(k_add_images<true>, dim3(nblk), dim3(NB_T), 0, st, alpha, Ia, Va, Ma, beta, Ib, Vb,
+                           Mb, W, H, pitch, S, VS, MS, partials);
+    else
+        hipLaunchKernelGGL(k_add_images<false>, dim3(nblk), dim3(NB_T), 0, st, alpha, Ia, Va, Ma, beta, Ib,
+                           Vb, Mb, W, H, pitch, S, VS, MS, partials);
     hipLaunchKernelGGL(k_add_cov, dim3(1), dim3(NB_T), 0, st, alpha, cov_a, cov_a ? cov_a_half : 0, beta,
                        cov_b, cov_b ? cov_b_half : 0, partials, nblk, cov_s, cov_s_half);
     PSFM_HIP_CHECK(hipGetLastError());
