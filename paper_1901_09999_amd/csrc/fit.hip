@@ -564,14 +564,22 @@ __global__ __launch_bounds__(256) void k_fit_band_b(const PairDesc* __restrict__
 }
 
 // Sum of the band partials of each stamp in FP64 and scatter to M_s, b_s, e_s.
+// One workgroup per stamp: the stored lower triangle (rows 0 .. nb + 1 of
+// the partial Gram, nb + 1 being the weighted target) is read row by row
+// (consecutive entries, consecutive lanes), each entry summed over the bands
+// in order into LDS; M_s is then written row-major from LDS (its upper part
+// mirrored), so both the reads and the writes are contiguous.
+constexpr int RED_TRI = (GC + 1) * GC / 2;     // lower-triangle entries of the partial (<= GC rows)
+
 __device__ void fit_reduce_body(const double* __restrict__ part, const int* __restrict__ band_flags,
                                 int nbands, int nb, int npix, double* __restrict__ Ms,
                                 double* __restrict__ bs, double* __restrict__ es,
                                 int32_t* __restrict__ npix_out, int32_t* __restrict__ flags_out,
-                                const int s, const int q, const int nq) {
+                                const int s) {
     const int tid = threadIdx.x;
-    const int L = nb + 1;
+    const int L = nb + 1, R = nb + 2;               // Gram rows: the L unknowns and the target
     __shared__ int s_fl;
+    __shared__ double tri[RED_TRI];                  // entry (r, c), c <= r, at r (r + 1) / 2 + c
     if (tid < 64) {     // the bands' flags, one per lane, OR over the wave
         int f = 0;
         for (int b = tid; b < nbands; b += 64) f |= band_flags[s * nbands + b];
@@ -580,21 +588,19 @@ __device__ void fit_reduce_body(const double* __restrict__ part, const int* __re
     }
     __syncthreads();
     const int fl = s_fl;
-    double* M = Ms + (size_t)s * L * L;
-    double* bv = bs + (size_t)s * L;
     const double* P0 = part + (size_t)s * nbands * GC * GC;
-    // workgroup q of the stamp's nq takes entries [1024 q, 1024 (q + 1)), and
-    // so on every nq-th chunk: four entries per thread, their band partials
-    // loaded together (clamped index beyond L * L); each sum runs over the
-    // bands in order
-    for (int e0 = 4 * 256 * q + tid; e0 < L * L; e0 += 4 * 256 * nq) {
+    const int ntri = R * (R + 1) / 2;
+    // four entries per thread, their band partials loaded together
+    for (int e0 = tid; e0 < ntri; e0 += 4 * 256) {
         double v[4] = {0.0, 0.0, 0.0, 0.0};
         int off[4];
 #pragma unroll
         for (int u = 0; u < 4; u++) {
-            const int e = e0 + 256 * u, ec = e < L * L ? e : 0;
-            const int i = ec / L, j = ec - i * L;
-            off[u] = (i > j ? i : j) * GC + (i > j ? j : i);
+            const int e = min(e0 + 256 * u, ntri - 1);
+            int r = (int)((sqrtf(8.0f * e + 1.0f) - 1.0f) * 0.5f);
+            while ((r + 1) * (r + 2) / 2 <= e) r++;
+            while (r * (r + 1) / 2 > e) r--;
+            off[u] = r * GC + (e - r * (r + 1) / 2);
         }
         if (!fl) {
             for (int b = 0; b < nbands; b++) {
@@ -605,16 +611,21 @@ __device__ void fit_reduce_body(const double* __restrict__ part, const int* __re
         }
 #pragma unroll
         for (int u = 0; u < 4; u++)
-            if (e0 + 256 * u < L * L) M[e0 + 256 * u] = v[u];
+            if (e0 + 256 * u < ntri) tri[e0 + 256 * u] = v[u];
     }
-    for (int i = tid; q == nq - 1 && i <= L; i += 256) {
-        double v = 0.0;
-        if (!fl)
-            for (int b = 0; b < nbands; b++) v += P0[(size_t)b * GC * GC + (nb + 1) * GC + i];
-        if (i < L) bv[i] = v;
+    __syncthreads();
+    double* M = Ms + (size_t)s * L * L;
+    for (int e = tid; e < L * L; e += 256) {
+        const int i = e / L, j = e - i * L;
+        const int r = i > j ? i : j, c = i > j ? j : i;
+        M[e] = tri[r * (r + 1) / 2 + c];
+    }
+    for (int i = tid; i <= L; i += 256) {
+        const double v = tri[(R - 1) * R / 2 + i];   // row nb + 1: b_i, then e at i = L
+        if (i < L) bs[(size_t)s * L + i] = v;
         else es[s] = v;
     }
-    if (tid == 0 && q == 0) {
+    if (tid == 0) {
         npix_out[s] = fl ? 0 : npix;
         flags_out[s] = fl;
     }
@@ -626,19 +637,16 @@ __global__ __launch_bounds__(256) void k_fit_reduce(const double* __restrict__ p
                                                     double* __restrict__ bs, double* __restrict__ es,
                                                     int32_t* __restrict__ npix_out,
                                                     int32_t* __restrict__ flags_out) {
-    fit_reduce_body(part, band_flags, nbands, nb, npix, Ms, bs, es, npix_out, flags_out, blockIdx.x,
-                    blockIdx.y, gridDim.y);
+    fit_reduce_body(part, band_flags, nbands, nb, npix, Ms, bs, es, npix_out, flags_out, blockIdx.x);
 }
 
-// Workgroups per stamp of the reduction: one 1024-entry chunk of L x L each.
-inline int reduce_parts(const psfm_context* ctx) { return (ctx->L * ctx->L + 1023) / 1024; }
 
 __global__ __launch_bounds__(256) void k_fit_reduce_b(const PairDesc* __restrict__ pairs,
                                                       const int* __restrict__ stamp_pair, int nbands,
                                                       int nb, int npix) {
     const PairDesc& pd = pairs[stamp_pair[blockIdx.x]];
     fit_reduce_body(pd.part, pd.bflags, nbands, nb, npix, pd.Ms, pd.bs, pd.es, pd.npix, pd.flags,
-                    blockIdx.x - pd.stamp_off, blockIdx.y, gridDim.y);
+                    blockIdx.x - pd.stamp_off);
 }
 
 // Per-stamp sums of the two-kernel form (Section 2, Eqs. 3-6 with the I2
@@ -879,7 +887,7 @@ int batch_fit(const psfm_context* ctx, const PairDesc* pairs, const int* item_pa
     int rc = dispatch_fit(ctx, base_fit_args(ctx), n_items, pairs, item_pair, st);
     if (rc) return rc;
     const int npix = (2 * ctx->r + 1) * (2 * ctx->r + 1);
-    hipLaunchKernelGGL(k_fit_reduce_b, dim3(n_stamps, reduce_parts(ctx)), dim3(256), 0, st, pairs,
+    hipLaunchKernelGGL(k_fit_reduce_b, dim3(n_stamps), dim3(256), 0, st, pairs,
                        stamp_pair, fit_bands(ctx), ctx->nb, npix);
     PSFM_HIP_CHECK(hipGetLastError());
     return PSFM_OK;
@@ -948,7 +956,7 @@ extern "C" int psfm_fit_stamps(const psfm_context* ctx, const float* I1, const f
     int rc = dispatch_fit(ctx, a, n_stamps * a.nbands, nullptr, nullptr, st);
     if (rc != PSFM_OK) return rc;
     const int npix = (2 * ctx->r + 1) * (2 * ctx->r + 1);
-    hipLaunchKernelGGL(k_fit_reduce, dim3(n_stamps, reduce_parts(ctx)), dim3(256), 0, st, part, bflags,
+    hipLaunchKernelGGL(k_fit_reduce, dim3(n_stamps), dim3(256), 0, st, part, bflags,
                        psfm::fit_bands(ctx), ctx->nb, npix, stamp_M, stamp_b, stamp_e, stamp_npix,
                        stamp_flags);
     PSFM_HIP_CHECK(hipGetLastError());
