@@ -179,6 +179,7 @@ void lay_out(const psfm_context* ctx, const psfm_pair* q, const int* order, int 
         d.cov_avg = c.take<double>((size_t)z.Rw * z.Rw);
         d.sub_part = c.take<double>((size_t)4 * z.ntx * z.nty);
         d.ptaps = c.take<float>((size_t)z.npatch * psfm::patch_taps_floats(ctx->h));
+        d.cellK = c.take<double>((size_t)PSFM_COV_SAMPLES * (2 * ctx->h + 1) * (2 * ctx->h + 1));
         d.patch_off = patch_off;
         patch_off += z.npatch;
         d.tiles_done = Lo.counters + k;

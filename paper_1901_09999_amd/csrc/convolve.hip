@@ -504,8 +504,10 @@ int dispatch_conv_pair(const float* I, const float* V, const uint8_t* M, int W, 
 // the kernel rows that overlap (partial sums added in a fixed order).  The
 // kernel's rows sit in LDS with 2h zeros either side, so every lane runs
 // the same 2h + 1 taps per kernel row.
+// Kpre: the cell's kernel realised beforehand (the batch), else realised here.
 __device__ void cov_auto_body(const double* __restrict__ a, const BasisArgs& B, int W, int H,
-                              double* __restrict__ out, const int j, const int ry) {
+                              double* __restrict__ out, const int j, const int ry,
+                              const double* __restrict__ Kpre = nullptr) {
     __shared__ RealiseLds sh;
     __shared__ double Kd[(2 * PSFM_HMAX + 1) * (2 * PSFM_HMAX + 1)];
     __shared__ double Kr[(2 * PSFM_HMAX + 1) * (6 * PSFM_HMAX + 1)];
@@ -513,9 +515,14 @@ __device__ void cov_auto_body(const double* __restrict__ a, const BasisArgs& B, 
     __shared__ double red[16];
     const int h = B.h, KW = 2 * h + 1, T = KW * KW, E = 4 * h + 1, RW = 6 * h + 1;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int jx = j % 3, jy = j / 3;
-    const int cx0 = jx * W / 3, cx1 = (jx + 1) * W / 3, cy0 = jy * H / 3, cy1 = (jy + 1) * H / 3;
-    realise_kernel(B, a, 0.5 * (cx0 + cx1 - 1), 0.5 * (cy0 + cy1 - 1), W, H, sh, Kd);
+    if (Kpre) {
+        for (int t = tid; t < T; t += 256) Kd[t] = Kpre[(size_t)j * T + t];
+        __syncthreads();
+    } else {
+        const int jx = j % 3, jy = j / 3;
+        const int cx0 = jx * W / 3, cx1 = (jx + 1) * W / 3, cy0 = jy * H / 3, cy1 = (jy + 1) * H / 3;
+        realise_kernel(B, a, 0.5 * (cx0 + cx1 - 1), 0.5 * (cy0 + cy1 - 1), W, H, sh, Kd);
+    }
     double s2 = 0.0;
     for (int t = tid; t < T; t += 256) s2 += Kd[t] * Kd[t];
     const double sumk2 = psfm_block_sum(s2, red);
@@ -591,14 +598,31 @@ __global__ __launch_bounds__(256) void k_cov_mix(const double* __restrict__ A, i
     cov_mix_body(A, h, cov_in, c_in, samples, blockIdx.x, blockIdx.y);
 }
 
-// Batched: the autocorrelation goes straight to the samples of a pair with
-// an uncorrelated input, else to its cov_auto buffer for k_cov_mix_b.
+// Batched: each cell kernel of each pair realised once (the same function,
+// so the same values as a workgroup of k_cov_auto realises), then the
+// autocorrelation rows read it; they go straight to the samples of a pair
+// with an uncorrelated input, else to its cov_auto buffer for k_cov_mix_b.
+__global__ __launch_bounds__(256) void k_cell_kernels_b(const PairDesc* __restrict__ pairs, BasisArgs B0) {
+    __shared__ RealiseLds sh;
+    __shared__ double Kd[(2 * PSFM_HMAX + 1) * (2 * PSFM_HMAX + 1)];
+    const PairDesc& p = pairs[blockIdx.y];
+    BasisArgs B = B0;
+    B.ns = p.ns;
+    B.S = p.S;
+    const int j = blockIdx.x, W = p.W, H = p.H, T = (2 * B.h + 1) * (2 * B.h + 1);
+    const int jx = j % 3, jy = j / 3;
+    const int cx0 = jx * W / 3, cx1 = (jx + 1) * W / 3, cy0 = jy * H / 3, cy1 = (jy + 1) * H / 3;
+    realise_kernel(B, p.coeffs, 0.5 * (cx0 + cx1 - 1), 0.5 * (cy0 + cy1 - 1), W, H, sh, Kd);
+    for (int t = threadIdx.x; t < T; t += 256) p.cellK[(size_t)j * T + t] = Kd[t];
+}
+
 __global__ __launch_bounds__(256) void k_cov_auto_b(const PairDesc* __restrict__ pairs, BasisArgs B0) {
     const PairDesc& p = pairs[blockIdx.z];
     BasisArgs B = B0;
     B.ns = p.ns;
     B.S = p.S;
-    cov_auto_body(p.coeffs, B, p.W, p.H, p.cov1 ? p.cov_auto : p.cov_samples, blockIdx.x, blockIdx.y);
+    cov_auto_body(p.coeffs, B, p.W, p.H, p.cov1 ? p.cov_auto : p.cov_samples, blockIdx.x, blockIdx.y,
+                  p.cellK);
 }
 
 __global__ __launch_bounds__(256) void k_cov_mix_b(const PairDesc* __restrict__ pairs, int h) {
@@ -1207,6 +1231,8 @@ int batch_apply(const psfm_context* ctx, const PairDesc* pairs, const int* tile_
     }
     if (parts & 1) {
         const int E = 4 * ctx->h + 1;
+        hipLaunchKernelGGL(k_cell_kernels_b, dim3(PSFM_COV_SAMPLES, n_pairs), dim3(256), 0, st, pairs,
+                           basis_args_of(ctx));
         hipLaunchKernelGGL(k_cov_auto_b, dim3(PSFM_COV_SAMPLES, E, n_pairs), dim3(256), 0, st,
                            pairs, basis_args_of(ctx));
         if (max_cov_in >= 0) {      // some pair has a correlated input

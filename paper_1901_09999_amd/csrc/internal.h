@@ -114,6 +114,7 @@ struct PairDesc {
     double* cov_avg;
     double* sub_part;                // [tiles][4] variance sums of the tiles
     float* ptaps;                    // batch: per patch, FP32 taps K, f K^2 and the BAD radius
+    double* cellK;                   // batch: the pseudo-matrix cells' kernels, PSFM_COV_SAMPLES x T (FP64)
                                      // (psfm::patch_taps_floats each); null: realised per tile
     unsigned int* tiles_done;        // tiles finished (batch completion counter)
     uint64_t* t_done;                // completion time stamp (nullable)
