@@ -1004,12 +1004,37 @@ __global__ __launch_bounds__(256) void k_realise_b(const PairDesc* __restrict__ 
     }
     wave_sync_lds();
     double* K = Kd[w];
-    for (int t = lane; t < T; t += 64) {
-        const int v = t / KW, u = t - v * KW;
-        double k4[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-        for (int j = 0; j < nb; j++) k4[j & 3] += gam[w][j] * F[rf[j] * KW + u] * F[cf[j] * KW + v];
-        K[t] = (k4[0] + k4[1]) + (k4[2] + k4[3]);
+    {
+        // the lane's NT taps t = lane + 64 k at once, the terms in the outer
+        // loop (each term's coefficient and factor rows read once for all of
+        // them); per tap the same sums in the same order as realise_kernel
+        // (term j into k4[j % 4]), so the same values
+        constexpr int NT = (T + 63) / 64;
+        double k4[NT][4];
+        int uo[NT], vo[NT];
+#pragma unroll
+        for (int k = 0; k < NT; k++) {
+            const int t = min(lane + 64 * k, T - 1);
+            vo[k] = t / KW;
+            uo[k] = t - vo[k] * KW;
+            k4[k][0] = k4[k][1] = k4[k][2] = k4[k][3] = 0.0;
+        }
+        for (int j0 = 0; j0 < nb; j0 += 4) {
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int j = j0 + r;
+                if (j < nb) {
+                    const double g = gam[w][j];
+                    const double* Fr = F + rf[j] * KW;
+                    const double* Fc = F + cf[j] * KW;
+#pragma unroll
+                    for (int k = 0; k < NT; k++) k4[k][r] += g * Fr[uo[k]] * Fc[vo[k]];
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NT; k++)
+            if (lane + 64 * k < T) K[lane + 64 * k] = (k4[k][0] + k4[k][1]) + (k4[k][2] + k4[k][3]);
     }
     wave_sync_lds();
     // kernel_stats' sums: lane partials over taps lane + 64 j, then the
