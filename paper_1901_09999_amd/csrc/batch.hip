@@ -12,8 +12,8 @@
 //                                     chi2 of all stamps, clip per pair
 //   k_realise_b                       patch kernels of all pairs: FP32 taps and
 //                                     BAD radii for the tile pass (stage 2)
-//   k_cov_auto_b / k_cov_mix_b /      pseudo-matrices of the convolved images
-//   k_cov_finish_b                    (stage 2)
+//   k_cell_kernels_b / k_cov_auto_b / pseudo-matrices of the convolved images
+//   k_cov_mix_b / k_cov_finish_b      (stage 2; each cell kernel realised once)
 //   k_match_tiles_b                   (stage 3) fused convolution + difference over the
 //                                     tiles of all pairs (grid-stride loop);
 //                                     per-pair C_D and completion time
