@@ -32,13 +32,14 @@ struct psfm_batch {
     int n_pairs;
     int n_items, n_stamps, n_tiles, n_patches;
     int max_n, max_N, max_cov_in;
-    unsigned ns_mask;
+    int ns_off[psfm::PSFM_BATCH_NS_MAX + 1], ns_cnt[psfm::PSFM_BATCH_NS_MAX + 1];
     psfm_batch_tuning tuning;
     PairDesc* d_pairs;          // device (in the workspace)
     int* d_item_pair;
     int* d_stamp_pair;
     int* d_tile_pair;
     int* d_patch_pair;
+    int* d_ns_pairs;
     unsigned* d_counters;
     uint64_t* times;
     hipGraph_t graph;
@@ -98,6 +99,7 @@ struct Layout {
     int* stamp_pair;
     int* tile_pair;
     int* patch_pair;
+    int* ns_pairs;
     unsigned* counters;
     std::vector<PairDesc> desc;
     size_t bytes;
@@ -119,6 +121,7 @@ void lay_out(const psfm_context* ctx, const psfm_pair* q, const int* order, int 
     Lo.stamp_pair = c.take<int>(Lo.n_stamps + 1);
     Lo.tile_pair = c.take<int>(Lo.n_tiles + 1);
     Lo.patch_pair = c.take<int>(Lo.n_patches + 1);
+    Lo.ns_pairs = c.take<int>(n + 1);
     Lo.counters = c.take<unsigned>(n + 1);
     Lo.desc.assign(n, PairDesc{});
     int band_off = 0, stamp_off = 0, tile_off = 0, patch_off = 0;
@@ -243,7 +246,6 @@ extern "C" int psfm_batch_plan(const psfm_context* ctx, const psfm_pair* pairs, 
     std::vector<int> item_pair(Lo.n_items + 1, 0), stamp_pair(Lo.n_stamps + 1, 0),
         tile_pair(Lo.n_tiles + 1, 0), patch_pair(Lo.n_patches + 1, 0);
     int max_n = 0, max_N = 0, max_cov_in = -1;   // -1: no pair has a correlated input
-    unsigned ns_mask = 0;
     for (int k = 0; k < n_pairs; k++) {
         const PairDesc& d = Lo.desc[k];
         const int nbands = psfm::fit_bands(ctx);
@@ -255,8 +257,25 @@ extern "C" int psfm_batch_plan(const psfm_context* ctx, const psfm_pair* pairs, 
         max_n = std::max(max_n, d.n);
         max_N = std::max(max_N, d.N);
         max_cov_in = std::max(max_cov_in, d.cov1 ? d.cov1_half : -1);
-        ns_mask |= 1u << d.ns;
         if (times) Lo.desc[k].t_done = times + 1 + k;
+    }
+    // the pairs of each spatial-term count, for the assembly launches
+    int ns_off[psfm::PSFM_BATCH_NS_MAX + 1] = {}, ns_cnt[psfm::PSFM_BATCH_NS_MAX + 1] = {};
+    std::vector<int> ns_pairs(n_pairs + 1, 0);
+    for (int k = 0; k < n_pairs; k++) {
+        if (Lo.desc[k].ns < 1 || Lo.desc[k].ns > psfm::PSFM_BATCH_NS_MAX) return PSFM_ERR_UNSUPPORTED;
+        ns_cnt[Lo.desc[k].ns]++;
+    }
+    for (int v = 1, o = 0; v <= psfm::PSFM_BATCH_NS_MAX; v++) {
+        ns_off[v] = o;
+        o += ns_cnt[v];
+    }
+    {
+        int fill[psfm::PSFM_BATCH_NS_MAX + 1] = {};
+        for (int k = 0; k < n_pairs; k++) {
+            const int v = Lo.desc[k].ns;
+            ns_pairs[ns_off[v] + fill[v]++] = k;
+        }
     }
     if (psfm::solve_lds_bytes(max_N) > 140 * 1024) return PSFM_ERR_UNSUPPORTED;
     hipStream_t st = (hipStream_t)stream;
@@ -269,6 +288,8 @@ extern "C" int psfm_batch_plan(const psfm_context* ctx, const psfm_pair* pairs, 
     PSFM_HIP_CHECK(hipMemcpyAsync(Lo.tile_pair, tile_pair.data(), sizeof(int) * tile_pair.size(),
                                   hipMemcpyHostToDevice, st));
     PSFM_HIP_CHECK(hipMemcpyAsync(Lo.patch_pair, patch_pair.data(), sizeof(int) * patch_pair.size(),
+                                  hipMemcpyHostToDevice, st));
+    PSFM_HIP_CHECK(hipMemcpyAsync(Lo.ns_pairs, ns_pairs.data(), sizeof(int) * ns_pairs.size(),
                                   hipMemcpyHostToDevice, st));
     PSFM_HIP_CHECK(hipStreamSynchronize(st));
     // grant dynamic LDS now, so that a later capture launches only kernels
@@ -287,13 +308,15 @@ extern "C" int psfm_batch_plan(const psfm_context* ctx, const psfm_pair* pairs, 
     b->max_n = max_n;
     b->max_N = max_N;
     b->max_cov_in = max_cov_in;
-    b->ns_mask = ns_mask;
+    std::copy(ns_off, ns_off + psfm::PSFM_BATCH_NS_MAX + 1, b->ns_off);
+    std::copy(ns_cnt, ns_cnt + psfm::PSFM_BATCH_NS_MAX + 1, b->ns_cnt);
     b->tuning = tu;
     b->d_pairs = Lo.pairs;
     b->d_item_pair = Lo.item_pair;
     b->d_stamp_pair = Lo.stamp_pair;
     b->d_tile_pair = Lo.tile_pair;
     b->d_patch_pair = Lo.patch_pair;
+    b->d_ns_pairs = Lo.ns_pairs;
     b->d_counters = Lo.counters;
     b->times = times;
     *out = b;
@@ -312,7 +335,7 @@ extern "C" int psfm_batch_run_stage(psfm_batch* b, int stage, void* stream) {
     }
     if (stage == 1)
         return psfm::batch_solve(b->ctx, b->d_pairs, b->d_stamp_pair, b->n_pairs, b->n_stamps,
-                                 b->max_n, b->max_N, b->ns_mask, st);
+                                 b->max_n, b->max_N, b->d_ns_pairs, b->ns_off, b->ns_cnt, st);
     return psfm::batch_apply(b->ctx, b->d_pairs, b->d_tile_pair, b->n_pairs, b->n_tiles,
                              b->d_patch_pair, b->n_patches, b->max_cov_in, b->tuning.apply_grid,
                              stage == 2 ? 1 : 2, st);

@@ -172,8 +172,13 @@ int check_hip(hipError_t e);
 // maps are device arrays.
 int batch_fit(const psfm_context* ctx, const PairDesc* pairs, const int* item_pair,
               const int* stamp_pair, int n_items, int n_stamps, hipStream_t st);
+// ns_pairs (device): the pair indices grouped by spatial-term count; the
+// pairs with ns terms are ns_pairs[ns_off[ns] .. ns_off[ns] + ns_cnt[ns])
+// (host tables indexed by ns, PSFM_BATCH_NS_MAX + 1 entries).
+constexpr int PSFM_BATCH_NS_MAX = 28;
 int batch_solve(const psfm_context* ctx, const PairDesc* pairs, const int* stamp_pair, int n_pairs,
-                int n_stamps_total, int max_n, int max_N, unsigned ns_mask, hipStream_t st);
+                int n_stamps_total, int max_n, int max_N, const int* ns_pairs, const int* ns_off,
+                const int* ns_cnt, hipStream_t st);
 // parts: 1 = the pseudo-matrices, 2 = the fused convolution / difference pass, 3 = both.
 int batch_apply(const psfm_context* ctx, const PairDesc* pairs, const int* tile_pair, int n_pairs,
                 int n_tiles, const int* patch_pair, int n_patches, int max_cov_in, int conv_grid,

@@ -273,10 +273,11 @@ __global__ __launch_bounds__(64 * ASM_WAVES) void k_assemble(int n, int nb, int 
     if (grp >= 0) assemble_group<NS, JC>(n, nb, N, Ms, bs, G, used, M, b, st, grp);
 }
 
-// Batched: only the pairs with NS spatial terms take part in this launch.
+// Batched: the launch covers the pairs with NS spatial terms, listed in plist.
 template <int NS>
-__global__ __launch_bounds__(64 * ASM_WAVES) void k_assemble_b(const PairDesc* __restrict__ pairs, int nb) {
-    const PairDesc& p = pairs[blockIdx.y];
+__global__ __launch_bounds__(64 * ASM_WAVES) void k_assemble_b(const PairDesc* __restrict__ pairs,
+                                                               const int* __restrict__ plist, int nb) {
+    const PairDesc& p = pairs[plist[blockIdx.y]];
     const int grp = xcd_item(blockIdx.x, asm_groups<NS>(nb));
     if (p.ns != NS || grp < 0) return;
     assemble_group<NS, 1>(p.n, nb, p.N, p.Ms, p.bs, p.G, p.used, p.A, p.b, p.st, grp);
@@ -1999,7 +2000,8 @@ size_t solve_il_doubles(int N) { return (size_t)IV_DOUBLES * ((N + CH_NB - 1) / 
 // pairs (blockIdx.y or one workgroup per pair); pairs that converged or
 // failed idle through the remaining rounds.
 int batch_solve(const psfm_context* ctx, const PairDesc* pairs, const int* stamp_pair, int n_pairs,
-                int n_stamps_total, int max_n, int max_N, unsigned ns_mask, hipStream_t st) {
+                int n_stamps_total, int max_n, int max_N, const int* ns_pairs, const int* ns_off,
+                const int* ns_cnt, hipStream_t st) {
     if (n_pairs == 0) return PSFM_OK;
     const psfm_config& cf = ctx->cfg;
     const int nb = ctx->nb;
@@ -2012,9 +2014,9 @@ int batch_solve(const psfm_context* ctx, const PairDesc* pairs, const int* stamp
     PSFM_HIP_CHECK(hipGetLastError());
     for (int it = 0; it < cf.max_iter; it++) {
 #define PSFM_ASM_B(NSV)                                                                          \
-        if (ns_mask & (1u << NSV))                                                               \
-            hipLaunchKernelGGL(k_assemble_b<NSV>, dim3(asm_width<NSV>(nb), n_pairs),              \
-                               dim3(64 * ASM_WAVES), 0, st, pairs, nb);
+        if (ns_cnt[NSV] > 0)                                                                     \
+            hipLaunchKernelGGL(k_assemble_b<NSV>, dim3(asm_width<NSV>(nb), ns_cnt[NSV]),          \
+                               dim3(64 * ASM_WAVES), 0, st, pairs, ns_pairs + ns_off[NSV], nb);
         PSFM_ASM_B(1) PSFM_ASM_B(3) PSFM_ASM_B(6) PSFM_ASM_B(10) PSFM_ASM_B(15) PSFM_ASM_B(21)
         PSFM_ASM_B(28)
 #undef PSFM_ASM_B
