@@ -212,6 +212,8 @@ int psfm_create(const psfm_config* cfg, psfm_context** out) {
     float* d_fac = layout.take<float>(fac.size());
     int* d_rowf = layout.take<int>(nb);
     int* d_colf = layout.take<int>(nb);
+    int* d_rorder = layout.take<int>(nb);
+    int* d_rstart = layout.take<int>(nf + 1);
     float* d_psi = layout.take<float>(nb);
     float* d_z = layout.take<float>(nb);
     double* d_fac64 = layout.take<double>(fac64.size());
@@ -230,6 +232,8 @@ int psfm_create(const psfm_config* cfg, psfm_context** out) {
     ctx->fac = rebase(d_fac);
     ctx->term_rowf = rebase(d_rowf);
     ctx->term_colf = rebase(d_colf);
+    ctx->term_rorder = rebase(d_rorder);
+    ctx->row_start = rebase(d_rstart);
     ctx->term_psi = rebase(d_psi);
     ctx->term_z = rebase(d_z);
     ctx->fac64 = rebase(d_fac64);
@@ -241,6 +245,18 @@ int psfm_create(const psfm_config* cfg, psfm_context** out) {
     if (e == hipSuccess) e = hipMemcpy(ctx->fac, fac.data(), fac.size() * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ctx->term_rowf, rowf.data(), nb * sizeof(int), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ctx->term_colf, colf.data(), nb * sizeof(int), hipMemcpyHostToDevice);
+    {
+        // the terms grouped by row factor (stable: increasing i within a group)
+        std::vector<int> rorder(nb), rstart(nf + 1, 0);
+        for (int i = 0; i < nb; i++) rstart[rowf[i] + 1]++;
+        for (int f = 0; f < nf; f++) rstart[f + 1] += rstart[f];
+        std::vector<int> fill(rstart.begin(), rstart.end() - 1);
+        for (int i = 0; i < nb; i++) rorder[fill[rowf[i]]++] = i;
+        if (e == hipSuccess)
+            e = hipMemcpy(ctx->term_rorder, rorder.data(), nb * sizeof(int), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(ctx->row_start, rstart.data(), (nf + 1) * sizeof(int), hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess) e = hipMemcpy(ctx->term_psi, psi.data(), nb * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ctx->term_z, z.data(), nb * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ctx->fac64, fac64.data(), fac64.size() * sizeof(double), hipMemcpyHostToDevice);

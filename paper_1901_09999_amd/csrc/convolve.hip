@@ -49,6 +49,8 @@ struct BasisArgs {
     const float* z;        // [nb]
     const int* rowf;       // [nb]
     const int* colf;       // [nb]
+    const int* rorder;     // [nb] terms grouped by row factor (increasing i within one)
+    const int* rstart;     // [nf + 1] group starts in rorder
     int nb, nf, ns, S, h;
 };
 
@@ -57,13 +59,23 @@ struct RealiseLds {
     double F[32 * (2 * PSFM_HMAX + 1)];
     double gam[64];
     int rf[64], cf[64];
+    int ro[64], rs[33];
 };
+
+// Taps per thread of the regrouped realisation (a 256-thread workgroup, up to 33 x 33 taps).
+constexpr int RK_MAX = ((2 * PSFM_HMAX + 1) * (2 * PSFM_HMAX + 1) + 255) / 256;
 
 // K(u, v) = sum_i alpha_i(x, y) k_i(u, v) in FP64, evaluated through the
 // separable factors: with k_i = psi_i f_{rowf}(u) f_{colf}(v) - z_i k_0,
 //   K = sum_i gamma_i f_{rowf_i}(u) f_{colf_i}(v),
 //   gamma_i = alpha_i psi_i (i >= 1),  gamma_0 = psi_0 (alpha_0 - sum_i z_i alpha_i).
-// Kd receives [(v+h)*KW + (u+h)].  All threads of the block call it.
+// When the factors are no more than the kernel side (nf <= 2h + 1), the
+// terms are regrouped by row factor first:
+//   C_r(v) = sum over the terms i with f_{rowf_i} = f_r (increasing i) of gamma_i f_{colf_i}(v),
+//   K(u, v) = sum_r f_r(u) C_r(v)  (increasing r),
+// each sum an FMA chain from zero (the table C sits in Kd's space until the
+// taps are stored), which is nf instead of nb products per tap.
+// Kd receives [(v+h)*KW + (u+h)].  All threads of the block (256) call it.
 // skip0: term 0 takes no coefficient (the sum over the zero-sum terms only,
 // as in the kernel applied to I2 in the two-kernel form; a then points
 // ns coefficients before that kernel's first term).
@@ -71,6 +83,8 @@ __device__ void realise_kernel(const BasisArgs& B, const double* __restrict__ a,
                                int W, int H, RealiseLds& sh, double* Kd, bool skip0 = false) {
     const int KW = 2 * B.h + 1, T = KW * KW, tid = threadIdx.x, nb = B.nb, ns = B.ns;
     for (int e = tid; e < B.nf * KW; e += blockDim.x) sh.F[e] = B.fac64[e];
+    for (int e = tid; e < nb; e += blockDim.x) sh.ro[e] = B.rorder[e];
+    for (int e = tid; e <= B.nf; e += blockDim.x) sh.rs[e] = B.rstart[e];
     if (tid < 64) {
         // wave 0, lane i: alpha_i(x, y) from the term's ns spatial
         // coefficients (all loads issued before the first use), the spatial
@@ -110,13 +124,42 @@ __device__ void realise_kernel(const BasisArgs& B, const double* __restrict__ a,
         }
     }
     __syncthreads();
-    for (int t = tid; t < T; t += blockDim.x) {
-        const int v = t / KW, u = t - v * KW;
-        double k4[4] = {0.0, 0.0, 0.0, 0.0};
+    const int nf = B.nf;
+    if (nf <= KW) {
+        double* C = Kd;                                // nf * KW <= T entries
+        for (int e = tid; e < nf * KW; e += blockDim.x) {
+            const int r = e / KW, v = e - r * KW;
+            double c = 0.0;
+            for (int m = sh.rs[r]; m < sh.rs[r + 1]; m++) {
+                const int i = sh.ro[m];
+                c = fma(sh.gam[i], sh.F[sh.cf[i] * KW + v], c);
+            }
+            C[e] = c;
+        }
+        __syncthreads();
+        double kv[RK_MAX];
+#pragma unroll
+        for (int k = 0; k < RK_MAX; k++) {
+            const int t = tid + 256 * k;
+            kv[k] = 0.0;
+            if (t < T) {
+                const int v = t / KW, u = t - v * KW;
+                for (int r = 0; r < nf; r++) kv[k] = fma(sh.F[r * KW + u], C[r * KW + v], kv[k]);
+            }
+        }
+        __syncthreads();                               // C is read; Kd takes the taps
+#pragma unroll
+        for (int k = 0; k < RK_MAX; k++)
+            if (tid + 256 * k < T) Kd[tid + 256 * k] = kv[k];
+    } else {
+        for (int t = tid; t < T; t += blockDim.x) {
+            const int v = t / KW, u = t - v * KW;
+            double k4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
-        for (int i = 0; i < nb; i++)
-            k4[i & 3] += sh.gam[i] * sh.F[sh.rf[i] * KW + u] * sh.F[sh.cf[i] * KW + v];
-        Kd[t] = (k4[0] + k4[1]) + (k4[2] + k4[3]);
+            for (int i = 0; i < nb; i++)
+                k4[i & 3] += sh.gam[i] * sh.F[sh.rf[i] * KW + u] * sh.F[sh.cf[i] * KW + v];
+            Kd[t] = (k4[0] + k4[1]) + (k4[2] + k4[3]);
+        }
     }
     __syncthreads();
 }
@@ -954,7 +997,7 @@ __global__ __launch_bounds__(256) void k_realise_b(const PairDesc* __restrict__ 
     constexpr int KW = 2 * H_ + 1;
     constexpr int T = KW * KW;
     __shared__ double F[32 * KW];
-    __shared__ int rf[64], cf[64];
+    __shared__ int rf[64], cf[64], ro[64], rs[33];
     __shared__ double gam[RB_WAVES][64];
     __shared__ double Kd[RB_WAVES][T];
     __shared__ double ring[RB_WAVES][H_ + 1];
@@ -963,7 +1006,9 @@ __global__ __launch_bounds__(256) void k_realise_b(const PairDesc* __restrict__ 
     if (tid < nb) {
         rf[tid] = B0.rowf[tid];
         cf[tid] = B0.colf[tid];
+        ro[tid] = B0.rorder[tid];
     }
+    if (tid <= B0.nf) rs[tid] = B0.rstart[tid];
     __syncthreads();
     const int q = blockIdx.x * RB_WAVES + w;
     if (q >= n_patches) return;                 // the whole wave; no barrier follows
@@ -1004,7 +1049,34 @@ __global__ __launch_bounds__(256) void k_realise_b(const PairDesc* __restrict__ 
     }
     wave_sync_lds();
     double* K = Kd[w];
-    {
+    const int nf = B0.nf;
+    if (nf <= KW) {
+        // realise_kernel's regrouped form, the same chains: the table C in
+        // this wave's K, then the lane's taps t = lane + 64 k in registers
+        constexpr int NT = (T + 63) / 64;
+        for (int e = lane; e < nf * KW; e += 64) {
+            const int r = e / KW, v = e - r * KW;
+            double c = 0.0;
+            for (int m = rs[r]; m < rs[r + 1]; m++) {
+                const int i = ro[m];
+                c = fma(gam[w][i], F[cf[i] * KW + v], c);
+            }
+            K[e] = c;
+        }
+        wave_sync_lds();
+        double kv[NT];
+#pragma unroll
+        for (int k = 0; k < NT; k++) {
+            const int t = min(lane + 64 * k, T - 1);
+            const int v = t / KW, u = t - v * KW;
+            kv[k] = 0.0;
+            for (int r = 0; r < nf; r++) kv[k] = fma(F[r * KW + u], K[r * KW + v], kv[k]);
+        }
+        wave_sync_lds();
+#pragma unroll
+        for (int k = 0; k < NT; k++)
+            if (lane + 64 * k < T) K[lane + 64 * k] = kv[k];
+    } else {
         // the lane's NT taps t = lane + 64 k at once, the terms in the outer
         // loop (each term's coefficient and factor rows read once for all of
         // them); per tap the same sums in the same order as realise_kernel
@@ -1213,6 +1285,8 @@ static BasisArgs basis_args_of(const psfm_context* ctx) {
     B.z = ctx->term_z;
     B.rowf = ctx->term_rowf;
     B.colf = ctx->term_colf;
+    B.rorder = ctx->term_rorder;
+    B.rstart = ctx->row_start;
     B.nb = ctx->nb;
     B.nf = ctx->nf;
     B.ns = ctx->ns;

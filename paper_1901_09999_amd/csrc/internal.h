@@ -33,6 +33,8 @@ struct psfm_context {
     float* fac;       // [nf][KW] 1-D factors e-th power x Gaussian j, at offsets -h..h
     int* term_rowf;   // [nb] factor index of the u (row-pass) profile of term i
     int* term_colf;   // [nb] factor index of the v (column-pass) profile of term i
+    int* term_rorder; // [nb] the terms ordered by row factor, increasing i within one
+    int* row_start;   // [nf + 1] row factor r's terms: term_rorder[row_start[r] .. row_start[r + 1])
     float* term_psi;  // [nb] normalisation of the separable product
     float* term_z;    // [nb] 1 if k_0 is subtracted (even terms i >= 1), else 0
     double* fac64;    // [nf][KW] the 1-D factors in FP64
