@@ -186,12 +186,15 @@ def bench_batch(args, torch, psfm, synth):
                   stamps=torch.from_numpy(d.stamps.astype(np.int32)).cuda(),
                   S=d.workload.spatial_order) for d in dps]
     if args.no_tune:
-        grid, order, band, table = 0, 1, 0, []
+        grid, order, band, groups, table = 0, 1, 0, [], []
     else:
         tu = tune.choose(ctx, pairs, c_out=10, log=log, use_cache=not args.retune)
         grid, order, band, table = tu["apply_grid"], tu["order"], tu["fit_band_rows"], tu["table"]
+        groups = tu.get("groups", [])
         ctx = tune.context_for(ctx, band)
-    log(f"tuned: apply_grid {grid}, order {order}, fit band rows {band}")
+    plans = psfm.split_by_order(pairs, groups)
+    log(f"tuned: apply_grid {grid}, order {order}, fit band rows {band}, "
+        f"plans by spatial order {[sorted({int(pairs[k]['S']) for k in ix}) for ix in plans]}")
     b = psfm.Batch(ctx, pairs, c_out=10, apply_grid=grid, order=order)
     b.run()
     torch.cuda.synchronize()
@@ -209,29 +212,9 @@ def bench_batch(args, torch, psfm, synth):
         ev[NS].synchronize()
         stage += [ev[i].elapsed_time(ev[i + 1]) for i in range(NS)]
     stage /= reps
-    b.capture()
-    for _ in range(args.warmup):
-        b.launch()
-    torch.cuda.synchronize()
-    lat, per = [], []
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        with torch.cuda.stream(b.stream):
-            e0.record()
-        b.launch()
-        with torch.cuda.stream(b.stream):
-            e1.record()
-        e1.synchronize()
-        per.append(e0.elapsed_time(e1))
-        lat.append(b.latencies_s() * 1e3)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-    ms_per_step = 1e3 * wall / args.steps
-    lat = np.concatenate(lat)
-    st = [b.stats(k) for k in range(len(wls))]
-    # the dominant kernel alone: k_match_tiles_b is stage 3 (one launch), timed
-    # with HIP events on the batch stream over as many launches as steps
+    # the dominant kernel alone: k_match_tiles_b is stage 3 (one launch over
+    # the tiles of every pair), timed with HIP events on the batch stream over
+    # as many launches as steps
     kreps = max(args.steps, 5)
     k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     with torch.cuda.stream(b.stream):
@@ -241,6 +224,42 @@ def bench_batch(args, torch, psfm, synth):
         k1.record()
     k1.synchronize()
     tiles_us = k0.elapsed_time(k1) * 1e3 / kreps
+    # the timed step: one graph; with a split by spatial order, one plan per
+    # group as the graph's parallel branches
+    if len(plans) > 1:
+        b.close()
+        del b
+        torch.cuda.empty_cache()
+        subs = [psfm.Batch(ctx, [pairs[k] for k in ix], c_out=10, apply_grid=grid, order=order)
+                for ix in plans]
+        runner = psfm.BatchGroup(subs)
+    else:
+        subs = [b]
+        b.capture()
+        runner = b
+    for _ in range(args.warmup):
+        runner.launch()
+    torch.cuda.synchronize()
+    lat, per = [], []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(runner.stream):
+            e0.record()
+        runner.launch()
+        with torch.cuda.stream(runner.stream):
+            e1.record()
+        e1.synchronize()
+        per.append(e0.elapsed_time(e1))
+        lat.append(np.concatenate([sb.latencies_s() for sb in subs]) * 1e3)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ms_per_step = 1e3 * wall / args.steps
+    lat = np.concatenate(lat)
+    st = [None] * len(wls)
+    for ix, sb in zip(plans, subs):
+        for j, k in enumerate(ix):
+            st[k] = sb.stats(j)
     T = (2 * spec.kernel_half + 1) ** 2
     flops = 4.0 * T * total_px                 # I' and V' (2T flop per pixel each)
     achieved = flops / (tiles_us * 1e-6) / 1e12
@@ -267,6 +286,7 @@ def bench_batch(args, torch, psfm, synth):
                                f"FP32 fit",
                    "pairs": len(wls), "total_pixels": int(total_px),
                    "apply_grid": grid, "tile_order": order, "fit_band_rows": band,
+                   "plans_by_spatial_order": [sorted({int(pairs[k]["S"]) for k in ix}) for ix in plans],
                    "parallelism": "single GPU"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                        "p99": round(float(np.percentile(lat, 99)), 3),

@@ -795,6 +795,28 @@ int psfm_batch_graph_launch(psfm_batch* batch, void* stream);
 
 int psfm_batch_destroy(psfm_batch* batch);
 
+/*
+ * Several plans run side by side (a scheduling of the same work, Section 2's
+ * fits and solves and Section 3.5's convolutions per pair unchanged): one HIP
+ * graph in which each plan's psfm_batch_run is a branch of its own, forked
+ * from and joined back to `stream` (not the NULL stream) during the capture.
+ * Plans whose pairs differ in unknown count (spatial order) finish their
+ * latency-bound solves at different times, so one plan's tile pass fills the
+ * device while another still solves.  batches: host array of n (1..16)
+ * plans that share no workspace or outputs; the group keeps the pointers,
+ * so the plans must outlive it and must not run while it runs.  The capture
+ * creates one stream and one event per plan and releases them before it
+ * returns; no device memory is allocated.  *out receives a host-side object
+ * freed by psfm_batch_group_destroy.  Each plan's time stamps (times of
+ * psfm_batch_plan) count from that plan's own start.
+ */
+typedef struct psfm_batch_group psfm_batch_group;
+int psfm_batch_group_capture(psfm_batch* const* batches, int n, void* stream,
+                             psfm_batch_group** out);
+/* Replays the group's graph on `stream`. */
+int psfm_batch_group_launch(psfm_batch_group* group, void* stream);
+int psfm_batch_group_destroy(psfm_batch_group* group);
+
 /* Tick rate of the device wall clock used by the batch time stamps. */
 double psfm_wall_clock_hz(void);
 

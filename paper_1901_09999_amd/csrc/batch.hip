@@ -395,6 +395,95 @@ extern "C" int psfm_batch_destroy(psfm_batch* b) {
     return PSFM_OK;
 }
 
+// ---- several plans as the branches of one graph
+struct psfm_batch_group {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+constexpr int PSFM_BATCH_GROUP_MAX = 16;
+
+extern "C" int psfm_batch_group_capture(psfm_batch* const* batches, int n, void* stream,
+                                        psfm_batch_group** out) {
+    if (!batches || n < 1 || n > PSFM_BATCH_GROUP_MAX || !stream || !out) return PSFM_ERR_INVALID_ARG;
+    for (int i = 0; i < n; i++) {
+        if (!batches[i]) return PSFM_ERR_INVALID_ARG;
+        for (int j = 0; j < i; j++)
+            if (batches[j] == batches[i]) return PSFM_ERR_INVALID_ARG;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    hipStream_t br[PSFM_BATCH_GROUP_MAX] = {};
+    hipEvent_t ev[PSFM_BATCH_GROUP_MAX + 1] = {};
+    int rc = PSFM_OK;
+    auto release = [&]() {
+        for (int i = 0; i < n; i++)
+            if (br[i]) (void)hipStreamDestroy(br[i]);
+        for (int i = 0; i <= n; i++)
+            if (ev[i]) (void)hipEventDestroy(ev[i]);
+    };
+    auto ok = [](hipError_t e) { return e == hipSuccess ? PSFM_OK : psfm::check_hip(e); };
+    for (int i = 0; i < n && rc == PSFM_OK; i++)
+        rc = ok(hipStreamCreateWithFlags(&br[i], hipStreamNonBlocking));
+    for (int i = 0; i <= n && rc == PSFM_OK; i++)
+        rc = ok(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+    if (rc) {
+        release();
+        return rc;
+    }
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        release();
+        return psfm::check_hip(e);
+    }
+    // fork, one branch per plan, join; every forked branch is joined even
+    // after an error, so that the capture ends cleanly
+    e = hipEventRecord(ev[n], st);
+    for (int i = 0; i < n && e == hipSuccess; i++) {
+        e = hipStreamWaitEvent(br[i], ev[n], 0);
+        if (e != hipSuccess) break;
+        if (rc == PSFM_OK) rc = psfm_batch_run(batches[i], br[i]);
+        e = hipEventRecord(ev[i], br[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, ev[i], 0);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t ee = hipStreamEndCapture(st, &g);
+    release();
+    if (rc == PSFM_OK && e != hipSuccess) rc = psfm::check_hip(e);
+    if (rc == PSFM_OK && ee != hipSuccess) rc = psfm::check_hip(ee);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    psfm_batch_group* grp = static_cast<psfm_batch_group*>(std::calloc(1, sizeof(psfm_batch_group)));
+    if (!grp) {
+        (void)hipGraphDestroy(g);
+        return PSFM_ERR_INVALID_ARG;
+    }
+    grp->graph = g;
+    e = hipGraphInstantiate(&grp->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        std::free(grp);
+        return psfm::check_hip(e);
+    }
+    *out = grp;
+    return PSFM_OK;
+}
+
+extern "C" int psfm_batch_group_launch(psfm_batch_group* grp, void* stream) {
+    if (!grp || !grp->exec) return PSFM_ERR_INVALID_ARG;
+    PSFM_HIP_CHECK(hipGraphLaunch(grp->exec, (hipStream_t)stream));
+    return PSFM_OK;
+}
+
+extern "C" int psfm_batch_group_destroy(psfm_batch_group* grp) {
+    if (!grp) return PSFM_ERR_INVALID_ARG;
+    if (grp->exec) (void)hipGraphExecDestroy(grp->exec);
+    if (grp->graph) (void)hipGraphDestroy(grp->graph);
+    std::free(grp);
+    return PSFM_OK;
+}
+
 extern "C" double psfm_wall_clock_hz(void) {
     int dev = 0, khz = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0.0;

@@ -10,7 +10,7 @@ from __future__ import annotations
 import ctypes as C
 import dataclasses
 import os
-from typing import Optional, Sequence, Tuple
+from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 import torch
@@ -184,6 +184,9 @@ def lib():
             "psfm_batch_graph_capture": (i, [P, P]),
             "psfm_batch_graph_launch": (i, [P, P]),
             "psfm_batch_destroy": (i, [P]),
+            "psfm_batch_group_capture": (i, [C.POINTER(P), i, P, C.POINTER(P)]),
+            "psfm_batch_group_launch": (i, [P, P]),
+            "psfm_batch_group_destroy": (i, [P]),
             "psfm_wall_clock_hz": (C.c_double, []),
             "psfm_solve_stamps": (i, [P, i, P, P, P, P, P, P, P]),
             "psfm_cholesky_workspace_bytes": (sz, [i]),
@@ -742,6 +745,54 @@ class Batch:
         return read_stats(self.out[k]["stats"])
 
 
+def split_by_order(pairs, groups) -> List[List[int]]:
+    """Indices of the pairs whose spatial order ``S`` lies in each group of
+    orders (a sequence of sequences); pairs of no listed order form a last
+    group.  Empty groups are dropped."""
+    listed = {int(s) for g in groups for s in g}
+    out = [[k for k, q in enumerate(pairs) if int(q["S"]) in set(int(s) for s in g)] for g in groups]
+    out.append([k for k, q in enumerate(pairs) if int(q["S"]) not in listed])
+    return [ix for ix in out if ix]
+
+
+class BatchGroup:
+    """Several :class:`Batch` plans as the branches of one HIP graph
+    (``psfm_batch_group_*``): each plan's run is forked from and joined back
+    to the group's stream, so that one plan's latency-bound solve overlaps
+    another's fits or tile pass.  The group holds the plans (which must not
+    run by themselves while it runs)."""
+
+    def __init__(self, batches, stream: Optional[torch.cuda.Stream] = None):
+        self.batches = list(batches)
+        if not self.batches:
+            raise PsfmError("empty batch group")
+        dev = self.batches[0].ctx.device
+        self.stream = torch.cuda.Stream(device=dev) if stream is None else stream
+        self._h = C.c_void_p()
+        arr = (C.c_void_p * len(self.batches))(*[b._h.value for b in self.batches])
+        torch.cuda.synchronize()
+        with torch.cuda.stream(self.stream):
+            _check(lib().psfm_batch_group_capture(arr, len(self.batches), _stream(), C.byref(self._h)),
+                   "psfm_batch_group_capture")
+
+    def launch(self):
+        self.stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(self.stream):
+            _check(lib().psfm_batch_group_launch(self._h, _stream()), "psfm_batch_group_launch")
+        torch.cuda.current_stream().wait_stream(self.stream)
+
+    def close(self):
+        if self._h:
+            lib().psfm_batch_group_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def cholesky_solve(M: torch.Tensor, b: torch.Tensor, x: Optional[torch.Tensor] = None,
                    info: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None):
     """psfm_cholesky_solve on device tensors (M n x n, b n, float64)."""
@@ -893,6 +944,7 @@ def exported_symbols() -> Sequence[str]:
             "psfm_status_string", "psfm_batch_workspace_bytes", "psfm_batch_plan",
             "psfm_batch_run", "psfm_batch_run_stage", "psfm_batch_set_tuning", "psfm_batch_graph_capture",
             "psfm_batch_graph_launch", "psfm_batch_destroy", "psfm_wall_clock_hz",
+            "psfm_batch_group_capture", "psfm_batch_group_launch", "psfm_batch_group_destroy",
             "psfm_solve_stamps", "psfm_solve_prior", "psfm_cholesky_workspace_bytes",
             "psfm_fit_norm", "psfm_solve_norm", "psfm_quality_eval", "psfm_bin_image",
             "psfm_resample_cov", "psfm_add_images",

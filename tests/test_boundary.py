@@ -127,3 +127,20 @@ def test_cnn_parameter_layout_matches_oracle(lib):
     assert lib.psfm_cholesky_workspace_bytes(0) == 0 and lib.psfm_cholesky_workspace_bytes(295) > 0
     assert lib.psfm_cholesky_solve(0, None, None, None, None, None, 0, None) == -1
     assert lib.psfm_cholesky_solve(600, *([None] * 4), None, 0, None) == -1
+
+
+def test_batch_group_argument_checks(lib):
+    """The batch-group entry points refuse bad arguments before any device call."""
+    g = C.c_void_p()
+    one = (C.c_void_p * 2)(C.c_void_p(16), C.c_void_p(16))      # the same plan twice
+    stream = C.c_void_p(8)
+    assert lib.psfm_batch_group_capture(None, 1, stream, C.byref(g)) == -1
+    assert lib.psfm_batch_group_capture(one, 0, stream, C.byref(g)) == -1
+    assert lib.psfm_batch_group_capture(one, 17, stream, C.byref(g)) == -1
+    assert lib.psfm_batch_group_capture(one, 1, None, C.byref(g)) == -1
+    assert lib.psfm_batch_group_capture(one, 1, stream, None) == -1
+    assert lib.psfm_batch_group_capture(one, 2, stream, C.byref(g)) == -1
+    nul = (C.c_void_p * 1)(None)
+    assert lib.psfm_batch_group_capture(nul, 1, stream, C.byref(g)) == -1
+    assert lib.psfm_batch_group_launch(None, stream) == -1
+    assert lib.psfm_batch_group_destroy(None) == -1

@@ -135,6 +135,47 @@ def test_batch_graph_replays_match_eager():
         assert np.all(lat > 0) and np.all(lat < 10.0), lat
 
 
+def test_batch_group_matches_one_plan():
+    """The batch split by spatial order into plans that run as the parallel
+    branches of one graph (psfm_batch_group_*) gives every pair the outputs
+    of the one-plan batch, bit for bit (each pair's work is the same device
+    code in either schedule), on replays with eager work between them."""
+    torch, psfm = hip()
+    pairs = _pairs(SPECS[:4], seed0=77)          # spatial orders 0, 2, 1, 3, all solvable
+    ctx, dev, b = _batch(psfm, torch, pairs, 10)
+    b.run()
+    torch.cuda.synchronize()
+    fields = ("coeffs", "diff", "diff_var", "diff_mask", "conv", "var", "conv_mask", "cov",
+              "cov_diff")
+    ref = [{f: _np(o[f]).copy() for f in fields + ("flags",)} for o in b.out]
+    b.close()
+    plans = psfm.split_by_order(dev, [[3], [2]])
+    assert sorted(k for ix in plans for k in ix) == list(range(len(dev))) and len(plans) == 3
+    subs = [psfm.Batch(ctx, [dev[k] for k in ix], c_out=10, keep_conv=True, apply_grid=64 * (j + 1),
+                       order=j % 3) for j, ix in enumerate(plans)]
+    grp = psfm.BatchGroup(subs)
+    for rep in range(3):
+        for sb in subs:                       # eager work between replays
+            for o in sb.out:
+                o["diff"].fill_(0.0)
+                o["coeffs"].fill_(0.0)
+        torch.cuda.synchronize()
+        grp.launch()
+        torch.cuda.synchronize()
+        for ix, sb in zip(plans, subs):
+            for j, k in enumerate(ix):
+                o = sb.out[j]
+                for f in fields:
+                    assert np.array_equal(_np(o[f]), ref[k][f]), (rep, k, f)
+                n = dev[k]["stamps"].shape[0]
+                assert np.array_equal(_np(o["flags"])[:n], ref[k]["flags"][:n]), (rep, k)
+            lat = sb.latencies_s()
+            assert np.all(lat > 0) and np.all(lat < 10.0), lat
+    grp.close()
+    for sb in subs:
+        sb.close()
+
+
 def _corr(c_in, seed):
     """A normalised autocorrelation pseudo-matrix of half-size c_in (the
     covariance of white noise after a small random filter)."""
