@@ -483,20 +483,22 @@ int psfm_match_pair(const psfm_context* ctx, const double* coeffs, const float* 
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc):
  * psfm_match_pair without a workspace argument.  Its scratch (covariance
- * samples and per-tile variance sums) lives in a static device array of
+ * samples, per-tile variance sums and the patch taps) lives in a static
+ * device array of
  * PSFM_STATIC_SCRATCH_BYTES on each device, held until the process ends;
  * the call allocates nothing.  Arguments, results and errors are those of
  * psfm_match_pair (bit-identical outputs, same kernels), plus
  * PSFM_ERR_WORKSPACE, returned before anything is launched, when the image
  * needs more scratch than the array holds: about 1 MB of covariance samples
- * at h = 10 (1.6 MB at h = 16) plus 32 bytes per 64 x 64 output tile, i.e.
- * images up to about 20000 x 20000 px at h = 10 with 64-px patches (smaller
- * patches mean more tiles).  Every call on a device shares that device's
+ * at h = 10 (1.6 MB at h = 16) plus the FP32 taps of every patch (3.5 KB at
+ * h = 10) and 32 bytes per 64 x 64 output tile, i.e. images up to about
+ * 8500 x 8500 px at h = 10 with 64-px patches (smaller patches mean more
+ * patches and tiles).  Every call on a device shares that device's
  * array and leaves its contents behind: calls that overlap on one device
  * (several streams or host threads) race and must be serialised by the
  * caller.
  */
-#define PSFM_STATIC_SCRATCH_BYTES ((size_t)4 << 20)
+#define PSFM_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
 int psfm_match_pair_static(const psfm_context* ctx, const double* coeffs, const float* I1,
                            const float* V1, const uint8_t* M1, const float* I2, const float* V2,
                            const uint8_t* M2, int W, int H, int64_t pitch, const double* cov1,

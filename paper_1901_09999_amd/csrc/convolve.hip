@@ -990,30 +990,44 @@ __device__ __forceinline__ void match_tile(const PairDesc& p, const int t, const
 // taps K and f K^2 and the BAD radius to p.ptaps for the tile pass.
 constexpr int RB_WAVES = 4;
 
+// LDS of the per-wave patch realisation: the basis factors and term tables
+// (shared), each wave's coefficients, taps and ring sums.
 template <int H_>
-__global__ __launch_bounds__(256) void k_realise_b(const PairDesc* __restrict__ pairs,
-                                                   const int* __restrict__ patch_pair, int n_patches,
-                                                   BasisArgs B0, int P, double bad_frac) {
+struct RealiseWaveLds {
+    double F[32 * (2 * H_ + 1)];
+    int rf[64], cf[64], ro[64], rs[33];
+    double gam[RB_WAVES][64];
+    double Kd[RB_WAVES][(2 * H_ + 1) * (2 * H_ + 1)];
+    double ring[RB_WAVES][H_ + 1];
+};
+
+// All threads: the factors and term tables into L (a barrier follows).
+template <int H_>
+__device__ void realise_wave_setup(const BasisArgs& B0, RealiseWaveLds<H_>& L) {
+    constexpr int KW = 2 * H_ + 1;
+    const int tid = threadIdx.x, nb = B0.nb;
+    for (int e = tid; e < B0.nf * KW; e += 256) L.F[e] = B0.fac64[e];
+    if (tid < nb) {
+        L.rf[tid] = B0.rowf[tid];
+        L.cf[tid] = B0.colf[tid];
+        L.ro[tid] = B0.rorder[tid];
+    }
+    if (tid <= B0.nf) L.rs[tid] = B0.rstart[tid];
+    __syncthreads();
+}
+
+// One wave realises patch ql of pair p into p.ptaps (see k_realise_b).
+template <int H_>
+__device__ void realise_patch_wave(const PairDesc& p, const int ql, const BasisArgs& B0, int P,
+                                   double bad_frac, RealiseWaveLds<H_>& L) {
     constexpr int KW = 2 * H_ + 1;
     constexpr int T = KW * KW;
-    __shared__ double F[32 * KW];
-    __shared__ int rf[64], cf[64], ro[64], rs[33];
-    __shared__ double gam[RB_WAVES][64];
-    __shared__ double Kd[RB_WAVES][T];
-    __shared__ double ring[RB_WAVES][H_ + 1];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nb = B0.nb;
-    for (int e = tid; e < B0.nf * KW; e += 256) F[e] = B0.fac64[e];
-    if (tid < nb) {
-        rf[tid] = B0.rowf[tid];
-        cf[tid] = B0.colf[tid];
-        ro[tid] = B0.rorder[tid];
-    }
-    if (tid <= B0.nf) rs[tid] = B0.rstart[tid];
-    __syncthreads();
-    const int q = blockIdx.x * RB_WAVES + w;
-    if (q >= n_patches) return;                 // the whole wave; no barrier follows
-    const PairDesc& p = pairs[patch_pair[q]];
-    const int ql = q - p.patch_off;
+    const double* F = L.F;
+    const int *rf = L.rf, *cf = L.cf, *ro = L.ro, *rs = L.rs;
+    double (*gam)[64] = L.gam;
+    double (*Kd)[T] = L.Kd;
+    double (*ring)[H_ + 1] = L.ring;
     const int W = p.W, H = p.H, ns = p.ns;
     const PatchGeom g = patch_geom(W, H, P);
     const int px = ql % g.npx, py = ql / g.npx;
@@ -1171,6 +1185,29 @@ __global__ __launch_bounds__(256) void k_realise_b(const PairDesc* __restrict__ 
     if (lane == 0) dst[2 * T] = __int_as_float(rb);
 }
 
+template <int H_>
+__global__ __launch_bounds__(256) void k_realise_b(const PairDesc* __restrict__ pairs,
+                                                   const int* __restrict__ patch_pair, int n_patches,
+                                                   BasisArgs B0, int P, double bad_frac) {
+    __shared__ RealiseWaveLds<H_> L;
+    realise_wave_setup<H_>(B0, L);
+    const int q = blockIdx.x * RB_WAVES + (threadIdx.x >> 6);
+    if (q >= n_patches) return;                 // the whole wave; no barrier follows
+    const PairDesc& p = pairs[patch_pair[q]];
+    realise_patch_wave<H_>(p, q - p.patch_off, B0, P, bad_frac, L);
+}
+
+// The same for the n_patches patches of one pair (psfm_match_pair).
+template <int H_>
+__global__ __launch_bounds__(256) void k_realise_1(PairDesc p, int n_patches, BasisArgs B0, int P,
+                                                   double bad_frac) {
+    __shared__ RealiseWaveLds<H_> L;
+    realise_wave_setup<H_>(B0, L);
+    const int q = blockIdx.x * RB_WAVES + (threadIdx.x >> 6);
+    if (q >= n_patches) return;
+    realise_patch_wave<H_>(p, q, B0, P, bad_frac, L);
+}
+
 // Fused apply for every pair of a batch: the tiles of all pairs (flattened,
 // pair after pair, visited by a grid-stride loop) go through match_tile; the
 // workgroup that finishes a pair's last tile forms that pair's C_D and
@@ -1228,7 +1265,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 }
 
 // The fused apply of one pair (psfm_match_pair): one workgroup per tile, the
-// pair's description by value; C_D follows in k_subtract_cov.
+// pair's description by value, the patch taps from k_realise_1; C_D follows
+// in k_cov_finish_diff.
 template <int H_>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_match_tile(PairDesc p, BasisArgs B0, int P,
                                                                                           double bad_frac) {
@@ -1244,7 +1282,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     __shared__ double red[16];
     __shared__ int s_rb;
     __shared__ double s_f;
-    match_tile<H_, false>(p, blockIdx.x, B0, P, bad_frac, halo, tapsK, tapsV, badw, ring, red, &s_rb, &s_f);
+    match_tile<H_, true>(p, blockIdx.x, B0, P, bad_frac, halo, tapsK, tapsV, badw, ring, red, &s_rb, &s_f);
 }
 
 constexpr int SUB_BLOCKS = 1024;
@@ -1269,11 +1307,16 @@ size_t subtract_workspace(const psfm_context*, int, int) {
     return c.off;
 }
 
-// psfm_match_pair: the pseudo-matrix scratch, then the tiles' variance sums.
+// psfm_match_pair: the pseudo-matrix scratch, the tiles' variance sums, then
+// the patch taps (FP32 K, f K^2 and the BAD radius of every patch).
+static size_t match_sub_bytes(const PatchGeom& g) {
+    return sizeof(double) * 4 * (size_t)(g.npx * g.tpp) * (g.npy * g.tpp);
+}
+
 size_t match_workspace(const psfm_context* ctx, int W, int H) {
     const PatchGeom g = patch_geom(W, H, ctx->cfg.patch);
-    return align_up(conv_workspace(ctx, W, H), 256) +
-           sizeof(double) * 4 * (size_t)(g.npx * g.tpp) * (g.npy * g.tpp);
+    return align_up(conv_workspace(ctx, W, H), 256) + align_up(match_sub_bytes(g), 256) +
+           sizeof(float) * (size_t)g.npx * g.npy * patch_taps_floats(ctx->h);
 }
 
 int cov_sample_side(const psfm_context* ctx, int c_in) { return 2 * (2 * ctx->h + c_in) + 1; }
@@ -1493,7 +1536,9 @@ extern "C" int psfm_subtract(const psfm_context* ctx, const double* coeffs, cons
 
 template <int H_>
 static void launch_match_tile(const PairDesc& p, const BasisArgs& B, int P, double bad_frac, int n_tiles,
-                              hipStream_t st) {
+                              int n_patches, hipStream_t st) {
+    hipLaunchKernelGGL(k_realise_1<H_>, dim3((n_patches + RB_WAVES - 1) / RB_WAVES), dim3(256), 0, st, p,
+                       n_patches, B, P, bad_frac);
     hipLaunchKernelGGL(k_match_tile<H_>, dim3(n_tiles), dim3(256), 0, st, p, B, P, bad_frac);
 }
 
@@ -1543,13 +1588,16 @@ int psfm::match_pair_ws(const psfm_context* ctx, const double* coeffs, const flo
     p.diff_mask = diff_mask;
     p.ntx = g.npx * g.tpp;
     p.nty = g.npy * g.tpp;
-    p.sub_part = reinterpret_cast<double*>(static_cast<char*>(ws) +
-                                           psfm::align_up(psfm::conv_workspace(ctx, W, H), 256));
+    const size_t sub_off = psfm::align_up(psfm::conv_workspace(ctx, W, H), 256);
+    p.sub_part = reinterpret_cast<double*>(static_cast<char*>(ws) + sub_off);
+    p.ptaps = reinterpret_cast<float*>(static_cast<char*>(ws) + sub_off +
+                                       psfm::align_up(psfm::match_sub_bytes(g), 256));
     const int n_tiles = p.ntx * p.nty;
+    const int n_patch = g.npx * g.npy;
     const BasisArgs B = basis_args(ctx);
     switch (ctx->h) {
 #define PSFM_M1_CASE(HH) \
-    case HH: launch_match_tile<HH>(p, B, cf.patch, cf.bad_frac, n_tiles, st); break;
+    case HH: launch_match_tile<HH>(p, B, cf.patch, cf.bad_frac, n_tiles, n_patch, st); break;
         PSFM_M1_CASE(1) PSFM_M1_CASE(2) PSFM_M1_CASE(3) PSFM_M1_CASE(4) PSFM_M1_CASE(5)
         PSFM_M1_CASE(6) PSFM_M1_CASE(7) PSFM_M1_CASE(8) PSFM_M1_CASE(9) PSFM_M1_CASE(10)
         PSFM_M1_CASE(11) PSFM_M1_CASE(12) PSFM_M1_CASE(13) PSFM_M1_CASE(14) PSFM_M1_CASE(15)

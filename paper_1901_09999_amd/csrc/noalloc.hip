@@ -1,10 +1,10 @@
 // psfm_match_pair_static: psfm_match_pair for callers that cannot allocate
 // device memory (code under HIP graph capture, tight serving loops).  The
-// call's scratch -- the covariance samples of the pseudo-matrix and the
-// per-tile variance sums of C_D -- lives in a file-scope device array of
-// PSFM_STATIC_SCRATCH_BYTES instead of a caller workspace; the kernels are
-// psfm_match_pair's own and take the array's device address as their
-// workspace pointer.
+// call's scratch -- the covariance samples of the pseudo-matrix, the
+// per-tile variance sums of C_D and the patch taps -- lives in a file-scope
+// device array of PSFM_STATIC_SCRATCH_BYTES instead of a caller workspace;
+// the kernels are psfm_match_pair's own and take the array's device address
+// as their workspace pointer.
 //
 // Each device holds its own copy of the array (for as long as the library is
 // loaded in the process).  Its address is looked up once per device, with
