@@ -107,9 +107,37 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data(const float* __restrict__
     }
     __syncthreads();
     const int npix = Hin * Hin;
+    // stride 2: the input pixels of one sample in four parity classes
+    // (p mod 2, q mod 2), each row-major, so that the lanes of a wave take
+    // the same taps (u, v) instead of alternating between one and two of them
+    const int n0 = (Hin + 1) / 2, n1 = Hin / 2;
     for (int t = blockIdx.x * 256 + threadIdx.x; t < B * npix; t += gridDim.x * 256) {
         const int b = t / npix, pp = t - b * npix;
-        const int p = pp / Hin, q = pp - p * Hin;
+        int p, q;
+        if constexpr (S == 2) {
+            int r = pp, rp = 0, rq = 0, nq = n0;
+            if (r >= n0 * n0) {
+                r -= n0 * n0;
+                if (r < n0 * n1) {
+                    rq = 1;
+                    nq = n1;
+                } else {
+                    r -= n0 * n1;
+                    rp = 1;
+                    if (r >= n1 * n0) {
+                        r -= n1 * n0;
+                        rq = 1;
+                        nq = n1;
+                    }
+                }
+            }
+            const int i2 = r / nq, j2 = r - i2 * nq;
+            p = 2 * i2 + rp;
+            q = 2 * j2 + rq;
+        } else {
+            p = pp / Hin;
+            q = pp - p * Hin;
+        }
         float acc[CH];
 #pragma unroll
         for (int c = 0; c < CH; c++) acc[c] = 0.0f;
