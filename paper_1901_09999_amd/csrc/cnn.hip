@@ -92,6 +92,90 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const __half* __restrict__ x, 
     }
 }
 
+typedef _Float16 cnn_half8 __attribute__((ext_vector_type(8)));
+typedef float cnn_floatx4 __attribute__((ext_vector_type(4)));
+
+// The 32 -> 32 layers (3 x 3, stride 2, zero padding 1) as the implicit GEMM
+// Y[pixel][o] = sum over k = (u, v, c) of X[pixel][k] W[k][o] on
+// v_mfma_f32_16x16x32_f16 (FP16 products exact, FP32 sums), k in nine
+// chunks of 32 channels, one tap (u, v) each.  One workgroup per (sample,
+// band of R output rows): the weights first pass through LDS into registers
+// (the B operands of a tile's 18 products: 9 taps x 2 blocks of 16 output
+// channels), then the band's 2R + 1 input rows fill the same LDS as
+// [row][col][channel] with a zero border (40 halves per pixel: the 16-byte
+// reads stay 16-byte aligned, and those of 16 output pixels two columns
+// apart meet at most two to a bank); each wave takes tiles of 16 output
+// pixels.  y = ReLU(sum + bias) in FP16.
+template <int HIN, int HOUT, int R>
+__global__ __launch_bounds__(256) void k_conv_fwd_mfma(const __half* __restrict__ x,
+                                                       const __half* __restrict__ w,
+                                                       const __half* __restrict__ bias,
+                                                       __half* __restrict__ y) {
+    static_assert(HOUT == (HIN + 1) / 2, "stride 2, padding 1");
+    constexpr int WT = HIN + 2;             // tile columns: input columns -1 .. HIN
+    constexpr int RT = 2 * R + 1;           // tile rows: input rows 2 i0 - 1 .. 2 i0 + 2 R - 1
+    constexpr int PS = 40;                  // halves per tile pixel (80 bytes)
+    constexpr int PW = 40;                  // halves per (tap, output channel) of the weights
+    constexpr int NBAND = (HOUT + R - 1) / R;
+    constexpr int XS = RT * WT * PS, WS = 9 * CH * PW, NSH = XS > WS ? XS : WS;
+    static_assert(XS % 8 == 0 && NSH % 8 == 0, "whole 16-byte words");
+    __shared__ __align__(16) __half sh[NSH];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int b = blockIdx.x / NBAND, i0 = (blockIdx.x - b * NBAND) * R;
+    // weights [o][c][u][v] -> LDS [uv][o][c] -> registers
+    for (int e = tid; e < CH * CH * 9; e += 256) {
+        const int o = e / (CH * 9), rem = e - o * (CH * 9), c = rem / 9, uv = rem - 9 * c;
+        sh[(uv * CH + o) * PW + c] = w[e];
+    }
+    __syncthreads();
+    cnn_half8 bw[9][2];
+#pragma unroll
+    for (int uv = 0; uv < 9; uv++)
+#pragma unroll
+        for (int k = 0; k < 2; k++)
+            bw[uv][k] = *reinterpret_cast<const cnn_half8*>(sh + (uv * CH + 16 * k + (lane & 15)) * PW +
+                                                            8 * (lane >> 4));
+    const float b0 = h2f(bias[lane & 15]), b1 = h2f(bias[16 + (lane & 15)]);
+    __syncthreads();
+    // the band's input rows, zero outside the input
+    for (int e = tid; e < XS / 8; e += 256) reinterpret_cast<uint4*>(sh)[e] = make_uint4(0u, 0u, 0u, 0u);
+    __syncthreads();
+    const int r_lo = 2 * i0 - 1;
+    for (int e = tid; e < CH * RT * HIN; e += 256) {
+        const int c = e / (RT * HIN), rem = e - c * (RT * HIN), lr = rem / HIN, col = rem - lr * HIN;
+        const int gr = r_lo + lr;
+        if (gr >= 0 && gr < HIN) sh[(lr * WT + col + 1) * PS + c] = x[(((size_t)b * CH + c) * HIN + gr) * HIN + col];
+    }
+    __syncthreads();
+    const int npx = min(R, HOUT - i0) * HOUT;
+    for (int t = wave; 16 * t < npx; t += 4) {
+        const int m = 16 * t + (lane & 15);
+        const bool valid = m < npx;
+        const int mi = valid ? m / HOUT : 0, mj = valid ? m - mi * HOUT : 0;
+        cnn_floatx4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int uv = 0; uv < 9; uv++) {
+            const int u = uv / 3, v = uv - 3 * u;
+            cnn_half8 a = *reinterpret_cast<const cnn_half8*>(sh + ((2 * mi + u) * WT + 2 * mj + v) * PS +
+                                                             8 * (lane >> 4));
+            if (!valid) a = cnn_half8{0, 0, 0, 0, 0, 0, 0, 0};
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, bw[uv][0], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, bw[uv][1], acc1, 0, 0, 0);
+        }
+        // lane: output channels lane % 16 and 16 + lane % 16 of pixels 4 (lane / 16) + e
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const int mm = 16 * t + 4 * (lane >> 4) + e;
+            if (mm < npx) {
+                const int i = i0 + mm / HOUT, j = mm % HOUT;
+                const size_t o0 = (((size_t)b * CH + (lane & 15)) * HOUT + i) * HOUT + j;
+                y[o0] = __float2half(fmaxf(acc0[e] + b0, 0.0f));
+                y[o0 + (size_t)16 * HOUT * HOUT] = __float2half(fmaxf(acc1[e] + b1, 0.0f));
+            }
+        }
+    }
+}
+
 // dx[b,c,p,q] = sum over (o,u,v) with p = s i + u - 1, q = s j + v - 1 of
 // w[o,c,u,v] dy[b,o,i,j];  dxm = dx * (a > 0) with a the layer's input
 // activation (post-ReLU of the layer below).
@@ -687,12 +771,13 @@ int grid_for(size_t items) {
 int forward_into(const __half* w, const __half* x, int B, const Acts& A, hipStream_t st) {
     hipLaunchKernelGGL((k_conv_fwd<2, 1>), dim3(grid_for((size_t)B * SIDE1 * SIDE1)), dim3(256), 0, st,
                        x, SIDE0, w + OFF_C1W, w + OFF_C1B, A.a1, SIDE1, B);
-    hipLaunchKernelGGL((k_conv_fwd<CH, 2>), dim3(grid_for((size_t)B * SIDE2 * SIDE2)), dim3(256), 0, st,
-                       A.a1, SIDE1, w + OFF_C2W, w + OFF_C2B, A.a2, SIDE2, B);
-    hipLaunchKernelGGL((k_conv_fwd<CH, 2>), dim3(grid_for((size_t)B * SIDE3 * SIDE3)), dim3(256), 0, st,
-                       A.a2, SIDE2, w + OFF_C3W, w + OFF_C3B, A.a3, SIDE3, B);
-    hipLaunchKernelGGL((k_conv_fwd<CH, 2>), dim3(grid_for((size_t)B * SIDE4 * SIDE4)), dim3(256), 0, st,
-                       A.a3, SIDE3, w + OFF_C4W, w + OFF_C4B, A.a4, SIDE4, B);
+    constexpr int RB = 3;                       // output rows per workgroup band
+    hipLaunchKernelGGL((k_conv_fwd_mfma<SIDE1, SIDE2, RB>), dim3(B * ((SIDE2 + RB - 1) / RB)), dim3(256), 0,
+                       st, A.a1, w + OFF_C2W, w + OFF_C2B, A.a2);
+    hipLaunchKernelGGL((k_conv_fwd_mfma<SIDE2, SIDE3, RB>), dim3(B * ((SIDE3 + RB - 1) / RB)), dim3(256), 0,
+                       st, A.a2, w + OFF_C3W, w + OFF_C3B, A.a3);
+    hipLaunchKernelGGL((k_conv_fwd_mfma<SIDE3, SIDE4, RB>), dim3(B * ((SIDE4 + RB - 1) / RB)), dim3(256), 0,
+                       st, A.a3, w + OFF_C4W, w + OFF_C4B, A.a4);
     hipLaunchKernelGGL((k_fc_fwd<true>), dim3((B * HID + 3) / 4), dim3(256), 0, st, A.a4, FLAT,
                        w + OFF_F1W, w + OFF_F1B, HID, B, A.h, nullptr);
     hipLaunchKernelGGL((k_fc_fwd<false>), dim3((B * NOUT + 3) / 4), dim3(256), 0, st, A.h, HID,
