@@ -8,10 +8,12 @@
 // A convolution is the cross-correlation
 //   y[b,o,i,j] = bias[o] + sum_{c,u,v} w[o,c,u,v] x[b,c, s i+u-1, s j+v-1].
 //
-// Kernels (VALU, FP32 accumulation):
-//   k_conv_fwd       one thread per output pixel, all 32 output channels in
-//                    registers, the layer's weights in LDS ordered [c][uv][o]
-//                    so a pixel's 32 products read 8 broadcast 16-byte words;
+// Kernels (FP32 accumulation):
+//   k_conv_fwd       first layer (2 input channels): one thread per output
+//                    pixel, all 32 output channels in registers, the weights
+//                    in LDS ordered [c][uv][o] (8 broadcast 16-byte words per
+//                    input value);
+//   k_conv_fwd_mfma  the 32 -> 32 layers: implicit GEMM on FP16 MFMA (below);
 //   k_conv_bwd_data  one thread per input pixel, all input channels, the
 //                    ReLU mask of the layer below applied on the way out;
 //   k_conv_bwd_w_gemm  32 -> 32 layers: the weight gradients as a GEMM over
