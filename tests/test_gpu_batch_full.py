@@ -11,6 +11,9 @@ The oracle cannot run 734 Mpx in seconds, so the checks sample:
   * the batch against single-pair calls on the largest pair (same device
     code per pair, so coefficients, flags and the difference planes are
     equal bit for bit: a property at any size);
+  * the benchmark's schedule (the batch split by spatial order into plans
+    that run as the branches of one graph) against the one-plan batch on
+    every pair, bit for bit;
   * the tile kernels against the oracle on the largest pair from the
     oracle's coefficients: sampled rectangles (the four corners, which hold
     the ragged right and bottom tails, a patch corner, the brightest source
@@ -179,3 +182,36 @@ def test_full_size_tiles_against_oracle_rectangles(full):
         tol = 2e-5 * scale + 1e-6 * np.abs(I2[okd])
         assert np.all(np.abs(D_g[sl][okd] - D_r[okd]) <= tol), (x0, y0)
         assert np.max(np.abs(VD_g[sl][okd] - VD_r[okd]) / np.abs(VD_r[okd]), initial=0.0) < 1e-5
+
+
+def test_full_batch_split_schedule_equals_one_plan(full):
+    """The schedule the benchmark times: the batch split by spatial order
+    (the tuner's choice, else orders 3 and 2 each alone) into plans that run
+    as the parallel branches of one graph.  Every pair's coefficients, stamp
+    flags and difference planes equal the one-plan batch's bit for bit."""
+    torch, psfm = hip()
+    wls, dps, pairs, b, tu = full
+    groups = tu.get("groups") or [[3], [2]]
+    plans = psfm.split_by_order(pairs, groups)
+    assert sorted(k for ix in plans for k in ix) == list(range(len(pairs)))
+    ctx = b.ctx
+    subs = [psfm.Batch(ctx, [pairs[k] for k in ix], c_out=10, apply_grid=tu["apply_grid"],
+                       order=tu["order"]) for ix in plans]
+    grp = psfm.BatchGroup(subs)
+    for _ in range(2):
+        grp.launch()
+    torch.cuda.synchronize()
+    print(f"{len(plans)} plans: {[len(ix) for ix in plans]} pairs", flush=True)
+    for ix, sb in zip(plans, subs):
+        for j, k in enumerate(ix):
+            o, r = sb.out[j], b.out[k]
+            n = pairs[k]["stamps"].shape[0]
+            assert torch.equal(o["coeffs"], r["coeffs"]), k
+            assert torch.equal(o["flags"][:n], r["flags"][:n]), k
+            for f in ("diff", "diff_var", "diff_mask", "cov_diff"):
+                assert torch.equal(o[f], r[f]), (k, f)
+    grp.close()
+    for sb in subs:
+        sb.close()
+    del grp, subs
+    torch.cuda.empty_cache()
