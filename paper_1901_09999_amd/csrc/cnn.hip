@@ -14,8 +14,9 @@
 //                    in LDS ordered [c][uv][o] (8 broadcast 16-byte words per
 //                    input value);
 //   k_conv_fwd_mfma  the 32 -> 32 layers: implicit GEMM on FP16 MFMA (below);
-//   k_conv_bwd_data  one thread per input pixel, all input channels, the
-//                    ReLU mask of the layer below applied on the way out;
+//   k_conv_bwd_data_mfma  the data gradients of the 32 -> 32 layers per
+//                    stride-2 parity class on BF16 MFMA (hi + lo parts, below),
+//                    the ReLU mask of the layer below applied on the way out;
 //   k_conv_bwd_w_gemm  32 -> 32 layers: the weight gradients as a GEMM over
 //                    the pixels, chunks of output gradients and input patches
 //                    staged in LDS, 4 x 9 sums per thread, a partial set per
@@ -178,85 +179,110 @@ __global__ __launch_bounds__(256) void k_conv_fwd_mfma(const __half* __restrict_
     }
 }
 
-// dx[b,c,p,q] = sum over (o,u,v) with p = s i + u - 1, q = s j + v - 1 of
-// w[o,c,u,v] dy[b,o,i,j];  dxm = dx * (a > 0) with a the layer's input
-// activation (post-ReLU of the layer below).
-template <int S>
-__global__ __launch_bounds__(256) void k_conv_bwd_data(const float* __restrict__ dy, int Hout,
-                                                       const __half* __restrict__ w,
-                                                       const __half* __restrict__ a,
-                                                       float* __restrict__ dxm, int Hin, int B) {
-    __shared__ __align__(16) float ws[9 * CH * CH];     // [uv][o][c]
-    for (int e = threadIdx.x; e < 9 * CH * CH; e += 256) {
-        const int c = e % CH, r = e / CH, o = r % CH, uv = r / CH;
-        ws[e] = h2f(w[(o * CH + c) * 9 + uv]);
+typedef __bf16 cnn_bf16x8 __attribute__((ext_vector_type(8)));
+
+// The data gradient of a 32 -> 32 layer (3 x 3, stride 2, padding 1, odd
+// input side) on v_mfma_f32_16x16x32_bf16.  For an input pixel of parity
+// (p mod 2, q mod 2) the taps that reach it are fixed: u = 1 for even p, u in
+// {0, 2} for odd p (likewise v), i = (p + 1 - u) / 2, j = (q + 1 - v) / 2, all
+// inside the output for an odd side.  So each parity class is a GEMM
+// dX[pixel][c] = sum over (tap, o) of dY[i, j][o] W[o][c][tap], K = 32 per
+// tap.  The FP32 dY and the FP16 weights enter as BF16 hi + lo parts (the
+// weights exactly, dY to 16 bits); the three products hi hi, hi lo, lo hi
+// have FP32 sums.  One workgroup per (sample, band of RB input rows): the
+// weights ([tap][c][o]) and the band's dY rows ([i][j][o]) in LDS with
+// 80-byte rows; each wave takes tiles of 16 pixels of one class and forms both
+// 16-channel blocks; dxm = dx * (a > 0).
+template <int HIN, int HOUT, int RB>
+__global__ __launch_bounds__(256) void k_conv_bwd_data_mfma(const float* __restrict__ dy,
+                                                            const __half* __restrict__ w,
+                                                            const __half* __restrict__ a,
+                                                            float* __restrict__ dxm) {
+    static_assert(HIN % 2 == 1 && HOUT == (HIN + 1) / 2, "stride 2, padding 1, odd side");
+    constexpr int PW = 40;                                   // halves per LDS row
+    constexpr int NRMAX = RB / 2 + 2;                        // dY rows of a band
+    constexpr int NBAND = (HIN + RB - 1) / RB;
+    constexpr int WSZ = 9 * CH * PW, DSZ = NRMAX * HOUT * PW;
+    __shared__ __align__(16) unsigned short wh[WSZ], wl[WSZ], dh[DSZ], dl[DSZ];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int b = blockIdx.x / NBAND, p0 = (blockIdx.x - b * NBAND) * RB, p1 = min(p0 + RB, HIN);
+    const int i_lo = max(0, (p0 - 1) >> 1), i_hi = p1 >> 1;   // dY rows the band reaches
+    auto hi_lo = [](float v, unsigned short& h, unsigned short& l) {
+        const __bf16 bh = (__bf16)v;
+        h = __builtin_bit_cast(unsigned short, bh);
+        l = __builtin_bit_cast(unsigned short, (__bf16)(v - (float)bh));
+    };
+    for (int e = tid; e < CH * CH * 9; e += 256) {
+        const int o = e / (CH * 9), rem = e - o * (CH * 9), c = rem / 9, uv = rem - 9 * c;
+        hi_lo(h2f(w[e]), wh[(uv * CH + c) * PW + o], wl[(uv * CH + c) * PW + o]);
+    }
+    const int nr = i_hi - i_lo + 1;
+    for (int e = tid; e < CH * nr * HOUT; e += 256) {
+        const int o = e / (nr * HOUT), rem = e - o * (nr * HOUT), r = rem / HOUT, j = rem - r * HOUT;
+        const float v = dy[(((size_t)b * CH + o) * HOUT + i_lo + r) * HOUT + j];
+        hi_lo(v, dh[(r * HOUT + j) * PW + o], dl[(r * HOUT + j) * PW + o]);
     }
     __syncthreads();
-    const int npix = Hin * Hin;
-    // stride 2: the input pixels of one sample in four parity classes
-    // (p mod 2, q mod 2), each row-major, so that the lanes of a wave take
-    // the same taps (u, v) instead of alternating between one and two of them
-    const int n0 = (Hin + 1) / 2, n1 = Hin / 2;
-    for (int t = blockIdx.x * 256 + threadIdx.x; t < B * npix; t += gridDim.x * 256) {
-        const int b = t / npix, pp = t - b * npix;
-        int p, q;
-        if constexpr (S == 2) {
-            int r = pp, rp = 0, rq = 0, nq = n0;
-            if (r >= n0 * n0) {
-                r -= n0 * n0;
-                if (r < n0 * n1) {
-                    rq = 1;
-                    nq = n1;
-                } else {
-                    r -= n0 * n1;
-                    rp = 1;
-                    if (r >= n1 * n0) {
-                        r -= n1 * n0;
-                        rq = 1;
-                        nq = n1;
-                    }
+    // the band's pixels in four parity classes (rp, rq), each row-major
+    int cnt[4], first[4], ncol[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const int rp = k >> 1, rq = k & 1;
+        first[k] = p0 + (((p0 & 1) != rp) ? 1 : 0);
+        const int nrow = first[k] < p1 ? (p1 - 1 - first[k]) / 2 + 1 : 0;
+        ncol[k] = (HIN + 1 - rq) / 2;
+        cnt[k] = nrow * ncol[k];
+    }
+    const int t1 = (cnt[0] + 15) / 16, t2 = t1 + (cnt[1] + 15) / 16, t3 = t2 + (cnt[2] + 15) / 16;
+    const int ntile = t3 + (cnt[3] + 15) / 16;
+    const int n = lane & 15, kq = lane >> 4;
+    for (int t = wave; t < ntile; t += 4) {
+        const int k = t < t1 ? 0 : t < t2 ? 1 : t < t3 ? 2 : 3;
+        const int tl = t - (k == 0 ? 0 : k == 1 ? t1 : k == 2 ? t2 : t3);
+        const int rp = k >> 1, rq = k & 1;
+        const int m = 16 * tl + n;                       // A row: pixel of the class
+        const bool valid = m < cnt[k];
+        const int mr = valid ? m / ncol[k] : 0, mc = valid ? m - mr * ncol[k] : 0;
+        const int p = first[k] + 2 * mr, q = rq + 2 * mc;
+        cnn_floatx4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int su = 0; su < (rp ? 2 : 1); su++) {
+            const int u = rp ? 2 * su : 1;
+            for (int sv = 0; sv < (rq ? 2 : 1); sv++) {
+                const int v = rq ? 2 * sv : 1;
+                const int r = (p + 1 - u) / 2 - i_lo, j = (q + 1 - v) / 2;
+                const int ao = (r * HOUT + j) * PW + 8 * kq;
+                cnn_bf16x8 ah = *reinterpret_cast<const cnn_bf16x8*>(dh + ao);
+                cnn_bf16x8 al = *reinterpret_cast<const cnn_bf16x8*>(dl + ao);
+                if (!valid) {
+                    ah = cnn_bf16x8{};
+                    al = cnn_bf16x8{};
                 }
-            }
-            const int i2 = r / nq, j2 = r - i2 * nq;
-            p = 2 * i2 + rp;
-            q = 2 * j2 + rq;
-        } else {
-            p = pp / Hin;
-            q = pp - p * Hin;
-        }
-        float acc[CH];
-#pragma unroll
-        for (int c = 0; c < CH; c++) acc[c] = 0.0f;
-#pragma unroll
-        for (int u = 0; u < 3; u++) {
-            const int ni = p + 1 - u;
-            if (ni < 0 || ni % S) continue;
-            const int i = ni / S;
-            if (i >= Hout) continue;
-#pragma unroll
-            for (int v = 0; v < 3; v++) {
-                const int nj = q + 1 - v;
-                if (nj < 0 || nj % S) continue;
-                const int j = nj / S;
-                if (j >= Hout) continue;
-                for (int o = 0; o < CH; o++) {
-                    const float g = dy[(((size_t)b * CH + o) * Hout + i) * Hout + j];
-                    const float4* wr = reinterpret_cast<const float4*>(ws + ((u * 3 + v) * CH + o) * CH);
-#pragma unroll
-                    for (int k = 0; k < CH / 4; k++) {
-                        const float4 ww = wr[k];
-                        acc[4 * k] = fmaf(ww.x, g, acc[4 * k]);
-                        acc[4 * k + 1] = fmaf(ww.y, g, acc[4 * k + 1]);
-                        acc[4 * k + 2] = fmaf(ww.z, g, acc[4 * k + 2]);
-                        acc[4 * k + 3] = fmaf(ww.w, g, acc[4 * k + 3]);
-                    }
-                }
+                const int uv = u * 3 + v;
+                const int bo0 = (uv * CH + n) * PW + 8 * kq, bo1 = bo0 + 16 * PW;
+                const cnn_bf16x8 bh0 = *reinterpret_cast<const cnn_bf16x8*>(wh + bo0);
+                const cnn_bf16x8 bl0 = *reinterpret_cast<const cnn_bf16x8*>(wl + bo0);
+                const cnn_bf16x8 bh1 = *reinterpret_cast<const cnn_bf16x8*>(wh + bo1);
+                const cnn_bf16x8 bl1 = *reinterpret_cast<const cnn_bf16x8*>(wl + bo1);
+                acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh0, acc0, 0, 0, 0);
+                acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl0, acc0, 0, 0, 0);
+                acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh0, acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh1, acc1, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl1, acc1, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh1, acc1, 0, 0, 0);
             }
         }
+        // lane: channels n and 16 + n of the class pixels 16 tl + 4 kq + e
 #pragma unroll
-        for (int c = 0; c < CH; c++) {
-            const size_t o = (((size_t)b * CH + c) * Hin + p) * Hin + q;
-            dxm[o] = h2f(a[o]) > 0.0f ? acc[c] : 0.0f;
+        for (int e = 0; e < 4; e++) {
+            const int mm = 16 * tl + 4 * kq + e;
+            if (mm < cnt[k]) {
+                const int rr = mm / ncol[k], cc = mm - rr * ncol[k];
+                const int pp = first[k] + 2 * rr, qq = rq + 2 * cc;
+                const size_t o0 = (((size_t)b * CH + n) * HIN + pp) * HIN + qq;
+                const size_t o1 = o0 + (size_t)16 * HIN * HIN;
+                dxm[o0] = h2f(a[o0]) > 0.0f ? acc0[e] : 0.0f;
+                dxm[o1] = h2f(a[o1]) > 0.0f ? acc1[e] : 0.0f;
+            }
         }
     }
 }
@@ -925,14 +951,14 @@ extern "C" int psfm_cnn_loss_grad(const uint16_t* w16, const uint16_t* x, const 
                        w + OFF_F1W, A.a4, FLAT, B, A.d4);
     // conv4 .. conv1 (d_k: gradient at the pre-activation of conv k, ReLU applied)
     conv_bwd_w<2>(st, A.d4, SIDE4, A.a3, CH, SIDE3, B, A.wpart, grad + OFF_C4W, grad + OFF_C4B);
-    hipLaunchKernelGGL((k_conv_bwd_data<2>), dim3(grid_for((size_t)B * SIDE3 * SIDE3)), dim3(256), 0, st,
-                       A.d4, SIDE4, w + OFF_C4W, A.a3, A.d3, SIDE3, B);
+    hipLaunchKernelGGL((k_conv_bwd_data_mfma<SIDE3, SIDE4, SIDE3>), dim3(B), dim3(256), 0, st, A.d4,
+                       w + OFF_C4W, A.a3, A.d3);
     conv_bwd_w<2>(st, A.d3, SIDE3, A.a2, CH, SIDE2, B, A.wpart, grad + OFF_C3W, grad + OFF_C3B);
-    hipLaunchKernelGGL((k_conv_bwd_data<2>), dim3(grid_for((size_t)B * SIDE2 * SIDE2)), dim3(256), 0, st,
-                       A.d3, SIDE3, w + OFF_C3W, A.a2, A.d2, SIDE2, B);
+    hipLaunchKernelGGL((k_conv_bwd_data_mfma<SIDE2, SIDE3, 10>), dim3(B * ((SIDE2 + 9) / 10)), dim3(256), 0,
+                       st, A.d3, w + OFF_C3W, A.a2, A.d2);
     conv_bwd_w<2>(st, A.d2, SIDE2, A.a1, CH, SIDE1, B, A.wpart, grad + OFF_C2W, grad + OFF_C2B);
-    hipLaunchKernelGGL((k_conv_bwd_data<2>), dim3(grid_for((size_t)B * SIDE1 * SIDE1)), dim3(256), 0, st,
-                       A.d2, SIDE2, w + OFF_C2W, A.a1, A.d1, SIDE1, B);
+    hipLaunchKernelGGL((k_conv_bwd_data_mfma<SIDE1, SIDE2, 6>), dim3(B * ((SIDE1 + 5) / 6)), dim3(256), 0, st,
+                       A.d2, w + OFF_C2W, A.a1, A.d1);
     conv_bwd_w<1>(st, A.d1, SIDE1, x0, 2, SIDE0, B, A.wpart, grad + OFF_C1W, grad + OFF_C1B);
     PSFM_HIP_CHECK(hipGetLastError());
     return PSFM_OK;
