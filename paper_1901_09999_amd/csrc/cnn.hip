@@ -350,7 +350,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(const float* __restrict__ dy
 // 4 x 9 sums of outputs 4 ob .. 4 ob + 3 and input channel c (the bias sums
 // ride with c = 0).  Partials per workgroup, (CH * CH * 9 + CH) floats each.
 constexpr int WG_PIX = 32;
-constexpr int WG_MAXG = 256;
+constexpr int WG_MAXG = 768;
 template <int S>
 __global__ __launch_bounds__(256) void k_conv_bwd_w_gemm(const float* __restrict__ dy, int Hout,
                                                          const __half* __restrict__ x, int Hin, int B,
@@ -745,7 +745,7 @@ void conv_bwd_w(hipStream_t st, const float* dy, int Hout, const __half* x, int 
                 float* wpart, float* dw, float* db) {
     if (CIN == CH) {
         const int nch = (B * Hout * Hout + WG_PIX - 1) / WG_PIX;
-        int G = (nch + 7) / 8;                    // at least eight pixel chunks per workgroup
+        int G = (nch + 1) / 2;                    // at least two pixel chunks per workgroup
         G = G < 1 ? 1 : G > WG_MAXG ? WG_MAXG : G;
         hipLaunchKernelGGL((k_conv_bwd_w_gemm<S>), dim3(G), dim3(256), 0, st, dy, Hout, x, Hin, B, wpart);
         const int nw = CH * CH * 9;
