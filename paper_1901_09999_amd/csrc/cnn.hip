@@ -21,8 +21,8 @@
 //                    the pixels, chunks of output gradients and input patches
 //                    staged in LDS, 4 x 9 sums per thread, a partial set per
 //                    workgroup;
-//   k_conv_bwd_w     first layer (2 input channels): one workgroup per (o, c)
-//                    and batch chunk;
+//   k_conv_bwd_w     first layer (2 input channels): one workgroup per (group
+//                    of 8 output channels, c) and batch chunk;
 //   k_conv_bwd_w_sum adds the partial sets in a fixed order;
 //   k_fc_fwd / k_fc_bwd_x / k_fc_bwd_w, k_mse, k_adam.
 // The backward pass stores activation gradients in FP32.
@@ -299,25 +299,29 @@ __device__ __forceinline__ float block_sum_f(float v, float* red) {
 }
 
 // dw[o,c,u,v] = sum_{b,i,j} dy[b,o,i,j] x[b,c,s i+u-1,s j+v-1]; db[o] = sum dy.
-// One workgroup per (o, c); fixed summation order.
-template <int S>
+// One workgroup per (group of OG output channels, input channel c) and batch
+// chunk: a pixel's nine input values serve OG outputs (OG x 9 sums per
+// thread); the sums are reduced per wave by shuffles and then over the four
+// waves in a fixed order.
+template <int S, int OG>
 __global__ __launch_bounds__(256) void k_conv_bwd_w(const float* __restrict__ dy, int Hout,
                                                     const __half* __restrict__ x, int CIN, int Hin,
                                                     int B, float* __restrict__ part) {
-    __shared__ float red[4];
-    const int o = blockIdx.x / CIN, c = blockIdx.x % CIN;
+    constexpr int NV = OG * 9 + OG;                     // weight sums, then bias sums
+    __shared__ float wred[4][NV];
+    const int og = blockIdx.x / CIN, c = blockIdx.x % CIN;
     const int nsplit = gridDim.y, split = blockIdx.y;
     const int b0 = split * B / nsplit, b1 = (split + 1) * B / nsplit;
-    float acc[9];
+    float acc[NV];
 #pragma unroll
-    for (int k = 0; k < 9; k++) acc[k] = 0.0f;
-    float accb = 0.0f;
+    for (int k = 0; k < NV; k++) acc[k] = 0.0f;
     const int npix = Hout * Hout;
     for (int t = b0 * npix + threadIdx.x; t < b1 * npix; t += 256) {
         const int b = t / npix, pp = t - b * npix;
         const int i = pp / Hout, j = pp - i * Hout;
-        const float g = dy[((size_t)b * CH + o) * npix + pp];
-        accb += g;
+        float g[OG];
+#pragma unroll
+        for (int q = 0; q < OG; q++) g[q] = dy[((size_t)b * CH + og * OG + q) * npix + pp];
         const __half* xc = x + ((size_t)b * CIN + c) * Hin * Hin;
         // nine input loads, unconditional from clamped addresses (zero outside)
         float xv[9];
@@ -331,16 +335,26 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(const float* __restrict__ dy
                 xv[u * 3 + v] = in ? xx : 0.0f;
             }
 #pragma unroll
-        for (int k = 0; k < 9; k++) acc[k] = fmaf(g, xv[k], acc[k]);
-    }
-    float* pw = part + (size_t)split * (CH * CIN * 9 + CH);
+        for (int q = 0; q < OG; q++) {
 #pragma unroll
-    for (int k = 0; k < 9; k++) {
-        const float s = block_sum_f(acc[k], red);
-        if (threadIdx.x == 0) pw[(o * CIN + c) * 9 + k] = s;
+            for (int k = 0; k < 9; k++) acc[q * 9 + k] = fmaf(g[q], xv[k], acc[q * 9 + k]);
+            acc[OG * 9 + q] += g[q];
+        }
     }
-    const float sb = block_sum_f(accb, red);
-    if (c == 0 && threadIdx.x == 0) pw[CH * CIN * 9 + o] = sb;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; k++) {
+        float v = acc[k];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (lane == 0) wred[wave][k] = v;
+    }
+    __syncthreads();
+    float* pw = part + (size_t)split * (CH * CIN * 9 + CH);
+    for (int k = threadIdx.x; k < NV; k += 256) {
+        const float sv = ((wred[0][k] + wred[1][k]) + wred[2][k]) + wred[3][k];
+        if (k < OG * 9) pw[((og * OG + k / 9) * CIN + c) * 9 + k % 9] = sv;
+        else if (c == 0) pw[CH * CIN * 9 + og * OG + (k - OG * 9)] = sv;
+    }
 }
 
 // Weight and bias gradients of a 32 -> 32 layer as a GEMM over the pixels
@@ -735,7 +749,7 @@ __global__ __launch_bounds__(64) void k_loss_weight(const double* __restrict__ R
     }
 }
 
-constexpr int WSPLIT_MAX = 32;   // batch chunks of the weight-gradient reduction
+constexpr int WSPLIT_MAX = 128;  // batch chunks of the weight-gradient reduction
 
 // Weight gradient of one convolution layer: (o, c) pairs x batch chunks
 // (enough workgroups to fill the chip), then the chunk partials summed in
@@ -753,13 +767,14 @@ void conv_bwd_w(hipStream_t st, const float* dy, int Hout, const __half* x, int 
                            dw, db);
         return;
     }
-    const int pairs = CH * CIN;
-    int nsplit = (2048 + pairs - 1) / pairs;
+    constexpr int OG = 8;                         // output channels per workgroup
+    const int groups = (CH / OG) * CIN;
+    int nsplit = (1024 + groups - 1) / groups;
     nsplit = nsplit < 1 ? 1 : nsplit > WSPLIT_MAX ? WSPLIT_MAX : nsplit;
     if (nsplit > B) nsplit = B;
-    hipLaunchKernelGGL((k_conv_bwd_w<S>), dim3(pairs, nsplit), dim3(256), 0, st, dy, Hout, x, CIN, Hin, B,
-                       wpart);
-    const int nw = pairs * 9;
+    hipLaunchKernelGGL((k_conv_bwd_w<S, OG>), dim3(groups, nsplit), dim3(256), 0, st, dy, Hout, x, CIN, Hin,
+                       B, wpart);
+    const int nw = CH * CIN * 9;
     hipLaunchKernelGGL(k_conv_bwd_w_sum, dim3((nw + CH + 63) / 64), dim3(256), 0, st, wpart, nsplit, nw,
                        dw, db);
 }
