@@ -454,15 +454,18 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w_gemm(const float* __restrict
 }
 
 // dw = sum of the nsplit partial sets of the weight-gradient kernels: 64
-// outputs per workgroup, each summed by four thread groups over fixed ranges
-// of the sets (two accumulators each), the four group sums added in order.
-__global__ __launch_bounds__(256) void k_conv_bwd_w_sum(const float* __restrict__ part, int nsplit,
-                                                        int nw, float* __restrict__ dw,
-                                                        float* __restrict__ db) {
-    __shared__ float gs[4][64];
+// outputs per workgroup, each summed by WSUM_GROUPS thread groups over fixed
+// ranges of the sets (two accumulators each), the group sums added in order.
+constexpr int WSUM_GROUPS = 16;
+
+__global__ __launch_bounds__(64 * WSUM_GROUPS) void k_conv_bwd_w_sum(const float* __restrict__ part,
+                                                                     int nsplit, int nw,
+                                                                     float* __restrict__ dw,
+                                                                     float* __restrict__ db) {
+    __shared__ float gs[WSUM_GROUPS][64];
     const int l = threadIdx.x & 63, grp = threadIdx.x >> 6;
     const int t = blockIdx.x * 64 + l;
-    const int k0 = grp * nsplit / 4, k1 = (grp + 1) * nsplit / 4;
+    const int k0 = grp * nsplit / WSUM_GROUPS, k1 = (grp + 1) * nsplit / WSUM_GROUPS;
     float s0 = 0.0f, s1 = 0.0f;
     if (t < nw + CH) {
         int k = k0;
@@ -475,7 +478,8 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w_sum(const float* __restrict_
     gs[grp][l] = s0 + s1;
     __syncthreads();
     if (grp == 0 && t < nw + CH) {
-        const float s = ((gs[0][l] + gs[1][l]) + gs[2][l]) + gs[3][l];
+        float s = gs[0][l];
+        for (int g = 1; g < WSUM_GROUPS; g++) s += gs[g][l];
         if (t < nw) dw[t] = s;
         else db[t - nw] = s;
     }
@@ -763,7 +767,7 @@ void conv_bwd_w(hipStream_t st, const float* dy, int Hout, const __half* x, int 
         G = G < 1 ? 1 : G > WG_MAXG ? WG_MAXG : G;
         hipLaunchKernelGGL((k_conv_bwd_w_gemm<S>), dim3(G), dim3(256), 0, st, dy, Hout, x, Hin, B, wpart);
         const int nw = CH * CH * 9;
-        hipLaunchKernelGGL(k_conv_bwd_w_sum, dim3((nw + CH + 63) / 64), dim3(256), 0, st, wpart, G, nw,
+        hipLaunchKernelGGL(k_conv_bwd_w_sum, dim3((nw + CH + 63) / 64), dim3(64 * WSUM_GROUPS), 0, st, wpart, G, nw,
                            dw, db);
         return;
     }
@@ -775,7 +779,7 @@ void conv_bwd_w(hipStream_t st, const float* dy, int Hout, const __half* x, int 
     hipLaunchKernelGGL((k_conv_bwd_w<S, OG>), dim3(groups, nsplit), dim3(256), 0, st, dy, Hout, x, CIN, Hin,
                        B, wpart);
     const int nw = CH * CIN * 9;
-    hipLaunchKernelGGL(k_conv_bwd_w_sum, dim3((nw + CH + 63) / 64), dim3(256), 0, st, wpart, nsplit, nw,
+    hipLaunchKernelGGL(k_conv_bwd_w_sum, dim3((nw + CH + 63) / 64), dim3(64 * WSUM_GROUPS), 0, st, wpart, nsplit, nw,
                        dw, db);
 }
 
