@@ -393,11 +393,12 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w_gemm(const float* __restrict
         }
         __syncthreads();
         // stage dy (WG_PIX x CH) and the patches (WG_PIX x CH*9); loads from
-        // clamped addresses, zero outside the chunk or the input
-        // all loads first (one round trip), then the LDS stores
-        constexpr int ND = WG_PIX * CH / 256, NX = WG_PIX * CH * 9 / 256;
+        // clamped addresses, zero outside the chunk or the input; the patch
+        // values in batches of XB loads in flight (each then stored), which
+        // keeps the registers of two waves per SIMD
+        constexpr int ND = WG_PIX * CH / 256, NX = WG_PIX * CH * 9 / 256, XB = 12;
+        static_assert(NX % XB == 0, "whole batches");
         float dv[ND];
-        __half xh[NX];
 #pragma unroll
         for (int k = 0; k < ND; k++) {
             const int e = tid + 256 * k, pl = e % WG_PIX, o = e / WG_PIX;
@@ -405,26 +406,30 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w_gemm(const float* __restrict
             dv[k] = dy[b >= 0 ? ((size_t)b * CH + o) * npix + spp[pl] : 0];
         }
 #pragma unroll
-        for (int k = 0; k < NX; k++) {
-            const int e = tid + 256 * k, pl = e % WG_PIX, cuv = e / WG_PIX;
-            const int cc = cuv / 9, uv = cuv - 9 * cc, u = uv / 3, v = uv - 3 * u;
-            const int b = sb[pl];
-            const int pi = S * si[pl] + u - 1, qj = S * sj[pl] + v - 1;
-            const bool in = b >= 0 && pi >= 0 && pi < Hin && qj >= 0 && qj < Hin;
-            xh[k] = x[in ? ((size_t)b * CH + cc) * Hin * Hin + pi * Hin + qj : 0];
-        }
-#pragma unroll
         for (int k = 0; k < ND; k++) {
             const int e = tid + 256 * k, pl = e % WG_PIX, o = e / WG_PIX;
             sdy[pl][o] = sb[pl] >= 0 ? dv[k] : 0.0f;
         }
+#pragma unroll 1
+        for (int k0 = 0; k0 < NX; k0 += XB) {
+            __half xh[XB];
 #pragma unroll
-        for (int k = 0; k < NX; k++) {
-            const int e = tid + 256 * k, pl = e % WG_PIX, cuv = e / WG_PIX;
-            const int cc = cuv / 9, uv = cuv - 9 * cc, u = uv / 3, v = uv - 3 * u;
-            const int pi = S * si[pl] + u - 1, qj = S * sj[pl] + v - 1;
-            const bool in = sb[pl] >= 0 && pi >= 0 && pi < Hin && qj >= 0 && qj < Hin;
-            sx[pl][cuv] = in ? h2f(xh[k]) : 0.0f;
+            for (int kk = 0; kk < XB; kk++) {
+                const int e = tid + 256 * (k0 + kk), pl = e % WG_PIX, cuv = e / WG_PIX;
+                const int cc = cuv / 9, uv = cuv - 9 * cc, u = uv / 3, v = uv - 3 * u;
+                const int b = sb[pl];
+                const int pi = S * si[pl] + u - 1, qj = S * sj[pl] + v - 1;
+                const bool in = b >= 0 && pi >= 0 && pi < Hin && qj >= 0 && qj < Hin;
+                xh[kk] = x[in ? ((size_t)b * CH + cc) * Hin * Hin + pi * Hin + qj : 0];
+            }
+#pragma unroll
+            for (int kk = 0; kk < XB; kk++) {
+                const int e = tid + 256 * (k0 + kk), pl = e % WG_PIX, cuv = e / WG_PIX;
+                const int cc = cuv / 9, uv = cuv - 9 * cc, u = uv / 3, v = uv - 3 * u;
+                const int pi = S * si[pl] + u - 1, qj = S * sj[pl] + v - 1;
+                const bool in = sb[pl] >= 0 && pi >= 0 && pi < Hin && qj >= 0 && qj < Hin;
+                sx[pl][cuv] = in ? h2f(xh[kk]) : 0.0f;
+            }
         }
         __syncthreads();
 #pragma unroll 4
