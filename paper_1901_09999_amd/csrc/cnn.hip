@@ -535,6 +535,8 @@ __global__ __launch_bounds__(256) void k_fc_bwd_w(const float* __restrict__ dy, 
         const int n = t / K, k = t - n * K;
         float a4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
         int b = 0;
+        // (sample b into a4[b % 4]; four groups of four samples' loads in flight)
+#pragma unroll 4
         for (; b + 3 < B; b += 4)
 #pragma unroll
             for (int u = 0; u < 4; u++)
