@@ -378,8 +378,14 @@ __global__ __launch_bounds__(256) void k_conv_tile(
     __shared__ double s_f;
     const int tid = threadIdx.x;
     const PatchGeom g = patch_geom(W, H, P);
-    const int px = blockIdx.x / g.tpp, sx = blockIdx.x % g.tpp;
-    const int py = blockIdx.y / g.tpp, sy = blockIdx.y % g.tpp;
+    // tiles XCD by XCD (workgroup L of the launch runs on XCD L mod 8): XCD x
+    // takes the x-th contiguous eighth of the tiles in row-major order, whose
+    // halos overlap in that XCD's L2
+    const int ngx = gridDim.x, nt = ngx * gridDim.y, L = blockIdx.y * ngx + blockIdx.x;
+    const int xq = L & 7, kq = L >> 3, qq = nt >> 3, rq = nt & 7;
+    const int tl = xq * qq + (xq < rq ? xq : rq) + kq, tx = tl % ngx, ty = tl / ngx;
+    const int px = tx / g.tpp, sx = tx % g.tpp;
+    const int py = ty / g.tpp, sy = ty % g.tpp;
     const int X0 = px * P + sx * TILE, Y0 = py * P + sy * TILE;
     const int X1 = min(min(X0 + TILE, (px + 1) * P), W);
     const int Y1 = min(min(Y0 + TILE, (py + 1) * P), H);
@@ -473,8 +479,14 @@ __global__ __launch_bounds__(256) void k_conv_pair_tile(
     __shared__ double s_f;
     const int tid = threadIdx.x;
     const PatchGeom g = patch_geom(W, H, P);
-    const int px = blockIdx.x / g.tpp, sx = blockIdx.x % g.tpp;
-    const int py = blockIdx.y / g.tpp, sy = blockIdx.y % g.tpp;
+    // tiles XCD by XCD (workgroup L of the launch runs on XCD L mod 8): XCD x
+    // takes the x-th contiguous eighth of the tiles in row-major order, whose
+    // halos overlap in that XCD's L2
+    const int ngx = gridDim.x, nt = ngx * gridDim.y, L = blockIdx.y * ngx + blockIdx.x;
+    const int xq = L & 7, kq = L >> 3, qq = nt >> 3, rq = nt & 7;
+    const int tl = xq * qq + (xq < rq ? xq : rq) + kq, tx = tl % ngx, ty = tl / ngx;
+    const int px = tx / g.tpp, sx = tx % g.tpp;
+    const int py = ty / g.tpp, sy = ty % g.tpp;
     const int X0 = px * P + sx * TILE, Y0 = py * P + sy * TILE;
     const int X1 = min(min(X0 + TILE, (px + 1) * P), W);
     const int Y1 = min(min(Y0 + TILE, (py + 1) * P), H);
@@ -1282,7 +1294,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     __shared__ double red[16];
     __shared__ int s_rb;
     __shared__ double s_f;
-    match_tile<H_, true>(p, blockIdx.x, B0, P, bad_frac, halo, tapsK, tapsV, badw, ring, red, &s_rb, &s_f);
+    // one workgroup per tile, XCD by XCD: workgroup b runs on XCD b mod 8, so
+    // XCD x takes the x-th contiguous eighth of the tiles, whose halos overlap
+    const int n = gridDim.x, x = blockIdx.x & 7, k = blockIdx.x >> 3, q = n >> 3, r = n & 7;
+    const int t = x * q + (x < r ? x : r) + k;
+    match_tile<H_, true>(p, t, B0, P, bad_frac, halo, tapsK, tapsV, badw, ring, red, &s_rb, &s_f);
 }
 
 constexpr int SUB_BLOCKS = 1024;
