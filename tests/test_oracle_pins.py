@@ -718,7 +718,7 @@ def test_clip_iterations_and_min_stamps(orc):
     qs = [1.0] * 12 + [3.0, 40.0]
     cfg, fit, st_xy = _clip_problem(qs)
     ret, a, chi2, fl, st = O.solve(cfg, 100, 100, st_xy, fit)
-    # round 1 drops the 40; round 2 (mean 1.15, std 0.53, threshold 2.74) drops the 3
+    # the first clip pass drops the 40; the second (mean 1.15, std 0.53, threshold 2.74) drops the 3
     assert ret == 0 and st["n_iter"] == 3 and st["n_rejected"] == 2
     assert fl[12] & O.STAMP_REJECTED and fl[13] & O.STAMP_REJECTED
     cfg1 = O.Config(**{**cfg.__dict__, "max_iter": 2})
