@@ -24,6 +24,7 @@
 //   k_conv_bwd_w     first layer (2 input channels): one workgroup per (group
 //                    of 8 output channels, c) and batch chunk;
 //   k_conv_bwd_w_sum adds the partial sets in a fixed order;
+//   k_fc_fwd_mfma  the first fully connected layer on FP16 MFMA (below);
 //   k_fc_fwd / k_fc_bwd_x / k_fc_bwd_w, k_mse, k_adam.
 // The backward pass stores activation gradients in FP32.
 #include "internal.h"
@@ -175,6 +176,52 @@ __global__ __launch_bounds__(256) void k_conv_fwd_mfma(const __half* __restrict_
                 y[o0] = __float2half(fmaxf(acc0[e] + b0, 0.0f));
                 y[o0 + (size_t)16 * HOUT * HOUT] = __float2half(fmaxf(acc1[e] + b1, 0.0f));
             }
+        }
+    }
+}
+
+// The first fully connected layer, h = ReLU(W x + bias) in FP16, as a GEMM
+// on v_mfma_f32_16x16x32_f16 (FP16 products exact, FP32 sums).  One
+// workgroup per 16 x 16 tile of (sample, hidden unit); its four waves take
+// a quarter of the inputs each, reading the k-contiguous rows of x and W
+// straight from global memory in 16-byte pieces (both 16-byte aligned), and
+// the four partial tiles are summed in a fixed order through LDS.  Samples
+// past B (a ragged last tile) take zero operands and are not written.
+template <int K>
+__global__ __launch_bounds__(256) void k_fc_fwd_mfma(const __half* __restrict__ x,
+                                                     const __half* __restrict__ W,
+                                                     const __half* __restrict__ bias, int N, int B,
+                                                     __half* __restrict__ y) {
+    static_assert(K % 128 == 0, "four waves of 32-wide k steps");
+    constexpr int KQ = K / 4;
+    __shared__ float part[3][4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nt = N / 16, tb = blockIdx.x / nt, tn = blockIdx.x - tb * nt;
+    const int b = 16 * tb + (lane & 15), n = 16 * tn + (lane & 15);
+    const bool bval = b < B;
+    const int k0 = wave * KQ + 8 * (lane >> 4);
+    const __half* xr = x + (size_t)(bval ? b : 0) * K + k0;
+    const __half* wr = W + (size_t)n * K + k0;
+    cnn_floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int k = 0; k < KQ; k += 32) {
+        const cnn_half8 a = bval ? *reinterpret_cast<const cnn_half8*>(xr + k)
+                                 : cnn_half8{0, 0, 0, 0, 0, 0, 0, 0};
+        const cnn_half8 w = *reinterpret_cast<const cnn_half8*>(wr + k);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, w, acc, 0, 0, 0);
+    }
+    if (wave > 0)
+#pragma unroll
+        for (int e = 0; e < 4; e++) part[wave - 1][e][lane] = acc[e];
+    __syncthreads();
+    if (wave == 0) {
+        const float bn = h2f(bias[n]);
+        // lane: hidden unit n of samples 16 tb + 4 (lane / 16) + e
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const int bb = 16 * tb + 4 * (lane >> 4) + e;
+            const float s = ((acc[e] + part[0][e][lane]) + part[1][e][lane]) + part[2][e][lane];
+            if (bb < B) y[(size_t)bb * N + n] = __float2half(fmaxf(s + bn, 0.0f));
         }
     }
 }
@@ -832,8 +879,14 @@ int forward_into(const __half* w, const __half* x, int B, const Acts& A, hipStre
                        st, A.a2, w + OFF_C3W, w + OFF_C3B, A.a3);
     hipLaunchKernelGGL((k_conv_fwd_mfma<SIDE3, SIDE4, RB>), dim3(B * ((SIDE4 + RB - 1) / RB)), dim3(256), 0,
                        st, A.a3, w + OFF_C4W, w + OFF_C4B, A.a4);
-    hipLaunchKernelGGL((k_fc_fwd<true>), dim3((B * HID + 3) / 4), dim3(256), 0, st, A.a4, FLAT,
-                       w + OFF_F1W, w + OFF_F1B, HID, B, A.h, nullptr);
+    static_assert(HID % 16 == 0 && (FLAT * sizeof(__half)) % 16 == 0 && OFF_F1W % 8 == 0,
+                  "16 x 16 tiles, 16-byte aligned rows");
+    if ((((uintptr_t)A.a4) | ((uintptr_t)(w + OFF_F1W))) % 16 == 0)
+        hipLaunchKernelGGL((k_fc_fwd_mfma<FLAT>), dim3(((B + 15) / 16) * (HID / 16)), dim3(256), 0, st,
+                           A.a4, w + OFF_F1W, w + OFF_F1B, HID, B, A.h);
+    else  // weights or workspace not 16-byte aligned: one wave per output
+        hipLaunchKernelGGL((k_fc_fwd<true>), dim3((B * HID + 3) / 4), dim3(256), 0, st, A.a4, FLAT,
+                           w + OFF_F1W, w + OFF_F1B, HID, B, A.h, nullptr);
     hipLaunchKernelGGL((k_fc_fwd<false>), dim3((B * NOUT + 3) / 4), dim3(256), 0, st, A.h, HID,
                        w + OFF_F2W, w + OFF_F2B, NOUT, B, nullptr, A.out);
     PSFM_HIP_CHECK(hipGetLastError());

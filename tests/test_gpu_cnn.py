@@ -47,6 +47,28 @@ def test_forward_matches_oracle():
     assert err < 2e-2
 
 
+def test_forward_ragged_batch_and_unaligned_weights():
+    """37 samples: two full 16-sample tiles of the first fully connected
+    layer and a ragged one; then the same weights one element past a 16-byte
+    boundary, which takes the layer's one-wave-per-output kernel instead."""
+    torch, cnn, net, x, t, theta16 = _net_and_batch(B=37, seed=11)
+    xd = torch.from_numpy(x).cuda()
+    ref = CO.forward(theta16, x.astype(np.float64))
+    out = _np(net.forward(xd))
+    err = np.max(np.abs(out - ref)) / np.max(np.abs(ref))
+    print(f"aligned: forward max error / scale {err:.2e}")
+    assert err < 2e-2
+    buf = torch.empty(net.w16.numel() + 1, dtype=torch.float16, device=net.w16.device)
+    buf[1:].copy_(net.w16)
+    net.w16 = buf[1:]
+    assert net.w16.data_ptr() % 16 != 0
+    out_u = _np(net.forward(xd))
+    err_u = np.max(np.abs(out_u - ref)) / np.max(np.abs(ref))
+    print(f"unaligned: forward max error / scale {err_u:.2e}")
+    assert err_u < 2e-2
+    assert np.max(np.abs(out_u - out)) <= 5e-3 * np.max(np.abs(ref))
+
+
 def test_gradient_matches_oracle():
     torch, cnn, net, x, t, theta16 = _net_and_batch()
     loss, grad = net.loss_grad(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda())
