@@ -573,28 +573,41 @@ __global__ __launch_bounds__(256) void k_fc_bwd_x(const float* __restrict__ dy, 
     dxm[t] = h2f(x[t]) > 0.0f ? acc : 0.0f;
 }
 
-// dW[n,k] = sum_b dy[b,n] x[b,k];  db[n] = sum_b dy[b,n]
+// dW[n,k] = sum_b dy[b,n] x[b,k];  db[n] = sum_b dy[b,n].  Lane l of a
+// workgroup takes output 64 blockIdx.x + l (coalesced rows of x, dy
+// broadcast); its four waves take a quarter of the samples each (four running
+// sums over every fourth sample, so four loads are in flight), and the
+// quarters are added in a fixed order through LDS.
 __global__ __launch_bounds__(256) void k_fc_bwd_w(const float* __restrict__ dy, int N,
                                                   const __half* __restrict__ x, int K, int B,
                                                   float* __restrict__ dW, float* __restrict__ db) {
-    const int t = blockIdx.x * 256 + threadIdx.x;
+    __shared__ float pw[3][64], pb[3][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int t = blockIdx.x * 64 + lane;
+    const int q = (B + 3) / 4, b0 = min(B, wave * q), b1 = min(B, b0 + q);
+    float w = 0.0f, bsum = 0.0f;
     if (t < N * K) {
         const int n = t / K, k = t - n * K;
         float a4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        int b = 0;
-        // (sample b into a4[b % 4]; four groups of four samples' loads in flight)
+        int b = b0;
 #pragma unroll 4
-        for (; b + 3 < B; b += 4)
+        for (; b + 3 < b1; b += 4)
 #pragma unroll
             for (int u = 0; u < 4; u++)
                 a4[u] = fmaf(dy[(size_t)(b + u) * N + n], h2f(x[(size_t)(b + u) * K + k]), a4[u]);
-        for (; b < B; b++) a4[0] = fmaf(dy[(size_t)b * N + n], h2f(x[(size_t)b * K + k]), a4[0]);
-        dW[t] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+        for (; b < b1; b++) a4[0] = fmaf(dy[(size_t)b * N + n], h2f(x[(size_t)b * K + k]), a4[0]);
+        w = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+        if (t < N)
+            for (int bb = b0; bb < b1; bb++) bsum += dy[(size_t)bb * N + t];
     }
-    if (t < N) {
-        float acc = 0.0f;
-        for (int b = 0; b < B; b++) acc += dy[(size_t)b * N + t];
-        db[t] = acc;
+    if (wave > 0) {
+        pw[wave - 1][lane] = w;
+        pb[wave - 1][lane] = bsum;
+    }
+    __syncthreads();
+    if (wave == 0 && t < N * K) {
+        dW[t] = ((w + pw[0][lane]) + pw[1][lane]) + pw[2][lane];
+        if (t < N) db[t] = ((bsum + pb[0][lane]) + pb[1][lane]) + pb[2][lane];
     }
 }
 
@@ -1020,11 +1033,11 @@ extern "C" int psfm_cnn_loss_grad(const uint16_t* w16, const uint16_t* x, const 
         hipLaunchKernelGGL(k_mse, dim3(1), dim3(256), 0, st, A.out, target, B * NOUT, A.dout, loss);
     }
     // fc2, fc1
-    hipLaunchKernelGGL(k_fc_bwd_w, dim3((NOUT * HID + 255) / 256), dim3(256), 0, st, A.dout, NOUT, A.h,
+    hipLaunchKernelGGL(k_fc_bwd_w, dim3((NOUT * HID + 63) / 64), dim3(256), 0, st, A.dout, NOUT, A.h,
                        HID, B, grad + OFF_F2W, grad + OFF_F2B);
     hipLaunchKernelGGL(k_fc_bwd_x, dim3((B * HID + 255) / 256), dim3(256), 0, st, A.dout, NOUT,
                        w + OFF_F2W, A.h, HID, B, A.dh);
-    hipLaunchKernelGGL(k_fc_bwd_w, dim3((HID * FLAT + 255) / 256), dim3(256), 0, st, A.dh, HID, A.a4,
+    hipLaunchKernelGGL(k_fc_bwd_w, dim3((HID * FLAT + 63) / 64), dim3(256), 0, st, A.dh, HID, A.a4,
                        FLAT, B, grad + OFF_F1W, grad + OFF_F1B);
     hipLaunchKernelGGL(k_fc_bwd_x, dim3((B * FLAT + 255) / 256), dim3(256), 0, st, A.dh, HID,
                        w + OFF_F1W, A.a4, FLAT, B, A.d4);

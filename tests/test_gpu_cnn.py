@@ -69,8 +69,11 @@ def test_forward_ragged_batch_and_unaligned_weights():
     assert np.max(np.abs(out_u - out)) <= 5e-3 * np.max(np.abs(ref))
 
 
-def test_gradient_matches_oracle():
-    torch, cnn, net, x, t, theta16 = _net_and_batch()
+@pytest.mark.parametrize("B", [8, 37])
+def test_gradient_matches_oracle(B):
+    """B = 37: the weight-gradient kernels' sample quarters are uneven (10,
+    10, 10, 7) and the first fully connected layer's last tile is ragged."""
+    torch, cnn, net, x, t, theta16 = _net_and_batch(B=B)
     loss, grad = net.loss_grad(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda())
     g = _np(grad).astype(np.float64)
     l_ref, g_ref = CO.loss_and_grad(theta16, x.astype(np.float64), t.astype(np.float64))
