@@ -560,17 +560,38 @@ __global__ __launch_bounds__(256) void k_fc_fwd(const __half* __restrict__ x, in
     }
 }
 
-// dxm[b,k] = (sum_n W[n,k] dy[b,n]) * (x[b,k] > 0)
+// dxm[b,k] = (sum_n W[n,k] dy[b,n]) * (x[b,k] > 0).  Lane l of a workgroup
+// takes output 64 blockIdx.x + l (coalesced rows of W, dy broadcast); its
+// four waves take a quarter of the n each (two running sums over alternate
+// n), and the quarters are added in a fixed order through LDS.
 __global__ __launch_bounds__(256) void k_fc_bwd_x(const float* __restrict__ dy, int N,
                                                   const __half* __restrict__ W,
                                                   const __half* __restrict__ x, int K, int B,
                                                   float* __restrict__ dxm) {
-    const int t = blockIdx.x * 256 + threadIdx.x;
-    if (t >= B * K) return;
-    const int b = t / K, k = t - b * K;
+    __shared__ float pd[3][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int t = blockIdx.x * 64 + lane;
+    const int q = (N + 3) / 4, n0 = min(N, wave * q), n1 = min(N, n0 + q);
     float acc = 0.0f;
-    for (int n = 0; n < N; n++) acc = fmaf(h2f(W[(size_t)n * K + k]), dy[(size_t)b * N + n], acc);
-    dxm[t] = h2f(x[t]) > 0.0f ? acc : 0.0f;
+    if (t < B * K) {
+        const int b = t / K, k = t - b * K;
+        const float* dyr = dy + (size_t)b * N;
+        float a0 = 0.0f, a1 = 0.0f;
+        int n = n0;
+#pragma unroll 4
+        for (; n + 1 < n1; n += 2) {
+            a0 = fmaf(h2f(W[(size_t)n * K + k]), dyr[n], a0);
+            a1 = fmaf(h2f(W[(size_t)(n + 1) * K + k]), dyr[n + 1], a1);
+        }
+        if (n < n1) a0 = fmaf(h2f(W[(size_t)n * K + k]), dyr[n], a0);
+        acc = a0 + a1;
+    }
+    if (wave > 0) pd[wave - 1][lane] = acc;
+    __syncthreads();
+    if (wave == 0 && t < B * K) {
+        const float s = ((acc + pd[0][lane]) + pd[1][lane]) + pd[2][lane];
+        dxm[t] = h2f(x[t]) > 0.0f ? s : 0.0f;
+    }
 }
 
 // dW[n,k] = sum_b dy[b,n] x[b,k];  db[n] = sum_b dy[b,n].  Lane l of a
@@ -1035,11 +1056,11 @@ extern "C" int psfm_cnn_loss_grad(const uint16_t* w16, const uint16_t* x, const 
     // fc2, fc1
     hipLaunchKernelGGL(k_fc_bwd_w, dim3((NOUT * HID + 63) / 64), dim3(256), 0, st, A.dout, NOUT, A.h,
                        HID, B, grad + OFF_F2W, grad + OFF_F2B);
-    hipLaunchKernelGGL(k_fc_bwd_x, dim3((B * HID + 255) / 256), dim3(256), 0, st, A.dout, NOUT,
+    hipLaunchKernelGGL(k_fc_bwd_x, dim3((B * HID + 63) / 64), dim3(256), 0, st, A.dout, NOUT,
                        w + OFF_F2W, A.h, HID, B, A.dh);
     hipLaunchKernelGGL(k_fc_bwd_w, dim3((HID * FLAT + 63) / 64), dim3(256), 0, st, A.dh, HID, A.a4,
                        FLAT, B, grad + OFF_F1W, grad + OFF_F1B);
-    hipLaunchKernelGGL(k_fc_bwd_x, dim3((B * FLAT + 255) / 256), dim3(256), 0, st, A.dh, HID,
+    hipLaunchKernelGGL(k_fc_bwd_x, dim3((B * FLAT + 63) / 64), dim3(256), 0, st, A.dh, HID,
                        w + OFF_F1W, A.a4, FLAT, B, A.d4);
     // conv4 .. conv1 (d_k: gradient at the pre-activation of conv k, ReLU applied)
     conv_bwd_w<2>(st, A.d4, SIDE4, A.a3, CH, SIDE3, B, A.wpart, grad + OFF_C4W, grad + OFF_C4B);
